@@ -1,0 +1,482 @@
+/*
+ * TEST INFRASTRUCTURE ONLY -- the CPU oracle for microcanonical simulated
+ * annealing (MicSA) on the 3D Edwards-Anderson +-J spin glass.
+ *
+ * This file is the plain, slow, obviously correct reference that the HIP
+ * product path is checked against.  It is used only by tests/, by the
+ * smoke check and by the CPU-baseline leg of the benchmark; the product
+ * library never links, loads or calls it, and it shares no code, header
+ * or table with the GPU path.  Everything here is written from the paper
+ * (Bernaschi et al., "Microcanonical simulated annealing", arXiv 2506.16240)
+ * in its own notation: spins s = +-1, couplings J = +-1, daemons n = 4m.
+ *
+ * Storage (natural order, chosen for readability, not speed):
+ *   site index     i = x + Lx*(y + Ly*z), N = Lx*Ly*Lz, periodic in all axes
+ *   sigma[l][i]    spin bit, s = 1 - 2*sigma, l = sample*R + replica
+ *   m[l][i]        daemon level, n = 4*m, m in {0,1,2,3}
+ *   J[sample][i]   bits 0,1,2 = coupling bit j of the forward bonds
+ *                  (i, i+e_x), (i, i+e_y), (i, i+e_z); J = 1 - 2*j
+ *
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11,
+ * "Parallel random numbers: as easy as 1, 2, 3"), key = (lo32(seed),
+ * hi32(seed)), with one counter per (stream, sample, replica, site, time):
+ *   couplings  ctr = (i,      0,      0, 1<<24 | s)  j_mu(i) = out[mu] >> 31
+ *   spins      ctr = (i>>2,   0,      r, 2<<24 | s)  sigma   = out[i&3] >> 31
+ *   daemons    ctr = (i>>2,   rho,    r, 3<<24 | s)  u       = out[i&3]
+ *   heat bath  ctr = (h>>2,   2k+p,   r, 4<<24 | s)  u       = out[h&3], h = i>>1
+ * (rho = refresh index, k = sweep index, p = parity being updated).  The
+ * paper leaves the generator unspecified; this map is the specification
+ * both implementations follow.
+ *
+ * Parallelism: the only OpenMP use is a parallel loop over the sites of one
+ * parity, which the paper's separability argument (Sec. 2.1, Sec. 2.3) makes
+ * order-independent; integer reductions make the result deterministic.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10, from its published definition (Salmon et al. 2011).  */
+/* ------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; round++) {
+        if (round > 0) { k0 += PHILOX_W0; k1 += PHILOX_W1; }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static uint32_t draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, int lane)
+{
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    return out[lane];
+}
+
+enum { STREAM_J = 1, STREAM_SPIN = 2, STREAM_DAEMON = 3, STREAM_HEATBATH = 4 };
+
+/* ------------------------------------------------------------------ */
+/* Lattice geometry                                                    */
+/* ------------------------------------------------------------------ */
+typedef struct { int Lx, Ly, Lz; int64_t N; } geom;
+
+static geom mk(int Lx, int Ly, int Lz)
+{
+    geom g = {Lx, Ly, Lz, (int64_t)Lx * Ly * Lz};
+    return g;
+}
+
+static void coords(const geom *g, int64_t i, int *x, int *y, int *z)
+{
+    *x = (int)(i % g->Lx);
+    *y = (int)((i / g->Lx) % g->Ly);
+    *z = (int)(i / ((int64_t)g->Lx * g->Ly));
+}
+
+static int64_t site(const geom *g, int x, int y, int z)
+{
+    x = (x % g->Lx + g->Lx) % g->Lx;
+    y = (y % g->Ly + g->Ly) % g->Ly;
+    z = (z % g->Lz + g->Lz) % g->Lz;
+    return x + (int64_t)g->Lx * (y + (int64_t)g->Ly * z);
+}
+
+static int parity_of(const geom *g, int64_t i)
+{
+    int x, y, z;
+    coords(g, i, &x, &y, &z);
+    return (x + y + z) & 1;
+}
+
+static int spin(uint8_t sigma_bit) { return 1 - 2 * (int)sigma_bit; }
+static int coupling(uint8_t jbits, int mu) { return 1 - 2 * (int)((jbits >> mu) & 1u); }
+
+/*
+ * Local field h_x = sum over the 6 neighbours y of J_xy s_y (eq. Hamiltonian,
+ * Sec. 2.1).  The forward bonds of x are stored at x, the backward bonds at
+ * the neighbour behind x.
+ */
+static int local_field(const geom *g, const uint8_t *J, const uint8_t *sig, int64_t i)
+{
+    int x, y, z;
+    coords(g, i, &x, &y, &z);
+    int64_t fwd[3] = {site(g, x + 1, y, z), site(g, x, y + 1, z), site(g, x, y, z + 1)};
+    int64_t bwd[3] = {site(g, x - 1, y, z), site(g, x, y - 1, z), site(g, x, y, z - 1)};
+    int h = 0;
+    for (int mu = 0; mu < 3; mu++) {
+        h += coupling(J[i], mu) * spin(sig[fwd[mu]]);
+        h += coupling(J[bwd[mu]], mu) * spin(sig[bwd[mu]]);
+    }
+    return h;
+}
+
+/* ------------------------------------------------------------------ */
+/* Initial state (Sec. 3: J = +-1 with probability 1/2, eq. Hamiltonian; */
+/* start from a fully disordered, infinite-temperature configuration).  */
+/* ------------------------------------------------------------------ */
+void oracle_init_couplings(int Lx, int Ly, int Lz, int S, uint64_t seed, uint8_t *J)
+{
+    geom g = mk(Lx, Ly, Lz);
+    for (int s = 0; s < S; s++)
+        for (int64_t i = 0; i < g.N; i++) {
+            uint32_t ctr[4] = {(uint32_t)i, 0u, 0u, (uint32_t)(STREAM_J << 24) | (uint32_t)s};
+            uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+            uint32_t o[4];
+            oracle_philox4x32_10(ctr, key, o);
+            J[(int64_t)s * g.N + i] = (uint8_t)((o[0] >> 31) | ((o[1] >> 31) << 1) | ((o[2] >> 31) << 2));
+        }
+}
+
+void oracle_init_spins(int Lx, int Ly, int Lz, int S, int R, uint64_t seed, uint8_t *sigma)
+{
+    geom g = mk(Lx, Ly, Lz);
+    for (int s = 0; s < S; s++)
+        for (int r = 0; r < R; r++)
+            for (int64_t i = 0; i < g.N; i++)
+                sigma[((int64_t)s * R + r) * g.N + i] =
+                    (uint8_t)(draw(seed, (uint32_t)(i >> 2), 0u, (uint32_t)r,
+                                   (uint32_t)(STREAM_SPIN << 24) | (uint32_t)s, (int)(i & 3)) >> 31);
+}
+
+/* ------------------------------------------------------------------ */
+/* Daemon refresh, eq. prob-daemons-walkers (Sec. 2.5):                */
+/*   p(n = 4m) = exp(-4 m beta) (1 - exp(-4 beta)) / (1 - exp(-16 beta)) */
+/* sampled by inverse CDF on a 32-bit uniform u:                       */
+/*   m = #{k in 0..2 : u >= t_k},  t_k = floor(2^32 * P(m <= k))       */
+/*   P(m <= k) = (1 - exp(-4 beta (k+1))) / (1 - exp(-16 beta))         */
+/* held as 64-bit integers so that P = 1 (T -> 0) gives t_k = 2^32.    */
+/* ------------------------------------------------------------------ */
+void oracle_daemon_thresholds(double T, uint64_t t[3])
+{
+    double beta = 1.0 / T;
+    for (int k = 0; k < 3; k++) {
+        double cdf = expm1(-4.0 * beta * (double)(k + 1)) / expm1(-16.0 * beta);
+        t[k] = (uint64_t)floor(cdf * 4294967296.0);
+    }
+}
+
+void oracle_refresh(int Lx, int Ly, int Lz, int S, int R, uint64_t seed, int64_t rho, double T,
+                    uint8_t *m)
+{
+    geom g = mk(Lx, Ly, Lz);
+    uint64_t t[3];
+    oracle_daemon_thresholds(T, t);
+    for (int s = 0; s < S; s++)
+        for (int r = 0; r < R; r++)
+            for (int64_t i = 0; i < g.N; i++) {
+                uint64_t u = draw(seed, (uint32_t)(i >> 2), (uint32_t)rho, (uint32_t)r,
+                                  (uint32_t)(STREAM_DAEMON << 24) | (uint32_t)s, (int)(i & 3));
+                int level = 0;
+                for (int k = 0; k < 3; k++) level += (u >= t[k]);
+                m[((int64_t)s * R + r) * g.N + i] = (uint8_t)level;
+            }
+}
+
+/* ------------------------------------------------------------------ */
+/* MicSA half sweep (Sec. 2.3 eq. Creutz, Sec. 2.5 eq. flip-OK,        */
+/* procedure of Sec. 2.8.1 with gamma = 1 daemon per site): for every  */
+/* site x of the given parity, dH = H(flipped) - H = 2 s_x h_x; the     */
+/* flip is legal iff 0 <= n_x - dH <= 12, and then n_x -> n_x - dH.    */
+/* dE[l] accumulates the change of H^EA of lattice l.                  */
+/* ------------------------------------------------------------------ */
+static int micsa_site(const geom *g, const uint8_t *Js, uint8_t *sig, uint8_t *dm, int64_t i)
+{
+    int dH = 2 * spin(sig[i]) * local_field(g, Js, sig, i);
+    int n = 4 * (int)dm[i];
+    if (n - dH >= 0 && n - dH <= 12) {
+        sig[i] ^= 1u;
+        dm[i] = (uint8_t)((n - dH) / 4);
+        return dH;
+    }
+    return 0;
+}
+
+/* One elementary move on site i of a single lattice; returns dH (0 if rejected). */
+int oracle_micsa_site(int Lx, int Ly, int Lz, int64_t i, const uint8_t *J, uint8_t *sigma, uint8_t *m)
+{
+    geom g = mk(Lx, Ly, Lz);
+    return micsa_site(&g, J, sigma, m, i);
+}
+
+void oracle_micsa_half(int Lx, int Ly, int Lz, int S, int R, int parity,
+                       const uint8_t *J, uint8_t *sigma, uint8_t *m, int64_t *dE)
+{
+    geom g = mk(Lx, Ly, Lz);
+    for (int s = 0; s < S; s++)
+        for (int r = 0; r < R; r++) {
+            const uint8_t *Js = J + (int64_t)s * g.N;
+            uint8_t *sig = sigma + ((int64_t)s * R + r) * g.N;
+            uint8_t *dm = m + ((int64_t)s * R + r) * g.N;
+            int64_t acc = 0;
+#pragma omp parallel for reduction(+ : acc) schedule(static)
+            for (int64_t i = 0; i < g.N; i++) {
+                if (parity_of(&g, i) != parity) continue;
+                acc += micsa_site(&g, Js, sig, dm, i);
+            }
+            dE[(int64_t)s * R + r] += acc;
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* Heat bath, the canonical baseline named in Sec. 2.1: the new spin is */
+/* +1 with probability 1/(1 + exp(-2 beta h)) whatever its old value.  */
+/* The probability is a 64-bit threshold tau(h) = floor(2^32 P(+1)) and */
+/* the spin is +1 iff u < tau.  Index v = (6 - h)/2 in 0..6.           */
+/* ------------------------------------------------------------------ */
+void oracle_heatbath_thresholds(double T, uint64_t tau[7])
+{
+    double beta = 1.0 / T;
+    for (int v = 0; v < 7; v++) {
+        double h = (double)(6 - 2 * v);
+        tau[v] = (uint64_t)floor(4294967296.0 / (1.0 + exp(-2.0 * beta * h)));
+    }
+}
+
+void oracle_heatbath_half(int Lx, int Ly, int Lz, int S, int R, uint64_t seed, int64_t k, int parity,
+                          double T, const uint8_t *J, uint8_t *sigma, int64_t *dE)
+{
+    geom g = mk(Lx, Ly, Lz);
+    uint64_t tau[7];
+    oracle_heatbath_thresholds(T, tau);
+    uint32_t time = (uint32_t)(2 * k + parity);
+    for (int s = 0; s < S; s++)
+        for (int r = 0; r < R; r++) {
+            const uint8_t *Js = J + (int64_t)s * g.N;
+            uint8_t *sig = sigma + ((int64_t)s * R + r) * g.N;
+            int64_t acc = 0;
+#pragma omp parallel for reduction(+ : acc) schedule(static)
+            for (int64_t i = 0; i < g.N; i++) {
+                if (parity_of(&g, i) != parity) continue;
+                int h = local_field(&g, Js, sig, i);
+                int64_t hidx = i >> 1;
+                uint64_t u = draw(seed, (uint32_t)(hidx >> 2), time, (uint32_t)r,
+                                  (uint32_t)(STREAM_HEATBATH << 24) | (uint32_t)s, (int)(hidx & 3));
+                int s_new = (u < tau[(6 - h) / 2]) ? +1 : -1;
+                int s_old = spin(sig[i]);
+                if (s_new != s_old) {
+                    acc += 2 * s_old * h;
+                    sig[i] = (uint8_t)(s_new < 0);
+                }
+            }
+            dE[(int64_t)s * R + r] += acc;
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* Observables                                                          */
+/* ------------------------------------------------------------------ */
+/* H^EA = - sum over bonds J_xy s_x s_y (eq. Hamiltonian), each bond once
+   as the forward bond of its lower-coordinate end. */
+void oracle_energy(int Lx, int Ly, int Lz, int S, int R, const uint8_t *J, const uint8_t *sigma,
+                   int64_t *E)
+{
+    geom g = mk(Lx, Ly, Lz);
+    for (int s = 0; s < S; s++)
+        for (int r = 0; r < R; r++) {
+            const uint8_t *Js = J + (int64_t)s * g.N;
+            const uint8_t *sig = sigma + ((int64_t)s * R + r) * g.N;
+            int64_t H = 0;
+            for (int64_t i = 0; i < g.N; i++) {
+                int x, y, z;
+                coords(&g, i, &x, &y, &z);
+                int64_t fwd[3] = {site(&g, x + 1, y, z), site(&g, x, y + 1, z), site(&g, x, y, z + 1)};
+                for (int mu = 0; mu < 3; mu++)
+                    H -= coupling(Js[i], mu) * spin(sig[i]) * spin(sig[fwd[mu]]);
+            }
+            E[(int64_t)s * R + r] = H;
+        }
+}
+
+/* H^aux = sum_x n_x (eq. H-total, gamma = 1). */
+void oracle_daemon_energy(int64_t N, int L, const uint8_t *m, int64_t *D)
+{
+    for (int l = 0; l < L; l++) {
+        int64_t sum = 0;
+        for (int64_t i = 0; i < N; i++) sum += 4 * (int64_t)m[(int64_t)l * N + i];
+        D[l] = sum;
+    }
+}
+
+/* Q_ab = sum_x s^a_x s^b_x (replica overlap, q = Q/N, App. C). */
+void oracle_overlap(int64_t N, int S, int R, int a, int b, const uint8_t *sigma, int64_t *Q)
+{
+    for (int s = 0; s < S; s++) {
+        const uint8_t *sa = sigma + ((int64_t)s * R + a) * N;
+        const uint8_t *sb = sigma + ((int64_t)s * R + b) * N;
+        int64_t q = 0;
+        for (int64_t i = 0; i < N; i++) q += spin(sa[i]) * spin(sb[i]);
+        Q[s] = q;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Schedule (Sec. 2.7, Sec. 2.8): when the daemons are refreshed and at */
+/* which temperature.                                                  */
+/*   period P >= 1 : refresh before sweep k iff k mod P == 0           */
+/*   period P == 0 : logarithmic schedule of the procedure in Sec.     */
+/*                   2.8.1 (refresh, 2^s steps, refresh, ...), i.e.    */
+/*                   before sweep k iff k + 1 is a power of two        */
+/* Temperature of refresh rho: CONST T0; LINEAR T0 -> T1 over the      */
+/* refreshes that fall in [0, n_sweeps); TABLE table[rho].             */
+/* ------------------------------------------------------------------ */
+enum { SCHED_CONST = 0, SCHED_LINEAR = 1, SCHED_TABLE = 2 };
+
+int oracle_is_refresh(int64_t k, int P)
+{
+    if (P >= 1) return k % P == 0;
+    return ((k + 1) & k) == 0;
+}
+
+int64_t oracle_refresh_index(int64_t k, int P)
+{
+    if (P >= 1) return k / P;
+    int64_t rho = -1;
+    for (int64_t t = k + 1; t > 0; t >>= 1) rho++;
+    return rho;
+}
+
+int64_t oracle_refresh_count(int64_t n_sweeps, int P)
+{
+    if (n_sweeps <= 0) return 0;
+    return oracle_refresh_index(n_sweeps - 1, P) + 1;
+}
+
+double oracle_temperature(int kind, double T0, double T1, int64_t n_sweeps, int P,
+                          const double *table, int64_t table_len, int64_t rho)
+{
+    if (kind == SCHED_CONST) return T0;
+    if (kind == SCHED_LINEAR) {
+        int64_t Rtot = oracle_refresh_count(n_sweeps, P);
+        if (Rtot <= 1) return T0;
+        double f = (double)rho / (double)(Rtot - 1);
+        return T0 * (1.0 - f) + T1 * f;
+    }
+    if (kind == SCHED_TABLE && rho >= 0 && rho < table_len) return table[rho];
+    return NAN;
+}
+
+/* ------------------------------------------------------------------ */
+/* Driver: sweeps k0 .. k0+n-1 of one algorithm on the state in place. */
+/* A sweep is the even half followed by the odd half (Sec. 2.8).  For  */
+/* MicSA the daemons are refreshed before sweep k when k is a refresh  */
+/* point; the heat bath uses the temperature of the last refresh point */
+/* at or before k.  After every `stride` sweeps the from-scratch H^EA  */
+/* and H^aux of every lattice are logged.  dE accumulates the tally.   */
+/* ------------------------------------------------------------------ */
+enum { ALGO_MICSA = 0, ALGO_HEATBATH = 1 };
+
+int oracle_run(int Lx, int Ly, int Lz, int S, int R, uint64_t seed, int algo, int kind, double T0,
+               double T1, int64_t n_sweeps, int P, const double *table, int64_t table_len, int64_t k0,
+               int64_t n, int64_t stride, const uint8_t *J, uint8_t *sigma, uint8_t *m, int64_t *dE,
+               int64_t *E_log, int64_t *D_log)
+{
+    int64_t N = (int64_t)Lx * Ly * Lz;
+    int L = S * R;
+    int64_t row = 0;
+    for (int64_t k = k0; k < k0 + n; k++) {
+        int64_t rho = oracle_refresh_index(k, P);
+        double T = oracle_temperature(kind, T0, T1, n_sweeps, P, table, table_len, rho);
+        if (!(T > 0.0) || isinf(T)) return -1;
+        if (algo == ALGO_MICSA) {
+            if (oracle_is_refresh(k, P)) oracle_refresh(Lx, Ly, Lz, S, R, seed, rho, T, m);
+            oracle_micsa_half(Lx, Ly, Lz, S, R, 0, J, sigma, m, dE);
+            oracle_micsa_half(Lx, Ly, Lz, S, R, 1, J, sigma, m, dE);
+        } else if (algo == ALGO_HEATBATH) {
+            oracle_heatbath_half(Lx, Ly, Lz, S, R, seed, k, 0, T, J, sigma, dE);
+            oracle_heatbath_half(Lx, Ly, Lz, S, R, seed, k, 1, T, J, sigma, dE);
+        } else {
+            return -1;
+        }
+        if (stride > 0 && (k - k0 + 1) % stride == 0) {
+            if (E_log) oracle_energy(Lx, Ly, Lz, S, R, J, sigma, E_log + row * L);
+            if (D_log) oracle_daemon_energy(N, L, m, D_log + row * L);
+            row++;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Brute force: density of states g(H) of one sample by enumerating   */
+/* all 2^N spin configurations (N <= 32), walking them in Gray-code   */
+/* order so that consecutive states differ by one spin and H changes  */
+/* by that spin's dH.  g has 3N+1 entries indexed by (H + 3N) / 2.    */
+/* ------------------------------------------------------------------ */
+int oracle_density_of_states(int Lx, int Ly, int Lz, const uint8_t *J, uint64_t *g)
+{
+    geom gm = mk(Lx, Ly, Lz);
+    int N = (int)gm.N;
+    if (N > 32 || N < 1) return -1;
+    memset(g, 0, sizeof(uint64_t) * (size_t)(3 * N + 1));
+    int split = N > 12 ? 8 : 0; /* top `split` bits are enumerated in parallel */
+    int64_t chunks = (int64_t)1 << split;
+    int low = N - split;
+#pragma omp parallel
+    {
+        uint64_t *gl = calloc((size_t)(3 * N + 1), sizeof(uint64_t));
+        uint8_t sig[32];
+#pragma omp for schedule(dynamic)
+        for (int64_t c = 0; c < chunks; c++) {
+            for (int b = 0; b < N; b++) sig[b] = 0;
+            for (int b = 0; b < split; b++) sig[low + b] = (uint8_t)((c >> b) & 1);
+            int64_t H = 0;
+            int64_t Ei[1];
+            oracle_energy(Lx, Ly, Lz, 1, 1, J, sig, Ei);
+            H = Ei[0];
+            gl[(H + 3 * N) / 2]++;
+            uint64_t nstates = (uint64_t)1 << low;
+            for (uint64_t t = 1; t < nstates; t++) {
+                int b = __builtin_ctzll(t); /* Gray code: flip bit b */
+                int dH = 2 * spin(sig[b]) * local_field(&gm, J, sig, b);
+                sig[b] ^= 1u;
+                H += dH;
+                gl[(H + 3 * N) / 2]++;
+            }
+        }
+#pragma omp critical
+        for (int e = 0; e <= 3 * N; e++) g[e] += gl[e];
+        free(gl);
+    }
+    return 0;
+}
+
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -1,0 +1,264 @@
+"""TEST INFRASTRUCTURE ONLY: Python face of the CPU oracle (oracle.c).
+
+Only tests/, the smoke check and the benchmark's CPU-baseline leg use this
+module.  The product library never imports it.  It wraps the plain C oracle
+with ctypes and numpy and adds nothing to the arithmetic: every number
+comes from oracle.c, which follows the paper (arXiv 2506.16240) step by step.
+
+Arrays are in the oracle's natural order (site i = x + Lx*(y + Ly*z)):
+  J[S, N]        bits 0..2 = forward-bond coupling bits j (J = 1 - 2j)
+  sigma[S, R, N] spin bits (s = 1 - 2 sigma)
+  m[S, R, N]     daemon levels (n = 4m)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "oracle.c")
+
+ALGO_MICSA, ALGO_HEATBATH = 0, 1
+SCHED_CONST, SCHED_LINEAR, SCHED_TABLE = 0, 1, 2
+REFRESH_LOG2 = 0
+
+_u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so (gcc, OpenMP, no FMA contraction)."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call([
+            "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+            "-Wall", "-Wextra", "-o", tmp, SRC_PATH, "-lm",
+        ])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        c = ctypes
+        L.oracle_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.oracle_init_couplings.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64, _u8p]
+        L.oracle_init_spins.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64, _u8p]
+        L.oracle_daemon_thresholds.argtypes = [c.c_double, _u64p]
+        L.oracle_heatbath_thresholds.argtypes = [c.c_double, _u64p]
+        L.oracle_refresh.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
+                                     c.c_int64, c.c_double, _u8p]
+        L.oracle_micsa_half.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int,
+                                        _u8p, _u8p, _u8p, _i64p]
+        L.oracle_micsa_site.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int64, _u8p, _u8p, _u8p]
+        L.oracle_micsa_site.restype = c.c_int
+        L.oracle_heatbath_half.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
+                                           c.c_int64, c.c_int, c.c_double, _u8p, _u8p, _i64p]
+        L.oracle_energy.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, _u8p, _u8p, _i64p]
+        L.oracle_daemon_energy.argtypes = [c.c_int64, c.c_int, _u8p, _i64p]
+        L.oracle_overlap.argtypes = [c.c_int64, c.c_int, c.c_int, c.c_int, c.c_int, _u8p, _i64p]
+        L.oracle_is_refresh.argtypes = [c.c_int64, c.c_int]
+        L.oracle_is_refresh.restype = c.c_int
+        L.oracle_refresh_index.argtypes = [c.c_int64, c.c_int]
+        L.oracle_refresh_index.restype = c.c_int64
+        L.oracle_refresh_count.argtypes = [c.c_int64, c.c_int]
+        L.oracle_refresh_count.restype = c.c_int64
+        L.oracle_temperature.argtypes = [c.c_int, c.c_double, c.c_double, c.c_int64, c.c_int,
+                                         c.c_void_p, c.c_int64, c.c_int64]
+        L.oracle_temperature.restype = c.c_double
+        L.oracle_run.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64, c.c_int,
+                                 c.c_int, c.c_double, c.c_double, c.c_int64, c.c_int, c.c_void_p,
+                                 c.c_int64, c.c_int64, c.c_int64, c.c_int64, _u8p, _u8p, _u8p, _i64p,
+                                 c.c_void_p, c.c_void_p]
+        L.oracle_run.restype = c.c_int
+        L.oracle_density_of_states.argtypes = [c.c_int, c.c_int, c.c_int, _u8p, _u64p]
+        L.oracle_density_of_states.restype = c.c_int
+        L.oracle_threads.restype = c.c_int
+        L.oracle_set_threads.argtypes = [c.c_int]
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------- scalars
+def philox(ctr, key) -> np.ndarray:
+    out = np.zeros(4, np.uint32)
+    lib().oracle_philox4x32_10(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), out)
+    return out
+
+
+def daemon_thresholds(T: float) -> np.ndarray:
+    t = np.zeros(3, np.uint64)
+    lib().oracle_daemon_thresholds(float(T), t)
+    return t
+
+
+def heatbath_thresholds(T: float) -> np.ndarray:
+    t = np.zeros(7, np.uint64)
+    lib().oracle_heatbath_thresholds(float(T), t)
+    return t
+
+
+def threads() -> int:
+    return int(lib().oracle_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().oracle_set_threads(int(n))
+
+
+@dataclass
+class Schedule:
+    """Temperature and refresh schedule (kind CONST / LINEAR / TABLE)."""
+    kind: int = SCHED_CONST
+    T0: float = 1.0
+    T1: float = 1.0
+    n_sweeps: int = 1
+    period: int = 10          # >= 1: every `period` sweeps; 0: logarithmic
+    table: np.ndarray | None = None
+
+    def _table_args(self):
+        if self.table is None:
+            return None, 0
+        t = np.ascontiguousarray(self.table, dtype=np.float64)
+        return t, len(t)
+
+    def temperature(self, rho: int) -> float:
+        t, n = self._table_args()
+        ptr = t.ctypes.data if t is not None else None
+        return float(lib().oracle_temperature(self.kind, self.T0, self.T1, self.n_sweeps, self.period,
+                                              ptr, n, int(rho)))
+
+    def is_refresh(self, k: int) -> bool:
+        return bool(lib().oracle_is_refresh(int(k), self.period))
+
+    def refresh_index(self, k: int) -> int:
+        return int(lib().oracle_refresh_index(int(k), self.period))
+
+    def refresh_count(self) -> int:
+        return int(lib().oracle_refresh_count(self.n_sweeps, self.period))
+
+
+@dataclass
+class Lattice:
+    """S samples x R replicas of an Lx x Ly x Lz periodic lattice, on the CPU."""
+    Lx: int
+    Ly: int
+    Lz: int
+    S: int = 1
+    R: int = 1
+    seed: int = 0
+    J: np.ndarray = field(init=False)
+    sigma: np.ndarray = field(init=False)
+    m: np.ndarray = field(init=False)
+    tally: np.ndarray = field(init=False)
+    k: int = field(init=False, default=0)
+
+    def __post_init__(self):
+        for L in (self.Lx, self.Ly, self.Lz):
+            if L < 2 or L % 2:
+                raise ValueError("every side must be even and >= 2 (checkerboard, Sec. 2.1)")
+        self.N = self.Lx * self.Ly * self.Lz
+        self.J = np.zeros((self.S, self.N), np.uint8)
+        self.sigma = np.zeros((self.S, self.R, self.N), np.uint8)
+        self.m = np.zeros((self.S, self.R, self.N), np.uint8)
+        d = self._dims()
+        lib().oracle_init_couplings(*d[:4], self.seed, self.J)
+        lib().oracle_init_spins(*d, self.seed, self.sigma)
+        self.tally = self.energy()
+
+    def _dims(self):
+        return (self.Lx, self.Ly, self.Lz, self.S, self.R)
+
+    # -- single steps ---------------------------------------------------
+    def refresh(self, rho: int, T: float) -> None:
+        lib().oracle_refresh(*self._dims(), self.seed, int(rho), float(T), self.m)
+
+    def micsa_half(self, parity: int) -> None:
+        dE = np.zeros(self.S * self.R, np.int64)
+        lib().oracle_micsa_half(*self._dims(), int(parity), self.J, self.sigma, self.m, dE)
+        self.tally += dE
+
+    def micsa_site(self, s: int, r: int, i: int) -> int:
+        """One elementary move on site i of lattice (s, r); returns dH (0 if rejected)."""
+        sig = np.ascontiguousarray(self.sigma[s, r])
+        m = np.ascontiguousarray(self.m[s, r])
+        dH = int(lib().oracle_micsa_site(self.Lx, self.Ly, self.Lz, int(i), np.ascontiguousarray(self.J[s]),
+                                         sig, m))
+        self.sigma[s, r] = sig
+        self.m[s, r] = m
+        self.tally[s * self.R + r] += dH
+        return dH
+
+    def heatbath_half(self, k: int, parity: int, T: float) -> None:
+        dE = np.zeros(self.S * self.R, np.int64)
+        lib().oracle_heatbath_half(*self._dims(), self.seed, int(k), int(parity), float(T), self.J,
+                                   self.sigma, dE)
+        self.tally += dE
+
+    # -- observables ----------------------------------------------------
+    def energy(self) -> np.ndarray:
+        E = np.zeros(self.S * self.R, np.int64)
+        lib().oracle_energy(*self._dims(), self.J, self.sigma, E)
+        return E
+
+    def daemon_energy(self) -> np.ndarray:
+        D = np.zeros(self.S * self.R, np.int64)
+        lib().oracle_daemon_energy(self.N, self.S * self.R, self.m, D)
+        return D
+
+    def overlap(self, a: int, b: int) -> np.ndarray:
+        Q = np.zeros(self.S, np.int64)
+        lib().oracle_overlap(self.N, self.S, self.R, int(a), int(b), self.sigma, Q)
+        return Q
+
+    # -- driver ---------------------------------------------------------
+    def run(self, algo: int, sched: Schedule, n: int, stride: int = 0):
+        """Sweeps k .. k+n-1; returns (E_log, D_log), each [n//stride, S*R]."""
+        Lc = self.S * self.R
+        rows = n // stride if stride > 0 else 0
+        E_log = np.zeros((max(rows, 1), Lc), np.int64)
+        D_log = np.zeros((max(rows, 1), Lc), np.int64)
+        dE = np.zeros(Lc, np.int64)
+        t, tn = sched._table_args()
+        rc = lib().oracle_run(*self._dims(), self.seed, int(algo), sched.kind, sched.T0, sched.T1,
+                              sched.n_sweeps, sched.period, t.ctypes.data if t is not None else None, tn,
+                              self.k, int(n), int(stride), self.J, self.sigma, self.m, dE,
+                              E_log.ctypes.data, D_log.ctypes.data)
+        if rc != 0:
+            raise ValueError("oracle_run rejected the schedule (non-positive or missing temperature)")
+        self.tally += dE
+        self.k += int(n)
+        return E_log[:rows], D_log[:rows]
+
+
+def density_of_states(Lx: int, Ly: int, Lz: int, J: np.ndarray) -> np.ndarray:
+    """Exact g(H) (uint64 counts, index (H + 3N)/2) of one sample by enumeration."""
+    N = Lx * Ly * Lz
+    g = np.zeros(3 * N + 1, np.uint64)
+    rc = lib().oracle_density_of_states(Lx, Ly, Lz, np.ascontiguousarray(J, np.uint8), g)
+    if rc != 0:
+        raise ValueError("enumeration needs N <= 32")
+    return g
+
+
+def canonical_mean_energy(g: np.ndarray, N: int, T: float) -> float:
+    """<H>_beta = sum_H H g(H) e^{-beta H} / sum_H g(H) e^{-beta H} (eq. canonical)."""
+    H = -3 * N + 2 * np.arange(len(g), dtype=np.float64)
+    beta = 1.0 / T
+    w = g.astype(np.float64) * np.exp(-beta * (H - H.min()))
+    return float((H * w).sum() / w.sum())

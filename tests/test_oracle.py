@@ -1,0 +1,448 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+None of these tests retypes an oracle formula: each checks the oracle
+against an independent fact -- published known-answer vectors, an
+independent library implementation, the Hamiltonian recomputed from
+scratch, symmetries, closed forms printed in the paper (eqs.
+prob-daemons-walkers and daemons-temperature), exact invariants of the
+Creutz move (Sec. 2.3), and exact enumeration of tiny lattices.
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ------------------------------------------------------------------ Philox
+def test_philox_known_answer_vectors():
+    rows = []
+    with open(os.path.join(HERE, "golden", "philox4x32_10_kat.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append([int(t, 16) for t in line.split()])
+    assert len(rows) == 3
+    for r in rows:
+        out = O.philox(r[0:4], r[4:6])
+        assert [int(v) for v in out] == r[6:10]
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None, reason="needs hipcc to build the rocRAND host check")
+def test_philox_matches_rocrand_host(tmp_path):
+    """rocRAND's philox4x32_10 engine (an independent implementation) on the host.
+    Its counter is (offset/4, subsequence) and its key the 64-bit seed."""
+    rng = np.random.default_rng(7)
+    cases = [(int(rng.integers(0, 2**32)), int(rng.integers(0, 2**30)), int(rng.integers(0, 2**32)),
+              int(rng.integers(0, 2**32)), int(rng.integers(0, 2**64, dtype=np.uint64))) for _ in range(64)]
+    src = tmp_path / "rr.cpp"
+    lines = ["#include <rocrand/rocrand_philox4x32_10.h>", "#include <cstdio>", "int main(){"]
+    for (c0, c1, c2, c3, seed) in cases:
+        off = ((c1 << 32) | c0) * 4
+        sub = (c3 << 32) | c2
+        lines.append(f"{{ rocrand_device::philox4x32_10_engine e({seed}ull, {sub}ull, {off}ull);"
+                     f" uint4 r = e.next4(); printf(\"%u %u %u %u\\n\", r.x, r.y, r.z, r.w); }}")
+    lines.append("return 0; }")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "rr"
+    subprocess.check_call(["hipcc", "-O1", "-o", str(exe), str(src)])
+    got = subprocess.check_output([str(exe)]).decode().split("\n")
+    for (c0, c1, c2, c3, seed), line in zip(cases, got):
+        want = [int(t) for t in line.split()]
+        out = O.philox([c0, c1, c2, c3], [seed & 0xFFFFFFFF, seed >> 32])
+        assert [int(v) for v in out] == want
+
+
+# ------------------------------------------------------------ Hamiltonian
+def _lat(Lx=6, Ly=4, Lz=8, S=2, R=3, seed=11):
+    return O.Lattice(Lx, Ly, Lz, S, R, seed)
+
+
+def _coords(L):
+    i = np.arange(L.N)
+    return i % L.Lx, (i // L.Lx) % L.Ly, i // (L.Lx * L.Ly)
+
+
+def test_energy_ground_states_and_symmetries():
+    L = _lat()
+    x, y, z = _coords(L)
+    par = ((x + y + z) & 1).astype(np.uint8)
+    N = L.N
+    # ferromagnet (all J=+1) all up: every bond satisfied, H = -3N
+    L.J[:] = 0
+    L.sigma[:] = 0
+    assert (L.energy() == -3 * N).all()
+    # ferromagnet, checkerboard spins: every bond frustrated, H = +3N
+    L.sigma[:] = par
+    assert (L.energy() == 3 * N).all()
+    # antiferromagnet (all J=-1) checkerboard: H = -3N
+    L.J[:] = 7
+    assert (L.energy() == -3 * N).all()
+    # random state: global spin flip leaves H unchanged
+    L2 = _lat(seed=5)
+    E = L2.energy()
+    L2.sigma ^= 1
+    assert (L2.energy() == E).all()
+    assert np.abs(E).max() <= 3 * N and (E % 2 == (3 * N) % 2).all()
+
+
+def test_energy_gauge_invariance():
+    """Flipping s_x together with the six couplings of x leaves H unchanged;
+    a wrong neighbour index or bond slot in the energy breaks this."""
+    L = _lat(seed=3)
+    E0 = L.energy()
+    rng = np.random.default_rng(0)
+    for _ in range(25):
+        i = int(rng.integers(L.N))
+        x, y, z = i % L.Lx, (i // L.Lx) % L.Ly, i // (L.Lx * L.Ly)
+        idx = lambda a, b, c: (a % L.Lx) + L.Lx * ((b % L.Ly) + L.Ly * (c % L.Lz))
+        L.sigma[:, :, i] ^= 1
+        L.J[:, i] ^= 7
+        L.J[:, idx(x - 1, y, z)] ^= 1
+        L.J[:, idx(x, y - 1, z)] ^= 2
+        L.J[:, idx(x, y, z - 1)] ^= 4
+        assert (L.energy() == E0).all()
+
+
+def test_local_move_matches_hamiltonian_difference():
+    """Every even site's accept/reject after one half sweep agrees with eq. flip-OK,
+    0 <= n - dH <= 12, where dH is the difference of two from-scratch energies."""
+    rng = np.random.default_rng(1)
+    L = O.Lattice(6, 6, 6, 1, 1, seed=21)
+    seen = set()
+    for trial in range(30):
+        L.sigma[:] = rng.integers(0, 2, L.sigma.shape, dtype=np.uint8)
+        L.J[:] = rng.integers(0, 8, L.J.shape, dtype=np.uint8)
+        L.m[:] = rng.integers(0, 4, L.m.shape, dtype=np.uint8)
+        x, y, z = _coords(L)
+        even = np.nonzero(((x + y + z) & 1) == 0)[0]
+        E0 = int(L.energy()[0])
+        dH = np.zeros(L.N, np.int64)
+        for i in even:
+            L.sigma[0, 0, i] ^= 1
+            dH[i] = int(L.energy()[0]) - E0
+            L.sigma[0, 0, i] ^= 1
+        s0, m0 = L.sigma.copy(), L.m.copy()
+        L.tally = np.array([E0], np.int64)
+        L.micsa_half(0)
+        for i in even:
+            n = 4 * int(m0[0, 0, i])
+            legal = 0 <= n - dH[i] <= 12
+            flipped = L.sigma[0, 0, i] != s0[0, 0, i]
+            assert flipped == legal
+            assert 4 * int(L.m[0, 0, i]) == (n - dH[i] if legal else n)
+            seen.add((int(dH[i]), int(m0[0, 0, i])))
+        odd = np.nonzero(((x + y + z) & 1) == 1)[0]
+        assert (L.sigma[0, 0, odd] == s0[0, 0, odd]).all() and (L.m[0, 0, odd] == m0[0, 0, odd]).all()
+        assert L.tally[0] == L.energy()[0]
+    # dH takes the values 0, +-4, +-8, +-12 (Sec. 2.4); all 7 x 4 cases were exercised
+    assert {d for d, _ in seen} == {-12, -8, -4, 0, 4, 8, 12}
+    assert len(seen) == 28
+
+
+# ----------------------------------------------------------- MicSA invariants
+def test_conservation_and_tally_between_refreshes():
+    """H^EA + H^aux is exactly constant across every half sweep (Sec. 2.3) and
+    the incremental tally equals the from-scratch energy."""
+    L = _lat(6, 4, 8, 2, 2, seed=9)
+    sched = O.Schedule(O.SCHED_CONST, 0.9, 0.9, 100, 7)
+    for k in range(40):
+        if sched.is_refresh(k):
+            L.refresh(sched.refresh_index(k), 0.9)
+        tot = L.energy() + L.daemon_energy()
+        for p in (0, 1):
+            L.micsa_half(p)
+            assert (L.energy() + L.daemon_energy() == tot).all()
+            assert (L.tally == L.energy()).all()
+    assert (L.m <= 3).all()
+
+
+def test_half_sweep_is_an_involution():
+    """Applying the same half sweep twice restores spins and daemons (Sec. 2.3),
+    so odd-then-even undoes a full sweep."""
+    L = _lat(8, 6, 4, 1, 2, seed=4)
+    L.refresh(0, 1.3)
+    for _ in range(5):
+        L.micsa_half(0)
+        L.micsa_half(1)
+    s0, m0 = L.sigma.copy(), L.m.copy()
+    L.micsa_half(0)
+    L.micsa_half(1)
+    assert not np.array_equal(L.sigma, s0)
+    L.micsa_half(1)
+    L.micsa_half(0)
+    assert np.array_equal(L.sigma, s0) and np.array_equal(L.m, m0)
+
+
+def test_site_order_within_a_half_is_immaterial():
+    """Separability (Sec. 2.3): a shuffled serial visit of the even sites gives the
+    same state as the half sweep."""
+    A = O.Lattice(6, 4, 6, 1, 1, seed=13)
+    A.refresh(0, 1.1)
+    B = O.Lattice(6, 4, 6, 1, 1, seed=13)
+    B.m[:] = A.m
+    x, y, z = _coords(A)
+    even = np.nonzero(((x + y + z) & 1) == 0)[0]
+    np.random.default_rng(2).shuffle(even)
+    A.micsa_half(0)
+    for i in even:
+        B.micsa_site(0, 0, int(i))
+    assert np.array_equal(A.sigma, B.sigma) and np.array_equal(A.m, B.m)
+    assert A.tally[0] == B.tally[0]
+
+
+# --------------------------------------------------------------- daemons
+@pytest.mark.parametrize("T", [0.2, 0.7, 1.1, 1.5, 3.0, 50.0])
+def test_daemon_thresholds_reproduce_eq_prob_daemons(T):
+    t = O.daemon_thresholds(T).astype(np.float64)
+    edges = np.concatenate([[0.0], t, [2.0**32]])
+    p_thr = np.diff(edges) / 2.0**32
+    b = 1.0 / T
+    p_paper = np.array([math.exp(-4 * m * b) * (1 - math.exp(-4 * b)) / (1 - math.exp(-16 * b))
+                        for m in range(4)])
+    assert np.all(np.diff(edges) >= 0)
+    assert np.abs(p_thr - p_paper).max() <= 2.0**-31
+    # mean daemon energy of the sampler vs eq. daemons-temperature
+    mean_thr = float((4 * np.arange(4) * p_thr).sum())
+    mean_paper = 4 * math.exp(-4 * b) / (1 - math.exp(-4 * b)) - 16 * math.exp(-16 * b) / (1 - math.exp(-16 * b))
+    assert abs(mean_thr - mean_paper) <= 1e-8 * max(1.0, mean_paper)
+
+
+def test_daemon_thresholds_limits():
+    # T -> 0: every daemon empty, exactly (threshold 2^32 not representable in u32)
+    for T in (0.1, 0.05, 1e-3):
+        assert list(O.daemon_thresholds(T)) == [2**32] * 3
+    # T -> infinity: uniform over {0,1,2,3}
+    t = O.daemon_thresholds(1e12)
+    for k in range(3):
+        assert abs(int(t[k]) - (k + 1) * 2**30) <= 2
+
+
+@pytest.mark.parametrize("T", [0.7, 1.5, 3.0])
+def test_refresh_histogram_chi2(T):
+    """The refreshed daemons follow eq. prob-daemons-walkers (chi^2, 3 dof)."""
+    L = O.Lattice(32, 32, 32, 2, 2, seed=77)
+    L.refresh(5, T)
+    counts = np.bincount(L.m.ravel(), minlength=4).astype(float)
+    n = counts.sum()
+    b = 1.0 / T
+    p = np.array([math.exp(-4 * m * b) * (1 - math.exp(-4 * b)) / (1 - math.exp(-16 * b)) for m in range(4)])
+    chi2 = float(((counts - n * p) ** 2 / (n * p)).sum())
+    assert chi2 < 21.1  # p = 1e-4 for 3 dof
+    # a different refresh index gives an independent draw: P(differ) = 1 - sum p^2
+    m_prev = L.m.copy()
+    L.refresh(6, T)
+    q = 1.0 - float((p ** 2).sum())
+    assert abs((L.m != m_prev).mean() - q) <= 5 * math.sqrt(q * (1 - q) / n) + 1e-12
+
+
+def test_acceptance_probability_with_fresh_daemons():
+    """With a refresh before every sweep each move sees a fresh daemon, so the
+    flip probability of a site with dH is A = sum_m p(m) [0 <= 4m - dH <= 12]."""
+    T = 1.2
+    b = 1.0 / T
+    p = np.array([math.exp(-4 * m * b) * (1 - math.exp(-4 * b)) / (1 - math.exp(-16 * b)) for m in range(4)])
+    L = O.Lattice(16, 16, 16, 1, 2, seed=5)
+    x, y, z = _coords(L)
+    even = ((x + y + z) & 1) == 0
+    tries = np.zeros(7)
+    flips = np.zeros(7)
+    for rho in range(12):
+        L.refresh(rho, T)
+        s0 = L.sigma.copy()
+        # dH per even site from two from-scratch energies is too slow here; use
+        # the count of unsatisfied bonds through the energy of single flips on a copy
+        h = np.zeros_like(L.sigma, dtype=np.int64)
+        for r in range(L.R):
+            sig = L.sigma[0, r].astype(np.int64)
+            s = 1 - 2 * sig
+            J = L.J[0]
+            Jx, Jy, Jz = [1 - 2 * ((J >> mu) & 1).astype(np.int64) for mu in range(3)]
+            s3 = s.reshape(L.Lz, L.Ly, L.Lx)
+            Jx3, Jy3, Jz3 = Jx.reshape(s3.shape), Jy.reshape(s3.shape), Jz.reshape(s3.shape)
+            hf = (Jx3 * np.roll(s3, -1, 2) + np.roll(Jx3 * s3, 1, 2) + Jy3 * np.roll(s3, -1, 1)
+                  + np.roll(Jy3 * s3, 1, 1) + Jz3 * np.roll(s3, -1, 0) + np.roll(Jz3 * s3, 1, 0))
+            h[0, r] = (s3 * hf).ravel() * 2  # dH = 2 s h
+        L.micsa_half(0)
+        dH = h[0][:, even]
+        flipped = (L.sigma[0][:, even] != s0[0][:, even])
+        for c, d in enumerate(range(-12, 13, 4)):
+            sel = dH == d
+            tries[c] += sel.sum()
+            flips[c] += flipped[sel].sum()
+        L.micsa_half(1)
+    for c, d in enumerate(range(-12, 13, 4)):
+        A = sum(p[m] for m in range(4) if 0 <= 4 * m - d <= 12)
+        if tries[c] < 50:
+            continue
+        sd = math.sqrt(max(A * (1 - A), 1e-12) / tries[c])
+        assert abs(flips[c] / tries[c] - A) <= 5 * sd + 1e-12, (d, flips[c] / tries[c], A)
+
+
+# ------------------------------------------------------------- heat bath
+def test_heatbath_thresholds_symmetry_and_limits():
+    for T in (0.2, 0.7, 1.5, 3.0, 10.0):
+        tau = [int(v) for v in O.heatbath_thresholds(T)]
+        assert tau[3] == 2**31
+        assert all(tau[v] >= tau[v + 1] for v in range(6))
+        for v in range(7):
+            assert tau[v] + tau[6 - v] in (2**32 - 1, 2**32)
+    tau = [int(v) for v in O.heatbath_thresholds(0.01)]
+    assert tau[:3] == [2**32] * 3 and tau[4:] == [0] * 3
+
+
+def test_heatbath_conditional_probability():
+    """Fraction of sites set to +1 given the local field h equals 1/(1+e^{-2 beta h})."""
+    T = 1.3
+    L = O.Lattice(16, 16, 16, 1, 2, seed=8)
+    ups = np.zeros(7)
+    tot = np.zeros(7)
+    x, y, z = _coords(L)
+    for k in range(8):
+        for p in (0, 1):
+            par = ((x + y + z) & 1) == p
+            hs = []
+            for r in range(L.R):
+                s3 = (1 - 2 * L.sigma[0, r].astype(np.int64)).reshape(L.Lz, L.Ly, L.Lx)
+                Jb = [(1 - 2 * ((L.J[0] >> mu) & 1).astype(np.int64)).reshape(s3.shape) for mu in range(3)]
+                hf = (Jb[0] * np.roll(s3, -1, 2) + np.roll(Jb[0] * s3, 1, 2) + Jb[1] * np.roll(s3, -1, 1)
+                      + np.roll(Jb[1] * s3, 1, 1) + Jb[2] * np.roll(s3, -1, 0) + np.roll(Jb[2] * s3, 1, 0))
+                hs.append(hf.ravel())
+            L.heatbath_half(k, p, T)
+            for r in range(L.R):
+                h = hs[r][par]
+                up = L.sigma[0, r][par] == 0
+                for v in range(7):
+                    sel = h == 6 - 2 * v
+                    tot[v] += sel.sum()
+                    ups[v] += up[sel].sum()
+    assert (L.tally == L.energy()).all()
+    for v in range(7):
+        if tot[v] < 100:
+            continue
+        P = 1.0 / (1.0 + math.exp(-2.0 * (6 - 2 * v) / T))
+        sd = math.sqrt(P * (1 - P) / tot[v])
+        assert abs(ups[v] / tot[v] - P) <= 5 * sd + 1e-9
+
+
+# ------------------------------------------------- exact enumeration pins
+def test_density_of_states_against_direct_enumeration():
+    L = O.Lattice(2, 2, 4, 1, 1, seed=31)
+    g = O.density_of_states(2, 2, 4, L.J[0])
+    N = L.N
+    assert int(g.sum()) == 2**N
+    # direct: every configuration through the from-scratch energy
+    cnt = np.zeros(3 * N + 1, np.int64)
+    for c in range(2**N):
+        L.sigma[0, 0] = (c >> np.arange(N)) & 1
+        cnt[(int(L.energy()[0]) + 3 * N) // 2] += 1
+    assert np.array_equal(cnt, g.astype(np.int64))
+    # global flip symmetry: every level has even degeneracy; sum_s H(s) = 0
+    assert (g % 2 == 0).all()
+    H = -3 * N + 2 * np.arange(3 * N + 1)
+    assert int((H * g.astype(np.int64)).sum()) == 0
+
+
+def test_density_of_states_ferromagnet_cube():
+    """2x2x2 with all J = +1: the periodic cube has every edge doubled, so
+    H = -2 sum_edges s s over the 12 edges of a cube; the two ground states
+    have H = -24 and the first excitation (one spin against 3 neighbours)
+    costs 12, giving 16 states at H = -12."""
+    J = np.zeros(8, np.uint8)
+    g = O.density_of_states(2, 2, 2, J)
+    assert int(g[0]) == 2
+    assert int(g[(-12 + 24) // 2]) == 16
+    assert int(g.sum()) == 256
+
+
+def _batch_mean(series, nb=20):
+    b = np.array_split(np.asarray(series, float), nb)
+    means = np.array([x.mean() for x in b])
+    return means.mean(), means.std(ddof=1) / math.sqrt(nb)
+
+
+@pytest.mark.parametrize("shape,T,period", [((2, 2, 2), 1.5, 1), ((2, 2, 4), 1.5, 10), ((2, 2, 4), 3.0, 1),
+                                            ((2, 2, 4), 2.0, 3)])
+def test_equilibrium_energy_matches_enumeration(shape, T, period):
+    """Canonical <H>_beta (eq. canonical) from exact enumeration vs long MicSA and
+    heat-bath runs; MicSA reaches canonical equilibrium through the refreshes
+    (Sec. 2.7)."""
+    Lx, Ly, Lz = shape
+    R = 32
+    L = O.Lattice(Lx, Ly, Lz, 1, R, seed=100 + Lz + period)
+    g = O.density_of_states(Lx, Ly, Lz, L.J[0])
+    exact = O.canonical_mean_energy(g, L.N, T)
+    n = 6000
+    sched = O.Schedule(O.SCHED_CONST, T, T, n, period)
+    for algo in (O.ALGO_MICSA, O.ALGO_HEATBATH):
+        X = O.Lattice(Lx, Ly, Lz, 1, R, seed=100 + Lz + period)
+        E_log, _ = X.run(algo, sched, n, 1)
+        series = E_log[n // 5:].mean(axis=1)
+        mean, err = _batch_mean(series)
+        assert abs(mean - exact) <= 4.5 * err + 1e-9, (algo, mean, exact, err)
+
+
+# -------------------------------------------------------------- schedule
+def test_schedule_semantics():
+    s = O.Schedule(O.SCHED_LINEAR, 3.0, 0.2, 10000, 20)
+    assert s.refresh_count() == 500
+    assert s.temperature(0) == 3.0 and s.temperature(499) == 0.2
+    assert [s.is_refresh(k) for k in (0, 19, 20, 21)] == [True, False, True, False]
+    assert s.refresh_index(39) == 1
+    log = O.Schedule(O.SCHED_CONST, 1.0, 1.0, 100, O.REFRESH_LOG2)
+    # procedure of Sec. 2.8.1: refresh, 2^s steps, refresh, ... -> k = 0, 1, 3, 7, 15, ...
+    assert [k for k in range(40) if log.is_refresh(k)] == [0, 1, 3, 7, 15, 31]
+    assert [log.refresh_index(k) for k in (0, 1, 2, 3, 6, 7)] == [0, 1, 1, 2, 2, 3]
+    assert log.refresh_count() == 7
+    tab = O.Schedule(O.SCHED_TABLE, 0, 0, 30, 10, np.array([2.0, 1.0, 0.5]))
+    assert [tab.temperature(r) for r in range(3)] == [2.0, 1.0, 0.5]
+    assert math.isnan(tab.temperature(3))
+
+
+def test_run_matches_manual_steps():
+    sched = O.Schedule(O.SCHED_LINEAR, 2.0, 0.5, 25, 4)
+    A = O.Lattice(8, 4, 6, 2, 2, seed=99)
+    E_log, D_log = A.run(O.ALGO_MICSA, sched, 25, 5)
+    B = O.Lattice(8, 4, 6, 2, 2, seed=99)
+    rows = []
+    for k in range(25):
+        if sched.is_refresh(k):
+            B.refresh(sched.refresh_index(k), sched.temperature(sched.refresh_index(k)))
+        B.micsa_half(0)
+        B.micsa_half(1)
+        if (k + 1) % 5 == 0:
+            rows.append((B.energy(), B.daemon_energy()))
+    assert np.array_equal(A.sigma, B.sigma) and np.array_equal(A.m, B.m)
+    assert np.array_equal(E_log, np.array([r[0] for r in rows]))
+    assert np.array_equal(D_log, np.array([r[1] for r in rows]))
+    assert (A.tally == A.energy()).all()
+
+
+def test_overlap_pins():
+    L = _lat(6, 4, 4, 2, 3, seed=1)
+    N = L.N
+    L.sigma[:, 1] = L.sigma[:, 0]
+    L.sigma[:, 2] = L.sigma[:, 0] ^ 1
+    assert (L.overlap(0, 1) == N).all() and (L.overlap(0, 2) == -N).all()
+    L2 = _lat(6, 4, 4, 2, 2, seed=2)
+    ham = (L2.sigma[:, 0] != L2.sigma[:, 1]).sum(axis=1)
+    assert np.array_equal(L2.overlap(0, 1), N - 2 * ham)
+
+
+def test_paramagnet_sanity_band():
+    """L = 16 at T = 1.5 (configuration 1 shape): MicSA and heat bath agree on the
+    equilibrium energy, which lies above the T = 1.4 value -1.607 of Table 2."""
+    n = 1500
+    res = {}
+    for algo in (O.ALGO_MICSA, O.ALGO_HEATBATH):
+        L = O.Lattice(16, 16, 16, 1, 4, seed=0x5EED0001)
+        E_log, _ = L.run(algo, O.Schedule(O.SCHED_CONST, 1.5, 1.5, n, 10), n, 1)
+        res[algo] = _batch_mean(E_log[300:].mean(axis=1) / L.N, 10)
+    (m1, e1), (m2, e2) = res[O.ALGO_MICSA], res[O.ALGO_HEATBATH]
+    assert abs(m1 - m2) <= 5 * math.hypot(e1, e2) + 2e-4
+    assert m1 > -1.607 and m2 > -1.607
