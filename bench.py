@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Spin updates/ns of MicSA and of the heat-bath baseline on one MI355X.
+
+Workload (default): the large anneal -- one 512^3 lattice (134M spins) of the
+3D EA +-J model, byte layout, linear schedule T = 3.0 -> 0.2 over 10^4 sweeps,
+daemon refresh every 20 sweeps.  A step is one refresh period: the refresh
+and 20 sweeps (even half + odd half each, with the incremental energy
+tally).  --steps 500 is the whole anneal.  The heat bath runs the same steps
+on a second lattice from the same seed.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+# Algorithmic bytes per spin update (state one sweep must move, byte layout):
+# spin read+write 2 B, daemon read+write 2 B, couplings 3 bits = 0.375 B.
+BYTES_PER_UPDATE = {"micsa": 4.375, "heatbath": 2.375}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2506_16240_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    e = d.get(name)
+    if not e or e.get("kernel_hash") != kernel_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def run_gpu(w, algo_name: str, steps: int, warmup: int, stream):
+    from paper_2506_16240_amd import micsa as M
+    import torch
+
+    algo = M.ALGO_MICSA if algo_name == "micsa" else M.ALGO_HEATBATH
+    sched = M.Schedule(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
+    P = w.period
+    if warmup > 0:
+        with M.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed, stream=stream.cuda_stream) as lw:
+            lw.set_schedule(sched)
+            lw.sweep(algo, warmup * P)
+            lw.sync()
+    lat = M.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed, stream=stream.cuda_stream)
+    lat.set_schedule(sched)
+    lat.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    lat.sweep(algo, steps * P)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    kind = M.TIME_SWEEP if algo == M.ALGO_MICSA else M.TIME_HEATBATH
+    k_ms, k_n = lat.timing(kind)
+    r_ms, r_n = lat.timing(M.TIME_REFRESH)
+    # property that holds at any size: the incremental tally equals the energy
+    E, tally = lat.energy(), lat.energy_tally()
+    ok = bool((E == tally).all())
+    name = lat.kernel_name(algo)
+    lat.close()
+    return {"ms": ms, "kernel_ms": k_ms, "kernel_launches": k_n, "refresh_ms": r_ms, "refresh_launches": r_n,
+            "tally_check": ok, "kernel": name, "E_final": int(E[0])}
+
+
+def cpu_baseline(w, seconds: float):
+    """The CPU oracle on a bounded sample of the same workload (sweep loop only)."""
+    from oracle import oracle as O
+
+    lat = O.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
+    sched = O.Schedule(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
+    sweeps = 0
+    t = time.perf_counter()
+    while True:
+        lat.run(O.ALGO_MICSA, sched, 1, 0)
+        sweeps += 1
+        el = time.perf_counter() - t
+        if el >= seconds or sweeps >= w.n_sweeps:
+            break
+    upd = w.N * w.lattices * sweeps
+    return {"value": round(upd / (el * 1e9), 4), "unit": "spin updates/ns", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": f"MicSA sweeps 0..{sweeps - 1} of {w.name} ({sweeps} x {w.N * w.lattices} updates, "
+                      f"{el:.1f} s, init excluded)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="anneal_L512_T3.0-0.2")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-heatbath", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: every lattice here fits one MI355X and the multi-GPU "
+              "decomposition is not built (run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    from paper_2506_16240_amd import workloads as W
+    import torch
+
+    w = W.ALL[args.workload]
+    steps = args.steps
+    if steps * w.period > w.n_sweeps:
+        print(f"--steps {steps} exceeds the {w.n_sweeps}-sweep schedule", file=sys.stderr)
+        return 2
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    sweeps = steps * w.period
+    updates = w.N * w.lattices * sweeps
+
+    log(f"micsa: {w.name}, {sweeps} sweeps")
+    mi = run_gpu(w, "micsa", steps, args.warmup, stream)
+    log(f"micsa: {mi['ms']:.1f} ms, tally check {mi['tally_check']}")
+    hb = None
+    if not args.no_heatbath:
+        log(f"heatbath: {w.name}, {sweeps} sweeps")
+        hb = run_gpu(w, "heatbath", steps, args.warmup, stream)
+        log(f"heatbath: {hb['ms']:.1f} ms")
+
+    value = updates / (mi["ms"] * 1e6)
+    # dominant kernel: the sweep kernel; each launch updates one parity of every lattice
+    per_launch_updates = updates / (mi["kernel_launches"] / sweeps) / sweeps
+    avg_ms = mi["kernel_ms"] / mi["kernel_launches"]
+    bytes_launch = BYTES_PER_UPDATE["micsa"] * per_launch_updates
+    achieved = bytes_launch / (avg_ms * 1e6)  # GB/s
+    traffic = measured_traffic(mi["kernel"])
+    out = {
+        "metric": "spin updates/ns (MicSA vs heat-bath, 1 GPU) + % of HBM roofline",
+        "value": round(value, 2),
+        "unit": "spin updates/ns",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mi["ms"] / steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": w.name, "L": [w.Lx, w.Ly, w.Lz], "samples": w.S, "replicas": w.R,
+                   "sweeps_per_step": w.period, "sweeps": sweeps, "schedule": f"T {w.T0}->{w.T1}",
+                   "layout": "byte", "kernel": mi["kernel"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": mi["kernel"], "avg_launch_ms": round(avg_ms, 5),
+                     "bytes_per_launch": bytes_launch, "launches": mi["kernel_launches"]},
+        "checks": {"micsa_tally_equals_energy": mi["tally_check"]},
+    }
+    if hb is not None:
+        out["heatbath"] = {"value": round(updates / (hb["ms"] * 1e6), 2), "unit": "spin updates/ns",
+                           "ms_per_step": round(hb["ms"] / steps, 4), "kernel": hb["kernel"]}
+        out["micsa_over_heatbath"] = round(hb["ms"] / mi["ms"], 3)
+        out["checks"]["heatbath_tally_equals_energy"] = hb["tally_check"]
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,184 @@
+/*
+ * micsa.h -- C ABI of libmicsa, microcanonical simulated annealing (MicSA)
+ * for the 3D Edwards-Anderson +-J spin glass on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Bernaschi et al., "Microcanonical simulated annealing: massively
+ * parallel Monte Carlo simulations with sporadic random-number generation",
+ * arXiv 2506.16240.  Section numbers below refer to that paper.
+ *
+ * Model (Sec. 2.1, eq. Hamiltonian): N = Lx*Ly*Lz Ising spins s = +-1 on a
+ * periodic cubic lattice, H = -sum_<xy> J_xy s_x s_y with J = +-1 drawn with
+ * probability 1/2 per bond.  Each site carries one daemon n = 4m, m in 0..3
+ * (Sec. 2.4-2.5).  A MicSA sweep updates the even sublattice, then the odd
+ * one (Sec. 2.8); a site flips iff 0 <= n - dH <= 12 (eq. flip-OK) and its
+ * daemon absorbs the change (eq. Creutz).  Daemons are redrawn from eq.
+ * prob-daemons-walkers only at refresh points (Sec. 2.7).  A heat-bath
+ * sweep (Sec. 2.1) is provided as the random-number-greedy baseline.
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns an int status (enum micsa_status); no call aborts,
+ *    throws or exits.  After a failure micsa_last_error() describes it.
+ *  - Host arrays passed in are owned by the caller and only read or written
+ *    during the call.  Device memory is owned by the context.
+ *  - Site index in all host arrays: i = x + Lx*(y + Ly*z); lattice index
+ *    l = sample*R + replica.  Spin bit sigma (s = 1 - 2 sigma); daemon level
+ *    m (n = 4m); coupling bits j (J = 1 - 2j) of the forward bonds
+ *    (i, i+e_x), (i, i+e_y), (i, i+e_z) in bits 0, 1, 2.
+ *  - Random numbers are Philox4x32-10 keyed by the 64-bit seed with one
+ *    counter per (stream, sample, replica, site, time); results are
+ *    therefore independent of launch shapes, layouts and device count.
+ *  - A context is not thread-safe.  Distinct contexts may run concurrently.
+ */
+#ifndef MICSA_H
+#define MICSA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum micsa_status {
+    MICSA_OK = 0,
+    MICSA_EINVAL = -1, /* invalid argument; nothing was changed */
+    MICSA_ENOMEM = -2, /* device allocation failed; nothing was changed */
+    MICSA_EHIP = -3,   /* a HIP runtime call failed; the context must be destroyed */
+    MICSA_ESTATE = -4, /* call not allowed in the current state (e.g. no schedule) */
+    MICSA_ERANGE = -5  /* sweep index outside the schedule */
+};
+
+enum micsa_layout {
+    MICSA_LAYOUT_BYTE = 0,    /* one byte per spin and per daemon, bit-planes for couplings */
+    MICSA_LAYOUT_BITPLANE = 1 /* multispin coding: 64 samples per 64-bit word (Sec. 2.5, App. B) */
+};
+
+enum micsa_algo {
+    MICSA_ALGO_MICSA = 0,   /* daemon update, Sec. 2.3-2.8 with gamma = 1 */
+    MICSA_ALGO_HEATBATH = 1 /* canonical heat bath, Sec. 2.1 */
+};
+
+enum micsa_sched_kind {
+    MICSA_SCHED_CONST = 0,  /* T = T0 at every refresh */
+    MICSA_SCHED_LINEAR = 1, /* T0 at the first refresh, T1 at the last one in [0, n_sweeps) */
+    MICSA_SCHED_TABLE = 2   /* T = T_table[rho] at refresh rho */
+};
+
+/* refresh_period value selecting the logarithmic refresh schedule of the
+   procedure in Sec. 2.8.1: refresh before sweep k iff k + 1 is a power of two. */
+#define MICSA_REFRESH_LOG2 0
+
+typedef struct micsa_params {
+    int32_t Lx, Ly, Lz;    /* lattice sides: even, Lx % 8 == 0, Lx >= 8, Ly, Lz >= 2 */
+    int32_t n_samples;     /* coupling realisations, 1 .. 2^24 - 1 */
+    int32_t n_replicas;    /* replicas per sample sharing the couplings (Sec. 3), >= 1 */
+    int32_t layout;        /* enum micsa_layout */
+    uint64_t seed;         /* Philox key */
+} micsa_params;
+
+typedef struct micsa_schedule {
+    int32_t kind;           /* enum micsa_sched_kind */
+    int32_t refresh_period; /* >= 1: refresh before sweep k iff k % period == 0; or MICSA_REFRESH_LOG2 */
+    double T0, T1;          /* temperatures (> 0, finite) */
+    int64_t n_sweeps;       /* schedule length; sweeps at k >= n_sweeps fail with ERANGE */
+    const double* T_table;  /* TABLE only: temperature of refresh rho, copied by the call */
+    int64_t T_len;          /* TABLE only: entries in T_table */
+} micsa_schedule;
+
+typedef struct micsa_ctx micsa_ctx;
+
+/* Static description of a status code. */
+const char* micsa_status_string(int status);
+
+/* Text of the last failure on this context ("" if none).  Valid until the
+   next call on the context. */
+const char* micsa_last_error(const micsa_ctx* ctx);
+
+/* Create S x R lattices from the seed (Sec. 3: couplings +-1 with
+   probability 1/2, spins drawn at infinite temperature; daemons start at
+   m = 0 and are drawn at the first refresh point).  hip_stream is a
+   hipStream_t (NULL = the null stream) on which every later call enqueues
+   its work.  On success *out owns all device memory; on failure *out is
+   NULL and nothing is leaked.
+   Errors: EINVAL (bad sides/counts/layout), ENOMEM, EHIP. */
+int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out);
+
+/* Synchronise the stream and free everything.  NULL is accepted. */
+int micsa_destroy(micsa_ctx* ctx);
+
+/* Install the temperature/refresh schedule (Sec. 2.7-2.8; the annealing
+   temperature applies to the daemon refresh and, for the heat bath, to the
+   sweeps after that refresh point).  The table is copied.  Resets nothing
+   else: the sweep counter k is kept.
+   Errors: EINVAL (T <= 0 or not finite, period < 0, bad table). */
+int micsa_set_schedule(micsa_ctx* ctx, const micsa_schedule* s);
+
+/* Enqueue n sweeps of algo at sweep indices k .. k+n-1 and advance k.  For
+   MICSA the daemons are refreshed before every refresh-point sweep at the
+   temperature of that refresh; a sweep is the even half then the odd half.
+   Asynchronous: returns once the work is enqueued.
+   Errors: ESTATE (no schedule), ERANGE (k+n > n_sweeps), EINVAL. */
+int micsa_sweep(micsa_ctx* ctx, int32_t algo, int64_t n);
+
+/* As micsa_sweep, and after every `stride` sweeps records the from-scratch
+   H^EA (eq. Hamiltonian) and H^aux = sum_x n_x (eq. H-total) of each
+   lattice.  E_log and D_log are host arrays [n/stride][S*R] (either may be
+   NULL), filled when the call returns (the call synchronises). */
+int micsa_sweep_logged(micsa_ctx* ctx, int32_t algo, int64_t n, int64_t stride, int64_t* E_log,
+                       int64_t* D_log);
+
+/* Wait for all enqueued work. */
+int micsa_sync(micsa_ctx* ctx);
+
+/* Reads (synchronous; outputs are host arrays in the natural layout above,
+   independent of the device layout). */
+int micsa_read_energy(micsa_ctx* ctx, int64_t* E);       /* [S*R] H^EA from scratch */
+int micsa_read_energy_tally(micsa_ctx* ctx, int64_t* E); /* [S*R] H^EA from the dH of every accepted move */
+int micsa_read_demon_energy(micsa_ctx* ctx, int64_t* D); /* [S*R] H^aux = 4 sum m */
+/* Q[s] = sum_x s^a_x s^b_x, the overlap of replicas a and b (App. C); EINVAL
+   unless 0 <= a, b < R and a != b. */
+int micsa_read_overlap(micsa_ctx* ctx, int32_t a, int32_t b, int64_t* Q);
+int micsa_read_spins(micsa_ctx* ctx, uint8_t* sigma);    /* [S][R][N] */
+int micsa_read_demons(micsa_ctx* ctx, uint8_t* m);       /* [S][R][N] */
+int micsa_read_couplings(micsa_ctx* ctx, uint8_t* j);    /* [S][N] forward-bond bits 0..2 */
+int micsa_get_counters(micsa_ctx* ctx, int64_t* k, int64_t* rho); /* next sweep, its refresh index */
+
+/* Thresholds the device uses for refresh rho of the installed schedule:
+   t[k] = floor(2^32 P(m <= k)) from eq. prob-daemons-walkers, and the heat
+   bath's tau[v] = floor(2^32 / (1 + exp(-2 beta (6 - 2v)))).  ESTATE
+   without a schedule, ERANGE if rho is outside it. */
+int micsa_get_thresholds(micsa_ctx* ctx, int64_t rho, uint64_t t[3]);
+int micsa_get_heatbath_thresholds(micsa_ctx* ctx, int64_t rho, uint64_t tau[7]);
+
+/* Writes (synchronous).  Spins reset the energy tally to the from-scratch
+   energy.  Daemon levels above 3 are rejected with EINVAL. */
+int micsa_write_spins(micsa_ctx* ctx, const uint8_t* sigma); /* [S][R][N] */
+int micsa_write_demons(micsa_ctx* ctx, const uint8_t* m);    /* [S][R][N] */
+
+/* Per-kernel timing with HIP events on the context's stream.  While
+   enabled every kernel launch is bracketed by an event pair; the sums are
+   read (synchronously) by micsa_get_timing.  kind: 0 = sweep kernels,
+   1 = refresh, 2 = heat bath, 3 = reductions.  Disabled by default. */
+int micsa_set_timing(micsa_ctx* ctx, int32_t enable);
+int micsa_get_timing(micsa_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches);
+
+/* Name of the sweep kernel variant the context uses (static string). */
+const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
+
+/* Launch-shape options (results never depend on them; they exist for the
+   tuner and for tests that compare variants).
+   MICSA_OPT_SWEEP_KERNEL: MICSA_KERNEL_AUTO (default), MICSA_KERNEL_SIMPLE
+     (one launch per half sweep), MICSA_KERNEL_FUSED (one launch per sweep,
+     refresh fused in; needs Lx % 32 == 0).
+   MICSA_OPT_TILE_Y / MICSA_OPT_TILE_Z: rows / planes per work-group of the
+     fused sweep (0 = automatic; must divide Ly / Lz).
+   Errors: EINVAL for an unknown option or a value the lattice cannot use. */
+enum micsa_option { MICSA_OPT_SWEEP_KERNEL = 1, MICSA_OPT_TILE_Y = 2, MICSA_OPT_TILE_Z = 3 };
+enum micsa_kernel_choice { MICSA_KERNEL_AUTO = 0, MICSA_KERNEL_SIMPLE = 1, MICSA_KERNEL_FUSED = 2 };
+int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MICSA_H */

@@ -96,11 +96,15 @@ static void coords(const geom *g, int64_t i, int *x, int *y, int *z)
     *z = (int)(i / ((int64_t)g->Lx * g->Ly));
 }
 
+/* Site at (x, y, z) with periodic wrap; callers step at most one site
+   outside the box. */
+static int wrap(int a, int L) { return a < 0 ? a + L : (a >= L ? a - L : a); }
+
 static int64_t site(const geom *g, int x, int y, int z)
 {
-    x = (x % g->Lx + g->Lx) % g->Lx;
-    y = (y % g->Ly + g->Ly) % g->Ly;
-    z = (z % g->Lz + g->Lz) % g->Lz;
+    x = wrap(x, g->Lx);
+    y = wrap(y, g->Ly);
+    z = wrap(z, g->Lz);
     return x + (int64_t)g->Lx * (y + (int64_t)g->Ly * z);
 }
 

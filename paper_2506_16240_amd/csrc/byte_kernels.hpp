@@ -1,0 +1,312 @@
+// Byte-layout kernels: initialisation, daemon refresh, one MicSA or
+// heat-bath half sweep per launch, and the reductions (energy, daemon
+// energy, overlap).  Layout and notation: geometry.hpp.
+#pragma once
+#include "geometry.hpp"
+#include "philox.hpp"
+
+namespace micsa {
+
+// Neighbourhood of a 4-site word (sites h0 .. h0+3 of parity P in row (y,z)):
+// the six words of opposite-parity neighbours and the six coupling nibbles of
+// the bonds to them, in matching order (A = same k, B = k +- 1 in the row).
+struct Nbhd {
+    uint32_t nb[6];
+    uint32_t jb[6];
+};
+
+template <int P>
+__device__ __forceinline__ Nbhd gather(const Geom& g, const uint32_t* __restrict__ oth,
+                                       const uint32_t* __restrict__ Js, int row, int c)
+{
+    const int z = (int)((uint32_t)row / (uint32_t)g.Ly), y = row - z * g.Ly;
+    const int q = (y + z) & 1;
+    const int dir = (q ^ P) ? 1 : -1;
+    const int cs = dir > 0 ? (c + 1 == g.Wr ? 0 : c + 1) : (c == 0 ? g.Wr - 1 : c - 1);
+    const int yp = y + 1 == g.Ly ? 0 : y + 1, ym = y == 0 ? g.Ly - 1 : y - 1;
+    const int zp = z + 1 == g.Lz ? 0 : z + 1, zm = z == 0 ? g.Lz - 1 : z - 1;
+    const int r_yp = yp + g.Ly * z, r_ym = ym + g.Ly * z, r_zp = y + g.Ly * zp, r_zm = y + g.Ly * zm;
+    const int64_t wr = g.Wr;
+    Nbhd n;
+    const uint32_t A = oth[row * wr + c];
+    n.nb[0] = A;
+    n.nb[1] = shift_word(A, oth[row * wr + cs], dir);
+    n.nb[2] = oth[r_yp * wr + c];
+    n.nb[3] = oth[r_ym * wr + c];
+    n.nb[4] = oth[r_zp * wr + c];
+    n.nb[5] = oth[r_zm * wr + c];
+    const int64_t K = g.Kx;
+    const int64_t h0 = row * K + 4 * c;
+    // The same-k neighbour A pairs with plane (q ? -x : +x) of the even site at
+    // A's position, the shifted neighbour B with (q ? +x : -x); this holds for
+    // both parities because the even site is at x = 2k + q.
+    const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
+    if (P == 0) {
+        // even sites own all six of their bonds
+        n.jb[0] = jnib(Js, g.P32, dA, h0);
+        n.jb[1] = jnib(Js, g.P32, dB, h0);
+        n.jb[2] = jnib(Js, g.P32, kPy, h0);
+        n.jb[3] = jnib(Js, g.P32, kMy, h0);
+        n.jb[4] = jnib(Js, g.P32, kPz, h0);
+        n.jb[5] = jnib(Js, g.P32, kMz, h0);
+    } else {
+        // odd sites read each bond from the even neighbour's opposite plane
+        n.jb[0] = jnib(Js, g.P32, dA, h0);
+        n.jb[1] = shift_nib(jnib(Js, g.P32, dB, h0), jnib(Js, g.P32, dB, row * K + 4 * cs), dir);
+        n.jb[2] = jnib(Js, g.P32, kMy, r_yp * K + 4 * c);
+        n.jb[3] = jnib(Js, g.P32, kPy, r_ym * K + 4 * c);
+        n.jb[4] = jnib(Js, g.P32, kMz, r_zp * K + 4 * c);
+        n.jb[5] = jnib(Js, g.P32, kPz, r_zm * K + 4 * c);
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) n.jb[d] = spread4(n.jb[d]);
+    return n;
+}
+
+// ------------------------------------------------------------------ init
+// Thread per 32 even sites: the six bond bits of each even site from the
+// forward-bond draws j_mu(i) = Philox(i, 0, 0, stream J | s)[mu] >> 31.
+__global__ void k_init_couplings(Geom g, uint32_t* __restrict__ J)
+{
+    const int s = blockIdx.y;
+    const int64_t wi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (wi >= g.P32) return;
+    uint32_t word[6] = {0, 0, 0, 0, 0, 0};
+    const uint32_t sw = stream_word(kStreamCoupling, (uint32_t)s);
+    for (int b = 0; b < 32; ++b) {
+        const int64_t h = wi * 32 + b;
+        if (h >= g.Nh) break;
+        const int k = (int)(h % g.Kx);
+        const int row = (int)(h / g.Kx);
+        const int y = row % g.Ly, z = row / g.Ly;
+        const int x = 2 * k + ((y + z) & 1);
+        auto fwd = [&](int xx, int yy, int zz) {
+            xx = (xx + g.Lx) % g.Lx;
+            yy = (yy + g.Ly) % g.Ly;
+            zz = (zz + g.Lz) % g.Lz;
+            const uint32_t i = (uint32_t)(xx + (int64_t)g.Lx * (yy + (int64_t)g.Ly * zz));
+            return philox10(i, 0u, 0u, sw, g.key0, g.key1);
+        };
+        const u32x4 o = fwd(x, y, z);
+        const uint32_t bits[6] = {o.v0 >> 31, fwd(x - 1, y, z).v0 >> 31, o.v1 >> 31,
+                                  fwd(x, y - 1, z).v1 >> 31, o.v2 >> 31, fwd(x, y, z - 1).v2 >> 31};
+#pragma unroll
+        for (int d = 0; d < 6; ++d) word[d] |= bits[d] << b;
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) J[((int64_t)s * 6 + d) * g.P32 + wi] = word[d];
+}
+
+// Thread per 8 consecutive natural sites i0 .. i0+7 (same row since Lx % 8 == 0):
+// two Philox calls give 8 draws; the 4 sites of each parity land in one word.
+template <typename F>
+__device__ __forceinline__ void split8(const Geom& g, int64_t i0, const u32x4& a, const u32x4& b, F&& val,
+                                       uint32_t& w_even, uint32_t& w_odd)
+{
+    const int x0 = (int)(i0 % g.Lx);
+    const int64_t row = i0 / g.Lx;
+    const int y = (int)(row % g.Ly), z = (int)(row / g.Ly);
+    const uint32_t d[8] = {a.v0, a.v1, a.v2, a.v3, b.v0, b.v1, b.v2, b.v3};
+    w_even = 0;
+    w_odd = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const uint32_t v = val(d[t]);
+        if (((x0 + t + y + z) & 1) == 0)
+            w_even |= v << (8 * (t >> 1));
+        else
+            w_odd |= v << (8 * (t >> 1));
+    }
+}
+
+__global__ void k_init_spins(Geom g, uint8_t* __restrict__ spin)
+{
+    const int l = blockIdx.y;
+    const int s = l / g.R, r = l % g.R;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= g.Nh / 4) return;
+    const int64_t i0 = 8 * t;
+    const uint32_t sw = stream_word(kStreamSpin, (uint32_t)s);
+    const u32x4 a = philox10((uint32_t)(i0 >> 2), 0u, (uint32_t)r, sw, g.key0, g.key1);
+    const u32x4 b = philox10((uint32_t)(i0 >> 2) + 1u, 0u, (uint32_t)r, sw, g.key0, g.key1);
+    uint32_t we, wo;
+    split8(g, i0, a, b, [](uint32_t u) { return u >> 31; }, we, wo);
+    reinterpret_cast<uint32_t*>(spin + ((int64_t)l * 2 + 0) * g.Nh)[t] = we;
+    reinterpret_cast<uint32_t*>(spin + ((int64_t)l * 2 + 1) * g.Nh)[t] = wo;
+}
+
+// Daemon refresh (Sec. 2.7, eq. prob-daemons-walkers): m = #{k : u >= t_k}.
+struct DaemonThresholds {
+    uint64_t t0, t1, t2;
+};
+
+__global__ void k_refresh(Geom g, uint8_t* __restrict__ dem, uint32_t rho, DaemonThresholds th)
+{
+    const int l = blockIdx.y;
+    const int s = l / g.R, r = l % g.R;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= g.Nh / 4) return;
+    const int64_t i0 = 8 * t;
+    const uint32_t sw = stream_word(kStreamDaemon, (uint32_t)s);
+    const u32x4 a = philox10((uint32_t)(i0 >> 2), rho, (uint32_t)r, sw, g.key0, g.key1);
+    const u32x4 b = philox10((uint32_t)(i0 >> 2) + 1u, rho, (uint32_t)r, sw, g.key0, g.key1);
+    uint32_t we, wo;
+    split8(g, i0, a, b,
+           [&](uint32_t u) {
+               const uint64_t v = u;
+               return (uint32_t)(v >= th.t0) + (uint32_t)(v >= th.t1) + (uint32_t)(v >= th.t2);
+           },
+           we, wo);
+    reinterpret_cast<uint32_t*>(dem + ((int64_t)l * 2 + 0) * g.Nh)[t] = we;
+    reinterpret_cast<uint32_t*>(dem + ((int64_t)l * 2 + 1) * g.Nh)[t] = wo;
+}
+
+// --------------------------------------------------------- MicSA half sweep
+// Creutz move with a 2-bit daemon (eqs. Creutz and flip-OK).  With u the
+// number of unsatisfied bonds of the site (sigma ^ sigma_nb ^ j = 1),
+// dH = 12 - 4u, so 0 <= 4m - dH <= 12  <=>  3 <= m + u <= 6, and then the
+// new level is m + u - 3.  Per byte, t = m + u + 5 lies in 5..14 and the
+// move is legal iff t is in 8..11, i.e. bit 3 set and bit 2 clear; the new
+// level is then t & 3.
+__device__ __forceinline__ void micsa_word(uint32_t& S, uint32_t& M, const Nbhd& n, int& dE)
+{
+    uint32_t u = 0;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) u += xor3(S, n.nb[d], n.jb[d]);
+    const uint32_t t = M + u + 0x05050505u;
+    const uint32_t acc = (t >> 3) & ~(t >> 2) & 0x01010101u;
+    const uint32_t mask = acc * 0xFFu;
+    S ^= acc;
+    M = (M & ~mask) | (t & 0x03030303u & mask);
+    dE += 12 * (int)__popc(acc) - 4 * (int)bytesum(u & mask);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_micsa_half(Geom g, uint8_t* __restrict__ spin,
+                                                    uint8_t* __restrict__ dem,
+                                                    const uint32_t* __restrict__ J,
+                                                    unsigned long long* __restrict__ tally)
+{
+    const int l = blockIdx.y;
+    const int s = l / g.R;
+    const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    int dE = 0;
+    if (w < (uint32_t)g.rows * (uint32_t)g.Wr) {
+        const int row = (int)(w / (uint32_t)g.Wr), c = (int)(w - (uint32_t)row * (uint32_t)g.Wr);
+        uint32_t* own = reinterpret_cast<uint32_t*>(spin + ((int64_t)l * 2 + P) * g.Nh);
+        const uint32_t* oth = reinterpret_cast<const uint32_t*>(spin + ((int64_t)l * 2 + (1 - P)) * g.Nh);
+        uint32_t* dm = reinterpret_cast<uint32_t*>(dem + ((int64_t)l * 2 + P) * g.Nh);
+        const Nbhd n = gather<P>(g, oth, J + (int64_t)s * 6 * g.P32, row, c);
+        uint32_t S = own[w], M = dm[w];
+        micsa_word(S, M, n, dE);
+        own[w] = S;
+        dm[w] = M;
+    }
+    block_add(tally + (int64_t)l * kSlots, dE);
+}
+
+// ------------------------------------------------------ heat-bath half sweep
+// New spin +1 iff u < tau[v], v = #neighbours with J s_nb = -1 (h = 6 - 2v);
+// u = Philox(h>>2, 2k+p, r, stream HB | s)[h & 3] for parity-split index h.
+struct HeatBathThresholds {
+    uint64_t tau[7];
+};
+
+template <int P>
+__global__ void __launch_bounds__(256) k_heatbath_half(Geom g, uint8_t* __restrict__ spin,
+                                                       const uint32_t* __restrict__ J, uint32_t time,
+                                                       HeatBathThresholds th,
+                                                       unsigned long long* __restrict__ tally)
+{
+    __shared__ uint64_t tau[8];
+    if (threadIdx.x < 7) tau[threadIdx.x] = th.tau[threadIdx.x];
+    __syncthreads();
+    const int l = blockIdx.y;
+    const int s = l / g.R, r = l % g.R;
+    const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    int dE = 0;
+    if (w < (uint32_t)g.rows * (uint32_t)g.Wr) {
+        const int row = (int)(w / (uint32_t)g.Wr), c = (int)(w - (uint32_t)row * (uint32_t)g.Wr);
+        uint32_t* own = reinterpret_cast<uint32_t*>(spin + ((int64_t)l * 2 + P) * g.Nh);
+        const uint32_t* oth = reinterpret_cast<const uint32_t*>(spin + ((int64_t)l * 2 + (1 - P)) * g.Nh);
+        const Nbhd n = gather<P>(g, oth, J + (int64_t)s * 6 * g.P32, row, c);
+        uint32_t v = 0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) v += n.nb[d] ^ n.jb[d];
+        const u32x4 rnd = philox10(w, time, (uint32_t)r, stream_word(kStreamHeatBath, (uint32_t)s),
+                                   g.key0, g.key1);
+        const uint32_t ru[4] = {rnd.v0, rnd.v1, rnd.v2, rnd.v3};
+        const uint32_t S = own[w];
+        uint32_t Snew = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t vb = (v >> (8 * b)) & 0xFFu;
+            const uint32_t up = (uint64_t)ru[b] < tau[vb] ? 0u : 1u;
+            const uint32_t old = (S >> (8 * b)) & 1u;
+            if (up != old) dE += 2 * (1 - 2 * (int)old) * (6 - 2 * (int)vb);
+            Snew |= up << (8 * b);
+        }
+        own[w] = Snew;
+    }
+    block_add(tally + (int64_t)l * kSlots, dE);
+}
+
+// -------------------------------------------------------------- reductions
+// U = number of unsatisfied bonds, counted once each from the even end;
+// H = 2U - 3N (eq. Hamiltonian).  Adds U to the slots of lattice l.
+__global__ void __launch_bounds__(256) k_unsat_bonds(Geom g, const uint8_t* __restrict__ spin,
+                                                     const uint32_t* __restrict__ J,
+                                                     unsigned long long* __restrict__ out)
+{
+    const int l = blockIdx.y;
+    const int s = l / g.R;
+    const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    int U = 0;
+    if (w < (uint32_t)g.rows * (uint32_t)g.Wr) {
+        const int row = (int)(w / (uint32_t)g.Wr), c = (int)(w - (uint32_t)row * (uint32_t)g.Wr);
+        const uint32_t* ev = reinterpret_cast<const uint32_t*>(spin + ((int64_t)l * 2 + 0) * g.Nh);
+        const uint32_t* od = reinterpret_cast<const uint32_t*>(spin + ((int64_t)l * 2 + 1) * g.Nh);
+        const Nbhd n = gather<0>(g, od, J + (int64_t)s * 6 * g.P32, row, c);
+        const uint32_t S = ev[w];
+        uint32_t u = 0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) u += xor3(S, n.nb[d], n.jb[d]);
+        U = (int)bytesum(u);
+    }
+    block_add(out + (int64_t)l * kSlots, U);
+}
+
+// Adds the sum of daemon levels of lattice l (both parities) to its slots.
+__global__ void __launch_bounds__(256) k_level_sum(int64_t words_per_lattice, const uint32_t* __restrict__ dem,
+                                                   unsigned long long* __restrict__ out)
+{
+    const int l = blockIdx.y;
+    const int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int v = 0;
+    if (w < words_per_lattice) v = (int)bytesum(dem[(int64_t)l * words_per_lattice + w]);
+    block_add(out + (int64_t)l * kSlots, v);
+}
+
+// Adds the number of sites where replicas a and b of sample s differ to its slots.
+__global__ void __launch_bounds__(256) k_differ_count(int64_t words_per_lattice, int R, int a, int b,
+                                                      const uint32_t* __restrict__ spin,
+                                                      unsigned long long* __restrict__ out)
+{
+    const int s = blockIdx.y;
+    const int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int v = 0;
+    if (w < words_per_lattice) {
+        const uint32_t xa = spin[((int64_t)s * R + a) * words_per_lattice + w];
+        const uint32_t xb = spin[((int64_t)s * R + b) * words_per_lattice + w];
+        v = (int)__popc(xa ^ xb);
+    }
+    block_add(out + (int64_t)s * kSlots, v);
+}
+
+__global__ void k_fill_i64(unsigned long long* __restrict__ p, int64_t n, unsigned long long v)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace micsa

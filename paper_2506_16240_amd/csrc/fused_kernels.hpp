@@ -1,0 +1,259 @@
+// Fused MicSA sweep for the byte layout: one launch performs a whole sweep
+// (even half, then odd half, Sec. 2.8) and, on refresh sweeps, the daemon
+// refresh (Sec. 2.7) -- reading each state byte from HBM about once and
+// writing it once.
+//
+// Decomposition.  A work-group owns a tile of TY full rows (all of x) and TZ
+// planes of one lattice and marches along z.  At step z it performs the
+// even half on plane z and the odd half on plane z-1: the odd sites of plane
+// z-1 see new even spins on planes z-2, z-1 and z, all final by then.  The
+// even half is also computed on one ring of rows/planes around the tile and
+// the odd spins are read on two rings, so a tile never needs another tile's
+// new values.  State is double-buffered (read "in", write "out"), so the
+// ring recomputations read exactly the old state and agree bit for bit with
+// the owning tile.
+//
+// Lanes.  Each lane owns one 16-site chunk of one row (16 even and 16 odd
+// sites, uint4 loads and stores) for the whole march.  Its z-neighbours live
+// in its registers; in-plane neighbours (y +- 1, and the byte-shifted x
+// neighbour from the adjacent chunk) come through LDS, one plane of odd
+// spins and one plane of "even view" bytes per step, double-buffered so one
+// barrier per step suffices.
+//
+// Even view.  After an even site is updated its byte X holds, in bit d, the
+// new even spin XOR the coupling bit of its bond in direction d (d = +x, -x,
+// +y, -y, +z, -z).  The odd neighbour across that bond reads bit d of X: the
+// spin and the coupling it needs, in one byte.
+#pragma once
+#include "byte_kernels.hpp"
+
+namespace micsa {
+
+struct FusedTile {
+    int32_t TY, TZ;  // tile rows (divides Ly) and planes (divides Lz)
+    int32_t NC;      // 16-site chunks per row = Lx / 32
+    int32_t nty;     // tiles along y = Ly / TY
+};
+
+struct V4 {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ V4 ldg16(const uint8_t* __restrict__ p)
+{
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    return {{v.x, v.y, v.z, v.w}};
+}
+
+__device__ __forceinline__ void stg16(uint8_t* __restrict__ p, const V4& v)
+{
+    *reinterpret_cast<uint4*>(p) = make_uint4(v.w[0], v.w[1], v.w[2], v.w[3]);
+}
+
+__device__ __forceinline__ V4 lds16(const uint4* s)
+{
+    const uint4 v = *s;
+    return {{v.x, v.y, v.z, v.w}};
+}
+
+__device__ __forceinline__ void sts16(uint4* s, const V4& v) { *s = make_uint4(v.w[0], v.w[1], v.w[2], v.w[3]); }
+
+// The 16 sites k+1 .. k+16 (dir > 0, nbw = first word of the next chunk) or
+// k-1 .. k+14 (dir < 0, nbw = last word of the previous chunk).
+__device__ __forceinline__ V4 shift16(const V4& a, uint32_t nbw, int dir)
+{
+    V4 r;
+    if (dir > 0) {
+        r.w[0] = __builtin_amdgcn_alignbyte(a.w[1], a.w[0], 1);
+        r.w[1] = __builtin_amdgcn_alignbyte(a.w[2], a.w[1], 1);
+        r.w[2] = __builtin_amdgcn_alignbyte(a.w[3], a.w[2], 1);
+        r.w[3] = __builtin_amdgcn_alignbyte(nbw, a.w[3], 1);
+    } else {
+        r.w[0] = __builtin_amdgcn_alignbyte(a.w[0], nbw, 3);
+        r.w[1] = __builtin_amdgcn_alignbyte(a.w[1], a.w[0], 3);
+        r.w[2] = __builtin_amdgcn_alignbyte(a.w[2], a.w[1], 3);
+        r.w[3] = __builtin_amdgcn_alignbyte(a.w[3], a.w[2], 3);
+    }
+    return r;
+}
+
+// Creutz move on 4 byte-sites given their unsatisfied-bond counts u (see
+// micsa_word): legal iff t = m + u + 5 lies in 8..11; new level t & 3.
+__device__ __forceinline__ void creutz4(uint32_t& S, uint32_t& M, uint32_t u, int& dE)
+{
+    const uint32_t t = M + u + 0x05050505u;
+    const uint32_t acc = (t >> 3) & ~(t >> 2) & 0x01010101u;
+    const uint32_t mask = acc * 0xFFu;
+    S ^= acc;
+    M = (M & ~mask) | (t & 0x03030303u & mask);
+    dE += 12 * (int)__popc(acc) - 4 * (int)bytesum(u & mask);
+}
+
+// Daemon levels of the 16 even and 16 odd sites of chunk c of a row from the
+// refresh draws: natural sites x = 32c .. 32c+31 of the row use the 8 Philox
+// calls with counters (i >> 2) = row*Lx/4 + 8c + j, one value per site.
+__device__ __forceinline__ void refresh_chunk(const Geom& g, int row, int c, int q, uint32_t rho, uint32_t r,
+                                              uint32_t sw, const DaemonThresholds& th, V4& Me, V4& Mo)
+{
+    const uint32_t base = (uint32_t)row * (uint32_t)(g.Lx / 4) + 8u * (uint32_t)c;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const u32x4 a = philox10(base + 2u * i, rho, r, sw, g.key0, g.key1);
+        const u32x4 b = philox10(base + 2u * i + 1u, rho, r, sw, g.key0, g.key1);
+        // even site t = 8i + q + {0,2,4,6} of the 32; odd site t = 8i + (1-q) + {0,2,4,6}
+        const uint32_t da[4] = {a.v0, a.v1, a.v2, a.v3};
+        const uint32_t db[4] = {b.v0, b.v1, b.v2, b.v3};
+        auto lvl = [&](uint32_t u) {
+            const uint64_t v = u;
+            return (uint32_t)(v >= th.t0) + (uint32_t)(v >= th.t1) + (uint32_t)(v >= th.t2);
+        };
+        const int qe = q, qo = 1 - q;
+        Me.w[i] = lvl(da[qe]) | (lvl(da[qe + 2]) << 8) | (lvl(db[qe]) << 16) | (lvl(db[qe + 2]) << 24);
+        Mo.w[i] = lvl(da[qo]) | (lvl(da[qo + 2]) << 8) | (lvl(db[qo]) << 16) | (lvl(db[qo + 2]) << 24);
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
+    Geom g, FusedTile f, const uint8_t* __restrict__ spin_in, const uint8_t* __restrict__ dem_in,
+    uint8_t* __restrict__ spin_out, uint8_t* __restrict__ dem_out, const uint32_t* __restrict__ J,
+    unsigned long long* __restrict__ tally, int refresh, uint32_t rho, DaemonThresholds th)
+{
+    extern __shared__ uint4 lds[];
+    const int rows_slots = f.TY + 4;
+    const int plane_slots = rows_slots * f.NC;
+    uint4* So = lds;                    // [2][TY+4][NC] odd spins of the current plane
+    uint4* Xs = lds + 2 * plane_slots;  // [2][TY+4][NC] even views of the previous plane
+
+    const int l = blockIdx.y;
+    const int s = l / g.R, r = l % g.R;
+    const int ty = blockIdx.x % f.nty, tz = blockIdx.x / f.nty;
+    const int y0 = ty * f.TY, z0 = tz * f.TZ;
+    const int ry = threadIdx.x / f.NC, c = threadIdx.x - ry * f.NC;
+    const bool active = ry < rows_slots;
+    int y = y0 - 2 + ry;
+    y = y < 0 ? y + g.Ly : (y >= g.Ly ? y - g.Ly : y);
+    const bool do_even = active && ry >= 1 && ry <= f.TY + 2;
+    const bool do_odd = active && ry >= 2 && ry <= f.TY + 1;  // also the rows the tile owns
+
+    const uint8_t* ev_in = spin_in + ((int64_t)l * 2 + 0) * g.Nh;
+    const uint8_t* od_in = spin_in + ((int64_t)l * 2 + 1) * g.Nh;
+    const uint8_t* me_in = dem_in + ((int64_t)l * 2 + 0) * g.Nh;
+    const uint8_t* mo_in = dem_in + ((int64_t)l * 2 + 1) * g.Nh;
+    uint8_t* ev_out = spin_out + ((int64_t)l * 2 + 0) * g.Nh;
+    uint8_t* od_out = spin_out + ((int64_t)l * 2 + 1) * g.Nh;
+    uint8_t* me_out = dem_out + ((int64_t)l * 2 + 0) * g.Nh;
+    uint8_t* mo_out = dem_out + ((int64_t)l * 2 + 1) * g.Nh;
+    const uint16_t* J16 = reinterpret_cast<const uint16_t*>(J + (int64_t)s * 6 * g.P32);
+    const int64_t plane16 = (int64_t)g.P32 * 2;  // uint16 words per coupling plane
+    const uint32_t sw = stream_word(kStreamDaemon, (uint32_t)s);
+
+    auto wrapz = [&](int z) { return z < 0 ? z + g.Lz : (z >= g.Lz ? z - g.Lz : z); };
+    auto hof = [&](int z) { return ((int64_t)y + (int64_t)g.Ly * z) * g.Kx + 16 * c; };
+    const int cn = c + 1 == f.NC ? 0 : c + 1, cp = c == 0 ? f.NC - 1 : c - 1;
+
+    V4 So_prev{}, So_cur{}, So_next{};  // odd spins (old) at planes z-1, z, z+1
+    V4 X_prev2{}, X_prev{}, X_cur{};    // even views at planes z-2, z-1, z
+    V4 Mo_gen{};                        // refreshed odd levels of plane z-1
+    if (active) {
+        So_prev = ldg16(od_in + hof(wrapz(z0 - 2)));
+        So_cur = ldg16(od_in + hof(wrapz(z0 - 1)));
+    }
+    int dE = 0;
+    const int steps = f.TZ + 2;
+    for (int st = 0; st < steps; ++st) {
+        const int buf = st & 1;
+        const int z = wrapz(z0 - 1 + st);
+        const int64_t h = hof(z);
+        V4 Se{}, Me{}, Mo_next{}, Mo{};
+        uint32_t j16[6] = {0, 0, 0, 0, 0, 0};
+        if (active) So_next = ldg16(od_in + hof(wrapz(z + 1)));
+        if (do_even) {
+            Se = ldg16(ev_in + h);
+            const int64_t hj = h >> 4;
+#pragma unroll
+            for (int d = 0; d < 6; ++d) j16[d] = J16[d * plane16 + hj];
+            if (refresh)
+                refresh_chunk(g, y + g.Ly * z, c, (y + z) & 1, rho, (uint32_t)r, sw, th, Me, Mo_next);
+            else
+                Me = ldg16(me_in + h);
+        }
+        const bool odd_now = do_odd && st >= 2;
+        const int zo = wrapz(z - 1);
+        if (odd_now && !refresh) Mo = ldg16(mo_in + hof(zo));
+        if (active) sts16(&So[buf * plane_slots + ry * f.NC + c], So_cur);
+        __syncthreads();
+
+        if (do_even) {
+            // ---- even half on plane z
+            const int q = (y + z) & 1;
+            const int dir = q ? 1 : -1;
+            const uint4* row = &So[buf * plane_slots + ry * f.NC];
+            const uint32_t nbw = dir > 0 ? row[cn].x : row[cp].w;
+            const V4 A = So_cur;
+            const V4 B = shift16(A, nbw, dir);
+            const V4 Yp = lds16(&So[buf * plane_slots + (ry + 1) * f.NC + c]);
+            const V4 Ym = lds16(&So[buf * plane_slots + (ry - 1) * f.NC + c]);
+            const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
+            const bool owned = do_odd && st >= 1 && st <= f.TZ;
+            int dEe = 0;
+            V4 Xn;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                uint32_t jb[6];
+#pragma unroll
+                for (int d = 0; d < 6; ++d) jb[d] = spread4((j16[d] >> (4 * i)) & 0xFu);
+                uint32_t S = Se.w[i];
+                const uint32_t u = xor3(S, A.w[i], jb[dA]) + xor3(S, B.w[i], jb[dB]) + xor3(S, Yp.w[i], jb[kPy]) +
+                                   xor3(S, Ym.w[i], jb[kMy]) + xor3(S, So_next.w[i], jb[kPz]) +
+                                   xor3(S, So_prev.w[i], jb[kMz]);
+                creutz4(S, Me.w[i], u, dEe);
+                Se.w[i] = S;
+                Xn.w[i] = (S * 0x3Fu) ^ (jb[0] | (jb[1] << 1) | (jb[2] << 2) | (jb[3] << 3) | (jb[4] << 4) |
+                                         (jb[5] << 5));
+            }
+            X_cur = Xn;
+            sts16(&Xs[buf * plane_slots + ry * f.NC + c], Xn);
+            if (owned) {  // ring rows and halo planes are recomputed, not owned
+                stg16(ev_out + h, Se);
+                stg16(me_out + h, Me);
+                dE += dEe;
+            }
+        }
+        if (odd_now) {
+            // ---- odd half on plane z-1 (its even neighbours are all final)
+            const int q = (y + zo) & 1;
+            const int dir = q ? -1 : 1;
+            const int pb = buf ^ 1;
+            const uint4* row = &Xs[pb * plane_slots + ry * f.NC];
+            const uint32_t nbw = dir > 0 ? row[cn].x : row[cp].w;
+            const V4 A = X_prev;
+            const V4 B = shift16(A, nbw, dir);
+            const V4 Yp = lds16(&Xs[pb * plane_slots + (ry + 1) * f.NC + c]);
+            const V4 Ym = lds16(&Xs[pb * plane_slots + (ry - 1) * f.NC + c]);
+            const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
+            if (refresh) Mo = Mo_gen;
+            V4 So_new;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                uint32_t S = So_prev.w[i];
+                const uint32_t u = (S ^ ((A.w[i] >> dA) & 0x01010101u)) + (S ^ ((B.w[i] >> dB) & 0x01010101u)) +
+                                   (S ^ ((Yp.w[i] >> kMy) & 0x01010101u)) + (S ^ ((Ym.w[i] >> kPy) & 0x01010101u)) +
+                                   (S ^ ((X_cur.w[i] >> kMz) & 0x01010101u)) +
+                                   (S ^ ((X_prev2.w[i] >> kPz) & 0x01010101u));
+                creutz4(S, Mo.w[i], u, dE);
+                So_new.w[i] = S;
+            }
+            const int64_t ho = hof(zo);
+            stg16(od_out + ho, So_new);
+            stg16(mo_out + ho, Mo);
+        }
+        So_prev = So_cur;
+        So_cur = So_next;
+        X_prev2 = X_prev;
+        X_prev = X_cur;
+        Mo_gen = Mo_next;
+    }
+    block_add(tally + (int64_t)l * kSlots, dE);
+}
+
+}  // namespace micsa

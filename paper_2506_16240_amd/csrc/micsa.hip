@@ -1,0 +1,800 @@
+// libmicsa: host side of the C ABI declared in include/micsa.h.
+//
+// The context owns the device state of S*R lattices in the byte layout
+// (geometry.hpp), the installed schedule, the sweep counter k and an energy
+// tally per lattice.  Every entry point validates its arguments, enqueues
+// kernels on the context's stream and reports failures as status codes.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fused_kernels.hpp"
+#include "micsa.h"
+
+using namespace micsa;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kTimingKinds = 4;
+enum TimingKind { kTimeSweep = 0, kTimeRefresh = 1, kTimeHeatBath = 2, kTimeReduce = 3 };
+
+struct Schedule {
+    bool set = false;
+    int32_t kind = MICSA_SCHED_CONST;
+    int32_t period = 1;
+    double T0 = 1.0, T1 = 1.0;
+    int64_t n_sweeps = 0;
+    std::vector<double> table;
+};
+
+}  // namespace
+
+struct micsa_ctx {
+    micsa_params p{};
+    hipStream_t stream = nullptr;
+    Geom g{};
+    int L = 0;  // lattices = S * R
+    // device state (byte layout), double-buffered: the fused sweep reads the
+    // current buffers and writes the alternate ones, then the two swap
+    uint8_t* spin = nullptr;  // [L][2][Nh] current
+    uint8_t* dem = nullptr;   // [L][2][Nh] current
+    uint8_t* spin_alt = nullptr;
+    uint8_t* dem_alt = nullptr;
+    // sweep kernel selection (MICSA_OPT_*)
+    int32_t kernel_opt = MICSA_KERNEL_AUTO;
+    int32_t tile_y = 0, tile_z = 0;
+    uint32_t* J = nullptr;    // [S][6][P32]
+    unsigned long long* tally = nullptr;  // [L][kSlots]
+    unsigned long long* red = nullptr;    // [max(L, S)][kSlots] reduction scratch
+    Schedule sched;
+    int64_t k = 0;
+    std::string err;
+    // timing
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events[kTimingKinds];
+    double time_ms[kTimingKinds] = {0, 0, 0, 0};
+    int64_t launches[kTimingKinds] = {0, 0, 0, 0};
+};
+
+namespace {
+
+int fail(micsa_ctx* c, int status, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return status;
+}
+
+#define HIP_TRY(ctx, call)                                                                       \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail((ctx), MICSA_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ----------------------------------------------------------- schedule maths
+// Refresh points and temperatures (Sec. 2.7-2.8).  Host double arithmetic,
+// compiled without FMA contraction so the thresholds are reproducible.
+bool is_refresh(int64_t k, int32_t P) { return P >= 1 ? (k % P == 0) : (((k + 1) & k) == 0); }
+
+int64_t refresh_index(int64_t k, int32_t P)
+{
+    if (P >= 1) return k / P;
+    int64_t rho = -1;
+    for (int64_t t = k + 1; t > 0; t >>= 1) ++rho;
+    return rho;
+}
+
+int64_t refresh_count(const Schedule& s)
+{
+    return s.n_sweeps <= 0 ? 0 : refresh_index(s.n_sweeps - 1, s.period) + 1;
+}
+
+double temperature(const Schedule& s, int64_t rho)
+{
+    switch (s.kind) {
+    case MICSA_SCHED_CONST: return s.T0;
+    case MICSA_SCHED_LINEAR: {
+        const int64_t n = refresh_count(s);
+        if (n <= 1) return s.T0;
+        const double f = (double)rho / (double)(n - 1);
+        return s.T0 * (1.0 - f) + s.T1 * f;
+    }
+    default: return (rho >= 0 && rho < (int64_t)s.table.size()) ? s.table[(size_t)rho] : NAN;
+    }
+}
+
+// t_k = floor(2^32 * P(m <= k)), P(m <= k) = (1 - e^{-4 beta (k+1)}) / (1 - e^{-16 beta}).
+DaemonThresholds daemon_thresholds(double T)
+{
+    const double beta = 1.0 / T;
+    uint64_t t[3];
+    for (int k = 0; k < 3; ++k)
+        t[k] = (uint64_t)std::floor(std::expm1(-4.0 * beta * (double)(k + 1)) / std::expm1(-16.0 * beta) *
+                                    4294967296.0);
+    return {t[0], t[1], t[2]};
+}
+
+// tau_v = floor(2^32 / (1 + e^{-2 beta h})), h = 6 - 2v.
+HeatBathThresholds heatbath_thresholds(double T)
+{
+    const double beta = 1.0 / T;
+    HeatBathThresholds th;
+    for (int v = 0; v < 7; ++v)
+        th.tau[v] = (uint64_t)std::floor(4294967296.0 / (1.0 + std::exp(-2.0 * beta * (double)(6 - 2 * v))));
+    return th;
+}
+
+// --------------------------------------------------------------- launching
+dim3 grid_for(int64_t threads, int y)
+{
+    return dim3((unsigned)((threads + kBlock - 1) / kBlock), (unsigned)y, 1);
+}
+
+struct TimedLaunch {
+    micsa_ctx* c;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    TimedLaunch(micsa_ctx* ctx, int kd) : c(ctx), kind(kd)
+    {
+        if (c->timing) {
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+                a = b = nullptr;
+                return;
+            }
+            (void)hipEventRecord(a, c->stream);
+        }
+    }
+    ~TimedLaunch()
+    {
+        if (a && b) {
+            (void)hipEventRecord(b, c->stream);
+            c->events[kind].push_back({a, b});
+        }
+    }
+};
+
+int check_launch(micsa_ctx* c, const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, MICSA_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return MICSA_OK;
+}
+
+// Zero the accumulator slots of n entities.
+int zero_slots(micsa_ctx* c, unsigned long long* p, int64_t n)
+{
+    k_fill_i64<<<grid_for(n * kSlots, 1), kBlock, 0, c->stream>>>(p, n * kSlots, 0ull);
+    return check_launch(c, "k_fill_i64");
+}
+
+// Copy the slots of n entities to the host and sum them per entity.
+int read_slots(micsa_ctx* c, const unsigned long long* dev, int64_t n, std::vector<int64_t>& out)
+{
+    std::vector<int64_t> raw((size_t)(n * kSlots));
+    HIP_TRY(c, hipMemcpyAsync(raw.data(), dev, raw.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    out.assign((size_t)n, 0);
+    for (int64_t e = 0; e < n; ++e)
+        for (int k = 0; k < kSlots; ++k) out[(size_t)e] += raw[(size_t)(e * kSlots + k)];
+    return MICSA_OK;
+}
+
+// tally <- E (slot 0 = E, other slots 0).
+int set_tally(micsa_ctx* c, const std::vector<int64_t>& E)
+{
+    std::vector<int64_t> raw((size_t)c->L * kSlots, 0);
+    for (int l = 0; l < c->L; ++l) raw[(size_t)l * kSlots] = E[(size_t)l];
+    HIP_TRY(c, hipMemcpyAsync(c->tally, raw.data(), raw.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MICSA_OK;
+}
+
+int launch_refresh(micsa_ctx* c, int64_t rho, double T)
+{
+    TimedLaunch t(c, kTimeRefresh);
+    k_refresh<<<grid_for(c->g.Nh / 4, c->L), kBlock, 0, c->stream>>>(c->g, c->dem, (uint32_t)rho,
+                                                                      daemon_thresholds(T));
+    return check_launch(c, "k_refresh");
+}
+
+// The fused sweep needs whole 16-site chunks per row and a work-group that
+// holds at least a one-row tile with its four ring rows.
+bool fused_eligible(const micsa_ctx* c) { return c->p.Lx % 32 == 0 && 5 * (c->p.Lx / 32) <= 1024; }
+
+bool use_fused(const micsa_ctx* c)
+{
+    if (c->kernel_opt == MICSA_KERNEL_SIMPLE) return false;
+    if (c->kernel_opt == MICSA_KERNEL_FUSED) return true;
+    return fused_eligible(c) && c->p.Lx >= 128;
+}
+
+// Largest divisor of n not above cap (n >= 1, cap >= 1).
+int divisor_at_most(int n, int cap)
+{
+    for (int d = std::min(n, cap); d > 1; --d)
+        if (n % d == 0) return d;
+    return 1;
+}
+
+// Tile of the fused sweep: TY rows (so that (TY+4) * NC lanes fit a
+// work-group of at most 1024), TZ planes chosen to give the device at least
+// two work-groups per compute unit when the lattice allows it.
+FusedTile choose_tile(const micsa_ctx* c)
+{
+    FusedTile f;
+    f.NC = c->p.Lx / 32;
+    const int ty_cap = std::max(1, std::min(32, 1024 / f.NC - 4));
+    f.TY = c->tile_y > 0 ? c->tile_y : divisor_at_most(c->p.Ly, ty_cap);
+    f.nty = c->p.Ly / f.TY;
+    if (c->tile_z > 0) {
+        f.TZ = c->tile_z;
+    } else {
+        f.TZ = divisor_at_most(c->p.Lz, 32);
+        while (f.TZ > 4 && (int64_t)f.nty * (c->p.Lz / f.TZ) * c->L < 512) {
+            const int next = divisor_at_most(c->p.Lz, f.TZ - 1);
+            if (next < 4) break;
+            f.TZ = next;
+        }
+    }
+    return f;
+}
+
+int launch_fused_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
+{
+    const FusedTile f = choose_tile(c);
+    const int lanes = (f.TY + 4) * f.NC;
+    const int block = (lanes + 63) / 64 * 64;
+    const size_t lds = (size_t)64 * (f.TY + 4) * f.NC;
+    const dim3 grid((unsigned)(f.nty * (c->p.Lz / f.TZ)), (unsigned)c->L, 1);
+    const DaemonThresholds th = refresh ? daemon_thresholds(T) : DaemonThresholds{0, 0, 0};
+    {
+        TimedLaunch t(c, kTimeSweep);
+        k_micsa_sweep_fused<<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->dem, c->spin_alt, c->dem_alt,
+                                                             c->J, c->tally, refresh ? 1 : 0, (uint32_t)rho, th);
+    }
+    const int st = check_launch(c, "k_micsa_sweep_fused");
+    if (st) return st;
+    std::swap(c->spin, c->spin_alt);
+    std::swap(c->dem, c->dem_alt);
+    return MICSA_OK;
+}
+
+int launch_micsa_sweep(micsa_ctx* c)
+{
+    const int64_t words = (int64_t)c->g.rows * c->g.Wr;
+    {
+        TimedLaunch t(c, kTimeSweep);
+        k_micsa_half<0><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally);
+    }
+    int st = check_launch(c, "k_micsa_half<0>");
+    if (st) return st;
+    {
+        TimedLaunch t(c, kTimeSweep);
+        k_micsa_half<1><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally);
+    }
+    return check_launch(c, "k_micsa_half<1>");
+}
+
+int launch_heatbath_sweep(micsa_ctx* c, int64_t k, double T)
+{
+    const int64_t words = (int64_t)c->g.rows * c->g.Wr;
+    const HeatBathThresholds th = heatbath_thresholds(T);
+    {
+        TimedLaunch t(c, kTimeHeatBath);
+        k_heatbath_half<0><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->J,
+                                                                             (uint32_t)(2 * k), th, c->tally);
+    }
+    int st = check_launch(c, "k_heatbath_half<0>");
+    if (st) return st;
+    {
+        TimedLaunch t(c, kTimeHeatBath);
+        k_heatbath_half<1><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->J,
+                                                                             (uint32_t)(2 * k + 1), th, c->tally);
+    }
+    return check_launch(c, "k_heatbath_half<1>");
+}
+
+// Enqueue: dst[l] = from-scratch H^EA of lattice l.
+int enqueue_energy(micsa_ctx* c, unsigned long long* dst)
+{
+    int st = zero_slots(c, dst, c->L);
+    if (st) return st;
+    TimedLaunch t(c, kTimeReduce);
+    k_unsat_bonds<<<grid_for((int64_t)c->g.rows * c->g.Wr, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->J,
+                                                                                           dst);
+    return check_launch(c, "k_unsat_bonds");
+}
+
+int enqueue_level_sum(micsa_ctx* c, unsigned long long* dst)
+{
+    int st = zero_slots(c, dst, c->L);
+    if (st) return st;
+    TimedLaunch t(c, kTimeReduce);
+    const int64_t wpl = 2 * c->g.Nh / 4;
+    k_level_sum<<<grid_for(wpl, c->L), kBlock, 0, c->stream>>>(wpl, reinterpret_cast<const uint32_t*>(c->dem),
+                                                               dst);
+    return check_launch(c, "k_level_sum");
+}
+
+int64_t n_sites(const micsa_ctx* c) { return (int64_t)c->p.Lx * c->p.Ly * c->p.Lz; }
+
+// Natural index i -> (parity, h) of the byte layout.
+inline void split_index(const micsa_ctx* c, int64_t i, int& par, int64_t& h)
+{
+    const int x = (int)(i % c->p.Lx);
+    const int64_t row = i / c->p.Lx;
+    const int y = (int)(row % c->p.Ly), z = (int)(row / c->p.Ly);
+    par = (x + y + z) & 1;
+    h = i >> 1;
+}
+
+int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
+{
+    if (!c) return MICSA_EINVAL;
+    if (algo != MICSA_ALGO_MICSA && algo != MICSA_ALGO_HEATBATH) return fail(c, MICSA_EINVAL, "unknown algo");
+    if (n < 0) return fail(c, MICSA_EINVAL, "negative sweep count");
+    if (!c->sched.set) return fail(c, MICSA_ESTATE, "no schedule installed");
+    if (c->k + n > c->sched.n_sweeps) return fail(c, MICSA_ERANGE, "sweeps beyond the schedule length");
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t k = c->k;
+        const int64_t rho = refresh_index(k, c->sched.period);
+        const double T = temperature(c->sched, rho);
+        if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
+        int st;
+        if (algo == MICSA_ALGO_MICSA) {
+            const bool refresh = is_refresh(k, c->sched.period);
+            if (use_fused(c)) {
+                if ((st = launch_fused_sweep(c, refresh, rho, T))) return st;
+            } else {
+                if (refresh && (st = launch_refresh(c, rho, T))) return st;
+                if ((st = launch_micsa_sweep(c))) return st;
+            }
+        } else {
+            if ((st = launch_heatbath_sweep(c, k, T))) return st;
+        }
+        c->k = k + 1;
+    }
+    return MICSA_OK;
+}
+
+void free_all(micsa_ctx* c)
+{
+    if (!c) return;
+    if (c->spin) (void)hipFree(c->spin);
+    if (c->dem) (void)hipFree(c->dem);
+    if (c->spin_alt) (void)hipFree(c->spin_alt);
+    if (c->dem_alt) (void)hipFree(c->dem_alt);
+    if (c->J) (void)hipFree(c->J);
+    if (c->tally) (void)hipFree(c->tally);
+    if (c->red) (void)hipFree(c->red);
+    for (auto& v : c->events)
+        for (auto& e : v) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* micsa_status_string(int status)
+{
+    switch (status) {
+    case MICSA_OK: return "ok";
+    case MICSA_EINVAL: return "invalid argument";
+    case MICSA_ENOMEM: return "out of device memory";
+    case MICSA_EHIP: return "HIP runtime error";
+    case MICSA_ESTATE: return "invalid state";
+    case MICSA_ERANGE: return "out of range";
+    default: return "unknown status";
+    }
+}
+
+const char* micsa_last_error(const micsa_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
+{
+    if (!out) return MICSA_EINVAL;
+    *out = nullptr;
+    if (!p) return MICSA_EINVAL;
+    if (p->Lx < 8 || p->Lx % 8 || p->Ly < 2 || p->Ly % 2 || p->Lz < 2 || p->Lz % 2) return MICSA_EINVAL;
+    if (p->n_samples < 1 || p->n_samples >= (1 << 24) || p->n_replicas < 1) return MICSA_EINVAL;
+    if (p->layout != MICSA_LAYOUT_BYTE) return MICSA_EINVAL;
+    const int64_t N = (int64_t)p->Lx * p->Ly * p->Lz;
+    if (N >= ((int64_t)1 << 32) || (int64_t)p->n_samples * p->n_replicas >= (1 << 16)) return MICSA_EINVAL;
+
+    micsa_ctx* c = new (std::nothrow) micsa_ctx();
+    if (!c) return MICSA_ENOMEM;
+    c->p = *p;
+    c->stream = (hipStream_t)hip_stream;
+    c->L = p->n_samples * p->n_replicas;
+    Geom& g = c->g;
+    g.Lx = p->Lx;
+    g.Ly = p->Ly;
+    g.Lz = p->Lz;
+    g.Kx = p->Lx / 2;
+    g.Wr = g.Kx / 4;
+    g.rows = p->Ly * p->Lz;
+    g.Nh = N / 2;
+    g.P32 = (int32_t)((g.Nh + 31) / 32);
+    g.S = p->n_samples;
+    g.R = p->n_replicas;
+    g.key0 = (uint32_t)p->seed;
+    g.key1 = (uint32_t)(p->seed >> 32);
+
+    const size_t state = (size_t)c->L * 2 * (size_t)g.Nh;
+    const size_t jw = (size_t)p->n_samples * 6 * (size_t)g.P32;
+    const size_t nred = (size_t)std::max(c->L, p->n_samples);
+    if (hipMalloc(&c->spin, state) != hipSuccess || hipMalloc(&c->dem, state) != hipSuccess ||
+        hipMalloc(&c->spin_alt, state) != hipSuccess || hipMalloc(&c->dem_alt, state) != hipSuccess ||
+        hipMalloc(&c->J, jw * 4) != hipSuccess || hipMalloc(&c->tally, (size_t)c->L * kSlots * 8) != hipSuccess ||
+        hipMalloc(&c->red, nred * kSlots * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        free_all(c);
+        delete c;
+        return MICSA_ENOMEM;
+    }
+    int st = MICSA_OK;
+    k_init_couplings<<<grid_for(g.P32, p->n_samples), kBlock, 0, c->stream>>>(g, c->J);
+    if (!st) st = check_launch(c, "k_init_couplings");
+    if (!st) {
+        k_init_spins<<<grid_for(g.Nh / 4, c->L), kBlock, 0, c->stream>>>(g, c->spin);
+        st = check_launch(c, "k_init_spins");
+    }
+    if (!st && hipMemsetAsync(c->dem, 0, state, c->stream) != hipSuccess) st = MICSA_EHIP;
+    if (!st) {
+        // tally <- from-scratch energy (2U - 3N)
+        std::vector<int64_t> U;
+        st = enqueue_energy(c, c->red);
+        if (!st) st = read_slots(c, c->red, c->L, U);
+        if (!st) {
+            for (auto& u : U) u = 2 * u - 3 * N;
+            st = set_tally(c, U);
+        }
+    }
+    if (st) {
+        free_all(c);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return MICSA_OK;
+}
+
+int micsa_destroy(micsa_ctx* ctx)
+{
+    if (!ctx) return MICSA_OK;
+    (void)hipStreamSynchronize(ctx->stream);
+    free_all(ctx);
+    delete ctx;
+    return MICSA_OK;
+}
+
+int micsa_set_schedule(micsa_ctx* ctx, const micsa_schedule* s)
+{
+    if (!ctx) return MICSA_EINVAL;
+    if (!s) return fail(ctx, MICSA_EINVAL, "null schedule");
+    if (s->refresh_period < 0) return fail(ctx, MICSA_EINVAL, "refresh_period < 0");
+    if (s->n_sweeps < 0) return fail(ctx, MICSA_EINVAL, "n_sweeps < 0");
+    Schedule n;
+    n.set = true;
+    n.kind = s->kind;
+    n.period = s->refresh_period;
+    n.T0 = s->T0;
+    n.T1 = s->T1;
+    n.n_sweeps = s->n_sweeps;
+    auto okT = [](double T) { return T > 0.0 && std::isfinite(T); };
+    if (s->kind == MICSA_SCHED_CONST) {
+        if (!okT(s->T0)) return fail(ctx, MICSA_EINVAL, "T0 must be positive and finite");
+    } else if (s->kind == MICSA_SCHED_LINEAR) {
+        if (!okT(s->T0) || !okT(s->T1)) return fail(ctx, MICSA_EINVAL, "T0, T1 must be positive and finite");
+    } else if (s->kind == MICSA_SCHED_TABLE) {
+        if (!s->T_table || s->T_len < refresh_count(n))
+            return fail(ctx, MICSA_EINVAL, "T_table must cover every refresh of the schedule");
+        n.table.assign(s->T_table, s->T_table + s->T_len);
+        for (double T : n.table)
+            if (!okT(T)) return fail(ctx, MICSA_EINVAL, "table temperatures must be positive and finite");
+    } else {
+        return fail(ctx, MICSA_EINVAL, "unknown schedule kind");
+    }
+    ctx->sched = std::move(n);
+    return MICSA_OK;
+}
+
+int micsa_sweep(micsa_ctx* ctx, int32_t algo, int64_t n) { return sweep_impl(ctx, algo, n); }
+
+int micsa_sweep_logged(micsa_ctx* ctx, int32_t algo, int64_t n, int64_t stride, int64_t* E_log, int64_t* D_log)
+{
+    if (!ctx) return MICSA_EINVAL;
+    if (stride < 1) return fail(ctx, MICSA_EINVAL, "stride must be >= 1");
+    if (!ctx->sched.set) return fail(ctx, MICSA_ESTATE, "no schedule installed");
+    if (n < 0 || ctx->k + n > ctx->sched.n_sweeps) return fail(ctx, MICSA_ERANGE, "sweeps beyond the schedule");
+    const int64_t rows = n / stride;
+    const int L = ctx->L;
+    unsigned long long* dlog = nullptr;
+    const size_t row_len = (size_t)L * 2 * kSlots;
+    if (rows > 0 && hipMalloc(&dlog, (size_t)rows * row_len * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, MICSA_ENOMEM, "log buffer");
+    }
+    int st = MICSA_OK;
+    int64_t done = 0;
+    for (int64_t r = 0; r < rows && !st; ++r) {
+        st = sweep_impl(ctx, algo, stride);
+        done += stride;
+        if (!st) st = enqueue_energy(ctx, dlog + (size_t)r * row_len);
+        if (!st) st = enqueue_level_sum(ctx, dlog + (size_t)r * row_len + (size_t)L * kSlots);
+    }
+    if (!st && n > done) st = sweep_impl(ctx, algo, n - done);
+    std::vector<int64_t> h;
+    if (!st && rows > 0) st = read_slots(ctx, dlog, rows * L * 2, h);
+    if (!st && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(ctx, MICSA_EHIP, "sync");
+    if (dlog) (void)hipFree(dlog);
+    if (st) return st;
+    const int64_t N = n_sites(ctx);
+    for (int64_t r = 0; r < rows; ++r)
+        for (int l = 0; l < L; ++l) {
+            if (E_log) E_log[r * L + l] = 2 * h[(size_t)(r * L * 2 + l)] - 3 * N;
+            if (D_log) D_log[r * L + l] = 4 * h[(size_t)(r * L * 2 + L + l)];
+        }
+    return MICSA_OK;
+}
+
+int micsa_sync(micsa_ctx* ctx)
+{
+    if (!ctx) return MICSA_EINVAL;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return MICSA_OK;
+}
+
+static int read_red(micsa_ctx* c, int64_t n, std::vector<int64_t>& out) { return read_slots(c, c->red, n, out); }
+
+int micsa_read_energy(micsa_ctx* ctx, int64_t* E)
+{
+    if (!ctx || !E) return MICSA_EINVAL;
+    int st = enqueue_energy(ctx, ctx->red);
+    std::vector<int64_t> U;
+    if (st || (st = read_red(ctx, ctx->L, U))) return st;
+    const int64_t N = n_sites(ctx);
+    for (int l = 0; l < ctx->L; ++l) E[l] = 2 * U[(size_t)l] - 3 * N;
+    return MICSA_OK;
+}
+
+int micsa_read_energy_tally(micsa_ctx* ctx, int64_t* E)
+{
+    if (!ctx || !E) return MICSA_EINVAL;
+    std::vector<int64_t> v;
+    int st = read_slots(ctx, ctx->tally, ctx->L, v);
+    if (st) return st;
+    for (int l = 0; l < ctx->L; ++l) E[l] = v[(size_t)l];
+    return MICSA_OK;
+}
+
+int micsa_read_demon_energy(micsa_ctx* ctx, int64_t* D)
+{
+    if (!ctx || !D) return MICSA_EINVAL;
+    int st = enqueue_level_sum(ctx, ctx->red);
+    std::vector<int64_t> v;
+    if (st || (st = read_red(ctx, ctx->L, v))) return st;
+    for (int l = 0; l < ctx->L; ++l) D[l] = 4 * v[(size_t)l];
+    return MICSA_OK;
+}
+
+int micsa_read_overlap(micsa_ctx* ctx, int32_t a, int32_t b, int64_t* Q)
+{
+    if (!ctx || !Q) return MICSA_EINVAL;
+    if (a < 0 || b < 0 || a >= ctx->p.n_replicas || b >= ctx->p.n_replicas || a == b)
+        return fail(ctx, MICSA_EINVAL, "replica indices out of range or equal");
+    const int S = ctx->p.n_samples;
+    int st = zero_slots(ctx, ctx->red, S);
+    if (st) return st;
+    const int64_t wpl = 2 * ctx->g.Nh / 4;
+    {
+        TimedLaunch t(ctx, kTimeReduce);
+        k_differ_count<<<grid_for(wpl, S), kBlock, 0, ctx->stream>>>(
+            wpl, ctx->p.n_replicas, a, b, reinterpret_cast<const uint32_t*>(ctx->spin), ctx->red);
+    }
+    if ((st = check_launch(ctx, "k_differ_count"))) return st;
+    std::vector<int64_t> v;
+    if ((st = read_red(ctx, S, v))) return st;
+    const int64_t N = n_sites(ctx);
+    for (int s = 0; s < S; ++s) Q[s] = N - 2 * v[(size_t)s];
+    return MICSA_OK;
+}
+
+static int read_state(micsa_ctx* ctx, const uint8_t* dev, uint8_t* host)
+{
+    const int64_t N = n_sites(ctx);
+    std::vector<uint8_t> buf((size_t)ctx->L * 2 * (size_t)ctx->g.Nh);
+    HIP_TRY(ctx, hipMemcpyAsync(buf.data(), dev, buf.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int l = 0; l < ctx->L; ++l)
+        for (int64_t i = 0; i < N; ++i) {
+            int par;
+            int64_t h;
+            split_index(ctx, i, par, h);
+            host[(int64_t)l * N + i] = buf[((size_t)l * 2 + par) * ctx->g.Nh + h];
+        }
+    return MICSA_OK;
+}
+
+int micsa_read_spins(micsa_ctx* ctx, uint8_t* sigma)
+{
+    if (!ctx || !sigma) return MICSA_EINVAL;
+    return read_state(ctx, ctx->spin, sigma);
+}
+
+int micsa_read_demons(micsa_ctx* ctx, uint8_t* m)
+{
+    if (!ctx || !m) return MICSA_EINVAL;
+    return read_state(ctx, ctx->dem, m);
+}
+
+int micsa_read_couplings(micsa_ctx* ctx, uint8_t* j)
+{
+    if (!ctx || !j) return MICSA_EINVAL;
+    const Geom& g = ctx->g;
+    const int S = ctx->p.n_samples;
+    std::vector<uint32_t> planes((size_t)S * 6 * g.P32);
+    HIP_TRY(ctx, hipMemcpyAsync(planes.data(), ctx->J, planes.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    const int64_t N = n_sites(ctx);
+    auto bit = [&](int s, int d, int64_t h) {
+        return (planes[((size_t)s * 6 + d) * g.P32 + (size_t)(h >> 5)] >> (h & 31)) & 1u;
+    };
+    for (int s = 0; s < S; ++s)
+        for (int64_t i = 0; i < N; ++i) {
+            const int x = (int)(i % g.Lx), y = (int)((i / g.Lx) % g.Ly), z = (int)(i / ((int64_t)g.Lx * g.Ly));
+            uint8_t v = 0;
+            if (((x + y + z) & 1) == 0) {
+                const int64_t h = i >> 1;
+                v = (uint8_t)(bit(s, kPx, h) | (bit(s, kPy, h) << 1) | (bit(s, kPz, h) << 2));
+            } else {
+                // forward bonds of an odd site are the backward bonds of its even neighbours
+                auto idx = [&](int xx, int yy, int zz) {
+                    return ((xx % g.Lx) + (int64_t)g.Lx * ((yy % g.Ly) + (int64_t)g.Ly * (zz % g.Lz))) >> 1;
+                };
+                v = (uint8_t)(bit(s, kMx, idx(x + 1, y, z)) | (bit(s, kMy, idx(x, y + 1, z)) << 1) |
+                              (bit(s, kMz, idx(x, y, z + 1)) << 2));
+            }
+            j[(int64_t)s * N + i] = v;
+        }
+    return MICSA_OK;
+}
+
+static int write_state(micsa_ctx* ctx, uint8_t* dev, const uint8_t* host, uint8_t maxv)
+{
+    const int64_t N = n_sites(ctx);
+    std::vector<uint8_t> buf((size_t)ctx->L * 2 * (size_t)ctx->g.Nh);
+    for (int l = 0; l < ctx->L; ++l)
+        for (int64_t i = 0; i < N; ++i) {
+            const uint8_t v = host[(int64_t)l * N + i];
+            if (v > maxv) return fail(ctx, MICSA_EINVAL, "value out of range");
+            int par;
+            int64_t h;
+            split_index(ctx, i, par, h);
+            buf[((size_t)l * 2 + par) * ctx->g.Nh + h] = v;
+        }
+    HIP_TRY(ctx, hipMemcpyAsync(dev, buf.data(), buf.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return MICSA_OK;
+}
+
+int micsa_write_spins(micsa_ctx* ctx, const uint8_t* sigma)
+{
+    if (!ctx || !sigma) return MICSA_EINVAL;
+    int st = write_state(ctx, ctx->spin, sigma, 1);
+    if (st) return st;
+    std::vector<int64_t> E((size_t)ctx->L);
+    if ((st = micsa_read_energy(ctx, E.data()))) return st;
+    return set_tally(ctx, E);
+}
+
+int micsa_write_demons(micsa_ctx* ctx, const uint8_t* m)
+{
+    if (!ctx || !m) return MICSA_EINVAL;
+    return write_state(ctx, ctx->dem, m, 3);
+}
+
+int micsa_get_counters(micsa_ctx* ctx, int64_t* k, int64_t* rho)
+{
+    if (!ctx) return MICSA_EINVAL;
+    if (k) *k = ctx->k;
+    if (rho) *rho = refresh_index(ctx->k, ctx->sched.set ? ctx->sched.period : 1);
+    return MICSA_OK;
+}
+
+int micsa_get_thresholds(micsa_ctx* ctx, int64_t rho, uint64_t t[3])
+{
+    if (!ctx || !t) return MICSA_EINVAL;
+    if (!ctx->sched.set) return fail(ctx, MICSA_ESTATE, "no schedule installed");
+    if (rho < 0 || rho >= std::max<int64_t>(refresh_count(ctx->sched), 1))
+        return fail(ctx, MICSA_ERANGE, "refresh index outside the schedule");
+    const DaemonThresholds th = daemon_thresholds(temperature(ctx->sched, rho));
+    t[0] = th.t0;
+    t[1] = th.t1;
+    t[2] = th.t2;
+    return MICSA_OK;
+}
+
+int micsa_get_heatbath_thresholds(micsa_ctx* ctx, int64_t rho, uint64_t tau[7])
+{
+    if (!ctx || !tau) return MICSA_EINVAL;
+    if (!ctx->sched.set) return fail(ctx, MICSA_ESTATE, "no schedule installed");
+    if (rho < 0 || rho >= std::max<int64_t>(refresh_count(ctx->sched), 1))
+        return fail(ctx, MICSA_ERANGE, "refresh index outside the schedule");
+    const HeatBathThresholds th = heatbath_thresholds(temperature(ctx->sched, rho));
+    for (int v = 0; v < 7; ++v) tau[v] = th.tau[v];
+    return MICSA_OK;
+}
+
+int micsa_set_timing(micsa_ctx* ctx, int32_t enable)
+{
+    if (!ctx) return MICSA_EINVAL;
+    ctx->timing = enable != 0;
+    return MICSA_OK;
+}
+
+int micsa_get_timing(micsa_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches)
+{
+    if (!ctx || kind < 0 || kind >= kTimingKinds) return MICSA_EINVAL;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int kd = 0; kd < kTimingKinds; ++kd) {
+        for (auto& e : ctx->events[kd]) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
+                ctx->time_ms[kd] += ms;
+                ctx->launches[kd] += 1;
+            }
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        ctx->events[kd].clear();
+    }
+    if (total_ms) *total_ms = ctx->time_ms[kind];
+    if (launches) *launches = ctx->launches[kind];
+    return MICSA_OK;
+}
+
+const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
+{
+    if (algo == MICSA_ALGO_HEATBATH) return "k_heatbath_half";
+    if (ctx && use_fused(ctx)) return "k_micsa_sweep_fused";
+    return "k_micsa_half";
+}
+
+int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value)
+{
+    if (!ctx) return MICSA_EINVAL;
+    switch (option) {
+    case MICSA_OPT_SWEEP_KERNEL:
+        if (value != MICSA_KERNEL_AUTO && value != MICSA_KERNEL_SIMPLE && value != MICSA_KERNEL_FUSED)
+            return fail(ctx, MICSA_EINVAL, "unknown sweep kernel");
+        if (value == MICSA_KERNEL_FUSED && !fused_eligible(ctx))
+            return fail(ctx, MICSA_EINVAL, "the fused sweep needs Lx % 32 == 0");
+        ctx->kernel_opt = (int32_t)value;
+        return MICSA_OK;
+    case MICSA_OPT_TILE_Y:
+        if (value < 0 || (value > 0 && (ctx->p.Ly % value != 0 || (value + 4) * (ctx->p.Lx / 32) > 1024)))
+            return fail(ctx, MICSA_EINVAL, "tile_y must divide Ly and fit a work-group");
+        ctx->tile_y = (int32_t)value;
+        return MICSA_OK;
+    case MICSA_OPT_TILE_Z:
+        if (value < 0 || (value > 0 && ctx->p.Lz % value != 0))
+            return fail(ctx, MICSA_EINVAL, "tile_z must divide Lz");
+        ctx->tile_z = (int32_t)value;
+        return MICSA_OK;
+    default: return fail(ctx, MICSA_EINVAL, "unknown option");
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,255 @@
+"""Python binding of libmicsa (include/micsa.h): argument marshalling only.
+
+Every step of the method runs in the HIP library; this module converts
+numpy arrays and Python values to the C ABI and raises on error statuses.
+If libmicsa.so has not been built the import of the library fails loudly:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmicsa.so")
+
+OK, EINVAL, ENOMEM, EHIP, ESTATE, ERANGE = 0, -1, -2, -3, -4, -5
+LAYOUT_BYTE, LAYOUT_BITPLANE = 0, 1
+ALGO_MICSA, ALGO_HEATBATH = 0, 1
+SCHED_CONST, SCHED_LINEAR, SCHED_TABLE = 0, 1, 2
+REFRESH_LOG2 = 0
+TIME_SWEEP, TIME_REFRESH, TIME_HEATBATH, TIME_REDUCE = 0, 1, 2, 3
+OPT_SWEEP_KERNEL, OPT_TILE_Y, OPT_TILE_Z = 1, 2, 3
+KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_FUSED = 0, 1, 2
+
+
+class MicsaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("Lz", ctypes.c_int32),
+                ("n_samples", ctypes.c_int32), ("n_replicas", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class _Schedule(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("refresh_period", ctypes.c_int32), ("T0", ctypes.c_double),
+                ("T1", ctypes.c_double), ("n_sweeps", ctypes.c_int64),
+                ("T_table", ctypes.POINTER(ctypes.c_double)), ("T_len", ctypes.c_int64)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point
+_SIGNATURES = [
+    ("micsa_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("micsa_last_error", ctypes.c_char_p, [ctypes.c_void_p]),
+    ("micsa_create", ctypes.c_int, [ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    ("micsa_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("micsa_set_schedule", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Schedule)]),
+    ("micsa_sweep", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64]),
+    ("micsa_sweep_logged", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_sync", ctypes.c_int, [ctypes.c_void_p]),
+    ("micsa_read_energy", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_read_energy_tally", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_read_demon_energy", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_read_overlap", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
+    ("micsa_read_spins", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_read_demons", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_read_couplings", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_get_counters", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_int64)]),
+    ("micsa_get_thresholds", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    ("micsa_get_heatbath_thresholds", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    ("micsa_write_spins", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_write_demons", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_set_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    ("micsa_get_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int64)]),
+    ("micsa_kernel_name", ctypes.c_char_p, [ctypes.c_void_p, ctypes.c_int32]),
+    ("micsa_set_option", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64]),
+]
+
+
+def exported_symbols() -> list[str]:
+    return [s[0] for s in _SIGNATURES]
+
+
+def lib():
+    """Load libmicsa.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> ctypes.c_void_p:
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+@dataclass
+class Schedule:
+    kind: int = SCHED_CONST
+    T0: float = 1.0
+    T1: float = 1.0
+    n_sweeps: int = 1
+    period: int = 10
+    table: np.ndarray | None = None
+
+
+class Lattice:
+    """S samples x R replicas on the GPU (one libmicsa context)."""
+
+    def __init__(self, Lx: int, Ly: int, Lz: int, S: int = 1, R: int = 1, seed: int = 0,
+                 layout: int = LAYOUT_BYTE, stream=None):
+        self.Lx, self.Ly, self.Lz, self.S, self.R = Lx, Ly, Lz, S, R
+        self.N = Lx * Ly * Lz
+        self.seed = seed
+        self._ctx = ctypes.c_void_p()
+        p = _Params(Lx, Ly, Lz, S, R, layout, seed & (2**64 - 1))
+        st = lib().micsa_create(ctypes.byref(p), _stream_handle(stream), ctypes.byref(self._ctx))
+        if st != OK:
+            raise MicsaError(st, f"micsa_create({Lx},{Ly},{Lz},S={S},R={R}): "
+                                 f"{lib().micsa_status_string(st).decode()}")
+        self._table = None
+
+    # -- plumbing -------------------------------------------------------
+    def _check(self, st: int, what: str) -> None:
+        if st != OK:
+            msg = lib().micsa_last_error(self._ctx).decode()
+            raise MicsaError(st, f"{what}: {lib().micsa_status_string(st).decode()}: {msg}")
+
+    def close(self) -> None:
+        if self._ctx:
+            lib().micsa_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- schedule and sweeps --------------------------------------------
+    def set_schedule(self, s: Schedule) -> None:
+        tab, n = None, 0
+        if s.table is not None:
+            self._table = np.ascontiguousarray(s.table, np.float64)
+            tab, n = self._table.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(self._table)
+        cs = _Schedule(s.kind, s.period, s.T0, s.T1, s.n_sweeps, tab, n)
+        self._check(lib().micsa_set_schedule(self._ctx, ctypes.byref(cs)), "set_schedule")
+
+    def sweep(self, algo: int, n: int) -> None:
+        self._check(lib().micsa_sweep(self._ctx, algo, n), "sweep")
+
+    def sweep_logged(self, algo: int, n: int, stride: int = 1):
+        rows = n // stride
+        E = np.zeros((rows, self.S * self.R), np.int64)
+        D = np.zeros((rows, self.S * self.R), np.int64)
+        self._check(lib().micsa_sweep_logged(self._ctx, algo, n, stride, _ptr(E), _ptr(D)), "sweep_logged")
+        return E, D
+
+    def sync(self) -> None:
+        self._check(lib().micsa_sync(self._ctx), "sync")
+
+    # -- reads ----------------------------------------------------------
+    def _read_vec(self, fn, n, what):
+        out = np.zeros(n, np.int64)
+        self._check(fn(self._ctx, _ptr(out)), what)
+        return out
+
+    def energy(self) -> np.ndarray:
+        return self._read_vec(lib().micsa_read_energy, self.S * self.R, "read_energy")
+
+    def energy_tally(self) -> np.ndarray:
+        return self._read_vec(lib().micsa_read_energy_tally, self.S * self.R, "read_energy_tally")
+
+    def daemon_energy(self) -> np.ndarray:
+        return self._read_vec(lib().micsa_read_demon_energy, self.S * self.R, "read_demon_energy")
+
+    def overlap(self, a: int, b: int) -> np.ndarray:
+        out = np.zeros(self.S, np.int64)
+        self._check(lib().micsa_read_overlap(self._ctx, a, b, _ptr(out)), "read_overlap")
+        return out
+
+    def spins(self) -> np.ndarray:
+        out = np.zeros((self.S, self.R, self.N), np.uint8)
+        self._check(lib().micsa_read_spins(self._ctx, _ptr(out)), "read_spins")
+        return out
+
+    def daemons(self) -> np.ndarray:
+        out = np.zeros((self.S, self.R, self.N), np.uint8)
+        self._check(lib().micsa_read_demons(self._ctx, _ptr(out)), "read_demons")
+        return out
+
+    def couplings(self) -> np.ndarray:
+        out = np.zeros((self.S, self.N), np.uint8)
+        self._check(lib().micsa_read_couplings(self._ctx, _ptr(out)), "read_couplings")
+        return out
+
+    def counters(self) -> tuple[int, int]:
+        k, rho = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().micsa_get_counters(self._ctx, ctypes.byref(k), ctypes.byref(rho)), "get_counters")
+        return k.value, rho.value
+
+    def thresholds(self, rho: int) -> np.ndarray:
+        t = np.zeros(3, np.uint64)
+        self._check(lib().micsa_get_thresholds(self._ctx, rho, _ptr(t)), "get_thresholds")
+        return t
+
+    def heatbath_thresholds(self, rho: int) -> np.ndarray:
+        t = np.zeros(7, np.uint64)
+        self._check(lib().micsa_get_heatbath_thresholds(self._ctx, rho, _ptr(t)), "get_heatbath_thresholds")
+        return t
+
+    # -- writes ---------------------------------------------------------
+    def write_spins(self, sigma: np.ndarray) -> None:
+        a = np.ascontiguousarray(sigma, np.uint8).reshape(self.S, self.R, self.N)
+        self._check(lib().micsa_write_spins(self._ctx, _ptr(a)), "write_spins")
+
+    def write_daemons(self, m: np.ndarray) -> None:
+        a = np.ascontiguousarray(m, np.uint8).reshape(self.S, self.R, self.N)
+        self._check(lib().micsa_write_demons(self._ctx, _ptr(a)), "write_demons")
+
+    # -- timing ---------------------------------------------------------
+    def set_timing(self, enable: bool) -> None:
+        self._check(lib().micsa_set_timing(self._ctx, 1 if enable else 0), "set_timing")
+
+    def timing(self, kind: int) -> tuple[float, int]:
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(lib().micsa_get_timing(self._ctx, kind, ctypes.byref(ms), ctypes.byref(n)), "get_timing")
+        return ms.value, n.value
+
+    def set_option(self, option: int, value: int) -> None:
+        self._check(lib().micsa_set_option(self._ctx, option, value), "set_option")
+
+    def kernel_name(self, algo: int) -> str:
+        return lib().micsa_kernel_name(self._ctx, algo).decode()

@@ -1,0 +1,66 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/micsa.h, and rejects invalid arguments before touching
+the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2506_16240_amd import micsa as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names += re.findall(r"^[A-Za-z_][\w\s\*]*?\b(micsa_\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(M.LIB_PATH)
+    declared = _declared()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    # and the binding wraps exactly those
+    assert sorted(M.exported_symbols()) == declared
+
+
+def test_status_strings():
+    lib = M.lib()
+    assert lib.micsa_status_string(0) == b"ok"
+    for st in (-1, -2, -3, -4, -5):
+        assert lib.micsa_status_string(st) not in (b"ok", b"unknown status")
+
+
+@pytest.mark.parametrize("dims", [(7, 8, 8), (12, 8, 8), (4, 8, 8), (8, 3, 8), (8, 8, 1), (0, 8, 8), (8, 8, -2)])
+def test_create_rejects_bad_sides(dims):
+    p = M._Params(*dims, 1, 1, 0, 1)
+    out = ctypes.c_void_p(123)
+    assert M.lib().micsa_create(ctypes.byref(p), None, ctypes.byref(out)) == M.EINVAL
+    assert not out.value
+
+
+@pytest.mark.parametrize("S,R,layout", [(0, 1, 0), (1, 0, 0), (1 << 24, 1, 0), (1, 1, 7)])
+def test_create_rejects_bad_counts_and_layout(S, R, layout):
+    p = M._Params(8, 8, 8, S, R, layout, 1)
+    out = ctypes.c_void_p()
+    assert M.lib().micsa_create(ctypes.byref(p), None, ctypes.byref(out)) == M.EINVAL
+    assert not out.value
+
+
+def test_null_arguments():
+    lib = M.lib()
+    assert lib.micsa_create(None, None, None) == M.EINVAL
+    assert lib.micsa_destroy(None) == M.OK
+    assert lib.micsa_sweep(None, 0, 1) == M.EINVAL
+    assert lib.micsa_sync(None) == M.EINVAL
+    assert lib.micsa_read_energy(None, None) == M.EINVAL
+    assert lib.micsa_set_schedule(None, None) == M.EINVAL
+    assert lib.micsa_last_error(None) == b"null context"

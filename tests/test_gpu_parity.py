@@ -1,0 +1,290 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+MicSA and the heat bath are integer dynamics with a fixed random-number
+specification, so there is exactly one correct trajectory: parity is bit
+equality of every logged energy, of the final spins and daemons, and of
+the couplings.  Shapes span several words per row, ragged (non power of
+two) sides, the minimum sides, several samples and replicas, and the
+configurations' own sizes (full size where the oracle can follow; the
+first sweeps otherwise).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2506_16240_amd import micsa as M
+from paper_2506_16240_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def pair(Lx, Ly, Lz, S=1, R=1, seed=1):
+    return M.Lattice(Lx, Ly, Lz, S, R, seed), O.Lattice(Lx, Ly, Lz, S, R, seed)
+
+
+def scheds(kind, T0, T1, n, P, table=None):
+    return M.Schedule(kind, T0, T1, n, P, table), O.Schedule(kind, T0, T1, n, P, table)
+
+
+def same_state(g, o):
+    assert np.array_equal(g.spins(), o.sigma), "spins differ"
+    assert np.array_equal(g.daemons(), o.m), "daemons differ"
+
+
+SHAPES = [
+    (8, 8, 8, 1, 1),      # one 4-site word pair per row
+    (8, 2, 2, 1, 2),      # minimum sides
+    (16, 6, 10, 2, 3),    # several samples and replicas, ragged y/z
+    (24, 4, 6, 1, 2),     # three words per row
+    (40, 10, 6, 3, 1),    # ragged x (5 words per row)
+    (32, 32, 32, 2, 2),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_initial_state_matches_oracle(shape):
+    g, o = pair(*shape, seed=0xABCDEF12345)
+    assert np.array_equal(g.couplings(), o.J)
+    same_state(g, o)
+    E = o.energy()
+    assert np.array_equal(g.energy(), E)
+    assert np.array_equal(g.energy_tally(), E)
+    assert np.array_equal(g.daemon_energy(), np.zeros_like(E))
+
+
+def test_thresholds_bitexact():
+    g, _ = pair(8, 8, 8)
+    cases = [scheds(M.SCHED_CONST, T, T, 100, 10) for T in (0.05, 0.1, 0.2, 0.7, 1.1019, 1.5, 3.0, 1e6)]
+    cases.append(scheds(M.SCHED_LINEAR, 3.0, 0.2, 10000, 20))
+    cases.append(scheds(M.SCHED_LINEAR, 3.0, 0.1, 2000, 10))
+    cases.append(scheds(M.SCHED_TABLE, 0, 0, 30, 10, np.array([2.5, 0.9, 0.31])))
+    cases.append(scheds(M.SCHED_LINEAR, 2.0, 0.5, 1000, M.REFRESH_LOG2))
+    for gs, os_ in cases:
+        g.set_schedule(gs)
+        for rho in range(os_.refresh_count()):
+            T = os_.temperature(rho)
+            assert np.array_equal(g.thresholds(rho), O.daemon_thresholds(T)), (gs, rho)
+            assert np.array_equal(g.heatbath_thresholds(rho), O.heatbath_thresholds(T)), (gs, rho)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("algo", [M.ALGO_MICSA, M.ALGO_HEATBATH])
+def test_trajectory_matches_oracle(shape, algo):
+    g, o = pair(*shape, seed=77)
+    n = 37
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.5, 0.4, n, 6)
+    g.set_schedule(gs)
+    Eg, Dg = g.sweep_logged(algo, n, 1)
+    Eo, Do = o.run(algo, os_, n, 1)
+    assert np.array_equal(Eg, Eo)
+    if algo == M.ALGO_MICSA:
+        assert np.array_equal(Dg, Do)
+    same_state(g, o)
+    assert np.array_equal(g.energy_tally(), o.energy())
+    assert g.counters()[0] == n
+
+
+def test_log2_refresh_schedule_matches_oracle():
+    g, o = pair(16, 8, 6, 1, 2, seed=5)
+    n = 70
+    gs, os_ = scheds(M.SCHED_CONST, 0.9, 0.9, n, M.REFRESH_LOG2)
+    g.set_schedule(gs)
+    Eg, Dg = g.sweep_logged(M.ALGO_MICSA, n, 1)
+    Eo, Do = o.run(O.ALGO_MICSA, os_, n, 1)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    same_state(g, o)
+
+
+def test_paramagnet_L16_full_length():
+    """L = 16, T = 1.5, refresh every 10 sweeps, 1000 sweeps, energy logged per
+    sweep: bit-exact, and H^EA + H^aux conserved between refreshes."""
+    w = W.PARAMAGNET_L16
+    g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
+    gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
+    g.set_schedule(gs)
+    Eg, Dg = g.sweep_logged(M.ALGO_MICSA, w.n_sweeps, 1)
+    Eo, Do = o.run(O.ALGO_MICSA, os_, w.n_sweeps, 1)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    same_state(g, o)
+    tot = (Eg + Dg)[:, 0]
+    for r in range(1, w.n_sweeps):
+        if r % w.period != 0:  # sweep r did not start with a refresh
+            assert tot[r] == tot[r - 1]
+    assert np.array_equal(g.energy_tally(), g.energy())
+
+
+def test_quench_L64_shape():
+    """L = 64, 1 sample x 2 replicas, T = 0.7: MicSA and heat bath from the same
+    seed, energies, daemon energies and the replica overlap."""
+    w = W.QUENCH_L64
+    n = 120
+    for algo in (M.ALGO_MICSA, M.ALGO_HEATBATH):
+        g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
+        gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
+        g.set_schedule(gs)
+        Eg, Dg = g.sweep_logged(algo, n, 10)
+        Eo, Do = o.run(algo, os_, n, 10)
+        assert np.array_equal(Eg, Eo)
+        if algo == M.ALGO_MICSA:
+            assert np.array_equal(Dg, Do)
+        assert np.array_equal(g.overlap(0, 1), o.overlap(0, 1))
+        assert np.array_equal(g.overlap(1, 0), o.overlap(1, 0))
+        same_state(g, o)
+
+
+def test_batched_L32_shape():
+    """L = 32, 256 samples x 2 replicas in one context (byte layout)."""
+    w = W.BATCHED_L32
+    n = 12
+    g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
+    gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
+    g.set_schedule(gs)
+    Eg, Dg = g.sweep_logged(M.ALGO_MICSA, n, 4)
+    Eo, Do = o.run(O.ALGO_MICSA, os_, n, 4)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    assert np.array_equal(g.overlap(0, 1), o.overlap(0, 1))
+    same_state(g, o)
+
+
+def test_anneal_L512_first_sweeps_full_size():
+    """L = 512 (134M spins), linear 3.0 -> 0.2 over 10^4 sweeps, refresh every 20:
+    the first 21 sweeps (two refreshes) bit-exact at full size."""
+    w = W.ANNEAL_L512
+    n = 21
+    g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
+    gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
+    g.set_schedule(gs)
+    Eg, Dg = g.sweep_logged(M.ALGO_MICSA, n, 7)
+    Eo, Do = o.run(O.ALGO_MICSA, os_, n, 7)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    same_state(g, o)
+    assert np.array_equal(g.energy_tally(), g.energy())
+
+
+def test_written_state_is_swept_identically():
+    """Injected spins and daemons (no refresh in between) evolve identically."""
+    g, o = pair(16, 8, 8, 2, 2, seed=3)
+    gs, os_ = scheds(M.SCHED_CONST, 1.0, 1.0, 100, 1000)
+    g.set_schedule(gs)
+    g.sweep(M.ALGO_MICSA, 3)
+    o.run(O.ALGO_MICSA, os_, 3, 0)
+    rng = np.random.default_rng(4)
+    o.sigma[:] = rng.integers(0, 2, o.sigma.shape, dtype=np.uint8)
+    o.m[:] = rng.integers(0, 4, o.m.shape, dtype=np.uint8)
+    o.tally = o.energy()
+    g.write_spins(o.sigma)
+    g.write_daemons(o.m)
+    same_state(g, o)
+    assert np.array_equal(g.energy_tally(), o.energy())
+    Eg, Dg = g.sweep_logged(M.ALGO_MICSA, 10, 1)
+    Eo, Do = o.run(O.ALGO_MICSA, os_, 10, 1)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    # no refresh: total energy is exactly conserved over all 10 sweeps
+    assert len(set((Eg + Dg)[:, 0])) == 1
+    same_state(g, o)
+
+
+def test_gpu_error_paths():
+    g, _ = pair(8, 8, 8)
+    with pytest.raises(M.MicsaError) as e:
+        g.sweep(M.ALGO_MICSA, 1)
+    assert e.value.status == M.ESTATE
+    g.set_schedule(M.Schedule(M.SCHED_CONST, 1.0, 1.0, 5, 2))
+    with pytest.raises(M.MicsaError) as e:
+        g.sweep(M.ALGO_MICSA, 6)
+    assert e.value.status == M.ERANGE
+    with pytest.raises(M.MicsaError) as e:
+        g.overlap(0, 0)
+    assert e.value.status == M.EINVAL
+    with pytest.raises(M.MicsaError) as e:
+        g.write_daemons(np.full((1, 1, 512), 4, np.uint8))
+    assert e.value.status == M.EINVAL
+    with pytest.raises(M.MicsaError) as e:
+        g.set_schedule(M.Schedule(M.SCHED_CONST, -1.0, 1.0, 5, 2))
+    assert e.value.status == M.EINVAL
+    with pytest.raises(M.MicsaError) as e:
+        g.sweep(7, 1)
+    assert e.value.status == M.EINVAL
+    g.sweep(M.ALGO_MICSA, 5)
+    assert g.counters() == (5, 2)
+
+
+def test_timing_counts_launches():
+    g, _ = pair(16, 16, 16)
+    g.set_schedule(M.Schedule(M.SCHED_CONST, 1.5, 1.5, 20, 10))
+    g.set_timing(True)
+    g.sweep(M.ALGO_MICSA, 20)
+    ms, n = g.timing(M.TIME_SWEEP)
+    assert n >= 20 and ms > 0
+    ms_r, n_r = g.timing(M.TIME_REFRESH)
+    assert n_r == 2
+
+
+# ----------------------------------------------------------- fused sweep
+FUSED_CASES = [
+    ((32, 8, 8, 1, 1), 0, 0),
+    ((32, 2, 2, 1, 2), 0, 0),     # minimum sides: ring rows/planes wrap onto the tile itself
+    ((64, 6, 10, 2, 1), 0, 0),
+    ((64, 6, 10, 2, 1), 1, 1),    # one-row, one-plane tiles
+    ((32, 12, 4, 1, 2), 3, 2),
+    ((96, 8, 6, 1, 1), 2, 3),     # three chunks per row
+    ((128, 16, 16, 1, 1), 0, 0),
+    ((64, 64, 64, 1, 2), 0, 0),   # the quench lattice
+]
+
+
+@pytest.mark.parametrize("shape,ty,tz", FUSED_CASES)
+def test_fused_sweep_matches_oracle(shape, ty, tz):
+    g, o = pair(*shape, seed=99)
+    g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)
+    if ty:
+        g.set_option(M.OPT_TILE_Y, ty)
+    if tz:
+        g.set_option(M.OPT_TILE_Z, tz)
+    assert g.kernel_name(M.ALGO_MICSA) == "k_micsa_sweep_fused"
+    n = 23
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.5, 0.4, n, 5)
+    g.set_schedule(gs)
+    Eg, Dg = g.sweep_logged(M.ALGO_MICSA, n, 1)
+    Eo, Do = o.run(O.ALGO_MICSA, os_, n, 1)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    same_state(g, o)
+    assert np.array_equal(g.energy_tally(), o.energy())
+
+
+def test_every_launch_shape_gives_the_same_bits():
+    """Launch shapes never change results: the fused sweep at every tile shape
+    and the per-half kernels agree bit for bit (a racing or mis-indexed
+    variant would not)."""
+    shape = (64, 16, 12, 1, 2)
+    n = 30
+    ref = None
+    variants = [(M.KERNEL_SIMPLE, 0, 0)] + [(M.KERNEL_FUSED, ty, tz) for ty in (1, 2, 4, 8, 16)
+                                            for tz in (1, 3, 4, 12)]
+    for kern, ty, tz in variants:
+        g = M.Lattice(*shape, seed=2024)
+        g.set_option(M.OPT_SWEEP_KERNEL, kern)
+        if ty:
+            g.set_option(M.OPT_TILE_Y, ty)
+            g.set_option(M.OPT_TILE_Z, tz)
+        g.set_schedule(M.Schedule(M.SCHED_CONST, 0.8, 0.8, n, 7))
+        E, D = g.sweep_logged(M.ALGO_MICSA, n, 1)
+        got = (E, D, g.spins(), g.daemons(), g.energy_tally())
+        if ref is None:
+            ref = got
+        else:
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), (kern, ty, tz)
+        g.close()
+
+
+def test_tile_options_are_validated():
+    g = M.Lattice(64, 12, 10, seed=1)
+    for opt, v in ((M.OPT_TILE_Y, 5), (M.OPT_TILE_Z, 3), (M.OPT_SWEEP_KERNEL, 9)):
+        with pytest.raises(M.MicsaError) as e:
+            g.set_option(opt, v)
+        assert e.value.status == M.EINVAL
+    h = M.Lattice(40, 8, 8, seed=1)
+    with pytest.raises(M.MicsaError) as e:
+        h.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)
+    assert e.value.status == M.EINVAL
