@@ -1,0 +1,283 @@
+// Bit-plane (multispin-coded) layout: 64 samples per 64-bit word (Sec. 2.5
+// and App. B pack 64 spins per word; here the 64 bits of a word are the same
+// site of 64 different samples).  Lane l of lane group G is sample 64G + l;
+// each replica has its own word arrays, the couplings of a lane group are
+// shared by its replicas.
+//
+//   spin [G][R][p][h]   uint64   bit l = spin bit of sample 64G+l
+//   dm0, dm1 [G][R][p][h]        bits 0 and 1 of the daemon level m
+//   Jw [G][d][h]        uint64   coupling bit of bond d of even site h
+//
+// with the same parity split h as the byte layout (geometry.hpp): site
+// words of one row are contiguous, so the x neighbours of site k are words
+// k and k +- 1 of the other parity in the same row.
+//
+// The Creutz move is evaluated for all 64 lanes with Boolean operations
+// only (Sec. 2.5): the six unsatisfied-bond bits are added by a bit-sliced
+// adder into u = (u2 u1 u0), the two-bit daemon added to it, the legality
+// window 3 <= m + u <= 6 tested and the new level m + u - 3 formed, each as
+// a handful of 64-bit logic operations.
+#pragma once
+#include "geometry.hpp"
+#include "philox.hpp"
+
+namespace micsa {
+
+struct GeomB {
+    Geom g;
+    int32_t G;  // lane groups = ceil(S / 64)
+};
+
+// Full adder on 64 lanes.
+__device__ __forceinline__ void fadd(uint64_t a, uint64_t b, uint64_t c, uint64_t& s, uint64_t& carry)
+{
+    const uint64_t t = a ^ b;
+    s = t ^ c;
+    carry = (a & b) | (c & t);
+}
+
+// MicSA move on 64 lanes: a[0..5] are the unsatisfied-bond bits.
+__device__ __forceinline__ void creutz64(const uint64_t a[6], uint64_t& S, uint64_t& M0, uint64_t& M1)
+{
+    uint64_t s1, c1, s2, c2;
+    fadd(a[0], a[1], a[2], s1, c1);
+    fadd(a[3], a[4], a[5], s2, c2);
+    const uint64_t u0 = s1 ^ s2;
+    const uint64_t c3 = s1 & s2;
+    uint64_t u1, u2;
+    fadd(c1, c2, c3, u1, u2);
+    // w = m + u (4 bits)
+    const uint64_t w0 = M0 ^ u0;
+    const uint64_t k0 = M0 & u0;
+    uint64_t w1, k1;
+    fadd(M1, u1, k0, w1, k1);
+    const uint64_t w2 = u2 ^ k1;
+    const uint64_t w3 = u2 & k1;
+    // legal iff w in {3,4,5,6} = {0011, 0100, 0101, 0110}
+    const uint64_t acc = ~w3 & (w2 ^ (w1 & w0));
+    // new level w - 3 = (w + 1) mod 4 on the legal window
+    S ^= acc;
+    M0 = (M0 & ~acc) | (~w0 & acc);
+    M1 = (M1 & ~acc) | ((w1 ^ w0) & acc);
+}
+
+// ---------------------------------------------------------------- init
+// One wave per (lane group, site group): lane l draws for sample 64G + l and
+// __ballot assembles the 64-lane words.
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Thread = (even site h, lane); block of 256 = 4 even sites x 64 lanes.
+__global__ void __launch_bounds__(256) kb_init_couplings(GeomB b, uint64_t* __restrict__ Jw)
+{
+    const Geom& g = b.g;
+    const int G = blockIdx.y;
+    const int64_t h = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = lane_id();
+    const uint32_t s = (uint32_t)(64 * G + lane);
+    const bool live = h < g.Nh;
+    uint32_t bits[6] = {0, 0, 0, 0, 0, 0};
+    if (live && s < (uint32_t)g.S) {
+        const int k = (int)(h % g.Kx);
+        const int row = (int)(h / g.Kx);
+        const int y = row % g.Ly, z = row / g.Ly;
+        const int x = 2 * k + ((y + z) & 1);
+        const uint32_t sw = stream_word(kStreamCoupling, s);
+        auto fwd = [&](int xx, int yy, int zz) {
+            xx = (xx + g.Lx) % g.Lx;
+            yy = (yy + g.Ly) % g.Ly;
+            zz = (zz + g.Lz) % g.Lz;
+            const uint32_t i = (uint32_t)(xx + (int64_t)g.Lx * (yy + (int64_t)g.Ly * zz));
+            return philox10(i, 0u, 0u, sw, g.key0, g.key1);
+        };
+        const u32x4 o = fwd(x, y, z);
+        bits[0] = o.v0 >> 31;
+        bits[1] = fwd(x - 1, y, z).v0 >> 31;
+        bits[2] = o.v1 >> 31;
+        bits[3] = fwd(x, y - 1, z).v1 >> 31;
+        bits[4] = o.v2 >> 31;
+        bits[5] = fwd(x, y, z - 1).v2 >> 31;
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+        const uint64_t w = __ballot(bits[d] != 0);
+        if (live && lane == 0) Jw[((int64_t)G * 6 + d) * g.Nh + h] = w;
+    }
+}
+
+// Thread = (4 consecutive natural sites, lane), one Philox call per thread;
+// the 4 sites are 2 even and 2 odd (Lx % 4 == 0), stored at h = i0/2, i0/2+1.
+template <typename F>
+__device__ __forceinline__ void ballot4(const Geom& g, int64_t i0, const u32x4& o, F&& planes_of,
+                                        uint64_t* __restrict__ arr0, uint64_t* __restrict__ arr1, bool live)
+{
+    const int x0 = (int)(i0 % g.Lx);
+    const int64_t row = i0 / g.Lx;
+    const int y = (int)(row % g.Ly), z = (int)(row / g.Ly);
+    const uint32_t d[4] = {o.v0, o.v1, o.v2, o.v3};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        uint32_t b0, b1;
+        planes_of(d[t], b0, b1);
+        const uint64_t w0 = __ballot(b0 != 0);
+        const uint64_t w1 = __ballot(b1 != 0);
+        if (live && lane_id() == 0) {
+            const int p = (x0 + t + y + z) & 1;
+            const int64_t h = (i0 + t) >> 1;
+            arr0[p * g.Nh + h] = w0;
+            if (arr1) arr1[p * g.Nh + h] = w1;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) kb_init_spins(GeomB b, uint64_t* __restrict__ spin)
+{
+    const Geom& g = b.g;
+    const int wl = blockIdx.y;  // word lattice = G * R + r
+    const int G = wl / g.R, r = wl % g.R;
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const bool live = t < g.Nh / 2;
+    const uint32_t s = (uint32_t)(64 * G + lane_id());
+    u32x4 o = {0, 0, 0, 0};
+    const int64_t i0 = 4 * t;
+    if (live && s < (uint32_t)g.S)
+        o = philox10((uint32_t)t, 0u, (uint32_t)r, stream_word(kStreamSpin, s), g.key0, g.key1);
+    ballot4(g, live ? i0 : 0, o, [](uint32_t u, uint32_t& b0, uint32_t& b1) { b0 = u >> 31; b1 = 0; },
+            spin + (int64_t)wl * 2 * g.Nh, nullptr, live);
+}
+
+__global__ void __launch_bounds__(256) kb_refresh(GeomB b, uint64_t* __restrict__ dm0, uint64_t* __restrict__ dm1,
+                                                  uint32_t rho, DaemonThresholds th)
+{
+    const Geom& g = b.g;
+    const int wl = blockIdx.y;
+    const int G = wl / g.R, r = wl % g.R;
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const bool live = t < g.Nh / 2;
+    const uint32_t s = (uint32_t)(64 * G + lane_id());
+    u32x4 o = {0, 0, 0, 0};
+    if (live && s < (uint32_t)g.S)
+        o = philox10((uint32_t)t, rho, (uint32_t)r, stream_word(kStreamDaemon, s), g.key0, g.key1);
+    ballot4(g, live ? 4 * t : 0, o,
+            [&](uint32_t u, uint32_t& b0, uint32_t& b1) {
+                const uint64_t v = u;
+                const uint32_t m = (uint32_t)(v >= th.t0) + (uint32_t)(v >= th.t1) + (uint32_t)(v >= th.t2);
+                b0 = m & 1u;
+                b1 = m >> 1;
+            },
+            dm0 + (int64_t)wl * 2 * g.Nh, dm1 + (int64_t)wl * 2 * g.Nh, live);
+}
+
+// ------------------------------------------------------------- half sweep
+// Thread per site word (64 lanes) of parity P.
+template <int P>
+__global__ void __launch_bounds__(256) kb_micsa_half(GeomB b, uint64_t* __restrict__ spin,
+                                                     uint64_t* __restrict__ dm0, uint64_t* __restrict__ dm1,
+                                                     const uint64_t* __restrict__ Jw)
+{
+    const Geom& g = b.g;
+    const int wl = blockIdx.y;
+    const int G = wl / g.R;
+    const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= (uint32_t)g.Nh) return;
+    const int row = (int)(h / (uint32_t)g.Kx), k = (int)(h - (uint32_t)row * (uint32_t)g.Kx);
+    const int z = row / g.Ly, y = row - z * g.Ly;
+    const int q = (y + z) & 1;
+    const int dir = (q ^ P) ? 1 : -1;
+    const int ks = dir > 0 ? (k + 1 == g.Kx ? 0 : k + 1) : (k == 0 ? g.Kx - 1 : k - 1);
+    const int yp = y + 1 == g.Ly ? 0 : y + 1, ym = y == 0 ? g.Ly - 1 : y - 1;
+    const int zp = z + 1 == g.Lz ? 0 : z + 1, zm = z == 0 ? g.Lz - 1 : z - 1;
+    const int64_t K = g.Kx;
+    const int64_t hA = h, hB = (int64_t)row * K + ks, hYp = (int64_t)(yp + g.Ly * z) * K + k,
+                  hYm = (int64_t)(ym + g.Ly * z) * K + k, hZp = (int64_t)(y + g.Ly * zp) * K + k,
+                  hZm = (int64_t)(y + g.Ly * zm) * K + k;
+    const int64_t base = (int64_t)wl * 2 * g.Nh;
+    const uint64_t* oth = spin + base + (1 - P) * g.Nh;
+    const uint64_t* Jg = Jw + (int64_t)G * 6 * g.Nh;
+    const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
+    uint64_t j[6];
+    if (P == 0) {
+        j[0] = Jg[dA * g.Nh + hA];
+        j[1] = Jg[dB * g.Nh + hA];
+        j[2] = Jg[kPy * g.Nh + hA];
+        j[3] = Jg[kMy * g.Nh + hA];
+        j[4] = Jg[kPz * g.Nh + hA];
+        j[5] = Jg[kMz * g.Nh + hA];
+    } else {
+        j[0] = Jg[dA * g.Nh + hA];
+        j[1] = Jg[dB * g.Nh + hB];
+        j[2] = Jg[kMy * g.Nh + hYp];
+        j[3] = Jg[kPy * g.Nh + hYm];
+        j[4] = Jg[kMz * g.Nh + hZp];
+        j[5] = Jg[kPz * g.Nh + hZm];
+    }
+    const int64_t own = base + P * g.Nh + h;
+    uint64_t S = spin[own], M0 = dm0[own], M1 = dm1[own];
+    const uint64_t a[6] = {S ^ oth[hA] ^ j[0], S ^ oth[hB] ^ j[1], S ^ oth[hYp] ^ j[2],
+                           S ^ oth[hYm] ^ j[3], S ^ oth[hZp] ^ j[4], S ^ oth[hZm] ^ j[5]};
+    creutz64(a, S, M0, M1);
+    spin[own] = S;
+    dm0[own] = M0;
+    dm1[own] = M1;
+}
+
+// ------------------------------------------------------------ reductions
+// Per-lane counts: one wave per block; lane l owns sample 64G + l and counts
+// its bit of every word the wave reads (the same word for all lanes).
+// kind 0: unsatisfied bonds U (H = 2U - 3N); 1: daemon levels sum m;
+// 2: sites where replicas a and b differ.
+template <int KIND>
+__global__ void __launch_bounds__(64) kb_lane_count(GeomB b, const uint64_t* __restrict__ spin,
+                                                   const uint64_t* __restrict__ dm0,
+                                                   const uint64_t* __restrict__ dm1,
+                                                   const uint64_t* __restrict__ Jw, int ra, int rb,
+                                                   int64_t sites_per_block, unsigned long long* __restrict__ out)
+{
+    const Geom& g = b.g;
+    const int wl = blockIdx.y;  // KIND 2: lane group; otherwise word lattice
+    const int G = KIND == 2 ? wl : wl / g.R, r = KIND == 2 ? 0 : wl % g.R;
+    const int lane = lane_id();
+    const int64_t h0 = (int64_t)blockIdx.x * sites_per_block;
+    const int64_t h1 = h0 + sites_per_block < g.Nh ? h0 + sites_per_block : g.Nh;
+    long long cnt = 0;
+    if (KIND == 0) {
+        const uint64_t* ev = spin + (int64_t)wl * 2 * g.Nh;
+        const uint64_t* od = ev + g.Nh;
+        const uint64_t* Jg = Jw + (int64_t)G * 6 * g.Nh;
+        for (int64_t h = h0; h < h1; ++h) {
+            const int row = (int)(h / g.Kx), k = (int)(h - (int64_t)row * g.Kx);
+            const int z = row / g.Ly, y = row - z * g.Ly;
+            const int q = (y + z) & 1;
+            const int ks = q ? (k + 1 == g.Kx ? 0 : k + 1) : (k == 0 ? g.Kx - 1 : k - 1);
+            const int yp = y + 1 == g.Ly ? 0 : y + 1, ym = y == 0 ? g.Ly - 1 : y - 1;
+            const int zp = z + 1 == g.Lz ? 0 : z + 1, zm = z == 0 ? g.Lz - 1 : z - 1;
+            const int64_t K = g.Kx;
+            const uint64_t S = ev[h];
+            const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
+            const uint64_t w[6] = {S ^ od[h] ^ Jg[dA * g.Nh + h], S ^ od[(int64_t)row * K + ks] ^ Jg[dB * g.Nh + h],
+                                   S ^ od[(int64_t)(yp + g.Ly * z) * K + k] ^ Jg[kPy * g.Nh + h],
+                                   S ^ od[(int64_t)(ym + g.Ly * z) * K + k] ^ Jg[kMy * g.Nh + h],
+                                   S ^ od[(int64_t)(y + g.Ly * zp) * K + k] ^ Jg[kPz * g.Nh + h],
+                                   S ^ od[(int64_t)(y + g.Ly * zm) * K + k] ^ Jg[kMz * g.Nh + h]};
+#pragma unroll
+            for (int d = 0; d < 6; ++d) cnt += (long long)((w[d] >> lane) & 1u);
+        }
+    } else if (KIND == 1) {
+        const uint64_t* m0 = dm0 + (int64_t)wl * 2 * g.Nh;
+        const uint64_t* m1 = dm1 + (int64_t)wl * 2 * g.Nh;
+        for (int64_t h = h0; h < h1; ++h)
+            for (int p = 0; p < 2; ++p)
+                cnt += (long long)((m0[p * g.Nh + h] >> lane) & 1u) + 2 * (long long)((m1[p * g.Nh + h] >> lane) & 1u);
+    } else {
+        const uint64_t* sa = spin + ((int64_t)G * g.R + ra) * 2 * g.Nh;
+        const uint64_t* sb = spin + ((int64_t)G * g.R + rb) * 2 * g.Nh;
+        for (int64_t h = h0; h < h1; ++h)
+            for (int p = 0; p < 2; ++p) cnt += (long long)(((sa[p * g.Nh + h] ^ sb[p * g.Nh + h]) >> lane) & 1u);
+    }
+    const int s = 64 * G + lane;
+    if (s < g.S && cnt != 0) {
+        const int64_t ent = KIND == 2 ? s : (int64_t)s * g.R + r;
+        atomicAdd(&out[ent * kSlots + (blockIdx.x % kSlots)], (unsigned long long)cnt);
+    }
+}
+
+}  // namespace micsa

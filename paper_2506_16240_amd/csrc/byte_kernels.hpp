@@ -35,47 +35,44 @@ __device__ __forceinline__ Nbhd gather(const Geom& g, const uint32_t* __restrict
     n.nb[3] = oth[r_ym * wr + c];
     n.nb[4] = oth[r_zp * wr + c];
     n.nb[5] = oth[r_zm * wr + c];
-    const int64_t K = g.Kx;
-    const int64_t h0 = row * K + 4 * c;
-    // The same-k neighbour A pairs with plane (q ? -x : +x) of the even site at
-    // A's position, the shifted neighbour B with (q ? +x : -x); this holds for
-    // both parities because the even site is at x = 2k + q.
+    // The same-k neighbour A is across bond (q ? -x : +x) of the even site at
+    // A's position, the shifted neighbour B across (q ? +x : -x); this holds
+    // for both parities because the even site is at x = 2k + q.
     const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
     if (P == 0) {
         // even sites own all six of their bonds
-        n.jb[0] = jnib(Js, g.P32, dA, h0);
-        n.jb[1] = jnib(Js, g.P32, dB, h0);
-        n.jb[2] = jnib(Js, g.P32, kPy, h0);
-        n.jb[3] = jnib(Js, g.P32, kMy, h0);
-        n.jb[4] = jnib(Js, g.P32, kPz, h0);
-        n.jb[5] = jnib(Js, g.P32, kMz, h0);
+        const uint32_t jw = Js[row * wr + c];
+        n.jb[0] = jbits(jw, dA);
+        n.jb[1] = jbits(jw, dB);
+        n.jb[2] = jbits(jw, kPy);
+        n.jb[3] = jbits(jw, kMy);
+        n.jb[4] = jbits(jw, kPz);
+        n.jb[5] = jbits(jw, kMz);
     } else {
-        // odd sites read each bond from the even neighbour's opposite plane
-        n.jb[0] = jnib(Js, g.P32, dA, h0);
-        n.jb[1] = shift_nib(jnib(Js, g.P32, dB, h0), jnib(Js, g.P32, dB, row * K + 4 * cs), dir);
-        n.jb[2] = jnib(Js, g.P32, kMy, r_yp * K + 4 * c);
-        n.jb[3] = jnib(Js, g.P32, kPy, r_ym * K + 4 * c);
-        n.jb[4] = jnib(Js, g.P32, kMz, r_zp * K + 4 * c);
-        n.jb[5] = jnib(Js, g.P32, kPz, r_zm * K + 4 * c);
+        // odd sites read each bond from the even neighbour's opposite slot
+        const uint32_t jA = Js[row * wr + c];
+        n.jb[0] = jbits(jA, dA);
+        n.jb[1] = jbits(shift_word(jA, Js[row * wr + cs], dir), dB);
+        n.jb[2] = jbits(Js[r_yp * wr + c], kMy);
+        n.jb[3] = jbits(Js[r_ym * wr + c], kPy);
+        n.jb[4] = jbits(Js[r_zp * wr + c], kMz);
+        n.jb[5] = jbits(Js[r_zm * wr + c], kPz);
     }
-#pragma unroll
-    for (int d = 0; d < 6; ++d) n.jb[d] = spread4(n.jb[d]);
     return n;
 }
 
 // ------------------------------------------------------------------ init
-// Thread per 32 even sites: the six bond bits of each even site from the
+// Thread per 4 even sites: the six bond bits of each even site from the
 // forward-bond draws j_mu(i) = Philox(i, 0, 0, stream J | s)[mu] >> 31.
 __global__ void k_init_couplings(Geom g, uint32_t* __restrict__ J)
 {
     const int s = blockIdx.y;
-    const int64_t wi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (wi >= g.P32) return;
-    uint32_t word[6] = {0, 0, 0, 0, 0, 0};
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= g.Nh / 4) return;
     const uint32_t sw = stream_word(kStreamCoupling, (uint32_t)s);
-    for (int b = 0; b < 32; ++b) {
-        const int64_t h = wi * 32 + b;
-        if (h >= g.Nh) break;
+    uint32_t word = 0;
+    for (int b = 0; b < 4; ++b) {
+        const int64_t h = 4 * t + b;
         const int k = (int)(h % g.Kx);
         const int row = (int)(h / g.Kx);
         const int y = row % g.Ly, z = row / g.Ly;
@@ -88,13 +85,12 @@ __global__ void k_init_couplings(Geom g, uint32_t* __restrict__ J)
             return philox10(i, 0u, 0u, sw, g.key0, g.key1);
         };
         const u32x4 o = fwd(x, y, z);
-        const uint32_t bits[6] = {o.v0 >> 31, fwd(x - 1, y, z).v0 >> 31, o.v1 >> 31,
-                                  fwd(x, y - 1, z).v1 >> 31, o.v2 >> 31, fwd(x, y, z - 1).v2 >> 31};
-#pragma unroll
-        for (int d = 0; d < 6; ++d) word[d] |= bits[d] << b;
+        const uint32_t byte = (o.v0 >> 31) | ((fwd(x - 1, y, z).v0 >> 31) << kMx) | ((o.v1 >> 31) << kPy) |
+                              ((fwd(x, y - 1, z).v1 >> 31) << kMy) | ((o.v2 >> 31) << kPz) |
+                              ((fwd(x, y, z - 1).v2 >> 31) << kMz);
+        word |= byte << (8 * b);
     }
-#pragma unroll
-    for (int d = 0; d < 6; ++d) J[((int64_t)s * 6 + d) * g.P32 + wi] = word[d];
+    J[(int64_t)s * (g.Nh / 4) + t] = word;
 }
 
 // Thread per 8 consecutive natural sites i0 .. i0+7 (same row since Lx % 8 == 0):
@@ -136,9 +132,6 @@ __global__ void k_init_spins(Geom g, uint8_t* __restrict__ spin)
 }
 
 // Daemon refresh (Sec. 2.7, eq. prob-daemons-walkers): m = #{k : u >= t_k}.
-struct DaemonThresholds {
-    uint64_t t0, t1, t2;
-};
 
 __global__ void k_refresh(Geom g, uint8_t* __restrict__ dem, uint32_t rho, DaemonThresholds th)
 {
@@ -196,7 +189,7 @@ __global__ void __launch_bounds__(256) k_micsa_half(Geom g, uint8_t* __restrict_
         uint32_t* own = reinterpret_cast<uint32_t*>(spin + ((int64_t)l * 2 + P) * g.Nh);
         const uint32_t* oth = reinterpret_cast<const uint32_t*>(spin + ((int64_t)l * 2 + (1 - P)) * g.Nh);
         uint32_t* dm = reinterpret_cast<uint32_t*>(dem + ((int64_t)l * 2 + P) * g.Nh);
-        const Nbhd n = gather<P>(g, oth, J + (int64_t)s * 6 * g.P32, row, c);
+        const Nbhd n = gather<P>(g, oth, J + (int64_t)s * (g.Nh / 4), row, c);
         uint32_t S = own[w], M = dm[w];
         micsa_word(S, M, n, dE);
         own[w] = S;
@@ -208,9 +201,6 @@ __global__ void __launch_bounds__(256) k_micsa_half(Geom g, uint8_t* __restrict_
 // ------------------------------------------------------ heat-bath half sweep
 // New spin +1 iff u < tau[v], v = #neighbours with J s_nb = -1 (h = 6 - 2v);
 // u = Philox(h>>2, 2k+p, r, stream HB | s)[h & 3] for parity-split index h.
-struct HeatBathThresholds {
-    uint64_t tau[7];
-};
 
 template <int P>
 __global__ void __launch_bounds__(256) k_heatbath_half(Geom g, uint8_t* __restrict__ spin,
@@ -229,7 +219,7 @@ __global__ void __launch_bounds__(256) k_heatbath_half(Geom g, uint8_t* __restri
         const int row = (int)(w / (uint32_t)g.Wr), c = (int)(w - (uint32_t)row * (uint32_t)g.Wr);
         uint32_t* own = reinterpret_cast<uint32_t*>(spin + ((int64_t)l * 2 + P) * g.Nh);
         const uint32_t* oth = reinterpret_cast<const uint32_t*>(spin + ((int64_t)l * 2 + (1 - P)) * g.Nh);
-        const Nbhd n = gather<P>(g, oth, J + (int64_t)s * 6 * g.P32, row, c);
+        const Nbhd n = gather<P>(g, oth, J + (int64_t)s * (g.Nh / 4), row, c);
         uint32_t v = 0;
 #pragma unroll
         for (int d = 0; d < 6; ++d) v += n.nb[d] ^ n.jb[d];
@@ -266,7 +256,7 @@ __global__ void __launch_bounds__(256) k_unsat_bonds(Geom g, const uint8_t* __re
         const int row = (int)(w / (uint32_t)g.Wr), c = (int)(w - (uint32_t)row * (uint32_t)g.Wr);
         const uint32_t* ev = reinterpret_cast<const uint32_t*>(spin + ((int64_t)l * 2 + 0) * g.Nh);
         const uint32_t* od = reinterpret_cast<const uint32_t*>(spin + ((int64_t)l * 2 + 1) * g.Nh);
-        const Nbhd n = gather<0>(g, od, J + (int64_t)s * 6 * g.P32, row, c);
+        const Nbhd n = gather<0>(g, od, J + (int64_t)s * (g.Nh / 4), row, c);
         const uint32_t S = ev[w];
         uint32_t u = 0;
 #pragma unroll

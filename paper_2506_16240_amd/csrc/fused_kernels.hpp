@@ -77,16 +77,35 @@ __device__ __forceinline__ V4 shift16(const V4& a, uint32_t nbw, int dir)
     return r;
 }
 
+// Three-input bit operations in one v_bitop3: the truth table indexes the
+// bits as (a << 2) | (b << 1) | c.
+__device__ __forceinline__ uint32_t xor_and(uint32_t a, uint32_t b, uint32_t c)  // a ^ (b & c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x78);
+}
+__device__ __forceinline__ uint32_t and_andn(uint32_t a, uint32_t b, uint32_t c)  // a & ~b & c
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x20);
+}
+__device__ __forceinline__ uint32_t bitsel(uint32_t a, uint32_t b, uint32_t c)  // a ? b : c, bitwise
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xCA);
+}
+
 // Creutz move on 4 byte-sites given their unsatisfied-bond counts u (see
-// micsa_word): legal iff t = m + u + 5 lies in 8..11; new level t & 3.
-__device__ __forceinline__ void creutz4(uint32_t& S, uint32_t& M, uint32_t u, int& dE)
+// micsa_word): legal iff t = m + u + 5 lies in 8..11, new level t & 3.
+// Energy: an accepted move changes H by dH = 4 (m - m') exactly (eq.
+// Creutz), a rejected one leaves m' = m, so the tally needs only the byte
+// sums of the old and new levels (v_sad_u8 accumulates them).
+__device__ __forceinline__ void creutz4(uint32_t& S, uint32_t& M, uint32_t u, uint32_t& sum_old, uint32_t& sum_new)
 {
     const uint32_t t = M + u + 0x05050505u;
-    const uint32_t acc = (t >> 3) & ~(t >> 2) & 0x01010101u;
-    const uint32_t mask = acc * 0xFFu;
+    const uint32_t acc = and_andn(t >> 3, t >> 2, 0x01010101u);
+    const uint32_t low2 = (acc << 1) + acc;  // 0x03 in accepted bytes
     S ^= acc;
-    M = (M & ~mask) | (t & 0x03030303u & mask);
-    dE += 12 * (int)__popc(acc) - 4 * (int)bytesum(u & mask);
+    sum_old = __builtin_amdgcn_sad_u8(M, 0u, sum_old);
+    M = bitsel(low2, t, M);
+    sum_new = __builtin_amdgcn_sad_u8(M, 0u, sum_new);
 }
 
 // Daemon levels of the 16 even and 16 odd sites of chunk c of a row from the
@@ -113,10 +132,11 @@ __device__ __forceinline__ void refresh_chunk(const Geom& g, int row, int c, int
     }
 }
 
+template <bool REFRESH>
 __global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
     Geom g, FusedTile f, const uint8_t* __restrict__ spin_in, const uint8_t* __restrict__ dem_in,
     uint8_t* __restrict__ spin_out, uint8_t* __restrict__ dem_out, const uint32_t* __restrict__ J,
-    unsigned long long* __restrict__ tally, int refresh, uint32_t rho, DaemonThresholds th)
+    unsigned long long* __restrict__ tally, uint32_t rho, DaemonThresholds th)
 {
     extern __shared__ uint4 lds[];
     const int rows_slots = f.TY + 4;
@@ -143,43 +163,48 @@ __global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
     uint8_t* od_out = spin_out + ((int64_t)l * 2 + 1) * g.Nh;
     uint8_t* me_out = dem_out + ((int64_t)l * 2 + 0) * g.Nh;
     uint8_t* mo_out = dem_out + ((int64_t)l * 2 + 1) * g.Nh;
-    const uint16_t* J16 = reinterpret_cast<const uint16_t*>(J + (int64_t)s * 6 * g.P32);
-    const int64_t plane16 = (int64_t)g.P32 * 2;  // uint16 words per coupling plane
+    const uint8_t* Jb = reinterpret_cast<const uint8_t*>(J) + (int64_t)s * g.Nh;  // coupling bytes
     const uint32_t sw = stream_word(kStreamDaemon, (uint32_t)s);
 
     auto wrapz = [&](int z) { return z < 0 ? z + g.Lz : (z >= g.Lz ? z - g.Lz : z); };
     auto hof = [&](int z) { return ((int64_t)y + (int64_t)g.Ly * z) * g.Kx + 16 * c; };
     const int cn = c + 1 == f.NC ? 0 : c + 1, cp = c == 0 ? f.NC - 1 : c - 1;
+    const int steps = f.TZ + 2;
 
+    // Step st works on plane z = z0 - 1 + st (even half) and z - 1 (odd half).
+    // Global loads are issued one step ahead (the "n" registers).
     V4 So_prev{}, So_cur{}, So_next{};  // odd spins (old) at planes z-1, z, z+1
     V4 X_prev2{}, X_prev{}, X_cur{};    // even views at planes z-2, z-1, z
     V4 Mo_gen{};                        // refreshed odd levels of plane z-1
+    V4 nSo{}, nSe{}, nJw{}, nMe{}, nMo{};
+    auto load_step = [&](int st2) {  // inputs of step st2 (plane z2 = z0 - 1 + st2)
+        const int z2 = wrapz(z0 - 1 + st2);
+        if (active) nSo = ldg16(od_in + hof(wrapz(z2 + 1)));
+        if (do_even) {
+            const int64_t h2 = hof(z2);
+            nSe = ldg16(ev_in + h2);
+            nJw = ldg16(Jb + h2);
+            if (!REFRESH) nMe = ldg16(me_in + h2);
+        }
+        if (!REFRESH && do_odd && st2 >= 2) nMo = ldg16(mo_in + hof(wrapz(z2 - 1)));
+    };
     if (active) {
         So_prev = ldg16(od_in + hof(wrapz(z0 - 2)));
         So_cur = ldg16(od_in + hof(wrapz(z0 - 1)));
     }
-    int dE = 0;
-    const int steps = f.TZ + 2;
+    load_step(0);
+    uint32_t sum_old = 0, sum_new = 0;  // daemon level sums before/after owned moves
     for (int st = 0; st < steps; ++st) {
         const int buf = st & 1;
         const int z = wrapz(z0 - 1 + st);
         const int64_t h = hof(z);
-        V4 Se{}, Me{}, Mo_next{}, Mo{};
-        uint32_t j16[6] = {0, 0, 0, 0, 0, 0};
-        if (active) So_next = ldg16(od_in + hof(wrapz(z + 1)));
-        if (do_even) {
-            Se = ldg16(ev_in + h);
-            const int64_t hj = h >> 4;
-#pragma unroll
-            for (int d = 0; d < 6; ++d) j16[d] = J16[d * plane16 + hj];
-            if (refresh)
-                refresh_chunk(g, y + g.Ly * z, c, (y + z) & 1, rho, (uint32_t)r, sw, th, Me, Mo_next);
-            else
-                Me = ldg16(me_in + h);
-        }
+        So_next = nSo;
+        V4 Se = nSe, Jw = nJw, Me = nMe, Mo = nMo;
+        V4 Mo_next{};
+        if (st + 1 < steps) load_step(st + 1);
+        if (REFRESH && do_even) refresh_chunk(g, y + g.Ly * z, c, (y + z) & 1, rho, (uint32_t)r, sw, th, Me, Mo_next);
         const bool odd_now = do_odd && st >= 2;
         const int zo = wrapz(z - 1);
-        if (odd_now && !refresh) Mo = ldg16(mo_in + hof(zo));
         if (active) sts16(&So[buf * plane_slots + ry * f.NC + c], So_cur);
         __syncthreads();
 
@@ -193,30 +218,33 @@ __global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
             const V4 B = shift16(A, nbw, dir);
             const V4 Yp = lds16(&So[buf * plane_slots + (ry + 1) * f.NC + c]);
             const V4 Ym = lds16(&So[buf * plane_slots + (ry - 1) * f.NC + c]);
+            // the same-k odd neighbour is across +x (q = 0) or -x (q = 1)
             const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
             const bool owned = do_odd && st >= 1 && st <= f.TZ;
-            int dEe = 0;
+            uint32_t so = 0, sn = 0;
             V4 Xn;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                uint32_t jb[6];
-#pragma unroll
-                for (int d = 0; d < 6; ++d) jb[d] = spread4((j16[d] >> (4 * i)) & 0xFu);
+                // bit d of v = old spin ^ j_d: the bond term for neighbour nb is nb ^ ((v >> d) & 1)
                 uint32_t S = Se.w[i];
-                const uint32_t u = xor3(S, A.w[i], jb[dA]) + xor3(S, B.w[i], jb[dB]) + xor3(S, Yp.w[i], jb[kPy]) +
-                                   xor3(S, Ym.w[i], jb[kMy]) + xor3(S, So_next.w[i], jb[kPz]) +
-                                   xor3(S, So_prev.w[i], jb[kMz]);
-                creutz4(S, Me.w[i], u, dEe);
+                const uint32_t v = ((S << 6) - S) ^ Jw.w[i];
+                const uint32_t m1 = 0x01010101u;
+                const uint32_t u = xor_and(A.w[i], v >> dA, m1) + xor_and(B.w[i], v >> dB, m1) +
+                                   xor_and(Yp.w[i], v >> kPy, m1) + xor_and(Ym.w[i], v >> kMy, m1) +
+                                   xor_and(So_next.w[i], v >> kPz, m1) + xor_and(So_prev.w[i], v >> kMz, m1);
+                const uint32_t S0 = S;
+                creutz4(S, Me.w[i], u, so, sn);
                 Se.w[i] = S;
-                Xn.w[i] = (S * 0x3Fu) ^ (jb[0] | (jb[1] << 1) | (jb[2] << 2) | (jb[3] << 3) | (jb[4] << 4) |
-                                         (jb[5] << 5));
+                const uint32_t flip = S ^ S0;
+                Xn.w[i] = v ^ ((flip << 6) - flip);  // even view: bit d = new spin ^ j_d
             }
             X_cur = Xn;
             sts16(&Xs[buf * plane_slots + ry * f.NC + c], Xn);
             if (owned) {  // ring rows and halo planes are recomputed, not owned
                 stg16(ev_out + h, Se);
                 stg16(me_out + h, Me);
-                dE += dEe;
+                sum_old += so;
+                sum_new += sn;
             }
         }
         if (odd_now) {
@@ -231,16 +259,16 @@ __global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
             const V4 Yp = lds16(&Xs[pb * plane_slots + (ry + 1) * f.NC + c]);
             const V4 Ym = lds16(&Xs[pb * plane_slots + (ry - 1) * f.NC + c]);
             const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
-            if (refresh) Mo = Mo_gen;
+            if (REFRESH) Mo = Mo_gen;
             V4 So_new;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 uint32_t S = So_prev.w[i];
-                const uint32_t u = (S ^ ((A.w[i] >> dA) & 0x01010101u)) + (S ^ ((B.w[i] >> dB) & 0x01010101u)) +
-                                   (S ^ ((Yp.w[i] >> kMy) & 0x01010101u)) + (S ^ ((Ym.w[i] >> kPy) & 0x01010101u)) +
-                                   (S ^ ((X_cur.w[i] >> kMz) & 0x01010101u)) +
-                                   (S ^ ((X_prev2.w[i] >> kPz) & 0x01010101u));
-                creutz4(S, Mo.w[i], u, dE);
+                const uint32_t m1 = 0x01010101u;
+                const uint32_t u = xor_and(S, A.w[i] >> dA, m1) + xor_and(S, B.w[i] >> dB, m1) +
+                                   xor_and(S, Yp.w[i] >> kMy, m1) + xor_and(S, Ym.w[i] >> kPy, m1) +
+                                   xor_and(S, X_cur.w[i] >> kMz, m1) + xor_and(S, X_prev2.w[i] >> kPz, m1);
+                creutz4(S, Mo.w[i], u, sum_old, sum_new);
                 So_new.w[i] = S;
             }
             const int64_t ho = hof(zo);
@@ -253,7 +281,8 @@ __global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
         X_prev = X_cur;
         Mo_gen = Mo_next;
     }
-    block_add(tally + (int64_t)l * kSlots, dE);
+    // dH = 4 (sum of old levels - sum of new levels) over the owned moves
+    block_add(tally + (int64_t)l * kSlots, 4 * ((long long)sum_old - (long long)sum_new));
 }
 
 }  // namespace micsa

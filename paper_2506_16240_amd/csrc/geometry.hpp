@@ -12,9 +12,10 @@
 //   k +- 1 of the same row -- so 4 sites packed in a 32-bit word see their
 //   neighbours as whole words (or one byte-shifted word).
 //   Couplings: every bond joins an even and an odd site, so each bond is
-//   stored once, with its even end, as a bit in one of six planes
-//   d = +x, -x, +y, -y, +z, -z over the even sites: J[s][d][h / 32] bit h % 32.
-//   That is 6 bits per even site = 3 bits per site.
+//   stored once, with its even end: one byte per even site whose bit d is the
+//   coupling bit of its bond in direction d = +x, -x, +y, -y, +z, -z
+//   (J[s][h], 6 bits used).  Four even sites' bytes form a 32-bit word in the
+//   same SWAR order as their spins, so bond d of 4 sites is (word >> d) & 0x01010101.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -29,30 +30,26 @@ struct Geom {
     int32_t Wr;    // 4-site words per row = Kx / 4
     int32_t rows;  // Ly * Lz
     int64_t Nh;    // N / 2: sites of one parity
-    int32_t P32;   // 32-bit words per coupling plane
     int32_t S, R;  // samples, replicas per sample
     uint32_t key0, key1;
+};
+
+// Daemon levels are drawn as m = #{k : u >= t_k} from a 32-bit uniform u,
+// t_k = floor(2^32 P(m <= k)) (eq. prob-daemons-walkers); the heat bath sets
+// s = +1 iff u < tau[v].  Thresholds are 64-bit so 2^32 ("always") fits.
+struct DaemonThresholds {
+    uint64_t t0, t1, t2;
+};
+
+struct HeatBathThresholds {
+    uint64_t tau[7];
 };
 
 // Byte-wise sum of a 32-bit word whose bytes add up to less than 256.
 __device__ __forceinline__ uint32_t bytesum(uint32_t v) { return (v * 0x01010101u) >> 24; }
 
-// Spread a nibble b3b2b1b0 into bytes: bit i -> bit 0 of byte i.  The
-// partial products b << 7i never overlap, so no carries cross bytes.
-__device__ __forceinline__ uint32_t spread4(uint32_t nib) { return (nib * 0x00204081u) & 0x01010101u; }
-
-// 4 bits of coupling plane d for the even sites h .. h+3 (h % 4 == 0).
-__device__ __forceinline__ uint32_t jnib(const uint32_t* __restrict__ Js, int32_t P32, int d, int64_t h)
-{
-    return (__ldg(&Js[(int64_t)d * P32 + (h >> 5)]) >> (h & 31)) & 0xFu;
-}
-
-// Nibble of the group shifted by one site along the row: dir > 0 takes
-// sites k+1 .. k+4 (n1 = group after), dir < 0 takes k-1 .. k+2 (n1 = group before).
-__device__ __forceinline__ uint32_t shift_nib(uint32_t n0, uint32_t n1, int dir)
-{
-    return dir > 0 ? ((n0 >> 1) | ((n1 & 1u) << 3)) : (((n0 << 1) & 0xFu) | (n1 >> 3));
-}
+// Coupling bits of bond d for the 4 sites of a word of coupling bytes.
+__device__ __forceinline__ uint32_t jbits(uint32_t jw, int d) { return (jw >> d) & 0x01010101u; }
 
 // Same shift for a word of 4 byte-sites.
 __device__ __forceinline__ uint32_t shift_word(uint32_t w0, uint32_t w1, int dir)
@@ -60,7 +57,11 @@ __device__ __forceinline__ uint32_t shift_word(uint32_t w0, uint32_t w1, int dir
     return dir > 0 ? ((w0 >> 8) | (w1 << 24)) : ((w0 << 8) | (w1 >> 24));
 }
 
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) { return a ^ b ^ c; }
+// a ^ b ^ c in one v_bitop3 (truth table 0x96, symmetric in its operands).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
 
 // Every per-lattice integer accumulator (energy tally, reduction outputs) is
 // spread over kSlots 64-bit slots; a block adds its sum to slot

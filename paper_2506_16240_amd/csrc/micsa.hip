@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "bitplane_kernels.hpp"
 #include "fused_kernels.hpp"
 #include "micsa.h"
 
@@ -47,10 +48,17 @@ struct micsa_ctx {
     uint8_t* dem = nullptr;   // [L][2][Nh] current
     uint8_t* spin_alt = nullptr;
     uint8_t* dem_alt = nullptr;
+    // bit-plane layout (MICSA_LAYOUT_BITPLANE): 64 samples per word
+    bool bit = false;
+    int32_t G = 0;              // lane groups
+    uint64_t* bspin = nullptr;  // [G][R][2][Nh]
+    uint64_t* bdm0 = nullptr;   // [G][R][2][Nh]
+    uint64_t* bdm1 = nullptr;   // [G][R][2][Nh]
+    uint64_t* bJ = nullptr;     // [G][6][Nh]
     // sweep kernel selection (MICSA_OPT_*)
     int32_t kernel_opt = MICSA_KERNEL_AUTO;
     int32_t tile_y = 0, tile_z = 0;
-    uint32_t* J = nullptr;    // [S][6][P32]
+    uint32_t* J = nullptr;    // [S][Nh] coupling bytes of the even sites
     unsigned long long* tally = nullptr;  // [L][kSlots]
     unsigned long long* red = nullptr;    // [max(L, S)][kSlots] reduction scratch
     Schedule sched;
@@ -196,6 +204,48 @@ int set_tally(micsa_ctx* c, const std::vector<int64_t>& E)
     return MICSA_OK;
 }
 
+GeomB geomb(const micsa_ctx* c) { return GeomB{c->g, c->G}; }
+
+int launch_bitplane_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
+{
+    const int WL = c->G * c->p.n_replicas;
+    if (refresh) {
+        TimedLaunch t(c, kTimeRefresh);
+        kb_refresh<<<dim3((unsigned)((c->g.Nh / 2 + 3) / 4), (unsigned)WL), 256, 0, c->stream>>>(
+            geomb(c), c->bdm0, c->bdm1, (uint32_t)rho, daemon_thresholds(T));
+    }
+    int st = check_launch(c, "kb_refresh");
+    if (st) return st;
+    const dim3 grid = grid_for(c->g.Nh, WL);
+    {
+        TimedLaunch t(c, kTimeSweep);
+        kb_micsa_half<0><<<grid, kBlock, 0, c->stream>>>(geomb(c), c->bspin, c->bdm0, c->bdm1, c->bJ);
+    }
+    if ((st = check_launch(c, "kb_micsa_half<0>"))) return st;
+    {
+        TimedLaunch t(c, kTimeSweep);
+        kb_micsa_half<1><<<grid, kBlock, 0, c->stream>>>(geomb(c), c->bspin, c->bdm0, c->bdm1, c->bJ);
+    }
+    return check_launch(c, "kb_micsa_half<1>");
+}
+
+// Per-lane counts of the bit-plane layout into dst slots (see kb_lane_count).
+template <int KIND>
+int enqueue_lane_count(micsa_ctx* c, unsigned long long* dst, int ra, int rb)
+{
+    const int64_t ent = KIND == 2 ? c->p.n_samples : c->L;
+    int st = zero_slots(c, dst, ent);
+    if (st) return st;
+    const int64_t per_block = 128;
+    const unsigned ny = (unsigned)(KIND == 2 ? c->G : c->G * c->p.n_replicas);
+    {
+        TimedLaunch t(c, kTimeReduce);
+        kb_lane_count<KIND><<<dim3((unsigned)((c->g.Nh + per_block - 1) / per_block), ny), 64, 0, c->stream>>>(
+            geomb(c), c->bspin, c->bdm0, c->bdm1, c->bJ, ra, rb, per_block, dst);
+    }
+    return check_launch(c, "kb_lane_count");
+}
+
 int launch_refresh(micsa_ctx* c, int64_t rho, double T)
 {
     TimedLaunch t(c, kTimeRefresh);
@@ -206,11 +256,14 @@ int launch_refresh(micsa_ctx* c, int64_t rho, double T)
 
 // The fused sweep needs whole 16-site chunks per row and a work-group that
 // holds at least a one-row tile with its four ring rows.
-bool fused_eligible(const micsa_ctx* c) { return c->p.Lx % 32 == 0 && 5 * (c->p.Lx / 32) <= 1024; }
+bool fused_eligible(const micsa_ctx* c)
+{
+    return !c->bit && c->p.Lx % 32 == 0 && 5 * (c->p.Lx / 32) <= 1024;
+}
 
 bool use_fused(const micsa_ctx* c)
 {
-    if (c->kernel_opt == MICSA_KERNEL_SIMPLE) return false;
+    if (c->bit || c->kernel_opt == MICSA_KERNEL_SIMPLE) return false;
     if (c->kernel_opt == MICSA_KERNEL_FUSED) return true;
     return fused_eligible(c) && c->p.Lx >= 128;
 }
@@ -256,8 +309,12 @@ int launch_fused_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
     const DaemonThresholds th = refresh ? daemon_thresholds(T) : DaemonThresholds{0, 0, 0};
     {
         TimedLaunch t(c, kTimeSweep);
-        k_micsa_sweep_fused<<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->dem, c->spin_alt, c->dem_alt,
-                                                             c->J, c->tally, refresh ? 1 : 0, (uint32_t)rho, th);
+        if (refresh)
+            k_micsa_sweep_fused<true><<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->dem, c->spin_alt,
+                                                                       c->dem_alt, c->J, c->tally, (uint32_t)rho, th);
+        else
+            k_micsa_sweep_fused<false><<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->dem, c->spin_alt,
+                                                                        c->dem_alt, c->J, c->tally, (uint32_t)rho, th);
     }
     const int st = check_launch(c, "k_micsa_sweep_fused");
     if (st) return st;
@@ -304,6 +361,7 @@ int launch_heatbath_sweep(micsa_ctx* c, int64_t k, double T)
 // Enqueue: dst[l] = from-scratch H^EA of lattice l.
 int enqueue_energy(micsa_ctx* c, unsigned long long* dst)
 {
+    if (c->bit) return enqueue_lane_count<0>(c, dst, 0, 0);
     int st = zero_slots(c, dst, c->L);
     if (st) return st;
     TimedLaunch t(c, kTimeReduce);
@@ -314,6 +372,7 @@ int enqueue_energy(micsa_ctx* c, unsigned long long* dst)
 
 int enqueue_level_sum(micsa_ctx* c, unsigned long long* dst)
 {
+    if (c->bit) return enqueue_lane_count<1>(c, dst, 0, 0);
     int st = zero_slots(c, dst, c->L);
     if (st) return st;
     TimedLaunch t(c, kTimeReduce);
@@ -339,6 +398,8 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
 {
     if (!c) return MICSA_EINVAL;
     if (algo != MICSA_ALGO_MICSA && algo != MICSA_ALGO_HEATBATH) return fail(c, MICSA_EINVAL, "unknown algo");
+    if (c->bit && algo != MICSA_ALGO_MICSA)
+        return fail(c, MICSA_EINVAL, "the heat-bath baseline runs in the byte layout");
     if (n < 0) return fail(c, MICSA_EINVAL, "negative sweep count");
     if (!c->sched.set) return fail(c, MICSA_ESTATE, "no schedule installed");
     if (c->k + n > c->sched.n_sweeps) return fail(c, MICSA_ERANGE, "sweeps beyond the schedule length");
@@ -350,7 +411,9 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
         int st;
         if (algo == MICSA_ALGO_MICSA) {
             const bool refresh = is_refresh(k, c->sched.period);
-            if (use_fused(c)) {
+            if (c->bit) {
+                if ((st = launch_bitplane_sweep(c, refresh, rho, T))) return st;
+            } else if (use_fused(c)) {
                 if ((st = launch_fused_sweep(c, refresh, rho, T))) return st;
             } else {
                 if (refresh && (st = launch_refresh(c, rho, T))) return st;
@@ -371,6 +434,10 @@ void free_all(micsa_ctx* c)
     if (c->dem) (void)hipFree(c->dem);
     if (c->spin_alt) (void)hipFree(c->spin_alt);
     if (c->dem_alt) (void)hipFree(c->dem_alt);
+    if (c->bspin) (void)hipFree(c->bspin);
+    if (c->bdm0) (void)hipFree(c->bdm0);
+    if (c->bdm1) (void)hipFree(c->bdm1);
+    if (c->bJ) (void)hipFree(c->bJ);
     if (c->J) (void)hipFree(c->J);
     if (c->tally) (void)hipFree(c->tally);
     if (c->red) (void)hipFree(c->red);
@@ -408,7 +475,7 @@ int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
     if (!p) return MICSA_EINVAL;
     if (p->Lx < 8 || p->Lx % 8 || p->Ly < 2 || p->Ly % 2 || p->Lz < 2 || p->Lz % 2) return MICSA_EINVAL;
     if (p->n_samples < 1 || p->n_samples >= (1 << 24) || p->n_replicas < 1) return MICSA_EINVAL;
-    if (p->layout != MICSA_LAYOUT_BYTE) return MICSA_EINVAL;
+    if (p->layout != MICSA_LAYOUT_BYTE && p->layout != MICSA_LAYOUT_BITPLANE) return MICSA_EINVAL;
     const int64_t N = (int64_t)p->Lx * p->Ly * p->Lz;
     if (N >= ((int64_t)1 << 32) || (int64_t)p->n_samples * p->n_replicas >= (1 << 16)) return MICSA_EINVAL;
 
@@ -417,6 +484,8 @@ int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
     c->p = *p;
     c->stream = (hipStream_t)hip_stream;
     c->L = p->n_samples * p->n_replicas;
+    c->bit = p->layout == MICSA_LAYOUT_BITPLANE;
+    c->G = (p->n_samples + 63) / 64;
     Geom& g = c->g;
     g.Lx = p->Lx;
     g.Ly = p->Ly;
@@ -425,32 +494,54 @@ int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
     g.Wr = g.Kx / 4;
     g.rows = p->Ly * p->Lz;
     g.Nh = N / 2;
-    g.P32 = (int32_t)((g.Nh + 31) / 32);
     g.S = p->n_samples;
     g.R = p->n_replicas;
     g.key0 = (uint32_t)p->seed;
     g.key1 = (uint32_t)(p->seed >> 32);
 
-    const size_t state = (size_t)c->L * 2 * (size_t)g.Nh;
-    const size_t jw = (size_t)p->n_samples * 6 * (size_t)g.P32;
     const size_t nred = (size_t)std::max(c->L, p->n_samples);
-    if (hipMalloc(&c->spin, state) != hipSuccess || hipMalloc(&c->dem, state) != hipSuccess ||
-        hipMalloc(&c->spin_alt, state) != hipSuccess || hipMalloc(&c->dem_alt, state) != hipSuccess ||
-        hipMalloc(&c->J, jw * 4) != hipSuccess || hipMalloc(&c->tally, (size_t)c->L * kSlots * 8) != hipSuccess ||
-        hipMalloc(&c->red, nred * kSlots * 8) != hipSuccess) {
+    bool ok = hipMalloc(&c->tally, (size_t)c->L * kSlots * 8) == hipSuccess &&
+              hipMalloc(&c->red, nred * kSlots * 8) == hipSuccess;
+    const size_t state = (size_t)c->L * 2 * (size_t)g.Nh;
+    const size_t words = (size_t)c->G * p->n_replicas * 2 * (size_t)g.Nh;
+    if (ok && !c->bit) {
+        const size_t jw = (size_t)p->n_samples * (size_t)g.Nh / 4;
+        ok = hipMalloc(&c->spin, state) == hipSuccess && hipMalloc(&c->dem, state) == hipSuccess &&
+             hipMalloc(&c->spin_alt, state) == hipSuccess && hipMalloc(&c->dem_alt, state) == hipSuccess &&
+             hipMalloc(&c->J, jw * 4) == hipSuccess;
+    } else if (ok) {
+        ok = hipMalloc(&c->bspin, words * 8) == hipSuccess && hipMalloc(&c->bdm0, words * 8) == hipSuccess &&
+             hipMalloc(&c->bdm1, words * 8) == hipSuccess &&
+             hipMalloc(&c->bJ, (size_t)c->G * 6 * (size_t)g.Nh * 8) == hipSuccess;
+    }
+    if (!ok) {
         (void)hipGetLastError();
         free_all(c);
         delete c;
         return MICSA_ENOMEM;
     }
     int st = MICSA_OK;
-    k_init_couplings<<<grid_for(g.P32, p->n_samples), kBlock, 0, c->stream>>>(g, c->J);
-    if (!st) st = check_launch(c, "k_init_couplings");
-    if (!st) {
-        k_init_spins<<<grid_for(g.Nh / 4, c->L), kBlock, 0, c->stream>>>(g, c->spin);
-        st = check_launch(c, "k_init_spins");
+    if (!c->bit) {
+        k_init_couplings<<<grid_for(g.Nh / 4, p->n_samples), kBlock, 0, c->stream>>>(g, c->J);
+        st = check_launch(c, "k_init_couplings");
+        if (!st) {
+            k_init_spins<<<grid_for(g.Nh / 4, c->L), kBlock, 0, c->stream>>>(g, c->spin);
+            st = check_launch(c, "k_init_spins");
+        }
+        if (!st && hipMemsetAsync(c->dem, 0, state, c->stream) != hipSuccess) st = MICSA_EHIP;
+    } else {
+        const int WL = c->G * p->n_replicas;
+        kb_init_couplings<<<dim3((unsigned)((g.Nh + 3) / 4), (unsigned)c->G), 256, 0, c->stream>>>(geomb(c), c->bJ);
+        st = check_launch(c, "kb_init_couplings");
+        if (!st) {
+            kb_init_spins<<<dim3((unsigned)((g.Nh / 2 + 3) / 4), (unsigned)WL), 256, 0, c->stream>>>(geomb(c),
+                                                                                               c->bspin);
+            st = check_launch(c, "kb_init_spins");
+        }
+        if (!st && (hipMemsetAsync(c->bdm0, 0, words * 8, c->stream) != hipSuccess ||
+                    hipMemsetAsync(c->bdm1, 0, words * 8, c->stream) != hipSuccess))
+            st = MICSA_EHIP;
     }
-    if (!st && hipMemsetAsync(c->dem, 0, state, c->stream) != hipSuccess) st = MICSA_EHIP;
     if (!st) {
         // tally <- from-scratch energy (2U - 3N)
         std::vector<int64_t> U;
@@ -572,6 +663,7 @@ int micsa_read_energy(micsa_ctx* ctx, int64_t* E)
 int micsa_read_energy_tally(micsa_ctx* ctx, int64_t* E)
 {
     if (!ctx || !E) return MICSA_EINVAL;
+    if (ctx->bit) return fail(ctx, MICSA_ESTATE, "the bit-plane layout keeps no incremental tally");
     std::vector<int64_t> v;
     int st = read_slots(ctx, ctx->tally, ctx->L, v);
     if (st) return st;
@@ -595,15 +687,19 @@ int micsa_read_overlap(micsa_ctx* ctx, int32_t a, int32_t b, int64_t* Q)
     if (a < 0 || b < 0 || a >= ctx->p.n_replicas || b >= ctx->p.n_replicas || a == b)
         return fail(ctx, MICSA_EINVAL, "replica indices out of range or equal");
     const int S = ctx->p.n_samples;
-    int st = zero_slots(ctx, ctx->red, S);
-    if (st) return st;
-    const int64_t wpl = 2 * ctx->g.Nh / 4;
-    {
-        TimedLaunch t(ctx, kTimeReduce);
-        k_differ_count<<<grid_for(wpl, S), kBlock, 0, ctx->stream>>>(
-            wpl, ctx->p.n_replicas, a, b, reinterpret_cast<const uint32_t*>(ctx->spin), ctx->red);
+    int st;
+    if (ctx->bit) {
+        if ((st = enqueue_lane_count<2>(ctx, ctx->red, a, b))) return st;
+    } else {
+        if ((st = zero_slots(ctx, ctx->red, S))) return st;
+        const int64_t wpl = 2 * ctx->g.Nh / 4;
+        {
+            TimedLaunch t(ctx, kTimeReduce);
+            k_differ_count<<<grid_for(wpl, S), kBlock, 0, ctx->stream>>>(
+                wpl, ctx->p.n_replicas, a, b, reinterpret_cast<const uint32_t*>(ctx->spin), ctx->red);
+        }
+        if ((st = check_launch(ctx, "k_differ_count"))) return st;
     }
-    if ((st = check_launch(ctx, "k_differ_count"))) return st;
     std::vector<int64_t> v;
     if ((st = read_red(ctx, S, v))) return st;
     const int64_t N = n_sites(ctx);
@@ -627,15 +723,43 @@ static int read_state(micsa_ctx* ctx, const uint8_t* dev, uint8_t* host)
     return MICSA_OK;
 }
 
+// Bit-plane words [G][R][2][Nh] -> host values [S][R][N]; with two planes
+// (daemons) the value is bit0 + 2 bit1.
+static int read_words(micsa_ctx* ctx, const uint64_t* w0, const uint64_t* w1, uint8_t* host)
+{
+    const int64_t N = n_sites(ctx);
+    const int R = ctx->p.n_replicas;
+    const size_t n = (size_t)ctx->G * R * 2 * (size_t)ctx->g.Nh;
+    std::vector<uint64_t> a(n), b(w1 ? n : 0);
+    HIP_TRY(ctx, hipMemcpyAsync(a.data(), w0, n * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if (w1) HIP_TRY(ctx, hipMemcpyAsync(b.data(), w1, n * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int s = 0; s < ctx->p.n_samples; ++s)
+        for (int r = 0; r < R; ++r)
+            for (int64_t i = 0; i < N; ++i) {
+                int par;
+                int64_t h;
+                split_index(ctx, i, par, h);
+                const size_t idx = (((size_t)(s / 64) * R + r) * 2 + par) * ctx->g.Nh + h;
+                const int lane = s % 64;
+                uint8_t v = (uint8_t)((a[idx] >> lane) & 1u);
+                if (w1) v = (uint8_t)(v | (((b[idx] >> lane) & 1u) << 1));
+                host[((int64_t)s * R + r) * N + i] = v;
+            }
+    return MICSA_OK;
+}
+
 int micsa_read_spins(micsa_ctx* ctx, uint8_t* sigma)
 {
     if (!ctx || !sigma) return MICSA_EINVAL;
+    if (ctx->bit) return read_words(ctx, ctx->bspin, nullptr, sigma);
     return read_state(ctx, ctx->spin, sigma);
 }
 
 int micsa_read_demons(micsa_ctx* ctx, uint8_t* m)
 {
     if (!ctx || !m) return MICSA_EINVAL;
+    if (ctx->bit) return read_words(ctx, ctx->bdm0, ctx->bdm1, m);
     return read_state(ctx, ctx->dem, m);
 }
 
@@ -644,12 +768,21 @@ int micsa_read_couplings(micsa_ctx* ctx, uint8_t* j)
     if (!ctx || !j) return MICSA_EINVAL;
     const Geom& g = ctx->g;
     const int S = ctx->p.n_samples;
-    std::vector<uint32_t> planes((size_t)S * 6 * g.P32);
-    HIP_TRY(ctx, hipMemcpyAsync(planes.data(), ctx->J, planes.size() * 4, hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<uint8_t> jbytes;
+    std::vector<uint64_t> wplanes;
+    if (ctx->bit) {
+        wplanes.resize((size_t)ctx->G * 6 * g.Nh);
+        HIP_TRY(ctx, hipMemcpyAsync(wplanes.data(), ctx->bJ, wplanes.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    } else {
+        jbytes.resize((size_t)S * g.Nh);
+        HIP_TRY(ctx, hipMemcpyAsync(jbytes.data(), ctx->J, jbytes.size(), hipMemcpyDeviceToHost, ctx->stream));
+    }
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     const int64_t N = n_sites(ctx);
-    auto bit = [&](int s, int d, int64_t h) {
-        return (planes[((size_t)s * 6 + d) * g.P32 + (size_t)(h >> 5)] >> (h & 31)) & 1u;
+    auto bit = [&](int s, int d, int64_t h) -> uint32_t {
+        if (ctx->bit)
+            return (uint32_t)((wplanes[((size_t)(s / 64) * 6 + d) * g.Nh + (size_t)h] >> (s % 64)) & 1u);
+        return (uint32_t)(jbytes[(size_t)s * g.Nh + (size_t)h] >> d) & 1u;
     };
     for (int s = 0; s < S; ++s)
         for (int64_t i = 0; i < N; ++i) {
@@ -689,10 +822,35 @@ static int write_state(micsa_ctx* ctx, uint8_t* dev, const uint8_t* host, uint8_
     return MICSA_OK;
 }
 
+// Host values [S][R][N] -> bit-plane words (bit0 into w0, bit1 into w1).
+static int write_words(micsa_ctx* ctx, uint64_t* w0, uint64_t* w1, const uint8_t* host, uint8_t maxv)
+{
+    const int64_t N = n_sites(ctx);
+    const int R = ctx->p.n_replicas;
+    const size_t n = (size_t)ctx->G * R * 2 * (size_t)ctx->g.Nh;
+    std::vector<uint64_t> a(n, 0), b(w1 ? n : 0, 0);
+    for (int s = 0; s < ctx->p.n_samples; ++s)
+        for (int r = 0; r < R; ++r)
+            for (int64_t i = 0; i < N; ++i) {
+                const uint8_t v = host[((int64_t)s * R + r) * N + i];
+                if (v > maxv) return fail(ctx, MICSA_EINVAL, "value out of range");
+                int par;
+                int64_t h;
+                split_index(ctx, i, par, h);
+                const size_t idx = (((size_t)(s / 64) * R + r) * 2 + par) * ctx->g.Nh + h;
+                a[idx] |= (uint64_t)(v & 1u) << (s % 64);
+                if (w1) b[idx] |= (uint64_t)(v >> 1) << (s % 64);
+            }
+    HIP_TRY(ctx, hipMemcpyAsync(w0, a.data(), n * 8, hipMemcpyHostToDevice, ctx->stream));
+    if (w1) HIP_TRY(ctx, hipMemcpyAsync(w1, b.data(), n * 8, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return MICSA_OK;
+}
+
 int micsa_write_spins(micsa_ctx* ctx, const uint8_t* sigma)
 {
     if (!ctx || !sigma) return MICSA_EINVAL;
-    int st = write_state(ctx, ctx->spin, sigma, 1);
+    int st = ctx->bit ? write_words(ctx, ctx->bspin, nullptr, sigma, 1) : write_state(ctx, ctx->spin, sigma, 1);
     if (st) return st;
     std::vector<int64_t> E((size_t)ctx->L);
     if ((st = micsa_read_energy(ctx, E.data()))) return st;
@@ -702,6 +860,7 @@ int micsa_write_spins(micsa_ctx* ctx, const uint8_t* sigma)
 int micsa_write_demons(micsa_ctx* ctx, const uint8_t* m)
 {
     if (!ctx || !m) return MICSA_EINVAL;
+    if (ctx->bit) return write_words(ctx, ctx->bdm0, ctx->bdm1, m, 3);
     return write_state(ctx, ctx->dem, m, 3);
 }
 
@@ -767,6 +926,7 @@ int micsa_get_timing(micsa_ctx* ctx, int32_t kind, double* total_ms, int64_t* la
 
 const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
 {
+    if (ctx && ctx->bit) return algo == MICSA_ALGO_MICSA ? "kb_micsa_half" : "";
     if (algo == MICSA_ALGO_HEATBATH) return "k_heatbath_half";
     if (ctx && use_fused(ctx)) return "k_micsa_sweep_fused";
     return "k_micsa_half";

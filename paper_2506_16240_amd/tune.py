@@ -1,0 +1,110 @@
+"""Launch-shape autotuner for the fused MicSA sweep.
+
+For a lattice shape it times every admissible tile (rows TY x planes TZ per
+work-group) with the library's per-launch event timing, rejects any
+candidate whose state after the trial sweeps differs in a single bit from
+the per-half reference kernel (the bit-exact gate: launch shapes must never
+change results), and returns the fastest.  Results are cached in a JSON
+file keyed by device and shape.
+
+Only argument marshalling and timing happen here; all sweeps run in
+libmicsa through the binding.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import micsa as M
+
+CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+@dataclass
+class TileResult:
+    ty: int
+    tz: int
+    us_per_sweep: float
+
+
+def _divisors(n: int, cap: int) -> list[int]:
+    return [d for d in range(1, min(n, cap) + 1) if n % d == 0]
+
+
+def candidates(Lx: int, Ly: int, Lz: int) -> list[tuple[int, int]]:
+    nc = Lx // 32
+    tys = [d for d in _divisors(Ly, 64) if (d + 4) * nc <= 1024 and d >= min(4, Ly)]
+    tzs = [d for d in _divisors(Lz, 64) if d >= min(4, Lz)]
+    # keep the grid reasonably small: powers of two and the largest admissible values
+    def trim(v):
+        keep = sorted({x for x in v if x & (x - 1) == 0} | set(v[-2:]))
+        return keep
+    return [(ty, tz) for ty in trim(tys) for tz in trim(tzs)]
+
+
+def _device_name() -> str:
+    try:
+        import torch
+        return torch.cuda.get_device_name(0)
+    except Exception:
+        return "unknown"
+
+
+def _state_digest(g: M.Lattice) -> str:
+    h = hashlib.sha256()
+    for a in (g.spins(), g.daemons(), g.energy_tally()):
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+def _run(shape, seed, kernel, ty, tz, sweeps, warm, timed):
+    Lx, Ly, Lz, S, R = shape
+    g = M.Lattice(Lx, Ly, Lz, S, R, seed)
+    try:
+        g.set_option(M.OPT_SWEEP_KERNEL, kernel)
+        if ty:
+            g.set_option(M.OPT_TILE_Y, ty)
+            g.set_option(M.OPT_TILE_Z, tz)
+        g.set_schedule(M.Schedule(M.SCHED_CONST, 0.9, 0.9, warm + sweeps, 7))
+        g.sweep(M.ALGO_MICSA, warm)
+        g.sync()
+        g.set_timing(timed)
+        g.sweep(M.ALGO_MICSA, sweeps)
+        ms, n = g.timing(M.TIME_SWEEP)
+        return _state_digest(g), (ms / n * 1e3 if n else float("nan"))
+    finally:
+        g.close()
+
+
+def tune(Lx: int, Ly: int, Lz: int, S: int = 1, R: int = 1, sweeps: int = 12, use_cache: bool = True,
+         verbose: bool = False) -> TileResult:
+    """Fastest bit-exact tile of the fused sweep for this lattice shape."""
+    shape = (Lx, Ly, Lz, S, R)
+    key = f"{_device_name()}|{Lx}x{Ly}x{Lz}|S{S}|R{R}"
+    cache = {}
+    if use_cache and os.path.exists(CACHE_PATH):
+        with open(CACHE_PATH) as f:
+            cache = json.load(f)
+        if key in cache:
+            return TileResult(**cache[key])
+    seed = 0x7E57
+    warm = 3
+    ref, _ = _run(shape, seed, M.KERNEL_SIMPLE, 0, 0, sweeps, warm, False)
+    best = None
+    for ty, tz in candidates(Lx, Ly, Lz):
+        digest, us = _run(shape, seed, M.KERNEL_FUSED, ty, tz, sweeps, warm, True)
+        if digest != ref:
+            raise RuntimeError(f"tile TY={ty} TZ={tz} changed the result: the fused sweep is wrong for {shape}")
+        if verbose:
+            print(f"  TY={ty:3d} TZ={tz:3d}: {us:9.2f} us/sweep", flush=True)
+        if best is None or us < best.us_per_sweep:
+            best = TileResult(ty, tz, us)
+    if use_cache:
+        cache[key] = best.__dict__
+        with open(CACHE_PATH, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    return best

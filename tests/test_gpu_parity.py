@@ -288,3 +288,76 @@ def test_tile_options_are_validated():
     with pytest.raises(M.MicsaError) as e:
         h.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)
     assert e.value.status == M.EINVAL
+
+
+# ------------------------------------------------------- bit-plane layout
+def bpair(Lx, Ly, Lz, S, R, seed):
+    return M.Lattice(Lx, Ly, Lz, S, R, seed, layout=M.LAYOUT_BITPLANE), O.Lattice(Lx, Ly, Lz, S, R, seed)
+
+
+BIT_SHAPES = [
+    (8, 4, 4, 1, 1),       # one live lane
+    (8, 2, 2, 3, 2),       # minimum sides
+    (16, 6, 10, 65, 2),    # two lane groups, the second with one live lane
+    (24, 8, 6, 130, 1),    # three lane groups
+    (32, 8, 8, 64, 3),
+]
+
+
+@pytest.mark.parametrize("shape", BIT_SHAPES)
+def test_bitplane_trajectory_matches_oracle(shape):
+    g, o = bpair(*shape, seed=31337)
+    assert np.array_equal(g.couplings(), o.J)
+    same_state(g, o)
+    n = 25
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.2, 0.5, n, 6)
+    g.set_schedule(gs)
+    Eg, Dg = g.sweep_logged(M.ALGO_MICSA, n, 1)
+    Eo, Do = o.run(O.ALGO_MICSA, os_, n, 1)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    same_state(g, o)
+    if shape[4] > 1:
+        assert np.array_equal(g.overlap(0, 1), o.overlap(0, 1))
+
+
+def test_bitplane_batched_L32_shape():
+    """256 samples x 2 replicas of L = 32 bit-packed in 4 lane groups."""
+    w = W.BATCHED_L32
+    n = 12
+    g, o = bpair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
+    gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
+    g.set_schedule(gs)
+    Eg, Dg = g.sweep_logged(M.ALGO_MICSA, n, 4)
+    Eo, Do = o.run(O.ALGO_MICSA, os_, n, 4)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    assert np.array_equal(g.overlap(0, 1), o.overlap(0, 1))
+    same_state(g, o)
+
+
+def test_layouts_are_bit_identical():
+    """The same seed gives the same trajectory in the byte and bit-plane layouts."""
+    shape = (32, 12, 10, 70, 2)
+    n = 40
+    res = []
+    for layout in (M.LAYOUT_BYTE, M.LAYOUT_BITPLANE):
+        g = M.Lattice(*shape, seed=4242, layout=layout)
+        g.set_schedule(M.Schedule(M.SCHED_CONST, 0.8, 0.8, n, 10))
+        E, D = g.sweep_logged(M.ALGO_MICSA, n, 5)
+        res.append((E, D, g.spins(), g.daemons(), g.overlap(0, 1)))
+        g.close()
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+
+
+def test_bitplane_error_paths():
+    g = M.Lattice(8, 4, 4, 3, 1, seed=1, layout=M.LAYOUT_BITPLANE)
+    g.set_schedule(M.Schedule(M.SCHED_CONST, 1.0, 1.0, 10, 2))
+    with pytest.raises(M.MicsaError) as e:
+        g.sweep(M.ALGO_HEATBATH, 1)
+    assert e.value.status == M.EINVAL
+    with pytest.raises(M.MicsaError) as e:
+        g.energy_tally()
+    assert e.value.status == M.ESTATE
+    with pytest.raises(M.MicsaError) as e:
+        g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)
+    assert e.value.status == M.EINVAL
