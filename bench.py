@@ -53,19 +53,26 @@ def measured_traffic(name: str):
     return e.get("bytes_per_launch")
 
 
-def run_gpu(w, algo_name: str, steps: int, warmup: int, stream):
+def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None):
     from paper_2506_16240_amd import micsa as M
     import torch
+
+    def configure(lat):
+        if tile and algo_name == "micsa":
+            lat.set_option(M.OPT_TILE_Y, tile[0])
+            lat.set_option(M.OPT_TILE_Z, tile[1])
 
     algo = M.ALGO_MICSA if algo_name == "micsa" else M.ALGO_HEATBATH
     sched = M.Schedule(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
     P = w.period
     if warmup > 0:
         with M.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed, stream=stream.cuda_stream) as lw:
+            configure(lw)
             lw.set_schedule(sched)
             lw.sweep(algo, warmup * P)
             lw.sync()
     lat = M.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed, stream=stream.cuda_stream)
+    configure(lat)
     lat.set_schedule(sched)
     lat.set_timing(True)
     torch.cuda.synchronize()
@@ -118,6 +125,10 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-heatbath", action="store_true")
+    ap.add_argument("--tile", default="tune",
+                    help="fused-sweep tile: 'tune' (autotuner, bit-exact gated), 'auto' (library default) or TY,TZ")
+    ap.add_argument("--copy-ref-gib", type=float, default=0.0,
+                    help="after the run, copy this many GiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -139,8 +150,17 @@ def main() -> int:
     sweeps = steps * w.period
     updates = w.N * w.lattices * sweeps
 
+    tile = None
+    if args.tile == "tune":
+        from paper_2506_16240_amd import tune
+        log("tuning fused-sweep tiles")
+        best = tune.tune(w.Lx, w.Ly, w.Lz, w.S, w.R, use_cache=False)
+        tile = (best.ty, best.tz)
+        log(f"tile TY={best.ty} TZ={best.tz} ({best.us_per_sweep:.1f} us/sweep in tuning)")
+    elif args.tile != "auto":
+        tile = tuple(int(v) for v in args.tile.split(","))
     log(f"micsa: {w.name}, {sweeps} sweeps")
-    mi = run_gpu(w, "micsa", steps, args.warmup, stream)
+    mi = run_gpu(w, "micsa", steps, args.warmup, stream, tile)
     log(f"micsa: {mi['ms']:.1f} ms, tally check {mi['tally_check']}")
     hb = None
     if not args.no_heatbath:
@@ -170,7 +190,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "L": [w.Lx, w.Ly, w.Lz], "samples": w.S, "replicas": w.R,
                    "sweeps_per_step": w.period, "sweeps": sweeps, "schedule": f"T {w.T0}->{w.T1}",
-                   "layout": "byte", "kernel": mi["kernel"]},
+                   "layout": "byte", "kernel": mi["kernel"], "tile": list(tile) if tile else "auto"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": mi["kernel"], "avg_launch_ms": round(avg_ms, 5),
@@ -182,6 +202,14 @@ def main() -> int:
                            "ms_per_step": round(hb["ms"] / steps, 4), "kernel": hb["kernel"]}
         out["micsa_over_heatbath"] = round(hb["ms"] / mi["ms"], 3)
         out["checks"]["heatbath_tally_equals_energy"] = hb["tally_check"]
+    if args.copy_ref_gib > 0:
+        n = int(args.copy_ref_gib * (1 << 30))
+        a = torch.ones(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

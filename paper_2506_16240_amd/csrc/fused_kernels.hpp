@@ -285,4 +285,159 @@ __global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
     block_add(tally + (int64_t)l * kSlots, 4 * ((long long)sum_old - (long long)sum_new));
 }
 
+// Fused heat-bath sweep (the random-number-greedy baseline): same z-march,
+// tiles, rings and LDS exchange as k_micsa_sweep_fused; every site draws one
+// 32-bit uniform, u = Philox(h>>2, 2k+p, r, stream HB | s)[h & 3] for its
+// parity-split index h, and becomes +1 iff u < tau[v], where v counts the
+// neighbours with J s_nb = -1.  No daemons.
+__device__ __forceinline__ void heatbath4(uint32_t& S, uint32_t v, const u32x4& rnd, const uint64_t* tau, int& dE)
+{
+    const uint32_t ru[4] = {rnd.v0, rnd.v1, rnd.v2, rnd.v3};
+    uint32_t Sn = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t vb = (v >> (8 * b)) & 0xFFu;
+        const uint32_t down = (uint64_t)ru[b] < tau[vb] ? 0u : 1u;
+        const uint32_t old = (S >> (8 * b)) & 1u;
+        // flipping s_old changes H by 2 s_old h, h = 6 - 2v
+        if (down != old) dE += 2 * (1 - 2 * (int)old) * (6 - 2 * (int)vb);
+        Sn |= down << (8 * b);
+    }
+    S = Sn;
+}
+
+__global__ void __launch_bounds__(1024) k_heatbath_sweep_fused(
+    Geom g, FusedTile f, const uint8_t* __restrict__ spin_in, uint8_t* __restrict__ spin_out,
+    const uint32_t* __restrict__ J, unsigned long long* __restrict__ tally, uint32_t time0, HeatBathThresholds th)
+{
+    extern __shared__ uint4 lds[];
+    __shared__ uint64_t tau[8];
+    if (threadIdx.x < 7) tau[threadIdx.x] = th.tau[threadIdx.x];
+    const int rows_slots = f.TY + 4;
+    const int plane_slots = rows_slots * f.NC;
+    uint4* So = lds;
+    uint4* Xs = lds + 2 * plane_slots;
+
+    const int l = blockIdx.y;
+    const int s = l / g.R, r = l % g.R;
+    const int ty = blockIdx.x % f.nty, tz = blockIdx.x / f.nty;
+    const int y0 = ty * f.TY, z0 = tz * f.TZ;
+    const int ry = threadIdx.x / f.NC, c = threadIdx.x - ry * f.NC;
+    const bool active = ry < rows_slots;
+    int y = y0 - 2 + ry;
+    y = y < 0 ? y + g.Ly : (y >= g.Ly ? y - g.Ly : y);
+    const bool do_even = active && ry >= 1 && ry <= f.TY + 2;
+    const bool do_odd = active && ry >= 2 && ry <= f.TY + 1;
+
+    const uint8_t* ev_in = spin_in + ((int64_t)l * 2 + 0) * g.Nh;
+    const uint8_t* od_in = spin_in + ((int64_t)l * 2 + 1) * g.Nh;
+    uint8_t* ev_out = spin_out + ((int64_t)l * 2 + 0) * g.Nh;
+    uint8_t* od_out = spin_out + ((int64_t)l * 2 + 1) * g.Nh;
+    const uint8_t* Jb = reinterpret_cast<const uint8_t*>(J) + (int64_t)s * g.Nh;
+    const uint32_t sw = stream_word(kStreamHeatBath, (uint32_t)s);
+
+    auto wrapz = [&](int z) { return z < 0 ? z + g.Lz : (z >= g.Lz ? z - g.Lz : z); };
+    auto hof = [&](int z) { return ((int64_t)y + (int64_t)g.Ly * z) * g.Kx + 16 * c; };
+    const int cn = c + 1 == f.NC ? 0 : c + 1, cp = c == 0 ? f.NC - 1 : c - 1;
+    const int steps = f.TZ + 2;
+
+    V4 So_prev{}, So_cur{}, So_next{};
+    V4 X_prev2{}, X_prev{}, X_cur{};
+    V4 nSo{}, nSe{}, nJw{};
+    auto load_step = [&](int st2) {
+        const int z2 = wrapz(z0 - 1 + st2);
+        if (active) nSo = ldg16(od_in + hof(wrapz(z2 + 1)));
+        if (do_even) {
+            const int64_t h2 = hof(z2);
+            nSe = ldg16(ev_in + h2);
+            nJw = ldg16(Jb + h2);
+        }
+    };
+    if (active) {
+        So_prev = ldg16(od_in + hof(wrapz(z0 - 2)));
+        So_cur = ldg16(od_in + hof(wrapz(z0 - 1)));
+    }
+    load_step(0);
+    int dE = 0;
+    for (int st = 0; st < steps; ++st) {
+        const int buf = st & 1;
+        const int z = wrapz(z0 - 1 + st);
+        const int64_t h = hof(z);
+        So_next = nSo;
+        V4 Se = nSe, Jw = nJw;
+        if (st + 1 < steps) load_step(st + 1);
+        const bool odd_now = do_odd && st >= 2;
+        const int zo = wrapz(z - 1);
+        if (active) sts16(&So[buf * plane_slots + ry * f.NC + c], So_cur);
+        __syncthreads();
+
+        if (do_even) {
+            const int q = (y + z) & 1;
+            const int dir = q ? 1 : -1;
+            const uint4* row = &So[buf * plane_slots + ry * f.NC];
+            const uint32_t nbw = dir > 0 ? row[cn].x : row[cp].w;
+            const V4 A = So_cur;
+            const V4 B = shift16(A, nbw, dir);
+            const V4 Yp = lds16(&So[buf * plane_slots + (ry + 1) * f.NC + c]);
+            const V4 Ym = lds16(&So[buf * plane_slots + (ry - 1) * f.NC + c]);
+            const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
+            const bool owned = do_odd && st >= 1 && st <= f.TZ;
+            int dEe = 0;
+            V4 Xn;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t jw = Jw.w[i];
+                const uint32_t m1 = 0x01010101u;
+                const uint32_t v = xor_and(A.w[i], jw >> dA, m1) + xor_and(B.w[i], jw >> dB, m1) +
+                                   xor_and(Yp.w[i], jw >> kPy, m1) + xor_and(Ym.w[i], jw >> kMy, m1) +
+                                   xor_and(So_next.w[i], jw >> kPz, m1) + xor_and(So_prev.w[i], jw >> kMz, m1);
+                const uint32_t ctr = (uint32_t)((h >> 2) + i);
+                const u32x4 rnd = philox10(ctr, time0, (uint32_t)r, sw, g.key0, g.key1);
+                uint32_t S = Se.w[i];
+                heatbath4(S, v, rnd, tau, dEe);
+                Se.w[i] = S;
+                Xn.w[i] = ((S << 6) - S) ^ jw;
+            }
+            X_cur = Xn;
+            sts16(&Xs[buf * plane_slots + ry * f.NC + c], Xn);
+            if (owned) {
+                stg16(ev_out + h, Se);
+                dE += dEe;
+            }
+        }
+        if (odd_now) {
+            const int q = (y + zo) & 1;
+            const int dir = q ? -1 : 1;
+            const int pb = buf ^ 1;
+            const uint4* row = &Xs[pb * plane_slots + ry * f.NC];
+            const uint32_t nbw = dir > 0 ? row[cn].x : row[cp].w;
+            const V4 A = X_prev;
+            const V4 B = shift16(A, nbw, dir);
+            const V4 Yp = lds16(&Xs[pb * plane_slots + (ry + 1) * f.NC + c]);
+            const V4 Ym = lds16(&Xs[pb * plane_slots + (ry - 1) * f.NC + c]);
+            const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
+            const int64_t ho = hof(zo);
+            V4 So_new;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t m1 = 0x01010101u;
+                const uint32_t v = ((A.w[i] >> dA) & m1) + ((B.w[i] >> dB) & m1) + ((Yp.w[i] >> kMy) & m1) +
+                                   ((Ym.w[i] >> kPy) & m1) + ((X_cur.w[i] >> kMz) & m1) +
+                                   ((X_prev2.w[i] >> kPz) & m1);
+                const uint32_t ctr = (uint32_t)((ho >> 2) + i);
+                const u32x4 rnd = philox10(ctr, time0 + 1u, (uint32_t)r, sw, g.key0, g.key1);
+                uint32_t S = So_prev.w[i];
+                heatbath4(S, v, rnd, tau, dE);
+                So_new.w[i] = S;
+            }
+            stg16(od_out + ho, So_new);
+        }
+        So_prev = So_cur;
+        So_cur = So_next;
+        X_prev2 = X_prev;
+        X_prev = X_cur;
+    }
+    block_add(tally + (int64_t)l * kSlots, dE);
+}
+
 }  // namespace micsa

@@ -339,8 +339,27 @@ int launch_micsa_sweep(micsa_ctx* c)
     return check_launch(c, "k_micsa_half<1>");
 }
 
+int launch_fused_heatbath(micsa_ctx* c, int64_t k, double T)
+{
+    const FusedTile f = choose_tile(c);
+    const int lanes = (f.TY + 4) * f.NC;
+    const int block = (lanes + 63) / 64 * 64;
+    const size_t lds = (size_t)64 * (f.TY + 4) * f.NC;
+    const dim3 grid((unsigned)(f.nty * (c->p.Lz / f.TZ)), (unsigned)c->L, 1);
+    {
+        TimedLaunch t(c, kTimeHeatBath);
+        k_heatbath_sweep_fused<<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->spin_alt, c->J, c->tally,
+                                                                (uint32_t)(2 * k), heatbath_thresholds(T));
+    }
+    const int st = check_launch(c, "k_heatbath_sweep_fused");
+    if (st) return st;
+    std::swap(c->spin, c->spin_alt);
+    return MICSA_OK;
+}
+
 int launch_heatbath_sweep(micsa_ctx* c, int64_t k, double T)
 {
+    if (use_fused(c)) return launch_fused_heatbath(c, k, T);
     const int64_t words = (int64_t)c->g.rows * c->g.Wr;
     const HeatBathThresholds th = heatbath_thresholds(T);
     {
@@ -927,7 +946,7 @@ int micsa_get_timing(micsa_ctx* ctx, int32_t kind, double* total_ms, int64_t* la
 const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
 {
     if (ctx && ctx->bit) return algo == MICSA_ALGO_MICSA ? "kb_micsa_half" : "";
-    if (algo == MICSA_ALGO_HEATBATH) return "k_heatbath_half";
+    if (algo == MICSA_ALGO_HEATBATH) return ctx && use_fused(ctx) ? "k_heatbath_sweep_fused" : "k_heatbath_half";
     if (ctx && use_fused(ctx)) return "k_micsa_sweep_fused";
     return "k_micsa_half";
 }

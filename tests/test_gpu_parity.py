@@ -161,6 +161,20 @@ def test_anneal_L512_first_sweeps_full_size():
     assert np.array_equal(g.energy_tally(), g.energy())
 
 
+def test_anneal_L512_heatbath_first_sweeps_full_size():
+    """The heat-bath baseline on the 512^3 lattice: first 6 sweeps bit-exact."""
+    w = W.ANNEAL_L512
+    n = 6
+    g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
+    gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
+    g.set_schedule(gs)
+    Eg, _ = g.sweep_logged(M.ALGO_HEATBATH, n, 3)
+    Eo, _ = o.run(O.ALGO_HEATBATH, os_, n, 3)
+    assert np.array_equal(Eg, Eo)
+    assert np.array_equal(g.spins(), o.sigma)
+    assert np.array_equal(g.energy_tally(), g.energy())
+
+
 def test_written_state_is_swept_identically():
     """Injected spins and daemons (no refresh in between) evolve identically."""
     g, o = pair(16, 8, 8, 2, 2, seed=3)
@@ -233,21 +247,24 @@ FUSED_CASES = [
 ]
 
 
+@pytest.mark.parametrize("algo", [M.ALGO_MICSA, M.ALGO_HEATBATH])
 @pytest.mark.parametrize("shape,ty,tz", FUSED_CASES)
-def test_fused_sweep_matches_oracle(shape, ty, tz):
+def test_fused_sweep_matches_oracle(shape, ty, tz, algo):
     g, o = pair(*shape, seed=99)
     g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)
     if ty:
         g.set_option(M.OPT_TILE_Y, ty)
     if tz:
         g.set_option(M.OPT_TILE_Z, tz)
-    assert g.kernel_name(M.ALGO_MICSA) == "k_micsa_sweep_fused"
+    assert g.kernel_name(algo) in ("k_micsa_sweep_fused", "k_heatbath_sweep_fused")
     n = 23
     gs, os_ = scheds(M.SCHED_LINEAR, 2.5, 0.4, n, 5)
     g.set_schedule(gs)
-    Eg, Dg = g.sweep_logged(M.ALGO_MICSA, n, 1)
-    Eo, Do = o.run(O.ALGO_MICSA, os_, n, 1)
-    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    Eg, Dg = g.sweep_logged(algo, n, 1)
+    Eo, Do = o.run(algo, os_, n, 1)
+    assert np.array_equal(Eg, Eo)
+    if algo == M.ALGO_MICSA:
+        assert np.array_equal(Dg, Do)
     same_state(g, o)
     assert np.array_equal(g.energy_tally(), o.energy())
 
