@@ -169,13 +169,68 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
    tuner and for tests that compare variants).
    MICSA_OPT_SWEEP_KERNEL: MICSA_KERNEL_AUTO (default), MICSA_KERNEL_SIMPLE
      (one launch per half sweep), MICSA_KERNEL_FUSED (one launch per sweep,
-     refresh fused in; needs Lx % 32 == 0).
+     refresh fused in; needs Lx % 32 == 0), MICSA_KERNEL_RESIDENT (whole
+     lattice in LDS for many sweeps per launch; byte layout, N <= 102400).
    MICSA_OPT_TILE_Y / MICSA_OPT_TILE_Z: rows / planes per work-group of the
      fused sweep (0 = automatic; must divide Ly / Lz).
    Errors: EINVAL for an unknown option or a value the lattice cannot use. */
 enum micsa_option { MICSA_OPT_SWEEP_KERNEL = 1, MICSA_OPT_TILE_Y = 2, MICSA_OPT_TILE_Z = 3 };
-enum micsa_kernel_choice { MICSA_KERNEL_AUTO = 0, MICSA_KERNEL_SIMPLE = 1, MICSA_KERNEL_FUSED = 2 };
+enum micsa_kernel_choice {
+    MICSA_KERNEL_AUTO = 0,    /* resident if the lattice fits, else fused if Lx >= 128, else simple */
+    MICSA_KERNEL_SIMPLE = 1,  /* one launch per half sweep */
+    MICSA_KERNEL_FUSED = 2,   /* one launch per sweep, refresh fused in (Lx % 32 == 0) */
+    MICSA_KERNEL_RESIDENT = 3 /* one work-group per lattice keeps it in LDS for many sweeps (<= 102400 sites) */
+};
 int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value);
+
+/* ------------------------------------------------------------------------
+   Serving pool: continuous batching of annealing jobs.
+
+   A job is one micsa_params (lattices from a seed) plus one schedule, run
+   with MicSA to the end of its schedule.  Jobs are queued on submission and
+   admitted in arrival order while their device footprint fits the pool's
+   HBM budget (and fewer than max_running jobs run); an admitted job keeps
+   its lattices and daemons resident until it is released.  micsa_pool_step
+   advances every running job by the same number of sweeps ("batching by
+   sweep"): the jobs whose lattices fit one work-group's LDS advance
+   together in one batched launch, each lattice at its own sweep index and
+   temperature; larger jobs run their own kernels on the same stream.  A job
+   that reaches the end of its schedule is DONE; its state stays readable
+   through micsa_pool_job_context until micsa_pool_release frees it.
+   Results never depend on the other jobs in the pool: every random number
+   is keyed by the job's own seed, sample, replica, site and time.
+   ------------------------------------------------------------------------ */
+typedef struct micsa_pool micsa_pool;
+
+enum micsa_job_state { MICSA_JOB_QUEUED = 0, MICSA_JOB_RUNNING = 1, MICSA_JOB_DONE = 2, MICSA_JOB_RELEASED = 3 };
+
+/* Device bytes a job with these parameters occupies while admitted. */
+int micsa_pool_footprint(const micsa_params* p, size_t* bytes);
+
+/* hbm_budget: bytes the pool may hold for admitted jobs; max_running >= 1.
+   hip_stream as in micsa_create.  Errors: EINVAL, ENOMEM. */
+int micsa_pool_create(size_t hbm_budget, int32_t max_running, void* hip_stream, micsa_pool** out);
+int micsa_pool_destroy(micsa_pool* pool); /* frees every job; NULL accepted */
+
+/* Queue a job (parameters and schedule are copied).  *job receives its id.
+   EINVAL for invalid parameters or schedule, or a footprint above the whole
+   budget (it could never be admitted). */
+int micsa_pool_submit(micsa_pool* pool, const micsa_params* p, const micsa_schedule* s, int64_t* job);
+
+/* Admit what fits, advance every running job by up to `sweeps` sweeps,
+   retire the finished ones (synchronous).  Outputs (may be NULL): number
+   of running and queued jobs after the step. */
+int micsa_pool_step(micsa_pool* pool, int64_t sweeps, int32_t* running, int32_t* queued);
+
+/* State of a job and its sweep counter. */
+int micsa_pool_job_state(micsa_pool* pool, int64_t job, int32_t* state, int64_t* k);
+
+/* The context of a RUNNING or DONE job (owned by the pool; valid until
+   release); read results through the micsa_read_* calls. */
+int micsa_pool_job_context(micsa_pool* pool, int64_t job, micsa_ctx** ctx);
+
+/* Free a DONE job's device memory (EINVAL for an unknown or unfinished job). */
+int micsa_pool_release(micsa_pool* pool, int64_t job);
 
 #ifdef __cplusplus
 }

@@ -16,6 +16,7 @@
 
 #include "bitplane_kernels.hpp"
 #include "fused_kernels.hpp"
+#include "resident_kernels.hpp"
 #include "micsa.h"
 
 using namespace micsa;
@@ -62,6 +63,9 @@ struct micsa_ctx {
     unsigned long long* tally = nullptr;  // [L][kSlots]
     unsigned long long* red = nullptr;    // [max(L, S)][kSlots] reduction scratch
     Schedule sched;
+    // device tables of the installed schedule, one entry per refresh index
+    DaemonThresholds* d_dth = nullptr;
+    HeatBathThresholds* d_hth = nullptr;
     int64_t k = 0;
     std::string err;
     // timing
@@ -256,6 +260,20 @@ int launch_refresh(micsa_ctx* c, int64_t rho, double T)
 
 // The fused sweep needs whole 16-site chunks per row and a work-group that
 // holds at least a one-row tile with its four ring rows.
+// Resident sweeps keep a state byte per site and a coupling byte per even
+// site (1.5 B per site) in the LDS of one work-group.
+constexpr size_t kResidentLdsMax = 150 * 1024;
+constexpr int kResidentBlock = 512;
+constexpr int64_t kResidentChunk = 2048;  // sweeps per resident launch
+
+bool resident_eligible(const micsa_ctx* c) { return !c->bit && (size_t)c->g.Nh * 3 <= kResidentLdsMax; }
+
+bool use_resident(const micsa_ctx* c)
+{
+    if (c->kernel_opt == MICSA_KERNEL_RESIDENT) return true;
+    return c->kernel_opt == MICSA_KERNEL_AUTO && resident_eligible(c);
+}
+
 bool fused_eligible(const micsa_ctx* c)
 {
     return !c->bit && c->p.Lx % 32 == 0 && 5 * (c->p.Lx / 32) <= 1024;
@@ -263,7 +281,7 @@ bool fused_eligible(const micsa_ctx* c)
 
 bool use_fused(const micsa_ctx* c)
 {
-    if (c->bit || c->kernel_opt == MICSA_KERNEL_SIMPLE) return false;
+    if (c->bit || c->kernel_opt == MICSA_KERNEL_SIMPLE || c->kernel_opt == MICSA_KERNEL_RESIDENT) return false;
     if (c->kernel_opt == MICSA_KERNEL_FUSED) return true;
     return fused_eligible(c) && c->p.Lx >= 128;
 }
@@ -413,15 +431,68 @@ inline void split_index(const micsa_ctx* c, int64_t i, int& par, int64_t& h)
     h = i >> 1;
 }
 
-int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
+// n sweeps from c->k in resident launches of up to kResidentChunk sweeps;
+// with dlog != nullptr every `stride` sweeps (U, D) per lattice are written
+// to dlog[row][L][2], rows counted from the first sweep of the call.
+int launch_resident(micsa_ctx* c, int32_t algo, int64_t n, long long* dlog, int64_t stride)
 {
-    if (!c) return MICSA_EINVAL;
+    const size_t lds = (size_t)c->g.Nh * 3;
+    static bool attr_set[2] = {false, false};
+    if (!attr_set[algo]) {
+        hipError_t e = algo == 0 ? hipFuncSetAttribute((const void*)k_resident<0>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kResidentLdsMax)
+                                 : hipFuncSetAttribute((const void*)k_resident<1>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kResidentLdsMax);
+        if (e != hipSuccess) return fail(c, MICSA_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+        attr_set[algo] = true;
+    }
+    int64_t done = 0;
+    while (done < n) {
+        int64_t chunk = std::min<int64_t>(kResidentChunk, n - done);
+        if (dlog && chunk % stride) chunk = std::max<int64_t>(stride, chunk / stride * stride);
+        chunk = std::min(chunk, n - done);
+        ResidentSched rs;
+        rs.k0 = c->k + done;
+        rs.n = chunk;
+        rs.rho0 = 0;
+        rs.period = c->sched.period;
+        rs.log_stride = dlog ? (int32_t)stride : 0;
+        rs.log_row0 = dlog ? done / stride : 0;
+        {
+            TimedLaunch t(c, algo == MICSA_ALGO_MICSA ? kTimeSweep : kTimeHeatBath);
+            if (algo == MICSA_ALGO_MICSA)
+                k_resident<0><<<c->L, kResidentBlock, lds, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally, rs,
+                                                                        c->d_dth, c->d_hth, dlog);
+            else
+                k_resident<1><<<c->L, kResidentBlock, lds, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally, rs,
+                                                                        c->d_dth, c->d_hth, dlog);
+        }
+        const int st = check_launch(c, "k_resident");
+        if (st) return st;
+        done += chunk;
+    }
+    c->k += n;
+    return MICSA_OK;
+}
+
+// Checks shared by every sweep entry point.
+int check_sweep(micsa_ctx* c, int32_t algo, int64_t n)
+{
     if (algo != MICSA_ALGO_MICSA && algo != MICSA_ALGO_HEATBATH) return fail(c, MICSA_EINVAL, "unknown algo");
     if (c->bit && algo != MICSA_ALGO_MICSA)
         return fail(c, MICSA_EINVAL, "the heat-bath baseline runs in the byte layout");
     if (n < 0) return fail(c, MICSA_EINVAL, "negative sweep count");
     if (!c->sched.set) return fail(c, MICSA_ESTATE, "no schedule installed");
     if (c->k + n > c->sched.n_sweeps) return fail(c, MICSA_ERANGE, "sweeps beyond the schedule length");
+    return MICSA_OK;
+}
+
+int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
+{
+    if (!c) return MICSA_EINVAL;
+    int st0 = check_sweep(c, algo, n);
+    if (st0) return st0;
+    if (use_resident(c)) return launch_resident(c, algo, n, nullptr, 0);
     for (int64_t i = 0; i < n; ++i) {
         const int64_t k = c->k;
         const int64_t rho = refresh_index(k, c->sched.period);
@@ -457,6 +528,8 @@ void free_all(micsa_ctx* c)
     if (c->bdm0) (void)hipFree(c->bdm0);
     if (c->bdm1) (void)hipFree(c->bdm1);
     if (c->bJ) (void)hipFree(c->bJ);
+    if (c->d_dth) (void)hipFree(c->d_dth);
+    if (c->d_hth) (void)hipFree(c->d_hth);
     if (c->J) (void)hipFree(c->J);
     if (c->tally) (void)hipFree(c->tally);
     if (c->red) (void)hipFree(c->red);
@@ -616,6 +689,32 @@ int micsa_set_schedule(micsa_ctx* ctx, const micsa_schedule* s)
     } else {
         return fail(ctx, MICSA_EINVAL, "unknown schedule kind");
     }
+    // threshold tables for every refresh of the schedule (used by the resident sweeps)
+    const int64_t nrho = std::max<int64_t>(refresh_count(n), 1);
+    std::vector<DaemonThresholds> dth((size_t)nrho);
+    std::vector<HeatBathThresholds> hth((size_t)nrho);
+    for (int64_t rho = 0; rho < nrho; ++rho) {
+        const double T = temperature(n, rho);
+        dth[(size_t)rho] = daemon_thresholds(T);
+        hth[(size_t)rho] = heatbath_thresholds(T);
+    }
+    DaemonThresholds* d1 = nullptr;
+    HeatBathThresholds* d2 = nullptr;
+    if (hipMalloc(&d1, dth.size() * sizeof(DaemonThresholds)) != hipSuccess ||
+        hipMalloc(&d2, hth.size() * sizeof(HeatBathThresholds)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (d1) (void)hipFree(d1);
+        return fail(ctx, MICSA_ENOMEM, "schedule tables");
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(d1, dth.data(), dth.size() * sizeof(DaemonThresholds), hipMemcpyHostToDevice,
+                                ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d2, hth.data(), hth.size() * sizeof(HeatBathThresholds), hipMemcpyHostToDevice,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->d_dth) (void)hipFree(ctx->d_dth);
+    if (ctx->d_hth) (void)hipFree(ctx->d_hth);
+    ctx->d_dth = d1;
+    ctx->d_hth = d2;
     ctx->sched = std::move(n);
     return MICSA_OK;
 }
@@ -630,6 +729,30 @@ int micsa_sweep_logged(micsa_ctx* ctx, int32_t algo, int64_t n, int64_t stride, 
     if (n < 0 || ctx->k + n > ctx->sched.n_sweeps) return fail(ctx, MICSA_ERANGE, "sweeps beyond the schedule");
     const int64_t rows = n / stride;
     const int L = ctx->L;
+    int st0 = check_sweep(ctx, algo, n);
+    if (st0) return st0;
+    if (use_resident(ctx)) {
+        long long* rlog = nullptr;
+        if (rows > 0 && hipMalloc(&rlog, (size_t)rows * L * 2 * 8) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(ctx, MICSA_ENOMEM, "log buffer");
+        }
+        int st = launch_resident(ctx, algo, n, rows > 0 ? rlog : nullptr, stride);
+        std::vector<int64_t> h((size_t)rows * L * 2);
+        if (!st && rows > 0 &&
+            hipMemcpyAsync(h.data(), rlog, h.size() * 8, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess)
+            st = fail(ctx, MICSA_EHIP, "log copy");
+        if (!st && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(ctx, MICSA_EHIP, "sync");
+        if (rlog) (void)hipFree(rlog);
+        if (st) return st;
+        const int64_t N = n_sites(ctx);
+        for (int64_t r = 0; r < rows; ++r)
+            for (int l = 0; l < L; ++l) {
+                if (E_log) E_log[r * L + l] = 2 * h[(size_t)((r * L + l) * 2)] - 3 * N;
+                if (D_log) D_log[r * L + l] = 4 * h[(size_t)((r * L + l) * 2 + 1)];
+            }
+        return MICSA_OK;
+    }
     unsigned long long* dlog = nullptr;
     const size_t row_len = (size_t)L * 2 * kSlots;
     if (rows > 0 && hipMalloc(&dlog, (size_t)rows * row_len * 8) != hipSuccess) {
@@ -946,6 +1069,7 @@ int micsa_get_timing(micsa_ctx* ctx, int32_t kind, double* total_ms, int64_t* la
 const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
 {
     if (ctx && ctx->bit) return algo == MICSA_ALGO_MICSA ? "kb_micsa_half" : "";
+    if (ctx && use_resident(ctx)) return algo == MICSA_ALGO_HEATBATH ? "k_resident<1>" : "k_resident<0>";
     if (algo == MICSA_ALGO_HEATBATH) return ctx && use_fused(ctx) ? "k_heatbath_sweep_fused" : "k_heatbath_half";
     if (ctx && use_fused(ctx)) return "k_micsa_sweep_fused";
     return "k_micsa_half";
@@ -956,8 +1080,11 @@ int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value)
     if (!ctx) return MICSA_EINVAL;
     switch (option) {
     case MICSA_OPT_SWEEP_KERNEL:
-        if (value != MICSA_KERNEL_AUTO && value != MICSA_KERNEL_SIMPLE && value != MICSA_KERNEL_FUSED)
+        if (value != MICSA_KERNEL_AUTO && value != MICSA_KERNEL_SIMPLE && value != MICSA_KERNEL_FUSED &&
+            value != MICSA_KERNEL_RESIDENT)
             return fail(ctx, MICSA_EINVAL, "unknown sweep kernel");
+        if (value == MICSA_KERNEL_RESIDENT && !resident_eligible(ctx))
+            return fail(ctx, MICSA_EINVAL, "the resident sweep needs a byte-layout lattice of at most 102400 sites");
         if (value == MICSA_KERNEL_FUSED && !fused_eligible(ctx))
             return fail(ctx, MICSA_EINVAL, "the fused sweep needs Lx % 32 == 0");
         ctx->kernel_opt = (int32_t)value;
@@ -974,6 +1101,233 @@ int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value)
         return MICSA_OK;
     default: return fail(ctx, MICSA_EINVAL, "unknown option");
     }
+}
+
+}  // extern "C"
+
+// =========================================================== serving pool
+namespace {
+
+struct PoolJob {
+    int64_t id = 0;
+    micsa_params p{};
+    Schedule sched;  // copied schedule (table owned here)
+    int32_t state = MICSA_JOB_QUEUED;
+    size_t bytes = 0;
+    micsa_ctx* ctx = nullptr;
+};
+
+size_t footprint(const micsa_params* p)
+{
+    const size_t N = (size_t)p->Lx * p->Ly * p->Lz;
+    const size_t L = (size_t)p->n_samples * p->n_replicas;
+    const size_t slots = (L + (size_t)p->n_samples) * kSlots * 8;
+    if (p->layout == MICSA_LAYOUT_BITPLANE) {
+        const size_t G = ((size_t)p->n_samples + 63) / 64;
+        return G * p->n_replicas * N * 8 * 3 + G * 6 * (N / 2) * 8 + slots;
+    }
+    return 4 * L * N + (size_t)p->n_samples * (N / 2) + slots;  // 2 state buffers x (spin + daemon), couplings
+}
+
+}  // namespace
+
+struct micsa_pool {
+    size_t budget = 0, used = 0;
+    int32_t max_running = 1;
+    hipStream_t stream = nullptr;
+    int64_t next_id = 1;
+    std::vector<PoolJob> jobs;  // every job not yet released, in arrival order
+    ResidentItem* d_items = nullptr;
+    size_t d_items_cap = 0;
+};
+
+extern "C" {
+
+int micsa_pool_footprint(const micsa_params* p, size_t* bytes)
+{
+    if (!p || !bytes) return MICSA_EINVAL;
+    *bytes = footprint(p);
+    return MICSA_OK;
+}
+
+int micsa_pool_create(size_t hbm_budget, int32_t max_running, void* hip_stream, micsa_pool** out)
+{
+    if (!out) return MICSA_EINVAL;
+    *out = nullptr;
+    if (hbm_budget == 0 || max_running < 1) return MICSA_EINVAL;
+    micsa_pool* pool = new (std::nothrow) micsa_pool();
+    if (!pool) return MICSA_ENOMEM;
+    pool->budget = hbm_budget;
+    pool->max_running = max_running;
+    pool->stream = (hipStream_t)hip_stream;
+    *out = pool;
+    return MICSA_OK;
+}
+
+int micsa_pool_destroy(micsa_pool* pool)
+{
+    if (!pool) return MICSA_OK;
+    for (auto& j : pool->jobs)
+        if (j.ctx) micsa_destroy(j.ctx);
+    if (pool->d_items) (void)hipFree(pool->d_items);
+    delete pool;
+    return MICSA_OK;
+}
+
+int micsa_pool_submit(micsa_pool* pool, const micsa_params* p, const micsa_schedule* s, int64_t* job)
+{
+    if (!pool || !p || !s || !job) return MICSA_EINVAL;
+    // validate parameters and schedule the same way a context would
+    if (p->Lx < 8 || p->Lx % 8 || p->Ly < 2 || p->Ly % 2 || p->Lz < 2 || p->Lz % 2) return MICSA_EINVAL;
+    if (p->n_samples < 1 || p->n_samples >= (1 << 24) || p->n_replicas < 1) return MICSA_EINVAL;
+    if (p->layout != MICSA_LAYOUT_BYTE && p->layout != MICSA_LAYOUT_BITPLANE) return MICSA_EINVAL;
+    if (s->refresh_period < 0 || s->n_sweeps < 1) return MICSA_EINVAL;
+    auto okT = [](double T) { return T > 0.0 && std::isfinite(T); };
+    if (s->kind == MICSA_SCHED_CONST ? !okT(s->T0)
+        : s->kind == MICSA_SCHED_LINEAR ? !(okT(s->T0) && okT(s->T1))
+        : s->kind != MICSA_SCHED_TABLE)
+        return MICSA_EINVAL;
+    PoolJob j;
+    j.p = *p;
+    j.sched.set = true;
+    j.sched.kind = s->kind;
+    j.sched.period = s->refresh_period;
+    j.sched.T0 = s->T0;
+    j.sched.T1 = s->T1;
+    j.sched.n_sweeps = s->n_sweeps;
+    if (s->kind == MICSA_SCHED_TABLE) {
+        if (!s->T_table || s->T_len < refresh_count(j.sched)) return MICSA_EINVAL;
+        j.sched.table.assign(s->T_table, s->T_table + s->T_len);
+    }
+    j.bytes = footprint(p);
+    if (j.bytes > pool->budget) return MICSA_EINVAL;
+    j.id = pool->next_id++;
+    *job = j.id;
+    pool->jobs.push_back(std::move(j));
+    return MICSA_OK;
+}
+
+static PoolJob* find_job(micsa_pool* pool, int64_t id)
+{
+    for (auto& j : pool->jobs)
+        if (j.id == id) return &j;
+    return nullptr;
+}
+
+int micsa_pool_step(micsa_pool* pool, int64_t sweeps, int32_t* running, int32_t* queued)
+{
+    if (!pool || sweeps < 0) return MICSA_EINVAL;
+    // 1. admit queued jobs in arrival order while they fit
+    int32_t nrun = 0;
+    for (auto& j : pool->jobs) nrun += j.state == MICSA_JOB_RUNNING;
+    for (auto& j : pool->jobs) {
+        if (j.state != MICSA_JOB_QUEUED) continue;
+        if (nrun >= pool->max_running || pool->used + j.bytes > pool->budget) break;
+        int st = micsa_create(&j.p, pool->stream, &j.ctx);
+        if (st == MICSA_ENOMEM) break;  // the device is fuller than the budget says: retry next step
+        if (st) return st;
+        micsa_schedule cs{j.sched.kind, j.sched.period, j.sched.T0, j.sched.T1, j.sched.n_sweeps,
+                          j.sched.table.empty() ? nullptr : j.sched.table.data(), (int64_t)j.sched.table.size()};
+        if ((st = micsa_set_schedule(j.ctx, &cs))) return st;
+        j.state = MICSA_JOB_RUNNING;
+        pool->used += j.bytes;
+        ++nrun;
+    }
+    // 2. advance: LDS-resident jobs in one batched launch, the others alone
+    std::vector<ResidentItem> items;
+    size_t lds = 0;
+    for (auto& j : pool->jobs) {
+        if (j.state != MICSA_JOB_RUNNING) continue;
+        micsa_ctx* c = j.ctx;
+        const int64_t n = std::min<int64_t>(sweeps, c->sched.n_sweeps - c->k);
+        if (n <= 0) continue;
+        if (use_resident(c)) {
+            ResidentSched rs{c->k, n, 0, c->sched.period, 0, 0};
+            for (int l = 0; l < c->L; ++l)
+                items.push_back(ResidentItem{c->g, c->spin, c->dem, c->J, c->tally, c->d_dth, rs, l});
+            lds = std::max(lds, (size_t)c->g.Nh * 3);
+            c->k += n;
+        } else {
+            const int st = micsa_sweep(c, MICSA_ALGO_MICSA, n);
+            if (st) return st;
+        }
+    }
+    if (!items.empty()) {
+        if (items.size() > pool->d_items_cap) {
+            if (pool->d_items) (void)hipFree(pool->d_items);
+            pool->d_items = nullptr;
+            pool->d_items_cap = 0;
+            if (hipMalloc(&pool->d_items, items.size() * sizeof(ResidentItem)) != hipSuccess) {
+                (void)hipGetLastError();
+                return MICSA_ENOMEM;
+            }
+            pool->d_items_cap = items.size();
+        }
+        if (hipMemcpyAsync(pool->d_items, items.data(), items.size() * sizeof(ResidentItem), hipMemcpyHostToDevice,
+                           pool->stream) != hipSuccess)
+            return MICSA_EHIP;
+        static bool attr = false;
+        if (!attr) {
+            if (hipFuncSetAttribute((const void*)k_resident_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kResidentLdsMax) != hipSuccess)
+                return MICSA_EHIP;
+            attr = true;
+        }
+        k_resident_batch<<<(unsigned)items.size(), kResidentBlock, lds, pool->stream>>>(pool->d_items);
+        if (hipGetLastError() != hipSuccess) return MICSA_EHIP;
+    }
+    if (hipStreamSynchronize(pool->stream) != hipSuccess) return MICSA_EHIP;
+    // 3. retire finished jobs
+    int32_t r = 0, q = 0;
+    for (auto& j : pool->jobs) {
+        if (j.state == MICSA_JOB_RUNNING && j.ctx->k >= j.ctx->sched.n_sweeps) j.state = MICSA_JOB_DONE;
+        r += j.state == MICSA_JOB_RUNNING;
+        q += j.state == MICSA_JOB_QUEUED;
+    }
+    if (running) *running = r;
+    if (queued) *queued = q;
+    return MICSA_OK;
+}
+
+int micsa_pool_job_state(micsa_pool* pool, int64_t job, int32_t* state, int64_t* k)
+{
+    if (!pool) return MICSA_EINVAL;
+    PoolJob* j = find_job(pool, job);
+    if (!j) {
+        if (job >= 1 && job < pool->next_id) {  // released
+            if (state) *state = MICSA_JOB_RELEASED;
+            if (k) *k = -1;
+            return MICSA_OK;
+        }
+        return MICSA_EINVAL;
+    }
+    if (state) *state = j->state;
+    if (k) *k = j->ctx ? j->ctx->k : 0;
+    return MICSA_OK;
+}
+
+int micsa_pool_job_context(micsa_pool* pool, int64_t job, micsa_ctx** ctx)
+{
+    if (!pool || !ctx) return MICSA_EINVAL;
+    PoolJob* j = find_job(pool, job);
+    if (!j || !j->ctx) return MICSA_EINVAL;
+    *ctx = j->ctx;
+    return MICSA_OK;
+}
+
+int micsa_pool_release(micsa_pool* pool, int64_t job)
+{
+    if (!pool) return MICSA_EINVAL;
+    for (size_t i = 0; i < pool->jobs.size(); ++i) {
+        PoolJob& j = pool->jobs[i];
+        if (j.id != job) continue;
+        if (j.state != MICSA_JOB_DONE) return MICSA_EINVAL;
+        micsa_destroy(j.ctx);
+        pool->used -= j.bytes;
+        pool->jobs.erase(pool->jobs.begin() + (long)i);
+        return MICSA_OK;
+    }
+    return MICSA_EINVAL;
 }
 
 }  // extern "C"

@@ -22,7 +22,8 @@ SCHED_CONST, SCHED_LINEAR, SCHED_TABLE = 0, 1, 2
 REFRESH_LOG2 = 0
 TIME_SWEEP, TIME_REFRESH, TIME_HEATBATH, TIME_REDUCE = 0, 1, 2, 3
 OPT_SWEEP_KERNEL, OPT_TILE_Y, OPT_TILE_Z = 1, 2, 3
-KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_FUSED = 0, 1, 2
+KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_FUSED, KERNEL_RESIDENT = 0, 1, 2, 3
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_RELEASED = 0, 1, 2, 3
 
 
 class MicsaError(RuntimeError):
@@ -74,6 +75,18 @@ _SIGNATURES = [
                                         ctypes.POINTER(ctypes.c_int64)]),
     ("micsa_kernel_name", ctypes.c_char_p, [ctypes.c_void_p, ctypes.c_int32]),
     ("micsa_set_option", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64]),
+    ("micsa_pool_footprint", ctypes.c_int, [ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_size_t)]),
+    ("micsa_pool_create", ctypes.c_int, [ctypes.c_size_t, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    ("micsa_pool_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("micsa_pool_submit", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Params), ctypes.POINTER(_Schedule),
+                                         ctypes.POINTER(ctypes.c_int64)]),
+    ("micsa_pool_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]),
+    ("micsa_pool_job_state", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int64)]),
+    ("micsa_pool_job_context", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p)]),
+    ("micsa_pool_release", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
 ]
 
 
@@ -119,8 +132,30 @@ class Schedule:
     table: np.ndarray | None = None
 
 
+def _schedule_struct(s: "Schedule"):
+    tab, n, keep = None, 0, None
+    if s.table is not None:
+        keep = np.ascontiguousarray(s.table, np.float64)
+        tab, n = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(keep)
+    return _Schedule(s.kind, s.period, s.T0, s.T1, s.n_sweeps, tab, n), keep
+
+
 class Lattice:
     """S samples x R replicas on the GPU (one libmicsa context)."""
+
+    _owned = True
+
+    @classmethod
+    def _borrow(cls, ctx: ctypes.c_void_p, Lx, Ly, Lz, S, R, seed=0) -> "Lattice":
+        """A view of a context owned by someone else (a pool job): never destroyed here."""
+        obj = cls.__new__(cls)
+        obj.Lx, obj.Ly, obj.Lz, obj.S, obj.R = Lx, Ly, Lz, S, R
+        obj.N = Lx * Ly * Lz
+        obj.seed = seed
+        obj._ctx = ctx
+        obj._owned = False
+        obj._table = None
+        return obj
 
     def __init__(self, Lx: int, Ly: int, Lz: int, S: int = 1, R: int = 1, seed: int = 0,
                  layout: int = LAYOUT_BYTE, stream=None):
@@ -142,9 +177,9 @@ class Lattice:
             raise MicsaError(st, f"{what}: {lib().micsa_status_string(st).decode()}: {msg}")
 
     def close(self) -> None:
-        if self._ctx:
+        if self._ctx and self._owned:
             lib().micsa_destroy(self._ctx)
-            self._ctx = ctypes.c_void_p()
+        self._ctx = ctypes.c_void_p()
 
     def __del__(self):
         try:
@@ -160,11 +195,7 @@ class Lattice:
 
     # -- schedule and sweeps --------------------------------------------
     def set_schedule(self, s: Schedule) -> None:
-        tab, n = None, 0
-        if s.table is not None:
-            self._table = np.ascontiguousarray(s.table, np.float64)
-            tab, n = self._table.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(self._table)
-        cs = _Schedule(s.kind, s.period, s.T0, s.T1, s.n_sweeps, tab, n)
+        cs, self._table = _schedule_struct(s)
         self._check(lib().micsa_set_schedule(self._ctx, ctypes.byref(cs)), "set_schedule")
 
     def sweep(self, algo: int, n: int) -> None:
@@ -253,3 +284,66 @@ class Lattice:
 
     def kernel_name(self, algo: int) -> str:
         return lib().micsa_kernel_name(self._ctx, algo).decode()
+
+
+def footprint(Lx: int, Ly: int, Lz: int, S: int = 1, R: int = 1, layout: int = LAYOUT_BYTE) -> int:
+    """Device bytes a pool job of this shape occupies."""
+    out = ctypes.c_size_t()
+    st = lib().micsa_pool_footprint(ctypes.byref(_Params(Lx, Ly, Lz, S, R, layout, 0)), ctypes.byref(out))
+    if st != OK:
+        raise MicsaError(st, "micsa_pool_footprint")
+    return out.value
+
+
+class Pool:
+    """Continuous-batching pool of annealing jobs (micsa_pool_*)."""
+
+    def __init__(self, hbm_budget: int, max_running: int = 1 << 20, stream=None):
+        self._pool = ctypes.c_void_p()
+        st = lib().micsa_pool_create(int(hbm_budget), int(max_running), _stream_handle(stream),
+                                     ctypes.byref(self._pool))
+        if st != OK:
+            raise MicsaError(st, "micsa_pool_create")
+        self._jobs = {}
+
+    def close(self) -> None:
+        if self._pool:
+            lib().micsa_pool_destroy(self._pool)
+            self._pool = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, what: str) -> None:
+        if st != OK:
+            raise MicsaError(st, f"{what}: {lib().micsa_status_string(st).decode()}")
+
+    def submit(self, Lx, Ly, Lz, S, R, seed, sched: Schedule, layout: int = LAYOUT_BYTE) -> int:
+        p = _Params(Lx, Ly, Lz, S, R, layout, seed & (2**64 - 1))
+        cs, keep = _schedule_struct(sched)
+        job = ctypes.c_int64()
+        self._check(lib().micsa_pool_submit(self._pool, ctypes.byref(p), ctypes.byref(cs), ctypes.byref(job)),
+                    "pool_submit")
+        self._jobs[job.value] = (Lx, Ly, Lz, S, R, seed)
+        return job.value
+
+    def step(self, sweeps: int) -> tuple[int, int]:
+        r, q = ctypes.c_int32(), ctypes.c_int32()
+        self._check(lib().micsa_pool_step(self._pool, int(sweeps), ctypes.byref(r), ctypes.byref(q)), "pool_step")
+        return r.value, q.value
+
+    def state(self, job: int) -> tuple[int, int]:
+        st, k = ctypes.c_int32(), ctypes.c_int64()
+        self._check(lib().micsa_pool_job_state(self._pool, job, ctypes.byref(st), ctypes.byref(k)), "job_state")
+        return st.value, k.value
+
+    def lattice(self, job: int) -> Lattice:
+        ctx = ctypes.c_void_p()
+        self._check(lib().micsa_pool_job_context(self._pool, job, ctypes.byref(ctx)), "job_context")
+        return Lattice._borrow(ctx, *self._jobs[job])
+
+    def release(self, job: int) -> None:
+        self._check(lib().micsa_pool_release(self._pool, job), "pool_release")

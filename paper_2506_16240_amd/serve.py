@@ -1,0 +1,114 @@
+"""Annealing service driver: Poisson arrivals into a continuous-batching pool.
+
+Jobs are instances of the 3D EA +-J model with L uniform in {8, 16, 32, 64,
+128} and 1..64 replicas of one sample, annealed with MicSA from T = 3.0 to
+0.1 over 2000 sweeps (refresh every 10 sweeps).  Arrivals follow a Poisson
+process of the given rate; each arrival is submitted to the pool as soon as
+its time has passed, and the pool advances every running job by
+`sweeps_per_step` sweeps per step, admitting queued jobs as memory frees
+up.  The time to solution of a job is its completion time minus its arrival
+time.  All device work happens in libmicsa.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import micsa as M
+
+L_CHOICES = (8, 16, 32, 64, 128)
+
+
+def splitmix64(x: int) -> int:
+    """Job seed from (stream seed, job id): the SplitMix64 finaliser."""
+    x = (x + 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+    x = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & 0xFFFFFFFFFFFFFFFF
+    x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & 0xFFFFFFFFFFFFFFFF
+    return x ^ (x >> 31)
+
+
+@dataclass
+class JobSpec:
+    L: int
+    R: int
+    seed: int
+    T0: float = 3.0
+    T1: float = 0.1
+    n_sweeps: int = 2000
+    period: int = 10
+
+    @property
+    def updates(self) -> int:
+        return self.L ** 3 * self.R * self.n_sweeps
+
+
+@dataclass
+class JobResult:
+    spec: JobSpec
+    arrival: float
+    done: float = float("nan")
+    best_energy: int = 0
+    energies: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int64))
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+def job_stream(n_jobs: int, rate: float, seed: int, n_sweeps: int = 2000, L_choices=L_CHOICES,
+               max_replicas: int = 64) -> list[tuple[float, JobSpec]]:
+    """Poisson arrivals (exponential gaps of mean 1/rate seconds) with random sizes."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for j in range(n_jobs):
+        t += float(rng.exponential(1.0 / rate))
+        spec = JobSpec(int(rng.choice(L_choices)), int(rng.integers(1, max_replicas + 1)),
+                       splitmix64((seed << 20) ^ j), n_sweeps=n_sweeps)
+        out.append((t, spec))
+    return out
+
+
+def serve(stream: list[tuple[float, JobSpec]], hbm_budget: int, sweeps_per_step: int = 100,
+          max_running: int = 1 << 20) -> tuple[list[JobResult], dict]:
+    """Run the arrival stream through a pool; returns per-job results and metrics."""
+    pool = M.Pool(hbm_budget, max_running)
+    results: dict[int, JobResult] = {}
+    pending = list(stream)
+    t0 = time.perf_counter()
+    live: set[int] = set()
+    max_running_seen = 0
+    while pending or live:
+        now = time.perf_counter() - t0
+        while pending and pending[0][0] <= now:
+            arr, spec = pending.pop(0)
+            job = pool.submit(spec.L, spec.L, spec.L, 1, spec.R, spec.seed,
+                              M.Schedule(M.SCHED_LINEAR, spec.T0, spec.T1, spec.n_sweeps, spec.period))
+            results[job] = JobResult(spec, arr)
+            live.add(job)
+        if not live:
+            time.sleep(max(0.0, min(pending[0][0] - now, 0.05)))
+            continue
+        running, _ = pool.step(sweeps_per_step)
+        max_running_seen = max(max_running_seen, running)
+        now = time.perf_counter() - t0
+        for job in list(live):
+            st, _ = pool.state(job)
+            if st == M.JOB_DONE:
+                lat = pool.lattice(job)
+                E = lat.energy()
+                r = results[job]
+                r.done, r.energies, r.best_energy = now, E, int(E.min())
+                pool.release(job)
+                live.discard(job)
+    wall = time.perf_counter() - t0
+    pool.close()
+    res = [results[j] for j in sorted(results)]
+    lat = np.array([r.latency for r in res])
+    upd = sum(r.spec.updates for r in res)
+    metrics = {"jobs": len(res), "wall_s": wall, "p50_s": float(np.percentile(lat, 50)),
+               "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
+               "updates_per_ns": upd / (wall * 1e9), "max_running": max_running_seen}
+    return res, metrics

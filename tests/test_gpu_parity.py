@@ -67,10 +67,12 @@ def test_thresholds_bitexact():
             assert np.array_equal(g.heatbath_thresholds(rho), O.heatbath_thresholds(T)), (gs, rho)
 
 
+@pytest.mark.parametrize("kernel", [M.KERNEL_SIMPLE, M.KERNEL_RESIDENT])
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("algo", [M.ALGO_MICSA, M.ALGO_HEATBATH])
-def test_trajectory_matches_oracle(shape, algo):
+def test_trajectory_matches_oracle(shape, algo, kernel):
     g, o = pair(*shape, seed=77)
+    g.set_option(M.OPT_SWEEP_KERNEL, kernel)
     n = 37
     gs, os_ = scheds(M.SCHED_LINEAR, 2.5, 0.4, n, 6)
     g.set_schedule(gs)
@@ -95,11 +97,13 @@ def test_log2_refresh_schedule_matches_oracle():
     same_state(g, o)
 
 
-def test_paramagnet_L16_full_length():
+@pytest.mark.parametrize("kernel", [M.KERNEL_AUTO, M.KERNEL_SIMPLE])
+def test_paramagnet_L16_full_length(kernel):
     """L = 16, T = 1.5, refresh every 10 sweeps, 1000 sweeps, energy logged per
     sweep: bit-exact, and H^EA + H^aux conserved between refreshes."""
     w = W.PARAMAGNET_L16
     g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
+    g.set_option(M.OPT_SWEEP_KERNEL, kernel)
     gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
     g.set_schedule(gs)
     Eg, Dg = g.sweep_logged(M.ALGO_MICSA, w.n_sweeps, 1)
@@ -111,6 +115,23 @@ def test_paramagnet_L16_full_length():
         if r % w.period != 0:  # sweep r did not start with a refresh
             assert tot[r] == tot[r - 1]
     assert np.array_equal(g.energy_tally(), g.energy())
+
+
+def test_resident_chunks_and_log_strides():
+    """Resident launches split long runs into chunks; logs and state must not
+    depend on where the chunks fall."""
+    shape = (16, 8, 8, 2, 2)
+    n = 4500  # crosses two chunk boundaries
+    for stride in (1, 7, 1000):
+        g, o = pair(*shape, seed=8)
+        g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_RESIDENT)
+        gs, os_ = scheds(M.SCHED_LINEAR, 3.0, 0.3, n, 9)
+        g.set_schedule(gs)
+        Eg, Dg = g.sweep_logged(M.ALGO_MICSA, n, stride)
+        Eo, Do = o.run(O.ALGO_MICSA, os_, n, stride)
+        assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+        same_state(g, o)
+        assert np.array_equal(g.energy_tally(), o.energy())
 
 
 def test_quench_L64_shape():
@@ -225,13 +246,20 @@ def test_gpu_error_paths():
 
 def test_timing_counts_launches():
     g, _ = pair(16, 16, 16)
+    g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_SIMPLE)
     g.set_schedule(M.Schedule(M.SCHED_CONST, 1.5, 1.5, 20, 10))
     g.set_timing(True)
     g.sweep(M.ALGO_MICSA, 20)
     ms, n = g.timing(M.TIME_SWEEP)
-    assert n >= 20 and ms > 0
+    assert n == 40 and ms > 0  # two half-sweep launches per sweep
     ms_r, n_r = g.timing(M.TIME_REFRESH)
     assert n_r == 2
+    h, _ = pair(16, 16, 16)
+    h.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_RESIDENT)
+    h.set_schedule(M.Schedule(M.SCHED_CONST, 1.5, 1.5, 20, 10))
+    h.set_timing(True)
+    h.sweep(M.ALGO_MICSA, 20)
+    assert h.timing(M.TIME_SWEEP)[1] == 1  # all 20 sweeps in one launch
 
 
 # ----------------------------------------------------------- fused sweep
@@ -276,8 +304,8 @@ def test_every_launch_shape_gives_the_same_bits():
     shape = (64, 16, 12, 1, 2)
     n = 30
     ref = None
-    variants = [(M.KERNEL_SIMPLE, 0, 0)] + [(M.KERNEL_FUSED, ty, tz) for ty in (1, 2, 4, 8, 16)
-                                            for tz in (1, 3, 4, 12)]
+    variants = [(M.KERNEL_SIMPLE, 0, 0), (M.KERNEL_RESIDENT, 0, 0)] + [
+        (M.KERNEL_FUSED, ty, tz) for ty in (1, 2, 4, 8, 16) for tz in (1, 3, 4, 12)]
     for kern, ty, tz in variants:
         g = M.Lattice(*shape, seed=2024)
         g.set_option(M.OPT_SWEEP_KERNEL, kern)
@@ -304,6 +332,10 @@ def test_tile_options_are_validated():
     h = M.Lattice(40, 8, 8, seed=1)
     with pytest.raises(M.MicsaError) as e:
         h.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)
+    assert e.value.status == M.EINVAL
+    big = M.Lattice(64, 64, 64, seed=1)  # 2.5 B/site does not fit one work-group's LDS
+    with pytest.raises(M.MicsaError) as e:
+        big.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_RESIDENT)
     assert e.value.status == M.EINVAL
 
 

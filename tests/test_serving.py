@@ -1,0 +1,129 @@
+"""Serving pool: admission by HBM footprint, continuous batching, and results
+that do not depend on the other jobs in the pool."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2506_16240_amd import micsa as M
+from paper_2506_16240_amd import serve as SV
+
+
+# ------------------------------------------------------------ CPU checks
+def test_footprint_grows_with_size():
+    a = M.footprint(8, 8, 8, 1, 1)
+    b = M.footprint(16, 16, 16, 1, 1)
+    c = M.footprint(16, 16, 16, 1, 4)
+    assert 0 < a < b < c
+    # byte layout: two state buffers of spin + daemon bytes, plus couplings
+    assert b >= 4 * 16 ** 3
+
+
+def test_submit_validation_without_device():
+    pool = M.Pool(hbm_budget=1 << 20)
+    sched = M.Schedule(M.SCHED_LINEAR, 3.0, 0.1, 100, 10)
+    for bad in ((7, 8, 8), (8, 3, 8), (8, 8, 0)):
+        with pytest.raises(M.MicsaError) as e:
+            pool.submit(*bad, 1, 1, 1, sched)
+        assert e.value.status == M.EINVAL
+    with pytest.raises(M.MicsaError) as e:  # larger than the whole budget: could never run
+        pool.submit(128, 128, 128, 1, 64, 1, sched)
+    assert e.value.status == M.EINVAL
+    with pytest.raises(M.MicsaError) as e:
+        pool.submit(8, 8, 8, 1, 1, 1, M.Schedule(M.SCHED_CONST, -1.0, 1.0, 100, 10))
+    assert e.value.status == M.EINVAL
+    job = pool.submit(8, 8, 8, 1, 2, 1, sched)
+    assert pool.state(job) == (M.JOB_QUEUED, 0)
+    with pytest.raises(M.MicsaError):
+        pool.release(job)  # not finished
+    pool.close()
+
+
+def test_job_stream_is_seeded():
+    a = SV.job_stream(20, 50.0, 7)
+    b = SV.job_stream(20, 50.0, 7)
+    assert a == b
+    assert all(s.L in SV.L_CHOICES and 1 <= s.R <= 64 for _, s in a)
+    assert len({s.seed for _, s in a}) == 20
+    assert all(t1 < t2 for (t1, _), (t2, _) in zip(a, a[1:]))
+
+
+# ------------------------------------------------------------ GPU checks
+def _run_alone(spec, sweeps_per_step):
+    pool = M.Pool(1 << 34)
+    job = pool.submit(spec.L, spec.L, spec.L, 1, spec.R, spec.seed,
+                      M.Schedule(M.SCHED_LINEAR, spec.T0, spec.T1, spec.n_sweeps, spec.period))
+    while pool.state(job)[0] != M.JOB_DONE:
+        pool.step(sweeps_per_step)
+    lat = pool.lattice(job)
+    out = (lat.energy(), lat.spins(), lat.daemons(), lat.energy_tally())
+    pool.release(job)
+    pool.close()
+    return out
+
+
+@pytest.mark.gpu
+def test_job_alone_equals_job_in_the_mix():
+    """A job's final state is bit-identical alone and among other jobs that
+    arrive before and after it, of other sizes and kernels."""
+    target = SV.JobSpec(16, 3, 0xC0FFEE, n_sweeps=300)
+    alone = _run_alone(target, 37)
+    others = [SV.JobSpec(8, 5, 11, n_sweeps=120), SV.JobSpec(32, 2, 12, n_sweeps=400),
+              SV.JobSpec(64, 1, 13, n_sweeps=90), SV.JobSpec(16, 7, 14, n_sweeps=250),
+              SV.JobSpec(128, 1, 15, n_sweeps=20)]
+    pool = M.Pool(1 << 34)
+    sub = lambda s: pool.submit(s.L, s.L, s.L, 1, s.R, s.seed,
+                                M.Schedule(M.SCHED_LINEAR, s.T0, s.T1, s.n_sweeps, s.period))
+    ids = [sub(others[0]), sub(others[1])]
+    pool.step(50)
+    tid = sub(target)  # arrives while others are running
+    ids.append(sub(others[2]))
+    steps = 0
+    while pool.state(tid)[0] != M.JOB_DONE:
+        pool.step(37)
+        steps += 1
+        if steps == 2:
+            ids += [sub(others[3]), sub(others[4])]
+    lat = pool.lattice(tid)
+    mixed = (lat.energy(), lat.spins(), lat.daemons(), lat.energy_tally())
+    for a, b in zip(alone, mixed):
+        assert np.array_equal(a, b)
+    # and the job equals the oracle's trajectory
+    o = O.Lattice(16, 16, 16, 1, 3, 0xC0FFEE)
+    o.run(O.ALGO_MICSA, O.Schedule(O.SCHED_LINEAR, 3.0, 0.1, 300, 10), 300, 0)
+    assert np.array_equal(mixed[1], o.sigma) and np.array_equal(mixed[0], o.energy())
+    pool.close()
+
+
+@pytest.mark.gpu
+def test_admission_respects_the_budget():
+    spec = SV.JobSpec(32, 4, 1, n_sweeps=60)
+    fp = M.footprint(32, 32, 32, 1, 4)
+    pool = M.Pool(int(fp * 2.5))  # room for two such jobs at a time
+    jobs = [pool.submit(32, 32, 32, 1, 4, 100 + i, M.Schedule(M.SCHED_LINEAR, 3.0, 0.1, 60, 10)) for i in range(5)]
+    seen = 0
+    finished = set()
+    for _ in range(50):
+        running, queued = pool.step(20)
+        assert running <= 2
+        seen = max(seen, running)
+        for j in jobs:
+            if j not in finished and pool.state(j)[0] == M.JOB_DONE:
+                finished.add(j)
+                pool.release(j)
+        if len(finished) == len(jobs):
+            break
+    assert seen == 2 and len(finished) == 5
+    del spec
+    pool.close()
+
+
+@pytest.mark.gpu
+def test_serve_short_stream():
+    stream = SV.job_stream(12, 200.0, 3, n_sweeps=200)
+    res, m = SV.serve(stream, hbm_budget=1 << 33, sweeps_per_step=50)
+    assert m["jobs"] == 12 and all(np.isfinite(r.latency) and r.latency > 0 for r in res)
+    assert m["p99_s"] >= m["p50_s"] > 0
+    for r in res:
+        N = r.spec.L ** 3
+        assert len(r.energies) == r.spec.R and r.best_energy == r.energies.min()
+        assert -3 * N <= r.best_energy <= 3 * N
