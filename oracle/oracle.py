@@ -20,7 +20,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# MICSA_ORACLE_LIB points the tests at another build of oracle.c (the
+# planted-mistake tests compile altered copies to check the pins fail).
+LIB_PATH = os.environ.get("MICSA_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "oracle.c")
 
 ALGO_MICSA, ALGO_HEATBATH = 0, 1

@@ -1,0 +1,59 @@
+"""Planted mistakes: each plausible error in the oracle (a dropped term, a
+wrong sign, index or bound, a transposed operand) must make at least one of
+the oracle pins in test_oracle.py fail.  Each altered copy of oracle.c is
+compiled into a temporary library and the pins run against it in a child
+process; nothing here touches the real oracle or any GPU code."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+# (name, original text, planted text, pins that must catch it)
+MUTATIONS = [
+    ("flip window upper bound", "n - dH <= 12", "n - dH < 12", "local_move or conservation"),
+    ("sign of dH", "int dH = 2 * spin(sig[i]) * local_field(g, Js, sig, i);",
+     "int dH = -2 * spin(sig[i]) * local_field(g, Js, sig, i);", "local_move or conservation"),
+    ("dropped backward bond", "        h += coupling(J[bwd[mu]], mu) * spin(sig[bwd[mu]]);\n", "",
+     "local_move or conservation or gauge"),
+    ("wrong neighbour index", "int64_t fwd[3] = {site(g, x + 1, y, z), site(g, x, y + 1, z), site(g, x, y, z + 1)};",
+     "int64_t fwd[3] = {site(g, x + 1, y, z), site(g, x, y - 1, z), site(g, x, y, z + 1)};",
+     "local_move or conservation"),
+    ("daemon update sign", "dm[i] = (uint8_t)((n - dH) / 4);", "dm[i] = (uint8_t)((n + dH) / 4);",
+     "local_move or conservation"),
+    ("energy transposed operand", "H -= coupling(Js[i], mu) * spin(sig[i]) * spin(sig[fwd[mu]]);",
+     "H -= coupling(Js[fwd[mu]], mu) * spin(sig[i]) * spin(sig[fwd[mu]]);", "energy or local_move"),
+    ("daemon CDF exponent", "expm1(-4.0 * beta * (double)(k + 1))", "expm1(-4.0 * beta * (double)(k))",
+     "daemon_thresholds"),
+    ("daemon CDF normaliser", "expm1(-16.0 * beta)", "expm1(-12.0 * beta)", "daemon_thresholds"),
+    ("heat-bath sign", "exp(-2.0 * beta * h)", "exp(2.0 * beta * h)", "heatbath"),
+    ("parity", "return (x + y + z) & 1;", "return (x + y) & 1;", "local_move or order or involution"),
+    ("Philox Weyl constant", "#define PHILOX_W1 0xBB67AE85u", "#define PHILOX_W1 0xBB67AE86u", "philox"),
+    ("Philox word order", "uint32_t n0 = hi1 ^ c1 ^ k0;", "uint32_t n0 = hi0 ^ c1 ^ k0;", "philox"),
+    ("overlap product", "q += spin(sa[i]) * spin(sb[i]);", "q += spin(sa[i]) * spin(sa[i]);", "overlap"),
+    ("linear schedule end", "return T0 * (1.0 - f) + T1 * f;", "return T0 * (1.0 - f) + T1;", "schedule"),
+    ("log refresh points", "return ((k + 1) & k) == 0;", "return (k & (k - 1)) == 0;", "schedule"),
+]
+
+
+@pytest.mark.parametrize("name,orig,planted,pins", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_is_caught(name, orig, planted, pins, tmp_path):
+    src = open(SRC).read()
+    assert src.count(orig) >= 1, f"mutation target not found: {orig!r}"
+    mutated = src.replace(orig, planted, 1)
+    c = tmp_path / "oracle_mut.c"
+    c.write_text(mutated)
+    lib = tmp_path / "liboracle_mut.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                           "-o", str(lib), str(c), "-lm"])
+    env = dict(os.environ, MICSA_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(HERE, "test_oracle.py"), "-k", pins],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    # caught means a pin assertion failed (not: no test selected, or a crash)
+    assert r.returncode == 1 and " failed" in r.stdout, \
+        f"planted mistake '{name}' was not caught by the pins:\n{r.stdout[-2000:]}"
