@@ -290,6 +290,31 @@ void oracle_heatbath_half(int Lx, int Ly, int Lz, int S, int R, uint64_t seed, i
 }
 
 /* ------------------------------------------------------------------ */
+/* Walkers (Sec. 2.6): a wandering step along direction dir (0..5 = +x, */
+/* -x, +y, -y, +z, -z) exchanges the auxiliary variable of every site x */
+/* of the given parity with that of its neighbour x + e_dir.  Forward-X */
+/* wandering is the two-timestep cycle: even sites at even timesteps,   */
+/* odd sites at odd timesteps.                                          */
+/* ------------------------------------------------------------------ */
+void oracle_wander(int Lx, int Ly, int Lz, int S, int R, int dir, int parity, uint8_t *m)
+{
+    geom g = mk(Lx, Ly, Lz);
+    static const int step[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+    for (int l = 0; l < S * R; l++) {
+        uint8_t *dm = m + (int64_t)l * g.N;
+        for (int64_t i = 0; i < g.N; i++) {
+            if (parity_of(&g, i) != parity) continue;
+            int x, y, z;
+            coords(&g, i, &x, &y, &z);
+            int64_t j = site(&g, x + step[dir][0], y + step[dir][1], z + step[dir][2]);
+            uint8_t t = dm[i];
+            dm[i] = dm[j];
+            dm[j] = t;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* Observables                                                          */
 /* ------------------------------------------------------------------ */
 /* H^EA = - sum over bonds J_xy s_x s_y (eq. Hamiltonian), each bond once
@@ -385,12 +410,13 @@ double oracle_temperature(int kind, double T0, double T1, int64_t n_sweeps, int 
 /* ------------------------------------------------------------------ */
 /* Driver: sweeps k0 .. k0+n-1 of one algorithm on the state in place. */
 /* A sweep is the even half followed by the odd half (Sec. 2.8).  For  */
-/* MicSA the daemons are refreshed before sweep k when k is a refresh  */
+/* MicSA (daemons or, with ALGO_WALKERS, one forward-X walker per site) */
+/* the auxiliary variables are refreshed before sweep k when k is a refresh  */
 /* point; the heat bath uses the temperature of the last refresh point */
 /* at or before k.  After every `stride` sweeps the from-scratch H^EA  */
 /* and H^aux of every lattice are logged.  dE accumulates the tally.   */
 /* ------------------------------------------------------------------ */
-enum { ALGO_MICSA = 0, ALGO_HEATBATH = 1 };
+enum { ALGO_MICSA = 0, ALGO_HEATBATH = 1, ALGO_WALKERS = 2 };
 
 int oracle_run(int Lx, int Ly, int Lz, int S, int R, uint64_t seed, int algo, int kind, double T0,
                double T1, int64_t n_sweeps, int P, const double *table, int64_t table_len, int64_t k0,
@@ -404,10 +430,13 @@ int oracle_run(int Lx, int Ly, int Lz, int S, int R, uint64_t seed, int algo, in
         int64_t rho = oracle_refresh_index(k, P);
         double T = oracle_temperature(kind, T0, T1, n_sweeps, P, table, table_len, rho);
         if (!(T > 0.0) || isinf(T)) return -1;
-        if (algo == ALGO_MICSA) {
+        if (algo == ALGO_MICSA || algo == ALGO_WALKERS) {
             if (oracle_is_refresh(k, P)) oracle_refresh(Lx, Ly, Lz, S, R, seed, rho, T, m);
             oracle_micsa_half(Lx, Ly, Lz, S, R, 0, J, sigma, m, dE);
             oracle_micsa_half(Lx, Ly, Lz, S, R, 1, J, sigma, m, dE);
+            /* gamma = 1 walker: one sweep per timestep t = k, then the part of
+               the forward-X cycle given by the parity of t (Sec. 2.8.1 step b) */
+            if (algo == ALGO_WALKERS) oracle_wander(Lx, Ly, Lz, S, R, 0, (int)(k & 1), m);
         } else if (algo == ALGO_HEATBATH) {
             oracle_heatbath_half(Lx, Ly, Lz, S, R, seed, k, 0, T, J, sigma, dE);
             oracle_heatbath_half(Lx, Ly, Lz, S, R, seed, k, 1, T, J, sigma, dE);

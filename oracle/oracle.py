@@ -25,7 +25,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MICSA_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "oracle.c")
 
-ALGO_MICSA, ALGO_HEATBATH = 0, 1
+ALGO_MICSA, ALGO_HEATBATH, ALGO_WALKERS = 0, 1, 2
 SCHED_CONST, SCHED_LINEAR, SCHED_TABLE = 0, 1, 2
 REFRESH_LOG2 = 0
 
@@ -71,6 +71,7 @@ def lib():
         L.oracle_micsa_site.restype = c.c_int
         L.oracle_heatbath_half.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
                                            c.c_int64, c.c_int, c.c_double, _u8p, _u8p, _i64p]
+        L.oracle_wander.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, _u8p]
         L.oracle_energy.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, _u8p, _u8p, _i64p]
         L.oracle_daemon_energy.argtypes = [c.c_int64, c.c_int, _u8p, _i64p]
         L.oracle_overlap.argtypes = [c.c_int64, c.c_int, c.c_int, c.c_int, c.c_int, _u8p, _i64p]
@@ -205,6 +206,11 @@ class Lattice:
         self.m[s, r] = m
         self.tally[s * self.R + r] += dH
         return dH
+
+    def wander(self, direction: int, parity: int) -> None:
+        """Exchange the auxiliary variable of every site of `parity` with its
+        neighbour along `direction` (0..5 = +x, -x, +y, -y, +z, -z)."""
+        lib().oracle_wander(*self._dims(), int(direction), int(parity), self.m)
 
     def heatbath_half(self, k: int, parity: int, T: float) -> None:
         dE = np.zeros(self.S * self.R, np.int64)

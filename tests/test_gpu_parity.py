@@ -219,6 +219,37 @@ def test_written_state_is_swept_identically():
     same_state(g, o)
 
 
+@pytest.mark.parametrize("layout", [M.LAYOUT_BYTE, M.LAYOUT_BITPLANE])
+@pytest.mark.parametrize("algo", [M.ALGO_MICSA, M.ALGO_HEATBATH])
+def test_graph_replays_match_eager_launches(layout, algo):
+    """Replayed graphs (16 sweeps each, device sweep counter) give the same bits
+    as eager launches and as the oracle, over several calls with eager work
+    and reads in between and a refresh period that does not divide 16."""
+    if layout == M.LAYOUT_BITPLANE and algo == M.ALGO_HEATBATH:
+        pytest.skip("the heat bath runs in the byte layout")
+    shape = (64, 8, 6, 3, 2)  # byte: neither resident (forced simple) nor fused
+    res = []
+    for graphs in (1, 0):
+        g = M.Lattice(*shape, seed=515, layout=layout)
+        if layout == M.LAYOUT_BYTE:
+            g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_SIMPLE)
+        g.set_option(M.OPT_GRAPHS, graphs)
+        g.set_schedule(M.Schedule(M.SCHED_LINEAR, 2.6, 0.3, 200, 7))
+        E = []
+        for n in (40, 3, 33, 16, 50):
+            g.sweep(algo, n)
+            E.append(g.energy())  # eager reduction between replays
+        res.append((np.array(E), g.spins(), g.daemons(), g.counters()))
+        g.close()
+    for a, b in zip(res[0][:3], res[1][:3]):
+        assert np.array_equal(a, b)
+    assert res[0][3] == res[1][3] == (142, 20)
+    o = O.Lattice(*shape, seed=515)
+    o.run(algo, O.Schedule(O.SCHED_LINEAR, 2.6, 0.3, 200, 7), 142, 0)
+    assert np.array_equal(res[0][1], o.sigma)
+    assert np.array_equal(res[0][0][-1], o.energy())
+
+
 def test_gpu_error_paths():
     g, _ = pair(8, 8, 8)
     with pytest.raises(M.MicsaError) as e:
@@ -304,11 +335,13 @@ def test_every_launch_shape_gives_the_same_bits():
     shape = (64, 16, 12, 1, 2)
     n = 30
     ref = None
-    variants = [(M.KERNEL_SIMPLE, 0, 0), (M.KERNEL_RESIDENT, 0, 0)] + [
-        (M.KERNEL_FUSED, ty, tz) for ty in (1, 2, 4, 8, 16) for tz in (1, 3, 4, 12)]
-    for kern, ty, tz in variants:
+    variants = [(M.KERNEL_SIMPLE, 0, 0, 1), (M.KERNEL_RESIDENT, 0, 0, 1)] + [
+        (M.KERNEL_FUSED, ty, tz, 1) for ty in (1, 2, 4, 8, 16) for tz in (1, 3, 4, 12)] + [
+        (M.KERNEL_FUSED, 1, 3, 0), (M.KERNEL_FUSED, 4, 1, 0)]
+    for kern, ty, tz, xcd in variants:
         g = M.Lattice(*shape, seed=2024)
         g.set_option(M.OPT_SWEEP_KERNEL, kern)
+        g.set_option(M.OPT_XCD_MAP, xcd)
         if ty:
             g.set_option(M.OPT_TILE_Y, ty)
             g.set_option(M.OPT_TILE_Z, tz)
@@ -319,7 +352,7 @@ def test_every_launch_shape_gives_the_same_bits():
             ref = got
         else:
             for a, b in zip(ref, got):
-                assert np.array_equal(a, b), (kern, ty, tz)
+                assert np.array_equal(a, b), (kern, ty, tz, xcd)
         g.close()
 
 

@@ -446,3 +446,71 @@ def test_paramagnet_sanity_band():
     (m1, e1), (m2, e2) = res[O.ALGO_MICSA], res[O.ALGO_HEATBATH]
     assert abs(m1 - m2) <= 5 * math.hypot(e1, e2) + 2e-4
     assert m1 > -1.607 and m2 > -1.607
+
+
+# ------------------------------------------------------------------ walkers
+def test_wandering_is_a_permutation_and_an_involution():
+    L = O.Lattice(6, 4, 8, 2, 2, seed=17)
+    L.refresh(0, 0.6)
+    m0 = L.m.copy()
+    for d in range(6):
+        for p in (0, 1):
+            L.wander(d, p)
+            assert np.array_equal(np.sort(L.m, axis=2), np.sort(m0, axis=2))  # same multiset per lattice
+            L.wander(d, p)
+            assert np.array_equal(L.m, m0)  # the same exchange twice is the identity
+
+
+def test_forward_walkers_return_after_L_timesteps():
+    """Sec. 2.6: after L/2 cycles (L timesteps) every forward-wandering walker is
+    back at its starting site; a walker starting on an even site moves +1 per
+    timestep in between."""
+    for d, Ld in ((0, 8), (2, 6), (4, 4), (1, 8), (5, 4)):
+        L = O.Lattice(8, 6, 4, 1, 1, seed=3)
+        N = L.N
+        L.m[0, 0] = np.arange(N) % 251  # label the walkers
+        L.m[0, 0, 0] = 255               # the walker of the even site 0
+        m0 = L.m.copy()
+        step = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)][d]
+        for t in range(Ld):
+            L.wander(d, t & 1)
+            pos = int(np.nonzero(L.m[0, 0] == 255)[0][0])
+            x, y, z = pos % 8, (pos // 8) % 6, pos // 48
+            assert (x, y, z) == ((step[0] * (t + 1)) % 8, (step[1] * (t + 1)) % 6, (step[2] * (t + 1)) % 4)
+        assert np.array_equal(L.m, m0)
+
+
+def test_walkers_conserve_energy_and_match_manual_steps():
+    sched = O.Schedule(O.SCHED_CONST, 1.1, 1.1, 60, 9)
+    A = O.Lattice(8, 6, 4, 1, 2, seed=12)
+    E_log, D_log = A.run(O.ALGO_WALKERS, sched, 60, 1)
+    B = O.Lattice(8, 6, 4, 1, 2, seed=12)
+    for k in range(60):
+        if sched.is_refresh(k):
+            B.refresh(sched.refresh_index(k), 1.1)
+        tot = B.energy() + B.daemon_energy()
+        B.micsa_half(0)
+        B.micsa_half(1)
+        B.wander(0, k & 1)
+        if not sched.is_refresh(k):
+            assert (B.energy() + B.daemon_energy() == tot).all()
+    assert np.array_equal(A.sigma, B.sigma) and np.array_equal(A.m, B.m)
+    assert (A.tally == A.energy()).all()
+    # walkers and daemons differ once wandering has moved daemons around
+    C = O.Lattice(8, 6, 4, 1, 2, seed=12)
+    C.run(O.ALGO_MICSA, sched, 60, 0)
+    assert not np.array_equal(C.sigma, A.sigma)
+
+
+@pytest.mark.parametrize("T,period", [(1.5, 1), (2.0, 4)])
+def test_walkers_reach_canonical_equilibrium(T, period):
+    """Wandering permutes i.i.d. canonical daemons, so the canonical measure stays
+    stationary: long walker runs reproduce the exact <H> of a 2x2x4 sample."""
+    R = 32
+    L = O.Lattice(2, 2, 4, 1, R, seed=400 + period)
+    g = O.density_of_states(2, 2, 4, L.J[0])
+    exact = O.canonical_mean_energy(g, L.N, T)
+    n = 6000
+    E_log, _ = L.run(O.ALGO_WALKERS, O.Schedule(O.SCHED_CONST, T, T, n, period), n, 1)
+    mean, err = _batch_mean(E_log[n // 5:].mean(axis=1))
+    assert abs(mean - exact) <= 4.5 * err + 1e-9, (mean, exact, err)

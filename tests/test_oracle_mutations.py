@@ -37,6 +37,9 @@ MUTATIONS = [
     ("overlap product", "q += spin(sa[i]) * spin(sb[i]);", "q += spin(sa[i]) * spin(sa[i]);", "overlap"),
     ("linear schedule end", "return T0 * (1.0 - f) + T1 * f;", "return T0 * (1.0 - f) + T1;", "schedule"),
     ("log refresh points", "return ((k + 1) & k) == 0;", "return (k & (k - 1)) == 0;", "schedule"),
+    ("walker cycle parity", "oracle_wander(Lx, Ly, Lz, S, R, 0, (int)(k & 1), m);",
+     "oracle_wander(Lx, Ly, Lz, S, R, 0, (int)((k + 1) & 1), m);", "walkers"),
+    ("walker step direction", "{{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}", "{{-1, 0, 0}, {1, 0, 0}, {0, 1, 0}", "walkers"),
 ]
 
 
