@@ -54,8 +54,11 @@ enum micsa_layout {
 };
 
 enum micsa_algo {
-    MICSA_ALGO_MICSA = 0,   /* daemon update, Sec. 2.3-2.8 with gamma = 1 */
-    MICSA_ALGO_HEATBATH = 1 /* canonical heat bath, Sec. 2.1 */
+    MICSA_ALGO_MICSA = 0,    /* daemon update, Sec. 2.3-2.8 with gamma = 1 */
+    MICSA_ALGO_HEATBATH = 1, /* canonical heat bath, Sec. 2.1 */
+    MICSA_ALGO_WALKERS = 2   /* gamma = 1 walker per site with forward-X wandering (Sec. 2.6, 2.8):
+                                each sweep t is followed by the exchange of the walkers of the
+                                sites of parity t mod 2 with their +x neighbours (byte layout) */
 };
 
 enum micsa_sched_kind {
@@ -173,8 +176,20 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      lattice in LDS for many sweeps per launch; byte layout, N <= 102400).
    MICSA_OPT_TILE_Y / MICSA_OPT_TILE_Z: rows / planes per work-group of the
      fused sweep (0 = automatic; must divide Ly / Lz).
+   MICSA_OPT_XCD_MAP: 1 (default) assigns neighbouring tiles of the fused
+     sweep to the same XCD (shared L2 for halo reads); 0 = plain order.
+   MICSA_OPT_GRAPHS: 1 (default) replays the per-half paths (bit-plane
+     layout; byte lattices using neither the resident nor the fused sweep)
+     as captured HIP graphs of 16 sweeps; 0 = launch every kernel.
+     Per-launch timing (micsa_set_timing) always launches every kernel.
    Errors: EINVAL for an unknown option or a value the lattice cannot use. */
-enum micsa_option { MICSA_OPT_SWEEP_KERNEL = 1, MICSA_OPT_TILE_Y = 2, MICSA_OPT_TILE_Z = 3 };
+enum micsa_option {
+    MICSA_OPT_SWEEP_KERNEL = 1,
+    MICSA_OPT_TILE_Y = 2,
+    MICSA_OPT_TILE_Z = 3,
+    MICSA_OPT_XCD_MAP = 4,
+    MICSA_OPT_GRAPHS = 5
+};
 enum micsa_kernel_choice {
     MICSA_KERNEL_AUTO = 0,    /* resident if the lattice fits, else fused if Lx >= 128, else simple */
     MICSA_KERNEL_SIMPLE = 1,  /* one launch per half sweep */

@@ -167,6 +167,34 @@ __global__ void __launch_bounds__(256) kb_refresh(GeomB b, uint64_t* __restrict_
             dm0 + (int64_t)wl * 2 * g.Nh, dm1 + (int64_t)wl * 2 * g.Nh, live);
 }
 
+// kb_refresh with the sweep index in device memory (replayable graphs).
+__global__ void __launch_bounds__(256) kb_refresh_dev(GeomB b, uint64_t* __restrict__ dm0, uint64_t* __restrict__ dm1,
+                                                      const int64_t* __restrict__ dk, int32_t period,
+                                                      const DaemonThresholds* __restrict__ dth)
+{
+    const int64_t k = *dk;
+    if (!(period >= 1 ? (k % period == 0) : (((k + 1) & k) == 0))) return;
+    const int64_t rho = period >= 1 ? k / period : 63 - __clzll((unsigned long long)(k + 1));
+    const DaemonThresholds th = dth[rho];
+    const Geom& g = b.g;
+    const int wl = blockIdx.y;
+    const int G = wl / g.R, r = wl % g.R;
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const bool live = t < g.Nh / 2;
+    const uint32_t s = (uint32_t)(64 * G + lane_id());
+    u32x4 o = {0, 0, 0, 0};
+    if (live && s < (uint32_t)g.S)
+        o = philox10((uint32_t)t, (uint32_t)rho, (uint32_t)r, stream_word(kStreamDaemon, s), g.key0, g.key1);
+    ballot4(g, live ? 4 * t : 0, o,
+            [&](uint32_t u, uint32_t& b0, uint32_t& b1) {
+                const uint64_t v = u;
+                const uint32_t m = (uint32_t)(v >= th.t0) + (uint32_t)(v >= th.t1) + (uint32_t)(v >= th.t2);
+                b0 = m & 1u;
+                b1 = m >> 1;
+            },
+            dm0 + (int64_t)wl * 2 * g.Nh, dm1 + (int64_t)wl * 2 * g.Nh, live);
+}
+
 // ------------------------------------------------------------- half sweep
 // Thread per site word (64 lanes) of parity P.
 template <int P>

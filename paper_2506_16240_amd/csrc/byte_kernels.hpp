@@ -154,6 +154,52 @@ __global__ void k_refresh(Geom g, uint8_t* __restrict__ dem, uint32_t rho, Daemo
     reinterpret_cast<uint32_t*>(dem + ((int64_t)l * 2 + 1) * g.Nh)[t] = wo;
 }
 
+__device__ __forceinline__ bool sweep_is_refresh(int64_t k, int32_t P)
+{
+    return P >= 1 ? (k % P == 0) : (((k + 1) & k) == 0);
+}
+
+__device__ __forceinline__ int64_t sweep_refresh_index(int64_t k, int32_t P)
+{
+    if (P >= 1) return k / P;
+    return 63 - __clzll((unsigned long long)(k + 1));  // floor(log2(k + 1))
+}
+
+// Refresh whose sweep index comes from device memory (*dk), for replayable
+// graphs: does nothing unless sweep *dk is a refresh point; thresholds from
+// the schedule's table.
+__global__ void k_refresh_dev(Geom g, uint8_t* __restrict__ dem, const int64_t* __restrict__ dk, int32_t period,
+                              const DaemonThresholds* __restrict__ dth)
+{
+    const int64_t k = *dk;
+    if (!sweep_is_refresh(k, period)) return;
+    const int64_t rho = sweep_refresh_index(k, period);
+    const DaemonThresholds th = dth[rho];
+    const int l = blockIdx.y;
+    const int s = l / g.R, r = l % g.R;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= g.Nh / 4) return;
+    const int64_t i0 = 8 * t;
+    const uint32_t sw = stream_word(kStreamDaemon, (uint32_t)s);
+    const u32x4 a = philox10((uint32_t)(i0 >> 2), (uint32_t)rho, (uint32_t)r, sw, g.key0, g.key1);
+    const u32x4 b = philox10((uint32_t)(i0 >> 2) + 1u, (uint32_t)rho, (uint32_t)r, sw, g.key0, g.key1);
+    uint32_t we, wo;
+    split8(g, i0, a, b,
+           [&](uint32_t u) {
+               const uint64_t v = u;
+               return (uint32_t)(v >= th.t0) + (uint32_t)(v >= th.t1) + (uint32_t)(v >= th.t2);
+           },
+           we, wo);
+    reinterpret_cast<uint32_t*>(dem + ((int64_t)l * 2 + 0) * g.Nh)[t] = we;
+    reinterpret_cast<uint32_t*>(dem + ((int64_t)l * 2 + 1) * g.Nh)[t] = wo;
+}
+
+// Advance the device sweep counter (one thread; launched after a sweep's
+// last kernel in replayable graphs).
+__global__ void k_count_sweep(int64_t* dk) { *dk += 1; }
+
+__global__ void k_set_counter(int64_t* dk, int64_t k) { *dk = k; }
+
 // --------------------------------------------------------- MicSA half sweep
 // Creutz move with a 2-bit daemon (eqs. Creutz and flip-OK).  With u the
 // number of unsatisfied bonds of the site (sigma ^ sigma_nb ^ j = 1),
@@ -202,14 +248,25 @@ __global__ void __launch_bounds__(256) k_micsa_half(Geom g, uint8_t* __restrict_
 // New spin +1 iff u < tau[v], v = #neighbours with J s_nb = -1 (h = 6 - 2v);
 // u = Philox(h>>2, 2k+p, r, stream HB | s)[h & 3] for parity-split index h.
 
+// With dk != nullptr the sweep index k = *dk and the thresholds of refresh
+// rho(k) come from device memory (replayable graphs); otherwise from the
+// arguments.
 template <int P>
 __global__ void __launch_bounds__(256) k_heatbath_half(Geom g, uint8_t* __restrict__ spin,
                                                        const uint32_t* __restrict__ J, uint32_t time,
                                                        HeatBathThresholds th,
-                                                       unsigned long long* __restrict__ tally)
+                                                       unsigned long long* __restrict__ tally,
+                                                       const int64_t* __restrict__ dk, int32_t period,
+                                                       const HeatBathThresholds* __restrict__ hth)
 {
     __shared__ uint64_t tau[8];
-    if (threadIdx.x < 7) tau[threadIdx.x] = th.tau[threadIdx.x];
+    if (dk) {
+        const int64_t k = *dk;
+        time = (uint32_t)(2 * k + P);
+        if (threadIdx.x < 7) tau[threadIdx.x] = hth[sweep_refresh_index(k, period)].tau[threadIdx.x];
+    } else if (threadIdx.x < 7) {
+        tau[threadIdx.x] = th.tau[threadIdx.x];
+    }
     __syncthreads();
     const int l = blockIdx.y;
     const int s = l / g.R, r = l % g.R;
@@ -239,6 +296,53 @@ __global__ void __launch_bounds__(256) k_heatbath_half(Geom g, uint8_t* __restri
         own[w] = Snew;
     }
     block_add(tally + (int64_t)l * kSlots, dE);
+}
+
+// ------------------------------------------------------------- wandering
+// Walkers (Sec. 2.6): the wandering step along direction dir (+x, -x, +y,
+// -y, +z, -z) exchanges the level of every site s of parity p with that of
+// s + e_dir.  Written as two gathers into the other buffer: a site of parity
+// p takes the level at s + e_dir, a site of parity 1-p the level at t - e_dir
+// (both sites of the other parity).  Thread per word position (row, c) of
+// both parity arrays.
+__global__ void __launch_bounds__(256) k_wander(Geom g, const uint8_t* __restrict__ dem_in,
+                                                uint8_t* __restrict__ dem_out, int dir, int p)
+{
+    const int l = blockIdx.y;
+    const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= (uint32_t)g.rows * (uint32_t)g.Wr) return;
+    const int row = (int)(w / (uint32_t)g.Wr), c = (int)(w - (uint32_t)row * (uint32_t)g.Wr);
+    const int z = row / g.Ly, y = row - z * g.Ly;
+    const int sgn = (dir & 1) ? -1 : 1;  // even dir index: forward
+    const int axis = dir >> 1;
+    const int qp = (p + y + z) & 1;      // sites of parity p sit at x = 2k + qp
+    const int64_t wr = g.Wr;
+    for (int a = 0; a < 2; ++a) {  // destination parity array: a == 0 -> parity p
+        const int par = a == 0 ? p : 1 - p;
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(dem_in + ((int64_t)l * 2 + (1 - par)) * g.Nh);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(dem_out + ((int64_t)l * 2 + par) * g.Nh);
+        const int toward = a == 0 ? sgn : -sgn;  // partner offset along the axis
+        uint32_t v;
+        if (axis == 0) {
+            // x +- 1 of a site at x = 2k + q of this parity is at index k + shift in the other array
+            const int q = a == 0 ? qp : 1 - qp;
+            const int shift = toward > 0 ? q : q - 1;  // 0 or +1, or -1 or 0
+            const uint32_t A = src[row * wr + c];
+            if (shift == 0) {
+                v = A;
+            } else {
+                const int cs = shift > 0 ? (c + 1 == g.Wr ? 0 : c + 1) : (c == 0 ? g.Wr - 1 : c - 1);
+                v = shift_word(A, src[row * wr + cs], shift);
+            }
+        } else if (axis == 1) {
+            const int yy = toward > 0 ? (y + 1 == g.Ly ? 0 : y + 1) : (y == 0 ? g.Ly - 1 : y - 1);
+            v = src[(int64_t)(yy + g.Ly * z) * wr + c];
+        } else {
+            const int zz = toward > 0 ? (z + 1 == g.Lz ? 0 : z + 1) : (z == 0 ? g.Lz - 1 : z - 1);
+            v = src[(int64_t)(y + g.Ly * zz) * wr + c];
+        }
+        dst[w] = v;
+    }
 }
 
 // -------------------------------------------------------------- reductions

@@ -33,7 +33,35 @@ struct FusedTile {
     int32_t TY, TZ;  // tile rows (divides Ly) and planes (divides Lz)
     int32_t NC;      // 16-site chunks per row = Lx / 32
     int32_t nty;     // tiles along y = Ly / TY
+    int32_t ntz;     // tiles along z = Lz / TZ
+    int32_t xcd;     // 1: map blocks to tiles XCD by XCD (tiles per lattice divisible by 8)
 };
+
+// Tile of block b.  Work-groups are dispatched round-robin over the 8 XCDs
+// (block b on XCD b % 8), each XCD with its own L2.  Tiles are numbered
+// z-fastest and, with xcd set, XCD x receives the contiguous tile range
+// [x T/8, (x+1) T/8): a band of whole y-tiles, so most y- and z-neighbour
+// tiles, which read each other's halo rows and planes, share an L2.
+__device__ __forceinline__ void tile_of(const FusedTile& f, int b, int& ty, int& tz)
+{
+    int t = b;
+    if (f.xcd) {
+        const int per = f.nty * f.ntz / 8;
+        t = (b & 7) * per + (b >> 3);
+    }
+    tz = t % f.ntz;
+    ty = t / f.ntz;
+}
+
+using v4u = unsigned int __attribute__((ext_vector_type(4)));
+
+// Streaming 16-byte store that does not allocate in L2 (the written state is
+// not read again in this sweep), leaving L2 to the halo reads.
+__device__ __forceinline__ void stg16_nt(uint8_t* __restrict__ p, const uint32_t w[4])
+{
+    v4u v = {w[0], w[1], w[2], w[3]};
+    __builtin_nontemporal_store(v, reinterpret_cast<v4u*>(p));
+}
 
 struct V4 {
     uint32_t w[4];
@@ -146,8 +174,14 @@ __global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
 
     const int l = blockIdx.y;
     const int s = l / g.R, r = l % g.R;
-    const int ty = blockIdx.x % f.nty, tz = blockIdx.x / f.nty;
+    int ty, tz;
+    tile_of(f, blockIdx.x, ty, tz);
     const int y0 = ty * f.TY, z0 = tz * f.TZ;
+    // Odd z-tiles march downwards: the tiles on both sides of a z boundary
+    // then reach its halo planes at the same time (both first or both last),
+    // so the second read of those planes is an L2 hit.
+    const int dz = (tz & 1) ? -1 : 1;
+    const int zstart = dz > 0 ? z0 - 1 : z0 + f.TZ;
     const int ry = threadIdx.x / f.NC, c = threadIdx.x - ry * f.NC;
     const bool active = ry < rows_slots;
     int y = y0 - 2 + ry;
@@ -171,32 +205,32 @@ __global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
     const int cn = c + 1 == f.NC ? 0 : c + 1, cp = c == 0 ? f.NC - 1 : c - 1;
     const int steps = f.TZ + 2;
 
-    // Step st works on plane z = z0 - 1 + st (even half) and z - 1 (odd half).
-    // Global loads are issued one step ahead (the "n" registers).
-    V4 So_prev{}, So_cur{}, So_next{};  // odd spins (old) at planes z-1, z, z+1
-    V4 X_prev2{}, X_prev{}, X_cur{};    // even views at planes z-2, z-1, z
-    V4 Mo_gen{};                        // refreshed odd levels of plane z-1
+    // Step st works on plane z = zstart + dz st (even half) and z - dz (odd
+    // half).  Global loads are issued one step ahead (the "n" registers).
+    V4 So_prev{}, So_cur{}, So_next{};  // odd spins (old) at planes z-dz, z, z+dz
+    V4 X_prev2{}, X_prev{}, X_cur{};    // even views at planes z-2dz, z-dz, z
+    V4 Mo_gen{};                        // refreshed odd levels of plane z-dz
     V4 nSo{}, nSe{}, nJw{}, nMe{}, nMo{};
-    auto load_step = [&](int st2) {  // inputs of step st2 (plane z2 = z0 - 1 + st2)
-        const int z2 = wrapz(z0 - 1 + st2);
-        if (active) nSo = ldg16(od_in + hof(wrapz(z2 + 1)));
+    auto load_step = [&](int st2) {  // inputs of step st2 (plane z2 = zstart + dz st2)
+        const int z2 = wrapz(zstart + dz * st2);
+        if (active) nSo = ldg16(od_in + hof(wrapz(z2 + dz)));
         if (do_even) {
             const int64_t h2 = hof(z2);
             nSe = ldg16(ev_in + h2);
             nJw = ldg16(Jb + h2);
             if (!REFRESH) nMe = ldg16(me_in + h2);
         }
-        if (!REFRESH && do_odd && st2 >= 2) nMo = ldg16(mo_in + hof(wrapz(z2 - 1)));
+        if (!REFRESH && do_odd && st2 >= 2) nMo = ldg16(mo_in + hof(wrapz(z2 - dz)));
     };
     if (active) {
-        So_prev = ldg16(od_in + hof(wrapz(z0 - 2)));
-        So_cur = ldg16(od_in + hof(wrapz(z0 - 1)));
+        So_prev = ldg16(od_in + hof(wrapz(zstart - dz)));
+        So_cur = ldg16(od_in + hof(wrapz(zstart)));
     }
     load_step(0);
     uint32_t sum_old = 0, sum_new = 0;  // daemon level sums before/after owned moves
     for (int st = 0; st < steps; ++st) {
         const int buf = st & 1;
-        const int z = wrapz(z0 - 1 + st);
+        const int z = wrapz(zstart + dz * st);
         const int64_t h = hof(z);
         So_next = nSo;
         V4 Se = nSe, Jw = nJw, Me = nMe, Mo = nMo;
@@ -204,9 +238,14 @@ __global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
         if (st + 1 < steps) load_step(st + 1);
         if (REFRESH && do_even) refresh_chunk(g, y + g.Ly * z, c, (y + z) & 1, rho, (uint32_t)r, sw, th, Me, Mo_next);
         const bool odd_now = do_odd && st >= 2;
-        const int zo = wrapz(z - 1);
+        const int zo = wrapz(z - dz);
         if (active) sts16(&So[buf * plane_slots + ry * f.NC + c], So_cur);
         __syncthreads();
+        // odd spins on planes z + 1 and z - 1 (old), even views on zo + 1 and zo - 1 (new)
+        const V4& Sz_up = dz > 0 ? So_next : So_prev;
+        const V4& Sz_dn = dz > 0 ? So_prev : So_next;
+        const V4& Xz_up = dz > 0 ? X_cur : X_prev2;
+        const V4& Xz_dn = dz > 0 ? X_prev2 : X_cur;
 
         if (do_even) {
             // ---- even half on plane z
@@ -231,7 +270,7 @@ __global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
                 const uint32_t m1 = 0x01010101u;
                 const uint32_t u = xor_and(A.w[i], v >> dA, m1) + xor_and(B.w[i], v >> dB, m1) +
                                    xor_and(Yp.w[i], v >> kPy, m1) + xor_and(Ym.w[i], v >> kMy, m1) +
-                                   xor_and(So_next.w[i], v >> kPz, m1) + xor_and(So_prev.w[i], v >> kMz, m1);
+                                   xor_and(Sz_up.w[i], v >> kPz, m1) + xor_and(Sz_dn.w[i], v >> kMz, m1);
                 const uint32_t S0 = S;
                 creutz4(S, Me.w[i], u, so, sn);
                 Se.w[i] = S;
@@ -241,14 +280,14 @@ __global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
             X_cur = Xn;
             sts16(&Xs[buf * plane_slots + ry * f.NC + c], Xn);
             if (owned) {  // ring rows and halo planes are recomputed, not owned
-                stg16(ev_out + h, Se);
-                stg16(me_out + h, Me);
+                stg16_nt(ev_out + h, Se.w);
+                stg16_nt(me_out + h, Me.w);
                 sum_old += so;
                 sum_new += sn;
             }
         }
         if (odd_now) {
-            // ---- odd half on plane z-1 (its even neighbours are all final)
+            // ---- odd half on plane zo = z - dz (its even neighbours are all final)
             const int q = (y + zo) & 1;
             const int dir = q ? -1 : 1;
             const int pb = buf ^ 1;
@@ -267,13 +306,13 @@ __global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
                 const uint32_t m1 = 0x01010101u;
                 const uint32_t u = xor_and(S, A.w[i] >> dA, m1) + xor_and(S, B.w[i] >> dB, m1) +
                                    xor_and(S, Yp.w[i] >> kMy, m1) + xor_and(S, Ym.w[i] >> kPy, m1) +
-                                   xor_and(S, X_cur.w[i] >> kMz, m1) + xor_and(S, X_prev2.w[i] >> kPz, m1);
+                                   xor_and(S, Xz_up.w[i] >> kMz, m1) + xor_and(S, Xz_dn.w[i] >> kPz, m1);
                 creutz4(S, Mo.w[i], u, sum_old, sum_new);
                 So_new.w[i] = S;
             }
             const int64_t ho = hof(zo);
-            stg16(od_out + ho, So_new);
-            stg16(mo_out + ho, Mo);
+            stg16_nt(od_out + ho, So_new.w);
+            stg16_nt(mo_out + ho, Mo.w);
         }
         So_prev = So_cur;
         So_cur = So_next;
@@ -320,7 +359,8 @@ __global__ void __launch_bounds__(1024) k_heatbath_sweep_fused(
 
     const int l = blockIdx.y;
     const int s = l / g.R, r = l % g.R;
-    const int ty = blockIdx.x % f.nty, tz = blockIdx.x / f.nty;
+    int ty, tz;
+    tile_of(f, blockIdx.x, ty, tz);
     const int y0 = ty * f.TY, z0 = tz * f.TZ;
     const int ry = threadIdx.x / f.NC, c = threadIdx.x - ry * f.NC;
     const bool active = ry < rows_slots;

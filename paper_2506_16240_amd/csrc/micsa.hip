@@ -59,6 +59,13 @@ struct micsa_ctx {
     // sweep kernel selection (MICSA_OPT_*)
     int32_t kernel_opt = MICSA_KERNEL_AUTO;
     int32_t tile_y = 0, tile_z = 0;
+    int32_t xcd_map = 1;  // XCD-aware tile order for the fused sweeps
+    int32_t use_graphs = 1;
+    // replayable graphs of kGraphSweeps sweeps for the per-half paths, per algo
+    int64_t* d_k = nullptr;  // device copy of the sweep counter
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    const void* gkey[2] = {nullptr, nullptr};  // state buffer the graph was captured with
     uint32_t* J = nullptr;    // [S][Nh] coupling bytes of the even sites
     unsigned long long* tally = nullptr;  // [L][kSlots]
     unsigned long long* red = nullptr;    // [max(L, S)][kSlots] reduction scratch
@@ -304,6 +311,7 @@ FusedTile choose_tile(const micsa_ctx* c)
     const int ty_cap = std::max(1, std::min(32, 1024 / f.NC - 4));
     f.TY = c->tile_y > 0 ? c->tile_y : divisor_at_most(c->p.Ly, ty_cap);
     f.nty = c->p.Ly / f.TY;
+    f.xcd = c->xcd_map;
     if (c->tile_z > 0) {
         f.TZ = c->tile_z;
     } else {
@@ -314,6 +322,8 @@ FusedTile choose_tile(const micsa_ctx* c)
             f.TZ = next;
         }
     }
+    f.ntz = c->p.Lz / f.TZ;
+    if ((f.nty * f.ntz) % 8 != 0) f.xcd = 0;
     return f;
 }
 
@@ -383,14 +393,16 @@ int launch_heatbath_sweep(micsa_ctx* c, int64_t k, double T)
     {
         TimedLaunch t(c, kTimeHeatBath);
         k_heatbath_half<0><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->J,
-                                                                             (uint32_t)(2 * k), th, c->tally);
+                                                                             (uint32_t)(2 * k), th, c->tally,
+                                                                             nullptr, 0, nullptr);
     }
     int st = check_launch(c, "k_heatbath_half<0>");
     if (st) return st;
     {
         TimedLaunch t(c, kTimeHeatBath);
         k_heatbath_half<1><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->J,
-                                                                             (uint32_t)(2 * k + 1), th, c->tally);
+                                                                             (uint32_t)(2 * k + 1), th, c->tally,
+                                                                             nullptr, 0, nullptr);
     }
     return check_launch(c, "k_heatbath_half<1>");
 }
@@ -475,10 +487,93 @@ int launch_resident(micsa_ctx* c, int32_t algo, int64_t n, long long* dlog, int6
     return MICSA_OK;
 }
 
+// ------------------------------------------------------- replayable graphs
+// The per-half paths (byte layout without the resident/fused kernels, and
+// the bit-plane layout) launch 3 kernels per sweep, so small and mid-size
+// lattices are bound by launch overhead.  Their sweeps are captured once per
+// context as a graph of kGraphSweeps sweeps whose kernels take the sweep
+// index from a device counter (refresh kernels that skip non-refresh
+// sweeps, thresholds from the schedule tables) and replayed.
+constexpr int kGraphSweeps = 16;
+
+bool use_graph(const micsa_ctx* c)
+{
+    return c->use_graphs && !c->timing && (c->bit || (!use_resident(c) && !use_fused(c)));
+}
+
+// One sweep in device-counter form on stream st.
+int enqueue_dev_sweep(micsa_ctx* c, int32_t algo, hipStream_t st)
+{
+    const int32_t P = c->sched.period;
+    if (c->bit) {
+        const int WL = c->G * c->p.n_replicas;
+        kb_refresh_dev<<<dim3((unsigned)((c->g.Nh / 2 + 3) / 4), (unsigned)WL), 256, 0, st>>>(
+            geomb(c), c->bdm0, c->bdm1, c->d_k, P, c->d_dth);
+        const dim3 grid = grid_for(c->g.Nh, WL);
+        kb_micsa_half<0><<<grid, kBlock, 0, st>>>(geomb(c), c->bspin, c->bdm0, c->bdm1, c->bJ);
+        kb_micsa_half<1><<<grid, kBlock, 0, st>>>(geomb(c), c->bspin, c->bdm0, c->bdm1, c->bJ);
+    } else {
+        const int64_t words = (int64_t)c->g.rows * c->g.Wr;
+        if (algo == MICSA_ALGO_MICSA) {
+            k_refresh_dev<<<grid_for(c->g.Nh / 4, c->L), kBlock, 0, st>>>(c->g, c->dem, c->d_k, P, c->d_dth);
+            k_micsa_half<0><<<grid_for(words, c->L), kBlock, 0, st>>>(c->g, c->spin, c->dem, c->J, c->tally);
+            k_micsa_half<1><<<grid_for(words, c->L), kBlock, 0, st>>>(c->g, c->spin, c->dem, c->J, c->tally);
+        } else {
+            const HeatBathThresholds none{};
+            k_heatbath_half<0><<<grid_for(words, c->L), kBlock, 0, st>>>(c->g, c->spin, c->J, 0u, none, c->tally,
+                                                                          c->d_k, P, c->d_hth);
+            k_heatbath_half<1><<<grid_for(words, c->L), kBlock, 0, st>>>(c->g, c->spin, c->J, 0u, none, c->tally,
+                                                                          c->d_k, P, c->d_hth);
+        }
+    }
+    k_count_sweep<<<1, 1, 0, st>>>(c->d_k);
+    return check_launch(c, "device-counter sweep");
+}
+
+int sweep_graph(micsa_ctx* c, int32_t algo, int64_t n)
+{
+    const void* key = c->bit ? (const void*)c->bspin : (const void*)c->spin;
+    hipGraphExec_t& ex = c->gexec[algo];
+    if (ex && c->gkey[algo] != key) {  // state buffers moved since the capture
+        (void)hipGraphExecDestroy(ex);
+        ex = nullptr;
+    }
+    if (!c->d_k) HIP_TRY(c, hipMalloc(&c->d_k, 8));
+    if (!ex && n >= kGraphSweeps) {
+        if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        int st = MICSA_OK;
+        for (int i = 0; i < kGraphSweeps && !st; ++i) st = enqueue_dev_sweep(c, algo, c->cap_stream);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+        if (st) return st;
+        if (e != hipSuccess) return fail(c, MICSA_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        const hipError_t e2 = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e2 != hipSuccess) {
+            ex = nullptr;
+            return fail(c, MICSA_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e2));
+        }
+        c->gkey[algo] = key;
+    }
+    k_set_counter<<<1, 1, 0, c->stream>>>(c->d_k, c->k);
+    int64_t done = 0;
+    if (ex)
+        for (; done + kGraphSweeps <= n; done += kGraphSweeps) HIP_TRY(c, hipGraphLaunch(ex, c->stream));
+    for (; done < n; ++done) {
+        const int st = enqueue_dev_sweep(c, algo, c->stream);
+        if (st) return st;
+    }
+    c->k += n;
+    return MICSA_OK;
+}
+
 // Checks shared by every sweep entry point.
 int check_sweep(micsa_ctx* c, int32_t algo, int64_t n)
 {
-    if (algo != MICSA_ALGO_MICSA && algo != MICSA_ALGO_HEATBATH) return fail(c, MICSA_EINVAL, "unknown algo");
+    if (algo != MICSA_ALGO_MICSA && algo != MICSA_ALGO_HEATBATH && algo != MICSA_ALGO_WALKERS)
+        return fail(c, MICSA_EINVAL, "unknown algo");
+    if (c->bit && algo == MICSA_ALGO_WALKERS) return fail(c, MICSA_EINVAL, "walkers run in the byte layout");
     if (c->bit && algo != MICSA_ALGO_MICSA)
         return fail(c, MICSA_EINVAL, "the heat-bath baseline runs in the byte layout");
     if (n < 0) return fail(c, MICSA_EINVAL, "negative sweep count");
@@ -487,19 +582,36 @@ int check_sweep(micsa_ctx* c, int32_t algo, int64_t n)
     return MICSA_OK;
 }
 
+// Wandering step of the walkers after sweep k: forward-X, parity of k.
+int launch_wander(micsa_ctx* c, int64_t k)
+{
+    const int64_t words = (int64_t)c->g.rows * c->g.Wr;
+    {
+        TimedLaunch t(c, kTimeSweep);
+        k_wander<<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->dem, c->dem_alt, kPx, (int)(k & 1));
+    }
+    const int st = check_launch(c, "k_wander");
+    if (st) return st;
+    std::swap(c->dem, c->dem_alt);
+    return MICSA_OK;
+}
+
 int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
 {
     if (!c) return MICSA_EINVAL;
     int st0 = check_sweep(c, algo, n);
     if (st0) return st0;
-    if (use_resident(c)) return launch_resident(c, algo, n, nullptr, 0);
+    if (algo != MICSA_ALGO_WALKERS) {
+        if (use_resident(c)) return launch_resident(c, algo, n, nullptr, 0);
+        if (use_graph(c) && n >= kGraphSweeps) return sweep_graph(c, algo, n);
+    }
     for (int64_t i = 0; i < n; ++i) {
         const int64_t k = c->k;
         const int64_t rho = refresh_index(k, c->sched.period);
         const double T = temperature(c->sched, rho);
         if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
         int st;
-        if (algo == MICSA_ALGO_MICSA) {
+        if (algo == MICSA_ALGO_MICSA || algo == MICSA_ALGO_WALKERS) {
             const bool refresh = is_refresh(k, c->sched.period);
             if (c->bit) {
                 if ((st = launch_bitplane_sweep(c, refresh, rho, T))) return st;
@@ -509,6 +621,7 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
                 if (refresh && (st = launch_refresh(c, rho, T))) return st;
                 if ((st = launch_micsa_sweep(c))) return st;
             }
+            if (algo == MICSA_ALGO_WALKERS && (st = launch_wander(c, k))) return st;
         } else {
             if ((st = launch_heatbath_sweep(c, k, T))) return st;
         }
@@ -530,6 +643,10 @@ void free_all(micsa_ctx* c)
     if (c->bJ) (void)hipFree(c->bJ);
     if (c->d_dth) (void)hipFree(c->d_dth);
     if (c->d_hth) (void)hipFree(c->d_hth);
+    for (auto& e : c->gexec)
+        if (e) (void)hipGraphExecDestroy(e);
+    if (c->d_k) (void)hipFree(c->d_k);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->J) (void)hipFree(c->J);
     if (c->tally) (void)hipFree(c->tally);
     if (c->red) (void)hipFree(c->red);
@@ -713,6 +830,11 @@ int micsa_set_schedule(micsa_ctx* ctx, const micsa_schedule* s)
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     if (ctx->d_dth) (void)hipFree(ctx->d_dth);
     if (ctx->d_hth) (void)hipFree(ctx->d_hth);
+    for (auto& e : ctx->gexec)  // captured graphs point at the old tables
+        if (e) {
+            (void)hipGraphExecDestroy(e);
+            e = nullptr;
+        }
     ctx->d_dth = d1;
     ctx->d_hth = d2;
     ctx->sched = std::move(n);
@@ -731,7 +853,7 @@ int micsa_sweep_logged(micsa_ctx* ctx, int32_t algo, int64_t n, int64_t stride, 
     const int L = ctx->L;
     int st0 = check_sweep(ctx, algo, n);
     if (st0) return st0;
-    if (use_resident(ctx)) {
+    if (use_resident(ctx) && algo != MICSA_ALGO_WALKERS) {
         long long* rlog = nullptr;
         if (rows > 0 && hipMalloc(&rlog, (size_t)rows * L * 2 * 8) != hipSuccess) {
             (void)hipGetLastError();
@@ -1069,6 +1191,7 @@ int micsa_get_timing(micsa_ctx* ctx, int32_t kind, double* total_ms, int64_t* la
 const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
 {
     if (ctx && ctx->bit) return algo == MICSA_ALGO_MICSA ? "kb_micsa_half" : "";
+    if (algo == MICSA_ALGO_WALKERS) return ctx && use_fused(ctx) ? "k_micsa_sweep_fused+k_wander" : "k_micsa_half+k_wander";
     if (ctx && use_resident(ctx)) return algo == MICSA_ALGO_HEATBATH ? "k_resident<1>" : "k_resident<0>";
     if (algo == MICSA_ALGO_HEATBATH) return ctx && use_fused(ctx) ? "k_heatbath_sweep_fused" : "k_heatbath_half";
     if (ctx && use_fused(ctx)) return "k_micsa_sweep_fused";
@@ -1093,6 +1216,14 @@ int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value)
         if (value < 0 || (value > 0 && (ctx->p.Ly % value != 0 || (value + 4) * (ctx->p.Lx / 32) > 1024)))
             return fail(ctx, MICSA_EINVAL, "tile_y must divide Ly and fit a work-group");
         ctx->tile_y = (int32_t)value;
+        return MICSA_OK;
+    case MICSA_OPT_GRAPHS:
+        if (value != 0 && value != 1) return fail(ctx, MICSA_EINVAL, "graphs is 0 or 1");
+        ctx->use_graphs = (int32_t)value;
+        return MICSA_OK;
+    case MICSA_OPT_XCD_MAP:
+        if (value != 0 && value != 1) return fail(ctx, MICSA_EINVAL, "xcd_map is 0 or 1");
+        ctx->xcd_map = (int32_t)value;
         return MICSA_OK;
     case MICSA_OPT_TILE_Z:
         if (value < 0 || (value > 0 && ctx->p.Lz % value != 0))

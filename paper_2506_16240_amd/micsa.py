@@ -17,11 +17,11 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmicsa.so
 
 OK, EINVAL, ENOMEM, EHIP, ESTATE, ERANGE = 0, -1, -2, -3, -4, -5
 LAYOUT_BYTE, LAYOUT_BITPLANE = 0, 1
-ALGO_MICSA, ALGO_HEATBATH = 0, 1
+ALGO_MICSA, ALGO_HEATBATH, ALGO_WALKERS = 0, 1, 2
 SCHED_CONST, SCHED_LINEAR, SCHED_TABLE = 0, 1, 2
 REFRESH_LOG2 = 0
 TIME_SWEEP, TIME_REFRESH, TIME_HEATBATH, TIME_REDUCE = 0, 1, 2, 3
-OPT_SWEEP_KERNEL, OPT_TILE_Y, OPT_TILE_Z = 1, 2, 3
+OPT_SWEEP_KERNEL, OPT_TILE_Y, OPT_TILE_Z, OPT_XCD_MAP, OPT_GRAPHS = 1, 2, 3, 4, 5
 KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_FUSED, KERNEL_RESIDENT = 0, 1, 2, 3
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_RELEASED = 0, 1, 2, 3
 

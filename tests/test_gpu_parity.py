@@ -250,6 +250,22 @@ def test_graph_replays_match_eager_launches(layout, algo):
     assert np.array_equal(res[0][0][-1], o.energy())
 
 
+@pytest.mark.parametrize("shape,kernel", [((16, 6, 10, 2, 2), M.KERNEL_AUTO), ((8, 2, 2, 1, 1), M.KERNEL_SIMPLE),
+                                          ((64, 8, 6, 1, 2), M.KERNEL_FUSED), ((96, 8, 4, 1, 1), M.KERNEL_SIMPLE)])
+def test_walkers_match_oracle(shape, kernel):
+    """One walker per site, forward-X wandering after every sweep (Sec. 2.6)."""
+    g, o = pair(*shape, seed=4321)
+    g.set_option(M.OPT_SWEEP_KERNEL, kernel)
+    n = 31
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.0, 0.5, n, 4)
+    g.set_schedule(gs)
+    Eg, Dg = g.sweep_logged(M.ALGO_WALKERS, n, 1)
+    Eo, Do = o.run(O.ALGO_WALKERS, os_, n, 1)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    same_state(g, o)
+    assert np.array_equal(g.energy_tally(), o.energy())
+
+
 def test_gpu_error_paths():
     g, _ = pair(8, 8, 8)
     with pytest.raises(M.MicsaError) as e:
