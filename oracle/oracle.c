@@ -24,6 +24,7 @@
  *   spins      ctr = (i>>2,   0,      r, 2<<24 | s)  sigma   = out[i&3] >> 31
  *   daemons    ctr = (i>>2,   rho,    r, 3<<24 | s)  u       = out[i&3]
  *   heat bath  ctr = (h>>2,   2k+p,   r, 4<<24 | s)  u       = out[h&3], h = i>>1
+ *   Metropolis ctr = (h>>2,   2k+p,   r, 5<<24 | s)  u       = out[h&3], h = i>>1
  * (rho = refresh index, k = sweep index, p = parity being updated).  The
  * paper leaves the generator unspecified; this map is the specification
  * both implementations follow.
@@ -76,7 +77,7 @@ static uint32_t draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint3
     return out[lane];
 }
 
-enum { STREAM_J = 1, STREAM_SPIN = 2, STREAM_DAEMON = 3, STREAM_HEATBATH = 4 };
+enum { STREAM_J = 1, STREAM_SPIN = 2, STREAM_DAEMON = 3, STREAM_HEATBATH = 4, STREAM_METROPOLIS = 5 };
 
 /* ------------------------------------------------------------------ */
 /* Lattice geometry                                                    */
@@ -290,6 +291,50 @@ void oracle_heatbath_half(int Lx, int Ly, int Lz, int S, int R, uint64_t seed, i
 }
 
 /* ------------------------------------------------------------------ */
+/* Metropolis, the canonical comparison of Sec. 4 (Table 3): the flip   */
+/* of s is proposed and accepted with probability min(1, exp(-beta dH)),*/
+/* dH = 2 s h.  As a 64-bit threshold theta(dH) = floor(2^32 e^{-beta  */
+/* dH}) for dH > 0 and 2^32 ("always") for dH <= 0; the flip happens   */
+/* iff u < theta.  Index q = (dH + 12) / 4 in 0..6.                    */
+/* ------------------------------------------------------------------ */
+void oracle_metropolis_thresholds(double T, uint64_t th[7])
+{
+    double beta = 1.0 / T;
+    for (int q = 0; q < 7; q++) {
+        int dH = 4 * q - 12;
+        th[q] = dH <= 0 ? 4294967296ull : (uint64_t)floor(exp(-beta * (double)dH) * 4294967296.0);
+    }
+}
+
+void oracle_metropolis_half(int Lx, int Ly, int Lz, int S, int R, uint64_t seed, int64_t k, int parity,
+                            double T, const uint8_t *J, uint8_t *sigma, int64_t *dE)
+{
+    geom g = mk(Lx, Ly, Lz);
+    uint64_t th[7];
+    oracle_metropolis_thresholds(T, th);
+    uint32_t time = (uint32_t)(2 * k + parity);
+    for (int s = 0; s < S; s++)
+        for (int r = 0; r < R; r++) {
+            const uint8_t *Js = J + (int64_t)s * g.N;
+            uint8_t *sig = sigma + ((int64_t)s * R + r) * g.N;
+            int64_t acc = 0;
+#pragma omp parallel for reduction(+ : acc) schedule(static)
+            for (int64_t i = 0; i < g.N; i++) {
+                if (parity_of(&g, i) != parity) continue;
+                int dH = 2 * spin(sig[i]) * local_field(&g, Js, sig, i);
+                int64_t hidx = i >> 1;
+                uint64_t u = draw(seed, (uint32_t)(hidx >> 2), time, (uint32_t)r,
+                                  (uint32_t)(STREAM_METROPOLIS << 24) | (uint32_t)s, (int)(hidx & 3));
+                if (u < th[(dH + 12) / 4]) {
+                    sig[i] ^= 1;
+                    acc += dH;
+                }
+            }
+            dE[(int64_t)s * R + r] += acc;
+        }
+}
+
+/* ------------------------------------------------------------------ */
 /* Walkers (Sec. 2.6): a wandering step along direction dir (0..5 = +x, */
 /* -x, +y, -y, +z, -z) exchanges the auxiliary variable of every site x */
 /* of the given parity with that of its neighbour x + e_dir.  Forward-X */
@@ -410,13 +455,14 @@ double oracle_temperature(int kind, double T0, double T1, int64_t n_sweeps, int 
 /* ------------------------------------------------------------------ */
 /* Driver: sweeps k0 .. k0+n-1 of one algorithm on the state in place. */
 /* A sweep is the even half followed by the odd half (Sec. 2.8).  For  */
-/* MicSA (daemons or, with ALGO_WALKERS, one forward-X walker per site) */
-/* the auxiliary variables are refreshed before sweep k when k is a refresh  */
-/* point; the heat bath uses the temperature of the last refresh point */
-/* at or before k.  After every `stride` sweeps the from-scratch H^EA  */
-/* and H^aux of every lattice are logged.  dE accumulates the tally.   */
+/* MicSA (daemons or, with ALGO_WALKERS, one forward-X walker per     */
+/* site) the auxiliary variables are refreshed before sweep k when k   */
+/* is a refresh point; the heat bath and Metropolis use the temperature*/
+/* of the last refresh point at or before k.  After every `stride`     */
+/* sweeps the from-scratch H^EA and H^aux of every lattice are logged. */
+/* dE accumulates the tally.                                           */
 /* ------------------------------------------------------------------ */
-enum { ALGO_MICSA = 0, ALGO_HEATBATH = 1, ALGO_WALKERS = 2 };
+enum { ALGO_MICSA = 0, ALGO_HEATBATH = 1, ALGO_WALKERS = 2, ALGO_METROPOLIS = 3 };
 
 int oracle_run(int Lx, int Ly, int Lz, int S, int R, uint64_t seed, int algo, int kind, double T0,
                double T1, int64_t n_sweeps, int P, const double *table, int64_t table_len, int64_t k0,
@@ -440,6 +486,9 @@ int oracle_run(int Lx, int Ly, int Lz, int S, int R, uint64_t seed, int algo, in
         } else if (algo == ALGO_HEATBATH) {
             oracle_heatbath_half(Lx, Ly, Lz, S, R, seed, k, 0, T, J, sigma, dE);
             oracle_heatbath_half(Lx, Ly, Lz, S, R, seed, k, 1, T, J, sigma, dE);
+        } else if (algo == ALGO_METROPOLIS) {
+            oracle_metropolis_half(Lx, Ly, Lz, S, R, seed, k, 0, T, J, sigma, dE);
+            oracle_metropolis_half(Lx, Ly, Lz, S, R, seed, k, 1, T, J, sigma, dE);
         } else {
             return -1;
         }

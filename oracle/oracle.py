@@ -25,7 +25,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MICSA_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 SRC_PATH = os.path.join(HERE, "oracle.c")
 
-ALGO_MICSA, ALGO_HEATBATH, ALGO_WALKERS = 0, 1, 2
+ALGO_MICSA, ALGO_HEATBATH, ALGO_WALKERS, ALGO_METROPOLIS = 0, 1, 2, 3
 SCHED_CONST, SCHED_LINEAR, SCHED_TABLE = 0, 1, 2
 REFRESH_LOG2 = 0
 
@@ -63,6 +63,7 @@ def lib():
         L.oracle_init_spins.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64, _u8p]
         L.oracle_daemon_thresholds.argtypes = [c.c_double, _u64p]
         L.oracle_heatbath_thresholds.argtypes = [c.c_double, _u64p]
+        L.oracle_metropolis_thresholds.argtypes = [c.c_double, _u64p]
         L.oracle_refresh.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
                                      c.c_int64, c.c_double, _u8p]
         L.oracle_micsa_half.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int,
@@ -71,6 +72,8 @@ def lib():
         L.oracle_micsa_site.restype = c.c_int
         L.oracle_heatbath_half.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
                                            c.c_int64, c.c_int, c.c_double, _u8p, _u8p, _i64p]
+        L.oracle_metropolis_half.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
+                                             c.c_int64, c.c_int, c.c_double, _u8p, _u8p, _i64p]
         L.oracle_wander.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, _u8p]
         L.oracle_energy.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, _u8p, _u8p, _i64p]
         L.oracle_daemon_energy.argtypes = [c.c_int64, c.c_int, _u8p, _i64p]
@@ -113,6 +116,14 @@ def daemon_thresholds(T: float) -> np.ndarray:
 def heatbath_thresholds(T: float) -> np.ndarray:
     t = np.zeros(7, np.uint64)
     lib().oracle_heatbath_thresholds(float(T), t)
+    return t
+
+
+def metropolis_thresholds(T: float) -> np.ndarray:
+    """theta[q], q = (dH + 12) / 4: a proposed flip with energy change dH is
+    accepted iff the 32-bit uniform is below theta[q]."""
+    t = np.zeros(7, np.uint64)
+    lib().oracle_metropolis_thresholds(float(T), t)
     return t
 
 
@@ -216,6 +227,12 @@ class Lattice:
         dE = np.zeros(self.S * self.R, np.int64)
         lib().oracle_heatbath_half(*self._dims(), self.seed, int(k), int(parity), float(T), self.J,
                                    self.sigma, dE)
+        self.tally += dE
+
+    def metropolis_half(self, k: int, parity: int, T: float) -> None:
+        dE = np.zeros(self.S * self.R, np.int64)
+        lib().oracle_metropolis_half(*self._dims(), self.seed, int(k), int(parity), float(T), self.J,
+                                     self.sigma, dE)
         self.tally += dE
 
     # -- observables ----------------------------------------------------

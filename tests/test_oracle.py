@@ -330,6 +330,75 @@ def test_heatbath_conditional_probability():
         assert abs(ups[v] / tot[v] - P) <= 5 * sd + 1e-9
 
 
+# ------------------------------------------------------------ Metropolis
+def _local_fields(L, r):
+    """h_i = sum_nb J s_nb of every site of lattice (0, r), from numpy rolls."""
+    s3 = (1 - 2 * L.sigma[0, r].astype(np.int64)).reshape(L.Lz, L.Ly, L.Lx)
+    Jb = [(1 - 2 * ((L.J[0] >> mu) & 1).astype(np.int64)).reshape(s3.shape) for mu in range(3)]
+    hf = (Jb[0] * np.roll(s3, -1, 2) + np.roll(Jb[0] * s3, 1, 2) + Jb[1] * np.roll(s3, -1, 1)
+          + np.roll(Jb[1] * s3, 1, 1) + Jb[2] * np.roll(s3, -1, 0) + np.roll(Jb[2] * s3, 1, 0))
+    return hf.ravel(), s3.ravel()
+
+
+def test_metropolis_acceptance_is_min_one_exp():
+    """A proposed flip with energy change dH is taken with probability
+    min(1, e^{-beta dH}); downhill and level moves always.  The expected
+    uphill rate is computed as the paper's limit: a freshly drawn daemon of
+    unlimited capacity, P(n >= dH) summed over the geometric law of eq.
+    prob-daemons-walkers without the cap (Sec. 2.3)."""
+    T = 1.7
+    beta = 1.0 / T
+    L = O.Lattice(16, 16, 16, 1, 2, seed=18)
+    flips = {d: 0 for d in range(-12, 13, 4)}
+    tries = dict(flips)
+    x, y, z = _coords(L)
+    for k in range(6):
+        for p in (0, 1):
+            par = ((x + y + z) & 1) == p
+            before = []
+            for r in range(L.R):
+                h, s = _local_fields(L, r)
+                before.append((2 * s * h)[par])
+            old = L.sigma[0].copy()
+            E0 = L.energy()
+            L.metropolis_half(k, p, T)
+            assert (L.sigma[0][:, ~par] == old[:, ~par]).all()
+            for r in range(L.R):
+                flipped = (L.sigma[0, r] != old[r])[par]
+                dH = before[r]
+                assert flipped[dH <= 0].all()
+                for d in flips:
+                    sel = dH == d
+                    tries[d] += int(sel.sum())
+                    flips[d] += int(flipped[sel].sum())
+                assert int(L.energy()[r] - E0[r]) == int(dH[flipped].sum())
+    assert (L.tally == L.energy()).all()
+    q = math.exp(-4 * beta)
+    for d in (4, 8, 12):
+        A = sum((1 - q) * q**m for m in range(d // 4, 400))  # P(4m >= d), m unbounded
+        if tries[d] < 100:
+            continue
+        sd = math.sqrt(A * (1 - A) / tries[d])
+        assert abs(flips[d] / tries[d] - A) <= 5 * sd, (d, flips[d] / tries[d], A)
+
+
+def test_metropolis_zero_temperature_is_the_greedy_quench():
+    """At T -> 0 only moves with dH <= 0 are taken, all of them: the
+    deterministic zero-temperature dynamics."""
+    L = O.Lattice(8, 6, 4, 1, 3, seed=4)
+    x, y, z = _coords(L)
+    for k in range(3):
+        for p in (0, 1):
+            par = ((x + y + z) & 1) == p
+            want = L.sigma[0].copy()
+            for r in range(L.R):
+                h, s = _local_fields(L, r)
+                go = par & (2 * s * h <= 0)
+                want[r][go] ^= 1
+            L.metropolis_half(k, p, 0.01)
+            assert np.array_equal(L.sigma[0], want)
+
+
 # ------------------------------------------------- exact enumeration pins
 def test_density_of_states_against_direct_enumeration():
     L = O.Lattice(2, 2, 4, 1, 1, seed=31)
@@ -369,9 +438,9 @@ def _batch_mean(series, nb=20):
 @pytest.mark.parametrize("shape,T,period", [((2, 2, 2), 1.5, 1), ((2, 2, 4), 1.5, 10), ((2, 2, 4), 3.0, 1),
                                             ((2, 2, 4), 2.0, 3)])
 def test_equilibrium_energy_matches_enumeration(shape, T, period):
-    """Canonical <H>_beta (eq. canonical) from exact enumeration vs long MicSA and
-    heat-bath runs; MicSA reaches canonical equilibrium through the refreshes
-    (Sec. 2.7)."""
+    """Canonical <H>_beta (eq. canonical) from exact enumeration vs long MicSA,
+    heat-bath and Metropolis runs; MicSA reaches canonical equilibrium
+    through the refreshes (Sec. 2.7)."""
     Lx, Ly, Lz = shape
     R = 32
     L = O.Lattice(Lx, Ly, Lz, 1, R, seed=100 + Lz + period)
@@ -379,7 +448,7 @@ def test_equilibrium_energy_matches_enumeration(shape, T, period):
     exact = O.canonical_mean_energy(g, L.N, T)
     n = 6000
     sched = O.Schedule(O.SCHED_CONST, T, T, n, period)
-    for algo in (O.ALGO_MICSA, O.ALGO_HEATBATH):
+    for algo in (O.ALGO_MICSA, O.ALGO_HEATBATH, O.ALGO_METROPOLIS):
         X = O.Lattice(Lx, Ly, Lz, 1, R, seed=100 + Lz + period)
         E_log, _ = X.run(algo, sched, n, 1)
         series = E_log[n // 5:].mean(axis=1)

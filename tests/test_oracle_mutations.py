@@ -39,6 +39,12 @@ MUTATIONS = [
     ("log refresh points", "return ((k + 1) & k) == 0;", "return (k & (k - 1)) == 0;", "schedule"),
     ("walker cycle parity", "oracle_wander(Lx, Ly, Lz, S, R, 0, (int)(k & 1), m);",
      "oracle_wander(Lx, Ly, Lz, S, R, 0, (int)((k + 1) & 1), m);", "walkers"),
+    ("Metropolis tally sign", "sig[i] ^= 1;\n                    acc += dH;", "sig[i] ^= 1;\n                    acc -= dH;",
+     "metropolis"),
+    ("Metropolis exponent", "floor(exp(-beta * (double)dH) * 4294967296.0)",
+     "floor(exp(-0.5 * beta * (double)dH) * 4294967296.0)", "metropolis"),
+    ("Metropolis threshold index", "if (u < th[(dH + 12) / 4]) {", "if (u < th[(12 - dH) / 4]) {",
+     "metropolis"),
     ("walker step direction", "{{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}", "{{-1, 0, 0}, {1, 0, 0}, {0, 1, 0}", "walkers"),
 ]
 
