@@ -56,9 +56,11 @@ enum micsa_layout {
 enum micsa_algo {
     MICSA_ALGO_MICSA = 0,    /* daemon update, Sec. 2.3-2.8 with gamma = 1 */
     MICSA_ALGO_HEATBATH = 1, /* canonical heat bath, Sec. 2.1 */
-    MICSA_ALGO_WALKERS = 2   /* gamma = 1 walker per site with forward-X wandering (Sec. 2.6, 2.8):
+    MICSA_ALGO_WALKERS = 2,  /* gamma = 1 walker per site with forward-X wandering (Sec. 2.6, 2.8):
                                 each sweep t is followed by the exchange of the walkers of the
                                 sites of parity t mod 2 with their +x neighbours (byte layout) */
+    MICSA_ALGO_METROPOLIS = 3 /* canonical Metropolis, the comparison of Sec. 4 (Table 3): the flip is
+                                 accepted with probability min(1, exp(-beta dH)) (byte layout) */
 };
 
 enum micsa_sched_kind {
@@ -152,6 +154,12 @@ int micsa_get_counters(micsa_ctx* ctx, int64_t* k, int64_t* rho); /* next sweep,
    without a schedule, ERANGE if rho is outside it. */
 int micsa_get_thresholds(micsa_ctx* ctx, int64_t rho, uint64_t t[3]);
 int micsa_get_heatbath_thresholds(micsa_ctx* ctx, int64_t rho, uint64_t tau[7]);
+/* Metropolis acceptance table of refresh rho: a flip with energy change
+   dH = 4q - 12 is taken iff the 32-bit uniform is below theta[q];
+   theta[q] = floor(2^32 e^{-beta dH}) for dH > 0 and 2^32 for dH <= 0.  The
+   uniform is Philox(h>>2, 2k+p, r, 5<<24 | s)[h & 3] for the parity-split
+   index h = i >> 1 of the site, as the heat bath's with stream tag 5. */
+int micsa_get_metropolis_thresholds(micsa_ctx* ctx, int64_t rho, uint64_t theta[7]);
 
 /* Writes (synchronous).  Spins reset the energy tally to the from-scratch
    energy.  Daemon levels above 3 are rejected with EINVAL. */
@@ -161,7 +169,8 @@ int micsa_write_demons(micsa_ctx* ctx, const uint8_t* m);    /* [S][R][N] */
 /* Per-kernel timing with HIP events on the context's stream.  While
    enabled every kernel launch is bracketed by an event pair; the sums are
    read (synchronously) by micsa_get_timing.  kind: 0 = sweep kernels,
-   1 = refresh, 2 = heat bath, 3 = reductions.  Disabled by default. */
+   1 = refresh, 2 = heat bath, 3 = reductions, 4 = Metropolis.  Disabled by
+   default. */
 int micsa_set_timing(micsa_ctx* ctx, int32_t enable);
 int micsa_get_timing(micsa_ctx* ctx, int32_t kind, double* total_ms, int64_t* launches);
 

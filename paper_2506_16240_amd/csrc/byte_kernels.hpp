@@ -244,14 +244,48 @@ __global__ void __launch_bounds__(256) k_micsa_half(Geom g, uint8_t* __restrict_
     block_add(tally + (int64_t)l * kSlots, dE);
 }
 
-// ------------------------------------------------------ heat-bath half sweep
-// New spin +1 iff u < tau[v], v = #neighbours with J s_nb = -1 (h = 6 - 2v);
-// u = Philox(h>>2, 2k+p, r, stream HB | s)[h & 3] for parity-split index h.
+// ------------------------------------------ canonical (random-number) updates
+// The two baselines draw one 32-bit uniform u per visited site:
+// u = Philox(h>>2, 2k+p, r, stream | s)[h & 3] for the parity-split index h.
+//   ALG 0, heat bath: the new spin is +1 iff u < tau[v], where v counts the
+//     neighbours with J s_nb = -1 (local field h = 6 - 2v).
+//   ALG 1, Metropolis: the flip is taken iff u < theta[q], q = (dH + 12)/4;
+//     dH = 2 s h, so q = 6 - v for s = +1 and q = v for s = -1.
+// Four sites per word (byte b = site b); v holds the four counts bytewise.
+// dE accumulates 2 s_old h for every spin that changed.
+template <int ALG>
+__device__ __forceinline__ uint32_t canonical4(uint32_t S, uint32_t v, const u32x4& rnd, const uint64_t* tab,
+                                               int& dE)
+{
+    const uint32_t ru[4] = {rnd.v0, rnd.v1, rnd.v2, rnd.v3};
+    uint32_t Sn = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t vb = (v >> (8 * b)) & 0xFFu;
+        const uint32_t old = (S >> (8 * b)) & 1u;
+        uint32_t nw;
+        if (ALG == 0) {
+            nw = (uint64_t)ru[b] < tab[vb] ? 0u : 1u;
+        } else {
+            const uint32_t q = old ? vb : 6u - vb;
+            nw = old ^ ((uint64_t)ru[b] < tab[q] ? 1u : 0u);
+        }
+        if (nw != old) dE += 2 * (1 - 2 * (int)old) * (6 - 2 * (int)vb);
+        Sn |= nw << (8 * b);
+    }
+    return Sn;
+}
 
-// With dk != nullptr the sweep index k = *dk and the thresholds of refresh
-// rho(k) come from device memory (replayable graphs); otherwise from the
-// arguments.
-template <int P>
+template <int ALG>
+__device__ __forceinline__ uint32_t canonical_stream(uint32_t s)
+{
+    return stream_word(ALG == 0 ? kStreamHeatBath : kStreamMetropolis, s);
+}
+
+// ------------------------------------------- heat-bath / Metropolis half sweep
+// With dk != nullptr the sweep index k = *dk and the table of refresh rho(k)
+// comes from device memory (replayable graphs); otherwise from the arguments.
+template <int P, int ALG>
 __global__ void __launch_bounds__(256) k_heatbath_half(Geom g, uint8_t* __restrict__ spin,
                                                        const uint32_t* __restrict__ J, uint32_t time,
                                                        HeatBathThresholds th,
@@ -280,20 +314,8 @@ __global__ void __launch_bounds__(256) k_heatbath_half(Geom g, uint8_t* __restri
         uint32_t v = 0;
 #pragma unroll
         for (int d = 0; d < 6; ++d) v += n.nb[d] ^ n.jb[d];
-        const u32x4 rnd = philox10(w, time, (uint32_t)r, stream_word(kStreamHeatBath, (uint32_t)s),
-                                   g.key0, g.key1);
-        const uint32_t ru[4] = {rnd.v0, rnd.v1, rnd.v2, rnd.v3};
-        const uint32_t S = own[w];
-        uint32_t Snew = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint32_t vb = (v >> (8 * b)) & 0xFFu;
-            const uint32_t up = (uint64_t)ru[b] < tau[vb] ? 0u : 1u;
-            const uint32_t old = (S >> (8 * b)) & 1u;
-            if (up != old) dE += 2 * (1 - 2 * (int)old) * (6 - 2 * (int)vb);
-            Snew |= up << (8 * b);
-        }
-        own[w] = Snew;
+        const u32x4 rnd = philox10(w, time, (uint32_t)r, canonical_stream<ALG>((uint32_t)s), g.key0, g.key1);
+        own[w] = canonical4<ALG>(own[w], v, rnd, tau, dE);
     }
     block_add(tally + (int64_t)l * kSlots, dE);
 }

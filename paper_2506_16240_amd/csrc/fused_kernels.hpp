@@ -324,27 +324,12 @@ __global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
     block_add(tally + (int64_t)l * kSlots, 4 * ((long long)sum_old - (long long)sum_new));
 }
 
-// Fused heat-bath sweep (the random-number-greedy baseline): same z-march,
-// tiles, rings and LDS exchange as k_micsa_sweep_fused; every site draws one
-// 32-bit uniform, u = Philox(h>>2, 2k+p, r, stream HB | s)[h & 3] for its
-// parity-split index h, and becomes +1 iff u < tau[v], where v counts the
-// neighbours with J s_nb = -1.  No daemons.
-__device__ __forceinline__ void heatbath4(uint32_t& S, uint32_t v, const u32x4& rnd, const uint64_t* tau, int& dE)
-{
-    const uint32_t ru[4] = {rnd.v0, rnd.v1, rnd.v2, rnd.v3};
-    uint32_t Sn = 0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const uint32_t vb = (v >> (8 * b)) & 0xFFu;
-        const uint32_t down = (uint64_t)ru[b] < tau[vb] ? 0u : 1u;
-        const uint32_t old = (S >> (8 * b)) & 1u;
-        // flipping s_old changes H by 2 s_old h, h = 6 - 2v
-        if (down != old) dE += 2 * (1 - 2 * (int)old) * (6 - 2 * (int)vb);
-        Sn |= down << (8 * b);
-    }
-    S = Sn;
-}
-
+// Fused sweep of the random-number-greedy baselines (ALG 0 heat bath, ALG 1
+// Metropolis; canonical4): same z-march, tiles, rings and LDS exchange as
+// k_micsa_sweep_fused, with one 32-bit uniform per visited site,
+// u = Philox(h>>2, 2k+p, r, stream | s)[h & 3] for its parity-split index h.
+// No daemons.
+template <int ALG>
 __global__ void __launch_bounds__(1024) k_heatbath_sweep_fused(
     Geom g, FusedTile f, const uint8_t* __restrict__ spin_in, uint8_t* __restrict__ spin_out,
     const uint32_t* __restrict__ J, unsigned long long* __restrict__ tally, uint32_t time0, HeatBathThresholds th)
@@ -374,7 +359,7 @@ __global__ void __launch_bounds__(1024) k_heatbath_sweep_fused(
     uint8_t* ev_out = spin_out + ((int64_t)l * 2 + 0) * g.Nh;
     uint8_t* od_out = spin_out + ((int64_t)l * 2 + 1) * g.Nh;
     const uint8_t* Jb = reinterpret_cast<const uint8_t*>(J) + (int64_t)s * g.Nh;
-    const uint32_t sw = stream_word(kStreamHeatBath, (uint32_t)s);
+    const uint32_t sw = canonical_stream<ALG>((uint32_t)s);
 
     auto wrapz = [&](int z) { return z < 0 ? z + g.Lz : (z >= g.Lz ? z - g.Lz : z); };
     auto hof = [&](int z) { return ((int64_t)y + (int64_t)g.Ly * z) * g.Kx + 16 * c; };
@@ -433,8 +418,7 @@ __global__ void __launch_bounds__(1024) k_heatbath_sweep_fused(
                                    xor_and(So_next.w[i], jw >> kPz, m1) + xor_and(So_prev.w[i], jw >> kMz, m1);
                 const uint32_t ctr = (uint32_t)((h >> 2) + i);
                 const u32x4 rnd = philox10(ctr, time0, (uint32_t)r, sw, g.key0, g.key1);
-                uint32_t S = Se.w[i];
-                heatbath4(S, v, rnd, tau, dEe);
+                const uint32_t S = canonical4<ALG>(Se.w[i], v, rnd, tau, dEe);
                 Se.w[i] = S;
                 Xn.w[i] = ((S << 6) - S) ^ jw;
             }
@@ -466,9 +450,7 @@ __global__ void __launch_bounds__(1024) k_heatbath_sweep_fused(
                                    ((X_prev2.w[i] >> kPz) & m1);
                 const uint32_t ctr = (uint32_t)((ho >> 2) + i);
                 const u32x4 rnd = philox10(ctr, time0 + 1u, (uint32_t)r, sw, g.key0, g.key1);
-                uint32_t S = So_prev.w[i];
-                heatbath4(S, v, rnd, tau, dE);
-                So_new.w[i] = S;
+                So_new.w[i] = canonical4<ALG>(So_prev.w[i], v, rnd, tau, dE);
             }
             stg16(od_out + ho, So_new);
         }

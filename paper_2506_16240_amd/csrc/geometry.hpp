@@ -45,6 +45,11 @@ struct HeatBathThresholds {
     uint64_t tau[7];
 };
 
+// Metropolis: a proposed flip with energy change dH = 4q - 12 (q in 0..6) is
+// accepted iff u < theta[q], theta = floor(2^32 e^{-beta dH}) uphill, 2^32
+// for dH <= 0.  Same 7-entry shape as the heat-bath table.
+using MetropolisThresholds = HeatBathThresholds;
+
 // Byte-wise sum of a 32-bit word whose bytes add up to less than 256.
 __device__ __forceinline__ uint32_t bytesum(uint32_t v) { return (v * 0x01010101u) >> 24; }
 

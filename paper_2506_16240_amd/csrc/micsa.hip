@@ -24,8 +24,9 @@ using namespace micsa;
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kTimingKinds = 4;
-enum TimingKind { kTimeSweep = 0, kTimeRefresh = 1, kTimeHeatBath = 2, kTimeReduce = 3 };
+constexpr int kTimingKinds = 5;
+enum TimingKind { kTimeSweep = 0, kTimeRefresh = 1, kTimeHeatBath = 2, kTimeReduce = 3, kTimeMetropolis = 4 };
+constexpr int kAlgos = 4;  // MICSA, HEATBATH, WALKERS, METROPOLIS
 
 struct Schedule {
     bool set = false;
@@ -64,8 +65,8 @@ struct micsa_ctx {
     // replayable graphs of kGraphSweeps sweeps for the per-half paths, per algo
     int64_t* d_k = nullptr;  // device copy of the sweep counter
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    const void* gkey[2] = {nullptr, nullptr};  // state buffer the graph was captured with
+    hipGraphExec_t gexec[kAlgos] = {};
+    const void* gkey[kAlgos] = {};  // state buffer the graph was captured with
     uint32_t* J = nullptr;    // [S][Nh] coupling bytes of the even sites
     unsigned long long* tally = nullptr;  // [L][kSlots]
     unsigned long long* red = nullptr;    // [max(L, S)][kSlots] reduction scratch
@@ -73,13 +74,14 @@ struct micsa_ctx {
     // device tables of the installed schedule, one entry per refresh index
     DaemonThresholds* d_dth = nullptr;
     HeatBathThresholds* d_hth = nullptr;
+    MetropolisThresholds* d_mth = nullptr;
     int64_t k = 0;
     std::string err;
     // timing
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events[kTimingKinds];
-    double time_ms[kTimingKinds] = {0, 0, 0, 0};
-    int64_t launches[kTimingKinds] = {0, 0, 0, 0};
+    double time_ms[kTimingKinds] = {};
+    int64_t launches[kTimingKinds] = {};
 };
 
 namespace {
@@ -149,6 +151,26 @@ HeatBathThresholds heatbath_thresholds(double T)
         th.tau[v] = (uint64_t)std::floor(4294967296.0 / (1.0 + std::exp(-2.0 * beta * (double)(6 - 2 * v))));
     return th;
 }
+
+// theta_q = floor(2^32 e^{-beta dH}) for dH = 4q - 12 > 0, 2^32 for dH <= 0.
+MetropolisThresholds metropolis_thresholds(double T)
+{
+    const double beta = 1.0 / T;
+    MetropolisThresholds th;
+    for (int q = 0; q < 7; ++q) {
+        const int dH = 4 * q - 12;
+        th.tau[q] = dH <= 0 ? 4294967296ull : (uint64_t)std::floor(std::exp(-beta * (double)dH) * 4294967296.0);
+    }
+    return th;
+}
+
+// The per-refresh table of a canonical baseline, and its timing kind.
+const HeatBathThresholds* canonical_table(const micsa_ctx* c, int32_t algo)
+{
+    return algo == MICSA_ALGO_METROPOLIS ? c->d_mth : c->d_hth;
+}
+
+int canonical_timing(int32_t algo) { return algo == MICSA_ALGO_METROPOLIS ? kTimeMetropolis : kTimeHeatBath; }
 
 // --------------------------------------------------------------- launching
 dim3 grid_for(int64_t threads, int y)
@@ -367,7 +389,7 @@ int launch_micsa_sweep(micsa_ctx* c)
     return check_launch(c, "k_micsa_half<1>");
 }
 
-int launch_fused_heatbath(micsa_ctx* c, int64_t k, double T)
+int launch_fused_canonical(micsa_ctx* c, int32_t algo, int64_t k, double T)
 {
     const FusedTile f = choose_tile(c);
     const int lanes = (f.TY + 4) * f.NC;
@@ -375,9 +397,13 @@ int launch_fused_heatbath(micsa_ctx* c, int64_t k, double T)
     const size_t lds = (size_t)64 * (f.TY + 4) * f.NC;
     const dim3 grid((unsigned)(f.nty * (c->p.Lz / f.TZ)), (unsigned)c->L, 1);
     {
-        TimedLaunch t(c, kTimeHeatBath);
-        k_heatbath_sweep_fused<<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->spin_alt, c->J, c->tally,
-                                                                (uint32_t)(2 * k), heatbath_thresholds(T));
+        TimedLaunch t(c, canonical_timing(algo));
+        if (algo == MICSA_ALGO_METROPOLIS)
+            k_heatbath_sweep_fused<1><<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->spin_alt, c->J, c->tally,
+                                                                       (uint32_t)(2 * k), metropolis_thresholds(T));
+        else
+            k_heatbath_sweep_fused<0><<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->spin_alt, c->J, c->tally,
+                                                                       (uint32_t)(2 * k), heatbath_thresholds(T));
     }
     const int st = check_launch(c, "k_heatbath_sweep_fused");
     if (st) return st;
@@ -385,24 +411,35 @@ int launch_fused_heatbath(micsa_ctx* c, int64_t k, double T)
     return MICSA_OK;
 }
 
-int launch_heatbath_sweep(micsa_ctx* c, int64_t k, double T)
+// One half sweep of a canonical baseline; with dk the sweep index and the
+// table come from device memory (graph form), otherwise from k and th.
+template <int P>
+void enqueue_canonical_half(micsa_ctx* c, int32_t algo, hipStream_t st, int64_t k, const HeatBathThresholds& th,
+                            const int64_t* dk)
 {
-    if (use_fused(c)) return launch_fused_heatbath(c, k, T);
     const int64_t words = (int64_t)c->g.rows * c->g.Wr;
-    const HeatBathThresholds th = heatbath_thresholds(T);
+    const dim3 grid = grid_for(words, c->L);
+    const uint32_t time = (uint32_t)(2 * k + P);
+    const int32_t period = c->sched.period;
+    if (algo == MICSA_ALGO_METROPOLIS)
+        k_heatbath_half<P, 1><<<grid, kBlock, 0, st>>>(c->g, c->spin, c->J, time, th, c->tally, dk, period, c->d_mth);
+    else
+        k_heatbath_half<P, 0><<<grid, kBlock, 0, st>>>(c->g, c->spin, c->J, time, th, c->tally, dk, period, c->d_hth);
+}
+
+int launch_canonical_sweep(micsa_ctx* c, int32_t algo, int64_t k, double T)
+{
+    if (use_fused(c)) return launch_fused_canonical(c, algo, k, T);
+    const HeatBathThresholds th = algo == MICSA_ALGO_METROPOLIS ? metropolis_thresholds(T) : heatbath_thresholds(T);
     {
-        TimedLaunch t(c, kTimeHeatBath);
-        k_heatbath_half<0><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->J,
-                                                                             (uint32_t)(2 * k), th, c->tally,
-                                                                             nullptr, 0, nullptr);
+        TimedLaunch t(c, canonical_timing(algo));
+        enqueue_canonical_half<0>(c, algo, c->stream, k, th, nullptr);
     }
     int st = check_launch(c, "k_heatbath_half<0>");
     if (st) return st;
     {
-        TimedLaunch t(c, kTimeHeatBath);
-        k_heatbath_half<1><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->J,
-                                                                             (uint32_t)(2 * k + 1), th, c->tally,
-                                                                             nullptr, 0, nullptr);
+        TimedLaunch t(c, canonical_timing(algo));
+        enqueue_canonical_half<1>(c, algo, c->stream, k, th, nullptr);
     }
     return check_launch(c, "k_heatbath_half<1>");
 }
@@ -449,15 +486,19 @@ inline void split_index(const micsa_ctx* c, int64_t i, int& par, int64_t& h)
 int launch_resident(micsa_ctx* c, int32_t algo, int64_t n, long long* dlog, int64_t stride)
 {
     const size_t lds = (size_t)c->g.Nh * 3;
-    static bool attr_set[2] = {false, false};
-    if (!attr_set[algo]) {
-        hipError_t e = algo == 0 ? hipFuncSetAttribute((const void*)k_resident<0>,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kResidentLdsMax)
-                                 : hipFuncSetAttribute((const void*)k_resident<1>,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kResidentLdsMax);
+    // kernel instance: 0 MicSA, 1 heat bath, 2 Metropolis
+    const int inst = algo == MICSA_ALGO_MICSA ? 0 : (algo == MICSA_ALGO_HEATBATH ? 1 : 2);
+    static const void* const kernels[3] = {(const void*)k_resident<0>, (const void*)k_resident<1>,
+                                           (const void*)k_resident<2>};
+    static bool attr_set[3] = {false, false, false};
+    if (!attr_set[inst]) {
+        const hipError_t e =
+            hipFuncSetAttribute(kernels[inst], hipFuncAttributeMaxDynamicSharedMemorySize, (int)kResidentLdsMax);
         if (e != hipSuccess) return fail(c, MICSA_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
-        attr_set[algo] = true;
+        attr_set[inst] = true;
     }
+    const HeatBathThresholds* tab = canonical_table(c, algo);
+    const int tkind = inst == 0 ? kTimeSweep : canonical_timing(algo);
     int64_t done = 0;
     while (done < n) {
         int64_t chunk = std::min<int64_t>(kResidentChunk, n - done);
@@ -471,13 +512,16 @@ int launch_resident(micsa_ctx* c, int32_t algo, int64_t n, long long* dlog, int6
         rs.log_stride = dlog ? (int32_t)stride : 0;
         rs.log_row0 = dlog ? done / stride : 0;
         {
-            TimedLaunch t(c, algo == MICSA_ALGO_MICSA ? kTimeSweep : kTimeHeatBath);
-            if (algo == MICSA_ALGO_MICSA)
+            TimedLaunch t(c, tkind);
+            if (inst == 0)
                 k_resident<0><<<c->L, kResidentBlock, lds, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally, rs,
-                                                                        c->d_dth, c->d_hth, dlog);
-            else
+                                                                        c->d_dth, tab, dlog);
+            else if (inst == 1)
                 k_resident<1><<<c->L, kResidentBlock, lds, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally, rs,
-                                                                        c->d_dth, c->d_hth, dlog);
+                                                                        c->d_dth, tab, dlog);
+            else
+                k_resident<2><<<c->L, kResidentBlock, lds, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally, rs,
+                                                                        c->d_dth, tab, dlog);
         }
         const int st = check_launch(c, "k_resident");
         if (st) return st;
@@ -520,10 +564,8 @@ int enqueue_dev_sweep(micsa_ctx* c, int32_t algo, hipStream_t st)
             k_micsa_half<1><<<grid_for(words, c->L), kBlock, 0, st>>>(c->g, c->spin, c->dem, c->J, c->tally);
         } else {
             const HeatBathThresholds none{};
-            k_heatbath_half<0><<<grid_for(words, c->L), kBlock, 0, st>>>(c->g, c->spin, c->J, 0u, none, c->tally,
-                                                                          c->d_k, P, c->d_hth);
-            k_heatbath_half<1><<<grid_for(words, c->L), kBlock, 0, st>>>(c->g, c->spin, c->J, 0u, none, c->tally,
-                                                                          c->d_k, P, c->d_hth);
+            enqueue_canonical_half<0>(c, algo, st, 0, none, c->d_k);
+            enqueue_canonical_half<1>(c, algo, st, 0, none, c->d_k);
         }
     }
     k_count_sweep<<<1, 1, 0, st>>>(c->d_k);
@@ -571,11 +613,12 @@ int sweep_graph(micsa_ctx* c, int32_t algo, int64_t n)
 // Checks shared by every sweep entry point.
 int check_sweep(micsa_ctx* c, int32_t algo, int64_t n)
 {
-    if (algo != MICSA_ALGO_MICSA && algo != MICSA_ALGO_HEATBATH && algo != MICSA_ALGO_WALKERS)
+    if (algo != MICSA_ALGO_MICSA && algo != MICSA_ALGO_HEATBATH && algo != MICSA_ALGO_WALKERS &&
+        algo != MICSA_ALGO_METROPOLIS)
         return fail(c, MICSA_EINVAL, "unknown algo");
     if (c->bit && algo == MICSA_ALGO_WALKERS) return fail(c, MICSA_EINVAL, "walkers run in the byte layout");
     if (c->bit && algo != MICSA_ALGO_MICSA)
-        return fail(c, MICSA_EINVAL, "the heat-bath baseline runs in the byte layout");
+        return fail(c, MICSA_EINVAL, "the heat-bath and Metropolis baselines run in the byte layout");
     if (n < 0) return fail(c, MICSA_EINVAL, "negative sweep count");
     if (!c->sched.set) return fail(c, MICSA_ESTATE, "no schedule installed");
     if (c->k + n > c->sched.n_sweeps) return fail(c, MICSA_ERANGE, "sweeps beyond the schedule length");
@@ -623,7 +666,7 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
             }
             if (algo == MICSA_ALGO_WALKERS && (st = launch_wander(c, k))) return st;
         } else {
-            if ((st = launch_heatbath_sweep(c, k, T))) return st;
+            if ((st = launch_canonical_sweep(c, algo, k, T))) return st;
         }
         c->k = k + 1;
     }
@@ -643,6 +686,7 @@ void free_all(micsa_ctx* c)
     if (c->bJ) (void)hipFree(c->bJ);
     if (c->d_dth) (void)hipFree(c->d_dth);
     if (c->d_hth) (void)hipFree(c->d_hth);
+    if (c->d_mth) (void)hipFree(c->d_mth);
     for (auto& e : c->gexec)
         if (e) (void)hipGraphExecDestroy(e);
     if (c->d_k) (void)hipFree(c->d_k);
@@ -810,26 +854,34 @@ int micsa_set_schedule(micsa_ctx* ctx, const micsa_schedule* s)
     const int64_t nrho = std::max<int64_t>(refresh_count(n), 1);
     std::vector<DaemonThresholds> dth((size_t)nrho);
     std::vector<HeatBathThresholds> hth((size_t)nrho);
+    std::vector<MetropolisThresholds> mth((size_t)nrho);
     for (int64_t rho = 0; rho < nrho; ++rho) {
         const double T = temperature(n, rho);
         dth[(size_t)rho] = daemon_thresholds(T);
         hth[(size_t)rho] = heatbath_thresholds(T);
+        mth[(size_t)rho] = metropolis_thresholds(T);
     }
     DaemonThresholds* d1 = nullptr;
     HeatBathThresholds* d2 = nullptr;
+    MetropolisThresholds* d3 = nullptr;
     if (hipMalloc(&d1, dth.size() * sizeof(DaemonThresholds)) != hipSuccess ||
-        hipMalloc(&d2, hth.size() * sizeof(HeatBathThresholds)) != hipSuccess) {
+        hipMalloc(&d2, hth.size() * sizeof(HeatBathThresholds)) != hipSuccess ||
+        hipMalloc(&d3, mth.size() * sizeof(MetropolisThresholds)) != hipSuccess) {
         (void)hipGetLastError();
         if (d1) (void)hipFree(d1);
+        if (d2) (void)hipFree(d2);
         return fail(ctx, MICSA_ENOMEM, "schedule tables");
     }
     HIP_TRY(ctx, hipMemcpyAsync(d1, dth.data(), dth.size() * sizeof(DaemonThresholds), hipMemcpyHostToDevice,
                                 ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(d2, hth.data(), hth.size() * sizeof(HeatBathThresholds), hipMemcpyHostToDevice,
                                 ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d3, mth.data(), mth.size() * sizeof(MetropolisThresholds), hipMemcpyHostToDevice,
+                                ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     if (ctx->d_dth) (void)hipFree(ctx->d_dth);
     if (ctx->d_hth) (void)hipFree(ctx->d_hth);
+    if (ctx->d_mth) (void)hipFree(ctx->d_mth);
     for (auto& e : ctx->gexec)  // captured graphs point at the old tables
         if (e) {
             (void)hipGraphExecDestroy(e);
@@ -837,6 +889,7 @@ int micsa_set_schedule(micsa_ctx* ctx, const micsa_schedule* s)
         }
     ctx->d_dth = d1;
     ctx->d_hth = d2;
+    ctx->d_mth = d3;
     ctx->sched = std::move(n);
     return MICSA_OK;
 }
@@ -1160,6 +1213,17 @@ int micsa_get_heatbath_thresholds(micsa_ctx* ctx, int64_t rho, uint64_t tau[7])
     return MICSA_OK;
 }
 
+int micsa_get_metropolis_thresholds(micsa_ctx* ctx, int64_t rho, uint64_t theta[7])
+{
+    if (!ctx || !theta) return MICSA_EINVAL;
+    if (!ctx->sched.set) return fail(ctx, MICSA_ESTATE, "no schedule installed");
+    if (rho < 0 || rho >= std::max<int64_t>(refresh_count(ctx->sched), 1))
+        return fail(ctx, MICSA_ERANGE, "refresh index outside the schedule");
+    const MetropolisThresholds th = metropolis_thresholds(temperature(ctx->sched, rho));
+    for (int q = 0; q < 7; ++q) theta[q] = th.tau[q];
+    return MICSA_OK;
+}
+
 int micsa_set_timing(micsa_ctx* ctx, int32_t enable)
 {
     if (!ctx) return MICSA_EINVAL;
@@ -1192,8 +1256,12 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
 {
     if (ctx && ctx->bit) return algo == MICSA_ALGO_MICSA ? "kb_micsa_half" : "";
     if (algo == MICSA_ALGO_WALKERS) return ctx && use_fused(ctx) ? "k_micsa_sweep_fused+k_wander" : "k_micsa_half+k_wander";
-    if (ctx && use_resident(ctx)) return algo == MICSA_ALGO_HEATBATH ? "k_resident<1>" : "k_resident<0>";
-    if (algo == MICSA_ALGO_HEATBATH) return ctx && use_fused(ctx) ? "k_heatbath_sweep_fused" : "k_heatbath_half";
+    if (ctx && use_resident(ctx))
+        return algo == MICSA_ALGO_HEATBATH ? "k_resident<1>" : (algo == MICSA_ALGO_METROPOLIS ? "k_resident<2>" : "k_resident<0>");
+    if (algo == MICSA_ALGO_HEATBATH)
+        return ctx && use_fused(ctx) ? "k_heatbath_sweep_fused<0>" : "k_heatbath_half<0>";
+    if (algo == MICSA_ALGO_METROPOLIS)
+        return ctx && use_fused(ctx) ? "k_heatbath_sweep_fused<1>" : "k_heatbath_half<1>";
     if (ctx && use_fused(ctx)) return "k_micsa_sweep_fused";
     return "k_micsa_half";
 }

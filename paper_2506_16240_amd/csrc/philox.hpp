@@ -35,7 +35,7 @@ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
 }
 
 // Stream tags in the top byte of the last counter word; sample in the low 24 bits.
-enum : uint32_t { kStreamCoupling = 1u, kStreamSpin = 2u, kStreamDaemon = 3u, kStreamHeatBath = 4u };
+enum : uint32_t { kStreamCoupling = 1u, kStreamSpin = 2u, kStreamDaemon = 3u, kStreamHeatBath = 4u, kStreamMetropolis = 5u };
 
 __device__ __forceinline__ uint32_t stream_word(uint32_t stream, uint32_t sample)
 {

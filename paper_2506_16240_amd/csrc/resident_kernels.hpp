@@ -90,9 +90,11 @@ __device__ __forceinline__ uint32_t unsat_resident(const Geom& g, const uint32_t
 }
 
 // Sweeps of lattice l of one context (all threads of the work-group call it).
+// hth: per-refresh table of the baseline (heat bath or Metropolis), unused
+// by MicSA.
 // LDS: per site one state byte (spin in bit 0, daemon level in bits 1-2),
 // plus one coupling byte per even site: 1.5 B per site.
-template <int ALGO>  // 0 MicSA, 1 heat bath
+template <int ALGO>  // 0 MicSA, 1 heat bath, 2 Metropolis
 __device__ __forceinline__ void resident_body(const Geom& g, uint8_t* __restrict__ spin, uint8_t* __restrict__ dem,
                                               const uint32_t* __restrict__ J, unsigned long long* __restrict__ tally,
                                               const ResidentSched& rs, const DaemonThresholds* __restrict__ dth,
@@ -143,7 +145,7 @@ __device__ __forceinline__ void resident_body(const Geom& g, uint8_t* __restrict
             }
             __syncthreads();
         }
-        if (ALGO == 1) {
+        if (ALGO != 0) {  // the baseline's table (heat bath tau or Metropolis theta) of refresh rho
             if (threadIdx.x < 7) tau[threadIdx.x] = hth[rho - rs.rho0].tau[threadIdx.x];
             __syncthreads();
         }
@@ -172,18 +174,8 @@ __device__ __forceinline__ void resident_body(const Geom& g, uint8_t* __restrict
                     const uint32_t mS = (S << 8) - S;
                     const uint32_t vbytes = bitsel(mS, 0x06060606u - u, u);
                     const u32x4 rnd = philox10((uint32_t)w, (uint32_t)(2 * k + P), (uint32_t)r,
-                                               stream_word(kStreamHeatBath, (uint32_t)s), g.key0, g.key1);
-                    const uint32_t ru[4] = {rnd.v0, rnd.v1, rnd.v2, rnd.v3};
-                    uint32_t Sn = 0;
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const uint32_t vb = (vbytes >> (8 * b)) & 0xFFu;
-                        const uint32_t down = (uint64_t)ru[b] < tau[vb] ? 0u : 1u;
-                        const uint32_t old = (S >> (8 * b)) & 1u;
-                        if (down != old) dE += 2 * (1 - 2 * (int)old) * (6 - 2 * (int)vb);
-                        Sn |= down << (8 * b);
-                    }
-                    own[w] = Sn;
+                                               canonical_stream<ALGO == 2>((uint32_t)s), g.key0, g.key1);
+                    own[w] = canonical4<ALGO == 2>(S, vbytes, rnd, tau, dE);
                 }
                 // next word of this thread: advance (c, y, z) by blockDim words
                 c += dc;

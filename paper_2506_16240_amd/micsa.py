@@ -17,10 +17,10 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmicsa.so
 
 OK, EINVAL, ENOMEM, EHIP, ESTATE, ERANGE = 0, -1, -2, -3, -4, -5
 LAYOUT_BYTE, LAYOUT_BITPLANE = 0, 1
-ALGO_MICSA, ALGO_HEATBATH, ALGO_WALKERS = 0, 1, 2
+ALGO_MICSA, ALGO_HEATBATH, ALGO_WALKERS, ALGO_METROPOLIS = 0, 1, 2, 3
 SCHED_CONST, SCHED_LINEAR, SCHED_TABLE = 0, 1, 2
 REFRESH_LOG2 = 0
-TIME_SWEEP, TIME_REFRESH, TIME_HEATBATH, TIME_REDUCE = 0, 1, 2, 3
+TIME_SWEEP, TIME_REFRESH, TIME_HEATBATH, TIME_REDUCE, TIME_METROPOLIS = 0, 1, 2, 3, 4
 OPT_SWEEP_KERNEL, OPT_TILE_Y, OPT_TILE_Z, OPT_XCD_MAP, OPT_GRAPHS = 1, 2, 3, 4, 5
 KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_FUSED, KERNEL_RESIDENT = 0, 1, 2, 3
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_RELEASED = 0, 1, 2, 3
@@ -68,6 +68,7 @@ _SIGNATURES = [
                                           ctypes.POINTER(ctypes.c_int64)]),
     ("micsa_get_thresholds", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     ("micsa_get_heatbath_thresholds", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    ("micsa_get_metropolis_thresholds", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     ("micsa_write_spins", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("micsa_write_demons", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("micsa_set_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
@@ -259,6 +260,11 @@ class Lattice:
     def heatbath_thresholds(self, rho: int) -> np.ndarray:
         t = np.zeros(7, np.uint64)
         self._check(lib().micsa_get_heatbath_thresholds(self._ctx, rho, _ptr(t)), "get_heatbath_thresholds")
+        return t
+
+    def metropolis_thresholds(self, rho: int) -> np.ndarray:
+        t = np.zeros(7, np.uint64)
+        self._check(lib().micsa_get_metropolis_thresholds(self._ctx, rho, _ptr(t)), "get_metropolis_thresholds")
         return t
 
     # -- writes ---------------------------------------------------------

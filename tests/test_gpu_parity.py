@@ -65,11 +65,12 @@ def test_thresholds_bitexact():
             T = os_.temperature(rho)
             assert np.array_equal(g.thresholds(rho), O.daemon_thresholds(T)), (gs, rho)
             assert np.array_equal(g.heatbath_thresholds(rho), O.heatbath_thresholds(T)), (gs, rho)
+            assert np.array_equal(g.metropolis_thresholds(rho), O.metropolis_thresholds(T)), (gs, rho)
 
 
 @pytest.mark.parametrize("kernel", [M.KERNEL_SIMPLE, M.KERNEL_RESIDENT])
 @pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("algo", [M.ALGO_MICSA, M.ALGO_HEATBATH])
+@pytest.mark.parametrize("algo", [M.ALGO_MICSA, M.ALGO_HEATBATH, M.ALGO_METROPOLIS])
 def test_trajectory_matches_oracle(shape, algo, kernel):
     g, o = pair(*shape, seed=77)
     g.set_option(M.OPT_SWEEP_KERNEL, kernel)
@@ -139,7 +140,7 @@ def test_quench_L64_shape():
     seed, energies, daemon energies and the replica overlap."""
     w = W.QUENCH_L64
     n = 120
-    for algo in (M.ALGO_MICSA, M.ALGO_HEATBATH):
+    for algo in (M.ALGO_MICSA, M.ALGO_HEATBATH, M.ALGO_METROPOLIS):
         g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
         gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
         g.set_schedule(gs)
@@ -182,15 +183,17 @@ def test_anneal_L512_first_sweeps_full_size():
     assert np.array_equal(g.energy_tally(), g.energy())
 
 
-def test_anneal_L512_heatbath_first_sweeps_full_size():
-    """The heat-bath baseline on the 512^3 lattice: first 6 sweeps bit-exact."""
+@pytest.mark.parametrize("algo", [M.ALGO_HEATBATH, M.ALGO_METROPOLIS])
+def test_anneal_L512_baseline_first_sweeps_full_size(algo):
+    """The heat-bath and Metropolis baselines on the 512^3 lattice: first 6
+    sweeps bit-exact."""
     w = W.ANNEAL_L512
     n = 6
     g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
     gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
     g.set_schedule(gs)
-    Eg, _ = g.sweep_logged(M.ALGO_HEATBATH, n, 3)
-    Eo, _ = o.run(O.ALGO_HEATBATH, os_, n, 3)
+    Eg, _ = g.sweep_logged(algo, n, 3)
+    Eo, _ = o.run(algo, os_, n, 3)
     assert np.array_equal(Eg, Eo)
     assert np.array_equal(g.spins(), o.sigma)
     assert np.array_equal(g.energy_tally(), g.energy())
@@ -220,13 +223,13 @@ def test_written_state_is_swept_identically():
 
 
 @pytest.mark.parametrize("layout", [M.LAYOUT_BYTE, M.LAYOUT_BITPLANE])
-@pytest.mark.parametrize("algo", [M.ALGO_MICSA, M.ALGO_HEATBATH])
+@pytest.mark.parametrize("algo", [M.ALGO_MICSA, M.ALGO_HEATBATH, M.ALGO_METROPOLIS])
 def test_graph_replays_match_eager_launches(layout, algo):
     """Replayed graphs (16 sweeps each, device sweep counter) give the same bits
     as eager launches and as the oracle, over several calls with eager work
     and reads in between and a refresh period that does not divide 16."""
-    if layout == M.LAYOUT_BITPLANE and algo == M.ALGO_HEATBATH:
-        pytest.skip("the heat bath runs in the byte layout")
+    if layout == M.LAYOUT_BITPLANE and algo != M.ALGO_MICSA:
+        pytest.skip("the canonical baselines run in the byte layout")
     shape = (64, 8, 6, 3, 2)  # byte: neither resident (forced simple) nor fused
     res = []
     for graphs in (1, 0):
@@ -307,6 +310,13 @@ def test_timing_counts_launches():
     h.set_timing(True)
     h.sweep(M.ALGO_MICSA, 20)
     assert h.timing(M.TIME_SWEEP)[1] == 1  # all 20 sweeps in one launch
+    m, _ = pair(16, 16, 16)
+    m.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_SIMPLE)
+    m.set_schedule(M.Schedule(M.SCHED_CONST, 1.5, 1.5, 20, 10))
+    m.set_timing(True)
+    m.sweep(M.ALGO_METROPOLIS, 7)
+    assert m.timing(M.TIME_METROPOLIS)[1] == 14 and m.timing(M.TIME_HEATBATH)[1] == 0
+    assert m.timing(M.TIME_SWEEP)[1] == 0
 
 
 # ----------------------------------------------------------- fused sweep
@@ -322,7 +332,7 @@ FUSED_CASES = [
 ]
 
 
-@pytest.mark.parametrize("algo", [M.ALGO_MICSA, M.ALGO_HEATBATH])
+@pytest.mark.parametrize("algo", [M.ALGO_MICSA, M.ALGO_HEATBATH, M.ALGO_METROPOLIS])
 @pytest.mark.parametrize("shape,ty,tz", FUSED_CASES)
 def test_fused_sweep_matches_oracle(shape, ty, tz, algo):
     g, o = pair(*shape, seed=99)
@@ -331,7 +341,7 @@ def test_fused_sweep_matches_oracle(shape, ty, tz, algo):
         g.set_option(M.OPT_TILE_Y, ty)
     if tz:
         g.set_option(M.OPT_TILE_Z, tz)
-    assert g.kernel_name(algo) in ("k_micsa_sweep_fused", "k_heatbath_sweep_fused")
+    assert g.kernel_name(algo) in ("k_micsa_sweep_fused", "k_heatbath_sweep_fused<0>", "k_heatbath_sweep_fused<1>")
     n = 23
     gs, os_ = scheds(M.SCHED_LINEAR, 2.5, 0.4, n, 5)
     g.set_schedule(gs)
@@ -450,9 +460,10 @@ def test_layouts_are_bit_identical():
 def test_bitplane_error_paths():
     g = M.Lattice(8, 4, 4, 3, 1, seed=1, layout=M.LAYOUT_BITPLANE)
     g.set_schedule(M.Schedule(M.SCHED_CONST, 1.0, 1.0, 10, 2))
-    with pytest.raises(M.MicsaError) as e:
-        g.sweep(M.ALGO_HEATBATH, 1)
-    assert e.value.status == M.EINVAL
+    for algo in (M.ALGO_HEATBATH, M.ALGO_METROPOLIS, M.ALGO_WALKERS, 4):
+        with pytest.raises(M.MicsaError) as e:
+            g.sweep(algo, 1)
+        assert e.value.status == M.EINVAL
     with pytest.raises(M.MicsaError) as e:
         g.energy_tally()
     assert e.value.status == M.ESTATE
