@@ -1,12 +1,12 @@
 #!/usr/bin/env python3
-"""Spin updates/ns of MicSA and of the heat-bath baseline on one MI355X.
+"""Spin updates/ns of MicSA and of the heat-bath and Metropolis baselines on one MI355X.
 
 Workload (default): the large anneal -- one 512^3 lattice (134M spins) of the
 3D EA +-J model, byte layout, linear schedule T = 3.0 -> 0.2 over 10^4 sweeps,
 daemon refresh every 20 sweeps.  A step is one refresh period: the refresh
 and 20 sweeps (even half + odd half each, with the incremental energy
-tally).  --steps 500 is the whole anneal.  The heat bath runs the same steps
-on a second lattice from the same seed.  Prints one JSON line.
+tally).  --steps 500 is the whole anneal.  The heat bath and Metropolis run
+the same steps on lattices from the same seed.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -23,7 +23,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 # Algorithmic bytes per spin update (state one sweep must move, byte layout):
 # spin read+write 2 B, daemon read+write 2 B, couplings 3 bits = 0.375 B.
-BYTES_PER_UPDATE = {"micsa": 4.375, "heatbath": 2.375}
+BYTES_PER_UPDATE = {"micsa": 4.375, "heatbath": 2.375, "metropolis": 2.375}
 
 
 def log(msg: str) -> None:
@@ -62,7 +62,7 @@ def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None):
             lat.set_option(M.OPT_TILE_Y, tile[0])
             lat.set_option(M.OPT_TILE_Z, tile[1])
 
-    algo = M.ALGO_MICSA if algo_name == "micsa" else M.ALGO_HEATBATH
+    algo = {"micsa": M.ALGO_MICSA, "heatbath": M.ALGO_HEATBATH, "metropolis": M.ALGO_METROPOLIS}[algo_name]
     sched = M.Schedule(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
     P = w.period
     if warmup > 0:
@@ -83,7 +83,7 @@ def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None):
     t1.record(stream)
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
-    kind = M.TIME_SWEEP if algo == M.ALGO_MICSA else M.TIME_HEATBATH
+    kind = {M.ALGO_MICSA: M.TIME_SWEEP, M.ALGO_HEATBATH: M.TIME_HEATBATH, M.ALGO_METROPOLIS: M.TIME_METROPOLIS}[algo]
     k_ms, k_n = lat.timing(kind)
     r_ms, r_n = lat.timing(M.TIME_REFRESH)
     # property that holds at any size: the incremental tally equals the energy
@@ -125,6 +125,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-heatbath", action="store_true")
+    ap.add_argument("--no-metropolis", action="store_true")
     ap.add_argument("--tile", default="tune",
                     help="fused-sweep tile: 'tune' (autotuner, bit-exact gated), 'auto' (library default) or TY,TZ")
     ap.add_argument("--copy-ref-gib", type=float, default=0.0,
@@ -167,6 +168,11 @@ def main() -> int:
         log(f"heatbath: {w.name}, {sweeps} sweeps")
         hb = run_gpu(w, "heatbath", steps, args.warmup, stream)
         log(f"heatbath: {hb['ms']:.1f} ms")
+    mp = None
+    if not args.no_metropolis:
+        log(f"metropolis: {w.name}, {sweeps} sweeps")
+        mp = run_gpu(w, "metropolis", steps, args.warmup, stream)
+        log(f"metropolis: {mp['ms']:.1f} ms")
 
     value = updates / (mi["ms"] * 1e6)
     # dominant kernel: the sweep kernel; each launch updates one parity of every lattice
@@ -202,6 +208,11 @@ def main() -> int:
                            "ms_per_step": round(hb["ms"] / steps, 4), "kernel": hb["kernel"]}
         out["micsa_over_heatbath"] = round(hb["ms"] / mi["ms"], 3)
         out["checks"]["heatbath_tally_equals_energy"] = hb["tally_check"]
+    if mp is not None:
+        out["metropolis"] = {"value": round(updates / (mp["ms"] * 1e6), 2), "unit": "spin updates/ns",
+                             "ms_per_step": round(mp["ms"] / steps, 4), "kernel": mp["kernel"]}
+        out["micsa_over_metropolis"] = round(mp["ms"] / mi["ms"], 3)
+        out["checks"]["metropolis_tally_equals_energy"] = mp["tally_check"]
     if args.copy_ref_gib > 0:
         n = int(args.copy_ref_gib * (1 << 30))
         a = torch.ones(n, dtype=torch.uint8, device="cuda")

@@ -13,7 +13,8 @@
  * Storage (natural order, chosen for readability, not speed):
  *   site index     i = x + Lx*(y + Ly*z), N = Lx*Ly*Lz, periodic in all axes
  *   sigma[l][i]    spin bit, s = 1 - 2*sigma, l = sample*R + replica
- *   m[l][i]        daemon level, n = 4*m, m in {0,1,2,3}
+ *   m[l][a][i]     level of daemon (or walker) a = 0..gamma-1 of site i,
+ *                  n = 4*m, m in {0,1,2,3} (Sec. 2.2: gamma per spin)
  *   J[sample][i]   bits 0,1,2 = coupling bit j of the forward bonds
  *                  (i, i+e_x), (i, i+e_y), (i, i+e_z); J = 1 - 2*j
  *
@@ -22,7 +23,7 @@
  * hi32(seed)), with one counter per (stream, sample, replica, site, time):
  *   couplings  ctr = (i,      0,      0, 1<<24 | s)  j_mu(i) = out[mu] >> 31
  *   spins      ctr = (i>>2,   0,      r, 2<<24 | s)  sigma   = out[i&3] >> 31
- *   daemons    ctr = (i>>2,   rho,    r, 3<<24 | s)  u       = out[i&3]
+ *   daemons    ctr = (j>>2,   rho,    r, 3<<24 | s)  u       = out[j&3], j = a*N + i
  *   heat bath  ctr = (h>>2,   2k+p,   r, 4<<24 | s)  u       = out[h&3], h = i>>1
  *   Metropolis ctr = (h>>2,   2k+p,   r, 5<<24 | s)  u       = out[h&3], h = i>>1
  * (rho = refresh index, k = sweep index, p = parity being updated).  The
@@ -183,29 +184,33 @@ void oracle_daemon_thresholds(double T, uint64_t t[3])
     }
 }
 
-void oracle_refresh(int Lx, int Ly, int Lz, int S, int R, uint64_t seed, int64_t rho, double T,
-                    uint8_t *m)
+/* A refresh redraws all gamma daemons of every site; daemon a of site i */
+/* is drawn as number j = a*N + i of the lattice's daemon stream.        */
+void oracle_refresh(int Lx, int Ly, int Lz, int S, int R, int gamma, uint64_t seed, int64_t rho,
+                    double T, uint8_t *m)
 {
     geom g = mk(Lx, Ly, Lz);
     uint64_t t[3];
     oracle_daemon_thresholds(T, t);
     for (int s = 0; s < S; s++)
         for (int r = 0; r < R; r++)
-            for (int64_t i = 0; i < g.N; i++) {
-                uint64_t u = draw(seed, (uint32_t)(i >> 2), (uint32_t)rho, (uint32_t)r,
-                                  (uint32_t)(STREAM_DAEMON << 24) | (uint32_t)s, (int)(i & 3));
-                int level = 0;
-                for (int k = 0; k < 3; k++) level += (u >= t[k]);
-                m[((int64_t)s * R + r) * g.N + i] = (uint8_t)level;
-            }
+            for (int a = 0; a < gamma; a++)
+                for (int64_t i = 0; i < g.N; i++) {
+                    int64_t j = (int64_t)a * g.N + i;
+                    uint64_t u = draw(seed, (uint32_t)(j >> 2), (uint32_t)rho, (uint32_t)r,
+                                      (uint32_t)(STREAM_DAEMON << 24) | (uint32_t)s, (int)(j & 3));
+                    int level = 0;
+                    for (int k = 0; k < 3; k++) level += (u >= t[k]);
+                    m[(((int64_t)s * R + r) * gamma + a) * g.N + i] = (uint8_t)level;
+                }
 }
 
 /* ------------------------------------------------------------------ */
 /* MicSA half sweep (Sec. 2.3 eq. Creutz, Sec. 2.5 eq. flip-OK,        */
-/* procedure of Sec. 2.8.1 with gamma = 1 daemon per site): for every  */
-/* site x of the given parity, dH = H(flipped) - H = 2 s_x h_x; the     */
-/* flip is legal iff 0 <= n_x - dH <= 12, and then n_x -> n_x - dH.    */
-/* dE[l] accumulates the change of H^EA of lattice l.                  */
+/* procedure of Sec. 2.8.1): for every site x of the given parity,     */
+/* dH = H(flipped) - H = 2 s_x h_x; with the site's daemon n = n_{x,a} */
+/* of the family a in use, the flip is legal iff 0 <= n - dH <= 12,    */
+/* and then n -> n - dH.  dE[l] accumulates the change of H^EA.        */
 /* ------------------------------------------------------------------ */
 static int micsa_site(const geom *g, const uint8_t *Js, uint8_t *sig, uint8_t *dm, int64_t i)
 {
@@ -226,7 +231,7 @@ int oracle_micsa_site(int Lx, int Ly, int Lz, int64_t i, const uint8_t *J, uint8
     return micsa_site(&g, J, sigma, m, i);
 }
 
-void oracle_micsa_half(int Lx, int Ly, int Lz, int S, int R, int parity,
+void oracle_micsa_half(int Lx, int Ly, int Lz, int S, int R, int gamma, int alpha, int parity,
                        const uint8_t *J, uint8_t *sigma, uint8_t *m, int64_t *dE)
 {
     geom g = mk(Lx, Ly, Lz);
@@ -234,7 +239,7 @@ void oracle_micsa_half(int Lx, int Ly, int Lz, int S, int R, int parity,
         for (int r = 0; r < R; r++) {
             const uint8_t *Js = J + (int64_t)s * g.N;
             uint8_t *sig = sigma + ((int64_t)s * R + r) * g.N;
-            uint8_t *dm = m + ((int64_t)s * R + r) * g.N;
+            uint8_t *dm = m + (((int64_t)s * R + r) * gamma + alpha) * g.N;
             int64_t acc = 0;
 #pragma omp parallel for reduction(+ : acc) schedule(static)
             for (int64_t i = 0; i < g.N; i++) {
@@ -336,17 +341,18 @@ void oracle_metropolis_half(int Lx, int Ly, int Lz, int S, int R, uint64_t seed,
 
 /* ------------------------------------------------------------------ */
 /* Walkers (Sec. 2.6): a wandering step along direction dir (0..5 = +x, */
-/* -x, +y, -y, +z, -z) exchanges the auxiliary variable of every site x */
-/* of the given parity with that of its neighbour x + e_dir.  Forward-X */
-/* wandering is the two-timestep cycle: even sites at even timesteps,   */
-/* odd sites at odd timesteps.                                          */
+/* -x, +y, -y, +z, -z) exchanges walker `alpha` of every site x of the  */
+/* given parity with walker `alpha` of its neighbour x + e_dir.  A      */
+/* wandering cycle is two timesteps: sites of one parity at even        */
+/* timesteps, of the other at odd ones.                                 */
 /* ------------------------------------------------------------------ */
-void oracle_wander(int Lx, int Ly, int Lz, int S, int R, int dir, int parity, uint8_t *m)
+void oracle_wander(int Lx, int Ly, int Lz, int S, int R, int gamma, int alpha, int dir, int parity,
+                   uint8_t *m)
 {
     geom g = mk(Lx, Ly, Lz);
     static const int step[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
     for (int l = 0; l < S * R; l++) {
-        uint8_t *dm = m + (int64_t)l * g.N;
+        uint8_t *dm = m + ((int64_t)l * gamma + alpha) * g.N;
         for (int64_t i = 0; i < g.N; i++) {
             if (parity_of(&g, i) != parity) continue;
             int x, y, z;
@@ -384,7 +390,8 @@ void oracle_energy(int Lx, int Ly, int Lz, int S, int R, const uint8_t *J, const
         }
 }
 
-/* H^aux = sum_x n_x (eq. H-total, gamma = 1). */
+/* H^aux = sum_x sum_a n_{x,a} (eq. H-total); n counts every daemon of */
+/* a lattice (N * gamma).                                              */
 void oracle_daemon_energy(int64_t N, int L, const uint8_t *m, int64_t *D)
 {
     for (int l = 0; l < L; l++) {
@@ -464,25 +471,41 @@ double oracle_temperature(int kind, double T0, double T1, int64_t n_sweeps, int 
 /* ------------------------------------------------------------------ */
 enum { ALGO_MICSA = 0, ALGO_HEATBATH = 1, ALGO_WALKERS = 2, ALGO_METROPOLIS = 3 };
 
-int oracle_run(int Lx, int Ly, int Lz, int S, int R, uint64_t seed, int algo, int kind, double T0,
-               double T1, int64_t n_sweeps, int P, const double *table, int64_t table_len, int64_t k0,
-               int64_t n, int64_t stride, const uint8_t *J, uint8_t *sigma, uint8_t *m, int64_t *dE,
-               int64_t *E_log, int64_t *D_log)
+/* Wandering direction of walker family a (Sec. 2.8): forward X, Y, Z, */
+/* then backward X, Y, Z (direction codes as in oracle_wander).        */
+static const int walker_dir[6] = {0, 2, 4, 1, 3, 5};
+
+/* With gamma daemons or walkers per site (Sec. 2.8), a timestep is     */
+/* gamma sweeps: sweep k is sweep a = k mod gamma of timestep           */
+/* t = k / gamma and uses family a.  Refresh points and temperatures    */
+/* are those of timestep t (a refresh happens before the first sweep of */
+/* the timestep and redraws every family); the schedule's length counts */
+/* sweeps, its refreshes the timesteps that start in it.  Walkers       */
+/* wander once per timestep, after its last sweep, each family along    */
+/* its own direction, the parity of t choosing the half of the cycle.   */
+int oracle_run(int Lx, int Ly, int Lz, int S, int R, int gamma, uint64_t seed, int algo, int kind,
+               double T0, double T1, int64_t n_sweeps, int P, const double *table, int64_t table_len,
+               int64_t k0, int64_t n, int64_t stride, const uint8_t *J, uint8_t *sigma, uint8_t *m,
+               int64_t *dE, int64_t *E_log, int64_t *D_log)
 {
     int64_t N = (int64_t)Lx * Ly * Lz;
     int L = S * R;
     int64_t row = 0;
+    if (gamma < 1 || gamma > 6) return -1;
+    int64_t n_steps = (n_sweeps + gamma - 1) / gamma;
     for (int64_t k = k0; k < k0 + n; k++) {
-        int64_t rho = oracle_refresh_index(k, P);
-        double T = oracle_temperature(kind, T0, T1, n_sweeps, P, table, table_len, rho);
+        int64_t t = k / gamma;
+        int a = (int)(k % gamma);
+        int64_t rho = oracle_refresh_index(t, P);
+        double T = oracle_temperature(kind, T0, T1, n_steps, P, table, table_len, rho);
         if (!(T > 0.0) || isinf(T)) return -1;
         if (algo == ALGO_MICSA || algo == ALGO_WALKERS) {
-            if (oracle_is_refresh(k, P)) oracle_refresh(Lx, Ly, Lz, S, R, seed, rho, T, m);
-            oracle_micsa_half(Lx, Ly, Lz, S, R, 0, J, sigma, m, dE);
-            oracle_micsa_half(Lx, Ly, Lz, S, R, 1, J, sigma, m, dE);
-            /* gamma = 1 walker: one sweep per timestep t = k, then the part of
-               the forward-X cycle given by the parity of t (Sec. 2.8.1 step b) */
-            if (algo == ALGO_WALKERS) oracle_wander(Lx, Ly, Lz, S, R, 0, (int)(k & 1), m);
+            if (a == 0 && oracle_is_refresh(t, P)) oracle_refresh(Lx, Ly, Lz, S, R, gamma, seed, rho, T, m);
+            oracle_micsa_half(Lx, Ly, Lz, S, R, gamma, a, 0, J, sigma, m, dE);
+            oracle_micsa_half(Lx, Ly, Lz, S, R, gamma, a, 1, J, sigma, m, dE);
+            if (algo == ALGO_WALKERS && a == gamma - 1)
+                for (int f = 0; f < gamma; f++)
+                    oracle_wander(Lx, Ly, Lz, S, R, gamma, f, walker_dir[f], (int)(t & 1), m);
         } else if (algo == ALGO_HEATBATH) {
             oracle_heatbath_half(Lx, Ly, Lz, S, R, seed, k, 0, T, J, sigma, dE);
             oracle_heatbath_half(Lx, Ly, Lz, S, R, seed, k, 1, T, J, sigma, dE);
@@ -494,7 +517,7 @@ int oracle_run(int Lx, int Ly, int Lz, int S, int R, uint64_t seed, int algo, in
         }
         if (stride > 0 && (k - k0 + 1) % stride == 0) {
             if (E_log) oracle_energy(Lx, Ly, Lz, S, R, J, sigma, E_log + row * L);
-            if (D_log) oracle_daemon_energy(N, L, m, D_log + row * L);
+            if (D_log) oracle_daemon_energy(N * gamma, L, m, D_log + row * L);
             row++;
         }
     }

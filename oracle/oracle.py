@@ -8,7 +8,7 @@ comes from oracle.c, which follows the paper (arXiv 2506.16240) step by step.
 Arrays are in the oracle's natural order (site i = x + Lx*(y + Ly*z)):
   J[S, N]        bits 0..2 = forward-bond coupling bits j (J = 1 - 2j)
   sigma[S, R, N] spin bits (s = 1 - 2 sigma)
-  m[S, R, N]     daemon levels (n = 4m)
+  m[S, R, N]     daemon levels (n = 4m); m[S, R, gamma, N] with gamma > 1
 """
 from __future__ import annotations
 
@@ -64,17 +64,18 @@ def lib():
         L.oracle_daemon_thresholds.argtypes = [c.c_double, _u64p]
         L.oracle_heatbath_thresholds.argtypes = [c.c_double, _u64p]
         L.oracle_metropolis_thresholds.argtypes = [c.c_double, _u64p]
-        L.oracle_refresh.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
+        L.oracle_refresh.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
                                      c.c_int64, c.c_double, _u8p]
-        L.oracle_micsa_half.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int,
-                                        _u8p, _u8p, _u8p, _i64p]
+        L.oracle_micsa_half.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int,
+                                        c.c_int, _u8p, _u8p, _u8p, _i64p]
         L.oracle_micsa_site.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int64, _u8p, _u8p, _u8p]
         L.oracle_micsa_site.restype = c.c_int
         L.oracle_heatbath_half.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
                                            c.c_int64, c.c_int, c.c_double, _u8p, _u8p, _i64p]
         L.oracle_metropolis_half.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
                                              c.c_int64, c.c_int, c.c_double, _u8p, _u8p, _i64p]
-        L.oracle_wander.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, _u8p]
+        L.oracle_wander.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int,
+                                    c.c_int, _u8p]
         L.oracle_energy.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, _u8p, _u8p, _i64p]
         L.oracle_daemon_energy.argtypes = [c.c_int64, c.c_int, _u8p, _i64p]
         L.oracle_overlap.argtypes = [c.c_int64, c.c_int, c.c_int, c.c_int, c.c_int, _u8p, _i64p]
@@ -87,7 +88,7 @@ def lib():
         L.oracle_temperature.argtypes = [c.c_int, c.c_double, c.c_double, c.c_int64, c.c_int,
                                          c.c_void_p, c.c_int64, c.c_int64]
         L.oracle_temperature.restype = c.c_double
-        L.oracle_run.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64, c.c_int,
+        L.oracle_run.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64, c.c_int,
                                  c.c_int, c.c_double, c.c_double, c.c_int64, c.c_int, c.c_void_p,
                                  c.c_int64, c.c_int64, c.c_int64, c.c_int64, _u8p, _u8p, _u8p, _i64p,
                                  c.c_void_p, c.c_void_p]
@@ -151,10 +152,13 @@ class Schedule:
         t = np.ascontiguousarray(self.table, dtype=np.float64)
         return t, len(t)
 
-    def temperature(self, rho: int) -> float:
+    def temperature(self, rho: int, gamma: int = 1) -> float:
+        """Temperature of refresh rho; with gamma sweeps per timestep the
+        refreshes are counted over the timesteps that start in the schedule."""
         t, n = self._table_args()
         ptr = t.ctypes.data if t is not None else None
-        return float(lib().oracle_temperature(self.kind, self.T0, self.T1, self.n_sweeps, self.period,
+        n_steps = (self.n_sweeps + gamma - 1) // gamma
+        return float(lib().oracle_temperature(self.kind, self.T0, self.T1, n_steps, self.period,
                                               ptr, n, int(rho)))
 
     def is_refresh(self, k: int) -> bool:
@@ -163,19 +167,21 @@ class Schedule:
     def refresh_index(self, k: int) -> int:
         return int(lib().oracle_refresh_index(int(k), self.period))
 
-    def refresh_count(self) -> int:
-        return int(lib().oracle_refresh_count(self.n_sweeps, self.period))
+    def refresh_count(self, gamma: int = 1) -> int:
+        return int(lib().oracle_refresh_count((self.n_sweeps + gamma - 1) // gamma, self.period))
 
 
 @dataclass
 class Lattice:
-    """S samples x R replicas of an Lx x Ly x Lz periodic lattice, on the CPU."""
+    """S samples x R replicas of an Lx x Ly x Lz periodic lattice, on the CPU,
+    with gamma daemons (or walkers) per site."""
     Lx: int
     Ly: int
     Lz: int
     S: int = 1
     R: int = 1
     seed: int = 0
+    gamma: int = 1
     J: np.ndarray = field(init=False)
     sigma: np.ndarray = field(init=False)
     m: np.ndarray = field(init=False)
@@ -189,7 +195,10 @@ class Lattice:
         self.N = self.Lx * self.Ly * self.Lz
         self.J = np.zeros((self.S, self.N), np.uint8)
         self.sigma = np.zeros((self.S, self.R, self.N), np.uint8)
-        self.m = np.zeros((self.S, self.R, self.N), np.uint8)
+        if not 1 <= self.gamma <= 6:
+            raise ValueError("gamma must be 1..6")
+        self.m = np.zeros((self.S, self.R, self.N) if self.gamma == 1 else (self.S, self.R, self.gamma, self.N),
+                          np.uint8)
         d = self._dims()
         lib().oracle_init_couplings(*d[:4], self.seed, self.J)
         lib().oracle_init_spins(*d, self.seed, self.sigma)
@@ -200,15 +209,21 @@ class Lattice:
 
     # -- single steps ---------------------------------------------------
     def refresh(self, rho: int, T: float) -> None:
-        lib().oracle_refresh(*self._dims(), self.seed, int(rho), float(T), self.m)
+        lib().oracle_refresh(*self._dims(), self.gamma, self.seed, int(rho), float(T), self.m)
 
-    def micsa_half(self, parity: int) -> None:
+    def micsa_half(self, parity: int, alpha: int = 0) -> None:
+        """Half sweep with daemon family alpha."""
+        if not 0 <= alpha < self.gamma:
+            raise ValueError("alpha out of range")
         dE = np.zeros(self.S * self.R, np.int64)
-        lib().oracle_micsa_half(*self._dims(), int(parity), self.J, self.sigma, self.m, dE)
+        lib().oracle_micsa_half(*self._dims(), self.gamma, int(alpha), int(parity), self.J, self.sigma, self.m, dE)
         self.tally += dE
 
     def micsa_site(self, s: int, r: int, i: int) -> int:
-        """One elementary move on site i of lattice (s, r); returns dH (0 if rejected)."""
+        """One elementary move on site i of lattice (s, r) with its daemon of
+        family 0; returns dH (0 if rejected)."""
+        if self.gamma != 1:
+            raise ValueError("micsa_site is for gamma = 1")
         sig = np.ascontiguousarray(self.sigma[s, r])
         m = np.ascontiguousarray(self.m[s, r])
         dH = int(lib().oracle_micsa_site(self.Lx, self.Ly, self.Lz, int(i), np.ascontiguousarray(self.J[s]),
@@ -218,10 +233,12 @@ class Lattice:
         self.tally[s * self.R + r] += dH
         return dH
 
-    def wander(self, direction: int, parity: int) -> None:
-        """Exchange the auxiliary variable of every site of `parity` with its
+    def wander(self, direction: int, parity: int, alpha: int = 0) -> None:
+        """Exchange walker `alpha` of every site of `parity` with that of its
         neighbour along `direction` (0..5 = +x, -x, +y, -y, +z, -z)."""
-        lib().oracle_wander(*self._dims(), int(direction), int(parity), self.m)
+        if not 0 <= alpha < self.gamma:
+            raise ValueError("alpha out of range")
+        lib().oracle_wander(*self._dims(), self.gamma, int(alpha), int(direction), int(parity), self.m)
 
     def heatbath_half(self, k: int, parity: int, T: float) -> None:
         dE = np.zeros(self.S * self.R, np.int64)
@@ -243,7 +260,7 @@ class Lattice:
 
     def daemon_energy(self) -> np.ndarray:
         D = np.zeros(self.S * self.R, np.int64)
-        lib().oracle_daemon_energy(self.N, self.S * self.R, self.m, D)
+        lib().oracle_daemon_energy(self.N * self.gamma, self.S * self.R, self.m, D)
         return D
 
     def overlap(self, a: int, b: int) -> np.ndarray:
@@ -260,7 +277,7 @@ class Lattice:
         D_log = np.zeros((max(rows, 1), Lc), np.int64)
         dE = np.zeros(Lc, np.int64)
         t, tn = sched._table_args()
-        rc = lib().oracle_run(*self._dims(), self.seed, int(algo), sched.kind, sched.T0, sched.T1,
+        rc = lib().oracle_run(*self._dims(), self.gamma, self.seed, int(algo), sched.kind, sched.T0, sched.T1,
                               sched.n_sweeps, sched.period, t.ctypes.data if t is not None else None, tn,
                               self.k, int(n), int(stride), self.J, self.sigma, self.m, dE,
                               E_log.ctypes.data, D_log.ctypes.data)

@@ -583,3 +583,129 @@ def test_walkers_reach_canonical_equilibrium(T, period):
     E_log, _ = L.run(O.ALGO_WALKERS, O.Schedule(O.SCHED_CONST, T, T, n, period), n, 1)
     mean, err = _batch_mean(E_log[n // 5:].mean(axis=1))
     assert abs(mean - exact) <= 4.5 * err + 1e-9, (mean, exact, err)
+
+
+# ------------------------------------------------- gamma daemons / walkers
+def test_gamma_refresh_draws_independent_canonical_families():
+    """Every family of a gamma = 3 refresh follows eq. prob-daemons-walkers
+    (chi^2, 3 dof) and the families are independent of each other (chi^2 of
+    the 4 x 4 contingency table of two families at the same site, 9 dof;
+    and no family equals another)."""
+    T = 0.9
+    L = O.Lattice(16, 16, 16, 1, 2, seed=90, gamma=3)
+    L.refresh(4, T)
+    assert L.m.shape == (1, 2, 3, L.N)
+    b = 1.0 / T
+    p = np.array([math.exp(-4 * m * b) * (1 - math.exp(-4 * b)) / (1 - math.exp(-16 * b)) for m in range(4)])
+    for a in range(3):
+        counts = np.bincount(L.m[:, :, a].ravel(), minlength=4).astype(float)
+        n = counts.sum()
+        assert float(((counts - n * p) ** 2 / (n * p)).sum()) < 21.1
+    for a, c in ((0, 1), (0, 2), (1, 2)):
+        x, y = L.m[:, :, a].ravel().astype(int), L.m[:, :, c].ravel().astype(int)
+        tab = np.zeros((4, 4))
+        np.add.at(tab, (x, y), 1)
+        exp = np.outer(tab.sum(1), tab.sum(0)) / tab.sum()
+        ok = exp > 5
+        assert float(((tab - exp)[ok] ** 2 / exp[ok]).sum()) < 33.7  # p = 1e-4, 9 dof
+        assert not np.array_equal(x, y)
+
+
+def test_timestep_uses_daemon_family_alpha_on_its_sweep_alpha():
+    """Sec. 2.8: sweep alpha of a timestep uses daemon n_{x,alpha}.  Ferromagnet
+    (all J = +1) in a ground state, every daemon 0 except family f = 1 at
+    level 3.  By the Creutz rule (eq. flip-OK), flipping a site costs 12, so
+    only a daemon at 12 allows it: sweeps 0 leaves everything; sweep 1 flips
+    every even site (their family-1 daemons drop to 0) and no odd site (each
+    now gains 12, which a daemon at 12 cannot absorb); sweep 2 flips the even
+    sites back, each family-2 daemon of an even site absorbing 12; sweep 3
+    finds the ground state again with empty family-3 daemons."""
+    gamma, f = 4, 1
+    L = O.Lattice(4, 4, 6, 1, 2, seed=1, gamma=gamma)
+    L.J[:] = 0
+    L.sigma[:] = 0
+    L.m[:] = 0
+    L.m[:, :, f] = 3
+    L.tally = L.energy()
+    x, y, z = _coords(L)
+    even = ((x + y + z) & 1) == 0
+    L.k = gamma  # start of timestep 1: no refresh with period 100
+    E, _ = L.run(O.ALGO_MICSA, O.Schedule(O.SCHED_CONST, 1.0, 1.0, 100 * gamma, 100), gamma, 1)
+    N = L.N
+    assert E[:, 0].tolist() == [-3 * N, -3 * N + 12 * (N // 2), -3 * N, -3 * N]
+    assert (L.sigma == 0).all()
+    want = np.zeros_like(L.m)
+    want[:, :, 1, ~even] = 3   # family 1: odd daemons untouched, even ones spent
+    want[:, :, 2, even] = 3    # family 2: absorbed the even sites' flip back
+    assert np.array_equal(L.m, want)
+
+
+def test_gamma_conservation_between_refreshes():
+    """H^EA + H^aux (eq. H-total, all gamma families) changes only at the first
+    sweep of a refresh timestep."""
+    for gamma, algo in ((3, O.ALGO_MICSA), (6, O.ALGO_WALKERS)):
+        sched = O.Schedule(O.SCHED_LINEAR, 2.5, 0.6, 60, 3)
+        L = O.Lattice(8, 6, 4, 2, 2, seed=7, gamma=gamma)
+        E, D = L.run(algo, sched, 60, 1)
+        tot = E + D
+        for k in range(1, 60):
+            refresh = k % gamma == 0 and (k // gamma) % 3 == 0
+            if not refresh:
+                assert (tot[k] == tot[k - 1]).all(), (gamma, k)
+        assert (L.tally == L.energy()).all()
+
+
+def test_six_walker_families_wander_along_their_own_axes():
+    """Sec. 2.6 and 2.8: with 6 walkers per spin, family alpha wanders forward
+    along X, Y, Z (alpha = 0, 1, 2) and backward along X, Y, Z (3, 4, 5), once
+    per timestep.  In the timestep t the sites of parity t mod 2 exchange with
+    their neighbour, so a walker that starts at timestep t0 on a site of
+    parity t0 mod 2 moves one site along its direction every timestep, the
+    others one site against it.  Spins cannot move here (ferromagnet ground
+    state, levels at most 2), so only the wandering acts."""
+    gamma = 6
+    Lx, Ly, Lz = 4, 6, 8
+    L = O.Lattice(Lx, Ly, Lz, 1, 1, seed=2, gamma=gamma)
+    L.J[:] = 0
+    L.sigma[:] = 0
+    rng = np.random.default_rng(5)
+    L.m[:] = rng.integers(0, 3, L.m.shape, dtype=np.uint8)
+    L.tally = L.energy()
+    m0 = L.m[0, 0].copy()
+    t0, nt = 1, 5
+    L.k = gamma * t0
+    L.run(O.ALGO_WALKERS, O.Schedule(O.SCHED_CONST, 1.0, 1.0, 100 * gamma, 100), gamma * nt, 0)
+    assert (L.sigma == 0).all()
+    x, y, z = _coords(L)
+    par = (x + y + z) & 1
+    axes = [(1, 0), (1, 1), (1, 2), (-1, 0), (-1, 1), (-1, 2)]  # (sign, axis) of family alpha
+    for alpha, (sgn, axis) in enumerate(axes):
+        d = sgn * nt * np.where(par == (t0 & 1), 1, -1)
+        pos = [x, y, z]
+        side = (Lx, Ly, Lz)[axis]
+        pos[axis] = (pos[axis] + d) % side
+        dest = pos[0] + Lx * (pos[1] + Ly * pos[2])
+        want = np.empty_like(m0[alpha])
+        want[dest] = m0[alpha]
+        assert np.array_equal(L.m[0, 0, alpha], want), alpha
+
+
+@pytest.mark.parametrize("shape,T,period,gamma,algo", [
+    ((2, 2, 4), 1.5, 2, 2, O.ALGO_MICSA),
+    ((2, 2, 4), 2.0, 1, 4, O.ALGO_MICSA),
+    ((2, 2, 2), 1.5, 1, 6, O.ALGO_WALKERS),
+    ((2, 2, 4), 2.0, 2, 6, O.ALGO_WALKERS),
+])
+def test_gamma_runs_reach_canonical_equilibrium(shape, T, period, gamma, algo):
+    """With gamma refreshed daemons (or wandering walkers) per spin the
+    stationary measure is still the canonical one (Sec. 2.2, 2.7): long runs
+    reproduce the exact <H> from enumeration."""
+    Lx, Ly, Lz = shape
+    R = 32
+    L = O.Lattice(Lx, Ly, Lz, 1, R, seed=700 + gamma + period, gamma=gamma)
+    g = O.density_of_states(Lx, Ly, Lz, L.J[0])
+    exact = O.canonical_mean_energy(g, L.N, T)
+    n = 6000
+    E_log, _ = L.run(algo, O.Schedule(O.SCHED_CONST, T, T, n, period), n, 1)
+    mean, err = _batch_mean(E_log[n // 5:].mean(axis=1))
+    assert abs(mean - exact) <= 4.5 * err + 1e-9, (mean, exact, err)

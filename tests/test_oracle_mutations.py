@@ -15,7 +15,8 @@ SRC = os.path.join(ROOT, "oracle", "oracle.c")
 
 # (name, original text, planted text, pins that must catch it)
 MUTATIONS = [
-    ("flip window upper bound", "n - dH <= 12", "n - dH < 12", "local_move or conservation"),
+    ("flip window upper bound", "if (n - dH >= 0 && n - dH <= 12) {", "if (n - dH >= 0 && n - dH < 12) {",
+     "local_move or conservation"),
     ("sign of dH", "int dH = 2 * spin(sig[i]) * local_field(g, Js, sig, i);",
      "int dH = -2 * spin(sig[i]) * local_field(g, Js, sig, i);", "local_move or conservation"),
     ("dropped backward bond", "        h += coupling(J[bwd[mu]], mu) * spin(sig[bwd[mu]]);\n", "",
@@ -37,8 +38,14 @@ MUTATIONS = [
     ("overlap product", "q += spin(sa[i]) * spin(sb[i]);", "q += spin(sa[i]) * spin(sa[i]);", "overlap"),
     ("linear schedule end", "return T0 * (1.0 - f) + T1 * f;", "return T0 * (1.0 - f) + T1;", "schedule"),
     ("log refresh points", "return ((k + 1) & k) == 0;", "return (k & (k - 1)) == 0;", "schedule"),
-    ("walker cycle parity", "oracle_wander(Lx, Ly, Lz, S, R, 0, (int)(k & 1), m);",
-     "oracle_wander(Lx, Ly, Lz, S, R, 0, (int)((k + 1) & 1), m);", "walkers"),
+    ("walker cycle parity", "walker_dir[f], (int)(t & 1), m);", "walker_dir[f], (int)((t + 1) & 1), m);",
+     "walkers or wander"),
+    ("daemon family draw index", "int64_t j = (int64_t)a * g.N + i;", "int64_t j = i;", "gamma_refresh"),
+    ("daemon family in use", "uint8_t *dm = m + (((int64_t)s * R + r) * gamma + alpha) * g.N;",
+     "uint8_t *dm = m + (((int64_t)s * R + r) * gamma) * g.N;", "family_alpha or gamma"),
+    ("walker family directions", "{0, 2, 4, 1, 3, 5}", "{0, 2, 4, 1, 5, 3}", "wander_along"),
+    ("refresh on every sweep of a timestep", "if (a == 0 && oracle_is_refresh(t, P))", "if (oracle_is_refresh(t, P))",
+     "gamma_conservation"),
     ("Metropolis tally sign", "sig[i] ^= 1;\n                    acc += dH;", "sig[i] ^= 1;\n                    acc -= dH;",
      "metropolis"),
     ("Metropolis exponent", "floor(exp(-beta * (double)dH) * 4294967296.0)",
@@ -52,7 +59,7 @@ MUTATIONS = [
 @pytest.mark.parametrize("name,orig,planted,pins", MUTATIONS, ids=[m[0] for m in MUTATIONS])
 def test_planted_mistake_is_caught(name, orig, planted, pins, tmp_path):
     src = open(SRC).read()
-    assert src.count(orig) >= 1, f"mutation target not found: {orig!r}"
+    assert src.count(orig) == 1, f"mutation target not found or not unique: {orig!r}"
     mutated = src.replace(orig, planted, 1)
     c = tmp_path / "oracle_mut.c"
     c.write_text(mutated)
