@@ -54,11 +54,12 @@ enum micsa_layout {
 };
 
 enum micsa_algo {
-    MICSA_ALGO_MICSA = 0,    /* daemon update, Sec. 2.3-2.8 with gamma = 1 */
+    MICSA_ALGO_MICSA = 0,    /* daemon update, Sec. 2.3-2.8 (gamma daemons per site) */
     MICSA_ALGO_HEATBATH = 1, /* canonical heat bath, Sec. 2.1 */
-    MICSA_ALGO_WALKERS = 2,  /* gamma = 1 walker per site with forward-X wandering (Sec. 2.6, 2.8):
-                                each sweep t is followed by the exchange of the walkers of the
-                                sites of parity t mod 2 with their +x neighbours (byte layout) */
+    MICSA_ALGO_WALKERS = 2,  /* gamma walkers per site with wandering (Sec. 2.6, 2.8): after the
+                                last sweep of timestep t, walker family a of every site of
+                                parity t mod 2 is exchanged with that of its neighbour along
+                                +x, +y, +z, -x, -y, -z for a = 0..5 (byte layout) */
     MICSA_ALGO_METROPOLIS = 3 /* canonical Metropolis, the comparison of Sec. 4 (Table 3): the flip is
                                  accepted with probability min(1, exp(-beta dH)) (byte layout) */
 };
@@ -78,6 +79,12 @@ typedef struct micsa_params {
     int32_t n_samples;     /* coupling realisations, 1 .. 2^24 - 1 */
     int32_t n_replicas;    /* replicas per sample sharing the couplings (Sec. 3), >= 1 */
     int32_t layout;        /* enum micsa_layout */
+    int32_t gamma;         /* daemons (or walkers) per site, 1..6 (0 means 1); > 1 needs the byte
+                              layout.  A timestep is gamma sweeps; sweep k is sweep a = k mod gamma of
+                              timestep k / gamma and uses family a (Sec. 2.8).  Refresh points and
+                              refresh temperatures are counted in timesteps; a refresh redraws
+                              every family, daemon a of site i as number a*N + i of the daemon
+                              stream.  n_sweeps of the schedule still counts sweeps. */
     uint64_t seed;         /* Philox key */
 } micsa_params;
 
@@ -105,7 +112,7 @@ const char* micsa_last_error(const micsa_ctx* ctx);
    hipStream_t (NULL = the null stream) on which every later call enqueues
    its work.  On success *out owns all device memory; on failure *out is
    NULL and nothing is leaked.
-   Errors: EINVAL (bad sides/counts/layout), ENOMEM, EHIP. */
+   Errors: EINVAL (bad sides/counts/layout/gamma), ENOMEM, EHIP. */
 int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out);
 
 /* Synchronise the stream and free everything.  NULL is accepted. */
@@ -126,7 +133,7 @@ int micsa_set_schedule(micsa_ctx* ctx, const micsa_schedule* s);
 int micsa_sweep(micsa_ctx* ctx, int32_t algo, int64_t n);
 
 /* As micsa_sweep, and after every `stride` sweeps records the from-scratch
-   H^EA (eq. Hamiltonian) and H^aux = sum_x n_x (eq. H-total) of each
+   H^EA (eq. Hamiltonian) and H^aux = sum_x sum_a n_{x,a} (eq. H-total) of each
    lattice.  E_log and D_log are host arrays [n/stride][S*R] (either may be
    NULL), filled when the call returns (the call synchronises). */
 int micsa_sweep_logged(micsa_ctx* ctx, int32_t algo, int64_t n, int64_t stride, int64_t* E_log,
@@ -144,7 +151,7 @@ int micsa_read_demon_energy(micsa_ctx* ctx, int64_t* D); /* [S*R] H^aux = 4 sum 
    unless 0 <= a, b < R and a != b. */
 int micsa_read_overlap(micsa_ctx* ctx, int32_t a, int32_t b, int64_t* Q);
 int micsa_read_spins(micsa_ctx* ctx, uint8_t* sigma);    /* [S][R][N] */
-int micsa_read_demons(micsa_ctx* ctx, uint8_t* m);       /* [S][R][N] */
+int micsa_read_demons(micsa_ctx* ctx, uint8_t* m);       /* [S][R][gamma][N] */
 int micsa_read_couplings(micsa_ctx* ctx, uint8_t* j);    /* [S][N] forward-bond bits 0..2 */
 int micsa_get_counters(micsa_ctx* ctx, int64_t* k, int64_t* rho); /* next sweep, its refresh index */
 
@@ -164,7 +171,7 @@ int micsa_get_metropolis_thresholds(micsa_ctx* ctx, int64_t rho, uint64_t theta[
 /* Writes (synchronous).  Spins reset the energy tally to the from-scratch
    energy.  Daemon levels above 3 are rejected with EINVAL. */
 int micsa_write_spins(micsa_ctx* ctx, const uint8_t* sigma); /* [S][R][N] */
-int micsa_write_demons(micsa_ctx* ctx, const uint8_t* m);    /* [S][R][N] */
+int micsa_write_demons(micsa_ctx* ctx, const uint8_t* m);    /* [S][R][gamma][N] */
 
 /* Per-kernel timing with HIP events on the context's stream.  While
    enabled every kernel launch is bracketed by an event pair; the sums are

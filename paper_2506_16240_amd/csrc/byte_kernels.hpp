@@ -132,17 +132,21 @@ __global__ void k_init_spins(Geom g, uint8_t* __restrict__ spin)
 }
 
 // Daemon refresh (Sec. 2.7, eq. prob-daemons-walkers): m = #{k : u >= t_k}.
-
+// Every family of every site is redrawn: grid.y runs over (lattice, family)
+// pairs d = l * gamma + a, and daemon a of site i is number j = a*N + i of
+// the lattice's daemon stream (N is a multiple of 8, so j & 3 = i & 3).
 __global__ void k_refresh(Geom g, uint8_t* __restrict__ dem, uint32_t rho, DaemonThresholds th)
 {
-    const int l = blockIdx.y;
+    const int d = blockIdx.y;
+    const int l = d / g.gamma, fam = d - l * g.gamma;
     const int s = l / g.R, r = l % g.R;
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= g.Nh / 4) return;
     const int64_t i0 = 8 * t;
+    const uint32_t c0 = (uint32_t)(i0 >> 2) + (uint32_t)fam * (uint32_t)(g.Nh / 2);  // (a*N + i0) >> 2
     const uint32_t sw = stream_word(kStreamDaemon, (uint32_t)s);
-    const u32x4 a = philox10((uint32_t)(i0 >> 2), rho, (uint32_t)r, sw, g.key0, g.key1);
-    const u32x4 b = philox10((uint32_t)(i0 >> 2) + 1u, rho, (uint32_t)r, sw, g.key0, g.key1);
+    const u32x4 a = philox10(c0, rho, (uint32_t)r, sw, g.key0, g.key1);
+    const u32x4 b = philox10(c0 + 1u, rho, (uint32_t)r, sw, g.key0, g.key1);
     uint32_t we, wo;
     split8(g, i0, a, b,
            [&](uint32_t u) {
@@ -150,8 +154,8 @@ __global__ void k_refresh(Geom g, uint8_t* __restrict__ dem, uint32_t rho, Daemo
                return (uint32_t)(v >= th.t0) + (uint32_t)(v >= th.t1) + (uint32_t)(v >= th.t2);
            },
            we, wo);
-    reinterpret_cast<uint32_t*>(dem + ((int64_t)l * 2 + 0) * g.Nh)[t] = we;
-    reinterpret_cast<uint32_t*>(dem + ((int64_t)l * 2 + 1) * g.Nh)[t] = wo;
+    reinterpret_cast<uint32_t*>(dem + ((int64_t)d * 2 + 0) * g.Nh)[t] = we;
+    reinterpret_cast<uint32_t*>(dem + ((int64_t)d * 2 + 1) * g.Nh)[t] = wo;
 }
 
 __device__ __forceinline__ bool sweep_is_refresh(int64_t k, int32_t P)
@@ -166,8 +170,8 @@ __device__ __forceinline__ int64_t sweep_refresh_index(int64_t k, int32_t P)
 }
 
 // Refresh whose sweep index comes from device memory (*dk), for replayable
-// graphs: does nothing unless sweep *dk is a refresh point; thresholds from
-// the schedule's table.
+// graphs (gamma = 1): does nothing unless sweep *dk is a refresh point;
+// thresholds from the schedule's table.
 __global__ void k_refresh_dev(Geom g, uint8_t* __restrict__ dem, const int64_t* __restrict__ dk, int32_t period,
                               const DaemonThresholds* __restrict__ dth)
 {
@@ -224,7 +228,7 @@ template <int P>
 __global__ void __launch_bounds__(256) k_micsa_half(Geom g, uint8_t* __restrict__ spin,
                                                     uint8_t* __restrict__ dem,
                                                     const uint32_t* __restrict__ J,
-                                                    unsigned long long* __restrict__ tally)
+                                                    unsigned long long* __restrict__ tally, int fam)
 {
     const int l = blockIdx.y;
     const int s = l / g.R;
@@ -234,7 +238,7 @@ __global__ void __launch_bounds__(256) k_micsa_half(Geom g, uint8_t* __restrict_
         const int row = (int)(w / (uint32_t)g.Wr), c = (int)(w - (uint32_t)row * (uint32_t)g.Wr);
         uint32_t* own = reinterpret_cast<uint32_t*>(spin + ((int64_t)l * 2 + P) * g.Nh);
         const uint32_t* oth = reinterpret_cast<const uint32_t*>(spin + ((int64_t)l * 2 + (1 - P)) * g.Nh);
-        uint32_t* dm = reinterpret_cast<uint32_t*>(dem + ((int64_t)l * 2 + P) * g.Nh);
+        uint32_t* dm = reinterpret_cast<uint32_t*>(dem + (((int64_t)l * g.gamma + fam) * 2 + P) * g.Nh);
         const Nbhd n = gather<P>(g, oth, J + (int64_t)s * (g.Nh / 4), row, c);
         uint32_t S = own[w], M = dm[w];
         micsa_word(S, M, n, dE);
@@ -326,11 +330,16 @@ __global__ void __launch_bounds__(256) k_heatbath_half(Geom g, uint8_t* __restri
 // s + e_dir.  Written as two gathers into the other buffer: a site of parity
 // p takes the level at s + e_dir, a site of parity 1-p the level at t - e_dir
 // (both sites of the other parity).  Thread per word position (row, c) of
-// both parity arrays.
+// both parity arrays; grid.y over (lattice, family) pairs d = l*gamma + a.
+// Family a wanders along kWalkerDir[a] (Sec. 2.8: forward X, Y, Z, then
+// backward X, Y, Z).
+__constant__ const int kWalkerDir[6] = {kPx, kPy, kPz, kMx, kMy, kMz};
+
 __global__ void __launch_bounds__(256) k_wander(Geom g, const uint8_t* __restrict__ dem_in,
-                                                uint8_t* __restrict__ dem_out, int dir, int p)
+                                                uint8_t* __restrict__ dem_out, int p)
 {
-    const int l = blockIdx.y;
+    const int l = blockIdx.y;  // (lattice, family) pair
+    const int dir = kWalkerDir[l % g.gamma];
     const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= (uint32_t)g.rows * (uint32_t)g.Wr) return;
     const int row = (int)(w / (uint32_t)g.Wr), c = (int)(w - (uint32_t)row * (uint32_t)g.Wr);

@@ -11,6 +11,7 @@
 //   the adjacent rows of the other parity, and the two x neighbours at k and
 //   k +- 1 of the same row -- so 4 sites packed in a 32-bit word see their
 //   neighbours as whole words (or one byte-shifted word).
+//   daemon[l][a][p][h] for the gamma daemon (walker) families a of a site.
 //   Couplings: every bond joins an even and an odd site, so each bond is
 //   stored once, with its even end: one byte per even site whose bit d is the
 //   coupling bit of its bond in direction d = +x, -x, +y, -y, +z, -z
@@ -32,6 +33,7 @@ struct Geom {
     int64_t Nh;    // N / 2: sites of one parity
     int32_t S, R;  // samples, replicas per sample
     uint32_t key0, key1;
+    int32_t gamma;  // daemons (walkers) per site: daemon arrays are [S*R][gamma][2][Nh]
 };
 
 // Daemon levels are drawn as m = #{k : u >= t_k} from a 32-bit uniform u,

@@ -34,6 +34,7 @@ struct Schedule {
     int32_t period = 1;
     double T0 = 1.0, T1 = 1.0;
     int64_t n_sweeps = 0;
+    int64_t n_steps = 0;  // timesteps that start in [0, n_sweeps): ceil(n_sweeps / gamma)
     std::vector<double> table;
 };
 
@@ -44,6 +45,7 @@ struct micsa_ctx {
     hipStream_t stream = nullptr;
     Geom g{};
     int L = 0;  // lattices = S * R
+    int gamma = 1;  // daemons (walkers) per site; a timestep is gamma sweeps
     // device state (byte layout), double-buffered: the fused sweep reads the
     // current buffers and writes the alternate ones, then the two swap
     uint8_t* spin = nullptr;  // [L][2][Nh] current
@@ -112,9 +114,11 @@ int64_t refresh_index(int64_t k, int32_t P)
     return rho;
 }
 
+// Refreshes over the timesteps of the schedule (Sec. 2.8: with gamma
+// daemons per site a timestep is gamma sweeps; refresh points count timesteps).
 int64_t refresh_count(const Schedule& s)
 {
-    return s.n_sweeps <= 0 ? 0 : refresh_index(s.n_sweeps - 1, s.period) + 1;
+    return s.n_steps <= 0 ? 0 : refresh_index(s.n_steps - 1, s.period) + 1;
 }
 
 double temperature(const Schedule& s, int64_t rho)
@@ -282,8 +286,8 @@ int enqueue_lane_count(micsa_ctx* c, unsigned long long* dst, int ra, int rb)
 int launch_refresh(micsa_ctx* c, int64_t rho, double T)
 {
     TimedLaunch t(c, kTimeRefresh);
-    k_refresh<<<grid_for(c->g.Nh / 4, c->L), kBlock, 0, c->stream>>>(c->g, c->dem, (uint32_t)rho,
-                                                                      daemon_thresholds(T));
+    k_refresh<<<grid_for(c->g.Nh / 4, c->L * c->gamma), kBlock, 0, c->stream>>>(c->g, c->dem, (uint32_t)rho,
+                                                                                 daemon_thresholds(T));
     return check_launch(c, "k_refresh");
 }
 
@@ -295,7 +299,10 @@ constexpr size_t kResidentLdsMax = 150 * 1024;
 constexpr int kResidentBlock = 512;
 constexpr int64_t kResidentChunk = 2048;  // sweeps per resident launch
 
-bool resident_eligible(const micsa_ctx* c) { return !c->bit && (size_t)c->g.Nh * 3 <= kResidentLdsMax; }
+bool resident_eligible(const micsa_ctx* c)
+{
+    return !c->bit && c->gamma == 1 && (size_t)c->g.Nh * 3 <= kResidentLdsMax;
+}
 
 bool use_resident(const micsa_ctx* c)
 {
@@ -305,7 +312,7 @@ bool use_resident(const micsa_ctx* c)
 
 bool fused_eligible(const micsa_ctx* c)
 {
-    return !c->bit && c->p.Lx % 32 == 0 && 5 * (c->p.Lx / 32) <= 1024;
+    return !c->bit && c->gamma == 1 && c->p.Lx % 32 == 0 && 5 * (c->p.Lx / 32) <= 1024;
 }
 
 bool use_fused(const micsa_ctx* c)
@@ -373,18 +380,21 @@ int launch_fused_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
     return MICSA_OK;
 }
 
-int launch_micsa_sweep(micsa_ctx* c)
+// Both halves with daemon family fam.
+int launch_micsa_sweep(micsa_ctx* c, int fam)
 {
     const int64_t words = (int64_t)c->g.rows * c->g.Wr;
     {
         TimedLaunch t(c, kTimeSweep);
-        k_micsa_half<0><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally);
+        k_micsa_half<0><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally,
+                                                                          fam);
     }
     int st = check_launch(c, "k_micsa_half<0>");
     if (st) return st;
     {
         TimedLaunch t(c, kTimeSweep);
-        k_micsa_half<1><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally);
+        k_micsa_half<1><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally,
+                                                                          fam);
     }
     return check_launch(c, "k_micsa_half<1>");
 }
@@ -462,7 +472,7 @@ int enqueue_level_sum(micsa_ctx* c, unsigned long long* dst)
     int st = zero_slots(c, dst, c->L);
     if (st) return st;
     TimedLaunch t(c, kTimeReduce);
-    const int64_t wpl = 2 * c->g.Nh / 4;
+    const int64_t wpl = (int64_t)c->gamma * 2 * c->g.Nh / 4;  // every family of the lattice
     k_level_sum<<<grid_for(wpl, c->L), kBlock, 0, c->stream>>>(wpl, reinterpret_cast<const uint32_t*>(c->dem),
                                                                dst);
     return check_launch(c, "k_level_sum");
@@ -542,7 +552,7 @@ constexpr int kGraphSweeps = 16;
 
 bool use_graph(const micsa_ctx* c)
 {
-    return c->use_graphs && !c->timing && (c->bit || (!use_resident(c) && !use_fused(c)));
+    return c->use_graphs && !c->timing && c->gamma == 1 && (c->bit || (!use_resident(c) && !use_fused(c)));
 }
 
 // One sweep in device-counter form on stream st.
@@ -560,8 +570,8 @@ int enqueue_dev_sweep(micsa_ctx* c, int32_t algo, hipStream_t st)
         const int64_t words = (int64_t)c->g.rows * c->g.Wr;
         if (algo == MICSA_ALGO_MICSA) {
             k_refresh_dev<<<grid_for(c->g.Nh / 4, c->L), kBlock, 0, st>>>(c->g, c->dem, c->d_k, P, c->d_dth);
-            k_micsa_half<0><<<grid_for(words, c->L), kBlock, 0, st>>>(c->g, c->spin, c->dem, c->J, c->tally);
-            k_micsa_half<1><<<grid_for(words, c->L), kBlock, 0, st>>>(c->g, c->spin, c->dem, c->J, c->tally);
+            k_micsa_half<0><<<grid_for(words, c->L), kBlock, 0, st>>>(c->g, c->spin, c->dem, c->J, c->tally, 0);
+            k_micsa_half<1><<<grid_for(words, c->L), kBlock, 0, st>>>(c->g, c->spin, c->dem, c->J, c->tally, 0);
         } else {
             const HeatBathThresholds none{};
             enqueue_canonical_half<0>(c, algo, st, 0, none, c->d_k);
@@ -625,13 +635,14 @@ int check_sweep(micsa_ctx* c, int32_t algo, int64_t n)
     return MICSA_OK;
 }
 
-// Wandering step of the walkers after sweep k: forward-X, parity of k.
-int launch_wander(micsa_ctx* c, int64_t k)
+// Wandering step of every walker family at the end of timestep t (each
+// family along its own direction, the half of the cycle given by t's parity).
+int launch_wander(micsa_ctx* c, int64_t t)
 {
     const int64_t words = (int64_t)c->g.rows * c->g.Wr;
     {
-        TimedLaunch t(c, kTimeSweep);
-        k_wander<<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->dem, c->dem_alt, kPx, (int)(k & 1));
+        TimedLaunch tl(c, kTimeSweep);
+        k_wander<<<grid_for(words, c->L * c->gamma), kBlock, 0, c->stream>>>(c->g, c->dem, c->dem_alt, (int)(t & 1));
     }
     const int st = check_launch(c, "k_wander");
     if (st) return st;
@@ -649,22 +660,25 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
         if (use_graph(c) && n >= kGraphSweeps) return sweep_graph(c, algo, n);
     }
     for (int64_t i = 0; i < n; ++i) {
+        // sweep k is sweep fam of timestep t (Sec. 2.8)
         const int64_t k = c->k;
-        const int64_t rho = refresh_index(k, c->sched.period);
+        const int64_t t = k / c->gamma;
+        const int fam = (int)(k - t * c->gamma);
+        const int64_t rho = refresh_index(t, c->sched.period);
         const double T = temperature(c->sched, rho);
         if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
         int st;
         if (algo == MICSA_ALGO_MICSA || algo == MICSA_ALGO_WALKERS) {
-            const bool refresh = is_refresh(k, c->sched.period);
+            const bool refresh = fam == 0 && is_refresh(t, c->sched.period);
             if (c->bit) {
                 if ((st = launch_bitplane_sweep(c, refresh, rho, T))) return st;
             } else if (use_fused(c)) {
                 if ((st = launch_fused_sweep(c, refresh, rho, T))) return st;
             } else {
                 if (refresh && (st = launch_refresh(c, rho, T))) return st;
-                if ((st = launch_micsa_sweep(c))) return st;
+                if ((st = launch_micsa_sweep(c, fam))) return st;
             }
-            if (algo == MICSA_ALGO_WALKERS && (st = launch_wander(c, k))) return st;
+            if (algo == MICSA_ALGO_WALKERS && fam == c->gamma - 1 && (st = launch_wander(c, t))) return st;
         } else {
             if ((st = launch_canonical_sweep(c, algo, k, T))) return st;
         }
@@ -701,6 +715,19 @@ void free_all(micsa_ctx* c)
         }
 }
 
+// Parameters a context accepts (include/micsa.h, micsa_create).
+bool params_ok(const micsa_params* p)
+{
+    if (p->Lx < 8 || p->Lx % 8 || p->Ly < 2 || p->Ly % 2 || p->Lz < 2 || p->Lz % 2) return false;
+    if (p->n_samples < 1 || p->n_samples >= (1 << 24) || p->n_replicas < 1) return false;
+    if (p->layout != MICSA_LAYOUT_BYTE && p->layout != MICSA_LAYOUT_BITPLANE) return false;
+    const int64_t N = (int64_t)p->Lx * p->Ly * p->Lz;
+    if (N >= ((int64_t)1 << 32) || (int64_t)p->n_samples * p->n_replicas >= (1 << 16)) return false;
+    const int gamma = p->gamma == 0 ? 1 : p->gamma;
+    if (gamma < 1 || gamma > 6 || (gamma > 1 && p->layout != MICSA_LAYOUT_BYTE)) return false;
+    return (int64_t)gamma * N / 4 < ((int64_t)1 << 32);  // daemon counters (a*N + i) >> 2 fit 32 bits
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -726,15 +753,15 @@ int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
     if (!out) return MICSA_EINVAL;
     *out = nullptr;
     if (!p) return MICSA_EINVAL;
-    if (p->Lx < 8 || p->Lx % 8 || p->Ly < 2 || p->Ly % 2 || p->Lz < 2 || p->Lz % 2) return MICSA_EINVAL;
-    if (p->n_samples < 1 || p->n_samples >= (1 << 24) || p->n_replicas < 1) return MICSA_EINVAL;
-    if (p->layout != MICSA_LAYOUT_BYTE && p->layout != MICSA_LAYOUT_BITPLANE) return MICSA_EINVAL;
+    if (!params_ok(p)) return MICSA_EINVAL;
     const int64_t N = (int64_t)p->Lx * p->Ly * p->Lz;
-    if (N >= ((int64_t)1 << 32) || (int64_t)p->n_samples * p->n_replicas >= (1 << 16)) return MICSA_EINVAL;
+    const int gamma = p->gamma == 0 ? 1 : p->gamma;
 
     micsa_ctx* c = new (std::nothrow) micsa_ctx();
     if (!c) return MICSA_ENOMEM;
     c->p = *p;
+    c->p.gamma = gamma;
+    c->gamma = gamma;
     c->stream = (hipStream_t)hip_stream;
     c->L = p->n_samples * p->n_replicas;
     c->bit = p->layout == MICSA_LAYOUT_BITPLANE;
@@ -751,16 +778,18 @@ int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
     g.R = p->n_replicas;
     g.key0 = (uint32_t)p->seed;
     g.key1 = (uint32_t)(p->seed >> 32);
+    g.gamma = gamma;
 
     const size_t nred = (size_t)std::max(c->L, p->n_samples);
     bool ok = hipMalloc(&c->tally, (size_t)c->L * kSlots * 8) == hipSuccess &&
               hipMalloc(&c->red, nred * kSlots * 8) == hipSuccess;
     const size_t state = (size_t)c->L * 2 * (size_t)g.Nh;
+    const size_t dstate = state * (size_t)gamma;  // every daemon family
     const size_t words = (size_t)c->G * p->n_replicas * 2 * (size_t)g.Nh;
     if (ok && !c->bit) {
         const size_t jw = (size_t)p->n_samples * (size_t)g.Nh / 4;
-        ok = hipMalloc(&c->spin, state) == hipSuccess && hipMalloc(&c->dem, state) == hipSuccess &&
-             hipMalloc(&c->spin_alt, state) == hipSuccess && hipMalloc(&c->dem_alt, state) == hipSuccess &&
+        ok = hipMalloc(&c->spin, state) == hipSuccess && hipMalloc(&c->dem, dstate) == hipSuccess &&
+             hipMalloc(&c->spin_alt, state) == hipSuccess && hipMalloc(&c->dem_alt, dstate) == hipSuccess &&
              hipMalloc(&c->J, jw * 4) == hipSuccess;
     } else if (ok) {
         ok = hipMalloc(&c->bspin, words * 8) == hipSuccess && hipMalloc(&c->bdm0, words * 8) == hipSuccess &&
@@ -781,7 +810,7 @@ int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
             k_init_spins<<<grid_for(g.Nh / 4, c->L), kBlock, 0, c->stream>>>(g, c->spin);
             st = check_launch(c, "k_init_spins");
         }
-        if (!st && hipMemsetAsync(c->dem, 0, state, c->stream) != hipSuccess) st = MICSA_EHIP;
+        if (!st && hipMemsetAsync(c->dem, 0, dstate, c->stream) != hipSuccess) st = MICSA_EHIP;
     } else {
         const int WL = c->G * p->n_replicas;
         kb_init_couplings<<<dim3((unsigned)((g.Nh + 3) / 4), (unsigned)c->G), 256, 0, c->stream>>>(geomb(c), c->bJ);
@@ -836,6 +865,7 @@ int micsa_set_schedule(micsa_ctx* ctx, const micsa_schedule* s)
     n.T0 = s->T0;
     n.T1 = s->T1;
     n.n_sweeps = s->n_sweeps;
+    n.n_steps = (s->n_sweeps + ctx->gamma - 1) / ctx->gamma;
     auto okT = [](double T) { return T > 0.0 && std::isfinite(T); };
     if (s->kind == MICSA_SCHED_CONST) {
         if (!okT(s->T0)) return fail(ctx, MICSA_EINVAL, "T0 must be positive and finite");
@@ -1024,13 +1054,15 @@ int micsa_read_overlap(micsa_ctx* ctx, int32_t a, int32_t b, int64_t* Q)
     return MICSA_OK;
 }
 
-static int read_state(micsa_ctx* ctx, const uint8_t* dev, uint8_t* host)
+// Byte-layout arrays of `count` parity-split lattices ([count][2][Nh]: the
+// spins, or the daemons with count = L * gamma) -> host [count][N].
+static int read_state(micsa_ctx* ctx, const uint8_t* dev, uint8_t* host, int64_t count)
 {
     const int64_t N = n_sites(ctx);
-    std::vector<uint8_t> buf((size_t)ctx->L * 2 * (size_t)ctx->g.Nh);
+    std::vector<uint8_t> buf((size_t)count * 2 * (size_t)ctx->g.Nh);
     HIP_TRY(ctx, hipMemcpyAsync(buf.data(), dev, buf.size(), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    for (int l = 0; l < ctx->L; ++l)
+    for (int64_t l = 0; l < count; ++l)
         for (int64_t i = 0; i < N; ++i) {
             int par;
             int64_t h;
@@ -1070,14 +1102,14 @@ int micsa_read_spins(micsa_ctx* ctx, uint8_t* sigma)
 {
     if (!ctx || !sigma) return MICSA_EINVAL;
     if (ctx->bit) return read_words(ctx, ctx->bspin, nullptr, sigma);
-    return read_state(ctx, ctx->spin, sigma);
+    return read_state(ctx, ctx->spin, sigma, ctx->L);
 }
 
 int micsa_read_demons(micsa_ctx* ctx, uint8_t* m)
 {
     if (!ctx || !m) return MICSA_EINVAL;
     if (ctx->bit) return read_words(ctx, ctx->bdm0, ctx->bdm1, m);
-    return read_state(ctx, ctx->dem, m);
+    return read_state(ctx, ctx->dem, m, (int64_t)ctx->L * ctx->gamma);
 }
 
 int micsa_read_couplings(micsa_ctx* ctx, uint8_t* j)
@@ -1121,11 +1153,11 @@ int micsa_read_couplings(micsa_ctx* ctx, uint8_t* j)
     return MICSA_OK;
 }
 
-static int write_state(micsa_ctx* ctx, uint8_t* dev, const uint8_t* host, uint8_t maxv)
+static int write_state(micsa_ctx* ctx, uint8_t* dev, const uint8_t* host, uint8_t maxv, int64_t count)
 {
     const int64_t N = n_sites(ctx);
-    std::vector<uint8_t> buf((size_t)ctx->L * 2 * (size_t)ctx->g.Nh);
-    for (int l = 0; l < ctx->L; ++l)
+    std::vector<uint8_t> buf((size_t)count * 2 * (size_t)ctx->g.Nh);
+    for (int64_t l = 0; l < count; ++l)
         for (int64_t i = 0; i < N; ++i) {
             const uint8_t v = host[(int64_t)l * N + i];
             if (v > maxv) return fail(ctx, MICSA_EINVAL, "value out of range");
@@ -1167,7 +1199,7 @@ static int write_words(micsa_ctx* ctx, uint64_t* w0, uint64_t* w1, const uint8_t
 int micsa_write_spins(micsa_ctx* ctx, const uint8_t* sigma)
 {
     if (!ctx || !sigma) return MICSA_EINVAL;
-    int st = ctx->bit ? write_words(ctx, ctx->bspin, nullptr, sigma, 1) : write_state(ctx, ctx->spin, sigma, 1);
+    int st = ctx->bit ? write_words(ctx, ctx->bspin, nullptr, sigma, 1) : write_state(ctx, ctx->spin, sigma, 1, ctx->L);
     if (st) return st;
     std::vector<int64_t> E((size_t)ctx->L);
     if ((st = micsa_read_energy(ctx, E.data()))) return st;
@@ -1178,14 +1210,14 @@ int micsa_write_demons(micsa_ctx* ctx, const uint8_t* m)
 {
     if (!ctx || !m) return MICSA_EINVAL;
     if (ctx->bit) return write_words(ctx, ctx->bdm0, ctx->bdm1, m, 3);
-    return write_state(ctx, ctx->dem, m, 3);
+    return write_state(ctx, ctx->dem, m, 3, (int64_t)ctx->L * ctx->gamma);
 }
 
 int micsa_get_counters(micsa_ctx* ctx, int64_t* k, int64_t* rho)
 {
     if (!ctx) return MICSA_EINVAL;
     if (k) *k = ctx->k;
-    if (rho) *rho = refresh_index(ctx->k, ctx->sched.set ? ctx->sched.period : 1);
+    if (rho) *rho = refresh_index(ctx->k / ctx->gamma, ctx->sched.set ? ctx->sched.period : 1);
     return MICSA_OK;
 }
 
@@ -1256,6 +1288,7 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
 {
     if (ctx && ctx->bit) return algo == MICSA_ALGO_MICSA ? "kb_micsa_half" : "";
     if (algo == MICSA_ALGO_WALKERS) return ctx && use_fused(ctx) ? "k_micsa_sweep_fused+k_wander" : "k_micsa_half+k_wander";
+    // gamma > 1 runs the per-half kernels (never resident or fused)
     if (ctx && use_resident(ctx))
         return algo == MICSA_ALGO_HEATBATH ? "k_resident<1>" : (algo == MICSA_ALGO_METROPOLIS ? "k_resident<2>" : "k_resident<0>");
     if (algo == MICSA_ALGO_HEATBATH)
@@ -1325,7 +1358,9 @@ size_t footprint(const micsa_params* p)
         const size_t G = ((size_t)p->n_samples + 63) / 64;
         return G * p->n_replicas * N * 8 * 3 + G * 6 * (N / 2) * 8 + slots;
     }
-    return 4 * L * N + (size_t)p->n_samples * (N / 2) + slots;  // 2 state buffers x (spin + daemon), couplings
+    const size_t gamma = p->gamma == 0 ? 1 : (size_t)p->gamma;
+    // 2 state buffers x (spin + gamma daemons), couplings
+    return 2 * L * N * (1 + gamma) + (size_t)p->n_samples * (N / 2) + slots;
 }
 
 }  // namespace
@@ -1377,9 +1412,7 @@ int micsa_pool_submit(micsa_pool* pool, const micsa_params* p, const micsa_sched
 {
     if (!pool || !p || !s || !job) return MICSA_EINVAL;
     // validate parameters and schedule the same way a context would
-    if (p->Lx < 8 || p->Lx % 8 || p->Ly < 2 || p->Ly % 2 || p->Lz < 2 || p->Lz % 2) return MICSA_EINVAL;
-    if (p->n_samples < 1 || p->n_samples >= (1 << 24) || p->n_replicas < 1) return MICSA_EINVAL;
-    if (p->layout != MICSA_LAYOUT_BYTE && p->layout != MICSA_LAYOUT_BITPLANE) return MICSA_EINVAL;
+    if (!params_ok(p)) return MICSA_EINVAL;
     if (s->refresh_period < 0 || s->n_sweeps < 1) return MICSA_EINVAL;
     auto okT = [](double T) { return T > 0.0 && std::isfinite(T); };
     if (s->kind == MICSA_SCHED_CONST ? !okT(s->T0)

@@ -35,7 +35,12 @@ class MicsaError(RuntimeError):
 class _Params(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("Lz", ctypes.c_int32),
                 ("n_samples", ctypes.c_int32), ("n_replicas", ctypes.c_int32), ("layout", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("gamma", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+def _params(Lx, Ly, Lz, S, R, layout, seed, gamma=1) -> _Params:
+    return _Params(Lx=Lx, Ly=Ly, Lz=Lz, n_samples=S, n_replicas=R, layout=layout, gamma=gamma,
+                   seed=seed & (2**64 - 1))
 
 
 class _Schedule(ctypes.Structure):
@@ -147,24 +152,26 @@ class Lattice:
     _owned = True
 
     @classmethod
-    def _borrow(cls, ctx: ctypes.c_void_p, Lx, Ly, Lz, S, R, seed=0) -> "Lattice":
+    def _borrow(cls, ctx: ctypes.c_void_p, Lx, Ly, Lz, S, R, seed=0, gamma=1) -> "Lattice":
         """A view of a context owned by someone else (a pool job): never destroyed here."""
         obj = cls.__new__(cls)
         obj.Lx, obj.Ly, obj.Lz, obj.S, obj.R = Lx, Ly, Lz, S, R
         obj.N = Lx * Ly * Lz
         obj.seed = seed
+        obj.gamma = gamma
         obj._ctx = ctx
         obj._owned = False
         obj._table = None
         return obj
 
     def __init__(self, Lx: int, Ly: int, Lz: int, S: int = 1, R: int = 1, seed: int = 0,
-                 layout: int = LAYOUT_BYTE, stream=None):
+                 layout: int = LAYOUT_BYTE, stream=None, gamma: int = 1):
         self.Lx, self.Ly, self.Lz, self.S, self.R = Lx, Ly, Lz, S, R
         self.N = Lx * Ly * Lz
         self.seed = seed
+        self.gamma = gamma
         self._ctx = ctypes.c_void_p()
-        p = _Params(Lx, Ly, Lz, S, R, layout, seed & (2**64 - 1))
+        p = _params(Lx, Ly, Lz, S, R, layout, seed, gamma)
         st = lib().micsa_create(ctypes.byref(p), _stream_handle(stream), ctypes.byref(self._ctx))
         if st != OK:
             raise MicsaError(st, f"micsa_create({Lx},{Ly},{Lz},S={S},R={R}): "
@@ -237,8 +244,12 @@ class Lattice:
         self._check(lib().micsa_read_spins(self._ctx, _ptr(out)), "read_spins")
         return out
 
+    def _daemon_shape(self):
+        return (self.S, self.R, self.N) if self.gamma == 1 else (self.S, self.R, self.gamma, self.N)
+
     def daemons(self) -> np.ndarray:
-        out = np.zeros((self.S, self.R, self.N), np.uint8)
+        """Levels [S, R, N] (gamma = 1) or [S, R, gamma, N]."""
+        out = np.zeros(self._daemon_shape(), np.uint8)
         self._check(lib().micsa_read_demons(self._ctx, _ptr(out)), "read_demons")
         return out
 
@@ -273,7 +284,7 @@ class Lattice:
         self._check(lib().micsa_write_spins(self._ctx, _ptr(a)), "write_spins")
 
     def write_daemons(self, m: np.ndarray) -> None:
-        a = np.ascontiguousarray(m, np.uint8).reshape(self.S, self.R, self.N)
+        a = np.ascontiguousarray(m, np.uint8).reshape(self._daemon_shape())
         self._check(lib().micsa_write_demons(self._ctx, _ptr(a)), "write_demons")
 
     # -- timing ---------------------------------------------------------
@@ -292,10 +303,10 @@ class Lattice:
         return lib().micsa_kernel_name(self._ctx, algo).decode()
 
 
-def footprint(Lx: int, Ly: int, Lz: int, S: int = 1, R: int = 1, layout: int = LAYOUT_BYTE) -> int:
+def footprint(Lx: int, Ly: int, Lz: int, S: int = 1, R: int = 1, layout: int = LAYOUT_BYTE, gamma: int = 1) -> int:
     """Device bytes a pool job of this shape occupies."""
     out = ctypes.c_size_t()
-    st = lib().micsa_pool_footprint(ctypes.byref(_Params(Lx, Ly, Lz, S, R, layout, 0)), ctypes.byref(out))
+    st = lib().micsa_pool_footprint(ctypes.byref(_params(Lx, Ly, Lz, S, R, layout, 0, gamma)), ctypes.byref(out))
     if st != OK:
         raise MicsaError(st, "micsa_pool_footprint")
     return out.value
@@ -327,13 +338,13 @@ class Pool:
         if st != OK:
             raise MicsaError(st, f"{what}: {lib().micsa_status_string(st).decode()}")
 
-    def submit(self, Lx, Ly, Lz, S, R, seed, sched: Schedule, layout: int = LAYOUT_BYTE) -> int:
-        p = _Params(Lx, Ly, Lz, S, R, layout, seed & (2**64 - 1))
+    def submit(self, Lx, Ly, Lz, S, R, seed, sched: Schedule, layout: int = LAYOUT_BYTE, gamma: int = 1) -> int:
+        p = _params(Lx, Ly, Lz, S, R, layout, seed, gamma)
         cs, keep = _schedule_struct(sched)
         job = ctypes.c_int64()
         self._check(lib().micsa_pool_submit(self._pool, ctypes.byref(p), ctypes.byref(cs), ctypes.byref(job)),
                     "pool_submit")
-        self._jobs[job.value] = (Lx, Ly, Lz, S, R, seed)
+        self._jobs[job.value] = (Lx, Ly, Lz, S, R, seed, gamma)
         return job.value
 
     def step(self, sweeps: int) -> tuple[int, int]:

@@ -41,7 +41,7 @@ def test_status_strings():
 
 @pytest.mark.parametrize("dims", [(7, 8, 8), (12, 8, 8), (4, 8, 8), (8, 3, 8), (8, 8, 1), (0, 8, 8), (8, 8, -2)])
 def test_create_rejects_bad_sides(dims):
-    p = M._Params(*dims, 1, 1, 0, 1)
+    p = M._params(*dims, 1, 1, 0, 1)
     out = ctypes.c_void_p(123)
     assert M.lib().micsa_create(ctypes.byref(p), None, ctypes.byref(out)) == M.EINVAL
     assert not out.value
@@ -49,10 +49,24 @@ def test_create_rejects_bad_sides(dims):
 
 @pytest.mark.parametrize("S,R,layout", [(0, 1, 0), (1, 0, 0), (1 << 24, 1, 0), (1, 1, 7)])
 def test_create_rejects_bad_counts_and_layout(S, R, layout):
-    p = M._Params(8, 8, 8, S, R, layout, 1)
+    p = M._params(8, 8, 8, S, R, layout, 1)
     out = ctypes.c_void_p()
     assert M.lib().micsa_create(ctypes.byref(p), None, ctypes.byref(out)) == M.EINVAL
     assert not out.value
+
+
+@pytest.mark.parametrize("gamma,layout", [(7, 0), (-1, 0), (2, 1), (6, 1)])
+def test_create_rejects_bad_gamma(gamma, layout):
+    """gamma daemons per site: 1..6, and more than one only in the byte layout."""
+    p = M._params(8, 8, 8, 1, 1, layout, 1, gamma)
+    out = ctypes.c_void_p()
+    assert M.lib().micsa_create(ctypes.byref(p), None, ctypes.byref(out)) == M.EINVAL
+    assert not out.value
+    size = ctypes.c_size_t()
+    assert M.lib().micsa_pool_footprint(ctypes.byref(M._params(8, 8, 8, 1, 2, 0, 1, 3)), ctypes.byref(size)) == M.OK
+    one = ctypes.c_size_t()
+    assert M.lib().micsa_pool_footprint(ctypes.byref(M._params(8, 8, 8, 1, 2, 0, 1, 1)), ctypes.byref(one)) == M.OK
+    assert size.value - one.value == 2 * 2 * 512 * 2  # two more families: 2 buffers x 2 lattices x N bytes each
 
 
 def test_null_arguments():

@@ -470,3 +470,60 @@ def test_bitplane_error_paths():
     with pytest.raises(M.MicsaError) as e:
         g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)
     assert e.value.status == M.EINVAL
+
+
+# ------------------------------------------------ gamma daemons / walkers
+GAMMA_CASES = [
+    ((16, 6, 10, 2, 2), 2, M.ALGO_MICSA),
+    ((64, 8, 6, 1, 2), 4, M.ALGO_MICSA),
+    ((8, 4, 4, 1, 3), 6, M.ALGO_WALKERS),
+    ((32, 8, 8, 1, 1), 6, M.ALGO_WALKERS),
+    ((24, 6, 4, 2, 1), 3, M.ALGO_WALKERS),
+]
+
+
+@pytest.mark.parametrize("shape,gamma,algo", GAMMA_CASES)
+def test_gamma_trajectory_matches_oracle(shape, gamma, algo):
+    """gamma daemons (walkers) per site: timesteps of gamma sweeps, family a on
+    sweep a, refreshes at timestep boundaries, six wandering directions."""
+    g = M.Lattice(*shape, seed=2024, gamma=gamma)
+    o = O.Lattice(*shape, seed=2024, gamma=gamma)
+    n = 9 * gamma + 2  # ends inside a timestep
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.4, 0.5, n + 5, 3)
+    g.set_schedule(gs)
+    Eg, Dg = g.sweep_logged(algo, n, 1)
+    Eo, Do = o.run(algo, os_, n, 1)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    assert np.array_equal(g.spins(), o.sigma)
+    assert g.daemons().shape == o.m.shape and np.array_equal(g.daemons(), o.m)
+    assert np.array_equal(g.energy_tally(), o.energy())
+    assert g.counters() == (n, (n // gamma) // 3)
+
+
+def test_gamma_heatbath_uses_timestep_temperatures():
+    g = M.Lattice(16, 4, 6, 1, 2, seed=31, gamma=3)
+    o = O.Lattice(16, 4, 6, 1, 2, seed=31, gamma=3)
+    gs, os_ = scheds(M.SCHED_LINEAR, 3.0, 0.3, 40, 2)
+    g.set_schedule(gs)
+    for algo in (M.ALGO_HEATBATH, M.ALGO_METROPOLIS):
+        Eg, _ = g.sweep_logged(algo, 20, 1)
+        Eo, _ = o.run(algo, os_, 20, 1)
+        assert np.array_equal(Eg, Eo)
+    assert np.array_equal(g.spins(), o.sigma)
+
+
+def test_gamma_state_round_trip_and_options():
+    g = M.Lattice(16, 4, 4, 2, 1, seed=3, gamma=4)
+    m = np.random.default_rng(0).integers(0, 4, (2, 1, 4, g.N), dtype=np.uint8)
+    g.write_daemons(m)
+    assert np.array_equal(g.daemons(), m)
+    D = g.daemon_energy()
+    assert np.array_equal(D, 4 * m.reshape(2, -1).sum(axis=1).astype(np.int64))
+    for kernel in (M.KERNEL_FUSED, M.KERNEL_RESIDENT):
+        with pytest.raises(M.MicsaError) as e:
+            g.set_option(M.OPT_SWEEP_KERNEL, kernel)
+        assert e.value.status == M.EINVAL
+    bad = m.copy()
+    bad[0, 0, 3, 5] = 4
+    with pytest.raises(M.MicsaError):
+        g.write_daemons(bad)
