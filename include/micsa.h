@@ -150,6 +150,19 @@ int micsa_read_demon_energy(micsa_ctx* ctx, int64_t* D); /* [S*R] H^aux = 4 sum 
 /* Q[s] = sum_x s^a_x s^b_x, the overlap of replicas a and b (App. C); EINVAL
    unless 0 <= a, b < R and a != b. */
 int micsa_read_overlap(micsa_ctx* ctx, int32_t a, int32_t b, int64_t* Q);
+/* Four-point correlation of the overlap field q_x = s^a_x s^b_x (Sec. 3):
+   G[s][mu][r] = sum over replica pairs a < b and sites x of q_x q_{x + r e_mu}
+   (periodic), mu = x, y, z, for r = 0 .. rmax with rmax = max(Lx, Ly, Lz)/2;
+   entries with r > L_mu / 2 are 0.  C4(r) is the mean of G over the three
+   axes divided by N R (R - 1) / 2 (so C4(0) = 1).  Host array
+   [S][3][rmax + 1]; EINVAL unless R >= 2.  Allocates and frees a device
+   buffer of at most 256 MiB for the packed overlap fields. */
+int micsa_read_c4(micsa_ctx* ctx, int64_t* G);
+/* Coherence lengths per sample (eq. xi-def): I_n = sum_{r=0}^{rmin} r^n C4(r),
+   rmin = min(Lx, Ly, Lz)/2 (the integral read as the sum over lattice
+   distances up to half the side), xi12 = I2/I1, xi23 = I3/I2 (NaN if I1 or
+   I2 is not positive).  Host arrays [S]; EINVAL unless R >= 2. */
+int micsa_read_xi(micsa_ctx* ctx, double* xi12, double* xi23);
 int micsa_read_spins(micsa_ctx* ctx, uint8_t* sigma);    /* [S][R][N] */
 int micsa_read_demons(micsa_ctx* ctx, uint8_t* m);       /* [S][R][gamma][N] */
 int micsa_read_couplings(micsa_ctx* ctx, uint8_t* j);    /* [S][N] forward-bond bits 0..2 */

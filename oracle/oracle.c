@@ -414,6 +414,61 @@ void oracle_overlap(int64_t N, int S, int R, int a, int b, const uint8_t *sigma,
 }
 
 /* ------------------------------------------------------------------ */
+/* Four-point correlation (Sec. 3): with the overlap field               */
+/* q_x = s^a_x s^b_x of two replicas, the lattice sums                   */
+/*   G_mu(r) = sum over pairs a < b of sum_x q_x q_{x + r e_mu}          */
+/* for r = 0 .. L_mu/2 along each axis mu (periodic).  C4(r) is their    */
+/* mean over the three axes divided by N * R(R-1)/2, so C4(0) = 1.       */
+/* G[s][mu][r] is written for r <= L_mu/2, the rest of the row (up to    */
+/* rmax + 1 entries) is set to 0.                                        */
+/* ------------------------------------------------------------------ */
+void oracle_c4_sums(int Lx, int Ly, int Lz, int S, int R, const uint8_t *sigma, int rmax, int64_t *G)
+{
+    geom g = mk(Lx, Ly, Lz);
+    int side[3] = {Lx, Ly, Lz};
+    for (int s = 0; s < S; s++)
+        for (int mu = 0; mu < 3; mu++)
+            for (int r = 0; r <= rmax; r++) {
+                int64_t tot = 0;
+                if (r <= side[mu] / 2)
+                    for (int a = 0; a < R; a++)
+                        for (int b = a + 1; b < R; b++) {
+                            const uint8_t *sa = sigma + ((int64_t)s * R + a) * g.N;
+                            const uint8_t *sb = sigma + ((int64_t)s * R + b) * g.N;
+#pragma omp parallel for reduction(+ : tot) schedule(static)
+                            for (int64_t i = 0; i < g.N; i++) {
+                                int x, y, z;
+                                coords(&g, i, &x, &y, &z);
+                                int64_t j = site(&g, x + (mu == 0) * r, y + (mu == 1) * r, z + (mu == 2) * r);
+                                tot += spin(sa[i]) * spin(sb[i]) * spin(sa[j]) * spin(sb[j]);
+                            }
+                        }
+                G[((int64_t)s * 3 + mu) * (rmax + 1) + r] = tot;
+            }
+}
+
+/* Coherence lengths (Sec. 3, eq. xi-def): I_n = sum_r r^n C4(r), the   */
+/* integral over r >= 0 taken as the sum over the lattice distances     */
+/* r = 0 .. rmax (rmax = half the smallest side: C4 of a periodic        */
+/* lattice is symmetric about it); xi12 = I2 / I1, xi23 = I3 / I2.  C4   */
+/* is given as C4[r], r = 0..rmax.  Returns -1 unless I1 and I2 > 0.     */
+int oracle_xi_from_c4(const double *C4, int rmax, double *xi12, double *xi23)
+{
+    double I[4] = {0, 0, 0, 0};
+    for (int r = 0; r <= rmax; r++) {
+        double p = 1.0;
+        for (int n = 0; n < 4; n++) {
+            I[n] += p * C4[r];
+            p *= (double)r;
+        }
+    }
+    if (!(I[1] > 0.0) || !(I[2] > 0.0)) return -1;
+    *xi12 = I[2] / I[1];
+    *xi23 = I[3] / I[2];
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Schedule (Sec. 2.7, Sec. 2.8): when the daemons are refreshed and at */
 /* which temperature.                                                  */
 /*   period P >= 1 : refresh before sweep k iff k mod P == 0           */

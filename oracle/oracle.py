@@ -79,6 +79,9 @@ def lib():
         L.oracle_energy.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, _u8p, _u8p, _i64p]
         L.oracle_daemon_energy.argtypes = [c.c_int64, c.c_int, _u8p, _i64p]
         L.oracle_overlap.argtypes = [c.c_int64, c.c_int, c.c_int, c.c_int, c.c_int, _u8p, _i64p]
+        L.oracle_c4_sums.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, _u8p, c.c_int, _i64p]
+        L.oracle_xi_from_c4.argtypes = [_f64p, c.c_int, c.POINTER(c.c_double), c.POINTER(c.c_double)]
+        L.oracle_xi_from_c4.restype = c.c_int
         L.oracle_is_refresh.argtypes = [c.c_int64, c.c_int]
         L.oracle_is_refresh.restype = c.c_int
         L.oracle_refresh_index.argtypes = [c.c_int64, c.c_int]
@@ -268,6 +271,29 @@ class Lattice:
         lib().oracle_overlap(self.N, self.S, self.R, int(a), int(b), self.sigma, Q)
         return Q
 
+    def c4_sums(self) -> np.ndarray:
+        """G[S, 3, rmax+1]: sum over replica pairs a < b and sites of q_x q_{x+r e_mu}
+        for r <= L_mu / 2 (0 beyond), rmax = max side / 2."""
+        rmax = max(self.Lx, self.Ly, self.Lz) // 2
+        G = np.zeros((self.S, 3, rmax + 1), np.int64)
+        lib().oracle_c4_sums(*self._dims(), self.sigma, rmax, G)
+        return G
+
+    def c4(self) -> np.ndarray:
+        """C4(r) [S, rmin+1], r = 0 .. min side / 2: mean over the three axes,
+        normalised by N R (R-1) / 2."""
+        G = self.c4_sums()
+        rmin = min(self.Lx, self.Ly, self.Lz) // 2
+        pairs = self.R * (self.R - 1) // 2
+        return G[:, :, :rmin + 1].sum(axis=1) / (3.0 * self.N * pairs)
+
+    def xi(self):
+        """(xi12, xi23) per sample from C4 (eq. xi-def)."""
+        out = []
+        for row in self.c4():
+            out.append(xi_from_c4(row))
+        return np.array(out)
+
     # -- driver ---------------------------------------------------------
     def run(self, algo: int, sched: Schedule, n: int, stride: int = 0):
         """Sweeps k .. k+n-1; returns (E_log, D_log), each [n//stride, S*R]."""
@@ -286,6 +312,16 @@ class Lattice:
         self.tally += dE
         self.k += int(n)
         return E_log[:rows], D_log[:rows]
+
+
+def xi_from_c4(C4) -> tuple[float, float]:
+    """(xi12, xi23) from C4(r), r = 0..len-1 (eq. xi-def, integrals as sums);
+    NaN when I1 or I2 is not positive (no correlation above the noise)."""
+    c = np.ascontiguousarray(C4, np.float64)
+    a, b = ctypes.c_double(), ctypes.c_double()
+    if lib().oracle_xi_from_c4(c, len(c) - 1, ctypes.byref(a), ctypes.byref(b)) != 0:
+        return float("nan"), float("nan")
+    return a.value, b.value
 
 
 def density_of_states(Lx: int, Ly: int, Lz: int, J: np.ndarray) -> np.ndarray:

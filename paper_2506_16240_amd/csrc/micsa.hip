@@ -16,6 +16,7 @@
 
 #include "bitplane_kernels.hpp"
 #include "fused_kernels.hpp"
+#include "observables.hpp"
 #include "resident_kernels.hpp"
 #include "micsa.h"
 
@@ -1025,6 +1026,113 @@ int micsa_read_demon_energy(micsa_ctx* ctx, int64_t* D)
     std::vector<int64_t> v;
     if (st || (st = read_red(ctx, ctx->L, v))) return st;
     for (int l = 0; l < ctx->L; ++l) D[l] = 4 * v[(size_t)l];
+    return MICSA_OK;
+}
+
+// D[s][mu][r] = #{(pair, x) : w_x != w_{x + r e_mu}} summed over the replica
+// pairs of sample s (observables.hpp), for r = 0 .. rmax.
+static int c4_counts(micsa_ctx* c, const C4Geom& cg, std::vector<int64_t>& D)
+{
+    const int64_t ent = (int64_t)c->p.n_samples * 3 * (cg.rmax + 1);
+    const int64_t per_pair = (int64_t)2 * c->g.rows * cg.E;
+    const int64_t total = (int64_t)c->p.n_samples * cg.npair;
+    const int64_t budget_words = ((int64_t)256 << 20) / 4;  // at most 256 MiB of packed pairs at a time
+    const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>({total, budget_words / per_pair, 65535}));
+    unsigned long long* dD = nullptr;
+    uint32_t* Q = nullptr;
+    if (hipMalloc(&dD, (size_t)ent * kSlots * 8) != hipSuccess ||
+        hipMalloc(&Q, (size_t)(chunk * per_pair) * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        if (dD) (void)hipFree(dD);
+        return fail(c, MICSA_ENOMEM, "correlation buffers");
+    }
+    int st = zero_slots(c, dD, ent);
+    const int64_t valid = (int64_t)2 * c->g.rows * cg.Wv;
+    for (int64_t sp0 = 0; sp0 < total && !st; sp0 += chunk) {
+        const unsigned n = (unsigned)std::min(chunk, total - sp0);
+        {
+            TimedLaunch t(c, kTimeReduce);
+            if (c->bit)
+                k_pack_overlap<true><<<dim3((unsigned)((per_pair + 255) / 256), n), 256, 0, c->stream>>>(
+                    c->g, cg, (int)sp0, nullptr, c->bspin, Q);
+            else
+                k_pack_overlap<false><<<dim3((unsigned)((per_pair + 255) / 256), n), 256, 0, c->stream>>>(
+                    c->g, cg, (int)sp0, c->spin, nullptr, Q);
+        }
+        if ((st = check_launch(c, "k_pack_overlap"))) break;
+        {
+            TimedLaunch t(c, kTimeReduce);
+            k_c4_count<<<dim3((unsigned)((valid + 255) / 256), (unsigned)(3 * (cg.rmax + 1)), n), 256, 0,
+                         c->stream>>>(c->g, cg, (int)sp0, Q, dD);
+        }
+        st = check_launch(c, "k_c4_count");
+    }
+    if (!st) st = read_slots(c, dD, ent, D);
+    (void)hipFree(Q);
+    (void)hipFree(dD);
+    return st;
+}
+
+static C4Geom c4_geom(const micsa_ctx* c)
+{
+    C4Geom cg;
+    cg.E = (c->g.Kx + 63) / 32;
+    cg.Wv = (c->g.Kx + 31) / 32;
+    cg.rmax = std::max({c->p.Lx, c->p.Ly, c->p.Lz}) / 2;
+    cg.npair = c->p.n_replicas * (c->p.n_replicas - 1) / 2;
+    return cg;
+}
+
+int micsa_read_c4(micsa_ctx* ctx, int64_t* G)
+{
+    if (!ctx || !G) return MICSA_EINVAL;
+    if (ctx->p.n_replicas < 2) return fail(ctx, MICSA_EINVAL, "C4 needs at least two replicas");
+    const C4Geom cg = c4_geom(ctx);
+    std::vector<int64_t> D;
+    const int st = c4_counts(ctx, cg, D);
+    if (st) return st;
+    const int64_t N = n_sites(ctx);
+    const int side[3] = {ctx->p.Lx, ctx->p.Ly, ctx->p.Lz};
+    for (int s = 0; s < ctx->p.n_samples; ++s)
+        for (int mu = 0; mu < 3; ++mu)
+            for (int r = 0; r <= cg.rmax; ++r) {
+                const int64_t e = ((int64_t)s * 3 + mu) * (cg.rmax + 1) + r;
+                G[e] = 2 * r <= side[mu] ? N * cg.npair - 2 * D[(size_t)e] : 0;
+            }
+    return MICSA_OK;
+}
+
+int micsa_read_xi(micsa_ctx* ctx, double* xi12, double* xi23)
+{
+    if (!ctx || !xi12 || !xi23) return MICSA_EINVAL;
+    if (ctx->p.n_replicas < 2) return fail(ctx, MICSA_EINVAL, "xi needs at least two replicas");
+    const C4Geom cg = c4_geom(ctx);
+    std::vector<int64_t> G((size_t)ctx->p.n_samples * 3 * (cg.rmax + 1));
+    int st = micsa_read_c4(ctx, G.data());
+    if (st) return st;
+    const int64_t N = n_sites(ctx);
+    const int rmin = std::min({ctx->p.Lx, ctx->p.Ly, ctx->p.Lz}) / 2;
+    for (int s = 0; s < ctx->p.n_samples; ++s) {
+        // C4(r): mean over the three axes, normalised so that C4(0) = 1;
+        // I_n = sum_{r = 0}^{rmin} r^n C4(r); xi12 = I2/I1, xi23 = I3/I2
+        double I[4] = {0, 0, 0, 0};
+        for (int r = 0; r <= rmin; ++r) {
+            int64_t sum = 0;
+            for (int mu = 0; mu < 3; ++mu) sum += G[(size_t)(((int64_t)s * 3 + mu) * (cg.rmax + 1) + r)];
+            const double c4 = (double)sum / (3.0 * (double)N * (double)cg.npair);
+            double pw = 1.0;
+            for (int n = 0; n < 4; ++n) {
+                I[n] += pw * c4;
+                pw *= (double)r;
+            }
+        }
+        if (!(I[1] > 0.0) || !(I[2] > 0.0)) {
+            xi12[s] = xi23[s] = NAN;
+        } else {
+            xi12[s] = I[2] / I[1];
+            xi23[s] = I[3] / I[2];
+        }
+    }
     return MICSA_OK;
 }
 

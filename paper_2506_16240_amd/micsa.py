@@ -74,6 +74,8 @@ _SIGNATURES = [
     ("micsa_get_thresholds", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     ("micsa_get_heatbath_thresholds", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     ("micsa_get_metropolis_thresholds", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
+    ("micsa_read_c4", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_read_xi", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("micsa_write_spins", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("micsa_write_demons", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("micsa_set_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
@@ -246,6 +248,20 @@ class Lattice:
 
     def _daemon_shape(self):
         return (self.S, self.R, self.N) if self.gamma == 1 else (self.S, self.R, self.gamma, self.N)
+
+    def c4_sums(self) -> np.ndarray:
+        """G[S, 3, rmax+1] (micsa_read_c4), rmax = max side / 2."""
+        rmax = max(self.Lx, self.Ly, self.Lz) // 2
+        out = np.zeros((self.S, 3, rmax + 1), np.int64)
+        self._check(lib().micsa_read_c4(self._ctx, _ptr(out)), "read_c4")
+        return out
+
+    def xi(self) -> np.ndarray:
+        """[S, 2]: (xi12, xi23) per sample (micsa_read_xi)."""
+        a = np.zeros(self.S, np.float64)
+        b = np.zeros(self.S, np.float64)
+        self._check(lib().micsa_read_xi(self._ctx, _ptr(a), _ptr(b)), "read_xi")
+        return np.stack([a, b], axis=1)
 
     def daemons(self) -> np.ndarray:
         """Levels [S, R, N] (gamma = 1) or [S, R, gamma, N]."""

@@ -527,3 +527,59 @@ def test_gamma_state_round_trip_and_options():
     bad[0, 0, 3, 5] = 4
     with pytest.raises(M.MicsaError):
         g.write_daemons(bad)
+
+
+# ------------------------------------------- C4 and coherence lengths (Sec. 3)
+C4_CASES = [
+    ((8, 4, 6, 1, 2), M.LAYOUT_BYTE),
+    ((40, 10, 6, 2, 3), M.LAYOUT_BYTE),     # ragged rows (Kx = 20), three pairs
+    ((64, 64, 64, 1, 2), M.LAYOUT_BYTE),    # the quench lattice
+    ((96, 8, 4, 1, 4), M.LAYOUT_BYTE),      # Kx = 48: windows across words
+    ((16, 8, 8, 70, 2), M.LAYOUT_BITPLANE), # two lane groups
+]
+
+
+@pytest.mark.parametrize("shape,layout", C4_CASES)
+def test_c4_and_xi_match_oracle(shape, layout):
+    g = M.Lattice(*shape, seed=808, layout=layout)
+    o = O.Lattice(*shape, seed=808)
+    n = 30
+    gs, os_ = scheds(M.SCHED_CONST, 0.8, 0.8, n, 5)
+    g.set_schedule(gs)
+    g.sweep(M.ALGO_MICSA, n)
+    o.run(O.ALGO_MICSA, os_, n, 0)
+    assert np.array_equal(g.spins(), o.sigma)
+    assert np.array_equal(g.c4_sums(), o.c4_sums())
+    xg = g.xi()
+    xo = o.xi()
+    # same integer sums and the same double operations in the same order
+    assert np.allclose(xg, xo, rtol=1e-13, atol=0, equal_nan=True), (xg, xo)
+    assert np.array_equal(np.isnan(xg), np.isnan(xo))
+
+
+def test_c4_needs_two_replicas():
+    g = M.Lattice(8, 4, 4, 1, 1, seed=1)
+    with pytest.raises(M.MicsaError) as e:
+        g.c4_sums()
+    assert e.value.status == M.EINVAL
+
+
+def test_xi_of_written_overlap_fields_matches_oracle():
+    """Finite coherence lengths: replica 1 is replica 0 with a slab and a
+    checkerboard patch flipped, so C4 decays over a known range."""
+    shape = (32, 16, 16, 2, 2)
+    g = M.Lattice(*shape, seed=9)
+    o = O.Lattice(*shape, seed=9)
+    N = o.N
+    i = np.arange(N)
+    x, y, z = i % 32, (i // 32) % 16, i // 512
+    flip = ((x < 8) | ((y < 4) & (z < 4))).astype(np.uint8)
+    sig = o.sigma.copy()
+    sig[:, 1] = sig[:, 0] ^ flip
+    sig[1, 1] ^= ((x + y) % 5 == 0).astype(np.uint8)
+    o.sigma[:] = sig
+    g.write_spins(sig)
+    assert np.array_equal(g.c4_sums(), o.c4_sums())
+    xg, xo = g.xi(), o.xi()
+    assert np.isfinite(xo).all()
+    assert np.allclose(xg, xo, rtol=1e-13, atol=0), (xg, xo)

@@ -709,3 +709,81 @@ def test_gamma_runs_reach_canonical_equilibrium(shape, T, period, gamma, algo):
     E_log, _ = L.run(algo, O.Schedule(O.SCHED_CONST, T, T, n, period), n, 1)
     mean, err = _batch_mean(E_log[n // 5:].mean(axis=1))
     assert abs(mean - exact) <= 4.5 * err + 1e-9, (mean, exact, err)
+
+
+# ------------------------------------------- C4 and coherence lengths (Sec. 3)
+def _set_replicas(L, a_bits, b_bits, c_bits=None):
+    L.sigma[0, 0] = a_bits
+    L.sigma[0, 1] = b_bits
+    if c_bits is not None:
+        L.sigma[0, 2] = c_bits
+
+
+def test_c4_closed_forms():
+    """Overlap fields whose correlations are known exactly: identical replicas
+    (q = 1: every sum is N), a slab along x (q = +1 for x < Lx/2, periodic
+    square wave: N (1 - 4r/Lx) along x, N along y and z), a checkerboard
+    (N (-1)^r along every axis), and three replicas (the sum over the three
+    pairs)."""
+    Lx, Ly, Lz = 8, 6, 4
+    L = O.Lattice(Lx, Ly, Lz, 1, 2, seed=1)
+    N = L.N
+    x, y, z = _coords(L)
+    rng = np.random.default_rng(3)
+    a = rng.integers(0, 2, N).astype(np.uint8)
+    _set_replicas(L, a, a)
+    G = L.c4_sums()
+    assert G.shape == (1, 3, 5)
+    for mu, side in enumerate((Lx, Ly, Lz)):
+        assert (G[0, mu, :side // 2 + 1] == N).all() and (G[0, mu, side // 2 + 1:] == 0).all()
+    slab = (x >= Lx // 2).astype(np.uint8)
+    _set_replicas(L, a, a ^ slab)
+    G = L.c4_sums()
+    assert G[0, 0].tolist() == [N * (Lx - 4 * r) // Lx for r in range(5)]
+    assert G[0, 1, :4].tolist() == [N] * 4 and G[0, 2, :3].tolist() == [N] * 3
+    cb = ((x + y + z) & 1).astype(np.uint8)
+    _set_replicas(L, a, a ^ cb)
+    G = L.c4_sums()
+    for mu, side in enumerate((Lx, Ly, Lz)):
+        assert G[0, mu, :side // 2 + 1].tolist() == [N * (-1) ** r for r in range(side // 2 + 1)]
+    C4 = L.c4()
+    assert C4.shape == (1, 3) and C4[0, 0] == 1.0
+    L3 = O.Lattice(Lx, Ly, Lz, 1, 3, seed=1)
+    _set_replicas(L3, a, a ^ slab, a)  # pairs: slab, identical, slab
+    G3 = L3.c4_sums()
+    assert G3[0, 0].tolist() == [2 * N * (Lx - 4 * r) // Lx + N for r in range(5)]
+    assert L3.c4()[0, 0] == 1.0
+
+
+def test_c4_symmetries_and_random_fields():
+    """Unchanged by a global flip of one replica and by a common translation;
+    for independent infinite-temperature replicas C4(r > 0) vanishes within
+    its 1/sqrt(N) fluctuation."""
+    L = O.Lattice(16, 16, 16, 1, 2, seed=21)
+    G = L.c4_sums()
+    L.sigma[0, 1] ^= 1
+    assert np.array_equal(L.c4_sums(), G)
+    L.sigma[0, 1] ^= 1
+    sh = L.sigma[0].reshape(2, 16, 16, 16)
+    L.sigma[0] = np.roll(sh, (3, -5, 7), axis=(1, 2, 3)).reshape(2, -1)
+    assert np.array_equal(L.c4_sums(), G)
+    C4 = L.c4()[0]
+    assert C4[0] == 1.0
+    assert np.abs(C4[1:]).max() < 5 / math.sqrt(L.N)
+
+
+def test_xi_from_c4_closed_forms():
+    """eq. xi-def with I_n as sums over r: a single peak at distance d gives
+    xi12 = xi23 = d; a geometric C4(r) = q^r summed far enough gives the
+    generating-function values xi12 = (1+q)/(1-q) and
+    xi23 = (1+4q+q^2)/((1+q)(1-q))."""
+    C = np.zeros(10)
+    C[0], C[4] = 1.0, 0.5
+    assert O.xi_from_c4(C) == (4.0, 4.0)
+    q = 0.8
+    C = q ** np.arange(4000, dtype=float)
+    a, b = O.xi_from_c4(C)
+    assert abs(a - (1 + q) / (1 - q)) < 1e-9
+    assert abs(b - (1 + 4 * q + q * q) / ((1 + q) * (1 - q))) < 1e-9
+    assert all(math.isnan(v) for v in O.xi_from_c4(np.array([1.0, 0.0, 0.0])))
+    assert all(math.isnan(v) for v in O.xi_from_c4(np.array([1.0, -0.1, 0.05])))

@@ -52,6 +52,10 @@ MUTATIONS = [
      "floor(exp(-0.5 * beta * (double)dH) * 4294967296.0)", "metropolis"),
     ("Metropolis threshold index", "if (u < th[(dH + 12) / 4]) {", "if (u < th[(12 - dH) / 4]) {",
      "metropolis"),
+    ("C4 axis of the shift", "site(&g, x + (mu == 0) * r, y + (mu == 1) * r, z + (mu == 2) * r)",
+     "site(&g, x + (mu == 1) * r, y + (mu == 0) * r, z + (mu == 2) * r)", "c4"),
+    ("C4 replica pairs", "for (int b = a + 1; b < R; b++) {", "for (int b = a; b < R; b++) {", "c4"),
+    ("xi ratio", "*xi12 = I[2] / I[1];", "*xi12 = I[2] / I[0];", "xi"),
     ("walker step direction", "{{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}", "{{-1, 0, 0}, {1, 0, 0}, {0, 1, 0}", "walkers"),
 ]
 
