@@ -61,6 +61,8 @@ def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None):
         if tile and algo_name == "micsa":
             lat.set_option(M.OPT_TILE_Y, tile[0])
             lat.set_option(M.OPT_TILE_Z, tile[1])
+            if len(tile) > 2:
+                lat.set_option(M.OPT_PREFETCH, tile[2])
 
     algo = {"micsa": M.ALGO_MICSA, "heatbath": M.ALGO_HEATBATH, "metropolis": M.ALGO_METROPOLIS}[algo_name]
     sched = M.Schedule(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
@@ -127,7 +129,8 @@ def main() -> int:
     ap.add_argument("--no-heatbath", action="store_true")
     ap.add_argument("--no-metropolis", action="store_true")
     ap.add_argument("--tile", default="tune",
-                    help="fused-sweep tile: 'tune' (autotuner, bit-exact gated), 'auto' (library default) or TY,TZ")
+                    help="fused-sweep tile: 'tune' (autotuner, bit-exact gated), 'auto' (library default) "
+                         "or TY,TZ[,PREFETCH]")
     ap.add_argument("--copy-ref-gib", type=float, default=0.0,
                     help="after the run, copy this many GiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -156,8 +159,8 @@ def main() -> int:
         from paper_2506_16240_amd import tune
         log("tuning fused-sweep tiles")
         best = tune.tune(w.Lx, w.Ly, w.Lz, w.S, w.R, use_cache=False)
-        tile = (best.ty, best.tz)
-        log(f"tile TY={best.ty} TZ={best.tz} ({best.us_per_sweep:.1f} us/sweep in tuning)")
+        tile = (best.ty, best.tz, best.prefetch)
+        log(f"tile TY={best.ty} TZ={best.tz} prefetch {best.prefetch} ({best.us_per_sweep:.1f} us/sweep in tuning)")
     elif args.tile != "auto":
         tile = tuple(int(v) for v in args.tile.split(","))
     log(f"micsa: {w.name}, {sweeps} sweeps")

@@ -207,17 +207,23 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      fused sweep (0 = automatic; must divide Ly / Lz).
    MICSA_OPT_XCD_MAP: 1 (default) assigns neighbouring tiles of the fused
      sweep to the same XCD (shared L2 for halo reads); 0 = plain order.
-   MICSA_OPT_GRAPHS: 1 (default) replays the per-half paths (bit-plane
-     layout; byte lattices using neither the resident nor the fused sweep)
-     as captured HIP graphs of 16 sweeps; 0 = launch every kernel.
-     Per-launch timing (micsa_set_timing) always launches every kernel.
+   MICSA_OPT_GRAPHS: 1 replays the per-half paths (bit-plane layout; byte
+     lattices using neither the resident nor the fused sweep) as captured
+     HIP graphs of 16 sweeps; 0 (default) launches every kernel, which is
+     faster for these kernels on MI355X (the graph form adds a refresh-check
+     and a counter kernel to every sweep).  Per-launch timing
+     (micsa_set_timing) always launches every kernel.
+   MICSA_OPT_PREFETCH: steps of global loads in flight in the fused MicSA
+     sweep, 1 (default) or 2 (used for work-groups of at most 640 lanes,
+     i.e. (tile_y + 4) * Lx / 32 <= 640; larger tiles run with 1).
    Errors: EINVAL for an unknown option or a value the lattice cannot use. */
 enum micsa_option {
     MICSA_OPT_SWEEP_KERNEL = 1,
     MICSA_OPT_TILE_Y = 2,
     MICSA_OPT_TILE_Z = 3,
     MICSA_OPT_XCD_MAP = 4,
-    MICSA_OPT_GRAPHS = 5
+    MICSA_OPT_GRAPHS = 5,
+    MICSA_OPT_PREFETCH = 6
 };
 enum micsa_kernel_choice {
     MICSA_KERNEL_AUTO = 0,    /* resident if the lattice fits, else fused if Lx >= 128, else simple */

@@ -160,8 +160,20 @@ __device__ __forceinline__ void refresh_chunk(const Geom& g, int row, int c, int
     }
 }
 
-template <bool REFRESH>
-__global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
+// Inputs of one step of the march (global loads issued ahead of use).
+struct StepIn {
+    V4 So, Se, Jw, Me, Mo;
+};
+
+// PF = steps of loads in flight: 1, or 2 with two input sets used
+// alternately (the march unrolled by two, so no register copy has to wait
+// for a load still in flight).
+// The two-step variant holds a second input set: it is built for
+// work-groups of at most kPf2Lanes lanes (up to 170 VGPRs per lane).
+constexpr int kPf2Lanes = 640;
+
+template <bool REFRESH, int PF>
+__global__ void __launch_bounds__(PF == 2 ? kPf2Lanes : 1024) k_micsa_sweep_fused(
     Geom g, FusedTile f, const uint8_t* __restrict__ spin_in, const uint8_t* __restrict__ dem_in,
     uint8_t* __restrict__ spin_out, uint8_t* __restrict__ dem_out, const uint32_t* __restrict__ J,
     unsigned long long* __restrict__ tally, uint32_t rho, DaemonThresholds th)
@@ -206,36 +218,37 @@ __global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
     const int steps = f.TZ + 2;
 
     // Step st works on plane z = zstart + dz st (even half) and z - dz (odd
-    // half).  Global loads are issued one step ahead (the "n" registers).
+    // half).  Global loads are issued PF steps ahead.
     V4 So_prev{}, So_cur{}, So_next{};  // odd spins (old) at planes z-dz, z, z+dz
     V4 X_prev2{}, X_prev{}, X_cur{};    // even views at planes z-2dz, z-dz, z
     V4 Mo_gen{};                        // refreshed odd levels of plane z-dz
-    V4 nSo{}, nSe{}, nJw{}, nMe{}, nMo{};
-    auto load_step = [&](int st2) {  // inputs of step st2 (plane z2 = zstart + dz st2)
+    auto load_step = [&](StepIn& in, int st2) {  // inputs of step st2 (plane z2 = zstart + dz st2)
         const int z2 = wrapz(zstart + dz * st2);
-        if (active) nSo = ldg16(od_in + hof(wrapz(z2 + dz)));
+        if (active) in.So = ldg16(od_in + hof(wrapz(z2 + dz)));
         if (do_even) {
             const int64_t h2 = hof(z2);
-            nSe = ldg16(ev_in + h2);
-            nJw = ldg16(Jb + h2);
-            if (!REFRESH) nMe = ldg16(me_in + h2);
+            in.Se = ldg16(ev_in + h2);
+            in.Jw = ldg16(Jb + h2);
+            if (!REFRESH) in.Me = ldg16(me_in + h2);
         }
-        if (!REFRESH && do_odd && st2 >= 2) nMo = ldg16(mo_in + hof(wrapz(z2 - dz)));
+        if (!REFRESH && do_odd && st2 >= 2) in.Mo = ldg16(mo_in + hof(wrapz(z2 - dz)));
     };
     if (active) {
         So_prev = ldg16(od_in + hof(wrapz(zstart - dz)));
         So_cur = ldg16(od_in + hof(wrapz(zstart)));
     }
-    load_step(0);
+    StepIn inA{}, inB{};
+    load_step(inA, 0);
+    if (PF == 2 && steps > 1) load_step(inB, 1);
     uint32_t sum_old = 0, sum_new = 0;  // daemon level sums before/after owned moves
-    for (int st = 0; st < steps; ++st) {
+    auto step = [&](const int st, StepIn& in) {
         const int buf = st & 1;
         const int z = wrapz(zstart + dz * st);
         const int64_t h = hof(z);
-        So_next = nSo;
-        V4 Se = nSe, Jw = nJw, Me = nMe, Mo = nMo;
+        So_next = in.So;
+        V4 Se = in.Se, Jw = in.Jw, Me = in.Me, Mo = in.Mo;
         V4 Mo_next{};
-        if (st + 1 < steps) load_step(st + 1);
+        if (st + PF < steps) load_step(in, st + PF);
         if (REFRESH && do_even) refresh_chunk(g, y + g.Ly * z, c, (y + z) & 1, rho, (uint32_t)r, sw, th, Me, Mo_next);
         const bool odd_now = do_odd && st >= 2;
         const int zo = wrapz(z - dz);
@@ -319,6 +332,10 @@ __global__ void __launch_bounds__(1024) k_micsa_sweep_fused(
         X_prev2 = X_prev;
         X_prev = X_cur;
         Mo_gen = Mo_next;
+    };
+    for (int st = 0; st < steps; st += PF) {
+        step(st, inA);
+        if (PF == 2 && st + 1 < steps) step(st + 1, inB);
     }
     // dH = 4 (sum of old levels - sum of new levels) over the owned moves
     block_add(tally + (int64_t)l * kSlots, 4 * ((long long)sum_old - (long long)sum_new));

@@ -64,7 +64,8 @@ struct micsa_ctx {
     int32_t kernel_opt = MICSA_KERNEL_AUTO;
     int32_t tile_y = 0, tile_z = 0;
     int32_t xcd_map = 1;  // XCD-aware tile order for the fused sweeps
-    int32_t use_graphs = 1;
+    int32_t prefetch = 1;  // steps of loads in flight in the fused MicSA sweep (1 or 2)
+    int32_t use_graphs = 0;
     // replayable graphs of kGraphSweeps sweeps for the per-half paths, per algo
     int64_t* d_k = nullptr;  // device copy of the sweep counter
     hipStream_t cap_stream = nullptr;
@@ -367,12 +368,11 @@ int launch_fused_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
     const DaemonThresholds th = refresh ? daemon_thresholds(T) : DaemonThresholds{0, 0, 0};
     {
         TimedLaunch t(c, kTimeSweep);
-        if (refresh)
-            k_micsa_sweep_fused<true><<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->dem, c->spin_alt,
-                                                                       c->dem_alt, c->J, c->tally, (uint32_t)rho, th);
-        else
-            k_micsa_sweep_fused<false><<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->dem, c->spin_alt,
-                                                                        c->dem_alt, c->J, c->tally, (uint32_t)rho, th);
+        const bool pf2 = c->prefetch == 2 && block <= kPf2Lanes;  // larger tiles run the one-step variant
+        const auto kern = refresh ? (pf2 ? k_micsa_sweep_fused<true, 2> : k_micsa_sweep_fused<true, 1>)
+                                  : (pf2 ? k_micsa_sweep_fused<false, 2> : k_micsa_sweep_fused<false, 1>);
+        kern<<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->dem, c->spin_alt, c->dem_alt, c->J, c->tally,
+                                              (uint32_t)rho, th);
     }
     const int st = check_launch(c, "k_micsa_sweep_fused");
     if (st) return st;
@@ -1429,6 +1429,10 @@ int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value)
     case MICSA_OPT_GRAPHS:
         if (value != 0 && value != 1) return fail(ctx, MICSA_EINVAL, "graphs is 0 or 1");
         ctx->use_graphs = (int32_t)value;
+        return MICSA_OK;
+    case MICSA_OPT_PREFETCH:
+        if (value != 1 && value != 2) return fail(ctx, MICSA_EINVAL, "prefetch is 1 or 2");
+        ctx->prefetch = (int32_t)value;
         return MICSA_OK;
     case MICSA_OPT_XCD_MAP:
         if (value != 0 && value != 1) return fail(ctx, MICSA_EINVAL, "xcd_map is 0 or 1");

@@ -168,12 +168,17 @@ def test_batched_L32_shape():
     same_state(g, o)
 
 
-def test_anneal_L512_first_sweeps_full_size():
+@pytest.mark.parametrize("prefetch", [1, 2])
+def test_anneal_L512_first_sweeps_full_size(prefetch):
     """L = 512 (134M spins), linear 3.0 -> 0.2 over 10^4 sweeps, refresh every 20:
-    the first 21 sweeps (two refreshes) bit-exact at full size."""
+    the first 21 sweeps (two refreshes) bit-exact at full size, with the
+    fused sweep's benchmark tile at both prefetch depths."""
     w = W.ANNEAL_L512
     n = 21
     g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
+    g.set_option(M.OPT_TILE_Y, 32)
+    g.set_option(M.OPT_TILE_Z, 32)
+    g.set_option(M.OPT_PREFETCH, prefetch)
     gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
     g.set_schedule(gs)
     Eg, Dg = g.sweep_logged(M.ALGO_MICSA, n, 7)
@@ -361,13 +366,14 @@ def test_every_launch_shape_gives_the_same_bits():
     shape = (64, 16, 12, 1, 2)
     n = 30
     ref = None
-    variants = [(M.KERNEL_SIMPLE, 0, 0, 1), (M.KERNEL_RESIDENT, 0, 0, 1)] + [
-        (M.KERNEL_FUSED, ty, tz, 1) for ty in (1, 2, 4, 8, 16) for tz in (1, 3, 4, 12)] + [
-        (M.KERNEL_FUSED, 1, 3, 0), (M.KERNEL_FUSED, 4, 1, 0)]
-    for kern, ty, tz, xcd in variants:
+    variants = [(M.KERNEL_SIMPLE, 0, 0, 1, 1), (M.KERNEL_RESIDENT, 0, 0, 1, 1)] + [
+        (M.KERNEL_FUSED, ty, tz, 1, pf) for ty in (1, 2, 4, 8, 16) for tz in (1, 3, 4, 12) for pf in (1, 2)] + [
+        (M.KERNEL_FUSED, 1, 3, 0, 1), (M.KERNEL_FUSED, 4, 1, 0, 2)]
+    for kern, ty, tz, xcd, pf in variants:
         g = M.Lattice(*shape, seed=2024)
         g.set_option(M.OPT_SWEEP_KERNEL, kern)
         g.set_option(M.OPT_XCD_MAP, xcd)
+        g.set_option(M.OPT_PREFETCH, pf)
         if ty:
             g.set_option(M.OPT_TILE_Y, ty)
             g.set_option(M.OPT_TILE_Z, tz)
@@ -378,7 +384,7 @@ def test_every_launch_shape_gives_the_same_bits():
             ref = got
         else:
             for a, b in zip(ref, got):
-                assert np.array_equal(a, b), (kern, ty, tz, xcd)
+                assert np.array_equal(a, b), (kern, ty, tz, xcd, pf)
         g.close()
 
 
