@@ -49,7 +49,8 @@ enum micsa_status {
 };
 
 enum micsa_layout {
-    MICSA_LAYOUT_BYTE = 0,    /* one byte per spin and per daemon, bit-planes for couplings */
+    MICSA_LAYOUT_BYTE = 0,    /* one byte per spin and per daemon; an even site's spin byte also
+                                 holds the coupling bits of its six bonds */
     MICSA_LAYOUT_BITPLANE = 1 /* multispin coding: 64 samples per 64-bit word (Sec. 2.5, App. B) */
 };
 

@@ -159,8 +159,7 @@ __global__ void __launch_bounds__(256) kb_refresh(GeomB b, uint64_t* __restrict_
         o = philox10((uint32_t)t, rho, (uint32_t)r, stream_word(kStreamDaemon, s), g.key0, g.key1);
     ballot4(g, live ? 4 * t : 0, o,
             [&](uint32_t u, uint32_t& b0, uint32_t& b1) {
-                const uint64_t v = u;
-                const uint32_t m = (uint32_t)(v >= th.t0) + (uint32_t)(v >= th.t1) + (uint32_t)(v >= th.t2);
+                const uint32_t m = daemon_level(u, th);
                 b0 = m & 1u;
                 b1 = m >> 1;
             },
@@ -187,8 +186,7 @@ __global__ void __launch_bounds__(256) kb_refresh_dev(GeomB b, uint64_t* __restr
         o = philox10((uint32_t)t, (uint32_t)rho, (uint32_t)r, stream_word(kStreamDaemon, s), g.key0, g.key1);
     ballot4(g, live ? 4 * t : 0, o,
             [&](uint32_t u, uint32_t& b0, uint32_t& b1) {
-                const uint64_t v = u;
-                const uint32_t m = (uint32_t)(v >= th.t0) + (uint32_t)(v >= th.t1) + (uint32_t)(v >= th.t2);
+                const uint32_t m = daemon_level(u, th);
                 b0 = m & 1u;
                 b1 = m >> 1;
             },

@@ -8,16 +8,19 @@
 namespace micsa {
 
 // Neighbourhood of a 4-site word (sites h0 .. h0+3 of parity P in row (y,z)):
-// the six words of opposite-parity neighbours and the six coupling nibbles of
-// the bonds to them, in matching order (A = same k, B = k +- 1 in the row).
+// the spin bits of the six opposite-parity neighbours and the coupling bits of
+// the bonds to them, in matching order (A = same k, B = k +- 1 in the row),
+// each as one bit per byte.  The coupling bits of a bond live in the spin
+// byte of its even end (geometry.hpp): for P = 0 in `own`, the word being
+// updated, for P = 1 in the neighbour words themselves.
 struct Nbhd {
     uint32_t nb[6];
     uint32_t jb[6];
 };
 
 template <int P>
-__device__ __forceinline__ Nbhd gather(const Geom& g, const uint32_t* __restrict__ oth,
-                                       const uint32_t* __restrict__ Js, int row, int c)
+__device__ __forceinline__ Nbhd gather(const Geom& g, uint32_t own, const uint32_t* __restrict__ oth, int row,
+                                       int c)
 {
     const int z = (int)((uint32_t)row / (uint32_t)g.Ly), y = row - z * g.Ly;
     const int q = (y + z) & 1;
@@ -27,21 +30,24 @@ __device__ __forceinline__ Nbhd gather(const Geom& g, const uint32_t* __restrict
     const int zp = z + 1 == g.Lz ? 0 : z + 1, zm = z == 0 ? g.Lz - 1 : z - 1;
     const int r_yp = yp + g.Ly * z, r_ym = ym + g.Ly * z, r_zp = y + g.Ly * zp, r_zm = y + g.Ly * zm;
     const int64_t wr = g.Wr;
+    const uint32_t m1 = 0x01010101u;
+    uint32_t w[6];
+    w[0] = oth[row * wr + c];
+    w[1] = shift_word(w[0], oth[row * wr + cs], dir);
+    w[2] = oth[r_yp * wr + c];
+    w[3] = oth[r_ym * wr + c];
+    w[4] = oth[r_zp * wr + c];
+    w[5] = oth[r_zm * wr + c];
     Nbhd n;
-    const uint32_t A = oth[row * wr + c];
-    n.nb[0] = A;
-    n.nb[1] = shift_word(A, oth[row * wr + cs], dir);
-    n.nb[2] = oth[r_yp * wr + c];
-    n.nb[3] = oth[r_ym * wr + c];
-    n.nb[4] = oth[r_zp * wr + c];
-    n.nb[5] = oth[r_zm * wr + c];
+#pragma unroll
+    for (int d = 0; d < 6; ++d) n.nb[d] = w[d] & m1;
     // The same-k neighbour A is across bond (q ? -x : +x) of the even site at
     // A's position, the shifted neighbour B across (q ? +x : -x); this holds
     // for both parities because the even site is at x = 2k + q.
     const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
     if (P == 0) {
         // even sites own all six of their bonds
-        const uint32_t jw = Js[row * wr + c];
+        const uint32_t jw = own >> 1;
         n.jb[0] = jbits(jw, dA);
         n.jb[1] = jbits(jw, dB);
         n.jb[2] = jbits(jw, kPy);
@@ -50,23 +56,25 @@ __device__ __forceinline__ Nbhd gather(const Geom& g, const uint32_t* __restrict
         n.jb[5] = jbits(jw, kMz);
     } else {
         // odd sites read each bond from the even neighbour's opposite slot
-        const uint32_t jA = Js[row * wr + c];
-        n.jb[0] = jbits(jA, dA);
-        n.jb[1] = jbits(shift_word(jA, Js[row * wr + cs], dir), dB);
-        n.jb[2] = jbits(Js[r_yp * wr + c], kMy);
-        n.jb[3] = jbits(Js[r_ym * wr + c], kPy);
-        n.jb[4] = jbits(Js[r_zp * wr + c], kMz);
-        n.jb[5] = jbits(Js[r_zm * wr + c], kPz);
+        n.jb[0] = jbits(w[0] >> 1, dA);
+        n.jb[1] = jbits(w[1] >> 1, dB);
+        n.jb[2] = jbits(w[2] >> 1, kMy);
+        n.jb[3] = jbits(w[3] >> 1, kPy);
+        n.jb[4] = jbits(w[4] >> 1, kMz);
+        n.jb[5] = jbits(w[5] >> 1, kPz);
     }
     return n;
 }
 
 // ------------------------------------------------------------------ init
-// Thread per 4 even sites: the six bond bits of each even site from the
-// forward-bond draws j_mu(i) = Philox(i, 0, 0, stream J | s)[mu] >> 31.
-__global__ void k_init_couplings(Geom g, uint32_t* __restrict__ J)
+// Thread per 4 even sites of lattice l: the six bond bits of each even site
+// from the forward-bond draws j_mu(i) = Philox(i, 0, 0, stream J | s)[mu] >> 31,
+// written into bits 1..6 of its spin byte (bit 0, the spin, is kept).  Every
+// replica of a sample carries the same bits.
+__global__ void k_init_couplings(Geom g, uint8_t* __restrict__ spin)
 {
-    const int s = blockIdx.y;
+    const int l = blockIdx.y;
+    const int s = l / g.R;
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= g.Nh / 4) return;
     const uint32_t sw = stream_word(kStreamCoupling, (uint32_t)s);
@@ -90,7 +98,8 @@ __global__ void k_init_couplings(Geom g, uint32_t* __restrict__ J)
                               ((fwd(x, y, z - 1).v2 >> 31) << kMz);
         word |= byte << (8 * b);
     }
-    J[(int64_t)s * (g.Nh / 4) + t] = word;
+    uint32_t* ev = reinterpret_cast<uint32_t*>(spin + (int64_t)l * 2 * g.Nh);
+    ev[t] = (ev[t] & 0x01010101u) | (word << 1);
 }
 
 // Thread per 8 consecutive natural sites i0 .. i0+7 (same row since Lx % 8 == 0):
@@ -149,10 +158,7 @@ __global__ void k_refresh(Geom g, uint8_t* __restrict__ dem, uint32_t rho, Daemo
     const u32x4 b = philox10(c0 + 1u, rho, (uint32_t)r, sw, g.key0, g.key1);
     uint32_t we, wo;
     split8(g, i0, a, b,
-           [&](uint32_t u) {
-               const uint64_t v = u;
-               return (uint32_t)(v >= th.t0) + (uint32_t)(v >= th.t1) + (uint32_t)(v >= th.t2);
-           },
+           [&](uint32_t u) { return daemon_level(u, th); },
            we, wo);
     reinterpret_cast<uint32_t*>(dem + ((int64_t)d * 2 + 0) * g.Nh)[t] = we;
     reinterpret_cast<uint32_t*>(dem + ((int64_t)d * 2 + 1) * g.Nh)[t] = wo;
@@ -189,10 +195,7 @@ __global__ void k_refresh_dev(Geom g, uint8_t* __restrict__ dem, const int64_t* 
     const u32x4 b = philox10((uint32_t)(i0 >> 2) + 1u, (uint32_t)rho, (uint32_t)r, sw, g.key0, g.key1);
     uint32_t we, wo;
     split8(g, i0, a, b,
-           [&](uint32_t u) {
-               const uint64_t v = u;
-               return (uint32_t)(v >= th.t0) + (uint32_t)(v >= th.t1) + (uint32_t)(v >= th.t2);
-           },
+           [&](uint32_t u) { return daemon_level(u, th); },
            we, wo);
     reinterpret_cast<uint32_t*>(dem + ((int64_t)l * 2 + 0) * g.Nh)[t] = we;
     reinterpret_cast<uint32_t*>(dem + ((int64_t)l * 2 + 1) * g.Nh)[t] = wo;
@@ -227,11 +230,9 @@ __device__ __forceinline__ void micsa_word(uint32_t& S, uint32_t& M, const Nbhd&
 template <int P>
 __global__ void __launch_bounds__(256) k_micsa_half(Geom g, uint8_t* __restrict__ spin,
                                                     uint8_t* __restrict__ dem,
-                                                    const uint32_t* __restrict__ J,
                                                     unsigned long long* __restrict__ tally, int fam)
 {
     const int l = blockIdx.y;
-    const int s = l / g.R;
     const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
     int dE = 0;
     if (w < (uint32_t)g.rows * (uint32_t)g.Wr) {
@@ -239,10 +240,12 @@ __global__ void __launch_bounds__(256) k_micsa_half(Geom g, uint8_t* __restrict_
         uint32_t* own = reinterpret_cast<uint32_t*>(spin + ((int64_t)l * 2 + P) * g.Nh);
         const uint32_t* oth = reinterpret_cast<const uint32_t*>(spin + ((int64_t)l * 2 + (1 - P)) * g.Nh);
         uint32_t* dm = reinterpret_cast<uint32_t*>(dem + (((int64_t)l * g.gamma + fam) * 2 + P) * g.Nh);
-        const Nbhd n = gather<P>(g, oth, J + (int64_t)s * (g.Nh / 4), row, c);
-        uint32_t S = own[w], M = dm[w];
+        const uint32_t W0 = own[w];
+        const Nbhd n = gather<P>(g, W0, oth, row, c);
+        const uint32_t S0 = W0 & 0x01010101u;  // spin bits (even bytes also hold their bonds)
+        uint32_t S = S0, M = dm[w];
         micsa_word(S, M, n, dE);
-        own[w] = S;
+        own[w] = W0 ^ S ^ S0;
         dm[w] = M;
     }
     block_add(tally + (int64_t)l * kSlots, dE);
@@ -290,8 +293,7 @@ __device__ __forceinline__ uint32_t canonical_stream(uint32_t s)
 // With dk != nullptr the sweep index k = *dk and the table of refresh rho(k)
 // comes from device memory (replayable graphs); otherwise from the arguments.
 template <int P, int ALG>
-__global__ void __launch_bounds__(256) k_heatbath_half(Geom g, uint8_t* __restrict__ spin,
-                                                       const uint32_t* __restrict__ J, uint32_t time,
+__global__ void __launch_bounds__(256) k_heatbath_half(Geom g, uint8_t* __restrict__ spin, uint32_t time,
                                                        HeatBathThresholds th,
                                                        unsigned long long* __restrict__ tally,
                                                        const int64_t* __restrict__ dk, int32_t period,
@@ -314,12 +316,14 @@ __global__ void __launch_bounds__(256) k_heatbath_half(Geom g, uint8_t* __restri
         const int row = (int)(w / (uint32_t)g.Wr), c = (int)(w - (uint32_t)row * (uint32_t)g.Wr);
         uint32_t* own = reinterpret_cast<uint32_t*>(spin + ((int64_t)l * 2 + P) * g.Nh);
         const uint32_t* oth = reinterpret_cast<const uint32_t*>(spin + ((int64_t)l * 2 + (1 - P)) * g.Nh);
-        const Nbhd n = gather<P>(g, oth, J + (int64_t)s * (g.Nh / 4), row, c);
+        const uint32_t W0 = own[w];
+        const Nbhd n = gather<P>(g, W0, oth, row, c);
         uint32_t v = 0;
 #pragma unroll
         for (int d = 0; d < 6; ++d) v += n.nb[d] ^ n.jb[d];
         const u32x4 rnd = philox10(w, time, (uint32_t)r, canonical_stream<ALG>((uint32_t)s), g.key0, g.key1);
-        own[w] = canonical4<ALG>(own[w], v, rnd, tau, dE);
+        // new spin bits; the bond bits of even bytes are kept
+        own[w] = canonical4<ALG>(W0, v, rnd, tau, dE) | (W0 & ~0x01010101u);
     }
     block_add(tally + (int64_t)l * kSlots, dE);
 }
@@ -380,19 +384,18 @@ __global__ void __launch_bounds__(256) k_wander(Geom g, const uint8_t* __restric
 // U = number of unsatisfied bonds, counted once each from the even end;
 // H = 2U - 3N (eq. Hamiltonian).  Adds U to the slots of lattice l.
 __global__ void __launch_bounds__(256) k_unsat_bonds(Geom g, const uint8_t* __restrict__ spin,
-                                                     const uint32_t* __restrict__ J,
                                                      unsigned long long* __restrict__ out)
 {
     const int l = blockIdx.y;
-    const int s = l / g.R;
     const uint32_t w = blockIdx.x * blockDim.x + threadIdx.x;
     int U = 0;
     if (w < (uint32_t)g.rows * (uint32_t)g.Wr) {
         const int row = (int)(w / (uint32_t)g.Wr), c = (int)(w - (uint32_t)row * (uint32_t)g.Wr);
         const uint32_t* ev = reinterpret_cast<const uint32_t*>(spin + ((int64_t)l * 2 + 0) * g.Nh);
         const uint32_t* od = reinterpret_cast<const uint32_t*>(spin + ((int64_t)l * 2 + 1) * g.Nh);
-        const Nbhd n = gather<0>(g, od, J + (int64_t)s * (g.Nh / 4), row, c);
-        const uint32_t S = ev[w];
+        const uint32_t W0 = ev[w];
+        const Nbhd n = gather<0>(g, W0, od, row, c);
+        const uint32_t S = W0 & 0x01010101u;
         uint32_t u = 0;
 #pragma unroll
         for (int d = 0; d < 6; ++d) u += xor3(S, n.nb[d], n.jb[d]);
@@ -423,7 +426,7 @@ __global__ void __launch_bounds__(256) k_differ_count(int64_t words_per_lattice,
     if (w < words_per_lattice) {
         const uint32_t xa = spin[((int64_t)s * R + a) * words_per_lattice + w];
         const uint32_t xb = spin[((int64_t)s * R + b) * words_per_lattice + w];
-        v = (int)__popc(xa ^ xb);
+        v = (int)__popc((xa ^ xb) & 0x01010101u);  // spin bits only
     }
     block_add(out + (int64_t)s * kSlots, v);
 }

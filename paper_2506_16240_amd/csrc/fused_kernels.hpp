@@ -150,10 +150,7 @@ __device__ __forceinline__ void refresh_chunk(const Geom& g, int row, int c, int
         // even site t = 8i + q + {0,2,4,6} of the 32; odd site t = 8i + (1-q) + {0,2,4,6}
         const uint32_t da[4] = {a.v0, a.v1, a.v2, a.v3};
         const uint32_t db[4] = {b.v0, b.v1, b.v2, b.v3};
-        auto lvl = [&](uint32_t u) {
-            const uint64_t v = u;
-            return (uint32_t)(v >= th.t0) + (uint32_t)(v >= th.t1) + (uint32_t)(v >= th.t2);
-        };
+        auto lvl = [&](uint32_t u) { return daemon_level(u, th); };
         const int qe = q, qo = 1 - q;
         Me.w[i] = lvl(da[qe]) | (lvl(da[qe + 2]) << 8) | (lvl(db[qe]) << 16) | (lvl(db[qe + 2]) << 24);
         Mo.w[i] = lvl(da[qo]) | (lvl(da[qo + 2]) << 8) | (lvl(db[qo]) << 16) | (lvl(db[qo + 2]) << 24);
@@ -162,7 +159,7 @@ __device__ __forceinline__ void refresh_chunk(const Geom& g, int row, int c, int
 
 // Inputs of one step of the march (global loads issued ahead of use).
 struct StepIn {
-    V4 So, Se, Jw, Me, Mo;
+    V4 So, Se, Me, Mo;
 };
 
 // PF = steps of loads in flight: 1, or 2 with two input sets used
@@ -175,8 +172,8 @@ constexpr int kPf2Lanes = 640;
 template <bool REFRESH, int PF>
 __global__ void __launch_bounds__(PF == 2 ? kPf2Lanes : 1024) k_micsa_sweep_fused(
     Geom g, FusedTile f, const uint8_t* __restrict__ spin_in, const uint8_t* __restrict__ dem_in,
-    uint8_t* __restrict__ spin_out, uint8_t* __restrict__ dem_out, const uint32_t* __restrict__ J,
-    unsigned long long* __restrict__ tally, uint32_t rho, DaemonThresholds th)
+    uint8_t* __restrict__ spin_out, uint8_t* __restrict__ dem_out, unsigned long long* __restrict__ tally,
+    uint32_t rho, DaemonThresholds th)
 {
     extern __shared__ uint4 lds[];
     const int rows_slots = f.TY + 4;
@@ -209,7 +206,6 @@ __global__ void __launch_bounds__(PF == 2 ? kPf2Lanes : 1024) k_micsa_sweep_fuse
     uint8_t* od_out = spin_out + ((int64_t)l * 2 + 1) * g.Nh;
     uint8_t* me_out = dem_out + ((int64_t)l * 2 + 0) * g.Nh;
     uint8_t* mo_out = dem_out + ((int64_t)l * 2 + 1) * g.Nh;
-    const uint8_t* Jb = reinterpret_cast<const uint8_t*>(J) + (int64_t)s * g.Nh;  // coupling bytes
     const uint32_t sw = stream_word(kStreamDaemon, (uint32_t)s);
 
     auto wrapz = [&](int z) { return z < 0 ? z + g.Lz : (z >= g.Lz ? z - g.Lz : z); };
@@ -227,8 +223,7 @@ __global__ void __launch_bounds__(PF == 2 ? kPf2Lanes : 1024) k_micsa_sweep_fuse
         if (active) in.So = ldg16(od_in + hof(wrapz(z2 + dz)));
         if (do_even) {
             const int64_t h2 = hof(z2);
-            in.Se = ldg16(ev_in + h2);
-            in.Jw = ldg16(Jb + h2);
+            in.Se = ldg16(ev_in + h2);  // even spins with their bond bits
             if (!REFRESH) in.Me = ldg16(me_in + h2);
         }
         if (!REFRESH && do_odd && st2 >= 2) in.Mo = ldg16(mo_in + hof(wrapz(z2 - dz)));
@@ -246,7 +241,7 @@ __global__ void __launch_bounds__(PF == 2 ? kPf2Lanes : 1024) k_micsa_sweep_fuse
         const int z = wrapz(zstart + dz * st);
         const int64_t h = hof(z);
         So_next = in.So;
-        V4 Se = in.Se, Jw = in.Jw, Me = in.Me, Mo = in.Mo;
+        V4 Se = in.Se, Me = in.Me, Mo = in.Mo;
         V4 Mo_next{};
         if (st + PF < steps) load_step(in, st + PF);
         if (REFRESH && do_even) refresh_chunk(g, y + g.Ly * z, c, (y + z) & 1, rho, (uint32_t)r, sw, th, Me, Mo_next);
@@ -278,16 +273,17 @@ __global__ void __launch_bounds__(PF == 2 ? kPf2Lanes : 1024) k_micsa_sweep_fuse
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 // bit d of v = old spin ^ j_d: the bond term for neighbour nb is nb ^ ((v >> d) & 1)
-                uint32_t S = Se.w[i];
-                const uint32_t v = ((S << 6) - S) ^ Jw.w[i];
                 const uint32_t m1 = 0x01010101u;
+                const uint32_t W = Se.w[i];  // spin in bit 0, bond d in bit 1 + d
+                uint32_t S = W & m1;
+                const uint32_t v = xor_and((S << 6) - S, W >> 1, 0x3F3F3F3Fu);
                 const uint32_t u = xor_and(A.w[i], v >> dA, m1) + xor_and(B.w[i], v >> dB, m1) +
                                    xor_and(Yp.w[i], v >> kPy, m1) + xor_and(Ym.w[i], v >> kMy, m1) +
                                    xor_and(Sz_up.w[i], v >> kPz, m1) + xor_and(Sz_dn.w[i], v >> kMz, m1);
                 const uint32_t S0 = S;
                 creutz4(S, Me.w[i], u, so, sn);
-                Se.w[i] = S;
                 const uint32_t flip = S ^ S0;
+                Se.w[i] = W ^ flip;
                 Xn.w[i] = v ^ ((flip << 6) - flip);  // even view: bit d = new spin ^ j_d
             }
             X_cur = Xn;
@@ -349,7 +345,7 @@ __global__ void __launch_bounds__(PF == 2 ? kPf2Lanes : 1024) k_micsa_sweep_fuse
 template <int ALG>
 __global__ void __launch_bounds__(1024) k_heatbath_sweep_fused(
     Geom g, FusedTile f, const uint8_t* __restrict__ spin_in, uint8_t* __restrict__ spin_out,
-    const uint32_t* __restrict__ J, unsigned long long* __restrict__ tally, uint32_t time0, HeatBathThresholds th)
+    unsigned long long* __restrict__ tally, uint32_t time0, HeatBathThresholds th)
 {
     extern __shared__ uint4 lds[];
     __shared__ uint64_t tau[8];
@@ -375,7 +371,6 @@ __global__ void __launch_bounds__(1024) k_heatbath_sweep_fused(
     const uint8_t* od_in = spin_in + ((int64_t)l * 2 + 1) * g.Nh;
     uint8_t* ev_out = spin_out + ((int64_t)l * 2 + 0) * g.Nh;
     uint8_t* od_out = spin_out + ((int64_t)l * 2 + 1) * g.Nh;
-    const uint8_t* Jb = reinterpret_cast<const uint8_t*>(J) + (int64_t)s * g.Nh;
     const uint32_t sw = canonical_stream<ALG>((uint32_t)s);
 
     auto wrapz = [&](int z) { return z < 0 ? z + g.Lz : (z >= g.Lz ? z - g.Lz : z); };
@@ -385,14 +380,13 @@ __global__ void __launch_bounds__(1024) k_heatbath_sweep_fused(
 
     V4 So_prev{}, So_cur{}, So_next{};
     V4 X_prev2{}, X_prev{}, X_cur{};
-    V4 nSo{}, nSe{}, nJw{};
+    V4 nSo{}, nSe{};
     auto load_step = [&](int st2) {
         const int z2 = wrapz(z0 - 1 + st2);
         if (active) nSo = ldg16(od_in + hof(wrapz(z2 + 1)));
         if (do_even) {
             const int64_t h2 = hof(z2);
             nSe = ldg16(ev_in + h2);
-            nJw = ldg16(Jb + h2);
         }
     };
     if (active) {
@@ -406,7 +400,7 @@ __global__ void __launch_bounds__(1024) k_heatbath_sweep_fused(
         const int z = wrapz(z0 - 1 + st);
         const int64_t h = hof(z);
         So_next = nSo;
-        V4 Se = nSe, Jw = nJw;
+        V4 Se = nSe;
         if (st + 1 < steps) load_step(st + 1);
         const bool odd_now = do_odd && st >= 2;
         const int zo = wrapz(z - 1);
@@ -428,15 +422,16 @@ __global__ void __launch_bounds__(1024) k_heatbath_sweep_fused(
             V4 Xn;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const uint32_t jw = Jw.w[i];
                 const uint32_t m1 = 0x01010101u;
+                const uint32_t W = Se.w[i];  // spin in bit 0, bond d in bit 1 + d
+                const uint32_t jw = (W >> 1) & 0x3F3F3F3Fu;
                 const uint32_t v = xor_and(A.w[i], jw >> dA, m1) + xor_and(B.w[i], jw >> dB, m1) +
                                    xor_and(Yp.w[i], jw >> kPy, m1) + xor_and(Ym.w[i], jw >> kMy, m1) +
                                    xor_and(So_next.w[i], jw >> kPz, m1) + xor_and(So_prev.w[i], jw >> kMz, m1);
                 const uint32_t ctr = (uint32_t)((h >> 2) + i);
                 const u32x4 rnd = philox10(ctr, time0, (uint32_t)r, sw, g.key0, g.key1);
-                const uint32_t S = canonical4<ALG>(Se.w[i], v, rnd, tau, dEe);
-                Se.w[i] = S;
+                const uint32_t S = canonical4<ALG>(W, v, rnd, tau, dEe);
+                Se.w[i] = S | (W & ~m1);
                 Xn.w[i] = ((S << 6) - S) ^ jw;
             }
             X_cur = Xn;

@@ -13,10 +13,12 @@
 //   neighbours as whole words (or one byte-shifted word).
 //   daemon[l][a][p][h] for the gamma daemon (walker) families a of a site.
 //   Couplings: every bond joins an even and an odd site, so each bond is
-//   stored once, with its even end: one byte per even site whose bit d is the
-//   coupling bit of its bond in direction d = +x, -x, +y, -y, +z, -z
-//   (J[s][h], 6 bits used).  Four even sites' bytes form a 32-bit word in the
-//   same SWAR order as their spins, so bond d of 4 sites is (word >> d) & 0x01010101.
+//   stored once, with its even end, in the even site's spin byte: bit 0 is
+//   the spin, bit 1 + d the coupling bit of its bond in direction d = +x, -x,
+//   +y, -y, +z, -z.  Odd spin bytes hold the spin only.  A sweep reads and
+//   writes the spin bytes anyway, so the couplings cost no extra traffic;
+//   every replica of a sample carries the same bits.  Four even bytes form a
+//   32-bit word, so bond d of 4 sites is (word >> (1 + d)) & 0x01010101.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -43,6 +45,15 @@ struct DaemonThresholds {
     uint64_t t0, t1, t2;
 };
 
+// m = #{k : u >= t_k} in 32-bit compares.  Every t_k lies in [2^30, 2^32]:
+// P(m <= 0) = 1 / (1 + x + x^2 + x^3) >= 1/4 with x = e^{-4 beta} in (0, 1),
+// so t_k - 1 fits 32 bits and u >= t_k  <=>  u > t_k - 1.
+__device__ __forceinline__ uint32_t daemon_level(uint32_t u, const DaemonThresholds& th)
+{
+    return (uint32_t)(u > (uint32_t)(th.t0 - 1u)) + (uint32_t)(u > (uint32_t)(th.t1 - 1u)) +
+           (uint32_t)(u > (uint32_t)(th.t2 - 1u));
+}
+
 struct HeatBathThresholds {
     uint64_t tau[7];
 };
@@ -55,7 +66,8 @@ using MetropolisThresholds = HeatBathThresholds;
 // Byte-wise sum of a 32-bit word whose bytes add up to less than 256.
 __device__ __forceinline__ uint32_t bytesum(uint32_t v) { return (v * 0x01010101u) >> 24; }
 
-// Coupling bits of bond d for the 4 sites of a word of coupling bytes.
+// Coupling bits of bond d for the 4 sites of a word of bond bytes (the even
+// spin bytes shifted right by one).
 __device__ __forceinline__ uint32_t jbits(uint32_t jw, int d) { return (jw >> d) & 0x01010101u; }
 
 // Same shift for a word of 4 byte-sites.

@@ -71,7 +71,6 @@ struct micsa_ctx {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec[kAlgos] = {};
     const void* gkey[kAlgos] = {};  // state buffer the graph was captured with
-    uint32_t* J = nullptr;    // [S][Nh] coupling bytes of the even sites
     unsigned long long* tally = nullptr;  // [L][kSlots]
     unsigned long long* red = nullptr;    // [max(L, S)][kSlots] reduction scratch
     Schedule sched;
@@ -371,7 +370,7 @@ int launch_fused_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
         const bool pf2 = c->prefetch == 2 && block <= kPf2Lanes;  // larger tiles run the one-step variant
         const auto kern = refresh ? (pf2 ? k_micsa_sweep_fused<true, 2> : k_micsa_sweep_fused<true, 1>)
                                   : (pf2 ? k_micsa_sweep_fused<false, 2> : k_micsa_sweep_fused<false, 1>);
-        kern<<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->dem, c->spin_alt, c->dem_alt, c->J, c->tally,
+        kern<<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->dem, c->spin_alt, c->dem_alt, c->tally,
                                               (uint32_t)rho, th);
     }
     const int st = check_launch(c, "k_micsa_sweep_fused");
@@ -387,14 +386,14 @@ int launch_micsa_sweep(micsa_ctx* c, int fam)
     const int64_t words = (int64_t)c->g.rows * c->g.Wr;
     {
         TimedLaunch t(c, kTimeSweep);
-        k_micsa_half<0><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally,
+        k_micsa_half<0><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->dem, c->tally,
                                                                           fam);
     }
     int st = check_launch(c, "k_micsa_half<0>");
     if (st) return st;
     {
         TimedLaunch t(c, kTimeSweep);
-        k_micsa_half<1><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally,
+        k_micsa_half<1><<<grid_for(words, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->dem, c->tally,
                                                                           fam);
     }
     return check_launch(c, "k_micsa_half<1>");
@@ -410,10 +409,10 @@ int launch_fused_canonical(micsa_ctx* c, int32_t algo, int64_t k, double T)
     {
         TimedLaunch t(c, canonical_timing(algo));
         if (algo == MICSA_ALGO_METROPOLIS)
-            k_heatbath_sweep_fused<1><<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->spin_alt, c->J, c->tally,
+            k_heatbath_sweep_fused<1><<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->spin_alt, c->tally,
                                                                        (uint32_t)(2 * k), metropolis_thresholds(T));
         else
-            k_heatbath_sweep_fused<0><<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->spin_alt, c->J, c->tally,
+            k_heatbath_sweep_fused<0><<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->spin_alt, c->tally,
                                                                        (uint32_t)(2 * k), heatbath_thresholds(T));
     }
     const int st = check_launch(c, "k_heatbath_sweep_fused");
@@ -433,9 +432,9 @@ void enqueue_canonical_half(micsa_ctx* c, int32_t algo, hipStream_t st, int64_t 
     const uint32_t time = (uint32_t)(2 * k + P);
     const int32_t period = c->sched.period;
     if (algo == MICSA_ALGO_METROPOLIS)
-        k_heatbath_half<P, 1><<<grid, kBlock, 0, st>>>(c->g, c->spin, c->J, time, th, c->tally, dk, period, c->d_mth);
+        k_heatbath_half<P, 1><<<grid, kBlock, 0, st>>>(c->g, c->spin, time, th, c->tally, dk, period, c->d_mth);
     else
-        k_heatbath_half<P, 0><<<grid, kBlock, 0, st>>>(c->g, c->spin, c->J, time, th, c->tally, dk, period, c->d_hth);
+        k_heatbath_half<P, 0><<<grid, kBlock, 0, st>>>(c->g, c->spin, time, th, c->tally, dk, period, c->d_hth);
 }
 
 int launch_canonical_sweep(micsa_ctx* c, int32_t algo, int64_t k, double T)
@@ -455,6 +454,13 @@ int launch_canonical_sweep(micsa_ctx* c, int32_t algo, int64_t k, double T)
     return check_launch(c, "k_heatbath_half<1>");
 }
 
+// Bond bits of every lattice into its even spin bytes (spins kept).
+int enqueue_bonds(micsa_ctx* c)
+{
+    k_init_couplings<<<grid_for(c->g.Nh / 4, c->L), kBlock, 0, c->stream>>>(c->g, c->spin);
+    return check_launch(c, "k_init_couplings");
+}
+
 // Enqueue: dst[l] = from-scratch H^EA of lattice l.
 int enqueue_energy(micsa_ctx* c, unsigned long long* dst)
 {
@@ -462,7 +468,7 @@ int enqueue_energy(micsa_ctx* c, unsigned long long* dst)
     int st = zero_slots(c, dst, c->L);
     if (st) return st;
     TimedLaunch t(c, kTimeReduce);
-    k_unsat_bonds<<<grid_for((int64_t)c->g.rows * c->g.Wr, c->L), kBlock, 0, c->stream>>>(c->g, c->spin, c->J,
+    k_unsat_bonds<<<grid_for((int64_t)c->g.rows * c->g.Wr, c->L), kBlock, 0, c->stream>>>(c->g, c->spin,
                                                                                            dst);
     return check_launch(c, "k_unsat_bonds");
 }
@@ -525,13 +531,13 @@ int launch_resident(micsa_ctx* c, int32_t algo, int64_t n, long long* dlog, int6
         {
             TimedLaunch t(c, tkind);
             if (inst == 0)
-                k_resident<0><<<c->L, kResidentBlock, lds, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally, rs,
+                k_resident<0><<<c->L, kResidentBlock, lds, c->stream>>>(c->g, c->spin, c->dem, c->tally, rs,
                                                                         c->d_dth, tab, dlog);
             else if (inst == 1)
-                k_resident<1><<<c->L, kResidentBlock, lds, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally, rs,
+                k_resident<1><<<c->L, kResidentBlock, lds, c->stream>>>(c->g, c->spin, c->dem, c->tally, rs,
                                                                         c->d_dth, tab, dlog);
             else
-                k_resident<2><<<c->L, kResidentBlock, lds, c->stream>>>(c->g, c->spin, c->dem, c->J, c->tally, rs,
+                k_resident<2><<<c->L, kResidentBlock, lds, c->stream>>>(c->g, c->spin, c->dem, c->tally, rs,
                                                                         c->d_dth, tab, dlog);
         }
         const int st = check_launch(c, "k_resident");
@@ -571,8 +577,8 @@ int enqueue_dev_sweep(micsa_ctx* c, int32_t algo, hipStream_t st)
         const int64_t words = (int64_t)c->g.rows * c->g.Wr;
         if (algo == MICSA_ALGO_MICSA) {
             k_refresh_dev<<<grid_for(c->g.Nh / 4, c->L), kBlock, 0, st>>>(c->g, c->dem, c->d_k, P, c->d_dth);
-            k_micsa_half<0><<<grid_for(words, c->L), kBlock, 0, st>>>(c->g, c->spin, c->dem, c->J, c->tally, 0);
-            k_micsa_half<1><<<grid_for(words, c->L), kBlock, 0, st>>>(c->g, c->spin, c->dem, c->J, c->tally, 0);
+            k_micsa_half<0><<<grid_for(words, c->L), kBlock, 0, st>>>(c->g, c->spin, c->dem, c->tally, 0);
+            k_micsa_half<1><<<grid_for(words, c->L), kBlock, 0, st>>>(c->g, c->spin, c->dem, c->tally, 0);
         } else {
             const HeatBathThresholds none{};
             enqueue_canonical_half<0>(c, algo, st, 0, none, c->d_k);
@@ -706,7 +712,6 @@ void free_all(micsa_ctx* c)
         if (e) (void)hipGraphExecDestroy(e);
     if (c->d_k) (void)hipFree(c->d_k);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    if (c->J) (void)hipFree(c->J);
     if (c->tally) (void)hipFree(c->tally);
     if (c->red) (void)hipFree(c->red);
     for (auto& v : c->events)
@@ -788,10 +793,8 @@ int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
     const size_t dstate = state * (size_t)gamma;  // every daemon family
     const size_t words = (size_t)c->G * p->n_replicas * 2 * (size_t)g.Nh;
     if (ok && !c->bit) {
-        const size_t jw = (size_t)p->n_samples * (size_t)g.Nh / 4;
         ok = hipMalloc(&c->spin, state) == hipSuccess && hipMalloc(&c->dem, dstate) == hipSuccess &&
-             hipMalloc(&c->spin_alt, state) == hipSuccess && hipMalloc(&c->dem_alt, dstate) == hipSuccess &&
-             hipMalloc(&c->J, jw * 4) == hipSuccess;
+             hipMalloc(&c->spin_alt, state) == hipSuccess && hipMalloc(&c->dem_alt, dstate) == hipSuccess;
     } else if (ok) {
         ok = hipMalloc(&c->bspin, words * 8) == hipSuccess && hipMalloc(&c->bdm0, words * 8) == hipSuccess &&
              hipMalloc(&c->bdm1, words * 8) == hipSuccess &&
@@ -805,12 +808,10 @@ int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
     }
     int st = MICSA_OK;
     if (!c->bit) {
-        k_init_couplings<<<grid_for(g.Nh / 4, p->n_samples), kBlock, 0, c->stream>>>(g, c->J);
-        st = check_launch(c, "k_init_couplings");
-        if (!st) {
-            k_init_spins<<<grid_for(g.Nh / 4, c->L), kBlock, 0, c->stream>>>(g, c->spin);
-            st = check_launch(c, "k_init_spins");
-        }
+        // spins first, then the bond bits into the even spin bytes
+        k_init_spins<<<grid_for(g.Nh / 4, c->L), kBlock, 0, c->stream>>>(g, c->spin);
+        st = check_launch(c, "k_init_spins");
+        if (!st) st = enqueue_bonds(c);
         if (!st && hipMemsetAsync(c->dem, 0, dstate, c->stream) != hipSuccess) st = MICSA_EHIP;
     } else {
         const int WL = c->G * p->n_replicas;
@@ -1164,7 +1165,7 @@ int micsa_read_overlap(micsa_ctx* ctx, int32_t a, int32_t b, int64_t* Q)
 
 // Byte-layout arrays of `count` parity-split lattices ([count][2][Nh]: the
 // spins, or the daemons with count = L * gamma) -> host [count][N].
-static int read_state(micsa_ctx* ctx, const uint8_t* dev, uint8_t* host, int64_t count)
+static int read_state(micsa_ctx* ctx, const uint8_t* dev, uint8_t* host, int64_t count, uint8_t mask = 0xFF)
 {
     const int64_t N = n_sites(ctx);
     std::vector<uint8_t> buf((size_t)count * 2 * (size_t)ctx->g.Nh);
@@ -1175,7 +1176,7 @@ static int read_state(micsa_ctx* ctx, const uint8_t* dev, uint8_t* host, int64_t
             int par;
             int64_t h;
             split_index(ctx, i, par, h);
-            host[(int64_t)l * N + i] = buf[((size_t)l * 2 + par) * ctx->g.Nh + h];
+            host[(int64_t)l * N + i] = buf[((size_t)l * 2 + par) * ctx->g.Nh + h] & mask;
         }
     return MICSA_OK;
 }
@@ -1210,7 +1211,7 @@ int micsa_read_spins(micsa_ctx* ctx, uint8_t* sigma)
 {
     if (!ctx || !sigma) return MICSA_EINVAL;
     if (ctx->bit) return read_words(ctx, ctx->bspin, nullptr, sigma);
-    return read_state(ctx, ctx->spin, sigma, ctx->L);
+    return read_state(ctx, ctx->spin, sigma, ctx->L, 1);  // bit 0: even bytes also hold their bonds
 }
 
 int micsa_read_demons(micsa_ctx* ctx, uint8_t* m)
@@ -1231,8 +1232,13 @@ int micsa_read_couplings(micsa_ctx* ctx, uint8_t* j)
         wplanes.resize((size_t)ctx->G * 6 * g.Nh);
         HIP_TRY(ctx, hipMemcpyAsync(wplanes.data(), ctx->bJ, wplanes.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
     } else {
+        // bits 1..6 of the even spin bytes of replica 0 of each sample
         jbytes.resize((size_t)S * g.Nh);
-        HIP_TRY(ctx, hipMemcpyAsync(jbytes.data(), ctx->J, jbytes.size(), hipMemcpyDeviceToHost, ctx->stream));
+        for (int s = 0; s < S; ++s)
+            HIP_TRY(ctx, hipMemcpyAsync(jbytes.data() + (size_t)s * g.Nh,
+                                        ctx->spin + (size_t)s * ctx->p.n_replicas * 2 * g.Nh, (size_t)g.Nh,
+                                        hipMemcpyDeviceToHost, ctx->stream));
+        for (auto& b : jbytes) b = (uint8_t)(b >> 1);
     }
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     const int64_t N = n_sites(ctx);
@@ -1308,6 +1314,7 @@ int micsa_write_spins(micsa_ctx* ctx, const uint8_t* sigma)
 {
     if (!ctx || !sigma) return MICSA_EINVAL;
     int st = ctx->bit ? write_words(ctx, ctx->bspin, nullptr, sigma, 1) : write_state(ctx, ctx->spin, sigma, 1, ctx->L);
+    if (!st && !ctx->bit) st = enqueue_bonds(ctx);  // the written bytes hold spins only: restore the bond bits
     if (st) return st;
     std::vector<int64_t> E((size_t)ctx->L);
     if ((st = micsa_read_energy(ctx, E.data()))) return st;
@@ -1471,8 +1478,8 @@ size_t footprint(const micsa_params* p)
         return G * p->n_replicas * N * 8 * 3 + G * 6 * (N / 2) * 8 + slots;
     }
     const size_t gamma = p->gamma == 0 ? 1 : (size_t)p->gamma;
-    // 2 state buffers x (spin + gamma daemons), couplings
-    return 2 * L * N * (1 + gamma) + (size_t)p->n_samples * (N / 2) + slots;
+    // 2 state buffers x (spin + gamma daemons); the couplings live in the even spin bytes
+    return 2 * L * N * (1 + gamma) + slots;
 }
 
 }  // namespace
@@ -1588,7 +1595,7 @@ int micsa_pool_step(micsa_pool* pool, int64_t sweeps, int32_t* running, int32_t*
         if (use_resident(c)) {
             ResidentSched rs{c->k, n, 0, c->sched.period, 0, 0};
             for (int l = 0; l < c->L; ++l)
-                items.push_back(ResidentItem{c->g, c->spin, c->dem, c->J, c->tally, c->d_dth, rs, l});
+                items.push_back(ResidentItem{c->g, c->spin, c->dem, c->tally, c->d_dth, rs, l});
             lds = std::max(lds, (size_t)c->g.Nh * 3);
             c->k += n;
         } else {

@@ -22,8 +22,9 @@ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = (uint64_t)kMulA * c0;
         const uint64_t pb = (uint64_t)kMulB * c2;
-        const uint32_t t0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-        const uint32_t t2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        // three-input XORs in one v_bitop3 each (truth table 0x96)
+        const uint32_t t0 = __builtin_amdgcn_bitop3_b32((uint32_t)(pb >> 32), c1, k0, 0x96);
+        const uint32_t t2 = __builtin_amdgcn_bitop3_b32((uint32_t)(pa >> 32), c3, k1, 0x96);
         c1 = (uint32_t)pb;
         c3 = (uint32_t)pa;
         c0 = t0;

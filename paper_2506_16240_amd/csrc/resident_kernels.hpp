@@ -96,7 +96,7 @@ __device__ __forceinline__ uint32_t unsat_resident(const Geom& g, const uint32_t
 // plus one coupling byte per even site: 1.5 B per site.
 template <int ALGO>  // 0 MicSA, 1 heat bath, 2 Metropolis
 __device__ __forceinline__ void resident_body(const Geom& g, uint8_t* __restrict__ spin, uint8_t* __restrict__ dem,
-                                              const uint32_t* __restrict__ J, unsigned long long* __restrict__ tally,
+                                              unsigned long long* __restrict__ tally,
                                               const ResidentSched& rs, const DaemonThresholds* __restrict__ dth,
                                               const HeatBathThresholds* __restrict__ hth, long long* __restrict__ log,
                                               int l, int n_lattices, uint32_t* lds32, long long* red, uint64_t* tau)
@@ -109,9 +109,9 @@ __device__ __forceinline__ void resident_body(const Geom& g, uint8_t* __restrict
 
     const uint32_t* spg = reinterpret_cast<const uint32_t*>(spin + (int64_t)l * 2 * g.Nh);
     const uint32_t* dmg = reinterpret_cast<const uint32_t*>(dem + (int64_t)l * 2 * g.Nh);
-    const uint32_t* jg = J + (int64_t)s * W;
-    for (int w = threadIdx.x; w < 2 * W; w += blockDim.x) st[w] = spg[w] | (ALGO == 0 ? dmg[w] << 1 : 0u);
-    for (int w = threadIdx.x; w < W; w += blockDim.x) jb[w] = jg[w];
+    // even spin bytes carry their bond bits in bits 1..6 (geometry.hpp)
+    for (int w = threadIdx.x; w < 2 * W; w += blockDim.x) st[w] = (spg[w] & m1) | (ALGO == 0 ? dmg[w] << 1 : 0u);
+    for (int w = threadIdx.x; w < W; w += blockDim.x) jb[w] = (spg[w] >> 1) & 0x3F3F3F3Fu;
 
     // The words of this thread: w = threadIdx.x + j * blockDim.x.  Their
     // (y, z, c) are advanced incrementally instead of divided out per word.
@@ -135,10 +135,7 @@ __device__ __forceinline__ void resident_body(const Geom& g, uint8_t* __restrict
                 const u32x4 b = philox10((uint32_t)(i0 >> 2) + 1u, (uint32_t)rho, (uint32_t)r, sw, g.key0, g.key1);
                 uint32_t we, wo;
                 split8(g, i0, a, b,
-                       [&](uint32_t u) {
-                           const uint64_t v = u;
-                           return (uint32_t)(v >= th.t0) + (uint32_t)(v >= th.t1) + (uint32_t)(v >= th.t2);
-                       },
+                       [&](uint32_t u) { return daemon_level(u, th); },
                        we, wo);
                 st[t] = (st[t] & m1) | (we << 1);
                 st[W + t] = (st[W + t] & m1) | (wo << 1);
@@ -225,7 +222,7 @@ __device__ __forceinline__ void resident_body(const Geom& g, uint8_t* __restrict
     uint32_t* spo = reinterpret_cast<uint32_t*>(spin + (int64_t)l * 2 * g.Nh);
     uint32_t* dmo = reinterpret_cast<uint32_t*>(dem + (int64_t)l * 2 * g.Nh);
     for (int w = threadIdx.x; w < 2 * W; w += blockDim.x) {
-        spo[w] = st[w] & m1;
+        spo[w] = (st[w] & m1) | (w < W ? jb[w] << 1 : 0u);
         if (ALGO == 0) dmo[w] = (st[w] >> 1) & 0x03030303u;
     }
     block_add(tally + (int64_t)l * kSlots, dE);
@@ -233,7 +230,7 @@ __device__ __forceinline__ void resident_body(const Geom& g, uint8_t* __restrict
 
 template <int ALGO>
 __global__ void __launch_bounds__(512) k_resident(Geom g, uint8_t* __restrict__ spin, uint8_t* __restrict__ dem,
-                                                  const uint32_t* __restrict__ J, unsigned long long* __restrict__ tally,
+                                                  unsigned long long* __restrict__ tally,
                                                   ResidentSched rs, const DaemonThresholds* __restrict__ dth,
                                                   const HeatBathThresholds* __restrict__ hth,
                                                   long long* __restrict__ log)
@@ -241,7 +238,7 @@ __global__ void __launch_bounds__(512) k_resident(Geom g, uint8_t* __restrict__ 
     extern __shared__ uint32_t lds32[];
     __shared__ long long red[16];
     __shared__ uint64_t tau[8];
-    resident_body<ALGO>(g, spin, dem, J, tally, rs, dth, hth, log, blockIdx.x, gridDim.x, lds32, red, tau);
+    resident_body<ALGO>(g, spin, dem, tally, rs, dth, hth, log, blockIdx.x, gridDim.x, lds32, red, tau);
 }
 
 // One lattice of some context per work-group: the batched launch of the
@@ -251,7 +248,6 @@ struct ResidentItem {
     Geom g;
     uint8_t* spin;
     uint8_t* dem;
-    const uint32_t* J;
     unsigned long long* tally;
     const DaemonThresholds* dth;
     ResidentSched rs;
@@ -264,7 +260,7 @@ __global__ void __launch_bounds__(512) k_resident_batch(const ResidentItem* __re
     __shared__ long long red[16];
     __shared__ uint64_t tau[8];
     const ResidentItem it = items[blockIdx.x];
-    resident_body<0>(it.g, it.spin, it.dem, it.J, it.tally, it.rs, it.dth, nullptr, nullptr, it.lattice,
+    resident_body<0>(it.g, it.spin, it.dem, it.tally, it.rs, it.dth, nullptr, nullptr, it.lattice,
                      it.g.S * it.g.R, lds32, red, tau);
 }
 
