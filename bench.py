@@ -21,7 +21,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-# Algorithmic bytes per spin update (state one sweep must move, byte layout):
+# Algorithmic bytes per site and pass over the state (one sweep, or two with
+# the two-sweep fused kernel; byte layout):
 # spin byte read+write 2 B (an even site's byte also holds its six bond bits,
 # so the couplings ride along at no cost), daemon read+write 2 B.  The
 # baselines move the spin bytes only (plus one 32-bit uniform per update,
@@ -66,6 +67,8 @@ def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None):
             lat.set_option(M.OPT_TILE_Z, tile[1])
             if len(tile) > 2:
                 lat.set_option(M.OPT_PREFETCH, tile[2])
+            if len(tile) > 3:
+                lat.set_option(M.OPT_TEMPORAL, tile[3])
 
     algo = {"micsa": M.ALGO_MICSA, "heatbath": M.ALGO_HEATBATH, "metropolis": M.ALGO_METROPOLIS}[algo_name]
     sched = M.Schedule(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
@@ -133,7 +136,7 @@ def main() -> int:
     ap.add_argument("--no-metropolis", action="store_true")
     ap.add_argument("--tile", default="tune",
                     help="fused-sweep tile: 'tune' (autotuner, bit-exact gated), 'auto' (library default) "
-                         "or TY,TZ[,PREFETCH]")
+                         "or TY,TZ[,PREFETCH[,SWEEPS_PER_PASS]]")
     ap.add_argument("--copy-ref-gib", type=float, default=0.0,
                     help="after the run, copy this many GiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -162,8 +165,9 @@ def main() -> int:
         from paper_2506_16240_amd import tune
         log("tuning fused-sweep tiles")
         best = tune.tune(w.Lx, w.Ly, w.Lz, w.S, w.R, use_cache=False)
-        tile = (best.ty, best.tz, best.prefetch)
-        log(f"tile TY={best.ty} TZ={best.tz} prefetch {best.prefetch} ({best.us_per_sweep:.1f} us/sweep in tuning)")
+        tile = (best.ty, best.tz, best.prefetch, best.temporal)
+        log(f"tile TY={best.ty} TZ={best.tz} prefetch {best.prefetch} sweeps/pass {best.temporal} "
+            f"({best.us_per_sweep:.1f} us/sweep in tuning)")
     elif args.tile != "auto":
         tile = tuple(int(v) for v in args.tile.split(","))
     log(f"micsa: {w.name}, {sweeps} sweeps")
@@ -181,10 +185,12 @@ def main() -> int:
         log(f"metropolis: {mp['ms']:.1f} ms")
 
     value = updates / (mi["ms"] * 1e6)
-    # dominant kernel: the sweep kernel; each launch updates one parity of every lattice
-    per_launch_updates = updates / (mi["kernel_launches"] / sweeps) / sweeps
+    # dominant kernel: the sweep kernel.  A launch is one pass over the state,
+    # covering one or two sweeps; the state it must move is the same either
+    # way, so the algorithmic bytes per launch are those of one sweep.
+    sweeps_per_launch = sweeps / mi["kernel_launches"]
     avg_ms = mi["kernel_ms"] / mi["kernel_launches"]
-    bytes_launch = BYTES_PER_UPDATE["micsa"] * per_launch_updates
+    bytes_launch = BYTES_PER_UPDATE["micsa"] * w.N * w.lattices
     achieved = bytes_launch / (avg_ms * 1e6)  # GB/s
     traffic = measured_traffic(mi["kernel"])
     out = {
@@ -206,7 +212,9 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": mi["kernel"], "avg_launch_ms": round(avg_ms, 5),
-                     "bytes_per_launch": bytes_launch, "launches": mi["kernel_launches"]},
+                     "bytes_per_launch": bytes_launch, "launches": mi["kernel_launches"],
+                     "sweeps_per_launch": round(sweeps_per_launch, 3),
+                     "bytes_per_update": round(bytes_launch / (sweeps_per_launch * w.N * w.lattices), 3)},
         "checks": {"micsa_tally_equals_energy": mi["tally_check"]},
     }
     if hb is not None:

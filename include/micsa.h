@@ -214,6 +214,10 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      faster for these kernels on MI355X (the graph form adds a refresh-check
      and a counter kernel to every sweep).  Per-launch timing
      (micsa_set_timing) always launches every kernel.
+   MICSA_OPT_TEMPORAL: MicSA sweeps per pass over memory on the fused path:
+     2 (default) runs sweeps k and k + 1 in one launch wherever a call
+     sweeps at least two (the state is read and written once per pair); 1
+     runs one sweep per launch.  Results are identical.
    MICSA_OPT_PREFETCH: steps of global loads in flight in the fused MicSA
      sweep, 1 (default) or 2 (used for work-groups of at most 640 lanes,
      i.e. (tile_y + 4) * Lx / 32 <= 640; larger tiles run with 1).
@@ -224,7 +228,8 @@ enum micsa_option {
     MICSA_OPT_TILE_Z = 3,
     MICSA_OPT_XCD_MAP = 4,
     MICSA_OPT_GRAPHS = 5,
-    MICSA_OPT_PREFETCH = 6
+    MICSA_OPT_PREFETCH = 6,
+    MICSA_OPT_TEMPORAL = 7
 };
 enum micsa_kernel_choice {
     MICSA_KERNEL_AUTO = 0,    /* resident if the lattice fits, else fused if Lx >= 128, else simple */

@@ -16,6 +16,7 @@
 
 #include "bitplane_kernels.hpp"
 #include "fused_kernels.hpp"
+#include "fused2_kernels.hpp"
 #include "observables.hpp"
 #include "resident_kernels.hpp"
 #include "micsa.h"
@@ -65,6 +66,7 @@ struct micsa_ctx {
     int32_t tile_y = 0, tile_z = 0;
     int32_t xcd_map = 1;  // XCD-aware tile order for the fused sweeps
     int32_t prefetch = 1;  // steps of loads in flight in the fused MicSA sweep (1 or 2)
+    int32_t temporal = 2;  // MicSA sweeps per pass of the fused kernel (1 or 2)
     int32_t use_graphs = 0;
     // replayable graphs of kGraphSweeps sweeps for the per-half paths, per algo
     int64_t* d_k = nullptr;  // device copy of the sweep counter
@@ -381,6 +383,64 @@ int launch_fused_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
 }
 
 // Both halves with daemon family fam.
+// Tile of the two-sweep kernel: TY + 8 ring rows of NC lanes within
+// kSweep2Lanes; the tile options apply where they fit.
+FusedTile choose_tile2(const micsa_ctx* c)
+{
+    FusedTile f = choose_tile(c);
+    const int ty_cap = kSweep2Lanes / f.NC - 8;
+    if (f.TY > ty_cap) {
+        f.TY = divisor_at_most(c->p.Ly, ty_cap);
+        f.nty = c->p.Ly / f.TY;
+        f.xcd = c->xcd_map && (f.nty * f.ntz) % 8 == 0;
+    }
+    return f;
+}
+
+bool sweep2_eligible(const micsa_ctx* c) { return kSweep2Lanes / (c->p.Lx / 32) - 8 >= 1; }
+
+// Sweeps k and k + 1 in one pass (fused2_kernels.hpp); refreshA / refreshB
+// say whether k / k + 1 are refresh points.
+int launch_fused_sweep2(micsa_ctx* c, bool refreshA, int64_t rhoA, double TA, bool refreshB, int64_t rhoB, double TB)
+{
+    const FusedTile f = choose_tile2(c);
+    const int lanes = (f.TY + 8) * f.NC;
+    const int block = (lanes + 63) / 64 * 64;
+    const size_t lds = (size_t)128 * (f.TY + 8) * f.NC;  // 4 planes x 2 buffers x 16 B per lane slot
+    static const void* const kernels[4] = {
+        (const void*)k_micsa_sweep2_fused<false, false>, (const void*)k_micsa_sweep2_fused<true, false>,
+        (const void*)k_micsa_sweep2_fused<false, true>, (const void*)k_micsa_sweep2_fused<true, true>};
+    static bool attr_set[4] = {false, false, false, false};
+    const int which = (refreshA ? 1 : 0) + (refreshB ? 2 : 0);
+    if (!attr_set[which]) {
+        const hipError_t e =
+            hipFuncSetAttribute(kernels[which], hipFuncAttributeMaxDynamicSharedMemorySize, (int)kResidentLdsMax);
+        if (e != hipSuccess) return fail(c, MICSA_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+        attr_set[which] = true;
+    }
+    const dim3 grid((unsigned)(f.nty * f.ntz), (unsigned)c->L, 1);
+    const DaemonThresholds thA = refreshA ? daemon_thresholds(TA) : DaemonThresholds{0, 0, 0};
+    const DaemonThresholds thB = refreshB ? daemon_thresholds(TB) : DaemonThresholds{0, 0, 0};
+    {
+        TimedLaunch t(c, kTimeSweep);
+        auto go = [&](auto kern) {
+            kern<<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->dem, c->spin_alt, c->dem_alt, c->tally,
+                                                  (uint32_t)rhoA, thA, (uint32_t)rhoB, thB);
+        };
+        switch (which) {
+        case 0: go(k_micsa_sweep2_fused<false, false>); break;
+        case 1: go(k_micsa_sweep2_fused<true, false>); break;
+        case 2: go(k_micsa_sweep2_fused<false, true>); break;
+        default: go(k_micsa_sweep2_fused<true, true>); break;
+        }
+    }
+    const int st = check_launch(c, "k_micsa_sweep2_fused");
+    if (st) return st;
+    std::swap(c->spin, c->spin_alt);
+    std::swap(c->dem, c->dem_alt);
+    return MICSA_OK;
+}
+
 int launch_micsa_sweep(micsa_ctx* c, int fam)
 {
     const int64_t words = (int64_t)c->g.rows * c->g.Wr;
@@ -675,6 +735,17 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
         const double T = temperature(c->sched, rho);
         if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
         int st;
+        if (algo == MICSA_ALGO_MICSA && c->temporal == 2 && i + 1 < n && use_fused(c) && sweep2_eligible(c)) {
+            // sweeps k and k + 1 in one pass (gamma = 1 on the fused path)
+            const bool refreshB = is_refresh(k + 1, c->sched.period);
+            const int64_t rhoB = refresh_index(k + 1, c->sched.period);
+            const double TB = temperature(c->sched, rhoB);
+            if (!(TB > 0.0) || !std::isfinite(TB)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
+            if ((st = launch_fused_sweep2(c, is_refresh(k, c->sched.period), rho, T, refreshB, rhoB, TB))) return st;
+            c->k = k + 2;
+            ++i;
+            continue;
+        }
         if (algo == MICSA_ALGO_MICSA || algo == MICSA_ALGO_WALKERS) {
             const bool refresh = fam == 0 && is_refresh(t, c->sched.period);
             if (c->bit) {
@@ -1410,7 +1481,8 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
         return ctx && use_fused(ctx) ? "k_heatbath_sweep_fused<0>" : "k_heatbath_half<0>";
     if (algo == MICSA_ALGO_METROPOLIS)
         return ctx && use_fused(ctx) ? "k_heatbath_sweep_fused<1>" : "k_heatbath_half<1>";
-    if (ctx && use_fused(ctx)) return "k_micsa_sweep_fused";
+    if (ctx && use_fused(ctx))
+        return ctx->temporal == 2 && sweep2_eligible(ctx) ? "k_micsa_sweep2_fused" : "k_micsa_sweep_fused";
     return "k_micsa_half";
 }
 
@@ -1436,6 +1508,10 @@ int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value)
     case MICSA_OPT_GRAPHS:
         if (value != 0 && value != 1) return fail(ctx, MICSA_EINVAL, "graphs is 0 or 1");
         ctx->use_graphs = (int32_t)value;
+        return MICSA_OK;
+    case MICSA_OPT_TEMPORAL:
+        if (value != 1 && value != 2) return fail(ctx, MICSA_EINVAL, "temporal is 1 or 2");
+        ctx->temporal = (int32_t)value;
         return MICSA_OK;
     case MICSA_OPT_PREFETCH:
         if (value != 1 && value != 2) return fail(ctx, MICSA_EINVAL, "prefetch is 1 or 2");

@@ -112,3 +112,40 @@ def serve(stream: list[tuple[float, JobSpec]], hbm_budget: int, sweeps_per_step:
                "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
                "updates_per_ns": upd / (wall * 1e9), "max_running": max_running_seen}
     return res, metrics
+
+
+def capacity(n_jobs: int, seed: int, hbm_budget: int, sweeps_per_step: int, n_sweeps: int) -> float:
+    """Service capacity in spin updates/ns: the same job mix, all arriving at once."""
+    stream = [(0.0, spec) for _, spec in job_stream(n_jobs, 1.0, seed, n_sweeps)]
+    _, m = serve(stream, hbm_budget, sweeps_per_step)
+    return m["updates_per_ns"]
+
+
+def main() -> int:
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="Poisson job stream through the continuous-batching pool: "
+                                             "p50/p99 time to solution, throughput, best energy per job.")
+    ap.add_argument("--jobs", type=int, default=60)
+    ap.add_argument("--loads", default="0.5,0.8,1.0", help="offered loads as fractions of the measured capacity")
+    ap.add_argument("--seed", type=int, default=0x5EED0005)
+    ap.add_argument("--sweeps", type=int, default=2000)
+    ap.add_argument("--sweeps-per-step", type=int, default=100)
+    ap.add_argument("--hbm-gib", type=float, default=64.0)
+    args = ap.parse_args()
+    budget = int(args.hbm_gib * (1 << 30))
+    cap = capacity(max(8, args.jobs // 4), args.seed + 1, budget, args.sweeps_per_step, args.sweeps)
+    mean_updates = float(np.mean([s.updates for _, s in job_stream(4096, 1.0, args.seed + 2, args.sweeps)]))
+    print(json.dumps({"capacity_updates_per_ns": round(cap, 1), "mean_job_updates": mean_updates}), flush=True)
+    for load in (float(x) for x in args.loads.split(",")):
+        rate = load * cap * 1e9 / mean_updates  # jobs per second
+        res, m = serve(job_stream(args.jobs, rate, args.seed, args.sweeps), budget, args.sweeps_per_step)
+        e_best = [r.best_energy / r.spec.L ** 3 for r in res]
+        print(json.dumps({"load": load, "rate_jobs_per_s": round(rate, 3), **{k: (round(v, 4) if isinstance(v, float)
+                          else v) for k, v in m.items()}, "best_e_per_spin_mean": round(float(np.mean(e_best)), 4),
+                          "best_e_per_spin_min": round(float(np.min(e_best)), 4)}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

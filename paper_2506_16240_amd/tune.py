@@ -1,8 +1,8 @@
 """Launch-shape autotuner for the fused MicSA sweep.
 
 For a lattice shape it times every admissible tile (rows TY x planes TZ per
-work-group) at both prefetch depths with the library's per-launch event
-timing, rejects any
+work-group) at both prefetch depths and with one or two sweeps per pass,
+with the library's per-launch event timing, rejects any
 candidate whose state after the trial sweeps differs in a single bit from
 the per-half reference kernel (the bit-exact gate: launch shapes must never
 change results), and returns the fastest.  Results are cached in a JSON
@@ -31,6 +31,7 @@ class TileResult:
     tz: int
     us_per_sweep: float
     prefetch: int = 1
+    temporal: int = 1
 
 
 def _divisors(n: int, cap: int) -> list[int]:
@@ -63,12 +64,13 @@ def _state_digest(g: M.Lattice) -> str:
     return h.hexdigest()
 
 
-def _run(shape, seed, kernel, ty, tz, sweeps, warm, timed, prefetch=1):
+def _run(shape, seed, kernel, ty, tz, sweeps, warm, timed, prefetch=1, temporal=1):
     Lx, Ly, Lz, S, R = shape
     g = M.Lattice(Lx, Ly, Lz, S, R, seed)
     try:
         g.set_option(M.OPT_SWEEP_KERNEL, kernel)
         g.set_option(M.OPT_PREFETCH, prefetch)
+        g.set_option(M.OPT_TEMPORAL, temporal)
         if ty:
             g.set_option(M.OPT_TILE_Y, ty)
             g.set_option(M.OPT_TILE_Z, tz)
@@ -78,7 +80,7 @@ def _run(shape, seed, kernel, ty, tz, sweeps, warm, timed, prefetch=1):
         g.set_timing(timed)
         g.sweep(M.ALGO_MICSA, sweeps)
         ms, n = g.timing(M.TIME_SWEEP)
-        return _state_digest(g), (ms / n * 1e3 if n else float("nan"))
+        return _state_digest(g), (ms / sweeps * 1e3 if n else float("nan"))
     finally:
         g.close()
 
@@ -99,15 +101,15 @@ def tune(Lx: int, Ly: int, Lz: int, S: int = 1, R: int = 1, sweeps: int = 12, us
     ref, _ = _run(shape, seed, M.KERNEL_SIMPLE, 0, 0, sweeps, warm, False)
     best = None
     for ty, tz in candidates(Lx, Ly, Lz):
-        for pf in (1, 2):
-            digest, us = _run(shape, seed, M.KERNEL_FUSED, ty, tz, sweeps, warm, True, pf)
+        for pf, tp in ((1, 1), (2, 1), (1, 2)):  # prefetch applies to one-sweep passes only
+            digest, us = _run(shape, seed, M.KERNEL_FUSED, ty, tz, sweeps, warm, True, pf, tp)
             if digest != ref:
-                raise RuntimeError(f"tile TY={ty} TZ={tz} prefetch {pf} changed the result: "
+                raise RuntimeError(f"tile TY={ty} TZ={tz} prefetch {pf} sweeps/pass {tp} changed the result: "
                                    f"the fused sweep is wrong for {shape}")
             if verbose:
-                print(f"  TY={ty:3d} TZ={tz:3d} PF={pf}: {us:9.2f} us/sweep", flush=True)
+                print(f"  TY={ty:3d} TZ={tz:3d} PF={pf} T={tp}: {us:9.2f} us/sweep", flush=True)
             if best is None or us < best.us_per_sweep:
-                best = TileResult(ty, tz, us, pf)
+                best = TileResult(ty, tz, us, pf, tp)
     if use_cache:
         cache[key] = best.__dict__
         with open(CACHE_PATH, "w") as f:

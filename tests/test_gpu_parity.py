@@ -168,17 +168,20 @@ def test_batched_L32_shape():
     same_state(g, o)
 
 
-@pytest.mark.parametrize("prefetch", [1, 2])
-def test_anneal_L512_first_sweeps_full_size(prefetch):
+@pytest.mark.parametrize("prefetch,temporal", [(1, 2), (2, 1)])
+def test_anneal_L512_first_sweeps_full_size(prefetch, temporal):
     """L = 512 (134M spins), linear 3.0 -> 0.2 over 10^4 sweeps, refresh every 20:
     the first 21 sweeps (two refreshes) bit-exact at full size, with the
-    fused sweep's benchmark tile at both prefetch depths."""
+    fused sweep's benchmark tile, two sweeps per pass (logging every 7
+    sweeps: pairs and a single sweep per call) and one sweep per pass at
+    both prefetch depths."""
     w = W.ANNEAL_L512
     n = 21
     g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
     g.set_option(M.OPT_TILE_Y, 32)
     g.set_option(M.OPT_TILE_Z, 32)
     g.set_option(M.OPT_PREFETCH, prefetch)
+    g.set_option(M.OPT_TEMPORAL, temporal)
     gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
     g.set_schedule(gs)
     Eg, Dg = g.sweep_logged(M.ALGO_MICSA, n, 7)
@@ -346,7 +349,8 @@ def test_fused_sweep_matches_oracle(shape, ty, tz, algo):
         g.set_option(M.OPT_TILE_Y, ty)
     if tz:
         g.set_option(M.OPT_TILE_Z, tz)
-    assert g.kernel_name(algo) in ("k_micsa_sweep_fused", "k_heatbath_sweep_fused<0>", "k_heatbath_sweep_fused<1>")
+    assert g.kernel_name(algo) in ("k_micsa_sweep_fused", "k_micsa_sweep2_fused", "k_heatbath_sweep_fused<0>",
+                                   "k_heatbath_sweep_fused<1>")
     n = 23
     gs, os_ = scheds(M.SCHED_LINEAR, 2.5, 0.4, n, 5)
     g.set_schedule(gs)
@@ -366,25 +370,26 @@ def test_every_launch_shape_gives_the_same_bits():
     shape = (64, 16, 12, 1, 2)
     n = 30
     ref = None
-    variants = [(M.KERNEL_SIMPLE, 0, 0, 1, 1), (M.KERNEL_RESIDENT, 0, 0, 1, 1)] + [
-        (M.KERNEL_FUSED, ty, tz, 1, pf) for ty in (1, 2, 4, 8, 16) for tz in (1, 3, 4, 12) for pf in (1, 2)] + [
-        (M.KERNEL_FUSED, 1, 3, 0, 1), (M.KERNEL_FUSED, 4, 1, 0, 2)]
-    for kern, ty, tz, xcd, pf in variants:
+    variants = [(M.KERNEL_SIMPLE, 0, 0, 1, 1, 1), (M.KERNEL_RESIDENT, 0, 0, 1, 1, 1)] + [
+        (M.KERNEL_FUSED, ty, tz, 1, pf, tp) for ty in (1, 2, 4, 8, 16) for tz in (1, 3, 4, 12) for pf in (1, 2)
+        for tp in (1, 2)] + [(M.KERNEL_FUSED, 1, 3, 0, 1, 2), (M.KERNEL_FUSED, 4, 1, 0, 2, 1)]
+    for kern, ty, tz, xcd, pf, tp in variants:
         g = M.Lattice(*shape, seed=2024)
         g.set_option(M.OPT_SWEEP_KERNEL, kern)
         g.set_option(M.OPT_XCD_MAP, xcd)
         g.set_option(M.OPT_PREFETCH, pf)
+        g.set_option(M.OPT_TEMPORAL, tp)
         if ty:
             g.set_option(M.OPT_TILE_Y, ty)
             g.set_option(M.OPT_TILE_Z, tz)
         g.set_schedule(M.Schedule(M.SCHED_CONST, 0.8, 0.8, n, 7))
-        E, D = g.sweep_logged(M.ALGO_MICSA, n, 1)
+        E, D = g.sweep_logged(M.ALGO_MICSA, n, 5)  # odd stride: pairs and single sweeps, refreshes on either
         got = (E, D, g.spins(), g.daemons(), g.energy_tally())
         if ref is None:
             ref = got
         else:
             for a, b in zip(ref, got):
-                assert np.array_equal(a, b), (kern, ty, tz, xcd, pf)
+                assert np.array_equal(a, b), (kern, ty, tz, xcd, pf, tp)
         g.close()
 
 
@@ -589,3 +594,29 @@ def test_xi_of_written_overlap_fields_matches_oracle():
     xg, xo = g.xi(), o.xi()
     assert np.isfinite(xo).all()
     assert np.allclose(xg, xo, rtol=1e-13, atol=0), (xg, xo)
+
+
+# ------------------------------------------------- two sweeps per pass
+@pytest.mark.parametrize("shape,ty,tz", [((32, 2, 2, 1, 2), 0, 0), ((64, 6, 10, 2, 1), 1, 1), ((32, 12, 4, 1, 2), 3, 2),
+                                         ((96, 8, 6, 1, 1), 2, 3), ((128, 16, 16, 1, 1), 0, 0),
+                                         ((64, 64, 64, 1, 2), 0, 0), ((32, 4, 2, 1, 1), 4, 2)])
+@pytest.mark.parametrize("period", [1, 2, 3])
+def test_two_sweep_pass_matches_oracle(shape, ty, tz, period):
+    """Sweeps k and k + 1 in one pass of the fused kernel: refreshes before the
+    first, the second, both or neither sweep of a pair; minimum sides (rings
+    that wrap several times onto the tile); ragged tiles."""
+    g, o = pair(*shape, seed=31337)
+    g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)
+    g.set_option(M.OPT_TEMPORAL, 2)
+    if ty:
+        g.set_option(M.OPT_TILE_Y, ty)
+        g.set_option(M.OPT_TILE_Z, tz)
+    assert g.kernel_name(M.ALGO_MICSA) == "k_micsa_sweep2_fused"
+    n = 24
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.5, 0.4, n, period)
+    g.set_schedule(gs)
+    Eg, Dg = g.sweep_logged(M.ALGO_MICSA, n, 4)
+    Eo, Do = o.run(O.ALGO_MICSA, os_, n, 4)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    same_state(g, o)
+    assert np.array_equal(g.energy_tally(), o.energy())
