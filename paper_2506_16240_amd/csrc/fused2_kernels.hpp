@@ -45,7 +45,7 @@ __device__ __forceinline__ V4 even_chunk(V4& W, V4& M, const V4& A, const V4& B,
         const uint32_t m1 = 0x01010101u;
         const uint32_t w = W.w[i];
         uint32_t S = w & m1;
-        const uint32_t v = xor_and((S << 6) - S, w >> 1, 0x3F3F3F3Fu);
+        const uint32_t v = xor_and(times63(S), w >> 1, 0x3F3F3F3Fu);
         const uint32_t u = xor_and(A.w[i], v >> dA, m1) + xor_and(B.w[i], v >> dB, m1) +
                            xor_and(Yp.w[i], v >> kPy, m1) + xor_and(Ym.w[i], v >> kMy, m1) +
                            xor_and(Zup.w[i], v >> kPz, m1) + xor_and(Zdn.w[i], v >> kMz, m1);
@@ -53,7 +53,7 @@ __device__ __forceinline__ V4 even_chunk(V4& W, V4& M, const V4& A, const V4& B,
         creutz4(S, M.w[i], u, so, sn);
         const uint32_t flip = S ^ S0;
         W.w[i] = w ^ flip;
-        X.w[i] = v ^ ((flip << 6) - flip);  // even view: bit d = new spin ^ j_d
+        X.w[i] = v ^ times63(flip);  // even view: bit d = new spin ^ j_d
     }
     return X;
 }
@@ -122,7 +122,9 @@ __global__ void __launch_bounds__(kSweep2Lanes) k_micsa_sweep2_fused(
     const uint32_t sw = stream_word(kStreamDaemon, (uint32_t)s);
 
     auto zof = [&](int st_plane) { return wrap(zstart + dz * st_plane, g.Lz); };
-    auto hof = [&](int z) { return ((int64_t)y + (int64_t)g.Ly * z) * g.Kx + 16 * c; };
+    const int64_t lane_off = (int64_t)y * g.Kx + 16 * c;
+    const int64_t plane = (int64_t)g.Ly * g.Kx;
+    auto hof = [&](int z) { return lane_off + plane * z; };  // z is uniform: the product is scalar
     const int cn = c + 1 == f.NC ? 0 : c + 1, cp = c == 0 ? f.NC - 1 : c - 1;
     const int steps = f.TZ + 6;
 

@@ -105,6 +105,18 @@ __device__ __forceinline__ V4 shift16(const V4& a, uint32_t nbw, int dir)
     return r;
 }
 
+// x * 0x3F for x with at most bit 0 of each byte set (each byte becomes 0x3F
+// or 0), as one packed 16-bit multiply: a 16-bit half holds two such bytes,
+// 0x0101 * 0x3F < 2^16, so no half carries into the next.  (Written as a
+// shift and a subtraction it compiles to a quarter-rate 32-bit multiply.)
+__device__ __forceinline__ uint32_t times63(uint32_t x)
+{
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    u16x2 v = __builtin_bit_cast(u16x2, x);
+    v = v * (u16x2){63, 63};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
 // Three-input bit operations in one v_bitop3: the truth table indexes the
 // bits as (a << 2) | (b << 1) | c.
 __device__ __forceinline__ uint32_t xor_and(uint32_t a, uint32_t b, uint32_t c)  // a ^ (b & c)
@@ -276,7 +288,7 @@ __global__ void __launch_bounds__(PF == 2 ? kPf2Lanes : 1024) k_micsa_sweep_fuse
                 const uint32_t m1 = 0x01010101u;
                 const uint32_t W = Se.w[i];  // spin in bit 0, bond d in bit 1 + d
                 uint32_t S = W & m1;
-                const uint32_t v = xor_and((S << 6) - S, W >> 1, 0x3F3F3F3Fu);
+                const uint32_t v = xor_and(times63(S), W >> 1, 0x3F3F3F3Fu);
                 const uint32_t u = xor_and(A.w[i], v >> dA, m1) + xor_and(B.w[i], v >> dB, m1) +
                                    xor_and(Yp.w[i], v >> kPy, m1) + xor_and(Ym.w[i], v >> kMy, m1) +
                                    xor_and(Sz_up.w[i], v >> kPz, m1) + xor_and(Sz_dn.w[i], v >> kMz, m1);
@@ -284,7 +296,7 @@ __global__ void __launch_bounds__(PF == 2 ? kPf2Lanes : 1024) k_micsa_sweep_fuse
                 creutz4(S, Me.w[i], u, so, sn);
                 const uint32_t flip = S ^ S0;
                 Se.w[i] = W ^ flip;
-                Xn.w[i] = v ^ ((flip << 6) - flip);  // even view: bit d = new spin ^ j_d
+                Xn.w[i] = v ^ times63(flip);  // even view: bit d = new spin ^ j_d
             }
             X_cur = Xn;
             sts16(&Xs[buf * plane_slots + ry * f.NC + c], Xn);
@@ -432,7 +444,7 @@ __global__ void __launch_bounds__(1024) k_heatbath_sweep_fused(
                 const u32x4 rnd = philox10(ctr, time0, (uint32_t)r, sw, g.key0, g.key1);
                 const uint32_t S = canonical4<ALG>(W, v, rnd, tau, dEe);
                 Se.w[i] = S | (W & ~m1);
-                Xn.w[i] = ((S << 6) - S) ^ jw;
+                Xn.w[i] = times63(S) ^ jw;
             }
             X_cur = Xn;
             sts16(&Xs[buf * plane_slots + ry * f.NC + c], Xn);
