@@ -28,6 +28,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 # baselines move the spin bytes only (plus one 32-bit uniform per update,
 # generated in registers).
 BYTES_PER_UPDATE = {"micsa": 4.0, "heatbath": 2.0, "metropolis": 2.0}
+# Bit-plane layout (64 samples per 64-bit word): spin word read+write 16 B,
+# two daemon planes read+write 32 B, three forward-bond planes 24 B shared by
+# the two replicas of a sample: (16 + 32 + 12) / 64 = 0.9375 B per update.
+BYTES_PER_UPDATE_BITPLANE = 0.9375
 
 
 def log(msg: str) -> None:
@@ -57,7 +61,11 @@ def measured_traffic(name: str):
     return e.get("bytes_per_launch")
 
 
-def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None):
+def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None, layout: int = 0, events: bool = False):
+    """One timed region of `steps` steps on a fresh lattice.  With events the
+    library brackets every launch with a HIP event pair (per-kernel
+    durations for the roofline); without, the region is timed as a whole
+    (the throughput), since per-launch events slow launch-bound paths."""
     from paper_2506_16240_amd import micsa as M
     import torch
 
@@ -74,15 +82,15 @@ def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None):
     sched = M.Schedule(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
     P = w.period
     if warmup > 0:
-        with M.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed, stream=stream.cuda_stream) as lw:
+        with M.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed, stream=stream.cuda_stream, layout=layout) as lw:
             configure(lw)
             lw.set_schedule(sched)
             lw.sweep(algo, warmup * P)
             lw.sync()
-    lat = M.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed, stream=stream.cuda_stream)
+    lat = M.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed, stream=stream.cuda_stream, layout=layout)
     configure(lat)
     lat.set_schedule(sched)
-    lat.set_timing(True)
+    lat.set_timing(events)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -95,8 +103,9 @@ def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None):
     k_ms, k_n = lat.timing(kind)
     r_ms, r_n = lat.timing(M.TIME_REFRESH)
     # property that holds at any size: the incremental tally equals the energy
-    E, tally = lat.energy(), lat.energy_tally()
-    ok = bool((E == tally).all())
+    # (the bit-plane layout keeps no tally)
+    E = lat.energy()
+    ok = bool((E == lat.energy_tally()).all()) if layout == M.LAYOUT_BYTE else None
     name = lat.kernel_name(algo)
     lat.close()
     return {"ms": ms, "kernel_ms": k_ms, "kernel_launches": k_n, "refresh_ms": r_ms, "refresh_launches": r_n,
@@ -134,6 +143,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-heatbath", action="store_true")
     ap.add_argument("--no-metropolis", action="store_true")
+    ap.add_argument("--layout", choices=("byte", "bitplane"), default="byte",
+                    help="MicSA layout (the baselines always run in the byte layout)")
     ap.add_argument("--tile", default="tune",
                     help="fused-sweep tile: 'tune' (autotuner, bit-exact gated), 'auto' (library default) "
                          "or TY,TZ[,PREFETCH[,SWEEPS_PER_PASS]]")
@@ -160,19 +171,24 @@ def main() -> int:
     sweeps = steps * w.period
     updates = w.N * w.lattices * sweeps
 
+    layout = 1 if args.layout == "bitplane" else 0
+    fused = layout == 0 and w.Lx % 32 == 0 and w.Lx >= 128
     tile = None
-    if args.tile == "tune":
+    if args.tile == "tune" and fused:
         from paper_2506_16240_amd import tune
         log("tuning fused-sweep tiles")
         best = tune.tune(w.Lx, w.Ly, w.Lz, w.S, w.R, use_cache=False)
         tile = (best.ty, best.tz, best.prefetch, best.temporal)
         log(f"tile TY={best.ty} TZ={best.tz} prefetch {best.prefetch} sweeps/pass {best.temporal} "
             f"({best.us_per_sweep:.1f} us/sweep in tuning)")
-    elif args.tile != "auto":
+    elif args.tile not in ("auto", "tune"):
         tile = tuple(int(v) for v in args.tile.split(","))
     log(f"micsa: {w.name}, {sweeps} sweeps")
-    mi = run_gpu(w, "micsa", steps, args.warmup, stream, tile)
+    mi = run_gpu(w, "micsa", steps, args.warmup, stream, tile, layout)
     log(f"micsa: {mi['ms']:.1f} ms, tally check {mi['tally_check']}")
+    log("micsa again with per-launch events (kernel durations)")
+    mk = run_gpu(w, "micsa", steps, 0, stream, tile, layout, events=True)
+    log(f"micsa with events: {mk['ms']:.1f} ms, {mk['kernel_launches']} launches")
     hb = None
     if not args.no_heatbath:
         log(f"heatbath: {w.name}, {sweeps} sweeps")
@@ -185,12 +201,14 @@ def main() -> int:
         log(f"metropolis: {mp['ms']:.1f} ms")
 
     value = updates / (mi["ms"] * 1e6)
-    # dominant kernel: the sweep kernel.  A launch is one pass over the state,
-    # covering one or two sweeps; the state it must move is the same either
-    # way, so the algorithmic bytes per launch are those of one sweep.
-    sweeps_per_launch = sweeps / mi["kernel_launches"]
-    avg_ms = mi["kernel_ms"] / mi["kernel_launches"]
-    bytes_launch = BYTES_PER_UPDATE["micsa"] * w.N * w.lattices
+    # dominant kernel: the sweep kernel.  A launch covers one half sweep
+    # (per-half kernels), one sweep, or two sweeps in one pass over the state;
+    # the algorithmic bytes per launch are those of one pass over the sites
+    # it touches: bytes per update x sites x min(1, sweeps per launch).
+    sweeps_per_launch = sweeps / mk["kernel_launches"]
+    avg_ms = mk["kernel_ms"] / mk["kernel_launches"]
+    per_update = BYTES_PER_UPDATE_BITPLANE if layout else BYTES_PER_UPDATE["micsa"]
+    bytes_launch = per_update * w.N * w.lattices * min(1.0, sweeps_per_launch)
     achieved = bytes_launch / (avg_ms * 1e6)  # GB/s
     traffic = measured_traffic(mi["kernel"])
     out = {
@@ -208,11 +226,11 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "L": [w.Lx, w.Ly, w.Lz], "samples": w.S, "replicas": w.R,
                    "sweeps_per_step": w.period, "sweeps": sweeps, "schedule": f"T {w.T0}->{w.T1}",
-                   "layout": "byte", "kernel": mi["kernel"], "tile": list(tile) if tile else "auto"},
+                   "layout": args.layout, "kernel": mi["kernel"], "tile": list(tile) if tile else "auto"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": mi["kernel"], "avg_launch_ms": round(avg_ms, 5),
-                     "bytes_per_launch": bytes_launch, "launches": mi["kernel_launches"],
+                     "bytes_per_launch": bytes_launch, "launches": mk["kernel_launches"],
                      "sweeps_per_launch": round(sweeps_per_launch, 3),
                      "bytes_per_update": round(bytes_launch / (sweeps_per_launch * w.N * w.lattices), 3)},
         "checks": {"micsa_tally_equals_energy": mi["tally_check"]},
