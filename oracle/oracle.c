@@ -33,6 +33,10 @@
  * Parallelism: the only OpenMP use is a parallel loop over the sites of one
  * parity, which the paper's separability argument (Sec. 2.1, Sec. 2.3) makes
  * order-independent; integer reductions make the result deterministic.
+ * The equilibrium workload of App. C (Gaussian couplings, continuous
+ * walkers, parallel tempering, Houdayer moves) has its own section near
+ * the end of the file, with its own storage and generator map; it runs
+ * independent lattices in parallel.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -620,6 +624,348 @@ int oracle_density_of_states(int Lx, int Ly, int Lz, const uint8_t *J, uint64_t 
         for (int e = 0; e <= 3 * N; e++) g[e] += gl[e];
         free(gl);
     }
+    return 0;
+}
+
+/* ================================================================== */
+/* Equilibrium workload of App. C: Gaussian couplings, continuous      */
+/* walkers, parallel tempering with Houdayer cluster moves.            */
+/*                                                                     */
+/* Energy mesh.  The paper allows continuous walkers or walkers on a   */
+/* fine energy mesh (Sec. 2.3).  Here every energy is an integer       */
+/* multiple of eps = 2^-17: a coupling J is held as Jq = nearest       */
+/* integer to J * 2^17 (ties to even), |J| <= 8, so H, dH and the      */
+/* walkers are integers and the move is exact integer arithmetic.      */
+/*   H = - sum over bonds Jq s_x s_y,   dH_x = 2 s_x sum_y Jq_xy s_y     */
+/* Couplings are stored per site and axis: Jq[mu][i] is the bond       */
+/* (i, i + e_mu).                                                      */
+/*                                                                     */
+/* Exponential on the mesh.  A walker refreshed at inverse temperature */
+/* beta is exponentially distributed (Sec. 2.3); on the mesh this is   */
+/* the geometric law P(n) = (1 - q) q^n, q = exp(-beta eps).  Its      */
+/* base-256 digits c_0..c_3 (n = sum c_d 256^d) are independent, c_d   */
+/* geometric with ratio r_d = q^(256^d), truncated to 0..255 for       */
+/* d < 3; the top digit is untruncated and is required to stay below   */
+/* 255 with probability 1 - 2^-32.  Each digit is an inverse CDF on    */
+/* one 32-bit word w_d of a Philox output:                              */
+/*   c_d = #{v in 0..254 : w_d >= t_d[v]},  t_d[v] = floor(2^32 F_d(v)) */
+/*   F_d(v) = P(c_d <= v) = (1 - r_d^(v+1)) / (1 - r_d^256)  (d < 3)    */
+/*   F_3(v) = 1 - r_3^(v+1)                                            */
+/* The same law with rate beta drives the walkers; with a fresh draw   */
+/* per attempt, accepting iff n >= dH is the Metropolis rule (Sec.     */
+/* 2.3: a fresh walker per flip attempt is textbook Metropolis), and   */
+/* with rate beta_t - beta_{t+1} it decides tempering swaps.           */
+/*                                                                     */
+/* Random numbers (Philox4x32-10, same key as above), per run u:       */
+/*   spins      ctr = (i>>2, t,     rep,      10<<24 | u)  out[i&3] >> 31 */
+/*   walkers    ctr = (i,    e,     2t + rep,  6<<24 | u)  w = out        */
+/*   Metropolis ctr = (i,    e*S+s, 2t + rep,  7<<24 | u)  w = out        */
+/*   Houdayer   ctr = (t,    e,     0,         8<<24 | u)  out[0]         */
+/*   swap       ctr = (t,    e,     rep,       9<<24 | u)  w = out        */
+/* (t = temperature index, rep = replica 0/1, e = EMCS index, s = sweep */
+/* within the EMCS).                                                    */
+/*                                                                     */
+/* One EMCS (App. C), for every run:                                    */
+/*  1. every (temperature t, replica): walkers drawn at beta_t, then S  */
+/*     times a full sweep (even sites, odd sites) followed by a forward- */
+/*     X wandering of the sites of parity s & 1.  The Creutz move is    */
+/*     uncapped (App. C): flip iff n - dH >= 0, then n -= dH.  With the */
+/*     Metropolis update instead, each visit draws a fresh n.           */
+/*  2. Houdayer move at every temperature between the two replicas.     */
+/*  3. one tempering step per replica: pairs (t, t+1) with t even, then */
+/*     with t odd; configurations are exchanged iff n >= E_{t+1} - E_t,  */
+/*     n drawn at rate beta_t - beta_{t+1}, i.e. with probability       */
+/*     min(1, exp((beta_t - beta_{t+1}) (E_t - E_{t+1}))).             */
+/* Temperatures are strictly increasing in t.                           */
+/* Storage: sigma[u][rep][t][i], the configuration at temperature t.    */
+/* ================================================================== */
+enum { STREAM_PT_WALKER = 6, STREAM_PT_METROPOLIS = 7, STREAM_PT_HOUDAYER = 8, STREAM_PT_SWAP = 9,
+       STREAM_PT_SPIN = 10 };
+enum { PT_WALKERS = 0, PT_METROPOLIS = 1 };
+#define PT_TABLE 1020 /* 4 digits x 255 thresholds */
+
+int oracle_pt_quantise(int64_t n, const double *J, int32_t *Jq)
+{
+    for (int64_t k = 0; k < n; k++) {
+        if (!(fabs(J[k]) <= 8.0)) return -1;
+        Jq[k] = (int32_t)nearbyint(J[k] * 131072.0);
+    }
+    return 0;
+}
+
+/* Thresholds of the four digits for rate lam (per unit energy); returns
+   0, or -1 if the top digit could reach 255. */
+int oracle_pt_exp_table(double lam, uint64_t *t)
+{
+    for (int d = 0; d < 4; d++) {
+        double a = -lam * ldexp(1.0, 8 * d - 17); /* log r_d */
+        for (int v = 0; v < 255; v++) {
+            double F = d < 3 ? expm1(a * (double)(v + 1)) / expm1(a * 256.0) : -expm1(a * (double)(v + 1));
+            t[d * 255 + v] = (uint64_t)floor(F * 4294967296.0);
+        }
+    }
+    return t[3 * 255 + 254] == 4294967296ull ? 0 : -1;
+}
+
+int64_t oracle_pt_exp_draw(const uint64_t *t, const uint32_t w[4])
+{
+    int64_t n = 0;
+    for (int d = 3; d >= 0; d--) {
+        int c = 0;
+        for (int v = 0; v < 255; v++) c += (uint64_t)w[d] >= t[d * 255 + v];
+        n = n * 256 + c;
+    }
+    return n;
+}
+
+static void philox_words(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t w[4])
+{
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    oracle_philox4x32_10(ctr, key, w);
+}
+
+/* dH of flipping site i: 2 s_i times the local field of the six bonds. */
+int64_t oracle_pt_delta(int Lx, int Ly, int Lz, const int32_t *Jq, const uint8_t *sig, int64_t i)
+{
+    geom g = mk(Lx, Ly, Lz);
+    int x, y, z;
+    coords(&g, i, &x, &y, &z);
+    int64_t fwd[3] = {site(&g, x + 1, y, z), site(&g, x, y + 1, z), site(&g, x, y, z + 1)};
+    int64_t bwd[3] = {site(&g, x - 1, y, z), site(&g, x, y - 1, z), site(&g, x, y, z - 1)};
+    int64_t h = 0;
+    for (int mu = 0; mu < 3; mu++) {
+        h += (int64_t)Jq[mu * g.N + i] * spin(sig[fwd[mu]]);
+        h += (int64_t)Jq[mu * g.N + bwd[mu]] * spin(sig[bwd[mu]]);
+    }
+    return 2 * spin(sig[i]) * h;
+}
+
+int64_t oracle_pt_energy(int Lx, int Ly, int Lz, const int32_t *Jq, const uint8_t *sig)
+{
+    geom g = mk(Lx, Ly, Lz);
+    int64_t H = 0;
+    for (int64_t i = 0; i < g.N; i++) {
+        int x, y, z;
+        coords(&g, i, &x, &y, &z);
+        int64_t fwd[3] = {site(&g, x + 1, y, z), site(&g, x, y + 1, z), site(&g, x, y, z + 1)};
+        for (int mu = 0; mu < 3; mu++) H -= (int64_t)Jq[mu * g.N + i] * spin(sig[i]) * spin(sig[fwd[mu]]);
+    }
+    return H;
+}
+
+void oracle_pt_init_spins(int Lx, int Ly, int Lz, int runs, int M, uint64_t seed, uint8_t *sigma)
+{
+    geom g = mk(Lx, Ly, Lz);
+    for (int u = 0; u < runs; u++)
+        for (int rep = 0; rep < 2; rep++)
+            for (int t = 0; t < M; t++)
+                for (int64_t i = 0; i < g.N; i++)
+                    sigma[(((int64_t)u * 2 + rep) * M + t) * g.N + i] =
+                        (uint8_t)(draw(seed, (uint32_t)(i >> 2), (uint32_t)t, (uint32_t)rep,
+                                       (uint32_t)(STREAM_PT_SPIN << 24) | (uint32_t)u, (int)(i & 3)) >> 31);
+}
+
+void oracle_pt_walker_refresh(int Lx, int Ly, int Lz, uint64_t seed, int run, int rep, int t, int64_t e,
+                              const uint64_t *table, int64_t *n)
+{
+    geom g = mk(Lx, Ly, Lz);
+    for (int64_t i = 0; i < g.N; i++) {
+        uint32_t w[4];
+        philox_words(seed, (uint32_t)i, (uint32_t)e, (uint32_t)(2 * t + rep),
+                     (uint32_t)(STREAM_PT_WALKER << 24) | (uint32_t)run, w);
+        n[i] = oracle_pt_exp_draw(table, w);
+    }
+}
+
+/* Creutz move on every site of one parity (Sec. 2.3, uncapped); returns
+   the summed dH of the accepted flips. */
+int64_t oracle_pt_creutz_half(int Lx, int Ly, int Lz, const int32_t *Jq, int parity, uint8_t *sig, int64_t *n)
+{
+    geom g = mk(Lx, Ly, Lz);
+    int64_t acc = 0;
+    for (int64_t i = 0; i < g.N; i++) {
+        if (parity_of(&g, i) != parity) continue;
+        int64_t dH = oracle_pt_delta(Lx, Ly, Lz, Jq, sig, i);
+        if (n[i] - dH >= 0) {
+            sig[i] ^= 1u;
+            n[i] -= dH;
+            acc += dH;
+        }
+    }
+    return acc;
+}
+
+/* Forward-X wandering (Sec. 2.6): the walker of each site of the given
+   parity is exchanged with the walker of its +x neighbour. */
+void oracle_pt_wander_x(int Lx, int Ly, int Lz, int parity, int64_t *n)
+{
+    geom g = mk(Lx, Ly, Lz);
+    for (int64_t i = 0; i < g.N; i++) {
+        if (parity_of(&g, i) != parity) continue;
+        int x, y, z;
+        coords(&g, i, &x, &y, &z);
+        int64_t j = site(&g, x + 1, y, z);
+        int64_t tmp = n[i];
+        n[i] = n[j];
+        n[j] = tmp;
+    }
+}
+
+int64_t oracle_pt_metropolis_half(int Lx, int Ly, int Lz, const int32_t *Jq, uint64_t seed, int run, int rep,
+                                  int t, int64_t k, int parity, const uint64_t *table, uint8_t *sig)
+{
+    geom g = mk(Lx, Ly, Lz);
+    int64_t acc = 0;
+    for (int64_t i = 0; i < g.N; i++) {
+        if (parity_of(&g, i) != parity) continue;
+        uint32_t w[4];
+        philox_words(seed, (uint32_t)i, (uint32_t)k, (uint32_t)(2 * t + rep),
+                     (uint32_t)(STREAM_PT_METROPOLIS << 24) | (uint32_t)run, w);
+        int64_t dH = oracle_pt_delta(Lx, Ly, Lz, Jq, sig, i);
+        if (oracle_pt_exp_draw(table, w) >= dH) {
+            sig[i] ^= 1u;
+            acc += dH;
+        }
+    }
+    return acc;
+}
+
+/* Houdayer move: the sites where the replicas differ form a graph with
+   the lattice bonds; the connected component of one of them, picked
+   uniformly (the k-th in site order, k = floor(u * count / 2^32)), is
+   flipped in both replicas.  Returns the cluster size (0: replicas equal). */
+int64_t oracle_pt_houdayer(int Lx, int Ly, int Lz, uint32_t u, uint8_t *sa, uint8_t *sb)
+{
+    geom g = mk(Lx, Ly, Lz);
+    int64_t count = 0;
+    for (int64_t i = 0; i < g.N; i++) count += sa[i] != sb[i];
+    if (count == 0) return 0;
+    int64_t k = (int64_t)(((uint64_t)u * (uint64_t)count) >> 32);
+    int64_t root = -1;
+    for (int64_t i = 0, c = 0; i < g.N; i++)
+        if (sa[i] != sb[i] && c++ == k) {
+            root = i;
+            break;
+        }
+    int64_t *queue = malloc(sizeof(int64_t) * (size_t)count);
+    uint8_t *seen = calloc((size_t)g.N, 1);
+    int64_t head = 0, tail = 0;
+    queue[tail++] = root;
+    seen[root] = 1;
+    while (head < tail) {
+        int64_t i = queue[head++];
+        int x, y, z;
+        coords(&g, i, &x, &y, &z);
+        int64_t nb[6] = {site(&g, x + 1, y, z), site(&g, x - 1, y, z), site(&g, x, y + 1, z),
+                         site(&g, x, y - 1, z), site(&g, x, y, z + 1), site(&g, x, y, z - 1)};
+        for (int d = 0; d < 6; d++)
+            if (!seen[nb[d]] && sa[nb[d]] != sb[nb[d]]) {
+                seen[nb[d]] = 1;
+                queue[tail++] = nb[d];
+            }
+    }
+    for (int64_t q = 0; q < tail; q++) {
+        sa[queue[q]] ^= 1u;
+        sb[queue[q]] ^= 1u;
+    }
+    free(queue);
+    free(seen);
+    return tail;
+}
+
+/* Tempering step of one replica group: sig[t] is the configuration at
+   temperature t; pair_tables[t] has rate beta_t - beta_{t+1}.  swaps[t]
+   (may be NULL) counts accepted exchanges of pair t. */
+void oracle_pt_swap_step(int Lx, int Ly, int Lz, const int32_t *Jq, int M, uint64_t seed, int run, int rep,
+                         int64_t e, const uint64_t *pair_tables, uint8_t *sig, int64_t *swaps)
+{
+    geom g = mk(Lx, Ly, Lz);
+    uint8_t *tmp = malloc((size_t)g.N);
+    for (int ph = 0; ph < 2; ph++)
+        for (int t = ph; t + 1 < M; t += 2) {
+            uint8_t *a = sig + (int64_t)t * g.N, *b = sig + (int64_t)(t + 1) * g.N;
+            int64_t x = oracle_pt_energy(Lx, Ly, Lz, Jq, a) - oracle_pt_energy(Lx, Ly, Lz, Jq, b);
+            uint32_t w[4];
+            philox_words(seed, (uint32_t)t, (uint32_t)e, (uint32_t)rep, (uint32_t)(STREAM_PT_SWAP << 24) | (uint32_t)run,
+                         w);
+            if (oracle_pt_exp_draw(pair_tables + (int64_t)t * PT_TABLE, w) >= -x) {
+                memcpy(tmp, a, (size_t)g.N);
+                memcpy(a, b, (size_t)g.N);
+                memcpy(b, tmp, (size_t)g.N);
+                if (swaps) swaps[t]++;
+            }
+        }
+    free(tmp);
+}
+
+/* Tables of a temperature ladder: walker_tables[t] at rate beta_t,
+   pair_tables[t] at rate beta_t - beta_{t+1}.  Returns -1 if T is not
+   strictly increasing and positive, or a table's top digit could reach 255. */
+int oracle_pt_tables(int M, const double *T, uint64_t *walker_tables, uint64_t *pair_tables)
+{
+    for (int t = 0; t < M; t++) {
+        if (!(T[t] > 0.0) || (t > 0 && !(T[t] > T[t - 1]))) return -1;
+        if (oracle_pt_exp_table(1.0 / T[t], walker_tables + (int64_t)t * PT_TABLE)) return -1;
+    }
+    for (int t = 0; t + 1 < M; t++)
+        if (oracle_pt_exp_table(1.0 / T[t] - 1.0 / T[t + 1], pair_tables + (int64_t)t * PT_TABLE)) return -1;
+    return 0;
+}
+
+/* n_emcs EMCS starting at index e0 on sigma[runs][2][M][N]; S sweeps per
+   EMCS.  swaps (may be NULL) is [runs][2][M-1]. */
+int oracle_pt_run(int Lx, int Ly, int Lz, int runs, int M, int S, int algo, int houdayer, uint64_t seed,
+                  const int32_t *Jq, const double *T, int64_t e0, int64_t n_emcs, uint8_t *sigma, int64_t *swaps)
+{
+    geom g = mk(Lx, Ly, Lz);
+    uint64_t *wt = malloc(sizeof(uint64_t) * PT_TABLE * (size_t)M);
+    uint64_t *pt = malloc(sizeof(uint64_t) * PT_TABLE * (size_t)(M > 1 ? M - 1 : 1));
+    if (oracle_pt_tables(M, T, wt, pt)) {
+        free(wt);
+        free(pt);
+        return -1;
+    }
+    for (int64_t e = e0; e < e0 + n_emcs; e++) {
+        /* 1. fixed-temperature moves, every lattice on its own */
+#pragma omp parallel for schedule(dynamic)
+        for (int64_t l = 0; l < (int64_t)runs * 2 * M; l++) {
+            int u = (int)(l / (2 * M)), rep = (int)((l / M) % 2), t = (int)(l % M);
+            uint8_t *sig = sigma + l * g.N;
+            if (algo == PT_WALKERS) {
+                int64_t *n = malloc(sizeof(int64_t) * (size_t)g.N);
+                oracle_pt_walker_refresh(Lx, Ly, Lz, seed, u, rep, t, e, wt + (int64_t)t * PT_TABLE, n);
+                for (int s = 0; s < S; s++) {
+                    oracle_pt_creutz_half(Lx, Ly, Lz, Jq, 0, sig, n);
+                    oracle_pt_creutz_half(Lx, Ly, Lz, Jq, 1, sig, n);
+                    oracle_pt_wander_x(Lx, Ly, Lz, s & 1, n);
+                }
+                free(n);
+            } else {
+                for (int s = 0; s < S; s++)
+                    for (int p = 0; p < 2; p++)
+                        oracle_pt_metropolis_half(Lx, Ly, Lz, Jq, seed, u, rep, t, e * S + s, p,
+                                                  wt + (int64_t)t * PT_TABLE, sig);
+            }
+        }
+        for (int u = 0; u < runs; u++) {
+            /* 2. Houdayer move at every temperature */
+            if (houdayer)
+                for (int t = 0; t < M; t++)
+                    oracle_pt_houdayer(Lx, Ly, Lz,
+                                       draw(seed, (uint32_t)t, (uint32_t)e, 0u,
+                                            (uint32_t)(STREAM_PT_HOUDAYER << 24) | (uint32_t)u, 0),
+                                       sigma + (((int64_t)u * 2 + 0) * M + t) * g.N,
+                                       sigma + (((int64_t)u * 2 + 1) * M + t) * g.N);
+            /* 3. tempering in each replica group */
+            for (int rep = 0; rep < 2; rep++)
+                oracle_pt_swap_step(Lx, Ly, Lz, Jq, M, seed, u, rep, e, pt,
+                                    sigma + ((int64_t)u * 2 + rep) * M * g.N,
+                                    swaps ? swaps + ((int64_t)u * 2 + rep) * (M - 1) : NULL);
+        }
+    }
+    free(wt);
+    free(pt);
     return 0;
 }
 

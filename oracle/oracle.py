@@ -98,6 +98,35 @@ def lib():
         L.oracle_run.restype = c.c_int
         L.oracle_density_of_states.argtypes = [c.c_int, c.c_int, c.c_int, _u8p, _u64p]
         L.oracle_density_of_states.restype = c.c_int
+        _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+        L.oracle_pt_quantise.argtypes = [c.c_int64, _f64p, _i32p]
+        L.oracle_pt_quantise.restype = c.c_int
+        L.oracle_pt_exp_table.argtypes = [c.c_double, _u64p]
+        L.oracle_pt_exp_table.restype = c.c_int
+        L.oracle_pt_exp_draw.argtypes = [_u64p, _u32p]
+        L.oracle_pt_exp_draw.restype = c.c_int64
+        L.oracle_pt_delta.argtypes = [c.c_int, c.c_int, c.c_int, _i32p, _u8p, c.c_int64]
+        L.oracle_pt_delta.restype = c.c_int64
+        L.oracle_pt_energy.argtypes = [c.c_int, c.c_int, c.c_int, _i32p, _u8p]
+        L.oracle_pt_energy.restype = c.c_int64
+        L.oracle_pt_init_spins.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64, _u8p]
+        L.oracle_pt_walker_refresh.argtypes = [c.c_int, c.c_int, c.c_int, c.c_uint64, c.c_int, c.c_int, c.c_int,
+                                               c.c_int64, _u64p, _i64p]
+        L.oracle_pt_creutz_half.argtypes = [c.c_int, c.c_int, c.c_int, _i32p, c.c_int, _u8p, _i64p]
+        L.oracle_pt_creutz_half.restype = c.c_int64
+        L.oracle_pt_wander_x.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, _i64p]
+        L.oracle_pt_metropolis_half.argtypes = [c.c_int, c.c_int, c.c_int, _i32p, c.c_uint64, c.c_int, c.c_int,
+                                                c.c_int, c.c_int64, c.c_int, _u64p, _u8p]
+        L.oracle_pt_metropolis_half.restype = c.c_int64
+        L.oracle_pt_houdayer.argtypes = [c.c_int, c.c_int, c.c_int, c.c_uint32, _u8p, _u8p]
+        L.oracle_pt_houdayer.restype = c.c_int64
+        L.oracle_pt_swap_step.argtypes = [c.c_int, c.c_int, c.c_int, _i32p, c.c_int, c.c_uint64, c.c_int, c.c_int,
+                                          c.c_int64, _u64p, _u8p, c.c_void_p]
+        L.oracle_pt_tables.argtypes = [c.c_int, _f64p, _u64p, _u64p]
+        L.oracle_pt_tables.restype = c.c_int
+        L.oracle_pt_run.argtypes = [c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int, c.c_int,
+                                    c.c_uint64, _i32p, _f64p, c.c_int64, c.c_int64, _u8p, c.c_void_p]
+        L.oracle_pt_run.restype = c.c_int
         L.oracle_threads.restype = c.c_int
         L.oracle_set_threads.argtypes = [c.c_int]
         _lib = L
@@ -340,3 +369,137 @@ def canonical_mean_energy(g: np.ndarray, N: int, T: float) -> float:
     beta = 1.0 / T
     w = g.astype(np.float64) * np.exp(-beta * (H - H.min()))
     return float((H * w).sum() / w.sum())
+
+
+# ------------------------------------------------- App. C equilibrium workload
+# Gaussian couplings on the energy mesh eps = 2^-17, continuous walkers
+# (exponential on the mesh), parallel tempering with Houdayer moves; every
+# number comes from the oracle_pt_* functions of oracle.c.
+PT_WALKERS, PT_METROPOLIS = 0, 1
+PT_MESH = 2.0 ** -17
+
+
+def pt_quantise(J: np.ndarray) -> np.ndarray:
+    """Couplings as integer multiples of the mesh (ValueError if |J| > 8 or not finite)."""
+    J = np.ascontiguousarray(J, np.float64)
+    Jq = np.zeros(J.shape, np.int32)
+    if lib().oracle_pt_quantise(J.size, J.reshape(-1), Jq.reshape(-1)) != 0:
+        raise ValueError("couplings must be finite with |J| <= 8")
+    return Jq
+
+
+def pt_exp_table(lam: float) -> tuple[np.ndarray, bool]:
+    """[4, 255] digit thresholds of the mesh exponential of rate lam; ok is
+    False if the top digit could reach 255."""
+    t = np.zeros((4, 255), np.uint64)
+    ok = lib().oracle_pt_exp_table(float(lam), t.reshape(-1)) == 0
+    return t, ok
+
+
+def pt_exp_draw(table: np.ndarray, w) -> int:
+    return int(lib().oracle_pt_exp_draw(np.ascontiguousarray(table, np.uint64).reshape(-1),
+                                        np.ascontiguousarray(w, np.uint32)))
+
+
+def pt_tables(T) -> tuple[np.ndarray, np.ndarray]:
+    """Walker tables [M, 4, 255] (rate beta_t) and pair tables [M-1, 4, 255]
+    (rate beta_t - beta_{t+1}); ValueError for an invalid ladder."""
+    T = np.ascontiguousarray(T, np.float64)
+    M = len(T)
+    wt = np.zeros((M, 4, 255), np.uint64)
+    pt = np.zeros((max(M - 1, 1), 4, 255), np.uint64)
+    if lib().oracle_pt_tables(M, T, wt.reshape(-1), pt.reshape(-1)) != 0:
+        raise ValueError("temperatures must be positive and strictly increasing, within the sampler's range")
+    return wt, pt[:M - 1]
+
+
+def pt_delta(dims, Jq, sig, i: int) -> int:
+    return int(lib().oracle_pt_delta(*dims, Jq.reshape(-1), sig, int(i)))
+
+
+def pt_energy(dims, Jq, sig) -> int:
+    return int(lib().oracle_pt_energy(*dims, Jq.reshape(-1), sig))
+
+
+def pt_walker_refresh(dims, seed, run, rep, t, e, table) -> np.ndarray:
+    n = np.zeros(dims[0] * dims[1] * dims[2], np.int64)
+    lib().oracle_pt_walker_refresh(*dims, seed, run, rep, t, e, np.ascontiguousarray(table).reshape(-1), n)
+    return n
+
+
+def pt_creutz_half(dims, Jq, parity, sig, n) -> int:
+    return int(lib().oracle_pt_creutz_half(*dims, Jq.reshape(-1), parity, sig, n))
+
+
+def pt_wander_x(dims, parity, n) -> None:
+    lib().oracle_pt_wander_x(*dims, parity, n)
+
+
+def pt_metropolis_half(dims, Jq, seed, run, rep, t, k, parity, table, sig) -> int:
+    return int(lib().oracle_pt_metropolis_half(*dims, Jq.reshape(-1), seed, run, rep, t, k, parity,
+                                               np.ascontiguousarray(table).reshape(-1), sig))
+
+
+def pt_houdayer(dims, u: int, sa, sb) -> int:
+    return int(lib().oracle_pt_houdayer(*dims, int(u) & 0xFFFFFFFF, sa, sb))
+
+
+def pt_swap_step(dims, Jq, seed, run, rep, e, pair_tables, sig, swaps=None) -> None:
+    """sig[M, N]: the configurations of one replica group by temperature."""
+    M = sig.shape[0]
+    lib().oracle_pt_swap_step(*dims, Jq.reshape(-1), M, seed, run, rep, e,
+                              np.ascontiguousarray(pair_tables, np.uint64).reshape(-1), sig.reshape(-1),
+                              None if swaps is None else swaps.ctypes.data)
+
+
+@dataclass
+class PTLattice:
+    """runs x 2 replicas x M temperatures of one Gaussian sample J[3, N]."""
+    Lx: int
+    Ly: int
+    Lz: int
+    runs: int
+    T: np.ndarray
+    J: np.ndarray
+    seed: int
+    sweeps: int = 10
+    algo: int = PT_WALKERS
+    houdayer: bool = True
+    e: int = 0
+    sigma: np.ndarray = field(default=None, repr=False)   # [runs, 2, M, N] by temperature
+
+    def __post_init__(self):
+        self.T = np.ascontiguousarray(self.T, np.float64)
+        self.M = len(self.T)
+        self.N = self.Lx * self.Ly * self.Lz
+        self.Jq = pt_quantise(np.asarray(self.J, np.float64).reshape(3, self.N))
+        if self.sigma is None:
+            self.sigma = np.zeros((self.runs, 2, self.M, self.N), np.uint8)
+            lib().oracle_pt_init_spins(self.Lx, self.Ly, self.Lz, self.runs, self.M, self.seed,
+                                       self.sigma.reshape(-1))
+
+    @property
+    def dims(self):
+        return (self.Lx, self.Ly, self.Lz)
+
+    def run(self, n_emcs: int, swaps: np.ndarray | None = None) -> None:
+        st = lib().oracle_pt_run(self.Lx, self.Ly, self.Lz, self.runs, self.M, self.sweeps, self.algo,
+                                 int(self.houdayer), self.seed, self.Jq.reshape(-1), self.T, self.e, n_emcs,
+                                 self.sigma.reshape(-1), None if swaps is None else swaps.ctypes.data)
+        if st != 0:
+            raise ValueError("invalid temperature ladder")
+        self.e += n_emcs
+
+    def energies(self) -> np.ndarray:
+        """[runs, 2, M] H in units of the mesh."""
+        E = np.zeros((self.runs, 2, self.M), np.int64)
+        for u in range(self.runs):
+            for r in range(2):
+                for t in range(self.M):
+                    E[u, r, t] = pt_energy(self.dims, self.Jq, self.sigma[u, r, t])
+        return E
+
+    def overlaps(self) -> np.ndarray:
+        """[runs, M] Q = sum_x s^a_x s^b_x of the two replicas at each temperature."""
+        s = 1 - 2 * self.sigma.astype(np.int64)
+        return (s[:, 0] * s[:, 1]).sum(axis=-1)

@@ -13,6 +13,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 
+import numpy as np
+
 SCHED_CONST, SCHED_LINEAR = 0, 1
 
 
@@ -52,3 +54,48 @@ ANNEAL_L512 = Workload("anneal_L512_T3.0-0.2", 512, 512, 512, 1, 1, 0x5EED0004, 
                        20)
 
 ALL = {w.name: w for w in (PARAMAGNET_L16, QUENCH_L64, BATCHED_L32, ANNEAL_L512)}
+
+
+# ----------------------------------------------------------- App. C workload
+def gaussian_couplings(Lx: int, Ly: int, Lz: int, seed: int) -> np.ndarray:
+    """One sample of Gaussian couplings J ~ N(0, 1) (App. C) as [3, N]: row mu
+    holds the bond (i, i + e_mu), site i = x + Lx (y + Ly z).  Values beyond
+    |J| = 8 (probability about 1e-15 per bond) are clipped to the range the
+    library accepts."""
+    rng = np.random.default_rng(seed)
+    return np.clip(rng.standard_normal((3, Lx * Ly * Lz)), -8.0, 8.0)
+
+
+@dataclass(frozen=True)
+class PTWorkload:
+    """Parallel tempering of one Gaussian sample: runs independent runs, each
+    with 2 replicas of M clones at temperatures uniform in [Tmin, Tmax]; an
+    EMCS is `sweeps` sweeps per clone, a Houdayer move per temperature and a
+    tempering step per replica (App. C)."""
+    name: str
+    L: int
+    runs: int
+    M: int
+    Tmin: float
+    Tmax: float
+    sweeps: int
+    seed: int
+
+    @property
+    def N(self) -> int:
+        return self.L ** 3
+
+    def temperatures(self) -> np.ndarray:
+        return np.linspace(self.Tmin, self.Tmax, self.M)
+
+    def couplings(self) -> np.ndarray:
+        return gaussian_couplings(self.L, self.L, self.L, self.seed)
+
+    def updates(self, emcs: int) -> int:
+        """Spin updates: every site of every clone once per sweep."""
+        return self.N * 2 * self.M * self.runs * self.sweeps * emcs
+
+
+# the paper's App. C set-up (L = 10, N_R = 2, N_beta = 40, T in [0.2, 2], 10
+# sweeps per EMCS) with 200 independent runs of the sample, as in its Table 4
+PT_L10 = PTWorkload("pt_gauss_L10_200x2x40", 10, 200, 40, 0.2, 2.0, 10, 0x5EED0006)

@@ -787,3 +787,337 @@ def test_xi_from_c4_closed_forms():
     assert abs(b - (1 + 4 * q + q * q) / ((1 + q) * (1 - q))) < 1e-9
     assert all(math.isnan(v) for v in O.xi_from_c4(np.array([1.0, 0.0, 0.0])))
     assert all(math.isnan(v) for v in O.xi_from_c4(np.array([1.0, -0.1, 0.05])))
+
+
+# ------------------------------------------- App. C: Gaussian PT workload
+EPS = 2.0 ** -17
+
+
+def _gauss(n_sites, seed):
+    return np.clip(np.random.default_rng(seed).standard_normal((3, n_sites)), -8, 8)
+
+
+def _np_energy(dims, Jq, sig):
+    """H = -sum over bonds Jq s_x s_y evaluated with array shifts (an
+    evaluation independent of the oracle's site loops)."""
+    Lx, Ly, Lz = dims
+    s = (1 - 2 * sig.astype(np.int64)).reshape(Lz, Ly, Lx)
+    J = Jq.astype(np.int64).reshape(3, Lz, Ly, Lx)
+    return int(-sum((J[mu] * s * np.roll(s, -1, axis=ax)).sum() for mu, ax in ((0, 2), (1, 1), (2, 0))))
+
+
+def _tail_from_digits(t, k):
+    """P(n >= k) from the digit thresholds alone: lexicographic comparison
+    of the independent digits, top digit first."""
+    pmf = [np.diff(np.concatenate(([0], t[d].astype(np.float64), [2.0 ** 32]))) / 2.0 ** 32 for d in range(4)]
+    kd = [(k >> (8 * d)) & 255 for d in range(4)]
+    P, prod = 0.0, 1.0
+    for d in (3, 2, 1, 0):
+        P += prod * pmf[d][kd[d] + 1:].sum()
+        prod *= pmf[d][kd[d]]
+    return P + prod
+
+
+def test_pt_quantise_mesh():
+    """Couplings go to the nearest multiple of 2^-17, ties to even; |J| <= 8."""
+    J = np.array([0.5, 1.5, -2.5, 3.25, 8.0, -8.0, 1.0 / 3.0]) * np.array([EPS] * 4 + [1, 1, 1])
+    assert O.pt_quantise(J).tolist() == [0, 2, -2, 3, 8 << 17, -(8 << 17), 43691]
+    Jr = _gauss(1000, 1)
+    Jq = O.pt_quantise(Jr)
+    assert np.abs(Jq * EPS - Jr).max() <= EPS / 2
+    for bad in (8.000001, np.nan, np.inf):
+        with pytest.raises(ValueError):
+            O.pt_quantise(np.array([0.0, bad]))
+
+
+@pytest.mark.parametrize("lam", [5.0, 2.0, 0.5, 0.087, 1 / 0.2 - 1 / 0.2462])
+def test_pt_exp_digits_factorise(lam):
+    """The four digit laws multiply to the geometric law of the mesh
+    exponential: P(n >= k) = exp(-lam eps k), to the 2^-32 resolution of
+    each threshold (Sec. 2.3: exponential walkers)."""
+    t, ok = O.pt_exp_table(lam)
+    assert ok
+    assert all(np.all(np.diff(t[d].astype(np.int64)) >= 0) for d in range(4))
+    mean = 1.0 / (lam * EPS)
+    rng = np.random.default_rng(3)
+    ks = [0, 1, 255, 256, 257, 65535, 65536, 1 << 24] + [int(v) for v in rng.exponential(mean, 40)]
+    for k in ks:
+        assert abs(_tail_from_digits(t, k) - math.exp(-lam * EPS * k)) < 1e-8, k
+
+
+def test_pt_exp_table_range():
+    """Rates too small for four digits are refused; walkers at T = 2 are fine."""
+    assert O.pt_exp_table(0.5)[1]
+    assert not O.pt_exp_table(1e-4)[1]
+
+
+def test_pt_exp_draw_statistics():
+    """Walker draws through the counter-based generator follow the geometric
+    law: chi^2 over 20 bins of equal probability."""
+    lam = 2.0
+    dims = (64, 64, 64)
+    t, _ = O.pt_exp_table(lam)
+    n = O.pt_walker_refresh(dims, 11, 0, 0, 0, 0, t)
+    q = lam * EPS
+    edges = [0] + [int(math.ceil(-math.log(1 - j / 20) / q)) for j in range(1, 20)] + [1 << 40]
+    obs = np.histogram(n, bins=edges)[0]
+    p = np.diff([1 - math.exp(-q * e) if e < (1 << 40) else 1.0 for e in edges])
+    chi2 = float(((obs - n.size * p) ** 2 / (n.size * p)).sum())
+    assert chi2 < 50, chi2  # 19 degrees of freedom
+    assert abs(n.mean() * q - 1) < 5 / math.sqrt(n.size)
+
+
+def test_pt_delta_and_energy_brute_force():
+    """dH of every single-spin flip equals the energy difference evaluated
+    from scratch; the oracle's energy equals the array evaluation."""
+    dims = (4, 6, 8)
+    N = 4 * 6 * 8
+    Jq = O.pt_quantise(_gauss(N, 5))
+    sig = np.random.default_rng(6).integers(0, 2, N).astype(np.uint8)
+    H0 = _np_energy(dims, Jq, sig)
+    assert O.pt_energy(dims, Jq, sig) == H0
+    for i in range(N):
+        s2 = sig.copy()
+        s2[i] ^= 1
+        assert O.pt_delta(dims, Jq, sig, i) == _np_energy(dims, Jq, s2) - H0
+
+
+def _dH_all(dims, Jq, sig):
+    H0 = _np_energy(dims, Jq, sig)
+    out = np.zeros(sig.size, np.int64)
+    for i in range(sig.size):
+        s2 = sig.copy()
+        s2[i] ^= 1
+        out[i] = _np_energy(dims, Jq, s2) - H0
+    return out
+
+
+def _parity(dims):
+    Lx, Ly, Lz = dims
+    z, y, x = np.meshgrid(np.arange(Lz), np.arange(Ly), np.arange(Lx), indexing="ij")
+    return ((x + y + z) & 1).reshape(-1)
+
+
+def test_pt_creutz_rule_at_the_boundary():
+    """Uncapped Creutz move (Sec. 2.3, App. C): a spin flips iff its walker
+    can pay dH (n - dH >= 0), and the walker then holds n - dH."""
+    dims = (4, 4, 4)
+    Jq = O.pt_quantise(_gauss(64, 7))
+    rng = np.random.default_rng(8)
+    sig = rng.integers(0, 2, 64).astype(np.uint8)
+    dH = _dH_all(dims, Jq, sig)
+    n = np.maximum(dH + rng.integers(-1, 2, 64), 0).astype(np.int64)
+    s2, n2 = sig.copy(), n.copy()
+    O.pt_creutz_half(dims, Jq, 0, s2, n2)
+    even = _parity(dims) == 0
+    flip = even & (n >= dH)
+    assert np.array_equal(s2, sig ^ flip.astype(np.uint8))
+    assert np.array_equal(n2, np.where(flip, n - dH, n))
+
+
+def test_pt_creutz_conservation_and_involution():
+    """H + sum n is constant under every half sweep and walkers stay >= 0;
+    each half sweep is its own inverse (Sec. 2.3: reversibility)."""
+    dims = (6, 4, 8)
+    N = 6 * 4 * 8
+    Jq = O.pt_quantise(_gauss(N, 9))
+    sig = np.random.default_rng(10).integers(0, 2, N).astype(np.uint8)
+    t, _ = O.pt_exp_table(1 / 0.7)
+    n = O.pt_walker_refresh(dims, 12, 0, 1, 3, 5, t)
+    total = _np_energy(dims, Jq, sig) + n.sum()
+    for s in range(6):
+        for p in (0, 1):
+            s0, n0 = sig.copy(), n.copy()
+            O.pt_creutz_half(dims, Jq, p, sig, n)
+            assert _np_energy(dims, Jq, sig) + n.sum() == total
+            assert n.min() >= 0
+            s1, n1 = sig.copy(), n.copy()
+            O.pt_creutz_half(dims, Jq, p, s1, n1)
+            assert np.array_equal(s1, s0) and np.array_equal(n1, n0)
+        O.pt_wander_x(dims, s & 1, n)
+        assert _np_energy(dims, Jq, sig) + n.sum() == total
+
+
+def test_pt_wander_cycle():
+    """Forward-X wandering (Sec. 2.6): the first step moves the walker of
+    each even site one site along +x; after L_x steps every walker is home."""
+    dims = (6, 2, 4)
+    N = 48
+    n0 = np.arange(N, dtype=np.int64)
+    n = n0.copy()
+    O.pt_wander_x(dims, 0, n)
+    x = np.arange(N) % 6
+    even = _parity(dims) == 0
+    fwd = np.where(x == 5, np.arange(N) - 5, np.arange(N) + 1)
+    assert np.array_equal(n[fwd[even]], n0[even])
+    for s in range(1, 6):
+        assert not np.array_equal(n, n0)
+        O.pt_wander_x(dims, s & 1, n)
+    assert np.array_equal(n, n0)
+
+
+def test_pt_metropolis_acceptance():
+    """A fresh exponential draw per attempt accepts a flip with probability
+    min(1, exp(-beta dH)) (Sec. 2.3): per-site chi^2 over 1500 attempts."""
+    dims = (4, 4, 4)
+    Jq = O.pt_quantise(_gauss(64, 13))
+    sig = np.random.default_rng(14).integers(0, 2, 64).astype(np.uint8)
+    T = 3.0
+    t, _ = O.pt_exp_table(1 / T)
+    dH = _dH_all(dims, Jq, sig)
+    even = np.flatnonzero(_parity(dims) == 0)
+    K = 1500
+    flips = np.zeros(64)
+    for k in range(K):
+        s2 = sig.copy()
+        O.pt_metropolis_half(dims, Jq, 15, 0, 1, 2, k, 0, t, s2)
+        flips += s2 != sig
+    P = np.minimum(1.0, np.exp(-dH * EPS / T))
+    assert np.all(flips[even][P[even] == 1.0] == K)
+    mid = even[(P[even] > 0.02) & (P[even] < 0.98)]
+    assert len(mid) >= 8
+    chi2 = float((((flips[mid] - K * P[mid]) ** 2) / (K * P[mid] * (1 - P[mid]))).sum())
+    assert chi2 < len(mid) + 6 * math.sqrt(2 * len(mid)), chi2
+    assert np.all(flips[np.flatnonzero(_parity(dims) == 1)] == 0)
+
+
+def _components(dims, diff):
+    """Connected components of the differing sites (union-find over the
+    lattice bonds, periodic)."""
+    Lx, Ly, Lz = dims
+    N = Lx * Ly * Lz
+    parent = list(range(N))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+    for i in range(N):
+        if not diff[i]:
+            continue
+        x, y, z = i % Lx, (i // Lx) % Ly, i // (Lx * Ly)
+        for j in ((x + 1) % Lx + Lx * (y + Ly * z), x + Lx * ((y + 1) % Ly + Ly * z),
+                  x + Lx * (y + Ly * ((z + 1) % Lz))):
+            if diff[j]:
+                parent[find(i)] = find(j)
+    return [find(i) for i in range(N)]
+
+
+def test_pt_houdayer_cluster():
+    """Houdayer move: the cluster of differing sites holding the chosen site
+    is flipped in both replicas -- the overlap field and E_a + E_b are
+    unchanged, and the flipped set is exactly one connected component."""
+    dims = (6, 6, 6)
+    N = 216
+    Jq = O.pt_quantise(_gauss(N, 16))
+    rng = np.random.default_rng(17)
+    for trial in range(12):
+        sa = rng.integers(0, 2, N).astype(np.uint8)
+        sb = sa ^ (rng.random(N) < 0.3).astype(np.uint8)
+        diff = sa != sb
+        sites = np.flatnonzero(diff)
+        u = [0, 0xFFFFFFFF][trial] if trial < 2 else int(rng.integers(0, 2 ** 32))
+        root = sites[(u * len(sites)) >> 32]
+        comp = np.array(_components(dims, diff))
+        cluster = diff & (comp == comp[root])
+        Ea, Eb = _np_energy(dims, Jq, sa), _np_energy(dims, Jq, sb)
+        a2, b2 = sa.copy(), sb.copy()
+        size = O.pt_houdayer(dims, u, a2, b2)
+        assert size == cluster.sum()
+        assert np.array_equal(a2, sa ^ cluster.astype(np.uint8))
+        assert np.array_equal(b2, sb ^ cluster.astype(np.uint8))
+        assert _np_energy(dims, Jq, a2) + _np_energy(dims, Jq, b2) == Ea + Eb
+    same = sa.copy()
+    assert O.pt_houdayer(dims, 123, sa, same) == 0 and np.array_equal(same, sa)
+
+
+def test_pt_swap_phase_order():
+    """A tempering step tries the pairs (t, t+1) with t even, then t odd;
+    with energies falling along the ladder every try is accepted, so the
+    configurations A B C D end as B D A C."""
+    dims = (4, 4, 4)
+    Jq = O.pt_quantise(_gauss(64, 18))
+    rng = np.random.default_rng(19)
+    cfg = [rng.integers(0, 2, 64).astype(np.uint8) for _ in range(4)]
+    cfg.sort(key=lambda s: -_np_energy(dims, Jq, s))
+    E = [_np_energy(dims, Jq, s) for s in cfg]
+    assert E[0] > E[1] > E[2] > E[3]
+    _, pt = O.pt_tables([0.5, 0.7, 1.0, 1.5])
+    sig = np.stack(cfg)
+    O.pt_swap_step(dims, Jq, 20, 0, 0, 0, pt, sig)
+    assert [next(k for k in range(4) if np.array_equal(sig[t], cfg[k])) for t in range(4)] == [1, 3, 0, 2]
+
+
+def test_pt_swap_acceptance():
+    """Exchange of a lower-energy configuration at the lower temperature is
+    accepted with probability exp((beta_0 - beta_1)(E_0 - E_1))."""
+    dims = (4, 4, 4)
+    Jq = O.pt_quantise(_gauss(64, 21))
+    rng = np.random.default_rng(22)
+    T = [1.0, 1.05]
+    db = 1 / T[0] - 1 / T[1]
+    while True:
+        a, b = (rng.integers(0, 2, 64).astype(np.uint8) for _ in range(2))
+        x = _np_energy(dims, Jq, a) - _np_energy(dims, Jq, b)
+        if 0.4 < -x * EPS * db < 1.5:
+            break
+    _, pt = O.pt_tables(T)
+    K = 4000
+    acc = 0
+    for e in range(K):
+        sig = np.stack([a, b])
+        O.pt_swap_step(dims, Jq, 23, 1, 0, e, pt, sig)
+        acc += np.array_equal(sig[0], b)
+    P = math.exp(x * EPS * db)
+    assert abs(acc - K * P) < 5 * math.sqrt(K * P * (1 - P)), (acc, K * P)
+
+
+def _fwht(a):
+    a = a.copy()
+    h = 1
+    while h < len(a):
+        a = a.reshape(-1, 2, h)
+        a = np.stack([a[:, 0] + a[:, 1], a[:, 0] - a[:, 1]], axis=1).reshape(-1)
+        h *= 2
+    return a
+
+
+@pytest.mark.parametrize("algo", [O.PT_WALKERS, O.PT_METROPOLIS])
+def test_pt_equilibrium_brute_force(algo):
+    """Parallel tempering with walkers (or Metropolis) and Houdayer moves
+    samples the canonical law (App. C): on a 2x2x4 Gaussian sample the
+    long-run <H> and <|q|> at each temperature match exact enumeration of
+    all 2^16 states (|q| through the XOR autocorrelation of the two
+    independent replicas' laws)."""
+    dims = (2, 2, 4)
+    N = 16
+    J = _gauss(N, 24)
+    Jq = O.pt_quantise(J)
+    T = np.array([0.5, 0.8, 1.2, 2.0])
+    states = ((np.arange(1 << N)[:, None] >> np.arange(N)) & 1).astype(np.int64)
+    s = (1 - 2 * states).reshape(-1, 4, 2, 2)
+    Jm = Jq.astype(np.int64).reshape(3, 4, 2, 2)
+    H = -sum((Jm[mu] * s * np.roll(s, -1, axis=ax)).sum(axis=(1, 2, 3)) for mu, ax in ((0, 3), (1, 2), (2, 1)))
+    pop = np.array([bin(c).count("1") for c in range(1 << N)])
+    exact_e, exact_q = [], []
+    for Tt in T:
+        w = np.exp(-(H - H.min()) * EPS / Tt)
+        p = w / w.sum()
+        exact_e.append(float((p * H).sum()) * EPS / N)
+        auto = _fwht(_fwht(p) ** 2) / (1 << N)
+        exact_q.append(float((auto * np.abs(N - 2 * pop)).sum()) / N)
+    runs, n_emcs, burn = 16, 500, 100
+    lat = O.PTLattice(*dims, runs=runs, T=T, J=J, seed=25 + algo, sweeps=10, algo=algo, houdayer=True)
+    e_sum = np.zeros((runs, 4))
+    q_sum = np.zeros((runs, 4))
+    for k in range(n_emcs):
+        lat.run(1)
+        if k >= burn:
+            e_sum += lat.energies().sum(axis=1) * EPS / (2 * N)
+            q_sum += np.abs(lat.overlaps()) / N
+    e_run, q_run = e_sum / (n_emcs - burn), q_sum / (n_emcs - burn)
+    for t in range(4):
+        for got, want in ((e_run[:, t], exact_e[t]), (q_run[:, t], exact_q[t])):
+            err = got.std(ddof=1) / math.sqrt(runs)
+            assert abs(got.mean() - want) < 4.5 * err + 2e-3, (t, got.mean(), want, err)

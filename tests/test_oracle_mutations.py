@@ -56,6 +56,28 @@ MUTATIONS = [
      "site(&g, x + (mu == 1) * r, y + (mu == 0) * r, z + (mu == 2) * r)", "c4"),
     ("C4 replica pairs", "for (int b = a + 1; b < R; b++) {", "for (int b = a; b < R; b++) {", "c4"),
     ("xi ratio", "*xi12 = I[2] / I[1];", "*xi12 = I[2] / I[0];", "xi"),
+    ("mesh exponential digit scale", "ldexp(1.0, 8 * d - 17)", "ldexp(1.0, 8 * d - 16)", "pt_exp_digits"),
+    ("mesh exponential top digit", ": -expm1(a * (double)(v + 1));", ": -expm1(a * (double)(v));",
+     "pt_exp_digits"),
+    ("mesh exponential digit word", "c += (uint64_t)w[d] >= t[d * 255 + v];", "c += (uint64_t)w[0] >= t[d * 255 + v];",
+     "pt_exp_draw"),
+    ("uncapped Creutz bound", "if (n[i] - dH >= 0) {", "if (n[i] - dH > 0) {", "pt_creutz_rule"),
+    ("walker update sign", "n[i] -= dH;", "n[i] += dH;", "pt_creutz"),
+    ("Gaussian backward bond", "h += (int64_t)Jq[mu * g.N + bwd[mu]] * spin(sig[bwd[mu]]);",
+     "h += (int64_t)Jq[mu * g.N + i] * spin(sig[bwd[mu]]);", "pt_delta"),
+    ("Houdayer flips one replica", "        sb[queue[q]] ^= 1u;\n", "", "pt_houdayer or pt_equilibrium"),
+    ("Houdayer neighbour", "int64_t nb[6] = {site(&g, x + 1, y, z), site(&g, x - 1, y, z),",
+     "int64_t nb[6] = {site(&g, x + 1, y, z), site(&g, x + 1, y, z),", "pt_houdayer"),
+    ("Houdayer root order", "int64_t k = (int64_t)(((uint64_t)u * (uint64_t)count) >> 32);",
+     "int64_t k = count - 1 - (int64_t)(((uint64_t)u * (uint64_t)count) >> 32);", "pt_houdayer"),
+    ("tempering swap sign", "if (oracle_pt_exp_draw(pair_tables + (int64_t)t * PT_TABLE, w) >= -x) {",
+     "if (oracle_pt_exp_draw(pair_tables + (int64_t)t * PT_TABLE, w) >= x) {", "pt_swap"),
+    ("tempering pair order", "for (int t = ph; t + 1 < M; t += 2) {", "for (int t = 0; t + 1 < M; t += 1) {",
+     "pt_swap_phase"),
+    ("tempering rate", "oracle_pt_exp_table(1.0 / T[t] - 1.0 / T[t + 1],", "oracle_pt_exp_table(1.0 / T[t],",
+     "pt_swap_acceptance or pt_equilibrium"),
+    ("Metropolis fresh draw per sweep", "philox_words(seed, (uint32_t)i, (uint32_t)k,",
+     "philox_words(seed, (uint32_t)i, 0u,", "pt_metropolis"),
     ("walker step direction", "{{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}", "{{-1, 0, 0}, {1, 0, 0}, {0, 1, 0}", "walkers"),
 ]
 
