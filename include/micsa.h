@@ -288,6 +288,92 @@ int micsa_pool_job_context(micsa_pool* pool, int64_t job, micsa_ctx** ctx);
 /* Free a DONE job's device memory (EINVAL for an unknown or unfinished job). */
 int micsa_pool_release(micsa_pool* pool, int64_t job);
 
+/* ------------------------------------------------------------------------
+ * Equilibrium workload (App. C): parallel tempering of one sample with
+ * Gaussian couplings, continuous walkers and Houdayer cluster moves.
+ *
+ * Energy mesh: the paper allows continuous walkers or walkers on a fine
+ * energy mesh (Sec. 2.3).  Every energy here is an integer multiple of
+ * 2^-17: a coupling J becomes Jq = nearest integer to J * 2^17 (ties to
+ * even), and H, dH, walkers and the energies returned are in those units.
+ * An exponential of rate lambda on the mesh, P(n) = (1 - q) q^n with
+ * q = exp(-lambda 2^-17), is drawn as four independent base-256 digits,
+ * digit d by inverse CDF on word d of one Philox output against a table
+ * t_d[v] = floor(2^32 P(c_d <= v)), v = 0..254 (micsa_pt_get_tables).
+ *
+ * One EMCS (App. C), for every run: (1) every (temperature t, replica)
+ * draws its walkers at beta_t and does `sweeps` times a full sweep (even,
+ * then odd sites; uncapped Creutz move: flip iff n - dH >= 0, n -= dH)
+ * followed by a forward-X wandering of the sites of parity s & 1 (Sec.
+ * 2.6); with MICSA_PT_METROPOLIS each visit draws a fresh walker instead,
+ * which is the Metropolis rule (Sec. 2.3); (2) a Houdayer move at every
+ * temperature: the connected cluster of sites where the two replicas
+ * differ that holds the k-th such site, k = floor(u * count / 2^32), is
+ * flipped in both; (3) per replica group, tempering exchanges of pairs
+ * (t, t+1), t even then t odd, accepted iff n >= E_{t+1} - E_t with n drawn
+ * at rate beta_t - beta_{t+1}, i.e. with probability
+ * min(1, exp((beta_t - beta_{t+1}) (E_t - E_{t+1}))).
+ *
+ * Random numbers: Philox4x32-10 keyed by the seed; per run u the counters
+ *   spins (i>>2, t, replica, 10<<24|u)   walkers (i, e, 2t+replica, 6<<24|u)
+ *   Metropolis (i, e*sweeps+s, 2t+replica, 7<<24|u)
+ *   Houdayer (t, e, 0, 8<<24|u)          swaps (t, e, replica, 9<<24|u)
+ * with e the EMCS index and s the sweep within it.
+ * Arrays "by temperature" are [runs][2][M][...] with index t the
+ * temperature; site i = x + Lx*(y + Ly*z).
+ * ------------------------------------------------------------------------ */
+typedef struct micsa_pt micsa_pt;
+
+enum micsa_pt_algo { MICSA_PT_WALKERS = 0, MICSA_PT_METROPOLIS = 1 };
+
+typedef struct {
+    int32_t Lx, Ly, Lz; /* even, >= 2; Lx <= 64; Lx*Ly*Lz <= MICSA_PT_MAX_SITES */
+    int32_t n_runs;     /* independent runs of the sample, 1 .. 2^24 - 1 */
+    int32_t n_temps;    /* temperatures M per replica group, 2 .. 64 */
+    int32_t sweeps;     /* sweeps per EMCS, 1 .. 64 */
+    int32_t algo;       /* enum micsa_pt_algo */
+    int32_t houdayer;   /* 1: a Houdayer move every EMCS; 0: none */
+    uint64_t seed;
+} micsa_pt_params;
+
+#define MICSA_PT_MAX_SITES 16384
+
+/* Create the runs of one sample.  J: host array [3][N], row mu the coupling
+   of bond (i, i + e_mu), finite with |J| <= 8.  T: host array [n_temps],
+   strictly increasing, positive; the walker tables need beta_t large
+   enough that a walker stays below 2^30 mesh units (T up to about 350) and
+   every table's top digit stays below 255.  Both arrays are copied.  The
+   start is random (infinite temperature), energies are computed.  Errors:
+   EINVAL (parameters, J or T), ENOMEM, EHIP; *out = NULL on error. */
+int micsa_pt_create(const micsa_pt_params* p, const double* J, const double* T, void* hip_stream,
+                    micsa_pt** out);
+int micsa_pt_destroy(micsa_pt* pt); /* syncs, then frees; NULL accepted */
+const char* micsa_pt_last_error(const micsa_pt* pt);
+
+/* Enqueue n_emcs EMCS (asynchronous).  ERANGE once the EMCS index or
+   e * sweeps would pass 2^32. */
+int micsa_pt_step(micsa_pt* pt, int64_t n_emcs);
+int micsa_pt_sync(micsa_pt* pt);
+int micsa_pt_get_emcs(const micsa_pt* pt, int64_t* e); /* EMCS done so far */
+
+/* Synchronous reads, by temperature.  E: [runs][2][M] energies (mesh
+   units); Q: [runs][M] overlap sum_x s^a_x s^b_x of the two replicas; either
+   may be NULL. */
+int micsa_pt_read(micsa_pt* pt, int64_t* E, int64_t* Q);
+int micsa_pt_read_spins(micsa_pt* pt, uint8_t* sigma);       /* [runs][2][M][N] spin bits */
+int micsa_pt_write_spins(micsa_pt* pt, const uint8_t* sigma); /* same layout, bits 0/1; energies recomputed */
+int micsa_pt_read_swaps(micsa_pt* pt, int64_t* swaps);        /* [runs][2][M-1] accepted exchanges per pair */
+
+/* The digit thresholds in use: kind 0 = walker table of temperature index,
+   kind 1 = exchange table of pair (index, index + 1); t receives [4][255]. */
+int micsa_pt_get_tables(micsa_pt* pt, int32_t kind, int32_t index, uint64_t* t);
+int micsa_pt_get_couplings(micsa_pt* pt, int32_t* Jq); /* [3][N] mesh units */
+
+/* Per-kernel timing with HIP events on the stream: kind 0 = EMCS kernel,
+   1 = exchange kernel. */
+int micsa_pt_set_timing(micsa_pt* pt, int32_t enable);
+int micsa_pt_get_timing(micsa_pt* pt, int32_t kind, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

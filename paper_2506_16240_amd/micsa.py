@@ -24,6 +24,9 @@ TIME_SWEEP, TIME_REFRESH, TIME_HEATBATH, TIME_REDUCE, TIME_METROPOLIS = 0, 1, 2,
 OPT_SWEEP_KERNEL, OPT_TILE_Y, OPT_TILE_Z, OPT_XCD_MAP, OPT_GRAPHS, OPT_PREFETCH, OPT_TEMPORAL = 1, 2, 3, 4, 5, 6, 7
 KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_FUSED, KERNEL_RESIDENT = 0, 1, 2, 3
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_RELEASED = 0, 1, 2, 3
+PT_WALKERS, PT_METROPOLIS = 0, 1
+PT_TIME_EMCS, PT_TIME_SWAP = 0, 1
+PT_MAX_SITES = 16384
 
 
 class MicsaError(RuntimeError):
@@ -50,6 +53,12 @@ class _Schedule(ctypes.Structure):
 
 
 _lib = None
+
+class _PtParams(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("Lz", ctypes.c_int32),
+                ("n_runs", ctypes.c_int32), ("n_temps", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("algo", ctypes.c_int32), ("houdayer", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
 
 # (name, restype, argtypes) of every exported entry point
 _SIGNATURES = [
@@ -95,6 +104,22 @@ _SIGNATURES = [
                                             ctypes.POINTER(ctypes.c_int64)]),
     ("micsa_pool_job_context", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p)]),
     ("micsa_pool_release", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    ("micsa_pt_create", ctypes.c_int, [ctypes.POINTER(_PtParams), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    ("micsa_pt_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("micsa_pt_last_error", ctypes.c_char_p, [ctypes.c_void_p]),
+    ("micsa_pt_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    ("micsa_pt_sync", ctypes.c_int, [ctypes.c_void_p]),
+    ("micsa_pt_get_emcs", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    ("micsa_pt_read", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_pt_read_spins", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_pt_write_spins", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_pt_read_swaps", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_pt_get_tables", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
+    ("micsa_pt_get_couplings", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_pt_set_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    ("micsa_pt_get_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int64)]),
 ]
 
 
@@ -380,3 +405,93 @@ class Pool:
 
     def release(self, job: int) -> None:
         self._check(lib().micsa_pool_release(self._pool, job), "pool_release")
+
+
+class PT:
+    """Parallel tempering of one Gaussian sample (micsa_pt_*, App. C): runs x 2
+    replicas x M temperatures; arrays are by temperature, energies in units
+    of the 2^-17 mesh."""
+
+    def __init__(self, Lx: int, Ly: int, Lz: int, runs: int, T, J, seed: int, sweeps: int = 10,
+                 algo: int = PT_WALKERS, houdayer: bool = True, stream=None):
+        self.Lx, self.Ly, self.Lz, self.runs = Lx, Ly, Lz, runs
+        self.N = Lx * Ly * Lz
+        self.T = np.ascontiguousarray(T, np.float64)
+        self.M = len(self.T)
+        J = np.ascontiguousarray(J, np.float64)
+        if J.size != 3 * self.N:
+            raise ValueError(f"J must hold 3 x {self.N} couplings")
+        self._ctx = ctypes.c_void_p()
+        p = _PtParams(Lx, Ly, Lz, runs, self.M, sweeps, algo, int(bool(houdayer)), seed)
+        st = lib().micsa_pt_create(ctypes.byref(p), _ptr(J), _ptr(self.T), _stream_handle(stream),
+                                   ctypes.byref(self._ctx))
+        if st != OK:
+            raise MicsaError(st, f"micsa_pt_create({Lx},{Ly},{Lz}, runs={runs}, M={self.M}): "
+                                 f"{lib().micsa_status_string(st).decode()}")
+
+    def close(self) -> None:
+        if self._ctx:
+            lib().micsa_pt_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, what: str) -> None:
+        if st != OK:
+            raise MicsaError(st, f"{what}: {lib().micsa_pt_last_error(self._ctx).decode()}")
+
+    def step(self, n_emcs: int) -> None:
+        self._check(lib().micsa_pt_step(self._ctx, int(n_emcs)), "pt_step")
+
+    def sync(self) -> None:
+        self._check(lib().micsa_pt_sync(self._ctx), "pt_sync")
+
+    @property
+    def emcs(self) -> int:
+        e = ctypes.c_int64()
+        self._check(lib().micsa_pt_get_emcs(self._ctx, ctypes.byref(e)), "pt_get_emcs")
+        return e.value
+
+    def read(self) -> tuple[np.ndarray, np.ndarray]:
+        """(E [runs, 2, M], Q [runs, M]) by temperature."""
+        E = np.zeros((self.runs, 2, self.M), np.int64)
+        Q = np.zeros((self.runs, self.M), np.int64)
+        self._check(lib().micsa_pt_read(self._ctx, _ptr(E), _ptr(Q)), "pt_read")
+        return E, Q
+
+    def spins(self) -> np.ndarray:
+        s = np.zeros((self.runs, 2, self.M, self.N), np.uint8)
+        self._check(lib().micsa_pt_read_spins(self._ctx, _ptr(s)), "pt_read_spins")
+        return s
+
+    def write_spins(self, sigma: np.ndarray) -> None:
+        s = np.ascontiguousarray(sigma, np.uint8).reshape(self.runs, 2, self.M, self.N)
+        self._check(lib().micsa_pt_write_spins(self._ctx, _ptr(s)), "pt_write_spins")
+
+    def swaps(self) -> np.ndarray:
+        w = np.zeros((self.runs, 2, self.M - 1), np.int64)
+        self._check(lib().micsa_pt_read_swaps(self._ctx, _ptr(w)), "pt_read_swaps")
+        return w
+
+    def tables(self, kind: int, index: int) -> np.ndarray:
+        t = np.zeros((4, 255), np.uint64)
+        self._check(lib().micsa_pt_get_tables(self._ctx, int(kind), int(index), _ptr(t)), "pt_get_tables")
+        return t
+
+    def couplings(self) -> np.ndarray:
+        Jq = np.zeros((3, self.N), np.int32)
+        self._check(lib().micsa_pt_get_couplings(self._ctx, _ptr(Jq)), "pt_get_couplings")
+        return Jq
+
+    def set_timing(self, on: bool) -> None:
+        self._check(lib().micsa_pt_set_timing(self._ctx, int(bool(on))), "pt_set_timing")
+
+    def timing(self, kind: int) -> tuple[float, int]:
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(lib().micsa_pt_get_timing(self._ctx, int(kind), ctypes.byref(ms), ctypes.byref(n)),
+                    "pt_get_timing")
+        return ms.value, n.value

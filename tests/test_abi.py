@@ -5,6 +5,8 @@ import ctypes
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from paper_2506_16240_amd import micsa as M
@@ -78,3 +80,34 @@ def test_null_arguments():
     assert lib.micsa_read_energy(None, None) == M.EINVAL
     assert lib.micsa_set_schedule(None, None) == M.EINVAL
     assert lib.micsa_last_error(None) == b"null context"
+
+
+def _pt_create(Lx=4, Ly=4, Lz=4, runs=1, T=(0.5, 1.0), J=None, sweeps=10, algo=0, houdayer=1):
+    N = Lx * Ly * Lz
+    J = np.zeros(3 * N) if J is None else np.asarray(J, np.float64)
+    T = np.asarray(T, np.float64)
+    p = M._PtParams(Lx, Ly, Lz, runs, len(T), sweeps, algo, houdayer, 1)
+    ctx = ctypes.c_void_p()
+    st = M.lib().micsa_pt_create(ctypes.byref(p), J.ctypes.data, T.ctypes.data, None, ctypes.byref(ctx))
+    return st, ctx
+
+
+@pytest.mark.parametrize("kw", [dict(Lx=5), dict(Ly=3), dict(Lz=0), dict(Lx=66, Ly=2, Lz=2), dict(Lx=32, Ly=32, Lz=32),
+                                dict(runs=0), dict(runs=1 << 24), dict(T=(1.0,)), dict(T=tuple(np.linspace(1, 2, 65))),
+                                dict(sweeps=0), dict(sweeps=65), dict(algo=2), dict(houdayer=2),
+                                dict(T=(1.0, 1.0)), dict(T=(1.0, 0.5)), dict(T=(-1.0, 1.0)), dict(T=(0.5, np.inf)),
+                                dict(T=(0.5, 1000.0)), dict(T=(1.0, 1.00001))])
+def test_pt_create_rejects_bad_arguments(kw):
+    """Invalid shapes, counts, ladders (not increasing, walkers too hot for
+    32 bits, exchange rates too small for four digits) are refused before
+    any device work."""
+    st, ctx = _pt_create(**kw)
+    assert st == M.EINVAL and not ctx
+
+
+@pytest.mark.parametrize("bad", [8.5, float("nan"), float("inf")])
+def test_pt_create_rejects_bad_couplings(bad):
+    J = np.zeros(3 * 64)
+    J[17] = bad
+    st, ctx = _pt_create(J=J)
+    assert st == M.EINVAL and not ctx
