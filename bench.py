@@ -7,6 +7,11 @@ daemon refresh every 20 sweeps.  A step is one refresh period: the refresh
 and 20 sweeps (even half + odd half each, with the incremental energy
 tally).  --steps 500 is the whole anneal.  The heat bath and Metropolis run
 the same steps on lattices from the same seed.  Prints one JSON line.
+
+--workload pt_gauss_L10_200x2x40: the equilibrium workload of App. C
+(parallel tempering of a Gaussian sample, L = 10, 200 runs x 2 replicas x
+40 temperatures, 10 sweeps per EMCS, Houdayer moves); a step is one EMCS;
+walkers against the Metropolis update.
 """
 from __future__ import annotations
 
@@ -133,6 +138,122 @@ def cpu_baseline(w, seconds: float):
                       f"{el:.1f} s, init excluded)"}
 
 
+# Parallel tempering (App. C): the EMCS kernel is bound by integer VALU work
+# in LDS, not by HBM (the spin rows of a clone are 800 B).  Algorithmic
+# operations per spin update of the uncapped Creutz move: six sign
+# applications and five additions for the local field, dH = 2 s h, n - dH,
+# the acceptance compare and the two selects (walker, spin): 16 int32 ops.
+# Peak: 256 CUs x 64 int32 lanes per clock x 2.4 GHz = 39.3 Tops/s.
+PT_OPS_PER_UPDATE = 16
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def run_pt(w, algo: int, steps: int, warmup: int, stream, events: bool = False):
+    from paper_2506_16240_amd import micsa as M
+    import torch
+
+    T, J = w.temperatures(), w.couplings()
+    if warmup > 0:
+        g = M.PT(w.L, w.L, w.L, w.runs, T, J, w.seed, w.sweeps, algo, True, stream=stream.cuda_stream)
+        g.step(warmup)
+        g.sync()
+        g.close()
+    g = M.PT(w.L, w.L, w.L, w.runs, T, J, w.seed, w.sweeps, algo, True, stream=stream.cuda_stream)
+    g.set_timing(events)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    g.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    k_ms, k_n = g.timing(M.PT_TIME_EMCS)
+    s_ms, s_n = g.timing(M.PT_TIME_SWAP)
+    E, Q = g.read()
+    sw = g.swaps()
+    name = g.kernel_name
+    g.close()
+    N = w.N
+    return {"ms": ms, "kernel_ms": k_ms, "kernel_launches": k_n, "swap_ms": s_ms, "swap_launches": s_n,
+            "e_lowT": float(E[:, :, 0].mean()) * 2.0 ** -17 / N, "absq_lowT": float(abs(Q[:, 0]).mean()) / N,
+            "swap_rate": float(sw.sum()) / (sw.size * steps), "kernel": name}
+
+
+def pt_cpu_baseline(w, seconds: float):
+    """The oracle on a bounded sample of the tempering workload: EMCS of the
+    first few runs (the runs are independent)."""
+    from oracle import oracle as O
+
+    runs = 8
+    lat = O.PTLattice(w.L, w.L, w.L, runs=runs, T=w.temperatures(), J=w.couplings(), seed=w.seed, sweeps=w.sweeps)
+    n = 0
+    t = time.perf_counter()
+    while True:
+        lat.run(1)
+        n += 1
+        el = time.perf_counter() - t
+        if el >= seconds:
+            break
+    upd = w.N * 2 * w.M * runs * w.sweeps * n
+    return {"value": round(upd / (el * 1e9), 4), "unit": "spin updates/ns", "cores": O.threads(), "kind": "oracle",
+            "sample": f"{n} EMCS of runs 0..{runs - 1} of {w.name} ({upd} updates, {el:.1f} s, walkers)"}
+
+
+def bench_pt(w, args) -> int:
+    from paper_2506_16240_amd import micsa as M
+    import torch
+
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    steps = args.steps
+    updates = w.updates(steps)
+    log(f"walkers: {w.name}, {steps} EMCS")
+    wk = run_pt(w, M.PT_WALKERS, steps, args.warmup, stream)
+    log(f"walkers: {wk['ms']:.1f} ms")
+    wke = run_pt(w, M.PT_WALKERS, steps, 0, stream, events=True)
+    mp = None
+    if not args.no_metropolis:
+        log(f"metropolis: {w.name}, {steps} EMCS")
+        mp = run_pt(w, M.PT_METROPOLIS, steps, args.warmup, stream)
+        log(f"metropolis: {mp['ms']:.1f} ms")
+    avg_ms = wke["kernel_ms"] / wke["kernel_launches"]
+    ops_launch = PT_OPS_PER_UPDATE * w.updates(1)
+    achieved = ops_launch / (avg_ms * 1e9)  # Tops/s
+    out = {
+        "metric": "spin updates/ns (walkers vs Metropolis, parallel tempering, 1 GPU) + % of int32 VALU peak",
+        "value": round(updates / (wk["ms"] * 1e6), 2),
+        "unit": "spin updates/ns",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wk["ms"] / steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "L": [w.L] * 3, "runs": w.runs, "replicas": 2, "temperatures": w.M,
+                   "T": [w.Tmin, w.Tmax], "sweeps_per_emcs": w.sweeps, "houdayer": True, "step": "one EMCS"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 1),
+                     "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                     "kernel": wke["kernel"], "avg_launch_ms": round(avg_ms, 5), "ops_per_launch": ops_launch,
+                     "ops_per_update": PT_OPS_PER_UPDATE, "launches": wke["kernel_launches"],
+                     "swap_kernel_avg_ms": round(wke["swap_ms"] / max(wke["swap_launches"], 1), 5)},
+        "observables": {"e_at_Tmin": round(wk["e_lowT"], 5), "absq_at_Tmin": round(wk["absq_lowT"], 4),
+                        "exchange_rate": round(wk["swap_rate"], 4)},
+    }
+    if mp is not None:
+        out["metropolis"] = {"value": round(updates / (mp["ms"] * 1e6), 2), "unit": "spin updates/ns",
+                             "ms_per_step": round(mp["ms"] / steps, 4)}
+        out["walkers_over_metropolis"] = round(mp["ms"] / wk["ms"], 3)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = pt_cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +282,11 @@ def main() -> int:
     from paper_2506_16240_amd import workloads as W
     import torch
 
+    if args.workload == W.PT_L10.name:
+        return bench_pt(W.PT_L10, args)
+    if args.workload not in W.ALL:
+        print(f"unknown workload {args.workload}; one of {sorted(W.ALL) + [W.PT_L10.name]}", file=sys.stderr)
+        return 2
     w = W.ALL[args.workload]
     steps = args.steps
     if steps * w.period > w.n_sweeps:

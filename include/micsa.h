@@ -369,6 +369,16 @@ int micsa_pt_read_swaps(micsa_pt* pt, int64_t* swaps);        /* [runs][2][M-1] 
 int micsa_pt_get_tables(micsa_pt* pt, int32_t kind, int32_t index, uint64_t* t);
 int micsa_pt_get_couplings(micsa_pt* pt, int32_t* Jq); /* [3][N] mesh units */
 
+/* Kernel of the fixed-temperature moves.  ROWS: a work-group per (run,
+   temperature), threads looping over rows, any shape.  REGISTER: several
+   temperatures per work-group, one row per thread with its walkers in
+   registers; needs Lx in {4, 6, 8, 10, 12, 16} and 2*Ly*Lz <= 1024 (EINVAL
+   otherwise).  AUTO (default) takes REGISTER where it applies.  Results are
+   identical. */
+enum micsa_pt_kernel { MICSA_PT_KERNEL_AUTO = 0, MICSA_PT_KERNEL_ROWS = 1, MICSA_PT_KERNEL_REGISTER = 2 };
+int micsa_pt_set_kernel(micsa_pt* pt, int32_t kernel);
+const char* micsa_pt_kernel_name(const micsa_pt* pt); /* kernel the next step launches */
+
 /* Per-kernel timing with HIP events on the stream: kind 0 = EMCS kernel,
    1 = exchange kernel. */
 int micsa_pt_set_timing(micsa_pt* pt, int32_t enable);

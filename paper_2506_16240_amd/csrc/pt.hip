@@ -5,6 +5,7 @@
 // records and the exponential tables of the temperature ladder.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstring>
@@ -24,15 +25,18 @@ struct micsa_pt {
     int64_t e = 0;  // EMCS done
     bool jl = false;  // coupling records staged in LDS
     uint32_t lds = 0;
+    int32_t kernel = MICSA_PT_KERNEL_AUTO;
+    int32_t G = 0;        // temperatures per work-group of the register kernel (0: not eligible)
+    uint32_t reg_lds = 0;
     int4* rec = nullptr;         // [N][2] records, x-major
     uint64_t* spins = nullptr;   // [runs][2][M][R0]
     int32_t* perm = nullptr;     // [runs][2][M]
     int64_t* E = nullptr;        // [runs][2][M] by slot
     int64_t* swaps = nullptr;    // [runs][2][M-1]
-    uint64_t* wtab = nullptr;    // [M][1024]
-    uint64_t* ptab = nullptr;    // [M-1][1024]
+    uint32_t* wtab = nullptr;    // [M][kPtTable] device form (thresholds - 1, guides)
+    uint32_t* ptab = nullptr;    // [M-1][kPtTable]
     std::vector<int32_t> Jq;     // [3][N]
-    std::vector<uint64_t> hw, hp;  // host copies of the tables
+    std::vector<uint64_t> hw, hp;  // thresholds [M][4][256], [M-1][4][256] (entry 255 unused)
     std::string err;
     bool timing = false;
     // per timed EMCS: events before the EMCS kernel, between the two kernels, after the exchange kernel
@@ -61,7 +65,7 @@ int pt_fail(micsa_pt* c, int st, const std::string& m)
 // Digit thresholds of the mesh exponential of rate lam (per unit energy):
 // digit d has ratio r_d = exp(-lam 2^(8d-17)); t_d[v] = floor(2^32 F_d(v)),
 // F_d(v) = (1 - r_d^(v+1)) / (1 - r_d^256) for d < 3 and 1 - r_3^(v+1) for
-// the untruncated top digit.  Entry 255 of each digit is a sentinel.
+// the untruncated top digit.  t has [4][256] entries, entry 255 unused.
 void exp_table(double lam, uint64_t* t)
 {
     for (int d = 0; d < 4; ++d) {
@@ -77,6 +81,35 @@ void exp_table(double lam, uint64_t* t)
 
 constexpr uint64_t kTwo32 = 4294967296ull;
 
+// Device form of a table: t_d[v] - 1 as u32 (every t_d[v] >= 2^24 since the
+// most likely digit value has probability >= 1/256) and, per top byte b of
+// the word, the counts at the two ends of its bucket [b 2^24, (b+1) 2^24).
+void device_table(const uint64_t* t, uint32_t* out)
+{
+    uint16_t* guide = (uint16_t*)(out + 1024);
+    for (int d = 0; d < 4; ++d) {
+        const uint64_t* td = t + d * 256;
+        for (int v = 0; v < 255; ++v) out[d * 256 + v] = (uint32_t)(td[v] - 1u);
+        out[d * 256 + 255] = 0xFFFFFFFFu;
+        auto count = [&](uint64_t w) {
+            int c = 0;
+            while (c < 255 && td[c] <= w) ++c;
+            return c;
+        };
+        for (int b = 0; b < 256; ++b) {
+            const int lo = count((uint64_t)b << 24), hi = count(((uint64_t)(b + 1) << 24) - 1u);
+            guide[d * 256 + b] = (uint16_t)(lo | (hi << 8));
+        }
+    }
+}
+
+bool table_in_range(const uint64_t* t)
+{
+    for (int d = 0; d < 4; ++d)
+        if (t[d * 256] < ((uint64_t)1 << 24)) return false;
+    return true;
+}
+
 void free_pt(micsa_pt* c)
 {
     if (!c) return;
@@ -87,7 +120,7 @@ void free_pt(micsa_pt* c)
         for (hipEvent_t x : ev) (void)hipEventDestroy(x);
 }
 
-using EmcsKernel = void (*)(PtGeom, const int4*, uint64_t*, const int32_t*, int64_t*, const uint64_t*, uint32_t);
+using EmcsKernel = void (*)(PtGeom, const int4*, uint64_t*, const int32_t*, int64_t*, const uint32_t*, uint32_t);
 
 EmcsKernel emcs_kernel(int algo, bool houd, bool jl)
 {
@@ -96,6 +129,35 @@ EmcsKernel emcs_kernel(int algo, bool houd, bool jl)
                     : (jl ? k_pt_emcs<0, false, true> : k_pt_emcs<0, false, false>);
     return houd ? (jl ? k_pt_emcs<1, true, true> : k_pt_emcs<1, true, false>)
                 : (jl ? k_pt_emcs<1, false, true> : k_pt_emcs<1, false, false>);
+}
+
+using RegKernel = void (*)(PtGeom, int, const int4*, uint64_t*, const int32_t*, int64_t*, const uint32_t*,
+                          uint32_t);
+
+template <int LX>
+RegKernel reg_kernel_lx(int algo, bool houd)
+{
+    if (algo == MICSA_PT_WALKERS) return houd ? k_pt_emcs_reg<LX, 0, true> : k_pt_emcs_reg<LX, 0, false>;
+    return houd ? k_pt_emcs_reg<LX, 1, true> : k_pt_emcs_reg<LX, 1, false>;
+}
+
+// Row lengths with a register-resident instance.
+RegKernel reg_kernel(int Lx, int algo, bool houd)
+{
+    switch (Lx) {
+    case 4: return reg_kernel_lx<4>(algo, houd);
+    case 6: return reg_kernel_lx<6>(algo, houd);
+    case 8: return reg_kernel_lx<8>(algo, houd);
+    case 10: return reg_kernel_lx<10>(algo, houd);
+    case 12: return reg_kernel_lx<12>(algo, houd);
+    case 16: return reg_kernel_lx<16>(algo, houd);
+    default: return nullptr;
+    }
+}
+
+bool use_reg(const micsa_pt* c)
+{
+    return c->G > 0 && c->kernel != MICSA_PT_KERNEL_ROWS;
 }
 
 int launch_energy(micsa_pt* c)
@@ -147,18 +209,21 @@ int micsa_pt_create(const micsa_pt_params* p, const double* J, const double* T, 
     // temperature ladder and its tables
     for (int t = 0; t < M; ++t)
         if (!(T[t] > 0.0) || !std::isfinite(T[t]) || (t > 0 && !(T[t] > T[t - 1]))) return MICSA_EINVAL;
-    std::vector<uint64_t> hw((size_t)M * kPtTable), hp((size_t)(M - 1) * kPtTable);
+    std::vector<uint64_t> hw((size_t)M * 1024), hp((size_t)(M - 1) * 1024);
+    std::vector<uint32_t> dw((size_t)M * kPtTable), dp((size_t)(M - 1) * kPtTable);
     for (int t = 0; t < M; ++t) {
-        uint64_t* tw = hw.data() + (size_t)t * kPtTable;
+        uint64_t* tw = hw.data() + (size_t)t * 1024;
         exp_table(1.0 / T[t], tw);
         // top digit below 255 always; walkers also below 64 (n < 2^30 in 32 bits)
-        if (tw[3 * 256 + 254] != kTwo32) return MICSA_EINVAL;
+        if (tw[3 * 256 + 254] != kTwo32 || !table_in_range(tw)) return MICSA_EINVAL;
         if (p->algo == MICSA_PT_WALKERS && tw[3 * 256 + 63] != kTwo32) return MICSA_EINVAL;
+        device_table(tw, dw.data() + (size_t)t * kPtTable);
     }
     for (int t = 0; t + 1 < M; ++t) {
-        uint64_t* tp = hp.data() + (size_t)t * kPtTable;
+        uint64_t* tp = hp.data() + (size_t)t * 1024;
         exp_table(1.0 / T[t] - 1.0 / T[t + 1], tp);
-        if (tp[3 * 256 + 254] != kTwo32) return MICSA_EINVAL;
+        if (tp[3 * 256 + 254] != kTwo32 || !table_in_range(tp)) return MICSA_EINVAL;
+        device_table(tp, dp.data() + (size_t)t * kPtTable);
     }
 
     micsa_pt* c = new (std::nothrow) micsa_pt();
@@ -213,7 +278,7 @@ int micsa_pt_create(const micsa_pt_params* p, const double* J, const double* T, 
               hipMalloc(&c->spins, nslot * g.R0 * 8) == hipSuccess && hipMalloc(&c->perm, nslot * 4) == hipSuccess &&
               hipMalloc(&c->E, nslot * 8) == hipSuccess &&
               hipMalloc(&c->swaps, (size_t)g.runs * 2 * (M - 1) * 8) == hipSuccess &&
-              hipMalloc(&c->wtab, c->hw.size() * 8) == hipSuccess && hipMalloc(&c->ptab, c->hp.size() * 8) == hipSuccess;
+              hipMalloc(&c->wtab, dw.size() * 4) == hipSuccess && hipMalloc(&c->ptab, std::max<size_t>(dp.size(), 1) * 4) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         free_pt(c);
@@ -230,8 +295,9 @@ int micsa_pt_create(const micsa_pt_params* p, const double* J, const double* T, 
         return s;
     };
     if (hipMemcpyAsync(c->rec, rec.data(), rec.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-        hipMemcpyAsync(c->wtab, c->hw.data(), c->hw.size() * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-        hipMemcpyAsync(c->ptab, c->hp.data(), c->hp.size() * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->wtab, dw.data(), dw.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->ptab, dp.data(), dp.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess ||
         hipMemsetAsync(c->swaps, 0, (size_t)g.runs * 2 * (M - 1) * 8, c->stream) != hipSuccess)
         return fin(MICSA_EHIP);
     const int64_t rows_total = (int64_t)nslot * g.R0;
@@ -244,6 +310,19 @@ int micsa_pt_create(const micsa_pt_params* p, const double* J, const double* T, 
         if (hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds) !=
             hipSuccess)
             return fin(MICSA_EHIP);
+    }
+    // register kernel: G temperatures per work-group, one row per thread
+    if (reg_kernel(g.Lx, p->algo, p->houdayer != 0) && 2 * g.R0 <= 1024) {
+        int G = std::min(M, 1024 / (2 * g.R0));
+        while (G > 0 && pt_reg_layout(g, G).total > kPtLdsMax) --G;
+        c->G = G;
+        if (G > 0) {
+            c->reg_lds = pt_reg_layout(g, G).total;
+            if (c->reg_lds > 65536u &&
+                hipFuncSetAttribute((const void*)reg_kernel(g.Lx, p->algo, p->houdayer != 0),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->reg_lds) != hipSuccess)
+                return fin(MICSA_EHIP);
+        }
     }
     *out = c;
     return MICSA_OK;
@@ -264,6 +343,10 @@ int micsa_pt_step(micsa_pt* pt, int64_t n)
     if ((pt->e + n) * (int64_t)pt->g.S > (int64_t)UINT32_MAX) return pt_fail(pt, MICSA_ERANGE, "EMCS index range");
     const EmcsKernel k = emcs_kernel(pt->p.algo, pt->p.houdayer != 0, pt->jl);
     const dim3 grid((unsigned)pt->g.M, (unsigned)pt->g.runs);
+    const bool reg = use_reg(pt);
+    const RegKernel kr = reg ? reg_kernel(pt->g.Lx, pt->p.algo, pt->p.houdayer != 0) : nullptr;
+    const dim3 rgrid((unsigned)((pt->g.M + pt->G - 1) / std::max(pt->G, 1)), (unsigned)pt->g.runs);
+    const unsigned rblock = reg ? (unsigned)(64 * ((2 * pt->G * pt->g.R0 + 63) / 64)) : 0u;
     const unsigned sgrid = (unsigned)((2 * pt->g.runs + 3) / 4);
     for (int64_t i = 0; i < n; ++i) {
         const uint32_t e = (uint32_t)pt->e;
@@ -273,7 +356,11 @@ int micsa_pt_step(micsa_pt* pt, int64_t n)
             pt->events.push_back(ev);  // owned by the context from here on
             PT_TRY(pt, hipEventRecord(ev[0], pt->stream));
         }
-        k<<<grid, kPtBlock, pt->lds, pt->stream>>>(pt->g, pt->rec, pt->spins, pt->perm, pt->E, pt->wtab, e);
+        if (reg)
+            kr<<<rgrid, rblock, pt->reg_lds, pt->stream>>>(pt->g, pt->G, pt->rec, pt->spins, pt->perm, pt->E,
+                                                           pt->wtab, e);
+        else
+            k<<<grid, kPtBlock, pt->lds, pt->stream>>>(pt->g, pt->rec, pt->spins, pt->perm, pt->E, pt->wtab, e);
         PT_TRY(pt, hipGetLastError());
         if (pt->timing) PT_TRY(pt, hipEventRecord(ev[1], pt->stream));
         k_pt_swap<<<sgrid, 256, 0, pt->stream>>>(pt->g, pt->perm, pt->E, pt->swaps, pt->ptab, e);
@@ -391,7 +478,7 @@ int micsa_pt_get_tables(micsa_pt* pt, int32_t kind, int32_t index, uint64_t* t)
     if (kind == 1 && index >= 0 && index + 1 < pt->g.M) src = &pt->hp;
     if (!src) return pt_fail(pt, MICSA_EINVAL, "table kind or index out of range");
     for (int d = 0; d < 4; ++d)
-        std::memcpy(t + d * 255, src->data() + (size_t)index * kPtTable + d * 256, 255 * 8);
+        std::memcpy(t + d * 255, src->data() + (size_t)index * 1024 + d * 256, 255 * 8);
     return MICSA_OK;
 }
 
@@ -400,6 +487,23 @@ int micsa_pt_get_couplings(micsa_pt* pt, int32_t* Jq)
     if (!pt || !Jq) return MICSA_EINVAL;
     std::memcpy(Jq, pt->Jq.data(), pt->Jq.size() * 4);
     return MICSA_OK;
+}
+
+int micsa_pt_set_kernel(micsa_pt* pt, int32_t kernel)
+{
+    if (!pt) return MICSA_EINVAL;
+    if (kernel != MICSA_PT_KERNEL_AUTO && kernel != MICSA_PT_KERNEL_ROWS && kernel != MICSA_PT_KERNEL_REGISTER)
+        return pt_fail(pt, MICSA_EINVAL, "unknown tempering kernel");
+    if (kernel == MICSA_PT_KERNEL_REGISTER && pt->G == 0)
+        return pt_fail(pt, MICSA_EINVAL, "the register kernel needs Lx in {4, 6, 8, 10, 12, 16} and 2*Ly*Lz <= 1024");
+    pt->kernel = kernel;
+    return MICSA_OK;
+}
+
+const char* micsa_pt_kernel_name(const micsa_pt* pt)
+{
+    if (!pt) return "";
+    return use_reg(pt) ? "k_pt_emcs_reg" : "k_pt_emcs";
 }
 
 int micsa_pt_set_timing(micsa_pt* pt, int32_t enable)

@@ -9,7 +9,12 @@
 // Exponential on the mesh: P(n) = (1 - q) q^n, q = exp(-lambda 2^-17), drawn
 // as four independent base-256 digits, digit d by inverse CDF on word d of
 // one Philox output: c_d = #{v : w_d >= t_d[v]} with the table t_d[0..254]
-// computed on the host (sentinel t_d[255] = 2^64 - 1).  The walkers use
+// computed on the host.  Every t_d[v] lies in [2^24, 2^32] (the most likely
+// value of a digit has probability >= 1/256), so the device holds
+// t_d[v] - 1 in 32 bits (w >= t <=> w > t - 1), plus an indexed-search guide
+// (Chen and Asau, 1974): for each top byte b of w the range [lo, hi] of
+// counts the words of that bucket can have, so a draw costs one guide read
+// and, in most buckets, no or one threshold compare.  The walkers use
 // lambda = beta_t; the Metropolis update (a fresh walker per attempt,
 // Sec. 2.3) and the tempering swaps (lambda = beta_t - beta_{t+1}) only
 // need "n >= k", which is decided digit by digit from the top with at most
@@ -40,7 +45,9 @@
 namespace micsa {
 
 constexpr int kPtBlock = 256;
-constexpr int kPtTable = 1024;  // 4 digits x 256 thresholds (last one a sentinel)
+// u32 words per exponential table: [d * 256 + v] = t_d[v] - 1 (v < 255),
+// then 4 x 256 guides as u16 lo | hi << 8 at byte offset 4096 + 2 (d * 256 + b)
+constexpr int kPtTable = 1536;
 enum : uint32_t { kStreamPtWalker = 6u, kStreamPtMetropolis = 7u, kStreamPtHoudayer = 8u, kStreamPtSwap = 9u,
                   kStreamPtSpin = 10u };
 
@@ -66,21 +73,33 @@ __device__ __forceinline__ uint64_t rot_down(uint64_t m, const PtGeom& g)  // bi
     return ((m >> 1) | (m << (g.Lx - 1))) & g.xmask;
 }
 
-// Full draw of digit d: the number of thresholds <= w (branch-free search
-// over 256 sorted entries, the last a sentinel no word reaches).
-__device__ __forceinline__ int32_t digit_draw(const uint64_t* t, uint32_t w)
+// Digit d of a draw: the number of thresholds <= w, found between the
+// guide's bounds for the bucket of w by bisection.
+__device__ __forceinline__ int32_t digit_draw(const uint32_t* tab, int d, uint32_t w)
 {
-    int32_t pos = 0;
-#pragma unroll
-    for (int step = 128; step >= 1; step >>= 1)
-        if (t[pos + step - 1] <= (uint64_t)w) pos += step;
-    return pos;
+    const uint32_t gb = ((const uint16_t*)(tab + 1024))[d * 256 + (w >> 24)];
+    int32_t lo = (int32_t)(gb & 255u), hi = (int32_t)(gb >> 8);
+    const uint32_t* t = tab + d * 256;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (w > t[mid])
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
 }
 
-// n >= k for the mesh exponential n drawn from words w (tables t[4][256]).
-// Digit d of n exceeds k_d iff w_d >= t_d[k_d] (k_d <= 254) and falls below
-// k_d iff w_d < t_d[k_d - 1] (k_d >= 1); equal digits pass to the next one.
-__device__ __forceinline__ bool exp_at_least(const uint64_t* t, const u32x4& w, int64_t k)
+__device__ __forceinline__ int32_t exp_draw4(const uint32_t* tab, const u32x4& w)
+{
+    return digit_draw(tab, 0, w.v0) + (digit_draw(tab, 1, w.v1) << 8) + (digit_draw(tab, 2, w.v2) << 16) +
+           (digit_draw(tab, 3, w.v3) << 24);
+}
+
+// n >= k for the mesh exponential n drawn from words w.  Digit d of n
+// exceeds k_d iff w_d >= t_d[k_d] (k_d <= 254) and falls below k_d iff
+// w_d < t_d[k_d - 1] (k_d >= 1); equal digits pass to the next one.
+__device__ __forceinline__ bool exp_at_least(const uint32_t* tab, const u32x4& w, int64_t k)
 {
     if (k <= 0) return true;
     if (k >= (int64_t)1 << 32) return false;
@@ -88,9 +107,9 @@ __device__ __forceinline__ bool exp_at_least(const uint64_t* t, const u32x4& w, 
 #pragma unroll
     for (int d = 3; d >= 0; --d) {
         const int32_t kd = (int32_t)((k >> (8 * d)) & 255);
-        const uint64_t* td = t + d * 256;
-        if (kd <= 254 && (uint64_t)ws[d] >= td[kd]) return true;
-        if (kd >= 1 && (uint64_t)ws[d] < td[kd - 1]) return false;
+        const uint32_t* td = tab + d * 256;
+        if (kd <= 254 && ws[d] > td[kd]) return true;
+        if (kd >= 1 && ws[d] <= td[kd - 1]) return false;
     }
     return true;
 }
@@ -142,7 +161,7 @@ __host__ __device__ inline PtLds pt_lds_layout(const PtGeom& g, bool jl, bool wa
     PtLds l;
     uint32_t o = 0;
     l.tab = o;
-    o += kPtTable * 8;
+    o += kPtTable * 4;
     l.rec = o;
     o += jl ? (uint32_t)g.N * 32u : 0u;
     l.rows = o;
@@ -168,11 +187,11 @@ template <int ALGO, bool HOUD, bool JL>
 __global__ __launch_bounds__(kPtBlock) void k_pt_emcs(PtGeom g, const int4* __restrict__ grec,
                                                         uint64_t* __restrict__ spins,
                                                         const int32_t* __restrict__ perm, int64_t* __restrict__ E,
-                                                        const uint64_t* __restrict__ wtab, uint32_t e)
+                                                        const uint32_t* __restrict__ wtab, uint32_t e)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     const PtLds L = pt_lds_layout(g, JL, ALGO == 0);
-    uint64_t* tab = (uint64_t*)(lds + L.tab);
+    uint32_t* tab = (uint32_t*)(lds + L.tab);
     const int4* rec = JL ? (const int4*)(lds + L.rec) : grec;
     uint64_t* rows = (uint64_t*)(lds + L.rows);  // [2][R0]
     int32_t* walk = (int32_t*)(lds + L.walk);    // [2][Lx][R0]
@@ -207,9 +226,7 @@ __global__ __launch_bounds__(kPtBlock) void k_pt_emcs(PtGeom g, const int4* __re
                 const uint32_t i = (uint32_t)(x + g.Lx * r);
                 const u32x4 w = philox10(i, e, (uint32_t)(2 * t + rep), stream_word(kStreamPtWalker, sw), g.key0,
                                          g.key1);
-                const int32_t n = digit_draw(tab, w.v0) + (digit_draw(tab + 256, w.v1) << 8) +
-                                  (digit_draw(tab + 512, w.v2) << 16) + (digit_draw(tab + 768, w.v3) << 24);
-                walk[(rep * g.Lx + x) * R0 + r] = n;
+                walk[(rep * g.Lx + x) * R0 + r] = exp_draw4(tab, w);
             }
         }
     }
@@ -347,11 +364,289 @@ __global__ __launch_bounds__(kPtBlock) void k_pt_emcs(PtGeom g, const int4* __re
     }
 }
 
+// ---------------------------------------------------------------------------
+// Register-resident variant for rows of LX <= 32 sites (LX a compile-time
+// constant) and 2 * Ly * Lz <= 1024: a work-group holds G temperatures (both
+// replicas each) and every thread owns exactly one row of one replica, so
+// the walkers of a row live in VGPRs, split by parity class (wk0: the
+// row's even sites x = 2j + ((y+z) & 1), wk1: its odd sites), and every bit
+// test uses a constant offset.  Forward-X wandering pairs site j of the
+// moving class with site j (or j + 1 when the class starts at x = 1) of the
+// other class, all within the row.
+// LDS: tables [G][1024] u64 | records [N][2] int4 | rows [G][2][R0] u32 |
+//      mark, diff [G][R0] u32 | energies [G][2] u64 | flag.
+struct PtRegLds {
+    uint32_t tab, rec, rows, mark, diff, esum, flag, total;
+};
+
+__host__ __device__ inline PtRegLds pt_reg_layout(const PtGeom& g, int G)
+{
+    PtRegLds l;
+    uint32_t o = 0;
+    l.tab = o;
+    o += (uint32_t)G * kPtTable * 4u;
+    l.rec = o;
+    o += (uint32_t)g.N * 32u;
+    l.rows = o;
+    o += (uint32_t)G * 2u * g.R0 * 4u;
+    l.mark = o;
+    o += (uint32_t)G * g.R0 * 4u;
+    l.diff = o;
+    o += (uint32_t)G * g.R0 * 4u;
+    o = (o + 7u) & ~7u;
+    l.esum = o;
+    o += (uint32_t)G * 16u;
+    l.flag = o;
+    o += 16u;
+    l.total = o;
+    return l;
+}
+
+template <int LX>
+__device__ __forceinline__ uint32_t rot_down32(uint32_t m)  // bit x <- bit x + 1
+{
+    constexpr uint32_t MASK = LX == 32 ? 0xFFFFFFFFu : ((1u << LX) - 1u);
+    return ((m >> 1) | (m << (LX - 1))) & MASK;
+}
+template <int LX>
+__device__ __forceinline__ uint32_t rot_up32(uint32_t m)  // bit x <- bit x - 1
+{
+    constexpr uint32_t MASK = LX == 32 ? 0xFFFFFFFFu : ((1u << LX) - 1u);
+    return ((m << 1) | (m >> (LX - 1))) & MASK;
+}
+
+__device__ __forceinline__ int32_t sbit(uint32_t w, int pos)  // 0 or -1
+{
+    return __builtin_amdgcn_sbfe((int32_t)w, pos, 1);
+}
+
+template <int LX, int ALGO, int P>
+__device__ __forceinline__ void reg_half(const PtGeom& g, const int4* rec, uint32_t* rows, int base, int r,
+                                         const PtRowNb& nb, int32_t (&wk)[LX / 2], const uint32_t* tab, uint32_t e,
+                                         int s, int t, int rep, uint32_t run)
+{
+    constexpr int K = LX / 2;
+    const int R0 = g.R0;
+    const int xs = (P + nb.y + nb.z) & 1;  // first x of this class in the row
+    const uint32_t own = rows[base + r];
+    const uint32_t wo = own >> xs, wxp = rot_down32<LX>(own) >> xs, wxm = rot_up32<LX>(own) >> xs;
+    const uint32_t wyp = rows[base + nb.yp] >> xs, wym = rows[base + nb.ym] >> xs;
+    const uint32_t wzp = rows[base + nb.zp] >> xs, wzm = rows[base + nb.zm] >> xs;
+    const int4* rc = rec + 2 * (xs * R0 + r);
+    uint32_t flips = 0;
+    // the walker path unrolls (walkers in registers); the Metropolis path
+    // keeps one generator output live at a time
+    constexpr int kUnroll = ALGO == 0 ? K : 1;
+#pragma unroll kUnroll
+    for (int j = 0; j < K; ++j) {
+        const int4 a = rc[4 * R0 * j], b = rc[4 * R0 * j + 1];
+        const int32_t up = (a.x & sbit(wxp, 2 * j)) + (a.y & sbit(wyp, 2 * j)) + (a.z & sbit(wzp, 2 * j)) +
+                           (a.w & sbit(wxm, 2 * j)) + (b.x & sbit(wym, 2 * j)) + (b.y & sbit(wzm, 2 * j));
+        const int32_t h2 = 2 * (b.z - 2 * up);
+        const int32_t m = sbit(wo, 2 * j);
+        const int32_t dH = (h2 ^ m) - m;
+        bool acc;
+        if (ALGO == 0) {
+            const int32_t n = wk[j], nn = n - dH;
+            acc = nn >= 0;
+            wk[j] = acc ? nn : n;
+        } else {
+            const uint32_t i = (uint32_t)(2 * j + xs + LX * r);
+            const u32x4 w = philox10(i, e * (uint32_t)g.S + (uint32_t)s, (uint32_t)(2 * t + rep),
+                                     stream_word(kStreamPtMetropolis, run), g.key0, g.key1);
+            acc = exp_at_least(tab, w, dH);
+        }
+        flips |= acc ? (1u << (2 * j)) : 0u;
+    }
+    rows[base + r] = own ^ (flips << xs);
+}
+
+// Forward-X wandering of the sites of class PW: site j of class PW at
+// x = 2j + xs swaps with site j + xs of the other class (periodic).
+template <int K>
+__device__ __forceinline__ void reg_wander(int32_t (&A)[K], int32_t (&B)[K], int xs)
+{
+    int32_t nA[K], nB[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        nA[j] = xs ? B[(j + 1) % K] : B[j];
+        nB[j] = xs ? A[(j + K - 1) % K] : A[j];
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        A[j] = nA[j];
+        B[j] = nB[j];
+    }
+}
+
+// Grid (ceil(M / G), runs); block 64 * ceil(2 G R0 / 64) <= 1024 threads;
+// dynamic LDS pt_reg_layout(g, G).
+template <int LX, int ALGO, bool HOUD>
+__global__ __launch_bounds__(1024) void k_pt_emcs_reg(PtGeom g, int G, const int4* __restrict__ grec,
+                                                      uint64_t* __restrict__ spins, const int32_t* __restrict__ perm,
+                                                      int64_t* __restrict__ E, const uint32_t* __restrict__ wtab,
+                                                      uint32_t e)
+{
+    constexpr int K = LX / 2;
+    constexpr uint32_t MASK = LX == 32 ? 0xFFFFFFFFu : ((1u << LX) - 1u);
+    extern __shared__ __align__(16) unsigned char lds[];
+    const PtRegLds L = pt_reg_layout(g, G);
+    uint32_t* tabs = (uint32_t*)(lds + L.tab);
+    int4* rec = (int4*)(lds + L.rec);
+    uint32_t* rows = (uint32_t*)(lds + L.rows);
+    uint32_t* mark = (uint32_t*)(lds + L.mark);
+    uint32_t* diff = (uint32_t*)(lds + L.diff);
+    unsigned long long* esum = (unsigned long long*)(lds + L.esum);
+    int32_t* flag = (int32_t*)(lds + L.flag);
+
+    const int R0 = g.R0, tid = threadIdx.x, nthr = blockDim.x;
+    const int tl = tid / (2 * R0), rem = tid - tl * 2 * R0;
+    const int rep = rem >= R0, r = rem - rep * R0;
+    const int t0 = blockIdx.x * G, t = t0 + tl;
+    const int run = blockIdx.y;
+    const uint32_t sw = (uint32_t)run;
+    const bool live = tl < G && t < g.M;
+    const int base = (tl * 2 + rep) * R0;
+
+    for (int k = tid; k < G * kPtTable; k += nthr) {
+        const int tg = t0 + k / kPtTable;
+        tabs[k] = tg < g.M ? wtab[(int64_t)tg * kPtTable + k % kPtTable] : 0u;
+    }
+    for (int k = tid; k < 2 * g.N; k += nthr) rec[k] = grec[k];
+    int32_t slot = 0;
+    uint64_t* grow = nullptr;
+    if (live) {
+        slot = perm[((int64_t)run * 2 + rep) * g.M + t];
+        grow = spins + (((int64_t)run * 2 + rep) * g.M + slot) * R0 + r;
+        rows[base + r] = (uint32_t)*grow;
+    }
+    if (tid < 2 * G) esum[tid] = 0ull;
+    __syncthreads();
+
+    const PtRowNb nb = pt_row_nb(g, live ? r : 0);
+    const uint32_t* tab = tabs + (live ? tl : 0) * kPtTable;
+    int32_t wk0[K], wk1[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) wk0[j] = wk1[j] = 0;
+    if (ALGO == 0 && live) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int xs = (c + nb.y + nb.z) & 1;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const uint32_t i = (uint32_t)(2 * j + xs + LX * r);
+                const u32x4 w = philox10(i, e, (uint32_t)(2 * t + rep), stream_word(kStreamPtWalker, sw), g.key0,
+                                         g.key1);
+                (c == 0 ? wk0 : wk1)[j] = exp_draw4(tab, w);
+            }
+        }
+    }
+
+    for (int s = 0; s < g.S; ++s) {
+        if (live) reg_half<LX, ALGO, 0>(g, rec, rows, base, r, nb, wk0, tab, e, s, t, rep, sw);
+        __syncthreads();
+        if (live) reg_half<LX, ALGO, 1>(g, rec, rows, base, r, nb, wk1, tab, e, s, t, rep, sw);
+        __syncthreads();
+        if (ALGO == 0) {
+            if ((s & 1) == 0)
+                reg_wander<K>(wk0, wk1, (nb.y + nb.z) & 1);
+            else
+                reg_wander<K>(wk1, wk0, (1 + nb.y + nb.z) & 1);
+        }
+    }
+
+    if (HOUD) {
+        // one wave per temperature: differing sites per row, prefix in site order, chosen site
+        const int wave = tid >> 6, lane = tid & 63, nwave = nthr >> 6;
+        const int chunk = (R0 + 63) / 64;
+        for (int q = wave; q < G; q += nwave) {
+            if (t0 + q >= g.M) continue;
+            const uint32_t* ra = rows + (q * 2 + 0) * R0;
+            const uint32_t* rb = rows + (q * 2 + 1) * R0;
+            int32_t mine = 0;
+            for (int rr = lane * chunk; rr < min(R0, (lane + 1) * chunk); ++rr) {
+                const uint32_t d = (ra[rr] ^ rb[rr]) & MASK;
+                diff[q * R0 + rr] = d;
+                mark[q * R0 + rr] = 0u;
+                mine += __popc(d);
+            }
+            int32_t incl = mine;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int32_t v = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += v;
+            }
+            const int32_t count = __shfl(incl, 63, 64);
+            if (count > 0) {
+                const uint32_t u = philox10((uint32_t)(t0 + q), e, 0u, stream_word(kStreamPtHoudayer, sw), g.key0,
+                                            g.key1).v0;
+                const int32_t k = (int32_t)(((uint64_t)u * (uint64_t)count) >> 32);
+                const int32_t before = incl - mine;
+                if (k >= before && k < incl) {
+                    int32_t left = k - before;
+                    for (int rr = lane * chunk; rr < min(R0, (lane + 1) * chunk); ++rr) {
+                        uint32_t d = diff[q * R0 + rr];
+                        const int32_t c = __popc(d);
+                        if (left < c) {
+                            for (; left > 0; --left) d &= d - 1;
+                            mark[q * R0 + rr] = d & (~d + 1u);
+                            break;
+                        }
+                        left -= c;
+                    }
+                }
+            }
+        }
+        // grow every temperature's cluster together until none changes
+        const int q = tid / R0, rr = tid - q * R0;
+        const bool grower = q < G && t0 + q < g.M;
+        const PtRowNb gb = pt_row_nb(g, grower ? rr : 0);
+        for (;;) {
+            __syncthreads();
+            if (tid == 0) flag[0] = 0;
+            __syncthreads();
+            if (grower) {
+                const uint32_t* mq = mark + q * R0;
+                const uint32_t d = diff[q * R0 + rr], m = mq[rr];
+                uint32_t m2 = d & (m | mq[gb.yp] | mq[gb.ym] | mq[gb.zp] | mq[gb.zm]);
+                for (;;) {
+                    const uint32_t m3 = d & (m2 | rot_up32<LX>(m2) | rot_down32<LX>(m2));
+                    if (m3 == m2) break;
+                    m2 = m3;
+                }
+                if (m2 != m) {
+                    mark[q * R0 + rr] = m2;
+                    flag[0] = 1;
+                }
+            }
+            __syncthreads();
+            if (flag[0] == 0) break;
+        }
+        if (live) rows[base + r] ^= mark[tl * R0 + r];
+        __syncthreads();
+    }
+
+    if (live) {
+        const uint32_t own = rows[base + r];
+        const uint32_t dx = own ^ rot_down32<LX>(own), dy = own ^ rows[base + nb.yp], dz = own ^ rows[base + nb.zp];
+        int32_t en = 0;
+#pragma unroll
+        for (int x = 0; x < LX; ++x) {
+            const int4 a = rec[2 * (x * R0 + r)];
+            en += (2 * (a.x & sbit(dx, x)) - a.x) + (2 * (a.y & sbit(dy, x)) - a.y) + (2 * (a.z & sbit(dz, x)) - a.z);
+        }
+        atomicAdd(&esum[tl * 2 + rep], (unsigned long long)(int64_t)en);
+        *grow = own;
+    }
+    __syncthreads();
+    if (live && r == 0) E[((int64_t)run * 2 + rep) * g.M + slot] = (int64_t)esum[tl * 2 + rep];
+}
+
 // Tempering step: one wave per replica group (run, replica); lane t decides
 // pair (t, t+1), first the pairs with t even, then those with t odd.
 __global__ __launch_bounds__(256) void k_pt_swap(PtGeom g, int32_t* __restrict__ perm,
                                                  const int64_t* __restrict__ E, int64_t* __restrict__ swaps,
-                                                 const uint64_t* __restrict__ ptab, uint32_t e)
+                                                 const uint32_t* __restrict__ ptab, uint32_t e)
 {
     __shared__ int32_t sp[4][64];
     __shared__ int64_t se[4][64];

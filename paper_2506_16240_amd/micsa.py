@@ -26,6 +26,7 @@ KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_FUSED, KERNEL_RESIDENT = 0, 1, 2, 3
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_RELEASED = 0, 1, 2, 3
 PT_WALKERS, PT_METROPOLIS = 0, 1
 PT_TIME_EMCS, PT_TIME_SWAP = 0, 1
+PT_KERNEL_AUTO, PT_KERNEL_ROWS, PT_KERNEL_REGISTER = 0, 1, 2
 PT_MAX_SITES = 16384
 
 
@@ -117,6 +118,8 @@ _SIGNATURES = [
     ("micsa_pt_read_swaps", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("micsa_pt_get_tables", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     ("micsa_pt_get_couplings", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_pt_set_kernel", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    ("micsa_pt_kernel_name", ctypes.c_char_p, [ctypes.c_void_p]),
     ("micsa_pt_set_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("micsa_pt_get_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int64)]),
@@ -486,6 +489,13 @@ class PT:
         Jq = np.zeros((3, self.N), np.int32)
         self._check(lib().micsa_pt_get_couplings(self._ctx, _ptr(Jq)), "pt_get_couplings")
         return Jq
+
+    def set_kernel(self, kernel: int) -> None:
+        self._check(lib().micsa_pt_set_kernel(self._ctx, int(kernel)), "pt_set_kernel")
+
+    @property
+    def kernel_name(self) -> str:
+        return lib().micsa_pt_kernel_name(self._ctx).decode()
 
     def set_timing(self, on: bool) -> None:
         self._check(lib().micsa_pt_set_timing(self._ctx, int(bool(on))), "pt_set_timing")

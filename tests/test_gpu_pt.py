@@ -19,9 +19,10 @@ from paper_2506_16240_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def make(dims, runs, T, seed, sweeps=10, algo=M.PT_WALKERS, houdayer=True, jseed=None):
+def make(dims, runs, T, seed, sweeps=10, algo=M.PT_WALKERS, houdayer=True, jseed=None, kernel=M.PT_KERNEL_AUTO):
     J = W.gaussian_couplings(*dims, seed if jseed is None else jseed)
     g = M.PT(*dims, runs, T, J, seed, sweeps, algo, houdayer)
+    g.set_kernel(kernel)
     o = O.PTLattice(*dims, runs=runs, T=T, J=J, seed=seed, sweeps=sweeps,
                     algo=O.PT_WALKERS if algo == M.PT_WALKERS else O.PT_METROPOLIS, houdayer=houdayer)
     return g, o
@@ -64,11 +65,17 @@ CASES = [
 ]
 
 
+REGISTER_LX = (4, 6, 8, 10, 12, 16)
+
+
+@pytest.mark.parametrize("kernel", [M.PT_KERNEL_AUTO, M.PT_KERNEL_ROWS], ids=["auto", "rows"])
 @pytest.mark.parametrize("dims,runs,T,sweeps,algo,houdayer,n", CASES,
                          ids=[f"{c[0][0]}x{c[0][1]}x{c[0][2]}-r{c[1]}-M{len(c[2])}-s{c[3]}-a{c[4]}-h{int(c[5])}"
                               for c in CASES])
-def test_trajectory_matches_oracle(dims, runs, T, sweeps, algo, houdayer, n):
-    g, o = make(dims, runs, np.array(T), 0x5EED0100 + runs * 7 + sweeps, sweeps, algo, houdayer)
+def test_trajectory_matches_oracle(dims, runs, T, sweeps, algo, houdayer, n, kernel):
+    g, o = make(dims, runs, np.array(T), 0x5EED0100 + runs * 7 + sweeps, sweeps, algo, houdayer, kernel=kernel)
+    reg = kernel == M.PT_KERNEL_AUTO and dims[0] in REGISTER_LX and 2 * dims[1] * dims[2] <= 1024
+    assert g.kernel_name == ("k_pt_emcs_reg" if reg else "k_pt_emcs")
     same(g, o)
     swaps = np.zeros((runs, 2, len(T) - 1), np.int64)
     for chunk in (1, n - 1):  # one EMCS, then the rest in one call
@@ -79,14 +86,25 @@ def test_trajectory_matches_oracle(dims, runs, T, sweeps, algo, houdayer, n):
     g.close()
 
 
-def test_records_from_global_memory():
-    """16^3 sites do not leave room for the coupling records in LDS; the
-    kernel then reads them from global memory."""
-    g, o = make((16, 16, 16), 1, np.array([0.5, 1.0]), 0x5EED0200, sweeps=4)
-    swaps = np.zeros((1, 2, 1), np.int64)
+@pytest.mark.parametrize("kernel", [M.PT_KERNEL_AUTO, M.PT_KERNEL_ROWS], ids=["register", "rows"])
+def test_large_lattice(kernel):
+    """16^3 sites: the register kernel holds one temperature per work-group;
+    the row kernel has no room for the coupling records in LDS and reads
+    them from global memory."""
+    g, o = make((16, 16, 16), 1, np.array([0.5, 1.0, 1.5]), 0x5EED0200, sweeps=4, kernel=kernel)
+    assert g.kernel_name == ("k_pt_emcs_reg" if kernel == M.PT_KERNEL_AUTO else "k_pt_emcs")
+    swaps = np.zeros((1, 2, 2), np.int64)
     g.step(3)
     o.run(3, swaps)
     same(g, o, swaps)
+    g.close()
+
+
+def test_register_kernel_refused_where_it_does_not_apply():
+    g, _ = make((64, 4, 2), 1, np.array([0.5, 1.0]), 9)
+    with pytest.raises(M.MicsaError):
+        g.set_kernel(M.PT_KERNEL_REGISTER)
+    assert g.kernel_name == "k_pt_emcs"
     g.close()
 
 
@@ -117,6 +135,7 @@ def test_full_workload_first_emcs(algo):
     w = W.PT_L10
     T = w.temperatures()
     g = M.PT(w.L, w.L, w.L, w.runs, T, w.couplings(), w.seed, w.sweeps, algo, True)
+    assert g.kernel_name == "k_pt_emcs_reg"
     o = O.PTLattice(w.L, w.L, w.L, runs=w.runs, T=T, J=w.couplings(), seed=w.seed, sweeps=w.sweeps,
                     algo=O.PT_WALKERS if algo == M.PT_WALKERS else O.PT_METROPOLIS, houdayer=True)
     swaps = np.zeros((w.runs, 2, w.M - 1), np.int64)
