@@ -114,10 +114,9 @@ def serve(stream: list[tuple[float, JobSpec]], hbm_budget: int, sweeps_per_step:
     return res, metrics
 
 
-def capacity(n_jobs: int, seed: int, hbm_budget: int, sweeps_per_step: int, n_sweeps: int) -> float:
-    """Service capacity in spin updates/ns: the same job mix, all arriving at once."""
-    stream = [(0.0, spec) for _, spec in job_stream(n_jobs, 1.0, seed, n_sweeps)]
-    _, m = serve(stream, hbm_budget, sweeps_per_step)
+def capacity(specs: list[JobSpec], hbm_budget: int, sweeps_per_step: int) -> float:
+    """Service capacity in spin updates/ns: these jobs, all arriving at once."""
+    _, m = serve([(0.0, spec) for spec in specs], hbm_budget, sweeps_per_step)
     return m["updates_per_ns"]
 
 
@@ -134,8 +133,11 @@ def main() -> int:
     ap.add_argument("--hbm-gib", type=float, default=64.0)
     args = ap.parse_args()
     budget = int(args.hbm_gib * (1 << 30))
-    cap = capacity(max(8, args.jobs // 4), args.seed + 1, budget, args.sweeps_per_step, args.sweeps)
-    mean_updates = float(np.mean([s.updates for _, s in job_stream(4096, 1.0, args.seed + 2, args.sweeps)]))
+    # the job sizes do not depend on the arrival rate (the gaps scale one
+    # exponential draw each), so every load level serves this same mix
+    specs = [spec for _, spec in job_stream(args.jobs, 1.0, args.seed, args.sweeps)]
+    cap = capacity(specs, budget, args.sweeps_per_step)
+    mean_updates = float(np.mean([s.updates for s in specs]))
     print(json.dumps({"capacity_updates_per_ns": round(cap, 1), "mean_job_updates": mean_updates}), flush=True)
     for load in (float(x) for x in args.loads.split(",")):
         rate = load * cap * 1e9 / mean_updates  # jobs per second
