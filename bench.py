@@ -32,7 +32,12 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 # so the couplings ride along at no cost), daemon read+write 2 B.  The
 # baselines move the spin bytes only (plus one 32-bit uniform per update,
 # generated in registers).
-BYTES_PER_UPDATE = {"micsa": 4.0, "heatbath": 2.0, "metropolis": 2.0}
+BYTES_PER_UPDATE = {"micsa": 4.0, "heatbath": 2.0, "metropolis": 2.0, "walkers": 4.0}
+# Walkers (Sec. 2.6) on the fused sweep: each timestep's wandering is applied
+# by the next sweep as it loads the daemons (a byte shift across the two
+# parity arrays of a row), so a walker sweep moves the same 4 B per site as a
+# daemon sweep.  (On the per-half path a separate wandering kernel reads and
+# writes every daemon byte once more.)
 # Bit-plane layout (64 samples per 64-bit word): spin word read+write 16 B,
 # two daemon planes read+write 32 B, three forward-bond planes 24 B shared by
 # the two replicas of a sample: (16 + 32 + 12) / 64 = 0.9375 B per update.
@@ -66,7 +71,8 @@ def measured_traffic(name: str):
     return e.get("bytes_per_launch")
 
 
-def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None, layout: int = 0, events: bool = False):
+def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None, layout: int = 0, events: bool = False,
+            gamma: int = 1, period=None, c4: int = 0):
     """One timed region of `steps` steps on a fresh lattice.  With events the
     library brackets every launch with a HIP event pair (per-kernel
     durations for the roofline); without, the region is timed as a whole
@@ -83,16 +89,18 @@ def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None, layou
             if len(tile) > 3:
                 lat.set_option(M.OPT_TEMPORAL, tile[3])
 
-    algo = {"micsa": M.ALGO_MICSA, "heatbath": M.ALGO_HEATBATH, "metropolis": M.ALGO_METROPOLIS}[algo_name]
-    sched = M.Schedule(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
+    algo = {"micsa": M.ALGO_MICSA, "heatbath": M.ALGO_HEATBATH, "metropolis": M.ALGO_METROPOLIS,
+            "walkers": M.ALGO_WALKERS}[algo_name]
+    sched = M.Schedule(w.kind, w.T0, w.T1, w.n_sweeps, w.period if period is None else period)
     P = w.period
     if warmup > 0:
-        with M.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed, stream=stream.cuda_stream, layout=layout) as lw:
+        with M.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed, stream=stream.cuda_stream, layout=layout,
+                       gamma=gamma) as lw:
             configure(lw)
             lw.set_schedule(sched)
             lw.sweep(algo, warmup * P)
             lw.sync()
-    lat = M.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed, stream=stream.cuda_stream, layout=layout)
+    lat = M.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed, stream=stream.cuda_stream, layout=layout, gamma=gamma)
     configure(lat)
     lat.set_schedule(sched)
     lat.set_timing(events)
@@ -104,7 +112,8 @@ def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None, layou
     t1.record(stream)
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
-    kind = {M.ALGO_MICSA: M.TIME_SWEEP, M.ALGO_HEATBATH: M.TIME_HEATBATH, M.ALGO_METROPOLIS: M.TIME_METROPOLIS}[algo]
+    kind = {M.ALGO_MICSA: M.TIME_SWEEP, M.ALGO_HEATBATH: M.TIME_HEATBATH, M.ALGO_METROPOLIS: M.TIME_METROPOLIS,
+            M.ALGO_WALKERS: M.TIME_SWEEP}[algo]
     k_ms, k_n = lat.timing(kind)
     r_ms, r_n = lat.timing(M.TIME_REFRESH)
     # property that holds at any size: the incremental tally equals the energy
@@ -112,9 +121,17 @@ def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None, layou
     E = lat.energy()
     ok = bool((E == lat.energy_tally()).all()) if layout == M.LAYOUT_BYTE else None
     name = lat.kernel_name(algo)
+    c4_ms = None
+    if c4 > 0 and w.R >= 2:  # C4(r) sums of the final state (Sec. 3), timed as a whole
+        lat.c4_sums()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(c4):
+            lat.c4_sums()
+        c4_ms = (time.perf_counter() - t) * 1e3 / c4
     lat.close()
     return {"ms": ms, "kernel_ms": k_ms, "kernel_launches": k_n, "refresh_ms": r_ms, "refresh_launches": r_n,
-            "tally_check": ok, "kernel": name, "E_final": int(E[0])}
+            "tally_check": ok, "kernel": name, "E_final": int(E[0]), "c4_ms": c4_ms}
 
 
 def cpu_baseline(w, seconds: float):
@@ -269,6 +286,13 @@ def main() -> int:
     ap.add_argument("--tile", default="tune",
                     help="fused-sweep tile: 'tune' (autotuner, bit-exact gated), 'auto' (library default) "
                          "or TY,TZ[,PREFETCH[,SWEEPS_PER_PASS]]")
+    ap.add_argument("--algo", choices=("micsa", "walkers"), default="micsa",
+                    help="daemons (default) or walkers wandering every timestep (Sec. 2.6)")
+    ap.add_argument("--gamma", type=int, default=1, help="daemons (walkers) per site (Sec. 2.8)")
+    ap.add_argument("--refresh", choices=("period", "log2"), default="period",
+                    help="refresh every period of the workload, or at t = 0 and t = 2^s (Sec. 2.7)")
+    ap.add_argument("--c4", type=int, default=0,
+                    help="after the MicSA run, time this many C4(r) evaluations of the final state (R >= 2)")
     ap.add_argument("--copy-ref-gib", type=float, default=0.0,
                     help="after the run, copy this many GiB device-to-device (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -279,6 +303,7 @@ def main() -> int:
               "decomposition is not built (run with --gpus 1)", file=sys.stderr)
         return 2
 
+    from paper_2506_16240_amd import micsa as M
     from paper_2506_16240_amd import workloads as W
     import torch
 
@@ -309,11 +334,16 @@ def main() -> int:
             f"({best.us_per_sweep:.1f} us/sweep in tuning)")
     elif args.tile not in ("auto", "tune"):
         tile = tuple(int(v) for v in args.tile.split(","))
-    log(f"micsa: {w.name}, {sweeps} sweeps")
-    mi = run_gpu(w, "micsa", steps, args.warmup, stream, tile, layout)
-    log(f"micsa: {mi['ms']:.1f} ms, tally check {mi['tally_check']}")
-    log("micsa again with per-launch events (kernel durations)")
-    mk = run_gpu(w, "micsa", steps, 0, stream, tile, layout, events=True)
+    algo_name = args.algo
+    period = M.REFRESH_LOG2 if args.refresh == "log2" else None
+    if args.gamma != 1 and (layout or tile):
+        tile = None  # gamma > 1 runs the per-half kernels
+    log(f"{algo_name}: {w.name}, {sweeps} sweeps, gamma {args.gamma}, refresh {args.refresh}")
+    mi = run_gpu(w, algo_name, steps, args.warmup, stream, tile, layout, gamma=args.gamma, period=period,
+                 c4=args.c4)
+    log(f"{algo_name}: {mi['ms']:.1f} ms, tally check {mi['tally_check']}")
+    log(f"{algo_name} again with per-launch events (kernel durations)")
+    mk = run_gpu(w, algo_name, steps, 0, stream, tile, layout, events=True, gamma=args.gamma, period=period)
     log(f"micsa with events: {mk['ms']:.1f} ms, {mk['kernel_launches']} launches")
     hb = None
     if not args.no_heatbath:
@@ -333,12 +363,13 @@ def main() -> int:
     # it touches: bytes per update x sites x min(1, sweeps per launch).
     sweeps_per_launch = sweeps / mk["kernel_launches"]
     avg_ms = mk["kernel_ms"] / mk["kernel_launches"]
-    per_update = BYTES_PER_UPDATE_BITPLANE if layout else BYTES_PER_UPDATE["micsa"]
+    per_update = BYTES_PER_UPDATE_BITPLANE if layout else BYTES_PER_UPDATE[algo_name]
     bytes_launch = per_update * w.N * w.lattices * min(1.0, sweeps_per_launch)
     achieved = bytes_launch / (avg_ms * 1e6)  # GB/s
     traffic = measured_traffic(mi["kernel"])
     out = {
         "metric": "spin updates/ns (MicSA vs heat-bath, 1 GPU) + % of HBM roofline",
+        "algo": algo_name,
         "value": round(value, 2),
         "unit": "spin updates/ns",
         "n_gpus": 1,
@@ -352,7 +383,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "L": [w.Lx, w.Ly, w.Lz], "samples": w.S, "replicas": w.R,
                    "sweeps_per_step": w.period, "sweeps": sweeps, "schedule": f"T {w.T0}->{w.T1}",
-                   "layout": args.layout, "kernel": mi["kernel"], "tile": list(tile) if tile else "auto"},
+                   "layout": args.layout, "kernel": mi["kernel"], "tile": list(tile) if tile else "auto",
+                   "gamma": args.gamma, "refresh": args.refresh},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": mi["kernel"], "avg_launch_ms": round(avg_ms, 5),
@@ -361,6 +393,10 @@ def main() -> int:
                      "bytes_per_update": round(bytes_launch / (sweeps_per_launch * w.N * w.lattices), 3)},
         "checks": {"micsa_tally_equals_energy": mi["tally_check"]},
     }
+    if mi["c4_ms"] is not None:
+        nbytes = w.N * w.lattices  # spin bytes read per evaluation
+        out["c4"] = {"ms_per_evaluation": round(mi["c4_ms"], 4), "spin_bytes": nbytes,
+                     "GB_per_s": round(nbytes / (mi["c4_ms"] * 1e6), 1)}
     if hb is not None:
         out["heatbath"] = {"value": round(updates / (hb["ms"] * 1e6), 2), "unit": "spin updates/ns",
                            "ms_per_step": round(hb["ms"] / steps, 4), "kernel": hb["kernel"]}

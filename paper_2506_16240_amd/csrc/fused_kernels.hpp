@@ -73,6 +73,30 @@ __device__ __forceinline__ V4 ldg16(const uint8_t* __restrict__ p)
     return {{v.x, v.y, v.z, v.w}};
 }
 
+// A row chunk of 16 daemon bytes shifted by sh sites, new[k] = src[k + sh]
+// (sh in {-1, 0, 1}), from the chunk v and the edge word x of the adjacent
+// chunk of the same row (the first word of the next chunk for sh = 1, the
+// last word of the previous one for sh = -1), so the shift wraps around the
+// row as the lattice does.  Branch-free (rows of both shifts share a wave):
+// each word is alignbyte((hi:lo) >> 8 * shift).
+__device__ __forceinline__ const uint8_t* shift_edge(const uint8_t* row, int cn, int cp, int sh)
+{
+    return sh < 0 ? row + 16 * cp + 12 : row + 16 * cn;
+}
+
+__device__ __forceinline__ V4 shift_bytes(const V4& v, uint32_t x, int sh)
+{
+    const uint32_t b = sh > 0 ? 1u : (sh < 0 ? 3u : 0u);
+    V4 o;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t up = i < 3 ? v.w[i + 1] : x;  // the word after w[i]
+        const uint32_t dn = i > 0 ? v.w[i - 1] : x;  // the word before w[i]
+        o.w[i] = __builtin_amdgcn_alignbyte(sh > 0 ? up : v.w[i], sh < 0 ? dn : v.w[i], b);
+    }
+    return o;
+}
+
 __device__ __forceinline__ void stg16(uint8_t* __restrict__ p, const V4& v)
 {
     *reinterpret_cast<uint4*>(p) = make_uint4(v.w[0], v.w[1], v.w[2], v.w[3]);
@@ -172,6 +196,7 @@ __device__ __forceinline__ void refresh_chunk(const Geom& g, int row, int c, int
 // Inputs of one step of the march (global loads issued ahead of use).
 struct StepIn {
     V4 So, Se, Me, Mo;
+    uint32_t mex, mox;  // edge words of a pending walker wandering (see load_step)
 };
 
 // PF = steps of loads in flight: 1, or 2 with two input sets used
@@ -185,7 +210,7 @@ template <bool REFRESH, int PF>
 __global__ void __launch_bounds__(PF == 2 ? kPf2Lanes : 1024) k_micsa_sweep_fused(
     Geom g, FusedTile f, const uint8_t* __restrict__ spin_in, const uint8_t* __restrict__ dem_in,
     uint8_t* __restrict__ spin_out, uint8_t* __restrict__ dem_out, unsigned long long* __restrict__ tally,
-    uint32_t rho, DaemonThresholds th)
+    uint32_t rho, DaemonThresholds th, int wander)
 {
     extern __shared__ uint4 lds[];
     const int rows_slots = f.TY + 4;
@@ -230,15 +255,44 @@ __global__ void __launch_bounds__(PF == 2 ? kPf2Lanes : 1024) k_micsa_sweep_fuse
     V4 So_prev{}, So_cur{}, So_next{};  // odd spins (old) at planes z-dz, z, z+dz
     V4 X_prev2{}, X_prev{}, X_cur{};    // even views at planes z-2dz, z-dz, z
     V4 Mo_gen{};                        // refreshed odd levels of plane z-dz
+    // Walkers (Sec. 2.6): with wander = p >= 0 the stored daemons have not yet
+    // made the forward-X wandering of the sites of parity p that ended the
+    // previous timestep; it is applied here, on load.  In a row with
+    // q = (y + z) & 1 the even site k pairs with odd site k + q (p = 0), and
+    // odd site k with even site k + 1 - q (p = 1).
+    // The loads only fetch (the chunk and an edge word); the byte shift is
+    // applied when the step uses them, so the prefetch stays asynchronous.
+    auto row_of = [&](int z) { return ((int64_t)y + (int64_t)g.Ly * z) * g.Kx; };
+    auto sh_even = [&](int z) { return wander == 0 ? ((y + z) & 1) : ((y + z) & 1) - 1; };
+    auto sh_odd = [&](int z) { return wander == 0 ? -((y + z) & 1) : 1 - ((y + z) & 1); };
     auto load_step = [&](StepIn& in, int st2) {  // inputs of step st2 (plane z2 = zstart + dz st2)
         const int z2 = wrapz(zstart + dz * st2);
+        in.mex = 0u;
+        in.mox = 0u;
         if (active) in.So = ldg16(od_in + hof(wrapz(z2 + dz)));
         if (do_even) {
             const int64_t h2 = hof(z2);
             in.Se = ldg16(ev_in + h2);  // even spins with their bond bits
-            if (!REFRESH) in.Me = ldg16(me_in + h2);
+            if (!REFRESH) {
+                if (wander < 0) {
+                    in.Me = ldg16(me_in + h2);
+                } else {  // new even daemons come from the odd array
+                    const uint8_t* row = mo_in + row_of(z2);
+                    in.Me = ldg16(row + 16 * c);
+                    in.mex = *reinterpret_cast<const uint32_t*>(shift_edge(row, cn, cp, sh_even(z2)));
+                }
+            }
         }
-        if (!REFRESH && do_odd && st2 >= 2) in.Mo = ldg16(mo_in + hof(wrapz(z2 - dz)));
+        if (!REFRESH && do_odd && st2 >= 2) {
+            const int zo2 = wrapz(z2 - dz);
+            if (wander < 0) {
+                in.Mo = ldg16(mo_in + hof(zo2));
+            } else {  // new odd daemons come from the even array
+                const uint8_t* row = me_in + row_of(zo2);
+                in.Mo = ldg16(row + 16 * c);
+                in.mox = *reinterpret_cast<const uint32_t*>(shift_edge(row, cn, cp, sh_odd(zo2)));
+            }
+        }
     };
     if (active) {
         So_prev = ldg16(od_in + hof(wrapz(zstart - dz)));
@@ -254,6 +308,10 @@ __global__ void __launch_bounds__(PF == 2 ? kPf2Lanes : 1024) k_micsa_sweep_fuse
         const int64_t h = hof(z);
         So_next = in.So;
         V4 Se = in.Se, Me = in.Me, Mo = in.Mo;
+        if (!REFRESH && wander >= 0) {
+            Me = shift_bytes(Me, in.mex, sh_even(z));
+            Mo = shift_bytes(Mo, in.mox, sh_odd(wrapz(z - dz)));
+        }
         V4 Mo_next{};
         if (st + PF < steps) load_step(in, st + PF);
         if (REFRESH && do_even) refresh_chunk(g, y + g.Ly * z, c, (y + z) & 1, rho, (uint32_t)r, sw, th, Me, Mo_next);

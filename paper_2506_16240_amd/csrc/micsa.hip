@@ -68,6 +68,9 @@ struct micsa_ctx {
     int32_t prefetch = 1;  // steps of loads in flight in the fused MicSA sweep (1 or 2)
     int32_t temporal = 2;  // MicSA sweeps per pass of the fused kernel (1 or 2)
     int32_t use_graphs = 0;
+    // walkers on the fused sweep: parity of a forward-X wandering the stored
+    // daemons still owe (applied by the next fused sweep on load), or -1
+    int32_t pend_wander = -1;
     // replayable graphs of kGraphSweeps sweeps for the per-half paths, per algo
     int64_t* d_k = nullptr;  // device copy of the sweep counter
     hipStream_t cap_stream = nullptr;
@@ -359,7 +362,7 @@ FusedTile choose_tile(const micsa_ctx* c)
     return f;
 }
 
-int launch_fused_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
+int launch_fused_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T, int wander = -1)
 {
     const FusedTile f = choose_tile(c);
     const int lanes = (f.TY + 4) * f.NC;
@@ -373,7 +376,7 @@ int launch_fused_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
         const auto kern = refresh ? (pf2 ? k_micsa_sweep_fused<true, 2> : k_micsa_sweep_fused<true, 1>)
                                   : (pf2 ? k_micsa_sweep_fused<false, 2> : k_micsa_sweep_fused<false, 1>);
         kern<<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->dem, c->spin_alt, c->dem_alt, c->tally,
-                                              (uint32_t)rho, th);
+                                              (uint32_t)rho, th, refresh ? -1 : wander);
     }
     const int st = check_launch(c, "k_micsa_sweep_fused");
     if (st) return st;
@@ -717,11 +720,24 @@ int launch_wander(micsa_ctx* c, int64_t t)
     return MICSA_OK;
 }
 
+// Apply a wandering the daemons still owe (walkers on the fused sweep).
+int settle_wander(micsa_ctx* c)
+{
+    if (c->pend_wander < 0) return MICSA_OK;
+    const int p = c->pend_wander;
+    c->pend_wander = -1;
+    return launch_wander(c, p);
+}
+
 int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
 {
     if (!c) return MICSA_EINVAL;
     int st0 = check_sweep(c, algo, n);
     if (st0) return st0;
+    // walkers (gamma = 1) on the fused sweep carry their wandering into the
+    // next sweep's loads; every other path needs the daemons in place
+    const bool walk_fused = algo == MICSA_ALGO_WALKERS && !c->bit && c->gamma == 1 && use_fused(c);
+    if (!walk_fused && (st0 = settle_wander(c))) return st0;
     if (algo != MICSA_ALGO_WALKERS) {
         if (use_resident(c)) return launch_resident(c, algo, n, nullptr, 0);
         if (use_graph(c) && n >= kGraphSweeps) return sweep_graph(c, algo, n);
@@ -750,13 +766,18 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
             const bool refresh = fam == 0 && is_refresh(t, c->sched.period);
             if (c->bit) {
                 if ((st = launch_bitplane_sweep(c, refresh, rho, T))) return st;
+            } else if (walk_fused) {
+                // a refresh redraws every daemon, so an owed wandering lapses
+                if ((st = launch_fused_sweep(c, refresh, rho, T, c->pend_wander))) return st;
+                c->pend_wander = (int32_t)(t & 1);  // this timestep's wandering, owed to the next sweep
             } else if (use_fused(c)) {
                 if ((st = launch_fused_sweep(c, refresh, rho, T))) return st;
             } else {
                 if (refresh && (st = launch_refresh(c, rho, T))) return st;
                 if ((st = launch_micsa_sweep(c, fam))) return st;
             }
-            if (algo == MICSA_ALGO_WALKERS && fam == c->gamma - 1 && (st = launch_wander(c, t))) return st;
+            if (algo == MICSA_ALGO_WALKERS && !walk_fused && fam == c->gamma - 1 && (st = launch_wander(c, t)))
+                return st;
         } else {
             if ((st = launch_canonical_sweep(c, algo, k, T))) return st;
         }
@@ -1289,6 +1310,8 @@ int micsa_read_demons(micsa_ctx* ctx, uint8_t* m)
 {
     if (!ctx || !m) return MICSA_EINVAL;
     if (ctx->bit) return read_words(ctx, ctx->bdm0, ctx->bdm1, m);
+    const int st = settle_wander(ctx);
+    if (st) return st;
     return read_state(ctx, ctx->dem, m, (int64_t)ctx->L * ctx->gamma);
 }
 
@@ -1396,7 +1419,9 @@ int micsa_write_demons(micsa_ctx* ctx, const uint8_t* m)
 {
     if (!ctx || !m) return MICSA_EINVAL;
     if (ctx->bit) return write_words(ctx, ctx->bdm0, ctx->bdm1, m, 3);
-    return write_state(ctx, ctx->dem, m, 3, (int64_t)ctx->L * ctx->gamma);
+    const int st = write_state(ctx, ctx->dem, m, 3, (int64_t)ctx->L * ctx->gamma);
+    if (!st) ctx->pend_wander = -1;  // the written daemons are where they are
+    return st;
 }
 
 int micsa_get_counters(micsa_ctx* ctx, int64_t* k, int64_t* rho)
@@ -1473,7 +1498,9 @@ int micsa_get_timing(micsa_ctx* ctx, int32_t kind, double* total_ms, int64_t* la
 const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
 {
     if (ctx && ctx->bit) return algo == MICSA_ALGO_MICSA ? "kb_micsa_half" : "";
-    if (algo == MICSA_ALGO_WALKERS) return ctx && use_fused(ctx) ? "k_micsa_sweep_fused+k_wander" : "k_micsa_half+k_wander";
+    // walkers on the fused sweep wander on the next sweep's loads
+    if (algo == MICSA_ALGO_WALKERS)
+        return ctx && use_fused(ctx) && ctx->gamma == 1 ? "k_micsa_sweep_fused" : "k_micsa_half+k_wander";
     // gamma > 1 runs the per-half kernels (never resident or fused)
     if (ctx && use_resident(ctx))
         return algo == MICSA_ALGO_HEATBATH ? "k_resident<1>" : (algo == MICSA_ALGO_METROPOLIS ? "k_resident<2>" : "k_resident<0>");

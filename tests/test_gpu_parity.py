@@ -277,6 +277,30 @@ def test_walkers_match_oracle(shape, kernel):
     assert np.array_equal(g.energy_tally(), o.energy())
 
 
+@pytest.mark.parametrize("prefetch", [1, 2])
+def test_walkers_fused_wander_on_load(prefetch):
+    """Walkers on the fused sweep carry each timestep's forward-X wandering
+    into the next sweep's daemon loads: stretches of up to 8 sweeps between
+    refreshes, rows of four 16-site chunks, a wandering still owed when the
+    daemons are read back, and a switch to daemons (which applies it first)."""
+    shape = (128, 8, 6, 1, 2)
+    g, o = pair(*shape, seed=777)
+    g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)
+    g.set_option(M.OPT_PREFETCH, prefetch)
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.2, 0.4, 60, 9)
+    g.set_schedule(gs)
+    assert g.kernel_name(M.ALGO_WALKERS) == "k_micsa_sweep_fused"
+    g.sweep(M.ALGO_WALKERS, 13)
+    o.run(O.ALGO_WALKERS, os_, 13)
+    same_state(g, o)
+    g.sweep(M.ALGO_WALKERS, 20)
+    o.run(O.ALGO_WALKERS, os_, 20)
+    g.sweep(M.ALGO_MICSA, 7)
+    o.run(O.ALGO_MICSA, os_, 7)
+    same_state(g, o)
+    assert np.array_equal(g.energy_tally(), o.energy())
+
+
 def test_gpu_error_paths():
     g, _ = pair(8, 8, 8)
     with pytest.raises(M.MicsaError) as e:
