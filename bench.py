@@ -364,6 +364,8 @@ def main() -> int:
     sweeps_per_launch = sweeps / mk["kernel_launches"]
     avg_ms = mk["kernel_ms"] / mk["kernel_launches"]
     per_update = BYTES_PER_UPDATE_BITPLANE if layout else BYTES_PER_UPDATE[algo_name]
+    if "k_wander" in mi["kernel"]:  # a separate wandering kernel moves every daemon byte once more
+        per_update += 2.0
     bytes_launch = per_update * w.N * w.lattices * min(1.0, sweeps_per_launch)
     achieved = bytes_launch / (avg_ms * 1e6)  # GB/s
     traffic = measured_traffic(mi["kernel"])
