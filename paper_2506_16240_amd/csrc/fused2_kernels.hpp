@@ -24,6 +24,16 @@
 // draws B's instead of taking A's new ones (the drawn levels of plane q are
 // made at the even half of q and the odd ones kept for the odd half of q one
 // step later).
+//
+// Walkers (WALK, gamma = 1, Sec. 2.6): the forward-X wandering that ends a
+// timestep moves daemons between a row's parity arrays by 0 or 1 site.  A
+// wandering owed from before the launch (wanderA >= 0) is applied as A
+// loads its daemons, as in the one-sweep kernel; the wandering of A's own
+// timestep (parity wanderAB) is applied in registers: B-even takes A's final
+// odd levels of its plane and B-odd A's final even levels, byte-shifted,
+// the edge byte coming from the neighbouring chunk's lane by a wave
+// shuffle (a row's NC lanes lie in one wave when NC divides 64).  B's own
+// wandering is left owed to the next sweep.
 #pragma once
 #include "fused_kernels.hpp"
 
@@ -76,11 +86,11 @@ __device__ __forceinline__ void odd_chunk(V4& S, V4& M, const V4& A, const V4& B
     }
 }
 
-template <bool RA, bool RB>
+template <bool RA, bool RB, bool WALK>
 __global__ void __launch_bounds__(kSweep2Lanes) k_micsa_sweep2_fused(
     Geom g, FusedTile f, const uint8_t* __restrict__ spin_in, const uint8_t* __restrict__ dem_in,
     uint8_t* __restrict__ spin_out, uint8_t* __restrict__ dem_out, unsigned long long* __restrict__ tally,
-    uint32_t rhoA, DaemonThresholds thA, uint32_t rhoB, DaemonThresholds thB)
+    uint32_t rhoA, DaemonThresholds thA, uint32_t rhoB, DaemonThresholds thB, int wanderA, int wanderAB)
 {
     extern __shared__ uint4 lds[];
     const int rows_slots = f.TY + 8;
@@ -132,22 +142,55 @@ __global__ void __launch_bounds__(kSweep2Lanes) k_micsa_sweep2_fused(
     V4 Oo_prev{}, Oo_cur{}, Oo_next{};  // old odd spins at p - dz, p, p + dz
     V4 XA0{}, XA1{}, XA2{};             // A even views at p, p - dz, p - 2dz
     V4 WA1{}, WA2{}, MA1{}, MA2{};      // A's new even spins/levels at p - dz, p - 2dz
+    V4 MA3{};                           // WALK: A's new even levels at p - 3dz
     V4 SA0{}, SA1{}, SA2{};             // A's new odd spins at p - dz, p - 2dz, p - 3dz
     V4 NA0{}, NA1{}, NA2{};             // A's new odd levels at the same planes
     V4 XB0{}, XB1{}, XB2{};             // B even views at p - 2dz, p - 3dz, p - 4dz
     V4 MoA_gen{};                       // RA: A's drawn odd levels of plane p - dz
     V4 MoB_gen{};                       // RB: B's drawn odd levels of plane p - 3dz
     V4 nSo{}, nSe{}, nMe{}, nMo{};      // loads for the next step
+    uint32_t nMex = 0, nMox = 0;        // WALK: edge words of an owed wandering
 
+    // shift of a row's even (odd) daemons in a wandering of parity w:
+    // new[k] = other parity array[k + shift] (see shift_bytes)
+    auto sh_even = [&](int w, int z) { return w == 0 ? ((y + z) & 1) : ((y + z) & 1) - 1; };
+    auto sh_odd = [&](int w, int z) { return w == 0 ? -((y + z) & 1) : 1 - ((y + z) & 1); };
+    auto row_of = [&](int z) { return (int64_t)y * g.Kx + plane * z; };
     auto load_step = [&](int st2) {
         const int z2 = zof(st2);
+        nMex = 0u;
+        nMox = 0u;
         if (active) nSo = ldg16(od_in + hof(wrap(z2 + dz, g.Lz)));
         if (rowA_e) {
             const int64_t h2 = hof(z2);
             nSe = ldg16(ev_in + h2);
-            if (!RA) nMe = ldg16(me_in + h2);
+            if (!RA) {
+                if (!WALK || wanderA < 0) {
+                    nMe = ldg16(me_in + h2);
+                } else {  // new even daemons come from the odd array
+                    const uint8_t* row = mo_in + row_of(z2);
+                    nMe = ldg16(row + 16 * c);
+                    nMex = *reinterpret_cast<const uint32_t*>(shift_edge(row, cn, cp, sh_even(wanderA, z2)));
+                }
+            }
         }
-        if (!RA && rowA_o && st2 >= 2) nMo = ldg16(mo_in + hof(wrap(z2 - dz, g.Lz)));
+        if (!RA && rowA_o && st2 >= 2) {
+            const int zo2 = wrap(z2 - dz, g.Lz);
+            if (!WALK || wanderA < 0) {
+                nMo = ldg16(mo_in + hof(zo2));
+            } else {  // new odd daemons come from the even array
+                const uint8_t* row = me_in + row_of(zo2);
+                nMo = ldg16(row + 16 * c);
+                nMox = *reinterpret_cast<const uint32_t*>(shift_edge(row, cn, cp, sh_odd(wanderA, zo2)));
+            }
+        }
+    };
+    // lanes of this row's neighbouring chunks (a row's lanes share a wave)
+    const int lane_next = (ry * f.NC + cn) & 63, lane_prev = (ry * f.NC + cp) & 63;
+    // the edge word a neighbour needs from v for a shift sh, taken from the lane it comes from
+    auto edge_from = [&](const V4& v, int sh) {
+        const uint32_t give = sh > 0 ? v.w[0] : v.w[3];
+        return (uint32_t)__shfl((int)give, sh > 0 ? lane_next : lane_prev, 64);
     };
     if (active) {
         Oo_prev = ldg16(od_in + hof(wrap(zstart - dz, g.Lz)));
@@ -163,6 +206,19 @@ __global__ void __launch_bounds__(kSweep2Lanes) k_micsa_sweep2_fused(
         const int zBo = zof(st - 3);      // B-odd plane p - 3dz
         Oo_next = nSo;
         V4 Se = nSe, Me = nMe, Mo = nMo;
+        if (WALK && !RA && wanderA >= 0) {
+            Me = shift_bytes(Me, nMex, sh_even(wanderA, zA));
+            Mo = shift_bytes(Mo, nMox, sh_odd(wanderA, zAo));
+        }
+        // WALK: B's daemons are A's final ones after the wandering of A's
+        // timestep: even levels of zBe from A's odd levels (NA1), odd levels
+        // of zBo from A's even levels (MA3); the edge bytes by shuffle, with
+        // every lane taking part
+        uint32_t edgeBe = 0, edgeBo = 0;
+        if (WALK && !RB) {
+            edgeBe = edge_from(NA1, sh_even(wanderAB, zBe));
+            edgeBo = edge_from(MA3, sh_odd(wanderAB, zBo));
+        }
         if (st + 1 < steps) load_step(st + 1);
         V4 MoA_next{}, MoB_next{};
         if (RA && rowA_e) refresh_chunk(g, y + g.Ly * zA, c, (y + zA) & 1, rhoA, (uint32_t)r, sw, thA, Me, MoA_next);
@@ -218,6 +274,7 @@ __global__ void __launch_bounds__(kSweep2Lanes) k_micsa_sweep2_fused(
             const V4 Yp = lds16(&SoA[pb * plane_slots + (ry + 1) * f.NC + c]);
             const V4 Ym = lds16(&SoA[pb * plane_slots + (ry - 1) * f.NC + c]);
             V4 W = WA2, M = MA2;
+            if (WALK && !RB) M = shift_bytes(NA1, edgeBe, sh_even(wanderAB, zBe));
             if (RB) refresh_chunk(g, y + g.Ly * zBe, c, (y + zBe) & 1, rhoB, (uint32_t)r, sw, thB, M, MoB_next);
             uint32_t so = 0, sn = 0;
             XB0 = even_chunk(W, M, SA1, B, Yp, Ym, dz > 0 ? SA0 : SA2, dz > 0 ? SA2 : SA0, q, so, sn);
@@ -240,6 +297,7 @@ __global__ void __launch_bounds__(kSweep2Lanes) k_micsa_sweep2_fused(
             const V4 Yp = lds16(&XB[pb * plane_slots + (ry + 1) * f.NC + c]);
             const V4 Ym = lds16(&XB[pb * plane_slots + (ry - 1) * f.NC + c]);
             V4 S = SA2, M = RB ? MoB_gen : NA2;
+            if (WALK && !RB) M = shift_bytes(MA3, edgeBo, sh_odd(wanderAB, zBo));
             uint32_t so = 0, sn = 0;
             odd_chunk(S, M, XB1, B, Yp, Ym, dz > 0 ? XB0 : XB2, dz > 0 ? XB2 : XB0, q, so, sn);
             if (owned_plane(st - 3)) {
@@ -256,6 +314,7 @@ __global__ void __launch_bounds__(kSweep2Lanes) k_micsa_sweep2_fused(
         XA2 = XA1;
         XA1 = XA0;
         WA2 = WA1;
+        if (WALK) MA3 = MA2;
         MA2 = MA1;
         WA1 = Se;
         MA1 = Me;

@@ -403,21 +403,28 @@ FusedTile choose_tile2(const micsa_ctx* c)
 bool sweep2_eligible(const micsa_ctx* c) { return kSweep2Lanes / (c->p.Lx / 32) - 8 >= 1; }
 
 // Sweeps k and k + 1 in one pass (fused2_kernels.hpp); refreshA / refreshB
-// say whether k / k + 1 are refresh points.
-int launch_fused_sweep2(micsa_ctx* c, bool refreshA, int64_t rhoA, double TA, bool refreshB, int64_t rhoB, double TB)
+// say whether k / k + 1 are refresh points.  Walkers (walk): wanderA is a
+// wandering owed from before (-1: none), wanderAB the parity of the
+// wandering between the two sweeps.
+int launch_fused_sweep2(micsa_ctx* c, bool refreshA, int64_t rhoA, double TA, bool refreshB, int64_t rhoB, double TB,
+                        bool walk = false, int wanderA = -1, int wanderAB = -1)
 {
     const FusedTile f = choose_tile2(c);
     const int lanes = (f.TY + 8) * f.NC;
     const int block = (lanes + 63) / 64 * 64;
     const size_t lds = (size_t)128 * (f.TY + 8) * f.NC;  // 4 planes x 2 buffers x 16 B per lane slot
-    static const void* const kernels[4] = {
-        (const void*)k_micsa_sweep2_fused<false, false>, (const void*)k_micsa_sweep2_fused<true, false>,
-        (const void*)k_micsa_sweep2_fused<false, true>, (const void*)k_micsa_sweep2_fused<true, true>};
-    static bool attr_set[4] = {false, false, false, false};
-    const int which = (refreshA ? 1 : 0) + (refreshB ? 2 : 0);
+    using Kern = void (*)(Geom, FusedTile, const uint8_t*, const uint8_t*, uint8_t*, uint8_t*, unsigned long long*,
+                          uint32_t, DaemonThresholds, uint32_t, DaemonThresholds, int, int);
+    static const Kern kernels[8] = {
+        k_micsa_sweep2_fused<false, false, false>, k_micsa_sweep2_fused<true, false, false>,
+        k_micsa_sweep2_fused<false, true, false>,  k_micsa_sweep2_fused<true, true, false>,
+        k_micsa_sweep2_fused<false, false, true>,  k_micsa_sweep2_fused<true, false, true>,
+        k_micsa_sweep2_fused<false, true, true>,   k_micsa_sweep2_fused<true, true, true>};
+    static bool attr_set[8] = {};
+    const int which = (refreshA ? 1 : 0) + (refreshB ? 2 : 0) + (walk ? 4 : 0);
     if (!attr_set[which]) {
-        const hipError_t e =
-            hipFuncSetAttribute(kernels[which], hipFuncAttributeMaxDynamicSharedMemorySize, (int)kResidentLdsMax);
+        const hipError_t e = hipFuncSetAttribute((const void*)kernels[which],
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kResidentLdsMax);
         if (e != hipSuccess) return fail(c, MICSA_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
         attr_set[which] = true;
     }
@@ -426,22 +433,22 @@ int launch_fused_sweep2(micsa_ctx* c, bool refreshA, int64_t rhoA, double TA, bo
     const DaemonThresholds thB = refreshB ? daemon_thresholds(TB) : DaemonThresholds{0, 0, 0};
     {
         TimedLaunch t(c, kTimeSweep);
-        auto go = [&](auto kern) {
-            kern<<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->dem, c->spin_alt, c->dem_alt, c->tally,
-                                                  (uint32_t)rhoA, thA, (uint32_t)rhoB, thB);
-        };
-        switch (which) {
-        case 0: go(k_micsa_sweep2_fused<false, false>); break;
-        case 1: go(k_micsa_sweep2_fused<true, false>); break;
-        case 2: go(k_micsa_sweep2_fused<false, true>); break;
-        default: go(k_micsa_sweep2_fused<true, true>); break;
-        }
+        kernels[which]<<<grid, block, lds, c->stream>>>(c->g, f, c->spin, c->dem, c->spin_alt, c->dem_alt, c->tally,
+                                                        (uint32_t)rhoA, thA, (uint32_t)rhoB, thB,
+                                                        refreshA ? -1 : wanderA, wanderAB);
     }
     const int st = check_launch(c, "k_micsa_sweep2_fused");
     if (st) return st;
     std::swap(c->spin, c->spin_alt);
     std::swap(c->dem, c->dem_alt);
     return MICSA_OK;
+}
+
+// Walkers in the two-sweep kernel need a row's chunks in one wave.
+bool sweep2_walk_eligible(const micsa_ctx* c)
+{
+    const int nc = c->p.Lx / 32;
+    return c->gamma == 1 && sweep2_eligible(c) && 64 % nc == 0;
 }
 
 int launch_micsa_sweep(micsa_ctx* c, int fam)
@@ -751,6 +758,20 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
         const double T = temperature(c->sched, rho);
         if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
         int st;
+        if (walk_fused && c->temporal == 2 && i + 1 < n && sweep2_walk_eligible(c)) {
+            // timesteps t and t + 1 (gamma = 1) in one pass, wandering between them in registers
+            const bool refreshB = is_refresh(t + 1, c->sched.period);
+            const int64_t rhoB = refresh_index(t + 1, c->sched.period);
+            const double TB = temperature(c->sched, rhoB);
+            if (!(TB > 0.0) || !std::isfinite(TB)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
+            if ((st = launch_fused_sweep2(c, is_refresh(t, c->sched.period), rho, T, refreshB, rhoB, TB, true,
+                                          c->pend_wander, (int)(t & 1))))
+                return st;
+            c->pend_wander = (int32_t)((t + 1) & 1);
+            c->k = k + 2;
+            ++i;
+            continue;
+        }
         if (algo == MICSA_ALGO_MICSA && c->temporal == 2 && i + 1 < n && use_fused(c) && sweep2_eligible(c)) {
             // sweeps k and k + 1 in one pass (gamma = 1 on the fused path)
             const bool refreshB = is_refresh(k + 1, c->sched.period);
@@ -1500,7 +1521,9 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
     if (ctx && ctx->bit) return algo == MICSA_ALGO_MICSA ? "kb_micsa_half" : "";
     // walkers on the fused sweep wander on the next sweep's loads
     if (algo == MICSA_ALGO_WALKERS)
-        return ctx && use_fused(ctx) && ctx->gamma == 1 ? "k_micsa_sweep_fused" : "k_micsa_half+k_wander";
+        return ctx && use_fused(ctx) && ctx->gamma == 1
+                   ? (ctx->temporal == 2 && sweep2_walk_eligible(ctx) ? "k_micsa_sweep2_fused" : "k_micsa_sweep_fused")
+                   : "k_micsa_half+k_wander";
     // gamma > 1 runs the per-half kernels (never resident or fused)
     if (ctx && use_resident(ctx))
         return algo == MICSA_ALGO_HEATBATH ? "k_resident<1>" : (algo == MICSA_ALGO_METROPOLIS ? "k_resident<2>" : "k_resident<0>");

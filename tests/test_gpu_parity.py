@@ -277,24 +277,31 @@ def test_walkers_match_oracle(shape, kernel):
     assert np.array_equal(g.energy_tally(), o.energy())
 
 
-@pytest.mark.parametrize("prefetch", [1, 2])
-def test_walkers_fused_wander_on_load(prefetch):
-    """Walkers on the fused sweep carry each timestep's forward-X wandering
-    into the next sweep's daemon loads: stretches of up to 8 sweeps between
-    refreshes, rows of four 16-site chunks, a wandering still owed when the
-    daemons are read back, and a switch to daemons (which applies it first)."""
-    shape = (128, 8, 6, 1, 2)
+@pytest.mark.parametrize("shape", [(128, 8, 6, 1, 2), (96, 6, 4, 1, 1), (64, 4, 8, 2, 1)])
+@pytest.mark.parametrize("prefetch,temporal", [(1, 1), (2, 1), (1, 2)])
+def test_walkers_fused_wander_on_load(shape, prefetch, temporal):
+    """Walkers on the fused sweeps: each timestep's forward-X wandering is
+    applied by the next sweep as it loads the daemons, and inside the
+    two-sweep kernel between its two sweeps (rows of 2 or 4 chunks; rows of
+    3 chunks fall back to the one-sweep kernel).  Stretches of up to 8
+    sweeps between refreshes, pairs and single sweeps in turn, a wandering
+    still owed when the daemons are read back, and a switch to daemons
+    (which applies it first)."""
     g, o = pair(*shape, seed=777)
     g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)
     g.set_option(M.OPT_PREFETCH, prefetch)
+    g.set_option(M.OPT_TEMPORAL, temporal)
     gs, os_ = scheds(M.SCHED_LINEAR, 2.2, 0.4, 60, 9)
     g.set_schedule(gs)
-    assert g.kernel_name(M.ALGO_WALKERS) == "k_micsa_sweep_fused"
-    g.sweep(M.ALGO_WALKERS, 13)
-    o.run(O.ALGO_WALKERS, os_, 13)
+    two = temporal == 2 and 64 % (shape[0] // 32) == 0
+    assert g.kernel_name(M.ALGO_WALKERS) == ("k_micsa_sweep2_fused" if two else "k_micsa_sweep_fused")
+    for n in (13, 1, 2, 3):
+        g.sweep(M.ALGO_WALKERS, n)
+        o.run(O.ALGO_WALKERS, os_, n)
     same_state(g, o)
     g.sweep(M.ALGO_WALKERS, 20)
     o.run(O.ALGO_WALKERS, os_, 20)
+    assert np.array_equal(g.energy(), o.energy())
     g.sweep(M.ALGO_MICSA, 7)
     o.run(O.ALGO_MICSA, os_, 7)
     same_state(g, o)
