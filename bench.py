@@ -281,6 +281,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-heatbath", action="store_true")
     ap.add_argument("--no-metropolis", action="store_true")
+    ap.add_argument("--no-walkers", action="store_true",
+                    help="skip the walker leg (MicSA with forward-X wandering walkers, the paper's Table 3 variant)")
     ap.add_argument("--layout", choices=("byte", "bitplane"), default="byte",
                     help="MicSA layout (the baselines always run in the byte layout)")
     ap.add_argument("--tile", default="tune",
@@ -355,6 +357,11 @@ def main() -> int:
         log(f"metropolis: {w.name}, {sweeps} sweeps")
         mp = run_gpu(w, "metropolis", steps, args.warmup, stream)
         log(f"metropolis: {mp['ms']:.1f} ms")
+    wk = None
+    if not args.no_walkers and algo_name == "micsa" and args.gamma == 1 and not layout:
+        log(f"walkers: {w.name}, {sweeps} sweeps")
+        wk = run_gpu(w, "walkers", steps, args.warmup, stream, tile, layout, period=period)
+        log(f"walkers: {wk['ms']:.1f} ms")
 
     value = updates / (mi["ms"] * 1e6)
     # dominant kernel: the sweep kernel.  A launch covers one half sweep
@@ -409,6 +416,12 @@ def main() -> int:
                              "ms_per_step": round(mp["ms"] / steps, 4), "kernel": mp["kernel"]}
         out["micsa_over_metropolis"] = round(mp["ms"] / mi["ms"], 3)
         out["checks"]["metropolis_tally_equals_energy"] = mp["tally_check"]
+    if wk is not None:
+        out["walkers"] = {"value": round(updates / (wk["ms"] * 1e6), 2), "unit": "spin updates/ns",
+                          "ms_per_step": round(wk["ms"] / steps, 4), "kernel": wk["kernel"]}
+        out["checks"]["walkers_tally_equals_energy"] = wk["tally_check"]
+        if mp is not None:
+            out["walkers_over_metropolis"] = round(mp["ms"] / wk["ms"], 3)
     if args.copy_ref_gib > 0:
         n = int(args.copy_ref_gib * (1 << 30))
         a = torch.ones(n, dtype=torch.uint8, device="cuda")
