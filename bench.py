@@ -42,6 +42,10 @@ BYTES_PER_UPDATE = {"micsa": 4.0, "heatbath": 2.0, "metropolis": 2.0, "walkers":
 # two daemon planes read+write 32 B, three forward-bond planes 24 B shared by
 # the two replicas of a sample: (16 + 32 + 12) / 64 = 0.9375 B per update.
 BYTES_PER_UPDATE_BITPLANE = 0.9375
+# Multispin planes of one lattice (64 sites of a row per word): spin bit read
+# and written, two daemon bits read and written, and the three couplings per
+# site (six per even site) read once per sweep: 9 bits = 1.125 B per update.
+BYTES_PER_UPDATE_MULTISPIN = 1.125
 
 
 def log(msg: str) -> None:
@@ -72,7 +76,7 @@ def measured_traffic(name: str):
 
 
 def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None, layout: int = 0, events: bool = False,
-            gamma: int = 1, period=None, c4: int = 0):
+            gamma: int = 1, period=None, c4: int = 0, kernel: int = 0):
     """One timed region of `steps` steps on a fresh lattice.  With events the
     library brackets every launch with a HIP event pair (per-kernel
     durations for the roofline); without, the region is timed as a whole
@@ -81,6 +85,8 @@ def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None, layou
     import torch
 
     def configure(lat):
+        if kernel:
+            lat.set_option(M.OPT_SWEEP_KERNEL, kernel)
         if tile and algo_name == "micsa":
             lat.set_option(M.OPT_TILE_Y, tile[0])
             lat.set_option(M.OPT_TILE_Z, tile[1])
@@ -291,6 +297,8 @@ def main() -> int:
     ap.add_argument("--algo", choices=("micsa", "walkers"), default="micsa",
                     help="daemons (default) or walkers wandering every timestep (Sec. 2.6)")
     ap.add_argument("--gamma", type=int, default=1, help="daemons (walkers) per site (Sec. 2.8)")
+    ap.add_argument("--kernel", choices=("auto", "fused", "multispin"), default="auto",
+                    help="MicSA sweep kernel: library choice, the fused byte sweep, or multispin bit planes")
     ap.add_argument("--refresh", choices=("period", "log2"), default="period",
                     help="refresh every period of the workload, or at t = 0 and t = 2^s (Sec. 2.7)")
     ap.add_argument("--c4", type=int, default=0,
@@ -341,11 +349,13 @@ def main() -> int:
     if args.gamma != 1 and (layout or tile):
         tile = None  # gamma > 1 runs the per-half kernels
     log(f"{algo_name}: {w.name}, {sweeps} sweeps, gamma {args.gamma}, refresh {args.refresh}")
+    kern = {"auto": 0, "fused": M.KERNEL_FUSED, "multispin": M.KERNEL_MULTISPIN}[args.kernel]
     mi = run_gpu(w, algo_name, steps, args.warmup, stream, tile, layout, gamma=args.gamma, period=period,
-                 c4=args.c4)
+                 c4=args.c4, kernel=kern)
     log(f"{algo_name}: {mi['ms']:.1f} ms, tally check {mi['tally_check']}")
     log(f"{algo_name} again with per-launch events (kernel durations)")
-    mk = run_gpu(w, algo_name, steps, 0, stream, tile, layout, events=True, gamma=args.gamma, period=period)
+    mk = run_gpu(w, algo_name, steps, 0, stream, tile, layout, events=True, gamma=args.gamma, period=period,
+                 kernel=kern)
     log(f"micsa with events: {mk['ms']:.1f} ms, {mk['kernel_launches']} launches")
     hb = None
     if not args.no_heatbath:
@@ -373,6 +383,8 @@ def main() -> int:
     per_update = BYTES_PER_UPDATE_BITPLANE if layout else BYTES_PER_UPDATE[algo_name]
     if "k_wander" in mi["kernel"]:  # a separate wandering kernel moves every daemon byte once more
         per_update += 2.0
+    if mi["kernel"] == "k_msc_half":
+        per_update = BYTES_PER_UPDATE_MULTISPIN
     bytes_launch = per_update * w.N * w.lattices * min(1.0, sweeps_per_launch)
     achieved = bytes_launch / (avg_ms * 1e6)  # GB/s
     traffic = measured_traffic(mi["kernel"])

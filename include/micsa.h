@@ -203,7 +203,12 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
    MICSA_OPT_SWEEP_KERNEL: MICSA_KERNEL_AUTO (default), MICSA_KERNEL_SIMPLE
      (one launch per half sweep), MICSA_KERNEL_FUSED (one launch per sweep,
      refresh fused in; needs Lx % 32 == 0), MICSA_KERNEL_RESIDENT (whole
-     lattice in LDS for many sweeps per launch; byte layout, N <= 102400).
+     lattice in LDS for many sweeps per launch; byte layout, N <= 102400),
+     MICSA_KERNEL_MULTISPIN (MicSA with daemons, gamma = 1, Lx % 128 == 0:
+     multispin coding, Sec. 2.5 -- a sweep call packs the state into bit
+     planes of 64 sites per word, sweeps there with one launch per half
+     sweep and the refresh fused in, and unpacks it at the end; the other
+     algorithms keep the fused path).
    MICSA_OPT_TILE_Y / MICSA_OPT_TILE_Z: rows / planes per work-group of the
      fused sweep (0 = automatic; must divide Ly / Lz).
    MICSA_OPT_XCD_MAP: 1 (default) assigns neighbouring tiles of the fused
@@ -235,7 +240,8 @@ enum micsa_kernel_choice {
     MICSA_KERNEL_AUTO = 0,    /* resident if the lattice fits, else fused if Lx >= 128, else simple */
     MICSA_KERNEL_SIMPLE = 1,  /* one launch per half sweep */
     MICSA_KERNEL_FUSED = 2,   /* one launch per sweep, refresh fused in (Lx % 32 == 0) */
-    MICSA_KERNEL_RESIDENT = 3 /* one work-group per lattice keeps it in LDS for many sweeps (<= 102400 sites) */
+    MICSA_KERNEL_RESIDENT = 3, /* one work-group per lattice keeps it in LDS for many sweeps (<= 102400 sites) */
+    MICSA_KERNEL_MULTISPIN = 4 /* MicSA daemon sweeps on bit planes, 64 sites of a row per word (Lx % 128 == 0) */
 };
 int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value);
 

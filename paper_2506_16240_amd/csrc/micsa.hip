@@ -17,6 +17,7 @@
 #include "bitplane_kernels.hpp"
 #include "fused_kernels.hpp"
 #include "fused2_kernels.hpp"
+#include "msc_kernels.hpp"
 #include "observables.hpp"
 #include "resident_kernels.hpp"
 #include "micsa.h"
@@ -61,6 +62,11 @@ struct micsa_ctx {
     uint64_t* bdm0 = nullptr;   // [G][R][2][Nh]
     uint64_t* bdm1 = nullptr;   // [G][R][2][Nh]
     uint64_t* bJ = nullptr;     // [G][6][Nh]
+    // multispin working planes (msc_kernels.hpp), allocated on first use
+    uint64_t* ms = nullptr;   // [L][2][rows][Lx/128] spins
+    uint64_t* md0 = nullptr;  // daemon level bit 0, same shape
+    uint64_t* md1 = nullptr;  // daemon level bit 1
+    uint64_t* mb = nullptr;   // [L][6][rows][Lx/128] couplings of the even sites
     // sweep kernel selection (MICSA_OPT_*)
     int32_t kernel_opt = MICSA_KERNEL_AUTO;
     int32_t tile_y = 0, tile_z = 0;
@@ -320,6 +326,10 @@ bool fused_eligible(const micsa_ctx* c)
 {
     return !c->bit && c->gamma == 1 && c->p.Lx % 32 == 0 && 5 * (c->p.Lx / 32) <= 1024;
 }
+
+bool msc_eligible(const micsa_ctx* c) { return !c->bit && c->gamma == 1 && c->p.Lx % 128 == 0; }
+
+bool use_msc(const micsa_ctx* c) { return c->kernel_opt == MICSA_KERNEL_MULTISPIN && msc_eligible(c); }
 
 bool use_fused(const micsa_ctx* c)
 {
@@ -727,6 +737,71 @@ int launch_wander(micsa_ctx* c, int64_t t)
     return MICSA_OK;
 }
 
+// MicSA daemon sweeps k .. k + n - 1 on multispin planes: pack the byte
+// state, one launch per half sweep (refresh fused into the refreshing
+// sweep's halves), unpack.
+int sweep_msc(micsa_ctx* c, int64_t n)
+{
+    MscGeom m;
+    m.W = c->p.Lx / 128;
+    m.R = c->g.rows;
+    m.plane = (int64_t)m.R * m.W;
+    const size_t words = (size_t)c->L * 2 * (size_t)m.plane;
+    if (!c->ms) {
+        if (hipMalloc(&c->ms, words * 8) != hipSuccess || hipMalloc(&c->md0, words * 8) != hipSuccess ||
+            hipMalloc(&c->md1, words * 8) != hipSuccess || hipMalloc(&c->mb, words * 3 * 8) != hipSuccess) {
+            (void)hipGetLastError();
+            for (uint64_t** q : {&c->ms, &c->md0, &c->md1, &c->mb}) {
+                if (*q) (void)hipFree(*q);
+                *q = nullptr;
+            }
+            return fail(c, MICSA_ENOMEM, "multispin planes");
+        }
+    }
+    const dim3 cgrid((unsigned)((2 * m.plane + 255) / 256), (unsigned)c->L);
+    {
+        TimedLaunch t(c, kTimeReduce);
+        k_msc_pack<<<cgrid, 256, 0, c->stream>>>(c->g, m, c->spin, c->dem, c->ms, c->md0, c->md1, c->mb);
+    }
+    int st = check_launch(c, "k_msc_pack");
+    if (st) return st;
+    const dim3 grid((unsigned)((m.plane + 255) / 256), (unsigned)c->L);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t k = c->k;
+        const bool refresh = is_refresh(k, c->sched.period);
+        const int64_t rho = refresh_index(k, c->sched.period);
+        const double T = temperature(c->sched, rho);
+        if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
+        const DaemonThresholds th = refresh ? daemon_thresholds(T) : DaemonThresholds{0, 0, 0};
+        {
+            TimedLaunch t(c, kTimeSweep);
+            if (refresh)
+                k_msc_half<0, true><<<grid, 256, 0, c->stream>>>(c->g, m, c->ms, c->md0, c->md1, c->mb, c->tally,
+                                                                (uint32_t)rho, th);
+            else
+                k_msc_half<0, false><<<grid, 256, 0, c->stream>>>(c->g, m, c->ms, c->md0, c->md1, c->mb, c->tally,
+                                                                 (uint32_t)rho, th);
+        }
+        if ((st = check_launch(c, "k_msc_half<0>"))) return st;
+        {
+            TimedLaunch t(c, kTimeSweep);
+            if (refresh)
+                k_msc_half<1, true><<<grid, 256, 0, c->stream>>>(c->g, m, c->ms, c->md0, c->md1, c->mb, c->tally,
+                                                                (uint32_t)rho, th);
+            else
+                k_msc_half<1, false><<<grid, 256, 0, c->stream>>>(c->g, m, c->ms, c->md0, c->md1, c->mb, c->tally,
+                                                                 (uint32_t)rho, th);
+        }
+        if ((st = check_launch(c, "k_msc_half<1>"))) return st;
+        c->k = k + 1;
+    }
+    {
+        TimedLaunch t(c, kTimeReduce);
+        k_msc_unpack<<<cgrid, 256, 0, c->stream>>>(c->g, m, c->ms, c->md0, c->md1, c->mb, c->spin, c->dem);
+    }
+    return check_launch(c, "k_msc_unpack");
+}
+
 // Apply a wandering the daemons still owe (walkers on the fused sweep).
 int settle_wander(micsa_ctx* c)
 {
@@ -745,6 +820,7 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
     // next sweep's loads; every other path needs the daemons in place
     const bool walk_fused = algo == MICSA_ALGO_WALKERS && !c->bit && c->gamma == 1 && use_fused(c);
     if (!walk_fused && (st0 = settle_wander(c))) return st0;
+    if (algo == MICSA_ALGO_MICSA && use_msc(c)) return n > 0 ? sweep_msc(c, n) : MICSA_OK;
     if (algo != MICSA_ALGO_WALKERS) {
         if (use_resident(c)) return launch_resident(c, algo, n, nullptr, 0);
         if (use_graph(c) && n >= kGraphSweeps) return sweep_graph(c, algo, n);
@@ -815,6 +891,8 @@ void free_all(micsa_ctx* c)
     if (c->spin_alt) (void)hipFree(c->spin_alt);
     if (c->dem_alt) (void)hipFree(c->dem_alt);
     if (c->bspin) (void)hipFree(c->bspin);
+    for (uint64_t* q : {c->ms, c->md0, c->md1, c->mb})
+        if (q) (void)hipFree(q);
     if (c->bdm0) (void)hipFree(c->bdm0);
     if (c->bdm1) (void)hipFree(c->bdm1);
     if (c->bJ) (void)hipFree(c->bJ);
@@ -1519,6 +1597,7 @@ int micsa_get_timing(micsa_ctx* ctx, int32_t kind, double* total_ms, int64_t* la
 const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
 {
     if (ctx && ctx->bit) return algo == MICSA_ALGO_MICSA ? "kb_micsa_half" : "";
+    if (ctx && algo == MICSA_ALGO_MICSA && use_msc(ctx)) return "k_msc_half";
     // walkers on the fused sweep wander on the next sweep's loads
     if (algo == MICSA_ALGO_WALKERS)
         return ctx && use_fused(ctx) && ctx->gamma == 1
@@ -1542,8 +1621,10 @@ int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value)
     switch (option) {
     case MICSA_OPT_SWEEP_KERNEL:
         if (value != MICSA_KERNEL_AUTO && value != MICSA_KERNEL_SIMPLE && value != MICSA_KERNEL_FUSED &&
-            value != MICSA_KERNEL_RESIDENT)
+            value != MICSA_KERNEL_RESIDENT && value != MICSA_KERNEL_MULTISPIN)
             return fail(ctx, MICSA_EINVAL, "unknown sweep kernel");
+        if (value == MICSA_KERNEL_MULTISPIN && !msc_eligible(ctx))
+            return fail(ctx, MICSA_EINVAL, "the multispin sweep needs the byte layout, gamma = 1 and Lx % 128 == 0");
         if (value == MICSA_KERNEL_RESIDENT && !resident_eligible(ctx))
             return fail(ctx, MICSA_EINVAL, "the resident sweep needs a byte-layout lattice of at most 102400 sites");
         if (value == MICSA_KERNEL_FUSED && !fused_eligible(ctx))

@@ -168,16 +168,18 @@ def test_batched_L32_shape():
     same_state(g, o)
 
 
-@pytest.mark.parametrize("prefetch,temporal", [(1, 2), (2, 1)])
-def test_anneal_L512_first_sweeps_full_size(prefetch, temporal):
+@pytest.mark.parametrize("prefetch,temporal,kernel", [(1, 2, M.KERNEL_AUTO), (2, 1, M.KERNEL_AUTO),
+                                                      (1, 2, M.KERNEL_MULTISPIN)])
+def test_anneal_L512_first_sweeps_full_size(prefetch, temporal, kernel):
     """L = 512 (134M spins), linear 3.0 -> 0.2 over 10^4 sweeps, refresh every 20:
     the first 21 sweeps (two refreshes) bit-exact at full size, with the
     fused sweep's benchmark tile, two sweeps per pass (logging every 7
     sweeps: pairs and a single sweep per call) and one sweep per pass at
-    both prefetch depths."""
+    both prefetch depths, and on the multispin planes."""
     w = W.ANNEAL_L512
     n = 21
     g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
+    g.set_option(M.OPT_SWEEP_KERNEL, kernel)
     g.set_option(M.OPT_TILE_Y, 32)
     g.set_option(M.OPT_TILE_Z, 32)
     g.set_option(M.OPT_PREFETCH, prefetch)
@@ -306,6 +308,42 @@ def test_walkers_fused_wander_on_load(shape, prefetch, temporal):
     o.run(O.ALGO_MICSA, os_, 7)
     same_state(g, o)
     assert np.array_equal(g.energy_tally(), o.energy())
+
+
+MSC_SHAPES = [(128, 4, 4, 1, 1), (128, 2, 2, 1, 1), (128, 6, 2, 2, 3), (384, 4, 6, 1, 2), (256, 8, 6, 2, 1)]
+
+
+@pytest.mark.parametrize("shape", MSC_SHAPES)
+def test_multispin_matches_oracle(shape):
+    """Multispin coding (Sec. 2.5): 64 sites of a row per word, the Creutz
+    move bit-sliced, the refresh drawn inside the half-sweep kernels.  Every
+    logged energy (one pack/unpack per sweep), then a long call (one pack,
+    many sweeps, one unpack), against the oracle; minimum sides, several
+    samples and replicas, three words per row."""
+    g, o = pair(*shape, seed=0x77AA)
+    g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_MULTISPIN)
+    assert g.kernel_name(M.ALGO_MICSA) == "k_msc_half"
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.4, 0.3, 60, 3)
+    g.set_schedule(gs)
+    Eg, Dg = g.sweep_logged(M.ALGO_MICSA, 9, 1)
+    Eo, Do = o.run(O.ALGO_MICSA, os_, 9, 1)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    same_state(g, o)
+    g.sweep(M.ALGO_MICSA, 31)
+    o.run(O.ALGO_MICSA, os_, 31)
+    same_state(g, o)
+    assert np.array_equal(g.energy_tally(), o.energy())
+    assert np.array_equal(g.couplings(), o.J)
+    # the other algorithms keep the fused path on the same context
+    g.sweep(M.ALGO_HEATBATH, 3)
+    o.run(O.ALGO_HEATBATH, os_, 3)
+    same_state(g, o)
+
+
+def test_multispin_refused_where_it_does_not_apply():
+    g, _ = pair(96, 4, 4)
+    with pytest.raises(M.MicsaError):
+        g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_MULTISPIN)
 
 
 def test_gpu_error_paths():
