@@ -334,8 +334,12 @@ def main() -> int:
 
     layout = 1 if args.layout == "bitplane" else 0
     fused = layout == 0 and w.Lx % 32 == 0 and w.Lx >= 128
+    # MicSA on the multispin planes (the library's choice for long calls on
+    # lattices with Lx % 128 == 0) has no tile to tune
+    multispin = (layout == 0 and args.kernel in ("auto", "multispin") and w.Lx % 128 == 0 and args.gamma == 1
+                 and args.algo == "micsa" and w.N * 3 > 150 * 1024 * 2)
     tile = None
-    if args.tile == "tune" and fused:
+    if args.tile == "tune" and fused and not multispin:
         from paper_2506_16240_amd import tune
         log("tuning fused-sweep tiles")
         best = tune.tune(w.Lx, w.Ly, w.Lz, w.S, w.R, use_cache=False)

@@ -237,7 +237,8 @@ enum micsa_option {
     MICSA_OPT_TEMPORAL = 7
 };
 enum micsa_kernel_choice {
-    MICSA_KERNEL_AUTO = 0,    /* resident if the lattice fits, else fused if Lx >= 128, else simple */
+    MICSA_KERNEL_AUTO = 0,    /* resident if the lattice fits; else, for MicSA calls of >= 8 sweeps, multispin
+                                 if Lx % 128 == 0; else fused if Lx >= 128, else simple */
     MICSA_KERNEL_SIMPLE = 1,  /* one launch per half sweep */
     MICSA_KERNEL_FUSED = 2,   /* one launch per sweep, refresh fused in (Lx % 32 == 0) */
     MICSA_KERNEL_RESIDENT = 3, /* one work-group per lattice keeps it in LDS for many sweeps (<= 102400 sites) */

@@ -329,7 +329,17 @@ bool fused_eligible(const micsa_ctx* c)
 
 bool msc_eligible(const micsa_ctx* c) { return !c->bit && c->gamma == 1 && c->p.Lx % 128 == 0; }
 
-bool use_msc(const micsa_ctx* c) { return c->kernel_opt == MICSA_KERNEL_MULTISPIN && msc_eligible(c); }
+// AUTO takes the multispin planes for MicSA calls of at least kMscMinSweeps
+// sweeps on lattices the resident kernel does not hold (a call packs and
+// unpacks the state once, about the traffic of two sweeps).
+constexpr int64_t kMscMinSweeps = 8;
+
+bool use_msc(const micsa_ctx* c, int64_t n = kMscMinSweeps)
+{
+    if (!msc_eligible(c)) return false;
+    if (c->kernel_opt == MICSA_KERNEL_MULTISPIN) return true;
+    return c->kernel_opt == MICSA_KERNEL_AUTO && !use_resident(c) && n >= kMscMinSweeps;
+}
 
 bool use_fused(const micsa_ctx* c)
 {
@@ -820,7 +830,7 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
     // next sweep's loads; every other path needs the daemons in place
     const bool walk_fused = algo == MICSA_ALGO_WALKERS && !c->bit && c->gamma == 1 && use_fused(c);
     if (!walk_fused && (st0 = settle_wander(c))) return st0;
-    if (algo == MICSA_ALGO_MICSA && use_msc(c)) return n > 0 ? sweep_msc(c, n) : MICSA_OK;
+    if (algo == MICSA_ALGO_MICSA && use_msc(c, n)) return n > 0 ? sweep_msc(c, n) : MICSA_OK;
     if (algo != MICSA_ALGO_WALKERS) {
         if (use_resident(c)) return launch_resident(c, algo, n, nullptr, 0);
         if (use_graph(c) && n >= kGraphSweeps) return sweep_graph(c, algo, n);
