@@ -223,6 +223,8 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      2 (default) runs sweeps k and k + 1 in one launch wherever a call
      sweeps at least two (the state is read and written once per pair); 1
      runs one sweep per launch.  Results are identical.
+   MICSA_OPT_MSC_FUSED: the multispin sweep in one launch per sweep marching
+     along z (1, default) or one launch per half sweep (0).
    MICSA_OPT_PREFETCH: steps of global loads in flight in the fused MicSA
      sweep, 1 (default) or 2 (used for work-groups of at most 640 lanes,
      i.e. (tile_y + 4) * Lx / 32 <= 640; larger tiles run with 1).
@@ -234,7 +236,8 @@ enum micsa_option {
     MICSA_OPT_XCD_MAP = 4,
     MICSA_OPT_GRAPHS = 5,
     MICSA_OPT_PREFETCH = 6,
-    MICSA_OPT_TEMPORAL = 7
+    MICSA_OPT_TEMPORAL = 7,
+    MICSA_OPT_MSC_FUSED = 8
 };
 enum micsa_kernel_choice {
     MICSA_KERNEL_AUTO = 0,    /* resident if the lattice fits; else, for MicSA calls of >= 8 sweeps, multispin

@@ -67,6 +67,8 @@ struct micsa_ctx {
     uint64_t* md0 = nullptr;  // daemon level bit 0, same shape
     uint64_t* md1 = nullptr;  // daemon level bit 1
     uint64_t* mb = nullptr;   // [L][6][rows][Lx/128] couplings of the even sites
+    uint64_t *ms_alt = nullptr, *md0_alt = nullptr, *md1_alt = nullptr;  // written by the one-launch sweep
+    int32_t msc_fused = 1;  // multispin: 1 = one launch per sweep (z march), 0 = one per half sweep
     // sweep kernel selection (MICSA_OPT_*)
     int32_t kernel_opt = MICSA_KERNEL_AUTO;
     int32_t tile_y = 0, tile_z = 0;
@@ -747,6 +749,21 @@ int launch_wander(micsa_ctx* c, int64_t t)
     return MICSA_OK;
 }
 
+// Tile of the one-launch multispin sweep: TY rows x TZ planes per work-group
+// ((TY + 4) Lx / 128 lanes); the tile options apply where they divide.
+MscTile msc_tile(const micsa_ctx* c)
+{
+    const int W = c->p.Lx / 128;
+    MscTile f{};
+    f.TY = c->tile_y ? c->tile_y : divisor_at_most(c->p.Ly, std::max(1, 256 / W - 4));
+    f.TZ = c->tile_z ? c->tile_z : divisor_at_most(c->p.Lz, 8);
+    f.nty = c->p.Ly / f.TY;
+    f.ntz = c->p.Lz / f.TZ;
+    return f;
+}
+
+bool msc_one_launch(const micsa_ctx* c) { return c->msc_fused && (msc_tile(c).TY + 4) * (c->p.Lx / 128) <= 1024; }
+
 // MicSA daemon sweeps k .. k + n - 1 on multispin planes: pack the byte
 // state, one launch per half sweep (refresh fused into the refreshing
 // sweep's halves), unpack.
@@ -757,11 +774,20 @@ int sweep_msc(micsa_ctx* c, int64_t n)
     m.R = c->g.rows;
     m.plane = (int64_t)m.R * m.W;
     const size_t words = (size_t)c->L * 2 * (size_t)m.plane;
-    if (!c->ms) {
-        if (hipMalloc(&c->ms, words * 8) != hipSuccess || hipMalloc(&c->md0, words * 8) != hipSuccess ||
-            hipMalloc(&c->md1, words * 8) != hipSuccess || hipMalloc(&c->mb, words * 3 * 8) != hipSuccess) {
+    const MscTile f = msc_tile(c);
+    const int lanes = (f.TY + 4) * m.W;
+    const bool one = msc_one_launch(c);
+    if (!c->ms || (one && !c->ms_alt)) {
+        bool ok = true;
+        for (uint64_t** q : {&c->ms, &c->md0, &c->md1})
+            if (!*q) ok = ok && hipMalloc(q, words * 8) == hipSuccess;
+        if (ok && !c->mb) ok = hipMalloc(&c->mb, words * 3 * 8) == hipSuccess;
+        if (ok && one)
+            for (uint64_t** q : {&c->ms_alt, &c->md0_alt, &c->md1_alt})
+                if (!*q) ok = ok && hipMalloc(q, words * 8) == hipSuccess;
+        if (!ok) {
             (void)hipGetLastError();
-            for (uint64_t** q : {&c->ms, &c->md0, &c->md1, &c->mb}) {
+            for (uint64_t** q : {&c->ms, &c->md0, &c->md1, &c->mb, &c->ms_alt, &c->md0_alt, &c->md1_alt}) {
                 if (*q) (void)hipFree(*q);
                 *q = nullptr;
             }
@@ -776,6 +802,9 @@ int sweep_msc(micsa_ctx* c, int64_t n)
     int st = check_launch(c, "k_msc_pack");
     if (st) return st;
     const dim3 grid((unsigned)((m.plane + 255) / 256), (unsigned)c->L);
+    const dim3 sgrid((unsigned)(f.nty * f.ntz), (unsigned)c->L);
+    const unsigned sblock = (unsigned)((lanes + 63) / 64 * 64);
+    const size_t slds = (size_t)96 * lanes;  // 6 planes x 2 step buffers x 8 B per lane
     for (int64_t i = 0; i < n; ++i) {
         const int64_t k = c->k;
         const bool refresh = is_refresh(k, c->sched.period);
@@ -783,6 +812,20 @@ int sweep_msc(micsa_ctx* c, int64_t n)
         const double T = temperature(c->sched, rho);
         if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
         const DaemonThresholds th = refresh ? daemon_thresholds(T) : DaemonThresholds{0, 0, 0};
+        if (one) {
+            {
+                TimedLaunch t(c, kTimeSweep);
+                const auto kern = refresh ? k_msc_sweep<true> : k_msc_sweep<false>;
+                kern<<<sgrid, sblock, slds, c->stream>>>(c->g, m, f, c->ms, c->md0, c->md1, c->mb, c->ms_alt,
+                                                         c->md0_alt, c->md1_alt, c->tally, (uint32_t)rho, th);
+            }
+            if ((st = check_launch(c, "k_msc_sweep"))) return st;
+            std::swap(c->ms, c->ms_alt);
+            std::swap(c->md0, c->md0_alt);
+            std::swap(c->md1, c->md1_alt);
+            c->k = k + 1;
+            continue;
+        }
         {
             TimedLaunch t(c, kTimeSweep);
             if (refresh)
@@ -901,7 +944,7 @@ void free_all(micsa_ctx* c)
     if (c->spin_alt) (void)hipFree(c->spin_alt);
     if (c->dem_alt) (void)hipFree(c->dem_alt);
     if (c->bspin) (void)hipFree(c->bspin);
-    for (uint64_t* q : {c->ms, c->md0, c->md1, c->mb})
+    for (uint64_t* q : {c->ms, c->md0, c->md1, c->mb, c->ms_alt, c->md0_alt, c->md1_alt})
         if (q) (void)hipFree(q);
     if (c->bdm0) (void)hipFree(c->bdm0);
     if (c->bdm1) (void)hipFree(c->bdm1);
@@ -1607,7 +1650,8 @@ int micsa_get_timing(micsa_ctx* ctx, int32_t kind, double* total_ms, int64_t* la
 const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
 {
     if (ctx && ctx->bit) return algo == MICSA_ALGO_MICSA ? "kb_micsa_half" : "";
-    if (ctx && algo == MICSA_ALGO_MICSA && use_msc(ctx)) return "k_msc_half";
+    if (ctx && algo == MICSA_ALGO_MICSA && use_msc(ctx))
+        return msc_one_launch(ctx) ? "k_msc_sweep" : "k_msc_half";
     // walkers on the fused sweep wander on the next sweep's loads
     if (algo == MICSA_ALGO_WALKERS)
         return ctx && use_fused(ctx) && ctx->gamma == 1
@@ -1649,6 +1693,10 @@ int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value)
     case MICSA_OPT_GRAPHS:
         if (value != 0 && value != 1) return fail(ctx, MICSA_EINVAL, "graphs is 0 or 1");
         ctx->use_graphs = (int32_t)value;
+        return MICSA_OK;
+    case MICSA_OPT_MSC_FUSED:
+        if (value != 0 && value != 1) return fail(ctx, MICSA_EINVAL, "msc_fused is 0 or 1");
+        ctx->msc_fused = (int32_t)value;
         return MICSA_OK;
     case MICSA_OPT_TEMPORAL:
         if (value != 1 && value != 2) return fail(ctx, MICSA_EINVAL, "temporal is 1 or 2");

@@ -150,6 +150,236 @@ __global__ __launch_bounds__(256) void k_msc_half(Geom g, MscGeom m, uint64_t* _
     block_add(tally + (int64_t)l * kSlots, dE);
 }
 
+// Daemon levels of both parities' words w of a row at a refresh: the Philox
+// call of sites x = 4a .. 4a + 3 serves even sites k = 2a, 2a + 1 (words i & 3
+// = q, 2 + q, q = x offset of the row's even sites) and odd sites k = 2a,
+// 2a + 1 (words 1 - q, 3 - q) of the same word index.
+__device__ __forceinline__ void msc_draw2(const Geom& g, int row, int w, int q, uint32_t rho, uint32_t r,
+                                          uint32_t sw, const DaemonThresholds& th, uint64_t& e0, uint64_t& e1,
+                                          uint64_t& o0, uint64_t& o1)
+{
+    e0 = e1 = o0 = o1 = 0;
+    const uint32_t base = (uint32_t)(((int64_t)g.Lx * row) >> 2);
+#pragma unroll 2
+    for (int b = 0; b < 64; b += 2) {
+        const u32x4 v = philox10(base + (uint32_t)((64 * w + b) >> 1), rho, r, sw, g.key0, g.key1);
+        const uint32_t ea = daemon_level(q ? v.v1 : v.v0, th), eb = daemon_level(q ? v.v3 : v.v2, th);
+        const uint32_t oa = daemon_level(q ? v.v0 : v.v1, th), ob = daemon_level(q ? v.v2 : v.v3, th);
+        e0 |= (uint64_t)((ea & 1u) | ((eb & 1u) << 1)) << b;
+        e1 |= (uint64_t)((ea >> 1) | ((eb >> 1) << 1)) << b;
+        o0 |= (uint64_t)((oa & 1u) | ((ob & 1u) << 1)) << b;
+        o1 |= (uint64_t)((oa >> 1) | ((ob >> 1) << 1)) << b;
+    }
+}
+
+// The Creutz move on a word: s the spins, six neighbour and coupling words
+// per direction (nb ^ j), m0/m1 the levels (updated); returns the new spins
+// and adds the level sums before/after to so/sn.
+__device__ __forceinline__ uint64_t msc_move(uint64_t s, uint64_t a, uint64_t b, uint64_t c, uint64_t d, uint64_t e,
+                                             uint64_t f, uint64_t& m0, uint64_t& m1, long long& so, long long& sn)
+{
+    a ^= s;
+    b ^= s;
+    c ^= s;
+    d ^= s;
+    e ^= s;
+    f ^= s;
+    const uint64_t s1 = a ^ b ^ c, c1 = maj3(a, b, c);
+    const uint64_t s2 = d ^ e ^ f, c2 = maj3(d, e, f);
+    const uint64_t u0 = s1 ^ s2, k0 = s1 & s2;
+    const uint64_t u1 = c1 ^ c2 ^ k0, u2 = maj3(c1, c2, k0);
+    const uint64_t w0 = m0 ^ u0, cw0 = m0 & u0;
+    const uint64_t w1 = m1 ^ u1 ^ cw0, cw1 = maj3(m1, u1, cw0);
+    const uint64_t w2 = u2 ^ cw1, w3 = u2 & cw1;
+    const uint64_t acc = ~w3 & (w2 ^ (w1 & w0));
+    const uint64_t n0 = (acc & ~w0) | (~acc & m0);
+    const uint64_t n1 = (acc & (w2 & (w1 | w0))) | (~acc & m1);
+    so += (long long)__popcll(m0) + 2ll * __popcll(m1);
+    sn += (long long)__popcll(n0) + 2ll * __popcll(n1);
+    m0 = n0;
+    m1 = n1;
+    return s ^ acc;
+}
+
+struct MscTile {
+    int32_t TY, TZ;  // rows (divides Ly) and planes (divides Lz) a work-group owns
+    int32_t nty, ntz;
+};
+
+// One whole sweep per launch (both halves), marching along z like the byte
+// layout's fused sweep: at step st, with z = zstart + dz st, the even half
+// on plane z and the odd half on plane z - dz, whose even neighbours (planes
+// z - 2dz .. z) are then all final.  A work-group owns TY rows x TZ planes of
+// one lattice, all words of a row; the even half also runs on one ring of
+// rows and planes and odd spins are read on two rings, so no tile needs
+// another tile's new values (state read from the "in" planes, written to the
+// "out" planes).  Lanes: (TY + 4) rows x W words; in-plane neighbours (rows
+// y +- 1, the x carry from words w +- 1) come through LDS, one buffer per
+// step parity (old odd spins, new even spins and the even sites' x and y
+// couplings of plane z); z neighbours through registers.  Each coupling
+// word is read once per sweep.  On refresh sweeps the even half draws both
+// parities' levels of its word and keeps the odd ones for the next step.
+// Grid (nty * ntz, L); block 64 ceil((TY + 4) W / 64); LDS 96 (TY + 4) W bytes.
+template <bool REFRESH>
+__global__ __launch_bounds__(1024) void k_msc_sweep(Geom g, MscGeom m, MscTile f,
+                                                    const uint64_t* __restrict__ spin_in,
+                                                    const uint64_t* __restrict__ d0_in,
+                                                    const uint64_t* __restrict__ d1_in,
+                                                    const uint64_t* __restrict__ bond, uint64_t* __restrict__ spin_out,
+                                                    uint64_t* __restrict__ d0_out, uint64_t* __restrict__ d1_out,
+                                                    unsigned long long* __restrict__ tally, uint32_t rho,
+                                                    DaemonThresholds th)
+{
+    extern __shared__ uint64_t lds64[];
+    const int W = m.W;
+    const int rows_slots = f.TY + 4;
+    const int ps = rows_slots * W;
+    auto LP = [&](int buf, int k) { return lds64 + ((size_t)buf * 6 + k) * ps; };  // 0 odd, 1 even, 2 Mx, 3 Px, 4 My, 5 Py
+
+    const int l = blockIdx.y;
+    const int ty = blockIdx.x / f.ntz, tz = blockIdx.x - (blockIdx.x / f.ntz) * f.ntz;
+    const int y0 = ty * f.TY, z0 = tz * f.TZ;
+    const int dz = (tz & 1) ? -1 : 1;
+    const int zstart = dz > 0 ? z0 - 1 : z0 + f.TZ;
+    const int ry = threadIdx.x / W, w = threadIdx.x - (threadIdx.x / W) * W;
+    const bool active = ry < rows_slots;
+    auto wrap = [](int v, int L) { v %= L; return v < 0 ? v + L : v; };
+    const int y = wrap(y0 - 2 + ry, g.Ly);
+    const bool do_even = active && ry >= 1 && ry <= f.TY + 2;
+    const bool do_odd = active && ry >= 2 && ry <= f.TY + 1;  // the rows the tile owns
+    const int wn = w + 1 == W ? 0 : w + 1, wp = w == 0 ? W - 1 : w - 1;
+    const int me = ry * W + w;
+
+    const uint64_t* ev_in = spin_in + ((int64_t)l * 2 + 0) * m.plane;
+    const uint64_t* od_in = spin_in + ((int64_t)l * 2 + 1) * m.plane;
+    const uint64_t* bl = bond + (int64_t)l * 6 * m.plane;
+    auto widx = [&](int zz) { return ((int64_t)y + (int64_t)g.Ly * zz) * W + w; };
+    const uint32_t rr = (uint32_t)(l % g.R), sw = stream_word(kStreamDaemon, (uint32_t)(l / g.R));
+    const int steps = f.TZ + 2;
+
+    uint64_t O_prev = 0, O_cur = 0, O_next = 0;  // old odd spins at z - dz, z, z + dz
+    uint64_t E0 = 0, E1 = 0, E2 = 0;             // new even spins at z, z - dz, z - 2dz
+    uint64_t MZ0 = 0, MZ1 = 0, MZ2 = 0;          // even couplings -z at z, z - dz, z - 2dz
+    uint64_t PZ0 = 0, PZ1 = 0, PZ2 = 0;          // even couplings +z at the same planes
+    uint64_t Go0 = 0, Go1 = 0;                   // REFRESH: drawn odd levels of plane z - dz
+    if (active) {
+        O_prev = od_in[widx(wrap(zstart - dz, g.Lz))];
+        O_cur = od_in[widx(wrap(zstart, g.Lz))];
+    }
+    // loads of step st are issued during step st - 1 (one step in flight)
+    uint64_t nO = 0, nEs = 0, nJ[6] = {0, 0, 0, 0, 0, 0}, nme0 = 0, nme1 = 0, nmo0 = 0, nmo1 = 0;
+    auto load = [&](int st2) {
+        const int zz2 = zstart + dz * st2;
+        const int z2 = wrap(zz2, g.Lz);
+        if (active) nO = od_in[widx(wrap(zz2 + dz, g.Lz))];
+        if (do_even) {
+            const int64_t h = widx(z2);
+            nEs = ev_in[h];
+#pragma unroll
+            for (int d = 0; d < 6; ++d) nJ[d] = bl[(int64_t)d * m.plane + h];
+            if (!REFRESH) {
+                nme0 = d0_in[((int64_t)l * 2 + 0) * m.plane + h];
+                nme1 = d1_in[((int64_t)l * 2 + 0) * m.plane + h];
+            }
+        }
+        if (!REFRESH && do_odd && st2 >= 2) {
+            const int64_t ho = ((int64_t)l * 2 + 1) * m.plane + widx(wrap(zz2 - dz, g.Lz));
+            nmo0 = d0_in[ho];
+            nmo1 = d1_in[ho];
+        }
+    };
+    load(0);
+    long long so = 0, sn = 0;
+    for (int st = 0; st < steps; ++st) {
+        const int buf = st & 1, pb = buf ^ 1;
+        const int zz = zstart + dz * st;  // unwrapped: owned iff in [z0, z0 + TZ)
+        const int z = wrap(zz, g.Lz), zo = wrap(zz - dz, g.Lz);
+        const bool own_e = zz >= z0 && zz < z0 + f.TZ, own_o = zz - dz >= z0 && zz - dz < z0 + f.TZ;
+        const bool odd_now = do_odd && st >= 2;
+        O_next = nO;
+        uint64_t Es = nEs, J[6], me0 = nme0, me1 = nme1, mo0 = nmo0, mo1 = nmo1, Gn0 = 0, Gn1 = 0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) J[d] = nJ[d];
+        if (st + 1 < steps) load(st + 1);
+        if (do_even) {
+            if (REFRESH) msc_draw2(g, y + g.Ly * z, w, (y + z) & 1, rho, rr, sw, th, me0, me1, Gn0, Gn1);
+            MZ0 = J[kMz];
+            PZ0 = J[kPz];
+        }
+        if (REFRESH && odd_now) {
+            mo0 = Go0;
+            mo1 = Go1;
+        }
+        // buffer buf was last read as the previous buffer by step st - 1's odd
+        // half: the odd spins go in before this step's barrier (their readers
+        // are this step's even half), everything step st + 1 reads after it
+        if (active) LP(buf, 0)[me] = O_cur;
+        __syncthreads();
+        if (do_even) {  // ---- even half on plane z (old odd neighbours)
+            LP(buf, 2)[me] = J[kMx];
+            LP(buf, 3)[me] = J[kPx];
+            LP(buf, 4)[me] = J[kMy];
+            LP(buf, 5)[me] = J[kPy];
+            const int q = (y + z) & 1;
+            const uint64_t* Op = LP(buf, 0);
+            const uint64_t nxp = q ? shift_next(O_cur, Op[ry * W + wn]) : O_cur;
+            const uint64_t nxm = q ? O_cur : shift_prev(O_cur, Op[ry * W + wp]);
+            const uint64_t nyp = Op[me + W], nym = Op[me - W];
+            const uint64_t nzp = dz > 0 ? O_next : O_prev, nzm = dz > 0 ? O_prev : O_next;
+            long long a = 0, b = 0;
+            E0 = msc_move(Es, nxp ^ J[kPx], nxm ^ J[kMx], nyp ^ J[kPy], nym ^ J[kMy], nzp ^ J[kPz], nzm ^ J[kMz],
+                          me0, me1, a, b);
+            LP(buf, 1)[me] = E0;
+            if (do_odd && own_e) {
+                const int64_t h = widx(z);
+                spin_out[((int64_t)l * 2 + 0) * m.plane + h] = E0;
+                d0_out[((int64_t)l * 2 + 0) * m.plane + h] = me0;
+                d1_out[((int64_t)l * 2 + 0) * m.plane + h] = me1;
+                so += a;
+                sn += b;
+            }
+        }
+        if (odd_now) {  // ---- odd half on plane zo = z - dz (new even neighbours)
+            const int q = (1 + y + zo) & 1;
+            const uint64_t* Ep = LP(pb, 1);
+            const uint64_t Ec = Ep[me];
+            const uint64_t nxp = q ? shift_next(Ec, Ep[ry * W + wn]) : Ec;
+            const uint64_t nxm = q ? Ec : shift_prev(Ec, Ep[ry * W + wp]);
+            const uint64_t nyp = Ep[me + W], nym = Ep[me - W];
+            const uint64_t nzp = dz > 0 ? E0 : E2, nzm = dz > 0 ? E2 : E0;
+            // an odd site's coupling in direction d is its even neighbour's in direction -d
+            const uint64_t* Mx = LP(pb, 2);
+            const uint64_t* Px = LP(pb, 3);
+            const uint64_t jxp = q ? shift_next(Mx[me], Mx[ry * W + wn]) : Mx[me];
+            const uint64_t jxm = q ? Px[me] : shift_prev(Px[me], Px[ry * W + wp]);
+            const uint64_t jyp = LP(pb, 4)[me + W], jym = LP(pb, 5)[me - W];
+            const uint64_t jzp = dz > 0 ? MZ0 : MZ2, jzm = dz > 0 ? PZ2 : PZ0;
+            long long a = 0, b = 0;
+            const uint64_t On = msc_move(O_prev, nxp ^ jxp, nxm ^ jxm, nyp ^ jyp, nym ^ jym, nzp ^ jzp, nzm ^ jzm,
+                                         mo0, mo1, a, b);
+            if (own_o) {
+                const int64_t ho = ((int64_t)l * 2 + 1) * m.plane + widx(zo);
+                spin_out[ho] = On;
+                d0_out[ho] = mo0;
+                d1_out[ho] = mo1;
+                so += a;
+                sn += b;
+            }
+        }
+        O_prev = O_cur;
+        O_cur = O_next;
+        E2 = E1;
+        E1 = E0;
+        MZ2 = MZ1;
+        MZ1 = MZ0;
+        PZ2 = PZ1;
+        PZ1 = PZ0;
+        Go0 = Gn0;
+        Go1 = Gn1;
+    }
+    block_add(tally + (int64_t)l * kSlots, 4 * (so - sn));
+}
+
 // Byte layout -> planes (and back): one thread per (lattice, parity, row,
 // word), 64 consecutive bytes of the parity array.  An even spin byte holds
 // the spin in bit 0 and the coupling of direction d in bit 1 + d.

@@ -310,19 +310,23 @@ def test_walkers_fused_wander_on_load(shape, prefetch, temporal):
     assert np.array_equal(g.energy_tally(), o.energy())
 
 
-MSC_SHAPES = [(128, 4, 4, 1, 1), (128, 2, 2, 1, 1), (128, 6, 2, 2, 3), (384, 4, 6, 1, 2), (256, 8, 6, 2, 1)]
+MSC_SHAPES = [(128, 4, 4, 1, 1), (128, 2, 2, 1, 1), (128, 6, 2, 2, 3), (384, 4, 6, 1, 2), (256, 8, 6, 2, 1),
+              (128, 70, 36, 1, 1)]  # several tiles along y and z
 
 
+@pytest.mark.parametrize("fused", [1, 0], ids=["one-launch", "per-half"])
 @pytest.mark.parametrize("shape", MSC_SHAPES)
-def test_multispin_matches_oracle(shape):
+def test_multispin_matches_oracle(shape, fused):
     """Multispin coding (Sec. 2.5): 64 sites of a row per word, the Creutz
-    move bit-sliced, the refresh drawn inside the half-sweep kernels.  Every
-    logged energy (one pack/unpack per sweep), then a long call (one pack,
-    many sweeps, one unpack), against the oracle; minimum sides, several
-    samples and replicas, three words per row."""
+    move bit-sliced, the refresh drawn in the kernels; one launch per sweep
+    marching along z (rings of rows and planes that wrap onto small sides)
+    or one per half sweep.  Every logged energy (one pack/unpack per sweep),
+    then a long call (one pack, many sweeps, one unpack), against the oracle;
+    minimum sides, several samples and replicas, three words per row."""
     g, o = pair(*shape, seed=0x77AA)
     g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_MULTISPIN)
-    assert g.kernel_name(M.ALGO_MICSA) == "k_msc_half"
+    g.set_option(M.OPT_MSC_FUSED, fused)
+    assert g.kernel_name(M.ALGO_MICSA) == ("k_msc_sweep" if fused else "k_msc_half")
     gs, os_ = scheds(M.SCHED_LINEAR, 2.4, 0.3, 60, 3)
     g.set_schedule(gs)
     Eg, Dg = g.sweep_logged(M.ALGO_MICSA, 9, 1)
