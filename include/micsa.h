@@ -206,9 +206,10 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      lattice in LDS for many sweeps per launch; byte layout, N <= 102400),
      MICSA_KERNEL_MULTISPIN (MicSA with daemons, gamma = 1, Lx % 128 == 0:
      multispin coding, Sec. 2.5 -- a sweep call packs the state into bit
-     planes of 64 sites per word, sweeps there with one launch per half
-     sweep and the refresh fused in, and unpacks it at the end; the other
-     algorithms keep the fused path).
+     planes of 64 sites per word, sweeps there with one launch per sweep
+     (or per half sweep, MICSA_OPT_MSC_FUSED) and the refresh fused in, and
+     unpacks it at the end; walkers (gamma = 1) run on the one-launch form
+     too; the heat bath and Metropolis keep the fused path).
    MICSA_OPT_TILE_Y / MICSA_OPT_TILE_Z: rows / planes per work-group of the
      fused sweep (0 = automatic; must divide Ly / Lz).
    MICSA_OPT_XCD_MAP: 1 (default) assigns neighbouring tiles of the fused

@@ -336,9 +336,12 @@ bool msc_eligible(const micsa_ctx* c) { return !c->bit && c->gamma == 1 && c->p.
 // unpacks the state once, about the traffic of two sweeps).
 constexpr int64_t kMscMinSweeps = 8;
 
-bool use_msc(const micsa_ctx* c, int64_t n = kMscMinSweeps)
+bool msc_one_launch(const micsa_ctx* c);
+
+bool use_msc(const micsa_ctx* c, int64_t n = kMscMinSweeps, int32_t algo = MICSA_ALGO_MICSA)
 {
     if (!msc_eligible(c)) return false;
+    if (algo == MICSA_ALGO_WALKERS && !msc_one_launch(c)) return false;  // walkers need the one-launch sweep
     if (c->kernel_opt == MICSA_KERNEL_MULTISPIN) return true;
     return c->kernel_opt == MICSA_KERNEL_AUTO && !use_resident(c) && n >= kMscMinSweeps;
 }
@@ -764,10 +767,12 @@ MscTile msc_tile(const micsa_ctx* c)
 
 bool msc_one_launch(const micsa_ctx* c) { return c->msc_fused && (msc_tile(c).TY + 4) * (c->p.Lx / 128) <= 1024; }
 
-// MicSA daemon sweeps k .. k + n - 1 on multispin planes: pack the byte
-// state, one launch per half sweep (refresh fused into the refreshing
-// sweep's halves), unpack.
-int sweep_msc(micsa_ctx* c, int64_t n)
+// MicSA sweeps k .. k + n - 1 on multispin planes: pack the byte state,
+// sweep (one launch per sweep marching along z, or one per half sweep; the
+// refresh drawn inside), unpack.  Walkers (one-launch only): each sweep
+// applies the previous timestep's wandering as it loads the levels; the last
+// one is left owed to the byte layout (pend_wander).
+int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
 {
     MscGeom m;
     m.W = c->p.Lx / 128;
@@ -817,12 +822,15 @@ int sweep_msc(micsa_ctx* c, int64_t n)
                 TimedLaunch t(c, kTimeSweep);
                 const auto kern = refresh ? k_msc_sweep<true> : k_msc_sweep<false>;
                 kern<<<sgrid, sblock, slds, c->stream>>>(c->g, m, f, c->ms, c->md0, c->md1, c->mb, c->ms_alt,
-                                                         c->md0_alt, c->md1_alt, c->tally, (uint32_t)rho, th);
+                                                         c->md0_alt, c->md1_alt, c->tally, (uint32_t)rho, th,
+                                                         refresh ? -1 : c->pend_wander);
             }
             if ((st = check_launch(c, "k_msc_sweep"))) return st;
             std::swap(c->ms, c->ms_alt);
             std::swap(c->md0, c->md0_alt);
             std::swap(c->md1, c->md1_alt);
+            // gamma = 1: sweep k is timestep k; walkers owe its wandering to the next load
+            c->pend_wander = walkers ? (int32_t)(k & 1) : -1;
             c->k = k + 1;
             continue;
         }
@@ -871,8 +879,14 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
     if (st0) return st0;
     // walkers (gamma = 1) on the fused sweep carry their wandering into the
     // next sweep's loads; every other path needs the daemons in place
+    const bool walk_msc = algo == MICSA_ALGO_WALKERS && use_msc(c, n, algo);
     const bool walk_fused = algo == MICSA_ALGO_WALKERS && !c->bit && c->gamma == 1 && use_fused(c);
-    if (!walk_fused && (st0 = settle_wander(c))) return st0;
+    // the one-launch multispin sweep takes an owed wandering on its loads
+    // (and leaves one), as the fused byte sweep does
+    if (!walk_fused && !walk_msc && !(algo == MICSA_ALGO_MICSA && use_msc(c, n) && msc_one_launch(c)) &&
+        (st0 = settle_wander(c)))
+        return st0;
+    if (walk_msc) return n > 0 ? sweep_msc(c, n, true) : MICSA_OK;
     if (algo == MICSA_ALGO_MICSA && use_msc(c, n)) return n > 0 ? sweep_msc(c, n) : MICSA_OK;
     if (algo != MICSA_ALGO_WALKERS) {
         if (use_resident(c)) return launch_resident(c, algo, n, nullptr, 0);
@@ -1652,7 +1666,8 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
     if (ctx && ctx->bit) return algo == MICSA_ALGO_MICSA ? "kb_micsa_half" : "";
     if (ctx && algo == MICSA_ALGO_MICSA && use_msc(ctx))
         return msc_one_launch(ctx) ? "k_msc_sweep" : "k_msc_half";
-    // walkers on the fused sweep wander on the next sweep's loads
+    // walkers on the fused sweeps wander on the next sweep's loads
+    if (ctx && algo == MICSA_ALGO_WALKERS && use_msc(ctx, kMscMinSweeps, algo)) return "k_msc_sweep";
     if (algo == MICSA_ALGO_WALKERS)
         return ctx && use_fused(ctx) && ctx->gamma == 1
                    ? (ctx->temporal == 2 && sweep2_walk_eligible(ctx) ? "k_micsa_sweep2_fused" : "k_micsa_sweep_fused")

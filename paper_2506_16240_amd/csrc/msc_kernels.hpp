@@ -228,7 +228,7 @@ __global__ __launch_bounds__(1024) void k_msc_sweep(Geom g, MscGeom m, MscTile f
                                                     const uint64_t* __restrict__ bond, uint64_t* __restrict__ spin_out,
                                                     uint64_t* __restrict__ d0_out, uint64_t* __restrict__ d1_out,
                                                     unsigned long long* __restrict__ tally, uint32_t rho,
-                                                    DaemonThresholds th)
+                                                    DaemonThresholds th, int wander)
 {
     extern __shared__ uint64_t lds64[];
     const int W = m.W;
@@ -266,6 +266,22 @@ __global__ __launch_bounds__(1024) void k_msc_sweep(Geom g, MscGeom m, MscTile f
         O_prev = od_in[widx(wrap(zstart - dz, g.Lz))];
         O_cur = od_in[widx(wrap(zstart, g.Lz))];
     }
+    // Walkers (Sec. 2.6): with wander = p >= 0 the input levels still owe the
+    // forward-X wandering of the sites of parity p (the previous timestep's);
+    // it is applied on load.  In a row whose even sites sit at x = 2k + q,
+    // even site k pairs with odd site k + q (p = 0), odd site k with even
+    // site k + 1 - q (p = 1): a shift by 0 or +-1 site across the two
+    // parities' planes, the carry from the neighbouring word.
+    auto load_shifted = [&](int64_t at, int sh, uint64_t& v0, uint64_t& v1) {
+        v0 = d0_in[at];
+        v1 = d1_in[at];
+        if (sh != 0) {
+            const int64_t an = at + (sh > 0 ? wn - w : wp - w);
+            const uint64_t c0 = d0_in[an], c1 = d1_in[an];
+            v0 = sh > 0 ? shift_next(v0, c0) : shift_prev(v0, c0);
+            v1 = sh > 0 ? shift_next(v1, c1) : shift_prev(v1, c1);
+        }
+    };
     // loads of step st are issued during step st - 1 (one step in flight)
     uint64_t nO = 0, nEs = 0, nJ[6] = {0, 0, 0, 0, 0, 0}, nme0 = 0, nme1 = 0, nmo0 = 0, nmo1 = 0;
     auto load = [&](int st2) {
@@ -278,14 +294,25 @@ __global__ __launch_bounds__(1024) void k_msc_sweep(Geom g, MscGeom m, MscTile f
 #pragma unroll
             for (int d = 0; d < 6; ++d) nJ[d] = bl[(int64_t)d * m.plane + h];
             if (!REFRESH) {
-                nme0 = d0_in[((int64_t)l * 2 + 0) * m.plane + h];
-                nme1 = d1_in[((int64_t)l * 2 + 0) * m.plane + h];
+                if (wander < 0) {
+                    nme0 = d0_in[((int64_t)l * 2 + 0) * m.plane + h];
+                    nme1 = d1_in[((int64_t)l * 2 + 0) * m.plane + h];
+                } else {  // the walkers' owed wandering: new even levels from the odd planes
+                    const int q = (y + z2) & 1;
+                    load_shifted(((int64_t)l * 2 + 1) * m.plane + widx(z2), wander == 0 ? q : q - 1, nme0, nme1);
+                }
             }
         }
         if (!REFRESH && do_odd && st2 >= 2) {
-            const int64_t ho = ((int64_t)l * 2 + 1) * m.plane + widx(wrap(zz2 - dz, g.Lz));
-            nmo0 = d0_in[ho];
-            nmo1 = d1_in[ho];
+            const int zo2 = wrap(zz2 - dz, g.Lz);
+            if (wander < 0) {
+                const int64_t ho = ((int64_t)l * 2 + 1) * m.plane + widx(zo2);
+                nmo0 = d0_in[ho];
+                nmo1 = d1_in[ho];
+            } else {  // new odd levels from the even planes
+                const int q = (y + zo2) & 1;
+                load_shifted(((int64_t)l * 2 + 0) * m.plane + widx(zo2), wander == 0 ? -q : 1 - q, nmo0, nmo1);
+            }
         }
     };
     load(0);

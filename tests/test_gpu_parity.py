@@ -344,6 +344,33 @@ def test_multispin_matches_oracle(shape, fused):
     same_state(g, o)
 
 
+@pytest.mark.parametrize("shape", [(128, 4, 4, 1, 1), (256, 6, 4, 1, 2), (384, 4, 6, 2, 1)])
+def test_multispin_walkers_match_oracle(shape):
+    """Walkers (gamma = 1, forward-X wandering after every timestep, Sec.
+    2.6) on the one-launch multispin sweep: each sweep applies the previous
+    timestep's wandering as it loads the levels (one or three words per
+    row), the last one is left owed to the byte state.  Calls of walkers
+    and daemons in turn, the daemons read back in between, single sweeps
+    and long calls, against the oracle."""
+    g, o = pair(*shape, seed=0x77AB)
+    g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_MULTISPIN)
+    assert g.kernel_name(M.ALGO_WALKERS) == "k_msc_sweep"
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.4, 0.3, 90, 7)
+    g.set_schedule(gs)
+    for algo, oalgo, n in ((M.ALGO_WALKERS, O.ALGO_WALKERS, 12), (M.ALGO_WALKERS, O.ALGO_WALKERS, 1),
+                           (M.ALGO_MICSA, O.ALGO_MICSA, 9), (M.ALGO_WALKERS, O.ALGO_WALKERS, 23)):
+        g.sweep(algo, n)
+        o.run(oalgo, os_, n)
+        same_state(g, o)
+    g.sweep(M.ALGO_WALKERS, 15)
+    o.run(O.ALGO_WALKERS, os_, 15)
+    g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)  # the owed wandering passes to the byte sweeps
+    g.sweep(M.ALGO_WALKERS, 5)
+    o.run(O.ALGO_WALKERS, os_, 5)
+    same_state(g, o)
+    assert np.array_equal(g.energy_tally(), o.energy())
+
+
 def test_multispin_refused_where_it_does_not_apply():
     g, _ = pair(96, 4, 4)
     with pytest.raises(M.MicsaError):
