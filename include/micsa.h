@@ -228,7 +228,16 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      along z (1, default) or one launch per half sweep (0).
    MICSA_OPT_PREFETCH: steps of global loads in flight in the fused MicSA
      sweep, 1 (default) or 2 (used for work-groups of at most 640 lanes,
-     i.e. (tile_y + 4) * Lx / 32 <= 640; larger tiles run with 1).
+     i.e. (tile_y + 4) * Lx / 32 <= 640; larger tiles run with 1); in the
+     one-launch multispin sweep 2 is used for work-groups of at most 256
+     lanes, (tile_y + 4) * Lx / 128 <= 256.
+   MICSA_OPT_DRAW_AHEAD: one-launch multispin sweep only.  1 (default) draws
+     the daemon levels of each refresh (Sec. 2.3; they depend on the refresh
+     index and temperature, not on the state) in a kernel of their own on a
+     second stream of the library, while the sweeps before the refresh run;
+     the refresh sweep then reads them.  0 draws them inside the refresh
+     sweep.  Every draw is joined into the context's stream before the call
+     that launched it returns.  Results are identical.
    Errors: EINVAL for an unknown option or a value the lattice cannot use. */
 enum micsa_option {
     MICSA_OPT_SWEEP_KERNEL = 1,
@@ -238,7 +247,8 @@ enum micsa_option {
     MICSA_OPT_GRAPHS = 5,
     MICSA_OPT_PREFETCH = 6,
     MICSA_OPT_TEMPORAL = 7,
-    MICSA_OPT_MSC_FUSED = 8
+    MICSA_OPT_MSC_FUSED = 8,
+    MICSA_OPT_DRAW_AHEAD = 9
 };
 enum micsa_kernel_choice {
     MICSA_KERNEL_AUTO = 0,    /* resident if the lattice fits; else, for MicSA calls of >= 8 sweeps, multispin

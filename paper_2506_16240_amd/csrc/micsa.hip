@@ -69,6 +69,12 @@ struct micsa_ctx {
     uint64_t* mb = nullptr;   // [L][6][rows][Lx/128] couplings of the even sites
     uint64_t *ms_alt = nullptr, *md0_alt = nullptr, *md1_alt = nullptr;  // written by the one-launch sweep
     int32_t msc_fused = 1;  // multispin: 1 = one launch per sweep (z march), 0 = one per half sweep
+    // one-launch multispin sweep: levels of the next refresh drawn ahead on a
+    // side stream (default priority) while the sweeps before it run
+    int32_t draw_ahead = 1;
+    uint64_t *mdr0 = nullptr, *mdr1 = nullptr;  // drawn levels, shape of md0 / md1
+    hipStream_t draw_stream = nullptr;
+    hipEvent_t draw_free = nullptr, draw_done = nullptr;
     // sweep kernel selection (MICSA_OPT_*)
     int32_t kernel_opt = MICSA_KERNEL_AUTO;
     int32_t tile_y = 0, tile_z = 0;
@@ -767,6 +773,43 @@ MscTile msc_tile(const micsa_ctx* c)
 
 bool msc_one_launch(const micsa_ctx* c) { return c->msc_fused && (msc_tile(c).TY + 4) * (c->p.Lx / 128) <= 1024; }
 
+constexpr int64_t kDrawBlocks = 1024;  // draw-ahead grid: one wave per SIMD, beside the sweeps
+
+// Steps of loads in flight in the one-launch multispin sweep.
+int msc_prefetch(const micsa_ctx* c)
+{
+    const int lanes = (msc_tile(c).TY + 4) * (c->p.Lx / 128);
+    return c->prefetch == 2 && (lanes + 63) / 64 * 64 <= kMscPf2Lanes ? 2 : 1;
+}
+
+// Launch the draw of refresh sweep kr's levels on the side stream, after
+// everything the library stream holds so far (the previous refresh sweep
+// reads the same planes); the refresh sweep waits for draw_done.
+int draw_levels(micsa_ctx* c, const MscGeom& m, int64_t kr)
+{
+    const int64_t rho = refresh_index(kr, c->sched.period);
+    const double T = temperature(c->sched, rho);
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
+    const int64_t total = (int64_t)c->L * m.plane;
+    const unsigned blocks = (unsigned)std::min<int64_t>((total + 63) / 64, kDrawBlocks);
+    HIP_TRY(c, hipEventRecord(c->draw_free, c->stream));
+    HIP_TRY(c, hipStreamWaitEvent(c->draw_stream, c->draw_free, 0));
+    k_msc_draw<<<blocks, 64, 0, c->draw_stream>>>(c->g, m, c->L, c->mdr0, c->mdr1, (uint32_t)rho,
+                                                   daemon_thresholds(T));
+    const int st = check_launch(c, "k_msc_draw");
+    if (st) return st;
+    HIP_TRY(c, hipEventRecord(c->draw_done, c->draw_stream));
+    return MICSA_OK;
+}
+
+// First refresh sweep in [from, end), or -1.
+int64_t next_refresh(const micsa_ctx* c, int64_t from, int64_t end)
+{
+    for (int64_t k = from; k < end; ++k)
+        if (is_refresh(k, c->sched.period)) return k;
+    return -1;
+}
+
 // MicSA sweeps k .. k + n - 1 on multispin planes: pack the byte state,
 // sweep (one launch per sweep marching along z, or one per half sweep; the
 // refresh drawn inside), unpack.  Walkers (one-launch only): each sweep
@@ -782,7 +825,8 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
     const MscTile f = msc_tile(c);
     const int lanes = (f.TY + 4) * m.W;
     const bool one = msc_one_launch(c);
-    if (!c->ms || (one && !c->ms_alt)) {
+    const bool ahead = one && c->draw_ahead;
+    if (!c->ms || (one && !c->ms_alt) || (ahead && !c->mdr0)) {
         bool ok = true;
         for (uint64_t** q : {&c->ms, &c->md0, &c->md1})
             if (!*q) ok = ok && hipMalloc(q, words * 8) == hipSuccess;
@@ -790,14 +834,23 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
         if (ok && one)
             for (uint64_t** q : {&c->ms_alt, &c->md0_alt, &c->md1_alt})
                 if (!*q) ok = ok && hipMalloc(q, words * 8) == hipSuccess;
+        if (ok && ahead)
+            for (uint64_t** q : {&c->mdr0, &c->mdr1})
+                if (!*q) ok = ok && hipMalloc(q, words * 8) == hipSuccess;
         if (!ok) {
             (void)hipGetLastError();
-            for (uint64_t** q : {&c->ms, &c->md0, &c->md1, &c->mb, &c->ms_alt, &c->md0_alt, &c->md1_alt}) {
+            for (uint64_t** q :
+                 {&c->ms, &c->md0, &c->md1, &c->mb, &c->ms_alt, &c->md0_alt, &c->md1_alt, &c->mdr0, &c->mdr1}) {
                 if (*q) (void)hipFree(*q);
                 *q = nullptr;
             }
             return fail(c, MICSA_ENOMEM, "multispin planes");
         }
+    }
+    if (ahead && !c->draw_stream) {
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->draw_stream, hipStreamNonBlocking));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->draw_free, hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->draw_done, hipEventDisableTiming));
     }
     const dim3 cgrid((unsigned)((2 * m.plane + 255) / 256), (unsigned)c->L);
     {
@@ -810,6 +863,9 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
     const dim3 sgrid((unsigned)(f.nty * f.ntz), (unsigned)c->L);
     const unsigned sblock = (unsigned)((lanes + 63) / 64 * 64);
     const size_t slds = (size_t)96 * lanes;  // 6 planes x 2 step buffers x 8 B per lane
+    const int64_t k_end = c->k + n;
+    int64_t drawn = -1;  // refresh sweep whose levels the draw planes hold (or are being drawn)
+    if (ahead && (drawn = next_refresh(c, c->k, k_end)) >= 0 && (st = draw_levels(c, m, drawn))) return st;
     for (int64_t i = 0; i < n; ++i) {
         const int64_t k = c->k;
         const bool refresh = is_refresh(k, c->sched.period);
@@ -818,14 +874,23 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
         if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
         const DaemonThresholds th = refresh ? daemon_thresholds(T) : DaemonThresholds{0, 0, 0};
         if (one) {
+            // a refresh sweep with levels drawn ahead is a plain sweep reading them
+            const bool use_drawn = refresh && ahead && drawn == k;
+            if (use_drawn) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->draw_done, 0));
             {
                 TimedLaunch t(c, kTimeSweep);
-                const auto kern = refresh ? k_msc_sweep<true> : k_msc_sweep<false>;
-                kern<<<sgrid, sblock, slds, c->stream>>>(c->g, m, f, c->ms, c->md0, c->md1, c->mb, c->ms_alt,
+                const bool pf2 = msc_prefetch(c) == 2;
+                const bool fresh = refresh && !use_drawn;
+                const auto kern = fresh ? (pf2 ? k_msc_sweep<true, 2> : k_msc_sweep<true, 1>)
+                                        : (pf2 ? k_msc_sweep<false, 2> : k_msc_sweep<false, 1>);
+                kern<<<sgrid, sblock, slds, c->stream>>>(c->g, m, f, c->ms, use_drawn ? c->mdr0 : c->md0,
+                                                         use_drawn ? c->mdr1 : c->md1, c->mb, c->ms_alt,
                                                          c->md0_alt, c->md1_alt, c->tally, (uint32_t)rho, th,
                                                          refresh ? -1 : c->pend_wander);
             }
             if ((st = check_launch(c, "k_msc_sweep"))) return st;
+            if (use_drawn && (drawn = next_refresh(c, k + 1, k_end)) >= 0 && (st = draw_levels(c, m, drawn)))
+                return st;
             std::swap(c->ms, c->ms_alt);
             std::swap(c->md0, c->md0_alt);
             std::swap(c->md1, c->md1_alt);
@@ -958,8 +1023,12 @@ void free_all(micsa_ctx* c)
     if (c->spin_alt) (void)hipFree(c->spin_alt);
     if (c->dem_alt) (void)hipFree(c->dem_alt);
     if (c->bspin) (void)hipFree(c->bspin);
-    for (uint64_t* q : {c->ms, c->md0, c->md1, c->mb, c->ms_alt, c->md0_alt, c->md1_alt})
+    if (c->draw_stream) (void)hipStreamSynchronize(c->draw_stream);
+    for (uint64_t* q : {c->ms, c->md0, c->md1, c->mb, c->ms_alt, c->md0_alt, c->md1_alt, c->mdr0, c->mdr1})
         if (q) (void)hipFree(q);
+    if (c->draw_free) (void)hipEventDestroy(c->draw_free);
+    if (c->draw_done) (void)hipEventDestroy(c->draw_done);
+    if (c->draw_stream) (void)hipStreamDestroy(c->draw_stream);
     if (c->bdm0) (void)hipFree(c->bdm0);
     if (c->bdm1) (void)hipFree(c->bdm1);
     if (c->bJ) (void)hipFree(c->bJ);
@@ -1708,6 +1777,10 @@ int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value)
     case MICSA_OPT_GRAPHS:
         if (value != 0 && value != 1) return fail(ctx, MICSA_EINVAL, "graphs is 0 or 1");
         ctx->use_graphs = (int32_t)value;
+        return MICSA_OK;
+    case MICSA_OPT_DRAW_AHEAD:
+        if (value != 0 && value != 1) return fail(ctx, MICSA_EINVAL, "draw_ahead is 0 or 1");
+        ctx->draw_ahead = (int32_t)value;
         return MICSA_OK;
     case MICSA_OPT_MSC_FUSED:
         if (value != 0 && value != 1) return fail(ctx, MICSA_EINVAL, "msc_fused is 0 or 1");

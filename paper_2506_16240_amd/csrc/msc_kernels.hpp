@@ -219,9 +219,19 @@ struct MscTile {
 // couplings of plane z); z neighbours through registers.  Each coupling
 // word is read once per sweep.  On refresh sweeps the even half draws both
 // parities' levels of its word and keeps the odd ones for the next step.
+// Global loads run DEPTH steps ahead of their use (DEPTH = 1 or 2 register
+// stages; the step loop is unrolled by DEPTH so that a stage is refilled
+// right after its own step consumed it and no register copy waits on a
+// load still in flight).
 // Grid (nty * ntz, L); block 64 ceil((TY + 4) W / 64); LDS 96 (TY + 4) W bytes.
-template <bool REFRESH>
-__global__ __launch_bounds__(1024) void k_msc_sweep(Geom g, MscGeom m, MscTile f,
+struct MscStage {
+    uint64_t O, Es, J[6], me0, me1, mo0, mo1;
+};
+
+constexpr int kMscPf2Lanes = 256;  // largest work-group of the two-stage form (its register budget)
+
+template <bool REFRESH, int DEPTH>
+__global__ __launch_bounds__(DEPTH == 2 ? kMscPf2Lanes : 1024) void k_msc_sweep(Geom g, MscGeom m, MscTile f,
                                                     const uint64_t* __restrict__ spin_in,
                                                     const uint64_t* __restrict__ d0_in,
                                                     const uint64_t* __restrict__ d1_in,
@@ -282,24 +292,23 @@ __global__ __launch_bounds__(1024) void k_msc_sweep(Geom g, MscGeom m, MscTile f
             v1 = sh > 0 ? shift_next(v1, c1) : shift_prev(v1, c1);
         }
     };
-    // loads of step st are issued during step st - 1 (one step in flight)
-    uint64_t nO = 0, nEs = 0, nJ[6] = {0, 0, 0, 0, 0, 0}, nme0 = 0, nme1 = 0, nmo0 = 0, nmo1 = 0;
-    auto load = [&](int st2) {
+    // the loads of step st2 into a register stage
+    auto load = [&](int st2, MscStage& S) {
         const int zz2 = zstart + dz * st2;
         const int z2 = wrap(zz2, g.Lz);
-        if (active) nO = od_in[widx(wrap(zz2 + dz, g.Lz))];
+        if (active) S.O = od_in[widx(wrap(zz2 + dz, g.Lz))];
         if (do_even) {
             const int64_t h = widx(z2);
-            nEs = ev_in[h];
+            S.Es = ev_in[h];
 #pragma unroll
-            for (int d = 0; d < 6; ++d) nJ[d] = bl[(int64_t)d * m.plane + h];
+            for (int d = 0; d < 6; ++d) S.J[d] = bl[(int64_t)d * m.plane + h];
             if (!REFRESH) {
                 if (wander < 0) {
-                    nme0 = d0_in[((int64_t)l * 2 + 0) * m.plane + h];
-                    nme1 = d1_in[((int64_t)l * 2 + 0) * m.plane + h];
+                    S.me0 = d0_in[((int64_t)l * 2 + 0) * m.plane + h];
+                    S.me1 = d1_in[((int64_t)l * 2 + 0) * m.plane + h];
                 } else {  // the walkers' owed wandering: new even levels from the odd planes
                     const int q = (y + z2) & 1;
-                    load_shifted(((int64_t)l * 2 + 1) * m.plane + widx(z2), wander == 0 ? q : q - 1, nme0, nme1);
+                    load_shifted(((int64_t)l * 2 + 1) * m.plane + widx(z2), wander == 0 ? q : q - 1, S.me0, S.me1);
                 }
             }
         }
@@ -307,27 +316,29 @@ __global__ __launch_bounds__(1024) void k_msc_sweep(Geom g, MscGeom m, MscTile f
             const int zo2 = wrap(zz2 - dz, g.Lz);
             if (wander < 0) {
                 const int64_t ho = ((int64_t)l * 2 + 1) * m.plane + widx(zo2);
-                nmo0 = d0_in[ho];
-                nmo1 = d1_in[ho];
+                S.mo0 = d0_in[ho];
+                S.mo1 = d1_in[ho];
             } else {  // new odd levels from the even planes
                 const int q = (y + zo2) & 1;
-                load_shifted(((int64_t)l * 2 + 0) * m.plane + widx(zo2), wander == 0 ? -q : 1 - q, nmo0, nmo1);
+                load_shifted(((int64_t)l * 2 + 0) * m.plane + widx(zo2), wander == 0 ? -q : 1 - q, S.mo0, S.mo1);
             }
         }
     };
-    load(0);
+    MscStage SA = {}, SB = {};
+    load(0, SA);
+    if (DEPTH == 2 && steps > 1) load(1, SB);
     long long so = 0, sn = 0;
-    for (int st = 0; st < steps; ++st) {
+    auto step = [&](int st, MscStage& S) {
         const int buf = st & 1, pb = buf ^ 1;
         const int zz = zstart + dz * st;  // unwrapped: owned iff in [z0, z0 + TZ)
         const int z = wrap(zz, g.Lz), zo = wrap(zz - dz, g.Lz);
         const bool own_e = zz >= z0 && zz < z0 + f.TZ, own_o = zz - dz >= z0 && zz - dz < z0 + f.TZ;
         const bool odd_now = do_odd && st >= 2;
-        O_next = nO;
-        uint64_t Es = nEs, J[6], me0 = nme0, me1 = nme1, mo0 = nmo0, mo1 = nmo1, Gn0 = 0, Gn1 = 0;
+        O_next = S.O;
+        uint64_t Es = S.Es, J[6], me0 = S.me0, me1 = S.me1, mo0 = S.mo0, mo1 = S.mo1, Gn0 = 0, Gn1 = 0;
 #pragma unroll
-        for (int d = 0; d < 6; ++d) J[d] = nJ[d];
-        if (st + 1 < steps) load(st + 1);
+        for (int d = 0; d < 6; ++d) J[d] = S.J[d];
+        if (st + DEPTH < steps) load(st + DEPTH, S);
         if (do_even) {
             if (REFRESH) msc_draw2(g, y + g.Ly * z, w, (y + z) & 1, rho, rr, sw, th, me0, me1, Gn0, Gn1);
             MZ0 = J[kMz];
@@ -403,8 +414,42 @@ __global__ __launch_bounds__(1024) void k_msc_sweep(Geom g, MscGeom m, MscTile f
         PZ1 = PZ0;
         Go0 = Gn0;
         Go1 = Gn1;
+    };
+    if (DEPTH == 2) {
+        for (int st = 0; st < steps; st += 2) {
+            step(st, SA);
+            if (st + 1 < steps) step(st + 1, SB);
+        }
+    } else {
+        for (int st = 0; st < steps; ++st) step(st, SA);
     }
     block_add(tally + (int64_t)l * kSlots, 4 * (so - sn));
+}
+
+// Daemon levels of a refresh sweep drawn ahead into planes of the working
+// layout: both parities of every word, with the same Philox counters as the
+// sweep's own draw.  The levels of a refresh depend on its index and
+// temperature only, not on the state, so they can be drawn while the sweeps
+// before that refresh run; the refresh sweep then reads them in place of the
+// stored levels.  Grid-stride over every (lattice, row, word); block 64.
+__global__ __launch_bounds__(64) void k_msc_draw(Geom g, MscGeom m, int32_t L, uint64_t* __restrict__ d0,
+                                                 uint64_t* __restrict__ d1, uint32_t rho, DaemonThresholds th)
+{
+    const int64_t total = (int64_t)L * m.plane;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)(i / m.plane);
+        const int64_t pw = i - (int64_t)l * m.plane;
+        const int row = (int)(pw / m.W), w = (int)(pw - (int64_t)row * m.W);
+        const int y = row % g.Ly, z = row / g.Ly;
+        uint64_t e0, e1, o0, o1;
+        msc_draw2(g, row, w, (y + z) & 1, rho, (uint32_t)(l % g.R), stream_word(kStreamDaemon, (uint32_t)(l / g.R)),
+                  th, e0, e1, o0, o1);
+        const int64_t he = (int64_t)l * 2 * m.plane + pw, ho = he + m.plane;
+        d0[he] = e0;
+        d1[he] = e1;
+        d0[ho] = o0;
+        d1[ho] = o1;
+    }
 }
 
 // Byte layout -> planes (and back): one thread per (lattice, parity, row,

@@ -111,3 +111,13 @@ def test_pt_create_rejects_bad_couplings(bad):
     J[17] = bad
     st, ctx = _pt_create(J=J)
     assert st == M.EINVAL and not ctx
+
+
+def test_binding_constants_match_the_header():
+    """Every MICSA_OPT_* / MICSA_KERNEL_* value the header declares has the
+    same value in the Python binding (a mismatch would set the wrong option)."""
+    text = open(os.path.join(ROOT, "include", "micsa.h")).read()
+    pairs = re.findall(r"\bMICSA_((?:OPT|KERNEL)_[A-Z0-9_]+)\s*=\s*(\d+)", text)
+    assert len(pairs) >= 14
+    for name, value in pairs:
+        assert getattr(M, name) == int(value), name
