@@ -211,7 +211,10 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      unpacks it at the end; walkers (gamma = 1) run on the one-launch form
      too; the heat bath and Metropolis keep the fused path).
    MICSA_OPT_TILE_Y / MICSA_OPT_TILE_Z: rows / planes per work-group of the
-     fused sweep (0 = automatic; must divide Ly / Lz).
+     fused and one-launch multispin sweeps (0 = automatic).  TILE_Z must
+     divide Lz.  TILE_Y is at most Ly; the fused byte sweep uses it where it
+     divides Ly (else the automatic choice), the multispin sweep as given,
+     its last tile along y holding the rows left over.
    MICSA_OPT_XCD_MAP: 1 (default) assigns neighbouring tiles of the fused
      sweep to the same XCD (shared L2 for halo reads); 0 = plain order.
    MICSA_OPT_GRAPHS: 1 replays the per-half paths (bit-plane layout; byte
@@ -228,9 +231,7 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      along z (1, default) or one launch per half sweep (0).
    MICSA_OPT_PREFETCH: steps of global loads in flight in the fused MicSA
      sweep, 1 (default) or 2 (used for work-groups of at most 640 lanes,
-     i.e. (tile_y + 4) * Lx / 32 <= 640; larger tiles run with 1); in the
-     one-launch multispin sweep 2 is used for work-groups of at most 256
-     lanes, (tile_y + 4) * Lx / 128 <= 256.
+     i.e. (tile_y + 4) * Lx / 32 <= 640; larger tiles run with 1).
    MICSA_OPT_DRAW_AHEAD: one-launch multispin sweep only.  1 (default) draws
      the daemon levels of each refresh (Sec. 2.3; they depend on the refresh
      index and temperature, not on the state) in a kernel of their own on a

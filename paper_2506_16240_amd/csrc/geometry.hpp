@@ -95,6 +95,18 @@ __device__ __forceinline__ long long wave_sum64(long long v)
     return v;
 }
 
+// Work-group barrier that orders LDS accesses only.  __syncthreads() also
+// fences global memory, which makes every wave wait for all of its global
+// loads before the barrier; kernels that prefetch the next step's operands
+// from global memory into registers, and share nothing through global memory
+// within a work-group, use this one so that the loads stay in flight.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Block-wide sum of v, added by one thread to slots[blockIdx.x % kSlots].
 // Must be reached by every thread of the block.
 __device__ __forceinline__ void block_add(unsigned long long* slots, long long v)

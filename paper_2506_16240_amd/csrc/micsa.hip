@@ -375,7 +375,7 @@ FusedTile choose_tile(const micsa_ctx* c)
     FusedTile f;
     f.NC = c->p.Lx / 32;
     const int ty_cap = std::max(1, std::min(32, 1024 / f.NC - 4));
-    f.TY = c->tile_y > 0 ? c->tile_y : divisor_at_most(c->p.Ly, ty_cap);
+    f.TY = c->tile_y > 0 && c->p.Ly % c->tile_y == 0 ? c->tile_y : divisor_at_most(c->p.Ly, ty_cap);
     f.nty = c->p.Ly / f.TY;
     f.xcd = c->xcd_map;
     if (c->tile_z > 0) {
@@ -759,28 +759,35 @@ int launch_wander(micsa_ctx* c, int64_t t)
 }
 
 // Tile of the one-launch multispin sweep: TY rows x TZ planes per work-group
-// ((TY + 4) Lx / 128 lanes); the tile options apply where they divide.
+// ((TY + 4) Lx / 128 lanes; the last tile along y holds the rows left over).
+// Automatic TY: the most rows whose lanes, ring of 4 rows included, fill
+// whole waves, up to three (Lx = 512: 44 rows, 192 lanes), so that no wave
+// runs mostly empty; TZ divides Lz.
 MscTile msc_tile(const micsa_ctx* c)
 {
     const int W = c->p.Lx / 128;
     MscTile f{};
-    f.TY = c->tile_y ? c->tile_y : divisor_at_most(c->p.Ly, std::max(1, 256 / W - 4));
+    if (c->tile_y) {
+        f.TY = c->tile_y;
+    } else {
+        int rows = 0;
+        for (int r = 5; r * W <= 192; ++r)
+            if ((r * W) % 64 == 0) rows = r;
+        f.TY = rows ? std::min(rows - 4, c->p.Ly) : divisor_at_most(c->p.Ly, std::max(1, 256 / W - 4));
+    }
     f.TZ = c->tile_z ? c->tile_z : divisor_at_most(c->p.Lz, 8);
-    f.nty = c->p.Ly / f.TY;
+    f.nty = (c->p.Ly + f.TY - 1) / f.TY;
     f.ntz = c->p.Lz / f.TZ;
     return f;
 }
 
-bool msc_one_launch(const micsa_ctx* c) { return c->msc_fused && (msc_tile(c).TY + 4) * (c->p.Lx / 128) <= 1024; }
+bool msc_one_launch(const micsa_ctx* c)
+{
+    return c->msc_fused && ((msc_tile(c).TY + 4) * (c->p.Lx / 128) + 63) / 64 * 64 <= kMscSweepLanes;
+}
 
 constexpr int64_t kDrawBlocks = 1024;  // draw-ahead grid: one wave per SIMD, beside the sweeps
 
-// Steps of loads in flight in the one-launch multispin sweep.
-int msc_prefetch(const micsa_ctx* c)
-{
-    const int lanes = (msc_tile(c).TY + 4) * (c->p.Lx / 128);
-    return c->prefetch == 2 && (lanes + 63) / 64 * 64 <= kMscPf2Lanes ? 2 : 1;
-}
 
 // Launch the draw of refresh sweep kr's levels on the side stream, after
 // everything the library stream holds so far (the previous refresh sweep
@@ -879,10 +886,10 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
             if (use_drawn) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->draw_done, 0));
             {
                 TimedLaunch t(c, kTimeSweep);
-                const bool pf2 = msc_prefetch(c) == 2;
-                const bool fresh = refresh && !use_drawn;
-                const auto kern = fresh ? (pf2 ? k_msc_sweep<true, 2> : k_msc_sweep<true, 1>)
-                                        : (pf2 ? k_msc_sweep<false, 2> : k_msc_sweep<false, 1>);
+                const bool fresh = refresh && !use_drawn, walk = !refresh && c->pend_wander >= 0;
+                const auto kern = fresh  ? k_msc_sweep<true, false>
+                                  : walk ? k_msc_sweep<false, true>
+                                         : k_msc_sweep<false, false>;
                 kern<<<sgrid, sblock, slds, c->stream>>>(c->g, m, f, c->ms, use_drawn ? c->mdr0 : c->md0,
                                                          use_drawn ? c->mdr1 : c->md1, c->mb, c->ms_alt,
                                                          c->md0_alt, c->md1_alt, c->tally, (uint32_t)rho, th,
@@ -1770,8 +1777,8 @@ int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value)
         ctx->kernel_opt = (int32_t)value;
         return MICSA_OK;
     case MICSA_OPT_TILE_Y:
-        if (value < 0 || (value > 0 && (ctx->p.Ly % value != 0 || (value + 4) * (ctx->p.Lx / 32) > 1024)))
-            return fail(ctx, MICSA_EINVAL, "tile_y must divide Ly and fit a work-group");
+        if (value < 0 || value > ctx->p.Ly || (value > 0 && (value + 4) * (ctx->p.Lx / 32) > 1024))
+            return fail(ctx, MICSA_EINVAL, "tile_y must be at most Ly and fit a work-group");
         ctx->tile_y = (int32_t)value;
         return MICSA_OK;
     case MICSA_OPT_GRAPHS:

@@ -209,8 +209,8 @@ struct MscTile {
 // One whole sweep per launch (both halves), marching along z like the byte
 // layout's fused sweep: at step st, with z = zstart + dz st, the even half
 // on plane z and the odd half on plane z - dz, whose even neighbours (planes
-// z - 2dz .. z) are then all final.  A work-group owns TY rows x TZ planes of
-// one lattice, all words of a row; the even half also runs on one ring of
+// z - 2dz .. z) are then all final.  A work-group owns TY rows (the last
+// along y what is left of Ly) x TZ planes of one lattice, all words of a row; the even half also runs on one ring of
 // rows and planes and odd spins are read on two rings, so no tile needs
 // another tile's new values (state read from the "in" planes, written to the
 // "out" planes).  Lanes: (TY + 4) rows x W words; in-plane neighbours (rows
@@ -219,20 +219,24 @@ struct MscTile {
 // couplings of plane z); z neighbours through registers.  Each coupling
 // word is read once per sweep.  On refresh sweeps the even half draws both
 // parities' levels of its word and keeps the odd ones for the next step.
-// Global loads run DEPTH steps ahead of their use (DEPTH = 1 or 2 register
-// stages; the step loop is unrolled by DEPTH so that a stage is refilled
-// right after its own step consumed it and no register copy waits on a
-// load still in flight).
+// Loads and barriers: every lane issues every load of a step (a lane
+// outside a word's rows reads a row of its own tile instead, a line the
+// work-group fetches anyway), so that no load sits under a lane-dependent
+// branch; two register stages alternate (the loop is unrolled by two), so
+// that a value in flight is never copied; and the barrier orders LDS only.
+// The loads of step st + 1 are thus in flight through the whole of step st.
+// Walkers (WALK): the owed wandering's shift is applied when the levels are
+// used, from the word and its carry word loaded side by side.
 // Grid (nty * ntz, L); block 64 ceil((TY + 4) W / 64); LDS 96 (TY + 4) W bytes.
 struct MscStage {
     uint64_t O, Es, J[6], me0, me1, mo0, mo1;
+    uint64_t mc0, mc1, oc0, oc1;  // WALK: carry words of the even and odd levels
 };
 
-constexpr int kMscPf2Lanes = 256;  // largest work-group of the two-stage form (its register budget)
+constexpr int kMscSweepLanes = 256;  // largest work-group of the one-launch sweep (its register budget)
 
-template <bool REFRESH, int DEPTH>
-__global__ __launch_bounds__(DEPTH == 2 ? kMscPf2Lanes : 1024) void k_msc_sweep(Geom g, MscGeom m, MscTile f,
-                                                    const uint64_t* __restrict__ spin_in,
+template <bool REFRESH, bool WALK>
+__global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(Geom g, MscGeom m, MscTile f, const uint64_t* __restrict__ spin_in,
                                                     const uint64_t* __restrict__ d0_in,
                                                     const uint64_t* __restrict__ d1_in,
                                                     const uint64_t* __restrict__ bond, uint64_t* __restrict__ spin_out,
@@ -240,6 +244,7 @@ __global__ __launch_bounds__(DEPTH == 2 ? kMscPf2Lanes : 1024) void k_msc_sweep(
                                                     unsigned long long* __restrict__ tally, uint32_t rho,
                                                     DaemonThresholds th, int wander)
 {
+    static_assert(!(REFRESH && WALK), "a refresh sweep owes no wandering");
     extern __shared__ uint64_t lds64[];
     const int W = m.W;
     const int rows_slots = f.TY + 4;
@@ -252,83 +257,80 @@ __global__ __launch_bounds__(DEPTH == 2 ? kMscPf2Lanes : 1024) void k_msc_sweep(
     const int dz = (tz & 1) ? -1 : 1;
     const int zstart = dz > 0 ? z0 - 1 : z0 + f.TZ;
     const int ry = threadIdx.x / W, w = threadIdx.x - (threadIdx.x / W) * W;
-    const bool active = ry < rows_slots;
+    const int own = min(f.TY, g.Ly - y0);  // the last tile along y may be shorter
+    const bool active = ry < own + 4;
     auto wrap = [](int v, int L) { v %= L; return v < 0 ? v + L : v; };
     const int y = wrap(y0 - 2 + ry, g.Ly);
-    const bool do_even = active && ry >= 1 && ry <= f.TY + 2;
-    const bool do_odd = active && ry >= 2 && ry <= f.TY + 1;  // the rows the tile owns
+    const bool do_even = active && ry >= 1 && ry <= own + 2;
+    const bool do_odd = active && ry >= 2 && ry <= own + 1;  // the rows the tile owns
+    // rows each lane loads from: odd spins on the whole ring, even-site words
+    // where the even half runs, odd levels where the odd half runs
+    const int yO = wrap(y0 - 2 + min(ry, own + 3), g.Ly);
+    const int yE = wrap(y0 - 2 + min(max(ry, 1), own + 2), g.Ly);
+    const int yD = wrap(y0 - 2 + min(max(ry, 2), own + 1), g.Ly);
     const int wn = w + 1 == W ? 0 : w + 1, wp = w == 0 ? W - 1 : w - 1;
     const int me = ry * W + w;
 
-    const uint64_t* ev_in = spin_in + ((int64_t)l * 2 + 0) * m.plane;
-    const uint64_t* od_in = spin_in + ((int64_t)l * 2 + 1) * m.plane;
+    const int64_t lp = (int64_t)l * 2 * m.plane;  // parity-0 plane of lattice l
+    const uint64_t* ev_in = spin_in + lp;
+    const uint64_t* od_in = spin_in + lp + m.plane;
     const uint64_t* bl = bond + (int64_t)l * 6 * m.plane;
-    auto widx = [&](int zz) { return ((int64_t)y + (int64_t)g.Ly * zz) * W + w; };
+    auto at = [&](int yy, int zz) { return ((int64_t)yy + (int64_t)g.Ly * zz) * W + w; };
     const uint32_t rr = (uint32_t)(l % g.R), sw = stream_word(kStreamDaemon, (uint32_t)(l / g.R));
     const int steps = f.TZ + 2;
 
-    uint64_t O_prev = 0, O_cur = 0, O_next = 0;  // old odd spins at z - dz, z, z + dz
-    uint64_t E0 = 0, E1 = 0, E2 = 0;             // new even spins at z, z - dz, z - 2dz
-    uint64_t MZ0 = 0, MZ1 = 0, MZ2 = 0;          // even couplings -z at z, z - dz, z - 2dz
-    uint64_t PZ0 = 0, PZ1 = 0, PZ2 = 0;          // even couplings +z at the same planes
-    uint64_t Go0 = 0, Go1 = 0;                   // REFRESH: drawn odd levels of plane z - dz
-    if (active) {
-        O_prev = od_in[widx(wrap(zstart - dz, g.Lz))];
-        O_cur = od_in[widx(wrap(zstart, g.Lz))];
-    }
-    // Walkers (Sec. 2.6): with wander = p >= 0 the input levels still owe the
-    // forward-X wandering of the sites of parity p (the previous timestep's);
-    // it is applied on load.  In a row whose even sites sit at x = 2k + q,
-    // even site k pairs with odd site k + q (p = 0), odd site k with even
-    // site k + 1 - q (p = 1): a shift by 0 or +-1 site across the two
-    // parities' planes, the carry from the neighbouring word.
-    auto load_shifted = [&](int64_t at, int sh, uint64_t& v0, uint64_t& v1) {
-        v0 = d0_in[at];
-        v1 = d1_in[at];
-        if (sh != 0) {
-            const int64_t an = at + (sh > 0 ? wn - w : wp - w);
-            const uint64_t c0 = d0_in[an], c1 = d1_in[an];
-            v0 = sh > 0 ? shift_next(v0, c0) : shift_prev(v0, c0);
-            v1 = sh > 0 ? shift_next(v1, c1) : shift_prev(v1, c1);
-        }
+    uint64_t O_prev = od_in[at(yO, wrap(zstart - dz, g.Lz))];  // old odd spins at z - dz, z, z + dz
+    uint64_t O_cur = od_in[at(yO, wrap(zstart, g.Lz))];
+    uint64_t O_next = 0;
+    uint64_t E0 = 0, E1 = 0, E2 = 0;     // new even spins at z, z - dz, z - 2dz
+    uint64_t MZ0 = 0, MZ1 = 0, MZ2 = 0;  // even couplings -z at z, z - dz, z - 2dz
+    uint64_t PZ0 = 0, PZ1 = 0, PZ2 = 0;  // even couplings +z at the same planes
+    uint64_t Go0 = 0, Go1 = 0;           // REFRESH: drawn odd levels of plane z - dz
+    // Walkers (Sec. 2.6): with WALK the input levels still owe the forward-X
+    // wandering of the sites of parity wander (the previous timestep's).  In
+    // a row whose even sites sit at x = 2k + q, even site k pairs with odd
+    // site k + q (wander = 0), odd site k with even site k + 1 - q (wander =
+    // 1): the levels move by 0 or +-1 site across the two parities' planes,
+    // with the carry from the neighbouring word of the row.
+    auto carry = [&](int sh) { return (int64_t)(sh > 0 ? wn - w : wp - w); };
+    auto shifted = [](uint64_t v, uint64_t c, int sh) {
+        return sh > 0 ? shift_next(v, c) : sh < 0 ? shift_prev(v, c) : v;
     };
     // the loads of step st2 into a register stage
     auto load = [&](int st2, MscStage& S) {
         const int zz2 = zstart + dz * st2;
         const int z2 = wrap(zz2, g.Lz);
-        if (active) S.O = od_in[widx(wrap(zz2 + dz, g.Lz))];
-        if (do_even) {
-            const int64_t h = widx(z2);
-            S.Es = ev_in[h];
+        S.O = od_in[at(yO, wrap(zz2 + dz, g.Lz))];
+        const int64_t h = at(yE, z2);
+        S.Es = ev_in[h];
 #pragma unroll
-            for (int d = 0; d < 6; ++d) S.J[d] = bl[(int64_t)d * m.plane + h];
-            if (!REFRESH) {
-                if (wander < 0) {
-                    S.me0 = d0_in[((int64_t)l * 2 + 0) * m.plane + h];
-                    S.me1 = d1_in[((int64_t)l * 2 + 0) * m.plane + h];
-                } else {  // the walkers' owed wandering: new even levels from the odd planes
-                    const int q = (y + z2) & 1;
-                    load_shifted(((int64_t)l * 2 + 1) * m.plane + widx(z2), wander == 0 ? q : q - 1, S.me0, S.me1);
-                }
-            }
-        }
-        if (!REFRESH && do_odd && st2 >= 2) {
+        for (int d = 0; d < 6; ++d) S.J[d] = bl[(int64_t)d * m.plane + h];
+        if (!REFRESH) {
+            // even levels of plane z2 (walkers: from the odd planes); odd
+            // levels of plane z2 - dz (walkers: from the even planes), which
+            // before the first odd step repeat the even-level words
+            const int64_t he = lp + (WALK ? m.plane : 0) + h;
+            const bool odd_ok = st2 >= 2;
             const int zo2 = wrap(zz2 - dz, g.Lz);
-            if (wander < 0) {
-                const int64_t ho = ((int64_t)l * 2 + 1) * m.plane + widx(zo2);
-                S.mo0 = d0_in[ho];
-                S.mo1 = d1_in[ho];
-            } else {  // new odd levels from the even planes
-                const int q = (y + zo2) & 1;
-                load_shifted(((int64_t)l * 2 + 0) * m.plane + widx(zo2), wander == 0 ? -q : 1 - q, S.mo0, S.mo1);
+            const int64_t ho = odd_ok ? lp + (WALK ? 0 : m.plane) + at(yD, zo2) : he;
+            S.me0 = d0_in[he];
+            S.me1 = d1_in[he];
+            S.mo0 = d0_in[ho];
+            S.mo1 = d1_in[ho];
+            if (WALK) {
+                const int qe = (yE + z2) & 1, qo = (yD + zo2) & 1;
+                const int64_t hec = he + carry(wander == 0 ? qe : qe - 1);
+                const int64_t hoc = ho + carry(wander == 0 ? -qo : 1 - qo);
+                S.mc0 = d0_in[hec];
+                S.mc1 = d1_in[hec];
+                S.oc0 = d0_in[hoc];
+                S.oc1 = d1_in[hoc];
             }
         }
     };
-    MscStage SA = {}, SB = {};
-    load(0, SA);
-    if (DEPTH == 2 && steps > 1) load(1, SB);
     long long so = 0, sn = 0;
-    auto step = [&](int st, MscStage& S) {
+    // step st: consumes stage S (loaded during step st - 1), loads step st + 1 into N
+    auto step = [&](int st, MscStage& S, MscStage& N) {
         const int buf = st & 1, pb = buf ^ 1;
         const int zz = zstart + dz * st;  // unwrapped: owned iff in [z0, z0 + TZ)
         const int z = wrap(zz, g.Lz), zo = wrap(zz - dz, g.Lz);
@@ -338,7 +340,15 @@ __global__ __launch_bounds__(DEPTH == 2 ? kMscPf2Lanes : 1024) void k_msc_sweep(
         uint64_t Es = S.Es, J[6], me0 = S.me0, me1 = S.me1, mo0 = S.mo0, mo1 = S.mo1, Gn0 = 0, Gn1 = 0;
 #pragma unroll
         for (int d = 0; d < 6; ++d) J[d] = S.J[d];
-        if (st + DEPTH < steps) load(st + DEPTH, S);
+        if (WALK) {
+            const int qe = (y + z) & 1, qo = (y + zo) & 1;
+            const int she = wander == 0 ? qe : qe - 1, sho = wander == 0 ? -qo : 1 - qo;
+            me0 = shifted(me0, S.mc0, she);
+            me1 = shifted(me1, S.mc1, she);
+            mo0 = shifted(mo0, S.oc0, sho);
+            mo1 = shifted(mo1, S.oc1, sho);
+        }
+        if (st + 1 < steps) load(st + 1, N);
         if (do_even) {
             if (REFRESH) msc_draw2(g, y + g.Ly * z, w, (y + z) & 1, rho, rr, sw, th, me0, me1, Gn0, Gn1);
             MZ0 = J[kMz];
@@ -352,7 +362,7 @@ __global__ __launch_bounds__(DEPTH == 2 ? kMscPf2Lanes : 1024) void k_msc_sweep(
         // half: the odd spins go in before this step's barrier (their readers
         // are this step's even half), everything step st + 1 reads after it
         if (active) LP(buf, 0)[me] = O_cur;
-        __syncthreads();
+        lds_barrier();
         if (do_even) {  // ---- even half on plane z (old odd neighbours)
             LP(buf, 2)[me] = J[kMx];
             LP(buf, 3)[me] = J[kPx];
@@ -369,10 +379,10 @@ __global__ __launch_bounds__(DEPTH == 2 ? kMscPf2Lanes : 1024) void k_msc_sweep(
                           me0, me1, a, b);
             LP(buf, 1)[me] = E0;
             if (do_odd && own_e) {
-                const int64_t h = widx(z);
-                spin_out[((int64_t)l * 2 + 0) * m.plane + h] = E0;
-                d0_out[((int64_t)l * 2 + 0) * m.plane + h] = me0;
-                d1_out[((int64_t)l * 2 + 0) * m.plane + h] = me1;
+                const int64_t h = lp + at(y, z);
+                spin_out[h] = E0;
+                d0_out[h] = me0;
+                d1_out[h] = me1;
                 so += a;
                 sn += b;
             }
@@ -396,7 +406,7 @@ __global__ __launch_bounds__(DEPTH == 2 ? kMscPf2Lanes : 1024) void k_msc_sweep(
             const uint64_t On = msc_move(O_prev, nxp ^ jxp, nxm ^ jxm, nyp ^ jyp, nym ^ jym, nzp ^ jzp, nzm ^ jzm,
                                          mo0, mo1, a, b);
             if (own_o) {
-                const int64_t ho = ((int64_t)l * 2 + 1) * m.plane + widx(zo);
+                const int64_t ho = lp + m.plane + at(y, zo);
                 spin_out[ho] = On;
                 d0_out[ho] = mo0;
                 d1_out[ho] = mo1;
@@ -415,13 +425,11 @@ __global__ __launch_bounds__(DEPTH == 2 ? kMscPf2Lanes : 1024) void k_msc_sweep(
         Go0 = Gn0;
         Go1 = Gn1;
     };
-    if (DEPTH == 2) {
-        for (int st = 0; st < steps; st += 2) {
-            step(st, SA);
-            if (st + 1 < steps) step(st + 1, SB);
-        }
-    } else {
-        for (int st = 0; st < steps; ++st) step(st, SA);
+    MscStage SA = {}, SB = {};
+    load(0, SA);
+    for (int st = 0; st < steps; st += 2) {
+        step(st, SA, SB);
+        if (st + 1 < steps) step(st + 1, SB, SA);
     }
     block_add(tally + (int64_t)l * kSlots, 4 * (so - sn));
 }

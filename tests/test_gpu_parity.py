@@ -311,23 +311,25 @@ def test_walkers_fused_wander_on_load(shape, prefetch, temporal):
 
 
 MSC_SHAPES = [(128, 4, 4, 1, 1), (128, 2, 2, 1, 1), (128, 6, 2, 2, 3), (384, 4, 6, 1, 2), (256, 8, 6, 2, 1),
-              (128, 70, 36, 1, 1)]  # several tiles along y and z
+              (128, 70, 36, 1, 1),  # several tiles along z
+              (512, 50, 4, 1, 1)]  # automatic tile of 44 rows: a second tile of 6 along y
 
 
-@pytest.mark.parametrize("fused,pf", [(1, 1), (1, 2), (0, 1)], ids=["one-launch", "one-launch-pf2", "per-half"])
+@pytest.mark.parametrize("fused,ahead", [(1, 1), (1, 0), (0, 1)], ids=["one-launch", "one-launch-in-sweep-draw",
+                                                                       "per-half"])
 @pytest.mark.parametrize("shape", MSC_SHAPES)
-def test_multispin_matches_oracle(shape, fused, pf):
+def test_multispin_matches_oracle(shape, fused, ahead):
     """Multispin coding (Sec. 2.5): 64 sites of a row per word, the Creutz
-    move bit-sliced, the refresh drawn in the kernels; one launch per sweep
-    marching along z (rings of rows and planes that wrap onto small sides;
-    loads one or two steps ahead) or one per half sweep.  Every logged
+    move bit-sliced; one launch per sweep marching along z (rings of rows
+    and planes that wrap onto small sides; refresh levels drawn ahead on the
+    side stream or inside the sweep) or one per half sweep.  Every logged
     energy (one pack/unpack per sweep), then a long call (one pack, many
     sweeps, one unpack), against the oracle; minimum sides, several samples
     and replicas, three words per row."""
     g, o = pair(*shape, seed=0x77AA)
     g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_MULTISPIN)
     g.set_option(M.OPT_MSC_FUSED, fused)
-    g.set_option(M.OPT_PREFETCH, pf)
+    g.set_option(M.OPT_DRAW_AHEAD, ahead)
     assert g.kernel_name(M.ALGO_MICSA) == ("k_msc_sweep" if fused else "k_msc_half")
     gs, os_ = scheds(M.SCHED_LINEAR, 2.4, 0.3, 60, 3)
     g.set_schedule(gs)
@@ -346,9 +348,8 @@ def test_multispin_matches_oracle(shape, fused, pf):
     same_state(g, o)
 
 
-@pytest.mark.parametrize("pf", [1, 2])
-@pytest.mark.parametrize("shape", [(128, 4, 4, 1, 1), (256, 6, 4, 1, 2), (384, 4, 6, 2, 1)])
-def test_multispin_walkers_match_oracle(shape, pf):
+@pytest.mark.parametrize("shape", [(128, 4, 4, 1, 1), (256, 6, 4, 1, 2), (384, 4, 6, 2, 1), (512, 50, 4, 1, 1)])
+def test_multispin_walkers_match_oracle(shape):
     """Walkers (gamma = 1, forward-X wandering after every timestep, Sec.
     2.6) on the one-launch multispin sweep: each sweep applies the previous
     timestep's wandering as it loads the levels (one or three words per
@@ -357,7 +358,6 @@ def test_multispin_walkers_match_oracle(shape, pf):
     and long calls, against the oracle."""
     g, o = pair(*shape, seed=0x77AB)
     g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_MULTISPIN)
-    g.set_option(M.OPT_PREFETCH, pf)
     assert g.kernel_name(M.ALGO_WALKERS) == "k_msc_sweep"
     gs, os_ = scheds(M.SCHED_LINEAR, 2.4, 0.3, 90, 7)
     g.set_schedule(gs)
@@ -377,19 +377,18 @@ def test_multispin_walkers_match_oracle(shape, pf):
 
 def test_multispin_launch_shapes_give_the_same_bits():
     """The one-launch multispin sweep at every tile shape (one row or plane
-    per tile, odd and even step counts, tiles that do not fill a wave), both
-    load depths, and the refresh levels drawn inside the sweep or ahead of
-    it on the side stream, agrees bit for bit with the per-half kernels,
-    for daemons and walkers."""
+    per tile, odd and even step counts, tiles that do not fill a wave, a
+    last tile along y shorter than the others), with the refresh levels
+    drawn inside the sweep or ahead of it on the side stream, agrees bit for
+    bit with the per-half kernels, for daemons and walkers."""
     shape = (256, 12, 6, 1, 2)
     ref = None
-    variants = [(0, 0, 0, 1, 1), (1, 0, 0, 1, 0), (1, 3, 2, 2, 0)] + [
-        (1, ty, tz, pf, 1) for ty in (1, 3, 4, 12) for tz in (1, 2, 3, 6) for pf in (1, 2)]
-    for fused, ty, tz, pf, ahead in variants:
+    variants = [(0, 0, 0, 1), (1, 0, 0, 0), (1, 3, 2, 0), (1, 5, 3, 0)] + [
+        (1, ty, tz, 1) for ty in (1, 3, 4, 5, 7, 12) for tz in (1, 2, 3, 6)]
+    for fused, ty, tz, ahead in variants:
         g = M.Lattice(*shape, seed=2025)
         g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_MULTISPIN)
         g.set_option(M.OPT_MSC_FUSED, fused)
-        g.set_option(M.OPT_PREFETCH, pf)
         g.set_option(M.OPT_DRAW_AHEAD, ahead)
         if ty:
             g.set_option(M.OPT_TILE_Y, ty)
@@ -404,10 +403,10 @@ def test_multispin_launch_shapes_give_the_same_bits():
             ref = got
         elif fused and len(ref) == 3:
             ref_w = got[3:]
-            assert all(np.array_equal(a, b) for a, b in zip(ref, got[:3])), (ty, tz, pf, ahead)
+            assert all(np.array_equal(a, b) for a, b in zip(ref, got[:3])), (ty, tz, ahead)
             ref = ref + ref_w
         else:
-            assert all(np.array_equal(a, b) for a, b in zip(ref, got)), (fused, ty, tz, pf, ahead)
+            assert all(np.array_equal(a, b) for a, b in zip(ref, got)), (fused, ty, tz, ahead)
         g.close()
 
 
@@ -535,7 +534,7 @@ def test_every_launch_shape_gives_the_same_bits():
 
 def test_tile_options_are_validated():
     g = M.Lattice(64, 12, 10, seed=1)
-    for opt, v in ((M.OPT_TILE_Y, 5), (M.OPT_TILE_Z, 3), (M.OPT_SWEEP_KERNEL, 9)):
+    for opt, v in ((M.OPT_TILE_Y, 13), (M.OPT_TILE_Z, 3), (M.OPT_SWEEP_KERNEL, 9)):
         with pytest.raises(M.MicsaError) as e:
             g.set_option(opt, v)
         assert e.value.status == M.EINVAL
