@@ -887,9 +887,9 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
             {
                 TimedLaunch t(c, kTimeSweep);
                 const bool fresh = refresh && !use_drawn, walk = !refresh && c->pend_wander >= 0;
-                const auto kern = fresh  ? k_msc_sweep<true, false>
-                                  : walk ? k_msc_sweep<false, true>
-                                         : k_msc_sweep<false, false>;
+                const auto kern = fresh  ? k_msc_sweep<true, 0>
+                                  : walk ? (64 % m.W == 0 ? k_msc_sweep<false, 1> : k_msc_sweep<false, 2>)
+                                         : k_msc_sweep<false, 0>;
                 kern<<<sgrid, sblock, slds, c->stream>>>(c->g, m, f, c->ms, use_drawn ? c->mdr0 : c->md0,
                                                          use_drawn ? c->mdr1 : c->md1, c->mb, c->ms_alt,
                                                          c->md0_alt, c->md1_alt, c->tally, (uint32_t)rho, th,

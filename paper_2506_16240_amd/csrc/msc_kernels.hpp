@@ -225,17 +225,19 @@ struct MscTile {
 // branch; two register stages alternate (the loop is unrolled by two), so
 // that a value in flight is never copied; and the barrier orders LDS only.
 // The loads of step st + 1 are thus in flight through the whole of step st.
-// Walkers (WALK): the owed wandering's shift is applied when the levels are
-// used, from the word and its carry word loaded side by side.
+// Walkers (WALK > 0): the owed wandering's shift is applied when the levels
+// are used, with the carry word of the row's neighbouring word taken from the
+// lane that loaded it (WALK = 1; needs Lx / 128 to divide 64, so that a row's
+// lanes share a wave) or loaded beside the word (WALK = 2).
 // Grid (nty * ntz, L); block 64 ceil((TY + 4) W / 64); LDS 96 (TY + 4) W bytes.
 struct MscStage {
     uint64_t O, Es, J[6], me0, me1, mo0, mo1;
-    uint64_t mc0, mc1, oc0, oc1;  // WALK: carry words of the even and odd levels
+    uint64_t mc0, mc1, oc0, oc1;  // WALK = 2: carry words of the even and odd levels
 };
 
 constexpr int kMscSweepLanes = 256;  // largest work-group of the one-launch sweep (its register budget)
 
-template <bool REFRESH, bool WALK>
+template <bool REFRESH, int WALK>
 __global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(Geom g, MscGeom m, MscTile f, const uint64_t* __restrict__ spin_in,
                                                     const uint64_t* __restrict__ d0_in,
                                                     const uint64_t* __restrict__ d1_in,
@@ -245,6 +247,7 @@ __global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(Geom g, MscGeom
                                                     DaemonThresholds th, int wander)
 {
     static_assert(!(REFRESH && WALK), "a refresh sweep owes no wandering");
+    static_assert(WALK >= 0 && WALK <= 2, "WALK: 0 none, 1 carry by shuffle, 2 carry loaded");
     extern __shared__ uint64_t lds64[];
     const int W = m.W;
     const int rows_slots = f.TY + 4;
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(Geom g, MscGeom
             S.me1 = d1_in[he];
             S.mo0 = d0_in[ho];
             S.mo1 = d1_in[ho];
-            if (WALK) {
+            if (WALK == 2) {
                 const int qe = (yE + z2) & 1, qo = (yD + zo2) & 1;
                 const int64_t hec = he + carry(wander == 0 ? qe : qe - 1);
                 const int64_t hoc = ho + carry(wander == 0 ? -qo : 1 - qo);
@@ -331,6 +334,10 @@ __global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(Geom g, MscGeom
     long long so = 0, sn = 0;
     // step st: consumes stage S (loaded during step st - 1), loads step st + 1 into N
     auto step = [&](int st, MscStage& S, MscStage& N) {
+        // stage S is complete here: waiting for it once, unconditionally, lets
+        // the compiler see that no load of S is pending inside the branches
+        // below (vmcnt(0); expcnt and lgkmcnt left at their maximum)
+        __builtin_amdgcn_s_waitcnt(0x0F70);
         const int buf = st & 1, pb = buf ^ 1;
         const int zz = zstart + dz * st;  // unwrapped: owned iff in [z0, z0 + TZ)
         const int z = wrap(zz, g.Lz), zo = wrap(zz - dz, g.Lz);
@@ -343,10 +350,18 @@ __global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(Geom g, MscGeom
         if (WALK) {
             const int qe = (y + z) & 1, qo = (y + zo) & 1;
             const int she = wander == 0 ? qe : qe - 1, sho = wander == 0 ? -qo : 1 - qo;
-            me0 = shifted(me0, S.mc0, she);
-            me1 = shifted(me1, S.mc1, she);
-            mo0 = shifted(mo0, S.oc0, sho);
-            mo1 = shifted(mo1, S.oc1, sho);
+            uint64_t mc0 = S.mc0, mc1 = S.mc1, oc0 = S.oc0, oc1 = S.oc1;
+            if (WALK == 1) {  // every lane of the row holds its own word of the same row
+                const int re = (ry * W + (she > 0 ? wn : wp)) & 63, ro = (ry * W + (sho > 0 ? wn : wp)) & 63;
+                mc0 = __shfl(me0, re, 64);
+                mc1 = __shfl(me1, re, 64);
+                oc0 = __shfl(mo0, ro, 64);
+                oc1 = __shfl(mo1, ro, 64);
+            }
+            me0 = shifted(me0, mc0, she);
+            me1 = shifted(me1, mc1, she);
+            mo0 = shifted(mo0, oc0, sho);
+            mo1 = shifted(mo1, oc1, sho);
         }
         if (st + 1 < steps) load(st + 1, N);
         if (do_even) {
