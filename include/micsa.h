@@ -216,7 +216,8 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      divides Ly (else the automatic choice), the multispin sweep as given,
      its last tile along y holding the rows left over.
    MICSA_OPT_XCD_MAP: 1 (default) assigns neighbouring tiles of the fused
-     sweep to the same XCD (shared L2 for halo reads); 0 = plain order.
+     and one-launch multispin sweeps to the same XCD (shared L2 for halo
+     reads); 0 = plain order.
    MICSA_OPT_GRAPHS: 1 replays the per-half paths (bit-plane layout; byte
      lattices using neither the resident nor the fused sweep) as captured
      HIP graphs of 16 sweeps; 0 (default) launches every kernel, which is

@@ -778,6 +778,7 @@ MscTile msc_tile(const micsa_ctx* c)
     f.TZ = c->tile_z ? c->tile_z : divisor_at_most(c->p.Lz, 8);
     f.nty = (c->p.Ly + f.TY - 1) / f.TY;
     f.ntz = c->p.Lz / f.TZ;
+    f.xcd = c->xcd_map && (f.nty * f.ntz) % 8 == 0;
     return f;
 }
 

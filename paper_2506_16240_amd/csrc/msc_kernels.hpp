@@ -202,8 +202,9 @@ __device__ __forceinline__ uint64_t msc_move(uint64_t s, uint64_t a, uint64_t b,
 }
 
 struct MscTile {
-    int32_t TY, TZ;  // rows (divides Ly) and planes (divides Lz) a work-group owns
+    int32_t TY, TZ;  // rows and planes (divides Lz) a work-group owns
     int32_t nty, ntz;
+    int32_t xcd;  // 1: tiles numbered XCD by XCD (tiles per lattice divisible by 8)
 };
 
 // One whole sweep per launch (both halves), marching along z like the byte
@@ -255,7 +256,14 @@ __global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(Geom g, MscGeom
     auto LP = [&](int buf, int k) { return lds64 + ((size_t)buf * 6 + k) * ps; };  // 0 odd, 1 even, 2 Mx, 3 Px, 4 My, 5 Py
 
     const int l = blockIdx.y;
-    const int ty = blockIdx.x / f.ntz, tz = blockIdx.x - (blockIdx.x / f.ntz) * f.ntz;
+    // Work-groups go round-robin over the 8 XCDs (block b on XCD b % 8), each
+    // with its own L2; with xcd set XCD x takes the contiguous tiles [x T/8,
+    // (x + 1) T/8) (z fastest), so that neighbouring tiles, which read each
+    // other's ring rows and planes at the same time (the z direction of the
+    // march alternates from tile to tile), share an L2.
+    int t = blockIdx.x;
+    if (f.xcd) t = (t & 7) * (f.nty * f.ntz / 8) + (t >> 3);
+    const int ty = t / f.ntz, tz = t - ty * f.ntz;
     const int y0 = ty * f.TY, z0 = tz * f.TZ;
     const int dz = (tz & 1) ? -1 : 1;
     const int zstart = dz > 0 ? z0 - 1 : z0 + f.TZ;

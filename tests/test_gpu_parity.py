@@ -378,18 +378,20 @@ def test_multispin_walkers_match_oracle(shape):
 def test_multispin_launch_shapes_give_the_same_bits():
     """The one-launch multispin sweep at every tile shape (one row or plane
     per tile, odd and even step counts, tiles that do not fill a wave, a
-    last tile along y shorter than the others), with the refresh levels
-    drawn inside the sweep or ahead of it on the side stream, agrees bit for
-    bit with the per-half kernels, for daemons and walkers."""
+    last tile along y shorter than the others; tiles in plain or XCD order),
+    with the refresh levels drawn inside the sweep or ahead of it on the
+    side stream, agrees bit for bit with the per-half kernels, for daemons
+    and walkers."""
     shape = (256, 12, 6, 1, 2)
     ref = None
-    variants = [(0, 0, 0, 1), (1, 0, 0, 0), (1, 3, 2, 0), (1, 5, 3, 0)] + [
-        (1, ty, tz, 1) for ty in (1, 3, 4, 5, 7, 12) for tz in (1, 2, 3, 6)]
-    for fused, ty, tz, ahead in variants:
+    variants = [(0, 0, 0, 1, 1), (1, 0, 0, 0, 1), (1, 3, 2, 0, 1), (1, 5, 3, 0, 1), (1, 3, 3, 1, 0), (1, 1, 1, 1, 0)] + [
+        (1, ty, tz, 1, 1) for ty in (1, 3, 4, 5, 7, 12) for tz in (1, 2, 3, 6)]  # 24, 72, 8 tiles: XCD order
+    for fused, ty, tz, ahead, xcd in variants:
         g = M.Lattice(*shape, seed=2025)
         g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_MULTISPIN)
         g.set_option(M.OPT_MSC_FUSED, fused)
         g.set_option(M.OPT_DRAW_AHEAD, ahead)
+        g.set_option(M.OPT_XCD_MAP, xcd)
         if ty:
             g.set_option(M.OPT_TILE_Y, ty)
             g.set_option(M.OPT_TILE_Z, tz)
@@ -403,10 +405,10 @@ def test_multispin_launch_shapes_give_the_same_bits():
             ref = got
         elif fused and len(ref) == 3:
             ref_w = got[3:]
-            assert all(np.array_equal(a, b) for a, b in zip(ref, got[:3])), (ty, tz, ahead)
+            assert all(np.array_equal(a, b) for a, b in zip(ref, got[:3])), (ty, tz, ahead, xcd)
             ref = ref + ref_w
         else:
-            assert all(np.array_equal(a, b) for a, b in zip(ref, got)), (fused, ty, tz, ahead)
+            assert all(np.array_equal(a, b) for a, b in zip(ref, got)), (fused, ty, tz, ahead, xcd)
         g.close()
 
 
