@@ -5,6 +5,7 @@
 // tally per lattice.  Every entry point validates its arguments, enqueues
 // kernels on the context's stream and reports failures as status codes.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <cstdio>
@@ -886,15 +887,41 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
             const bool use_drawn = refresh && ahead && drawn == k;
             if (use_drawn) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->draw_done, 0));
             {
-                TimedLaunch t(c, kTimeSweep);
                 const bool fresh = refresh && !use_drawn, walk = !refresh && c->pend_wander >= 0;
                 const auto kern = fresh  ? k_msc_sweep<true, 0>
                                   : walk ? (64 % m.W == 0 ? k_msc_sweep<false, 1> : k_msc_sweep<false, 2>)
                                          : k_msc_sweep<false, 0>;
-                kern<<<sgrid, sblock, slds, c->stream>>>(c->g, m, f, c->ms, use_drawn ? c->mdr0 : c->md0,
-                                                         use_drawn ? c->mdr1 : c->md1, c->mb, c->ms_alt,
-                                                         c->md0_alt, c->md1_alt, c->tally, (uint32_t)rho, th,
-                                                         refresh ? -1 : c->pend_wander);
+                // arguments typed as the kernel declares them
+                Geom a_g = c->g;
+                MscGeom a_m = m;
+                MscTile a_f = f;
+                const uint64_t *a_s = c->ms, *a_d0 = use_drawn ? c->mdr0 : c->md0,
+                               *a_d1 = use_drawn ? c->mdr1 : c->md1, *a_b = c->mb;
+                uint64_t *o_s = c->ms_alt, *o_d0 = c->md0_alt, *o_d1 = c->md1_alt;
+                unsigned long long* a_t = c->tally;
+                uint32_t a_rho = (uint32_t)rho;
+                DaemonThresholds a_th = th;
+                int a_w = refresh ? -1 : c->pend_wander;
+                void* args[] = {&a_g, &a_m, &a_f, &a_s, &a_d0, &a_d1, &a_b, &o_s, &o_d0, &o_d1, &a_t, &a_rho, &a_th, &a_w};
+                // with timing on, the events belong to the dispatch itself and
+                // time the kernel alone (separate event packets around it add
+                // a few microseconds per launch)
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (c->timing && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
+                    if (e0) (void)hipEventDestroy(e0);
+                    e0 = e1 = nullptr;
+                }
+                const hipError_t le =
+                    hipExtLaunchKernel((const void*)kern, sgrid, sblock, args, slds, c->stream, e0, e1, 0);
+                if (e0 && e1) {
+                    if (le == hipSuccess) {
+                        c->events[kTimeSweep].push_back({e0, e1});
+                    } else {
+                        (void)hipEventDestroy(e0);
+                        (void)hipEventDestroy(e1);
+                    }
+                }
+                if (le != hipSuccess) return fail(c, MICSA_EHIP, std::string("k_msc_sweep: ") + hipGetErrorString(le));
             }
             if ((st = check_launch(c, "k_msc_sweep"))) return st;
             if (use_drawn && (drawn = next_refresh(c, k + 1, k_end)) >= 0 && (st = draw_levels(c, m, drawn)))

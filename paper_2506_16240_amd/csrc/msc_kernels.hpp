@@ -249,6 +249,10 @@ __global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(Geom g, MscGeom
 {
     static_assert(!(REFRESH && WALK), "a refresh sweep owes no wandering");
     static_assert(WALK >= 0 && WALK <= 2, "WALK: 0 none, 1 carry by shuffle, 2 carry loaded");
+    // issue ahead of the refresh draw that runs beside the sweeps (its waves
+    // keep the default priority 0 and fill the slots the sweep leaves while it
+    // waits on memory)
+    __builtin_amdgcn_s_setprio(1);
     extern __shared__ uint64_t lds64[];
     const int W = m.W;
     const int rows_slots = f.TY + 4;
