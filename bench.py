@@ -382,8 +382,15 @@ def main() -> int:
     # (per-half kernels), one sweep, or two sweeps in one pass over the state;
     # the algorithmic bytes per launch are those of one pass over the sites
     # it touches: bytes per update x sites x min(1, sweeps per launch).
+    # The average launch duration is the timed region (HIP events on the
+    # library's stream around the whole region, no per-launch events) over its
+    # launches: an upper bound on the kernel's own duration, since the region
+    # also holds the gaps between launches and any other kernel of the path.
+    # Per-launch events (the second region) slow the launches and include
+    # dispatch latency; their average is reported beside it.
     sweeps_per_launch = sweeps / mk["kernel_launches"]
-    avg_ms = mk["kernel_ms"] / mk["kernel_launches"]
+    avg_ms = mi["ms"] / mk["kernel_launches"]
+    event_ms = mk["kernel_ms"] / mk["kernel_launches"]
     per_update = BYTES_PER_UPDATE_BITPLANE if layout else BYTES_PER_UPDATE[algo_name]
     if "k_wander" in mi["kernel"]:  # a separate wandering kernel moves every daemon byte once more
         per_update += 2.0
@@ -413,6 +420,7 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": mi["kernel"], "avg_launch_ms": round(avg_ms, 5),
+                     "event_launch_ms": round(event_ms, 5),
                      "bytes_per_launch": bytes_launch, "launches": mk["kernel_launches"],
                      "sweeps_per_launch": round(sweeps_per_launch, 3),
                      "bytes_per_update": round(bytes_launch / (sweeps_per_launch * w.N * w.lattices), 3)},
