@@ -336,7 +336,11 @@ bool fused_eligible(const micsa_ctx* c)
     return !c->bit && c->gamma == 1 && c->p.Lx % 32 == 0 && 5 * (c->p.Lx / 32) <= 1024;
 }
 
-bool msc_eligible(const micsa_ctx* c) { return !c->bit && c->gamma == 1 && c->p.Lx % 128 == 0; }
+// (the one-launch sweep addresses a plane with 32-bit byte offsets: fewer than 2^29 words)
+bool msc_eligible(const micsa_ctx* c)
+{
+    return !c->bit && c->gamma == 1 && c->p.Lx % 128 == 0 && (int64_t)c->g.rows * (c->p.Lx / 128) < (int64_t(1) << 29);
+}
 
 // AUTO takes the multispin planes for MicSA calls of at least kMscMinSweeps
 // sweeps on lattices the resident kernel does not hold (a call packs and

@@ -172,24 +172,35 @@ __device__ __forceinline__ void msc_draw2(const Geom& g, int row, int w, int q, 
     }
 }
 
-// The Creutz move on a word: s the spins, six neighbour and coupling words
-// per direction (nb ^ j), m0/m1 the levels (updated); returns the new spins
-// and adds the level sums before/after to so/sn.
-__device__ __forceinline__ uint64_t msc_move(uint64_t s, uint64_t a, uint64_t b, uint64_t c, uint64_t d, uint64_t e,
-                                             uint64_t f, uint64_t& m0, uint64_t& m1, long long& so, long long& sn)
+// Three-input XOR and majority of 64-bit words, one v_bitop3 per 32-bit half
+// (truth tables 0x96 and 0xE8, the same for any order of the operands).
+__device__ __forceinline__ uint64_t xor3(uint64_t a, uint64_t b, uint64_t c)
 {
-    a ^= s;
-    b ^= s;
-    c ^= s;
-    d ^= s;
-    e ^= s;
-    f ^= s;
-    const uint64_t s1 = a ^ b ^ c, c1 = maj3(a, b, c);
-    const uint64_t s2 = d ^ e ^ f, c2 = maj3(d, e, f);
+    const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, 0x96);
+    const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), 0x96);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+__device__ __forceinline__ uint64_t maj3w(uint64_t a, uint64_t b, uint64_t c)
+{
+    const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, 0xE8);
+    const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), 0xE8);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// The Creutz move on a word: s the spins, n[] the six neighbour words and j[]
+// the six coupling words (+x, -x, +y, -y, +z, -z), m0/m1 the levels (updated);
+// returns the new spins and adds the level sums before/after to so/sn.
+__device__ __forceinline__ uint64_t msc_move(uint64_t s, const uint64_t (&n)[6], const uint64_t (&j)[6], uint64_t& m0,
+                                             uint64_t& m1, long long& so, long long& sn)
+{
+    const uint64_t a = xor3(s, n[0], j[0]), b = xor3(s, n[1], j[1]), c = xor3(s, n[2], j[2]);
+    const uint64_t d = xor3(s, n[3], j[3]), e = xor3(s, n[4], j[4]), f = xor3(s, n[5], j[5]);
+    const uint64_t s1 = xor3(a, b, c), c1 = maj3w(a, b, c);
+    const uint64_t s2 = xor3(d, e, f), c2 = maj3w(d, e, f);
     const uint64_t u0 = s1 ^ s2, k0 = s1 & s2;
-    const uint64_t u1 = c1 ^ c2 ^ k0, u2 = maj3(c1, c2, k0);
+    const uint64_t u1 = xor3(c1, c2, k0), u2 = maj3w(c1, c2, k0);
     const uint64_t w0 = m0 ^ u0, cw0 = m0 & u0;
-    const uint64_t w1 = m1 ^ u1 ^ cw0, cw1 = maj3(m1, u1, cw0);
+    const uint64_t w1 = xor3(m1, u1, cw0), cw1 = maj3w(m1, u1, cw0);
     const uint64_t w2 = u2 ^ cw1, w3 = u2 & cw1;
     const uint64_t acc = ~w3 & (w2 ^ (w1 & w0));
     const uint64_t n0 = (acc & ~w0) | (~acc & m0);
@@ -286,16 +297,28 @@ __global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(Geom g, MscGeom
     const int wn = w + 1 == W ? 0 : w + 1, wp = w == 0 ? W - 1 : w - 1;
     const int me = ry * W + w;
 
+    // Addresses: a uniform base per plane (scalar registers) and a 32-bit
+    // word offset within the plane (the plane holds fewer than 2^29 words),
+    // the lane's row part fixed and the z part uniform per step.
     const int64_t lp = (int64_t)l * 2 * m.plane;  // parity-0 plane of lattice l
     const uint64_t* ev_in = spin_in + lp;
     const uint64_t* od_in = spin_in + lp + m.plane;
     const uint64_t* bl = bond + (int64_t)l * 6 * m.plane;
-    auto at = [&](int yy, int zz) { return ((int64_t)yy + (int64_t)g.Ly * zz) * W + w; };
+    const uint32_t zstride = (uint32_t)(g.Ly * W);
+    const uint32_t rO = (uint32_t)(yO * W + w), rE = (uint32_t)(yE * W + w), rD = (uint32_t)(yD * W + w),
+                   rY = (uint32_t)(y * W + w);
+    auto zoff = [&](int zz) { return (uint32_t)zz * zstride; };
+    auto ld = [](const uint64_t* base, uint32_t i) {
+        return *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(base) + (i << 3));
+    };
+    auto st8 = [](uint64_t* base, uint32_t i, uint64_t v) {
+        *reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(base) + (i << 3)) = v;
+    };
     const uint32_t rr = (uint32_t)(l % g.R), sw = stream_word(kStreamDaemon, (uint32_t)(l / g.R));
     const int steps = f.TZ + 2;
 
-    uint64_t O_prev = od_in[at(yO, wrap(zstart - dz, g.Lz))];  // old odd spins at z - dz, z, z + dz
-    uint64_t O_cur = od_in[at(yO, wrap(zstart, g.Lz))];
+    uint64_t O_prev = ld(od_in, zoff(wrap(zstart - dz, g.Lz)) + rO);  // old odd spins at z - dz, z, z + dz
+    uint64_t O_cur = ld(od_in, zoff(wrap(zstart, g.Lz)) + rO);
     uint64_t O_next = 0;
     uint64_t E0 = 0, E1 = 0, E2 = 0;     // new even spins at z, z - dz, z - 2dz
     uint64_t MZ0 = 0, MZ1 = 0, MZ2 = 0;  // even couplings -z at z, z - dz, z - 2dz
@@ -307,7 +330,7 @@ __global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(Geom g, MscGeom
     // site k + q (wander = 0), odd site k with even site k + 1 - q (wander =
     // 1): the levels move by 0 or +-1 site across the two parities' planes,
     // with the carry from the neighbouring word of the row.
-    auto carry = [&](int sh) { return (int64_t)(sh > 0 ? wn - w : wp - w); };
+    auto carry = [&](int sh) { return (uint32_t)(sh > 0 ? wn - w : wp - w); };  // modulo 2^32
     auto shifted = [](uint64_t v, uint64_t c, int sh) {
         return sh > 0 ? shift_next(v, c) : sh < 0 ? shift_prev(v, c) : v;
     };
@@ -315,31 +338,32 @@ __global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(Geom g, MscGeom
     auto load = [&](int st2, MscStage& S) {
         const int zz2 = zstart + dz * st2;
         const int z2 = wrap(zz2, g.Lz);
-        S.O = od_in[at(yO, wrap(zz2 + dz, g.Lz))];
-        const int64_t h = at(yE, z2);
-        S.Es = ev_in[h];
+        S.O = ld(od_in, zoff(wrap(zz2 + dz, g.Lz)) + rO);
+        const uint32_t h = zoff(z2) + rE;
+        S.Es = ld(ev_in, h);
 #pragma unroll
-        for (int d = 0; d < 6; ++d) S.J[d] = bl[(int64_t)d * m.plane + h];
+        for (int d = 0; d < 6; ++d) S.J[d] = ld(bl + (int64_t)d * m.plane, h);
         if (!REFRESH) {
             // even levels of plane z2 (walkers: from the odd planes); odd
             // levels of plane z2 - dz (walkers: from the even planes), which
             // before the first odd step repeat the even-level words
-            const int64_t he = lp + (WALK ? m.plane : 0) + h;
+            const int64_t pe = lp + (WALK ? m.plane : 0);
             const bool odd_ok = st2 >= 2;
             const int zo2 = wrap(zz2 - dz, g.Lz);
-            const int64_t ho = odd_ok ? lp + (WALK ? 0 : m.plane) + at(yD, zo2) : he;
-            S.me0 = d0_in[he];
-            S.me1 = d1_in[he];
-            S.mo0 = d0_in[ho];
-            S.mo1 = d1_in[ho];
+            const int64_t po = odd_ok ? lp + (WALK ? 0 : m.plane) : pe;
+            const uint32_t ho = odd_ok ? zoff(zo2) + rD : h;
+            S.me0 = ld(d0_in + pe, h);
+            S.me1 = ld(d1_in + pe, h);
+            S.mo0 = ld(d0_in + po, ho);
+            S.mo1 = ld(d1_in + po, ho);
             if (WALK == 2) {
                 const int qe = (yE + z2) & 1, qo = (yD + zo2) & 1;
-                const int64_t hec = he + carry(wander == 0 ? qe : qe - 1);
-                const int64_t hoc = ho + carry(wander == 0 ? -qo : 1 - qo);
-                S.mc0 = d0_in[hec];
-                S.mc1 = d1_in[hec];
-                S.oc0 = d0_in[hoc];
-                S.oc1 = d1_in[hoc];
+                const uint32_t hec = h + carry(wander == 0 ? qe : qe - 1);
+                const uint32_t hoc = ho + carry(wander == 0 ? -qo : 1 - qo);
+                S.mc0 = ld(d0_in + pe, hec);
+                S.mc1 = ld(d1_in + pe, hec);
+                S.oc0 = ld(d0_in + po, hoc);
+                S.oc1 = ld(d1_in + po, hoc);
             }
         }
     };
@@ -402,14 +426,15 @@ __global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(Geom g, MscGeom
             const uint64_t nyp = Op[me + W], nym = Op[me - W];
             const uint64_t nzp = dz > 0 ? O_next : O_prev, nzm = dz > 0 ? O_prev : O_next;
             long long a = 0, b = 0;
-            E0 = msc_move(Es, nxp ^ J[kPx], nxm ^ J[kMx], nyp ^ J[kPy], nym ^ J[kMy], nzp ^ J[kPz], nzm ^ J[kMz],
-                          me0, me1, a, b);
+            const uint64_t nb[6] = {nxp, nxm, nyp, nym, nzp, nzm};
+            const uint64_t jb[6] = {J[kPx], J[kMx], J[kPy], J[kMy], J[kPz], J[kMz]};
+            E0 = msc_move(Es, nb, jb, me0, me1, a, b);
             LP(buf, 1)[me] = E0;
             if (do_odd && own_e) {
-                const int64_t h = lp + at(y, z);
-                spin_out[h] = E0;
-                d0_out[h] = me0;
-                d1_out[h] = me1;
+                const uint32_t h = zoff(z) + rY;
+                st8(spin_out + lp, h, E0);
+                st8(d0_out + lp, h, me0);
+                st8(d1_out + lp, h, me1);
                 so += a;
                 sn += b;
             }
@@ -430,13 +455,14 @@ __global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(Geom g, MscGeom
             const uint64_t jyp = LP(pb, 4)[me + W], jym = LP(pb, 5)[me - W];
             const uint64_t jzp = dz > 0 ? MZ0 : MZ2, jzm = dz > 0 ? PZ2 : PZ0;
             long long a = 0, b = 0;
-            const uint64_t On = msc_move(O_prev, nxp ^ jxp, nxm ^ jxm, nyp ^ jyp, nym ^ jym, nzp ^ jzp, nzm ^ jzm,
-                                         mo0, mo1, a, b);
+            const uint64_t nb[6] = {nxp, nxm, nyp, nym, nzp, nzm};
+            const uint64_t jb[6] = {jxp, jxm, jyp, jym, jzp, jzm};
+            const uint64_t On = msc_move(O_prev, nb, jb, mo0, mo1, a, b);
             if (own_o) {
-                const int64_t ho = lp + m.plane + at(y, zo);
-                spin_out[ho] = On;
-                d0_out[ho] = mo0;
-                d1_out[ho] = mo1;
+                const uint32_t ho = zoff(zo) + rY;
+                st8(spin_out + lp + m.plane, ho, On);
+                st8(d0_out + lp + m.plane, ho, mo0);
+                st8(d1_out + lp + m.plane, ho, mo1);
                 so += a;
                 sn += b;
             }
