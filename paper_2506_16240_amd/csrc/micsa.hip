@@ -906,7 +906,8 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
                 uint32_t a_rho = (uint32_t)rho;
                 DaemonThresholds a_th = th;
                 int a_w = refresh ? -1 : c->pend_wander;
-                void* args[] = {&a_g, &a_m, &a_f, &a_s, &a_d0, &a_d1, &a_b, &o_s, &o_d0, &o_d1, &a_t, &a_rho, &a_th, &a_w};
+                void* args[] = {&a_g,  &a_m, &a_f, &a_s, &a_d0,  &a_d1, &a_b,
+                                &o_s,  &o_d0, &o_d1, &a_t, &a_rho, &a_th, &a_w};
                 // with timing on, the events belong to the dispatch itself and
                 // time the kernel alone (separate event packets around it add
                 // a few microseconds per launch)

@@ -177,13 +177,15 @@ __device__ __forceinline__ void msc_draw2(const Geom& g, int row, int w, int q, 
 __device__ __forceinline__ uint64_t xor3(uint64_t a, uint64_t b, uint64_t c)
 {
     const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, 0x96);
-    const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), 0x96);
+    const uint32_t hi =
+        __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), 0x96);
     return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 __device__ __forceinline__ uint64_t maj3w(uint64_t a, uint64_t b, uint64_t c)
 {
     const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, 0xE8);
-    const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), 0xE8);
+    const uint32_t hi =
+        __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), 0xE8);
     return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
@@ -221,27 +223,30 @@ struct MscTile {
 // One whole sweep per launch (both halves), marching along z like the byte
 // layout's fused sweep: at step st, with z = zstart + dz st, the even half
 // on plane z and the odd half on plane z - dz, whose even neighbours (planes
-// z - 2dz .. z) are then all final.  A work-group owns TY rows (the last
-// along y what is left of Ly) x TZ planes of one lattice, all words of a row; the even half also runs on one ring of
-// rows and planes and odd spins are read on two rings, so no tile needs
-// another tile's new values (state read from the "in" planes, written to the
-// "out" planes).  Lanes: (TY + 4) rows x W words; in-plane neighbours (rows
-// y +- 1, the x carry from words w +- 1) come through LDS, one buffer per
-// step parity (old odd spins, new even spins and the even sites' x and y
-// couplings of plane z); z neighbours through registers.  Each coupling
-// word is read once per sweep.  On refresh sweeps the even half draws both
-// parities' levels of its word and keeps the odd ones for the next step.
-// Loads and barriers: every lane issues every load of a step (a lane
-// outside a word's rows reads a row of its own tile instead, a line the
-// work-group fetches anyway), so that no load sits under a lane-dependent
-// branch; two register stages alternate (the loop is unrolled by two), so
-// that a value in flight is never copied; and the barrier orders LDS only.
-// The loads of step st + 1 are thus in flight through the whole of step st.
+// z - 2dz .. z) are then all final.  A work-group owns TY rows (the last tile
+// along y what is left of Ly) x TZ planes of one lattice, all words of a
+// row; the even half also runs on one ring of rows and planes and odd spins
+// are read on two rings, so no tile needs another tile's new values (state
+// read from the "in" planes, written to the "out" planes).  Lanes: (TY + 4)
+// rows x W words; in-plane neighbours (rows y +- 1, the x carry from words
+// w +- 1) come through LDS, one buffer per step parity (old odd spins, new
+// even spins and the even sites' x and y couplings of plane z); z neighbours
+// through registers.  Each coupling word is read once per sweep.
+// REFRESH: the even half draws both parities' levels of its word and keeps
+// the odd ones for the next step (used when the levels are not drawn ahead).
+// Loads and barriers: every lane issues every load of a step (a lane outside
+// a word's rows reads a row of its own tile instead, a line the work-group
+// fetches anyway), so that no load sits under a lane-dependent branch; two
+// register stages alternate (the loop is unrolled by two), so that a value in
+// flight is never copied; each step starts with one explicit wait for the
+// stage it uses; and the barrier orders LDS only.  The loads of step st + 1
+// are thus in flight through the whole of step st.
 // Walkers (WALK > 0): the owed wandering's shift is applied when the levels
 // are used, with the carry word of the row's neighbouring word taken from the
 // lane that loaded it (WALK = 1; needs Lx / 128 to divide 64, so that a row's
 // lanes share a wave) or loaded beside the word (WALK = 2).
-// Grid (nty * ntz, L); block 64 ceil((TY + 4) W / 64); LDS 96 (TY + 4) W bytes.
+// Grid (nty * ntz, L); block 64 ceil((TY + 4) W / 64) <= kMscSweepLanes;
+// LDS 96 (TY + 4) W bytes.
 struct MscStage {
     uint64_t O, Es, J[6], me0, me1, mo0, mo1;
     uint64_t mc0, mc1, oc0, oc1;  // WALK = 2: carry words of the even and odd levels
@@ -250,13 +255,11 @@ struct MscStage {
 constexpr int kMscSweepLanes = 256;  // largest work-group of the one-launch sweep (its register budget)
 
 template <bool REFRESH, int WALK>
-__global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(Geom g, MscGeom m, MscTile f, const uint64_t* __restrict__ spin_in,
-                                                    const uint64_t* __restrict__ d0_in,
-                                                    const uint64_t* __restrict__ d1_in,
-                                                    const uint64_t* __restrict__ bond, uint64_t* __restrict__ spin_out,
-                                                    uint64_t* __restrict__ d0_out, uint64_t* __restrict__ d1_out,
-                                                    unsigned long long* __restrict__ tally, uint32_t rho,
-                                                    DaemonThresholds th, int wander)
+__global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(
+    Geom g, MscGeom m, MscTile f, const uint64_t* __restrict__ spin_in, const uint64_t* __restrict__ d0_in,
+    const uint64_t* __restrict__ d1_in, const uint64_t* __restrict__ bond, uint64_t* __restrict__ spin_out,
+    uint64_t* __restrict__ d0_out, uint64_t* __restrict__ d1_out, unsigned long long* __restrict__ tally,
+    uint32_t rho, DaemonThresholds th, int wander)
 {
     static_assert(!(REFRESH && WALK), "a refresh sweep owes no wandering");
     static_assert(WALK >= 0 && WALK <= 2, "WALK: 0 none, 1 carry by shuffle, 2 carry loaded");
@@ -268,7 +271,8 @@ __global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(Geom g, MscGeom
     const int W = m.W;
     const int rows_slots = f.TY + 4;
     const int ps = rows_slots * W;
-    auto LP = [&](int buf, int k) { return lds64 + ((size_t)buf * 6 + k) * ps; };  // 0 odd, 1 even, 2 Mx, 3 Px, 4 My, 5 Py
+    // LDS planes per step buffer: 0 odd, 1 even, 2 Mx, 3 Px, 4 My, 5 Py
+    auto LP = [&](int buf, int k) { return lds64 + ((size_t)buf * 6 + k) * ps; };
 
     const int l = blockIdx.y;
     // Work-groups go round-robin over the 8 XCDs (block b on XCD b % 8), each
