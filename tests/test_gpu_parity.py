@@ -594,6 +594,23 @@ def test_bitplane_batched_L32_shape():
     same_state(g, o)
 
 
+def test_bitplane_long_calls_match_oracle():
+    """Bit-plane layout, calls of many sweeps with a refresh every 3 (the
+    refresh kernel ahead of each refresh sweep inside one call), against the
+    oracle; two lane groups, two replicas."""
+    g, o = bpair(32, 12, 10, 70, 2, seed=9090)
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.5, 0.4, 80, 3)
+    g.set_schedule(gs)
+    for n in (31, 1, 2, 17):
+        g.sweep(M.ALGO_MICSA, n)
+        o.run(O.ALGO_MICSA, os_, n)
+        same_state(g, o)
+    Eg, Dg = g.sweep_logged(M.ALGO_MICSA, 12, 4)
+    Eo, Do = o.run(O.ALGO_MICSA, os_, 12, 4)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    assert np.array_equal(g.overlap(0, 1), o.overlap(0, 1))
+
+
 def test_layouts_are_bit_identical():
     """The same seed gives the same trajectory in the byte and bit-plane layouts."""
     shape = (32, 12, 10, 70, 2)
