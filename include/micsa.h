@@ -214,7 +214,9 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      fused and one-launch multispin sweeps (0 = automatic).  TILE_Z must
      divide Lz.  TILE_Y is at most Ly; the fused byte sweep uses it where it
      divides Ly (else the automatic choice), the multispin sweep as given,
-     its last tile along y holding the rows left over.
+     its last tile along y holding the rows left over (a tile wider than 256
+     lanes, (tile_y + 4) * Lx / 128 > 256, runs the per-half multispin
+     kernels instead).
    MICSA_OPT_XCD_MAP: 1 (default) assigns neighbouring tiles of the fused
      and one-launch multispin sweeps to the same XCD (shared L2 for halo
      reads); 0 = plain order.
