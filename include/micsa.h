@@ -217,9 +217,13 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      its last tile along y holding the rows left over (a tile wider than 256
      lanes, (tile_y + 4) * Lx / 128 > 256, runs the per-half multispin
      kernels instead).
-   MICSA_OPT_XCD_MAP: 1 (default) assigns neighbouring tiles of the fused
-     and one-launch multispin sweeps to the same XCD (shared L2 for halo
-     reads); 0 = plain order.
+   MICSA_OPT_XCD_MAP: tile order over the 8 XCDs, for shared L2 among
+     neighbouring tiles' halo reads.  1 gives each XCD a contiguous range of
+     tiles (fused and one-launch multispin sweeps; needs the tile count
+     divisible by 8).  2 (default) gives each XCD a band of z tiles across
+     every y tile on the multispin sweep (needs the z-tile count divisible
+     by 8, else it falls back to 1), and acts as 1 on the fused byte sweeps.
+     0 is the plain order.
    MICSA_OPT_GRAPHS: 1 replays the per-half paths (bit-plane layout; byte
      lattices using neither the resident nor the fused sweep) as captured
      HIP graphs of 16 sweeps; 0 (default) launches every kernel, which is

@@ -79,7 +79,7 @@ struct micsa_ctx {
     // sweep kernel selection (MICSA_OPT_*)
     int32_t kernel_opt = MICSA_KERNEL_AUTO;
     int32_t tile_y = 0, tile_z = 0;
-    int32_t xcd_map = 1;  // XCD-aware tile order for the fused sweeps
+    int32_t xcd_map = 2;  // XCD-aware tile order for the fused sweeps (2: z bands on the multispin sweep)
     int32_t prefetch = 1;  // steps of loads in flight in the fused MicSA sweep (1 or 2)
     int32_t temporal = 2;  // MicSA sweeps per pass of the fused kernel (1 or 2)
     int32_t use_graphs = 0;
@@ -783,7 +783,7 @@ MscTile msc_tile(const micsa_ctx* c)
     f.TZ = c->tile_z ? c->tile_z : divisor_at_most(c->p.Lz, 8);
     f.nty = (c->p.Ly + f.TY - 1) / f.TY;
     f.ntz = c->p.Lz / f.TZ;
-    f.xcd = c->xcd_map && (f.nty * f.ntz) % 8 == 0;
+    f.xcd = c->xcd_map == 2 && f.ntz % 8 == 0 ? 2 : (c->xcd_map && (f.nty * f.ntz) % 8 == 0 ? 1 : 0);
     return f;
 }
 
@@ -1835,7 +1835,7 @@ int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value)
         ctx->prefetch = (int32_t)value;
         return MICSA_OK;
     case MICSA_OPT_XCD_MAP:
-        if (value != 0 && value != 1) return fail(ctx, MICSA_EINVAL, "xcd_map is 0 or 1");
+        if (value < 0 || value > 2) return fail(ctx, MICSA_EINVAL, "xcd_map is 0, 1 or 2");
         ctx->xcd_map = (int32_t)value;
         return MICSA_OK;
     case MICSA_OPT_TILE_Z:

@@ -217,7 +217,8 @@ __device__ __forceinline__ uint64_t msc_move(uint64_t s, const uint64_t (&n)[6],
 struct MscTile {
     int32_t TY, TZ;  // rows and planes (divides Lz) a work-group owns
     int32_t nty, ntz;
-    int32_t xcd;  // 1: tiles numbered XCD by XCD (tiles per lattice divisible by 8)
+    int32_t xcd;  // 1: tiles numbered XCD by XCD (tiles per lattice divisible by 8);
+                  // 2: XCD x takes the z band [x ntz/8, (x + 1) ntz/8) of every y tile (ntz divisible by 8)
 };
 
 // One whole sweep per launch (both halves), marching along z like the byte
@@ -280,9 +281,16 @@ __global__ __launch_bounds__(kMscSweepLanes, 3) void k_msc_sweep(
     // (x + 1) T/8) (z fastest), so that neighbouring tiles, which read each
     // other's ring rows and planes at the same time (the z direction of the
     // march alternates from tile to tile), share an L2.
-    int t = blockIdx.x;
-    if (f.xcd) t = (t & 7) * (f.nty * f.ntz / 8) + (t >> 3);
-    const int ty = t / f.ntz, tz = t - ty * f.ntz;
+    int t = blockIdx.x, ty, tz;
+    if (f.xcd == 2) {  // every y-neighbour and all but one z-neighbour in 8 on the same XCD
+        const int band = f.ntz >> 3, i = t >> 3;
+        ty = i / band;
+        tz = (t & 7) * band + (i - ty * band);
+    } else {
+        if (f.xcd) t = (t & 7) * (f.nty * f.ntz / 8) + (t >> 3);
+        ty = t / f.ntz;
+        tz = t - ty * f.ntz;
+    }
     const int y0 = ty * f.TY, z0 = tz * f.TZ;
     const int dz = (tz & 1) ? -1 : 1;
     const int zstart = dz > 0 ? z0 - 1 : z0 + f.TZ;

@@ -412,6 +412,28 @@ def test_multispin_launch_shapes_give_the_same_bits():
         g.close()
 
 
+def test_multispin_tile_orders_give_the_same_bits():
+    """Tiles in plain order, XCD by XCD, and in z bands per XCD (8 tiles
+    along z) give the same bits, for daemons and walkers."""
+    shape = (256, 12, 16, 1, 2)
+    ref = None
+    for xcd in (0, 1, 2):
+        g = M.Lattice(*shape, seed=2026)
+        g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_MULTISPIN)
+        g.set_option(M.OPT_XCD_MAP, xcd)
+        g.set_option(M.OPT_TILE_Y, 3)
+        g.set_option(M.OPT_TILE_Z, 2)
+        g.set_schedule(M.Schedule(M.SCHED_CONST, 0.8, 0.8, 60, 7))
+        g.sweep(M.ALGO_MICSA, 15)
+        g.sweep(M.ALGO_WALKERS, 11)
+        got = (g.spins(), g.daemons(), g.energy_tally())
+        if ref is None:
+            ref = got
+        else:
+            assert all(np.array_equal(a, b) for a, b in zip(ref, got)), xcd
+        g.close()
+
+
 def test_multispin_refused_where_it_does_not_apply():
     g, _ = pair(96, 4, 4)
     with pytest.raises(M.MicsaError):
