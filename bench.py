@@ -22,6 +22,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -140,8 +142,12 @@ def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None, layou
             "tally_check": ok, "kernel": name, "E_final": int(E[0]), "c4_ms": c4_ms}
 
 
-def cpu_baseline(w, seconds: float):
-    """The CPU oracle on a bounded sample of the same workload (sweep loop only)."""
+def cpu_baseline(w, seconds: float, configure_gpu=None, stream=None, single_core_seconds: float = 8.0):
+    """The CPU oracle on a bounded sample of the same workload (sweep loop
+    only, all host threads, then one thread), and a parity check: the GPU
+    path runs the same first K sweeps in one call with the launch options of
+    the timed region, and its spins, daemons, energy and daemon energy must
+    equal the oracle's bit for bit."""
     from oracle import oracle as O
 
     lat = O.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
@@ -155,10 +161,66 @@ def cpu_baseline(w, seconds: float):
         if el >= seconds or sweeps >= w.n_sweeps:
             break
     upd = w.N * w.lattices * sweeps
-    return {"value": round(upd / (el * 1e9), 4), "unit": "spin updates/ns", "cores": O.threads(),
-            "kind": "oracle",
-            "sample": f"MicSA sweeps 0..{sweeps - 1} of {w.name} ({sweeps} x {w.N * w.lattices} updates, "
-                      f"{el:.1f} s, init excluded)"}
+    out = {"value": round(upd / (el * 1e9), 4), "unit": "spin updates/ns", "cores": O.threads(),
+           "kind": "oracle",
+           "sample": f"MicSA sweeps 0..{sweeps - 1} of {w.name} ({sweeps} x {w.N * w.lattices} updates, "
+                     f"{el:.1f} s, init excluded)"}
+    parity = None
+    if configure_gpu is not None:
+        from paper_2506_16240_amd import micsa as M
+        g = M.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed, stream=stream.cuda_stream)
+        configure_gpu(g)
+        g.set_schedule(M.Schedule(w.kind, w.T0, w.T1, w.n_sweeps, w.period))
+        g.sweep(M.ALGO_MICSA, sweeps)
+        same = (np.array_equal(g.spins(), lat.sigma) and np.array_equal(g.daemons(), lat.m)
+                and np.array_equal(g.energy(), lat.energy()) and np.array_equal(g.daemon_energy(), lat.daemon_energy())
+                and np.array_equal(g.energy_tally(), lat.energy()))
+        parity = {"sweeps": sweeps, "calls": 1, "kernel": g.kernel_name(M.ALGO_MICSA), "bit_exact": bool(same)}
+        g.close()
+    del lat
+    # one core: the same sweeps from the start on one thread
+    n_all = O.threads()
+    O.set_threads(1)
+    try:
+        lat1 = O.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
+        s1 = 0
+        t = time.perf_counter()
+        while True:
+            lat1.run(O.ALGO_MICSA, sched, 1, 0)
+            s1 += 1
+            el1 = time.perf_counter() - t
+            if el1 >= single_core_seconds or s1 >= w.n_sweeps:
+                break
+        del lat1
+    finally:
+        O.set_threads(n_all)
+    out["single_core"] = {"value": round(w.N * w.lattices * s1 / (el1 * 1e9), 4), "unit": "spin updates/ns",
+                          "cores": 1, "sample": f"MicSA sweeps 0..{s1 - 1} of {w.name} ({el1:.1f} s)"}
+    return out, parity
+
+
+def copy_rate_gbs(stream, gib: float = 2.0, reps: int = 5) -> float:
+    """Device-to-device copy rate (bytes read + bytes written per second, GB/s),
+    the best of a few copies of `gib` GiB: the practical HBM ceiling beside
+    the 8 TB/s vendor figure."""
+    import torch
+
+    n = int(gib * (1 << 30))
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        b.copy_(a)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    return 2.0 * n / (best * 1e6)
 
 
 # Parallel tempering (App. C): the EMCS kernel is bound by integer VALU work
@@ -285,6 +347,8 @@ def main() -> int:
     ap.add_argument("--workload", default="anneal_L512_T3.0-0.2")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true",
+                    help="skip the GPU run of the oracle's sample that is compared with it bit for bit")
     ap.add_argument("--no-heatbath", action="store_true")
     ap.add_argument("--no-metropolis", action="store_true")
     ap.add_argument("--no-walkers", action="store_true",
@@ -300,7 +364,8 @@ def main() -> int:
     ap.add_argument("--kernel", choices=("auto", "fused", "multispin"), default="auto",
                     help="MicSA sweep kernel: library choice, the fused byte sweep, or multispin bit planes")
     ap.add_argument("--refresh", choices=("period", "log2"), default="period",
-                    help="refresh every period of the workload, or at t = 0 and t = 2^s (Sec. 2.7)")
+                    help="refresh every period of the workload, or before every sweep t with t + 1 a power "
+                         "of two (the procedure of Sec. 2.8.1: refresh, 2^s steps, refresh, ...)")
     ap.add_argument("--c4", type=int, default=0,
                     help="after the MicSA run, time this many C4(r) evaluations of the final state (R >= 2)")
     ap.add_argument("--copy-ref-gib", type=float, default=0.0,
@@ -399,6 +464,16 @@ def main() -> int:
     bytes_launch = per_update * w.N * w.lattices * min(1.0, sweeps_per_launch)
     achieved = bytes_launch / (avg_ms * 1e6)  # GB/s
     traffic = measured_traffic(mi["kernel"])
+    # what the timed kernel computes on: the multispin sweep holds 1-bit
+    # spin and coupling planes and 2-bit daemons as two planes (64 sites per
+    # 64-bit word); the bit-plane layout the same with 64 samples per word;
+    # the byte kernels one byte per spin and per daemon
+    if mi["kernel"].startswith("k_msc"):
+        layout_name, dtype = "multispin", "u1 bit planes (2-bit daemons)"
+    elif layout:
+        layout_name, dtype = "bitplane", "u1 bit planes (2-bit daemons)"
+    else:
+        layout_name, dtype = "byte", "u8"
     out = {
         "metric": "spin updates/ns (MicSA vs heat-bath, 1 GPU) + % of HBM roofline",
         "algo": algo_name,
@@ -411,11 +486,11 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u8",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": w.name, "L": [w.Lx, w.Ly, w.Lz], "samples": w.S, "replicas": w.R,
                    "sweeps_per_step": w.period, "sweeps": sweeps, "schedule": f"T {w.T0}->{w.T1}",
-                   "layout": args.layout, "kernel": mi["kernel"], "tile": list(tile) if tile else "auto",
+                   "layout": layout_name, "kernel": mi["kernel"], "tile": list(tile) if tile else "auto",
                    "gamma": args.gamma, "refresh": args.refresh},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -446,6 +521,9 @@ def main() -> int:
         out["checks"]["walkers_tally_equals_energy"] = wk["tally_check"]
         if mp is not None:
             out["walkers_over_metropolis"] = round(mp["ms"] / wk["ms"], 3)
+    copy_gbs = copy_rate_gbs(stream)
+    out["roofline"]["copy_GBs"] = round(copy_gbs, 1)
+    out["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
     if args.copy_ref_gib > 0:
         n = int(args.copy_ref_gib * (1 << 30))
         a = torch.ones(n, dtype=torch.uint8, device="cuda")
@@ -456,7 +534,22 @@ def main() -> int:
         del a, b
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        cfg = None
+        if not args.no_parity and algo_name == "micsa" and args.gamma == 1 and not layout:
+            def cfg(lat):
+                lat.set_option(M.OPT_SWEEP_KERNEL, kern)
+                if tile:
+                    lat.set_option(M.OPT_TILE_Y, tile[0])
+                    lat.set_option(M.OPT_TILE_Z, tile[1])
+                    if len(tile) > 2:
+                        lat.set_option(M.OPT_PREFETCH, tile[2])
+                    if len(tile) > 3:
+                        lat.set_option(M.OPT_TEMPORAL, tile[3])
+        cb, parity = cpu_baseline(w, args.cpu_seconds, cfg, stream)
+        out["cpu_baseline"] = cb
+        if parity is not None:
+            out["checks"]["oracle_parity_K"] = parity
+            log(f"oracle parity over the first {parity['sweeps']} sweeps: {parity['bit_exact']}")
     print(json.dumps(out), flush=True)
     return 0
 

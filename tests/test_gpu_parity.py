@@ -193,6 +193,31 @@ def test_anneal_L512_first_sweeps_full_size(prefetch, temporal, kernel):
     assert np.array_equal(g.energy_tally(), g.energy())
 
 
+@pytest.mark.parametrize("algo", [M.ALGO_MICSA, M.ALGO_WALKERS])
+def test_anneal_L512_default_launch_full_size(algo):
+    """The 512^3 anneal exactly as the benchmark times it: no launch option
+    (the library's own choice: the one-launch multispin sweep with its
+    automatic 44-row tile and ragged last y tile, z-band XCD order over the
+    z tiles, refresh levels drawn ahead on the side stream), 41 sweeps in ONE
+    call (refreshes before sweeps 0, 20 and 40, two of them drawn ahead
+    inside the call), then 3 more in a second call.  Spins, daemons, energy,
+    daemon energy and the tally equal the oracle's bit for bit."""
+    w = W.ANNEAL_L512
+    g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
+    gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
+    g.set_schedule(gs)
+    oalgo = O.ALGO_MICSA if algo == M.ALGO_MICSA else O.ALGO_WALKERS
+    for n in (41, 3):
+        g.sweep(algo, n)
+        o.run(oalgo, os_, n, 0)
+        assert g.kernel_name(algo) == "k_msc_sweep"
+        same_state(g, o)
+        E = o.energy()
+        assert np.array_equal(g.energy(), E)
+        assert np.array_equal(g.daemon_energy(), o.daemon_energy())
+        assert np.array_equal(g.energy_tally(), E)
+
+
 @pytest.mark.parametrize("algo", [M.ALGO_HEATBATH, M.ALGO_METROPOLIS])
 def test_anneal_L512_baseline_first_sweeps_full_size(algo):
     """The heat-bath and Metropolis baselines on the 512^3 lattice: first 6
@@ -800,3 +825,31 @@ def test_two_sweep_pass_matches_oracle(shape, ty, tz, period):
     assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
     same_state(g, o)
     assert np.array_equal(g.energy_tally(), o.energy())
+
+
+def test_autotuner_gate_and_choice_match_oracle(tmp_path, monkeypatch):
+    """The fused-sweep tuner on a small lattice: every candidate passes its
+    bit-exact gate against the per-half kernel (tune raises otherwise), the
+    cache is keyed and written, and the chosen launch shape reproduces the
+    oracle's trajectory."""
+    from paper_2506_16240_amd import tune
+
+    monkeypatch.setattr(tune, "CACHE_PATH", str(tmp_path / "tune_cache.json"))
+    shape = (128, 12, 8, 1, 2)
+    best = tune.tune(*shape, sweeps=6, use_cache=True)
+    assert (best.ty, best.tz) in tune.candidates(*shape[:3])
+    assert best.us_per_sweep > 0
+    again = tune.tune(*shape, sweeps=6, use_cache=True)  # from the cache
+    assert again == best
+    g, o = pair(*shape, seed=0x7E58)
+    g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)
+    g.set_option(M.OPT_TILE_Y, best.ty)
+    g.set_option(M.OPT_TILE_Z, best.tz)
+    g.set_option(M.OPT_PREFETCH, best.prefetch)
+    g.set_option(M.OPT_TEMPORAL, best.temporal)
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.5, 0.5, 30, 4)
+    g.set_schedule(gs)
+    Eg, Dg = g.sweep_logged(M.ALGO_MICSA, 30, 5)
+    Eo, Do = o.run(O.ALGO_MICSA, os_, 30, 5)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    same_state(g, o)

@@ -456,6 +456,51 @@ def test_equilibrium_energy_matches_enumeration(shape, T, period):
         assert abs(mean - exact) <= 4.5 * err + 1e-9, (algo, mean, exact, err)
 
 
+@pytest.fixture(scope="module")
+def dos_2x4x4():
+    """Exact density of states of one 2x4x4 sample: all 2^32 spin states
+    (Gray code with the local field giving each dH), as exact counts."""
+    L = O.Lattice(2, 4, 4, 1, 1, seed=0x5EED0244)
+    g = O.density_of_states(2, 4, 4, L.J[0])
+    return L.J[0].copy(), g
+
+
+def test_density_of_states_2x4x4_invariants(dos_2x4x4):
+    J, g = dos_2x4x4
+    N = 32
+    assert int(g.sum()) == 2**N
+    assert (g % 2 == 0).all()  # global spin flip
+    H = -3 * N + 2 * np.arange(3 * N + 1, dtype=np.int64)
+    assert int((H * g.astype(np.int64)).sum()) == 0  # sum over states of H is 0
+    # second moment: sum_s H^2 = 2^N sum_{b,b'} J_b J_b' [b, b' join the same
+    # two sites].  Along the side of 2 the forward x-bonds of x = 0 and x = 1
+    # join the same pair (reading: two distinct couplings), so
+    # sum_s H^2 = 2^N (3N + 2 sum_{pairs} J_x(x=0) J_x(x=1)).
+    c = 1 - 2 * (J.astype(np.int64) & 1)
+    cross = int((c[0::2] * c[1::2]).sum())
+    assert int(((H * H) * g.astype(object)).sum()) == 2**N * (3 * N + 2 * cross)
+    # the energy is 2U - 3N with U unsatisfied bonds: only even shifts occur
+    assert g[::2].sum() + g[1::2].sum() == 2**N
+
+
+@pytest.mark.parametrize("T,period", [(1.5, 10), (2.0, 1), (3.0, 5)])
+def test_equilibrium_energy_2x4x4_matches_enumeration(dos_2x4x4, T, period):
+    """<H>_beta of the 2x4x4 sample (the largest lattice enumerated, with
+    distinct couplings along its sides of 4) against long MicSA, heat-bath
+    and Metropolis runs of the same sample, each over 32 replicas."""
+    J, g = dos_2x4x4
+    exact = O.canonical_mean_energy(g, 32, T)
+    n = 6000
+    sched = O.Schedule(O.SCHED_CONST, T, T, n, period)
+    for algo in (O.ALGO_MICSA, O.ALGO_HEATBATH, O.ALGO_METROPOLIS):
+        X = O.Lattice(2, 4, 4, 1, 32, seed=0x5EED0244)
+        assert np.array_equal(X.J[0], J)
+        E_log, _ = X.run(algo, sched, n, 1)
+        series = E_log[n // 5:].mean(axis=1)
+        mean, err = _batch_mean(series)
+        assert abs(mean - exact) <= 4.5 * err + 1e-9, (algo, mean, exact, err)
+
+
 # -------------------------------------------------------------- schedule
 def test_schedule_semantics():
     s = O.Schedule(O.SCHED_LINEAR, 3.0, 0.2, 10000, 20)
@@ -1121,3 +1166,117 @@ def test_pt_equilibrium_brute_force(algo):
         for got, want in ((e_run[:, t], exact_e[t]), (q_run[:, t], exact_q[t])):
             err = got.std(ddof=1) / math.sqrt(runs)
             assert abs(got.mean() - want) < 4.5 * err + 2e-3, (t, got.mean(), want, err)
+
+
+# ---------------------------------------------------------- initial state
+# Sec. 2.1: every coupling is +-1 with probability 1/2, independently per
+# bond; Sec. 3: the runs start from a fully disordered (infinite-temperature)
+# configuration, i.e. independent fair spins.  These pins test the oracle's
+# initial state against those distributions: balance per axis, independence
+# of the three bonds of a site, of neighbouring sites and of samples and
+# replicas.  Thresholds are 5 standard deviations (or a chi^2 tail of about
+# 1e-7), so a correct generator fails them with negligible probability and
+# any structural mistake (a shared output word, a counter that ignores the
+# sample, the site or the replica) fails them by hundreds of sigma.
+def _fair_z(count, n):
+    """z-score of `count` successes in n fair Bernoulli trials."""
+    return (count - 0.5 * n) / math.sqrt(0.25 * n)
+
+
+def _chi2_uniform(counts):
+    counts = np.asarray(counts, np.float64)
+    e = counts.sum() / len(counts)
+    return float(((counts - e) ** 2 / e).sum())
+
+
+# chi^2 critical values with tail probability about 1e-7
+_CHI2_CRIT = {3: 35.3, 7: 44.6, 15: 57.7, 63: 143.0}
+
+
+def test_initial_couplings_are_fair_per_axis():
+    L = O.Lattice(32, 32, 32, 8, 1, seed=0x5EED0007)
+    assert L.J.max() <= 7
+    for mu in range(3):
+        b = (L.J >> mu) & 1
+        assert abs(_fair_z(int(b.sum()), b.size)) < 5, mu
+        for s in range(L.S):  # each sample on its own, too (32768 bonds)
+            assert abs(_fair_z(int(b[s].sum()), b[s].size)) < 5, (mu, s)
+
+
+def test_initial_couplings_three_bonds_of_a_site_are_independent():
+    """The eight patterns (j_x, j_y, j_z) of a site are equally likely: one
+    shared output word for the three bonds leaves only 000 and 111."""
+    L = O.Lattice(32, 32, 32, 8, 1, seed=0x5EED0008)
+    counts = np.bincount(L.J.reshape(-1), minlength=8)
+    assert _chi2_uniform(counts) < _CHI2_CRIT[7], counts
+    # pairwise: agreement of two axes at a site is fair
+    for a, b in ((0, 1), (0, 2), (1, 2)):
+        agree = int((((L.J >> a) ^ (L.J >> b)) & 1 == 0).sum())
+        assert abs(_fair_z(agree, L.J.size)) < 5, (a, b)
+
+
+def test_initial_couplings_independent_across_sites_and_samples():
+    L = O.Lattice(32, 32, 32, 8, 1, seed=0x5EED0009)
+    J = L.J.reshape(L.S, L.Lz, L.Ly, L.Lx)
+    # neighbouring sites along each axis carry independent bonds
+    for ax in (1, 2, 3):
+        agree = int((J == np.roll(J, 1, axis=ax)).sum())
+        # a site's whole 3-bit pattern equals its neighbour's w.p. 1/8
+        n = J.size
+        p = 1 / 8
+        assert abs(agree - p * n) < 5 * math.sqrt(n * p * (1 - p)), ax
+    # sites 4 apart in the site index (one Philox word apart for the spins)
+    agree = int((L.J[:, 4:] == L.J[:, :-4]).sum())
+    n = L.J[:, 4:].size
+    assert abs(agree - n / 8) < 5 * math.sqrt(n * (1 / 8) * (7 / 8))
+    # different samples are different realisations
+    for s in range(1, L.S):
+        agree = int((L.J[0] == L.J[s]).sum())
+        assert abs(agree - L.N / 8) < 5 * math.sqrt(L.N * (1 / 8) * (7 / 8)), s
+    # the seed changes the realisation; the same seed reproduces it
+    L2 = O.Lattice(32, 32, 32, 8, 1, seed=0x5EED0009 + (1 << 32))
+    assert abs(int((L.J == L2.J).sum()) - L.J.size / 8) < 5 * math.sqrt(L.J.size * 7 / 64)
+    assert np.array_equal(L.J, O.Lattice(32, 32, 32, 8, 1, seed=0x5EED0009).J)
+
+
+def test_initial_spins_are_fair_and_independent():
+    """Infinite-temperature start (Sec. 3): fair spins, independent across
+    sites, replicas and samples; the couplings do not enter."""
+    L = O.Lattice(32, 32, 16, 4, 4, seed=0x5EED000A)
+    sig = L.sigma
+    assert sig.max() <= 1
+    for s in range(L.S):
+        for r in range(L.R):
+            assert abs(_fair_z(int(sig[s, r].sum()), L.N)) < 5, (s, r)
+    # the 16 patterns of four consecutive sites (one Philox output each)
+    q = sig.reshape(L.S, L.R, L.N // 4, 4).astype(np.int64)
+    pat = q[..., 0] | (q[..., 1] << 1) | (q[..., 2] << 2) | (q[..., 3] << 3)
+    assert _chi2_uniform(np.bincount(pat.reshape(-1), minlength=16)) < _CHI2_CRIT[15]
+    # patterns of sites 4 apart (consecutive counters)
+    a = sig[..., :-4].astype(np.int64) | (sig[..., 4:].astype(np.int64) << 1)
+    assert _chi2_uniform(np.bincount(a.reshape(-1), minlength=4)) < _CHI2_CRIT[3]
+    # neighbouring sites along each axis agree half the time
+    V = sig.reshape(L.S, L.R, L.Lz, L.Ly, L.Lx)
+    for ax in (2, 3, 4):
+        assert abs(_fair_z(int((V == np.roll(V, 1, axis=ax)).sum()), V.size)) < 5, ax
+    # replicas and samples are independent draws
+    for s in range(L.S):
+        for r in range(1, L.R):
+            assert abs(_fair_z(int((sig[s, 0] == sig[s, r]).sum()), L.N)) < 5, (s, r)
+    for s in range(1, L.S):
+        assert abs(_fair_z(int((sig[0, 0] == sig[s, 0]).sum()), L.N)) < 5, s
+    # the spins do not depend on the couplings' draw: the energy of the start
+    # is that of random spins, mean 0 and variance 3N per lattice
+    E = L.energy().astype(np.float64)
+    assert abs(E.mean()) < 5 * math.sqrt(3 * L.N / E.size)
+    assert 0.5 < E.var() / (3 * L.N) < 2.0
+
+
+def test_initial_state_of_one_site_draws_its_own_words():
+    """Moving one site's index moves only that site's draws: the state of a
+    lattice is the restriction of a larger lattice's stream layout with the
+    same site index (the counters depend on i, not on the shape)."""
+    A = O.Lattice(8, 4, 4, 2, 2, seed=77)
+    B = O.Lattice(8, 4, 8, 2, 2, seed=77)  # first 128 sites share their indices
+    assert np.array_equal(A.J, B.J[:, :A.N])
+    assert np.array_equal(A.sigma, B.sigma[:, :, :A.N])

@@ -78,6 +78,17 @@ MUTATIONS = [
      "pt_swap_acceptance or pt_equilibrium"),
     ("Metropolis fresh draw per sweep", "philox_words(seed, (uint32_t)i, (uint32_t)k,",
      "philox_words(seed, (uint32_t)i, 0u,", "pt_metropolis"),
+    ("all three bonds from output 0",
+     "((o[0] >> 31) | ((o[1] >> 31) << 1) | ((o[2] >> 31) << 2))",
+     "((o[0] >> 31) | ((o[0] >> 31) << 1) | ((o[0] >> 31) << 2))", "initial_couplings"),
+    ("coupling counter without the sample", "(uint32_t)(STREAM_J << 24) | (uint32_t)s};",
+     "(uint32_t)(STREAM_J << 24)};", "initial_couplings"),
+    ("coupling counter per site word", "uint32_t ctr[4] = {(uint32_t)i, 0u, 0u, (uint32_t)(STREAM_J",
+     "uint32_t ctr[4] = {(uint32_t)(i >> 2), 0u, 0u, (uint32_t)(STREAM_J", "initial_couplings"),
+    ("spin from output 0", "(uint32_t)(STREAM_SPIN << 24) | (uint32_t)s, (int)(i & 3)) >> 31);",
+     "(uint32_t)(STREAM_SPIN << 24) | (uint32_t)s, 0) >> 31);", "initial_spins"),
+    ("spins without the replica", "draw(seed, (uint32_t)(i >> 2), 0u, (uint32_t)r,\n",
+     "draw(seed, (uint32_t)(i >> 2), 0u, 0u,\n", "initial_spins"),
     ("walker step direction", "{{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}", "{{-1, 0, 0}, {1, 0, 0}, {0, 1, 0}", "walkers"),
 ]
 
