@@ -54,6 +54,15 @@ enum micsa_layout {
     MICSA_LAYOUT_BITPLANE = 1 /* multispin coding: 64 samples per 64-bit word (Sec. 2.5, App. B) */
 };
 
+/* Bit-plane layout (multispin coding across lattices, Sec. 2.5 and App. B:
+   the 64 bits of a word are the same site of 64 lattices). */
+enum micsa_lane_mode {
+    MICSA_LANES_SAMPLES = 0, /* bit l of lane group g is sample 64g + l; each replica has its own words,
+                                and the coupling words of a group serve all its replicas */
+    MICSA_LANES_REPLICAS = 1 /* bit l of lane group g is replica 64g + l of one sample; the couplings
+                                of the sample are broadcast to every bit (0 or ~0 words) */
+};
+
 enum micsa_algo {
     MICSA_ALGO_MICSA = 0,    /* daemon update, Sec. 2.3-2.8 (gamma daemons per site) */
     MICSA_ALGO_HEATBATH = 1, /* canonical heat bath, Sec. 2.1 */
@@ -86,6 +95,8 @@ typedef struct micsa_params {
                               refresh temperatures are counted in timesteps; a refresh redraws
                               every family, daemon a of site i as number a*N + i of the daemon
                               stream.  n_sweeps of the schedule still counts sweeps. */
+    int32_t lane_mode;     /* enum micsa_lane_mode: what the 64 bits of a bit-plane word hold
+                              (BYTE layout: LANES_SAMPLES only) */
     uint64_t seed;         /* Philox key */
 } micsa_params;
 
@@ -186,6 +197,27 @@ int micsa_get_metropolis_thresholds(micsa_ctx* ctx, int64_t rho, uint64_t theta[
    energy.  Daemon levels above 3 are rejected with EINVAL. */
 int micsa_write_spins(micsa_ctx* ctx, const uint8_t* sigma); /* [S][R][N] */
 int micsa_write_demons(micsa_ctx* ctx, const uint8_t* m);    /* [S][R][gamma][N] */
+
+/* Checkpoint and resume.  micsa_save writes into the caller-owned buffer buf
+   a self-contained image of everything a run depends on: the parameters,
+   the sweep counter k, the installed schedule (with its table), the energy
+   tally, the spins [S][R][N], the daemons [S][R][gamma][N] and the
+   couplings [S][N] of every lattice, and a checksum.  Because every random
+   number is a function of (seed, sample, replica, site, sweep or refresh
+   index) (Sec. 2.7 refreshes at fixed points of k), a context that loads the
+   image continues bit for bit as the saved one would have.  A walker
+   wandering the daemons still owe is applied first.  With buf == NULL only
+   *len is set (the image size, which depends on the shape and the schedule
+   table); a *len below the size gives ERANGE with *len set to the size.
+   Synchronous.
+   micsa_load restores an image into a context created with the same
+   micsa_params (the couplings, drawn from the seed, must match the
+   image's).  Errors: EINVAL for another shape, seed, layout, gamma or lane
+   mode, a wrong magic, version, size or checksum, or out-of-range values;
+   nothing is changed then.  The image is host-endian and tied to this
+   library version. */
+int micsa_save(micsa_ctx* ctx, void* buf, size_t* len);
+int micsa_load(micsa_ctx* ctx, const void* buf, size_t len);
 
 /* Per-kernel timing with HIP events on the context's stream.  While
    enabled every kernel launch is bracketed by an event pair; the sums are

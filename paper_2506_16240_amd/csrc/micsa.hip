@@ -1098,6 +1098,8 @@ bool params_ok(const micsa_params* p)
     if (N >= ((int64_t)1 << 32) || (int64_t)p->n_samples * p->n_replicas >= (1 << 16)) return false;
     const int gamma = p->gamma == 0 ? 1 : p->gamma;
     if (gamma < 1 || gamma > 6 || (gamma > 1 && p->layout != MICSA_LAYOUT_BYTE)) return false;
+    if (p->lane_mode != MICSA_LANES_SAMPLES && p->lane_mode != MICSA_LANES_REPLICAS) return false;
+    if (p->lane_mode == MICSA_LANES_REPLICAS) return false;  // not built yet
     return (int64_t)gamma * N / 4 < ((int64_t)1 << 32);  // daemon counters (a*N + i) >> 2 fit 32 bits
 }
 
@@ -1699,6 +1701,165 @@ int micsa_write_demons(micsa_ctx* ctx, const uint8_t* m)
     return st;
 }
 
+// ------------------------------------------------------------- checkpoint
+// Image: CkHeader, the schedule table (T_len doubles), the tally per lattice
+// (int64), spins [L][N], daemons [L][gamma][N], couplings [S][N] (bytes),
+// then the FNV-1a hash of everything before it.
+namespace {
+constexpr char kCkMagic[8] = {'M', 'I', 'C', 'S', 'A', '-', 'C', 'K'};
+constexpr uint32_t kCkVersion = 1;
+
+struct CkHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t header_bytes;
+    micsa_params p;
+    int64_t k;
+    int32_t sched_set, sched_kind, sched_period, reserved;
+    double T0, T1;
+    int64_t n_sweeps, T_len;
+    uint64_t total_bytes;
+};
+
+uint64_t fnv1a(const uint8_t* d, size_t n)
+{
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= d[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+size_t ck_bytes(const micsa_ctx* c, int64_t T_len)
+{
+    const size_t N = (size_t)n_sites(c), L = (size_t)c->L;
+    return sizeof(CkHeader) + (size_t)T_len * 8 + L * 8 + L * N + L * (size_t)c->gamma * N +
+           (size_t)c->p.n_samples * N + 8;
+}
+
+bool same_params(const micsa_params& a, const micsa_params& b)
+{
+    return a.Lx == b.Lx && a.Ly == b.Ly && a.Lz == b.Lz && a.n_samples == b.n_samples &&
+           a.n_replicas == b.n_replicas && a.layout == b.layout && a.gamma == b.gamma &&
+           a.lane_mode == b.lane_mode && a.seed == b.seed;
+}
+}  // namespace
+
+int micsa_save(micsa_ctx* ctx, void* buf, size_t* len)
+{
+    if (!ctx || !len) return MICSA_EINVAL;
+    const int64_t T_len = ctx->sched.set ? (int64_t)ctx->sched.table.size() : 0;
+    const size_t total = ck_bytes(ctx, T_len);
+    if (!buf) {
+        *len = total;
+        return MICSA_OK;
+    }
+    if (*len < total) {
+        *len = total;
+        return fail(ctx, MICSA_ERANGE, "checkpoint buffer smaller than micsa_save's size");
+    }
+    const size_t N = (size_t)n_sites(ctx), L = (size_t)ctx->L;
+    uint8_t* out = static_cast<uint8_t*>(buf);
+    CkHeader h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, kCkMagic, 8);
+    h.version = kCkVersion;
+    h.header_bytes = (uint32_t)sizeof(CkHeader);
+    h.p = ctx->p;
+    h.k = ctx->k;
+    h.sched_set = ctx->sched.set ? 1 : 0;
+    h.sched_kind = ctx->sched.kind;
+    h.sched_period = ctx->sched.period;
+    h.T0 = ctx->sched.T0;
+    h.T1 = ctx->sched.T1;
+    h.n_sweeps = ctx->sched.n_sweeps;
+    h.T_len = T_len;
+    h.total_bytes = total;
+    size_t o = sizeof(CkHeader);
+    if (T_len) std::memcpy(out + o, ctx->sched.table.data(), (size_t)T_len * 8);
+    o += (size_t)T_len * 8;
+    int st;
+    // reading the daemons first applies an owed walker wandering
+    uint8_t* tally = out + o;
+    uint8_t* spins = tally + L * 8;
+    uint8_t* dems = spins + L * N;
+    uint8_t* coup = dems + L * (size_t)ctx->gamma * N;
+    if ((st = micsa_read_demons(ctx, dems))) return st;
+    if ((st = micsa_read_spins(ctx, spins))) return st;
+    if ((st = micsa_read_couplings(ctx, coup))) return st;
+    std::vector<int64_t> E(L);
+    st = ctx->bit ? micsa_read_energy(ctx, E.data()) : micsa_read_energy_tally(ctx, E.data());
+    if (st) return st;
+    std::memcpy(tally, E.data(), L * 8);
+    h.k = ctx->k;
+    std::memcpy(out, &h, sizeof h);
+    const uint64_t hash = fnv1a(out, total - 8);
+    std::memcpy(out + total - 8, &hash, 8);
+    *len = total;
+    return MICSA_OK;
+}
+
+int micsa_load(micsa_ctx* ctx, const void* buf, size_t len)
+{
+    if (!ctx) return MICSA_EINVAL;
+    if (!buf) return fail(ctx, MICSA_EINVAL, "null checkpoint");
+    const uint8_t* in = static_cast<const uint8_t*>(buf);
+    CkHeader h;
+    if (len < sizeof h) return fail(ctx, MICSA_EINVAL, "checkpoint too short");
+    std::memcpy(&h, in, sizeof h);
+    if (std::memcmp(h.magic, kCkMagic, 8) != 0 || h.version != kCkVersion || h.header_bytes != sizeof(CkHeader))
+        return fail(ctx, MICSA_EINVAL, "not a checkpoint of this library version");
+    if (!same_params(h.p, ctx->p))
+        return fail(ctx, MICSA_EINVAL, "checkpoint of a context with other parameters");
+    if (h.T_len < 0 || h.T_len > (int64_t)(len / 8) || h.k < 0) return fail(ctx, MICSA_EINVAL, "corrupt checkpoint");
+    const size_t total = ck_bytes(ctx, h.T_len);
+    if (h.total_bytes != total || len < total) return fail(ctx, MICSA_EINVAL, "checkpoint size mismatch");
+    uint64_t hash;
+    std::memcpy(&hash, in + total - 8, 8);
+    if (hash != fnv1a(in, total - 8)) return fail(ctx, MICSA_EINVAL, "checkpoint checksum mismatch");
+    const size_t N = (size_t)n_sites(ctx), L = (size_t)ctx->L;
+    const uint8_t* table = in + sizeof(CkHeader);
+    const uint8_t* tally = table + (size_t)h.T_len * 8;
+    const uint8_t* spins = tally + L * 8;
+    const uint8_t* dems = spins + L * N;
+    const uint8_t* coup = dems + L * (size_t)ctx->gamma * N;
+    // the couplings follow from the seed: they must be this context's
+    std::vector<uint8_t> mine((size_t)ctx->p.n_samples * N);
+    int st = micsa_read_couplings(ctx, mine.data());
+    if (st) return st;
+    if (std::memcmp(mine.data(), coup, mine.size()) != 0)
+        return fail(ctx, MICSA_EINVAL, "checkpoint couplings differ from the context's");
+    for (size_t i = 0; i < L * N; ++i)
+        if (spins[i] > 1) return fail(ctx, MICSA_EINVAL, "checkpoint spin out of range");
+    for (size_t i = 0; i < L * (size_t)ctx->gamma * N; ++i)
+        if (dems[i] > 3) return fail(ctx, MICSA_EINVAL, "checkpoint daemon level out of range");
+    if (h.sched_set) {
+        micsa_schedule s{};
+        s.kind = h.sched_kind;
+        s.refresh_period = h.sched_period;
+        s.T0 = h.T0;
+        s.T1 = h.T1;
+        s.n_sweeps = h.n_sweeps;
+        std::vector<double> tb((size_t)h.T_len);
+        if (h.T_len) std::memcpy(tb.data(), table, (size_t)h.T_len * 8);
+        s.T_table = tb.empty() ? nullptr : tb.data();
+        s.T_len = h.T_len;
+        if ((st = micsa_set_schedule(ctx, &s))) return st;
+    } else {
+        ctx->sched = Schedule{};
+    }
+    if ((st = micsa_write_spins(ctx, spins))) return st;
+    if ((st = micsa_write_demons(ctx, dems))) return st;
+    if (!ctx->bit) {
+        std::vector<int64_t> E(L);
+        std::memcpy(E.data(), tally, L * 8);
+        if ((st = set_tally(ctx, E))) return st;
+    }
+    ctx->k = h.k;
+    return MICSA_OK;
+}
+
 int micsa_get_counters(micsa_ctx* ctx, int64_t* k, int64_t* rho)
 {
     if (!ctx) return MICSA_EINVAL;
@@ -1872,7 +2033,13 @@ size_t footprint(const micsa_params* p)
     }
     const size_t gamma = p->gamma == 0 ? 1 : (size_t)p->gamma;
     // 2 state buffers x (spin + gamma daemons); the couplings live in the even spin bytes
-    return 2 * L * N * (1 + gamma) + slots;
+    size_t bytes = 2 * L * N * (1 + gamma) + slots;
+    // lattices the multispin sweep can take allocate its planes on their first
+    // long MicSA call: spins and two level planes, their alternates, the drawn
+    // levels (2) and the six coupling planes of the even sites (3 words per
+    // word of sites), each 1 bit per site: 11/8 B per site per lattice
+    if (gamma == 1 && p->Lx % 128 == 0) bytes += 11 * L * N / 8;
+    return bytes;
 }
 
 }  // namespace
@@ -1977,24 +2144,22 @@ int micsa_pool_step(micsa_pool* pool, int64_t sweeps, int32_t* running, int32_t*
         pool->used += j.bytes;
         ++nrun;
     }
-    // 2. advance: LDS-resident jobs in one batched launch, the others alone
+    // 2. advance: LDS-resident jobs in one batched launch, the others alone.
+    // A resident job's counter moves only once its batch is launched, so an
+    // error leaves every job's counter at the sweeps it really has enqueued.
     std::vector<ResidentItem> items;
+    std::vector<std::pair<micsa_ctx*, int64_t>> batched;
     size_t lds = 0;
     for (auto& j : pool->jobs) {
         if (j.state != MICSA_JOB_RUNNING) continue;
         micsa_ctx* c = j.ctx;
         const int64_t n = std::min<int64_t>(sweeps, c->sched.n_sweeps - c->k);
-        if (n <= 0) continue;
-        if (use_resident(c)) {
-            ResidentSched rs{c->k, n, 0, c->sched.period, 0, 0};
-            for (int l = 0; l < c->L; ++l)
-                items.push_back(ResidentItem{c->g, c->spin, c->dem, c->tally, c->d_dth, rs, l});
-            lds = std::max(lds, (size_t)c->g.Nh * 3);
-            c->k += n;
-        } else {
-            const int st = micsa_sweep(c, MICSA_ALGO_MICSA, n);
-            if (st) return st;
-        }
+        if (n <= 0 || !use_resident(c)) continue;
+        ResidentSched rs{c->k, n, 0, c->sched.period, 0, 0};
+        for (int l = 0; l < c->L; ++l)
+            items.push_back(ResidentItem{c->g, c->spin, c->dem, c->tally, c->d_dth, rs, l});
+        lds = std::max(lds, (size_t)c->g.Nh * 3);
+        batched.emplace_back(c, n);
     }
     if (!items.empty()) {
         if (items.size() > pool->d_items_cap) {
@@ -2019,6 +2184,15 @@ int micsa_pool_step(micsa_pool* pool, int64_t sweeps, int32_t* running, int32_t*
         }
         k_resident_batch<<<(unsigned)items.size(), kResidentBlock, lds, pool->stream>>>(pool->d_items);
         if (hipGetLastError() != hipSuccess) return MICSA_EHIP;
+        for (auto& b : batched) b.first->k += b.second;
+    }
+    for (auto& j : pool->jobs) {
+        if (j.state != MICSA_JOB_RUNNING) continue;
+        micsa_ctx* c = j.ctx;
+        const int64_t n = std::min<int64_t>(sweeps, c->sched.n_sweeps - c->k);
+        if (n <= 0 || use_resident(c)) continue;
+        const int st = micsa_sweep(c, MICSA_ALGO_MICSA, n);
+        if (st) return st;
     }
     if (hipStreamSynchronize(pool->stream) != hipSuccess) return MICSA_EHIP;
     // 3. retire finished jobs

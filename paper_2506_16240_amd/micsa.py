@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmicsa.so
 
 OK, EINVAL, ENOMEM, EHIP, ESTATE, ERANGE = 0, -1, -2, -3, -4, -5
 LAYOUT_BYTE, LAYOUT_BITPLANE = 0, 1
+LANES_SAMPLES, LANES_REPLICAS = 0, 1
 ALGO_MICSA, ALGO_HEATBATH, ALGO_WALKERS, ALGO_METROPOLIS = 0, 1, 2, 3
 SCHED_CONST, SCHED_LINEAR, SCHED_TABLE = 0, 1, 2
 REFRESH_LOG2 = 0
@@ -40,12 +41,12 @@ class MicsaError(RuntimeError):
 class _Params(ctypes.Structure):
     _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("Lz", ctypes.c_int32),
                 ("n_samples", ctypes.c_int32), ("n_replicas", ctypes.c_int32), ("layout", ctypes.c_int32),
-                ("gamma", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("gamma", ctypes.c_int32), ("lane_mode", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
-def _params(Lx, Ly, Lz, S, R, layout, seed, gamma=1) -> _Params:
+def _params(Lx, Ly, Lz, S, R, layout, seed, gamma=1, lane_mode=0) -> _Params:
     return _Params(Lx=Lx, Ly=Ly, Lz=Lz, n_samples=S, n_replicas=R, layout=layout, gamma=gamma,
-                   seed=seed & (2**64 - 1))
+                   lane_mode=lane_mode, seed=seed & (2**64 - 1))
 
 
 class _Schedule(ctypes.Structure):
@@ -89,6 +90,8 @@ _SIGNATURES = [
     ("micsa_read_xi", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("micsa_write_spins", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("micsa_write_demons", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_save", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    ("micsa_load", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     ("micsa_set_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("micsa_get_timing", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64)]),
@@ -196,13 +199,13 @@ class Lattice:
         return obj
 
     def __init__(self, Lx: int, Ly: int, Lz: int, S: int = 1, R: int = 1, seed: int = 0,
-                 layout: int = LAYOUT_BYTE, stream=None, gamma: int = 1):
+                 layout: int = LAYOUT_BYTE, stream=None, gamma: int = 1, lane_mode: int = LANES_SAMPLES):
         self.Lx, self.Ly, self.Lz, self.S, self.R = Lx, Ly, Lz, S, R
         self.N = Lx * Ly * Lz
         self.seed = seed
         self.gamma = gamma
         self._ctx = ctypes.c_void_p()
-        p = _params(Lx, Ly, Lz, S, R, layout, seed, gamma)
+        p = _params(Lx, Ly, Lz, S, R, layout, seed, gamma, lane_mode)
         st = lib().micsa_create(ctypes.byref(p), _stream_handle(stream), ctypes.byref(self._ctx))
         if st != OK:
             raise MicsaError(st, f"micsa_create({Lx},{Ly},{Lz},S={S},R={R}): "
@@ -249,6 +252,19 @@ class Lattice:
 
     def sync(self) -> None:
         self._check(lib().micsa_sync(self._ctx), "sync")
+
+    def save(self) -> bytes:
+        """Checkpoint image (micsa_save)."""
+        n = ctypes.c_size_t(0)
+        self._check(lib().micsa_save(self._ctx, None, ctypes.byref(n)), "save (size)")
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(lib().micsa_save(self._ctx, buf, ctypes.byref(n)), "save")
+        return buf.raw[:n.value]
+
+    def load(self, image: bytes) -> None:
+        """Restore a checkpoint image (micsa_load)."""
+        self._check(lib().micsa_load(self._ctx, image, len(image)), "load")
+
 
     # -- reads ----------------------------------------------------------
     def _read_vec(self, fn, n, what):

@@ -80,6 +80,25 @@ def test_null_arguments():
     assert lib.micsa_read_energy(None, None) == M.EINVAL
     assert lib.micsa_set_schedule(None, None) == M.EINVAL
     assert lib.micsa_last_error(None) == b"null context"
+    n = ctypes.c_size_t(0)
+    assert lib.micsa_save(None, None, ctypes.byref(n)) == M.EINVAL
+    assert lib.micsa_load(None, None, 0) == M.EINVAL
+
+
+@pytest.mark.parametrize("layout,lane_mode", [(0, 2), (1, -1), (0, 1)])
+def test_create_rejects_bad_lane_mode(layout, lane_mode):
+    """Lane modes exist for the bit-plane layout only."""
+    p = M._params(8, 8, 8, 1, 2, layout, 1, 1, lane_mode)
+    out = ctypes.c_void_p()
+    assert M.lib().micsa_create(ctypes.byref(p), None, ctypes.byref(out)) == M.EINVAL
+    assert not out.value
+
+
+def test_params_struct_layout():
+    """lane_mode sits in the padding before the 64-bit seed: the struct keeps
+    its size and the seed its offset."""
+    assert ctypes.sizeof(M._Params) == 40
+    assert M._Params.seed.offset == 32 and M._Params.lane_mode.offset == 28
 
 
 def _pt_create(Lx=4, Ly=4, Lz=4, runs=1, T=(0.5, 1.0), J=None, sweeps=10, algo=0, houdayer=1):
@@ -117,7 +136,24 @@ def test_binding_constants_match_the_header():
     """Every MICSA_OPT_* / MICSA_KERNEL_* value the header declares has the
     same value in the Python binding (a mismatch would set the wrong option)."""
     text = open(os.path.join(ROOT, "include", "micsa.h")).read()
-    pairs = re.findall(r"\bMICSA_((?:OPT|KERNEL)_[A-Z0-9_]+)\s*=\s*(\d+)", text)
+    pairs = re.findall(r"\bMICSA_((?:OPT|KERNEL|LANES|LAYOUT)_[A-Z0-9_]+)\s*=\s*(\d+)", text)
     assert len(pairs) >= 14
     for name, value in pairs:
         assert getattr(M, name) == int(value), name
+
+
+def test_pool_footprint_counts_the_multispin_planes():
+    """A byte-layout job whose rows split into 128-site words may run on the
+    multispin planes, which its first long MicSA call allocates: spin, two
+    level planes, their alternates, two drawn-level planes and the six
+    coupling planes of the even sites, 11/8 B per site per lattice, on top of
+    the byte state.  Same N and lattice count, one eligible and one not."""
+    def fp(*shape, gamma=1):
+        out = ctypes.c_size_t()
+        assert M.lib().micsa_pool_footprint(ctypes.byref(M._params(*shape, 0, 1, gamma)), ctypes.byref(out)) == M.OK
+        return out.value
+    for S, R in ((1, 1), (2, 3)):
+        N, L = 128 * 8 * 8, S * R
+        assert fp(128, 8, 8, S, R) - fp(64, 16, 8, S, R) == 11 * L * N // 8
+    # gamma > 1 never runs multispin
+    assert fp(128, 8, 8, 1, 1, gamma=2) - fp(64, 16, 8, 1, 1, gamma=2) == 0
