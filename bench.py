@@ -77,6 +77,19 @@ def measured_traffic(name: str):
     return e.get("bytes_per_launch")
 
 
+def tile_options(tile):
+    """Launch options of a tile: a dict {option: value} (from the tuner) or a
+    tuple (TY, TZ[, PREFETCH[, SWEEPS_PER_PASS]])."""
+    from paper_2506_16240_amd import micsa as M
+
+    if not tile:
+        return []
+    if isinstance(tile, dict):
+        return [(getattr(M, k), v) for k, v in tile.items()]
+    names = (M.OPT_TILE_Y, M.OPT_TILE_Z, M.OPT_PREFETCH, M.OPT_TEMPORAL)
+    return list(zip(names, tile))
+
+
 def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None, layout: int = 0, events: bool = False,
             gamma: int = 1, period=None, c4: int = 0, kernel: int = 0):
     """One timed region of `steps` steps on a fresh lattice.  With events the
@@ -89,13 +102,9 @@ def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None, layou
     def configure(lat):
         if kernel:
             lat.set_option(M.OPT_SWEEP_KERNEL, kernel)
-        if tile and algo_name == "micsa":
-            lat.set_option(M.OPT_TILE_Y, tile[0])
-            lat.set_option(M.OPT_TILE_Z, tile[1])
-            if len(tile) > 2:
-                lat.set_option(M.OPT_PREFETCH, tile[2])
-            if len(tile) > 3:
-                lat.set_option(M.OPT_TEMPORAL, tile[3])
+        if algo_name == "micsa":
+            for opt, v in tile_options(tile):
+                lat.set_option(opt, v)
 
     algo = {"micsa": M.ALGO_MICSA, "heatbath": M.ALGO_HEATBATH, "metropolis": M.ALGO_METROPOLIS,
             "walkers": M.ALGO_WALKERS}[algo_name]
@@ -124,10 +133,10 @@ def run_gpu(w, algo_name: str, steps: int, warmup: int, stream, tile=None, layou
             M.ALGO_WALKERS: M.TIME_SWEEP}[algo]
     k_ms, k_n = lat.timing(kind)
     r_ms, r_n = lat.timing(M.TIME_REFRESH)
-    # property that holds at any size: the incremental tally equals the energy
-    # (the bit-plane layout keeps no tally)
+    # property that holds at any size: the incremental tally (per lattice; per
+    # lane of the bit-plane words) equals the from-scratch energy
     E = lat.energy()
-    ok = bool((E == lat.energy_tally()).all()) if layout == M.LAYOUT_BYTE else None
+    ok = bool((E == lat.energy_tally()).all())
     name = lat.kernel_name(algo)
     c4_ms = None
     if c4 > 0 and w.R >= 2:  # C4(r) sums of the final state (Sec. 3), timed as a whole
@@ -404,13 +413,28 @@ def main() -> int:
     multispin = (layout == 0 and args.kernel in ("auto", "multispin") and w.Lx % 128 == 0 and args.gamma == 1
                  and args.algo == "micsa" and w.N * 3 > 150 * 1024 * 2)
     tile = None
-    if args.tile == "tune" and fused and not multispin:
+    if args.tile == "tune" and args.algo == "micsa" and args.gamma == 1:
+        # warm-up: the tuner times launch shapes of the path this workload runs
+        # (bit-exact gate against the per-half kernels); cached per device and shape
         from paper_2506_16240_amd import tune
-        log("tuning fused-sweep tiles")
-        best = tune.tune(w.Lx, w.Ly, w.Lz, w.S, w.R, use_cache=False)
-        tile = (best.ty, best.tz, best.prefetch, best.temporal)
-        log(f"tile TY={best.ty} TZ={best.tz} prefetch {best.prefetch} sweeps/pass {best.temporal} "
-            f"({best.us_per_sweep:.1f} us/sweep in tuning)")
+        if multispin:
+            log("tuning the multispin sweep (tile, XCD order, sweeps per pass)")
+            best = tune.tune_multispin(w.Lx, w.Ly, w.Lz, w.S, w.R)
+            tile = {"OPT_TILE_Y": best.ty, "OPT_TILE_Z": best.tz, "OPT_XCD_MAP": best.xcd,
+                    "OPT_MSC_PASS": best.temporal}
+            log(f"multispin TY={best.ty} TZ={best.tz} xcd {best.xcd} sweeps/pass {best.temporal} "
+                f"({best.us_per_sweep:.2f} us/sweep in tuning)")
+        elif layout:
+            log("tuning the bit-plane sweep (planes per work-group, draw ahead)")
+            best = tune.tune_bitplane(w.Lx, w.Ly, w.Lz, w.S, w.R)
+            tile = {"OPT_TILE_Z": best.tz, "OPT_DRAW_AHEAD": best.draw_ahead}
+            log(f"bit-plane TZ={best.tz} draw-ahead {best.draw_ahead} ({best.us_per_sweep:.2f} us/sweep in tuning)")
+        elif fused:
+            log("tuning fused-sweep tiles")
+            best = tune.tune(w.Lx, w.Ly, w.Lz, w.S, w.R, use_cache=False)
+            tile = (best.ty, best.tz, best.prefetch, best.temporal)
+            log(f"tile TY={best.ty} TZ={best.tz} prefetch {best.prefetch} sweeps/pass {best.temporal} "
+                f"({best.us_per_sweep:.1f} us/sweep in tuning)")
     elif args.tile not in ("auto", "tune"):
         tile = tuple(int(v) for v in args.tile.split(","))
     algo_name = args.algo
@@ -490,7 +514,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "L": [w.Lx, w.Ly, w.Lz], "samples": w.S, "replicas": w.R,
                    "sweeps_per_step": w.period, "sweeps": sweeps, "schedule": f"T {w.T0}->{w.T1}",
-                   "layout": layout_name, "kernel": mi["kernel"], "tile": list(tile) if tile else "auto",
+                   "layout": layout_name, "kernel": mi["kernel"],
+                   "tile": (tile if isinstance(tile, dict) else list(tile)) if tile else "auto",
                    "gamma": args.gamma, "refresh": args.refresh},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -538,13 +563,8 @@ def main() -> int:
         if not args.no_parity and algo_name == "micsa" and args.gamma == 1 and not layout:
             def cfg(lat):
                 lat.set_option(M.OPT_SWEEP_KERNEL, kern)
-                if tile:
-                    lat.set_option(M.OPT_TILE_Y, tile[0])
-                    lat.set_option(M.OPT_TILE_Z, tile[1])
-                    if len(tile) > 2:
-                        lat.set_option(M.OPT_PREFETCH, tile[2])
-                    if len(tile) > 3:
-                        lat.set_option(M.OPT_TEMPORAL, tile[3])
+                for opt, v in tile_options(tile):
+                    lat.set_option(opt, v)
         cb, parity = cpu_baseline(w, args.cpu_seconds, cfg, stream)
         out["cpu_baseline"] = cb
         if parity is not None:

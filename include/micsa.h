@@ -51,7 +51,9 @@ enum micsa_status {
 enum micsa_layout {
     MICSA_LAYOUT_BYTE = 0,    /* one byte per spin and per daemon; an even site's spin byte also
                                  holds the coupling bits of its six bonds */
-    MICSA_LAYOUT_BITPLANE = 1 /* multispin coding: 64 samples per 64-bit word (Sec. 2.5, App. B) */
+    MICSA_LAYOUT_BITPLANE = 1 /* multispin coding: 64 lattices per 64-bit word (Sec. 2.5, App. B), the
+                                 lanes set by micsa_params.lane_mode; one launch per sweep with both
+                                 halves, ring planes recomputed, per-lane energy tally */
 };
 
 /* Bit-plane layout (multispin coding across lattices, Sec. 2.5 and App. B:
@@ -157,7 +159,10 @@ int micsa_sync(micsa_ctx* ctx);
 /* Reads (synchronous; outputs are host arrays in the natural layout above,
    independent of the device layout). */
 int micsa_read_energy(micsa_ctx* ctx, int64_t* E);       /* [S*R] H^EA from scratch */
-int micsa_read_energy_tally(micsa_ctx* ctx, int64_t* E); /* [S*R] H^EA from the dH of every accepted move */
+int micsa_read_energy_tally(micsa_ctx* ctx, int64_t* E); /* [S*R] H^EA from the dH of every accepted move;
+                                                            bit-plane layout: kept per lane by the one-launch
+                                                            sweep, ESTATE after a per-half sweep until the
+                                                            spins are written */
 int micsa_read_demon_energy(micsa_ctx* ctx, int64_t* D); /* [S*R] H^aux = 4 sum m */
 /* Q[s] = sum_x s^a_x s^b_x, the overlap of replicas a and b (App. C); EINVAL
    unless 0 <= a, b < R and a != b. */
@@ -243,7 +248,8 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      unpacks it at the end; walkers (gamma = 1) run on the one-launch form
      too; the heat bath and Metropolis keep the fused path).
    MICSA_OPT_TILE_Y / MICSA_OPT_TILE_Z: rows / planes per work-group of the
-     fused and one-launch multispin sweeps (0 = automatic).  TILE_Z must
+     fused and one-launch multispin sweeps (0 = automatic); TILE_Z is also
+     the planes per work-group of the one-launch bit-plane sweep.  TILE_Z must
      divide Lz.  TILE_Y is at most Ly; the fused byte sweep uses it where it
      divides Ly (else the automatic choice), the multispin sweep as given,
      its last tile along y holding the rows left over (a tile wider than 256
@@ -262,10 +268,17 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      faster for these kernels on MI355X (the graph form adds a refresh-check
      and a counter kernel to every sweep).  Per-launch timing
      (micsa_set_timing) always launches every kernel.
-   MICSA_OPT_TEMPORAL: MicSA sweeps per pass over memory on the fused path:
-     2 (default) runs sweeps k and k + 1 in one launch wherever a call
+   MICSA_OPT_TEMPORAL: MicSA sweeps per pass over memory on the fused byte
+     sweep: 2 (default) runs sweeps k and k + 1 in one launch wherever a call
      sweeps at least two (the state is read and written once per pair); 1
      runs one sweep per launch.  Results are identical.
+   MICSA_OPT_MSC_PASS: MicSA sweeps per pass on the one-launch multispin
+     sweep: 1 (default) or 2 (sweeps k and k + 1 in one launch, rings of 8
+     rows and planes, the state read and written once per pair; a pass whose
+     sweeps include a refresh takes the levels drawn ahead, and a pair with
+     two refreshes, or a refresh with DRAW_AHEAD 0, runs one sweep per
+     launch).  Results are identical; on MI355X the pair form is bound by
+     VALU latency and slower at 512^3, so it is off by default.
    MICSA_OPT_MSC_FUSED: the multispin sweep in one launch per sweep marching
      along z (1, default) or one launch per half sweep (0).
    MICSA_OPT_PREFETCH: steps of global loads in flight in the fused MicSA
@@ -288,12 +301,13 @@ enum micsa_option {
     MICSA_OPT_PREFETCH = 6,
     MICSA_OPT_TEMPORAL = 7,
     MICSA_OPT_MSC_FUSED = 8,
-    MICSA_OPT_DRAW_AHEAD = 9
+    MICSA_OPT_DRAW_AHEAD = 9,
+    MICSA_OPT_MSC_PASS = 10
 };
 enum micsa_kernel_choice {
     MICSA_KERNEL_AUTO = 0,    /* resident if the lattice fits; else, for MicSA calls of >= 8 sweeps, multispin
                                  if Lx % 128 == 0; else fused if Lx >= 128, else simple */
-    MICSA_KERNEL_SIMPLE = 1,  /* one launch per half sweep */
+    MICSA_KERNEL_SIMPLE = 1,  /* one launch per half sweep (bit-plane layout: instead of its one-launch sweep) */
     MICSA_KERNEL_FUSED = 2,   /* one launch per sweep, refresh fused in (Lx % 32 == 0) */
     MICSA_KERNEL_RESIDENT = 3, /* one work-group per lattice keeps it in LDS for many sweeps (<= 102400 sites) */
     MICSA_KERNEL_MULTISPIN = 4 /* MicSA daemon sweeps on bit planes, 64 sites of a row per word (Lx % 128 == 0) */

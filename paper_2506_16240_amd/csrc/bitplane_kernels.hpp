@@ -1,12 +1,16 @@
-// Bit-plane (multispin-coded) layout: 64 samples per 64-bit word (Sec. 2.5
+// Bit-plane (multispin-coded) layout: 64 lattices per 64-bit word (Sec. 2.5
 // and App. B pack 64 spins per word; here the 64 bits of a word are the same
-// site of 64 different samples).  Lane l of lane group G is sample 64G + l;
-// each replica has its own word arrays, the couplings of a lane group are
-// shared by its replicas.
+// site of 64 different lattices).  Two lane modes (enum micsa_lane_mode):
+//   samples:  word lattice wl = G r-major: wl = group * R + r; lane l is
+//             sample 64 group + l, replica r; the coupling words of a group
+//             (coupling set = group) serve all its replicas;
+//   replicas: wl = s * G + group; lane l is replica 64 group + l of sample s;
+//             the couplings of sample s (coupling set = s) are broadcast to
+//             every lane (each coupling word is 0 or ~0).
 //
-//   spin [G][R][p][h]   uint64   bit l = spin bit of sample 64G+l
-//   dm0, dm1 [G][R][p][h]        bits 0 and 1 of the daemon level m
-//   Jw [G][d][h]        uint64   coupling bit of bond d of even site h
+//   spin [WL][p][h]     uint64   bit l = spin bit of the lane's lattice
+//   dm0, dm1 [WL][p][h]          bits 0 and 1 of the daemon level m
+//   Jw [NJ][d][h]       uint64   coupling bit of bond d of even site h
 //
 // with the same parity split h as the byte layout (geometry.hpp): site
 // words of one row are contiguous, so the x neighbours of site k are words
@@ -25,8 +29,39 @@ namespace micsa {
 
 struct GeomB {
     Geom g;
-    int32_t G;  // lane groups = ceil(S / 64)
+    int32_t G;     // lane groups: ceil(S / 64) (samples mode) or ceil(R / 64) per sample (replicas mode)
+    int32_t mode;  // 0: lanes are samples, 1: lanes are the replicas of one sample
 };
+
+__host__ __device__ __forceinline__ int bp_word_lattices(const GeomB& b) { return b.mode ? b.g.S * b.G : b.G * b.g.R; }
+__host__ __device__ __forceinline__ int bp_coupling_sets(const GeomB& b) { return b.mode ? b.g.S : b.G; }
+// coupling set of word lattice wl
+__host__ __device__ __forceinline__ int bp_cset(const GeomB& b, int wl) { return b.mode ? wl / b.G : wl / b.g.R; }
+
+// Lattice (s, r) of lane l of word lattice wl; false for a lane beyond the counts.
+__host__ __device__ __forceinline__ bool bp_lattice(const GeomB& b, int wl, int l, int& s, int& r)
+{
+    if (b.mode) {
+        s = wl / b.G;
+        r = 64 * (wl - s * b.G) + l;
+    } else {
+        const int grp = wl / b.g.R;
+        s = 64 * grp + l;
+        r = wl - grp * b.g.R;
+    }
+    return s < b.g.S && r < b.g.R;
+}
+
+// Word lattice and lane of lattice (s, r).
+__host__ __device__ __forceinline__ int bp_word_of(const GeomB& b, int s, int r, int& lane)
+{
+    if (b.mode) {
+        lane = r & 63;
+        return s * b.G + (r >> 6);
+    }
+    lane = s & 63;
+    return (s >> 6) * b.g.R + r;
+}
 
 // Full adder on 64 lanes.
 __device__ __forceinline__ void fadd(uint64_t a, uint64_t b, uint64_t c, uint64_t& s, uint64_t& carry)
@@ -67,13 +102,15 @@ __device__ __forceinline__ void creutz64(const uint64_t a[6], uint64_t& S, uint6
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
 // Thread = (even site h, lane); block of 256 = 4 even sites x 64 lanes.
+// Grid y: coupling sets; lane l draws for sample 64 set + l (samples mode)
+// or every lane for sample `set` (replicas mode: broadcast words).
 __global__ void __launch_bounds__(256) kb_init_couplings(GeomB b, uint64_t* __restrict__ Jw)
 {
     const Geom& g = b.g;
     const int G = blockIdx.y;
     const int64_t h = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = lane_id();
-    const uint32_t s = (uint32_t)(64 * G + lane);
+    const uint32_t s = (uint32_t)(b.mode ? G : 64 * G + lane);
     const bool live = h < g.Nh;
     uint32_t bits[6] = {0, 0, 0, 0, 0, 0};
     if (live && s < (uint32_t)g.S) {
@@ -132,14 +169,15 @@ __device__ __forceinline__ void ballot4(const Geom& g, int64_t i0, const u32x4& 
 __global__ void __launch_bounds__(256) kb_init_spins(GeomB b, uint64_t* __restrict__ spin)
 {
     const Geom& g = b.g;
-    const int wl = blockIdx.y;  // word lattice = G * R + r
-    const int G = wl / g.R, r = wl % g.R;
+    const int wl = blockIdx.y;  // word lattice
     const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const bool live = t < g.Nh / 2;
-    const uint32_t s = (uint32_t)(64 * G + lane_id());
+    int si, r;
+    const bool lane_ok = bp_lattice(b, wl, lane_id(), si, r);
+    const uint32_t s = (uint32_t)si;
     u32x4 o = {0, 0, 0, 0};
     const int64_t i0 = 4 * t;
-    if (live && s < (uint32_t)g.S)
+    if (live && lane_ok)
         o = philox10((uint32_t)t, 0u, (uint32_t)r, stream_word(kStreamSpin, s), g.key0, g.key1);
     ballot4(g, live ? i0 : 0, o, [](uint32_t u, uint32_t& b0, uint32_t& b1) { b0 = u >> 31; b1 = 0; },
             spin + (int64_t)wl * 2 * g.Nh, nullptr, live);
@@ -150,12 +188,13 @@ __global__ void __launch_bounds__(256) kb_refresh(GeomB b, uint64_t* __restrict_
 {
     const Geom& g = b.g;
     const int wl = blockIdx.y;
-    const int G = wl / g.R, r = wl % g.R;
     const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const bool live = t < g.Nh / 2;
-    const uint32_t s = (uint32_t)(64 * G + lane_id());
+    int si, r;
+    const bool lane_ok = bp_lattice(b, wl, lane_id(), si, r);
+    const uint32_t s = (uint32_t)si;
     u32x4 o = {0, 0, 0, 0};
-    if (live && s < (uint32_t)g.S)
+    if (live && lane_ok)
         o = philox10((uint32_t)t, rho, (uint32_t)r, stream_word(kStreamDaemon, s), g.key0, g.key1);
     ballot4(g, live ? 4 * t : 0, o,
             [&](uint32_t u, uint32_t& b0, uint32_t& b1) {
@@ -177,12 +216,13 @@ __global__ void __launch_bounds__(256) kb_refresh_dev(GeomB b, uint64_t* __restr
     const DaemonThresholds th = dth[rho];
     const Geom& g = b.g;
     const int wl = blockIdx.y;
-    const int G = wl / g.R, r = wl % g.R;
     const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const bool live = t < g.Nh / 2;
-    const uint32_t s = (uint32_t)(64 * G + lane_id());
+    int si, r;
+    const bool lane_ok = bp_lattice(b, wl, lane_id(), si, r);
+    const uint32_t s = (uint32_t)si;
     u32x4 o = {0, 0, 0, 0};
-    if (live && s < (uint32_t)g.S)
+    if (live && lane_ok)
         o = philox10((uint32_t)t, (uint32_t)rho, (uint32_t)r, stream_word(kStreamDaemon, s), g.key0, g.key1);
     ballot4(g, live ? 4 * t : 0, o,
             [&](uint32_t u, uint32_t& b0, uint32_t& b1) {
@@ -202,7 +242,7 @@ __global__ void __launch_bounds__(256) kb_micsa_half(GeomB b, uint64_t* __restri
 {
     const Geom& g = b.g;
     const int wl = blockIdx.y;
-    const int G = wl / g.R;
+    const int G = bp_cset(b, wl);
     const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= (uint32_t)g.Nh) return;
     const int row = (int)(h / (uint32_t)g.Kx), k = (int)(h - (uint32_t)row * (uint32_t)g.Kx);
@@ -247,10 +287,12 @@ __global__ void __launch_bounds__(256) kb_micsa_half(GeomB b, uint64_t* __restri
 }
 
 // ------------------------------------------------------------ reductions
-// Per-lane counts: one wave per block; lane l owns sample 64G + l and counts
-// its bit of every word the wave reads (the same word for all lanes).
-// kind 0: unsatisfied bonds U (H = 2U - 3N); 1: daemon levels sum m;
-// 2: sites where replicas a and b differ.
+// Per-lane counts: one wave per block; lane l owns the lattice of its bit
+// and counts its bit of every word the wave reads (the same word for all
+// lanes).  kind 0: unsatisfied bonds U (H = 2U - 3N); 1: daemon levels sum
+// m; 2: sites where replicas a and b differ (samples mode: grid y over the
+// lane groups, lane l = sample; replicas mode: grid y over the samples, the
+// lanes splitting the words and the wave summing one count per sample).
 template <int KIND>
 __global__ void __launch_bounds__(64) kb_lane_count(GeomB b, const uint64_t* __restrict__ spin,
                                                    const uint64_t* __restrict__ dm0,
@@ -259,12 +301,23 @@ __global__ void __launch_bounds__(64) kb_lane_count(GeomB b, const uint64_t* __r
                                                    int64_t sites_per_block, unsigned long long* __restrict__ out)
 {
     const Geom& g = b.g;
-    const int wl = blockIdx.y;  // KIND 2: lane group; otherwise word lattice
-    const int G = KIND == 2 ? wl : wl / g.R, r = KIND == 2 ? 0 : wl % g.R;
+    const int wl = blockIdx.y;  // KIND 2: lane group (samples) or sample (replicas); otherwise word lattice
+    const int G = KIND == 2 ? wl : bp_cset(b, wl);
     const int lane = lane_id();
     const int64_t h0 = (int64_t)blockIdx.x * sites_per_block;
     const int64_t h1 = h0 + sites_per_block < g.Nh ? h0 + sites_per_block : g.Nh;
     long long cnt = 0;
+    if (KIND == 2 && b.mode) {
+        int la, lb;
+        const uint64_t* sa = spin + (int64_t)bp_word_of(b, wl, ra, la) * 2 * g.Nh;
+        const uint64_t* sb = spin + (int64_t)bp_word_of(b, wl, rb, lb) * 2 * g.Nh;
+        for (int64_t h = h0 + lane; h < h1; h += 64)
+            for (int p = 0; p < 2; ++p)
+                cnt += (long long)(((sa[p * g.Nh + h] >> la) ^ (sb[p * g.Nh + h] >> lb)) & 1u);
+        cnt = wave_sum64(cnt);
+        if (lane == 0 && cnt != 0) atomicAdd(&out[(int64_t)wl * kSlots + (blockIdx.x % kSlots)], (unsigned long long)cnt);
+        return;
+    }
     if (KIND == 0) {
         const uint64_t* ev = spin + (int64_t)wl * 2 * g.Nh;
         const uint64_t* od = ev + g.Nh;
@@ -299,8 +352,9 @@ __global__ void __launch_bounds__(64) kb_lane_count(GeomB b, const uint64_t* __r
         for (int64_t h = h0; h < h1; ++h)
             for (int p = 0; p < 2; ++p) cnt += (long long)(((sa[p * g.Nh + h] ^ sb[p * g.Nh + h]) >> lane) & 1u);
     }
-    const int s = 64 * G + lane;
-    if (s < g.S && cnt != 0) {
+    int s, r;
+    const bool ok = KIND == 2 ? ((s = 64 * G + lane) < g.S) : bp_lattice(b, wl, lane, s, r);
+    if (ok && cnt != 0) {
         const int64_t ent = KIND == 2 ? s : (int64_t)s * g.R + r;
         atomicAdd(&out[ent * kSlots + (blockIdx.x % kSlots)], (unsigned long long)cnt);
     }

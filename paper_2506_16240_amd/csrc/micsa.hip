@@ -16,9 +16,11 @@
 #include <vector>
 
 #include "bitplane_kernels.hpp"
+#include "bitplane_sweep.hpp"
 #include "fused_kernels.hpp"
 #include "fused2_kernels.hpp"
 #include "msc_kernels.hpp"
+#include "msc2_kernels.hpp"
 #include "observables.hpp"
 #include "resident_kernels.hpp"
 #include "micsa.h"
@@ -63,6 +65,13 @@ struct micsa_ctx {
     uint64_t* bdm0 = nullptr;   // [G][R][2][Nh]
     uint64_t* bdm1 = nullptr;   // [G][R][2][Nh]
     uint64_t* bJ = nullptr;     // [G][6][Nh]
+    // one-launch bit-plane sweep (bitplane_sweep.hpp): it writes these, then
+    // they swap with the current arrays (allocated on first use)
+    uint64_t *bspin_alt = nullptr, *bdm0_alt = nullptr, *bdm1_alt = nullptr;
+    uint64_t *bdr0 = nullptr, *bdr1 = nullptr;  // levels of the next refresh, drawn ahead
+    // the bit-plane tally is kept by the one-launch sweep only; a per-half
+    // sweep leaves it stale until the spins are written again
+    bool tally_ok = true;
     // multispin working planes (msc_kernels.hpp), allocated on first use
     uint64_t* ms = nullptr;   // [L][2][rows][Lx/128] spins
     uint64_t* md0 = nullptr;  // daemon level bit 0, same shape
@@ -82,6 +91,7 @@ struct micsa_ctx {
     int32_t xcd_map = 2;  // XCD-aware tile order for the fused sweeps (2: z bands on the multispin sweep)
     int32_t prefetch = 1;  // steps of loads in flight in the fused MicSA sweep (1 or 2)
     int32_t temporal = 2;  // MicSA sweeps per pass of the fused kernel (1 or 2)
+    int32_t msc_pass = 1;  // MicSA sweeps per pass of the one-launch multispin sweep (1 or 2)
     int32_t use_graphs = 0;
     // walkers on the fused sweep: parity of a forward-X wandering the stored
     // daemons still owe (applied by the next fused sweep on load), or -1
@@ -262,11 +272,150 @@ int set_tally(micsa_ctx* c, const std::vector<int64_t>& E)
     return MICSA_OK;
 }
 
-GeomB geomb(const micsa_ctx* c) { return GeomB{c->g, c->G}; }
+GeomB geomb(const micsa_ctx* c) { return GeomB{c->g, c->G, c->p.lane_mode}; }
+
+int word_lattices(const micsa_ctx* c) { return bp_word_lattices(geomb(c)); }
+
+// Launch shape of the one-launch bit-plane sweep: TZ planes per work-group
+// (1, or 2 with TILE_Z = 2), one thread per word of a plane, LDS for TZ + 4
+// odd and TZ + 2 even planes.
+struct BpLaunch {
+    BpTile f;
+    unsigned block;
+    size_t lds;
+};
+
+BpLaunch bp_launch(const micsa_ctx* c)
+{
+    BpLaunch b{};
+    const int P = c->p.Ly * (c->p.Lx / 2);
+    const int TZ = c->tile_z == 2 && c->p.Lz % 2 == 0 && P <= 512 ? 2 : 1;
+    b.f = BpTile{TZ, c->p.Lz / TZ, P};
+    b.block = (unsigned)((P + 63) / 64 * 64);
+    const size_t planes = (size_t)(2 * TZ + 6) * P * 8, part = (size_t)(b.block / 64) * 64 * 8;
+    b.lds = std::max(planes, part);
+    return b;
+}
+
+// The one-launch sweep fits: a word position per thread (at most 1024 per
+// work-group) and LDS within a work-group's 160 KB.
+bool bp_fits(const micsa_ctx* c, const BpLaunch& b)
+{
+    return b.f.P <= (b.f.TZ == 1 ? 1024 : 512) && b.lds <= 160 * 1024;
+}
+
+bool bp_one_launch(const micsa_ctx* c)
+{
+    return c->bit && c->kernel_opt != MICSA_KERNEL_SIMPLE && bp_fits(c, bp_launch(c));
+}
+
+// One-launch bit-plane sweep; with drawn the levels are read from the drawn
+// planes (a refresh drawn ahead).
+int launch_bp_sweep(micsa_ctx* c, bool drawn)
+{
+    const BpLaunch b = bp_launch(c);
+    if (!c->bspin_alt) {
+        const size_t words = (size_t)word_lattices(c) * 2 * (size_t)c->g.Nh;
+        bool ok = true;
+        for (uint64_t** q : {&c->bspin_alt, &c->bdm0_alt, &c->bdm1_alt})
+            ok = ok && hipMalloc(q, words * 8) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            for (uint64_t** q : {&c->bspin_alt, &c->bdm0_alt, &c->bdm1_alt}) {
+                if (*q) (void)hipFree(*q);
+                *q = nullptr;
+            }
+            return fail(c, MICSA_ENOMEM, "bit-plane sweep buffers");
+        }
+    }
+    const auto kern = b.f.TZ == 2 ? kb_sweep<true, 2> : kb_sweep<true, 1>;
+    if (b.lds > 64 * 1024 &&
+        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.lds) != hipSuccess)
+        return fail(c, MICSA_EHIP, "kb_sweep LDS attribute");
+    const dim3 grid((unsigned)(b.f.ntz * word_lattices(c)));
+    {
+        TimedLaunch t(c, kTimeSweep);
+        kern<<<grid, b.block, b.lds, c->stream>>>(geomb(c), b.f, c->bspin, drawn ? c->bdr0 : c->bdm0,
+                                                  drawn ? c->bdr1 : c->bdm1, c->bJ, c->bspin_alt, c->bdm0_alt,
+                                                  c->bdm1_alt, c->tally);
+    }
+    const int st = check_launch(c, "kb_sweep");
+    if (st) return st;
+    std::swap(c->bspin, c->bspin_alt);
+    std::swap(c->bdm0, c->bdm0_alt);
+    std::swap(c->bdm1, c->bdm1_alt);
+    return MICSA_OK;
+}
+
+int64_t next_refresh(const micsa_ctx* c, int64_t from, int64_t end);
+
+// Draw the levels of bit-plane refresh sweep kr into the drawn planes on the
+// side stream, after everything the library stream holds so far (the sweep
+// that last read them); the refresh sweep waits for draw_done.
+int draw_bp_levels(micsa_ctx* c, int64_t kr)
+{
+    const int64_t rho = refresh_index(kr, c->sched.period);
+    const double T = temperature(c->sched, rho);
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
+    if (!c->bdr0) {
+        const size_t words = (size_t)word_lattices(c) * 2 * (size_t)c->g.Nh;
+        if (hipMalloc(&c->bdr0, words * 8) != hipSuccess || hipMalloc(&c->bdr1, words * 8) != hipSuccess) {
+            (void)hipGetLastError();
+            if (c->bdr0) (void)hipFree(c->bdr0);
+            c->bdr0 = c->bdr1 = nullptr;
+            return fail(c, MICSA_ENOMEM, "bit-plane drawn levels");
+        }
+    }
+    if (!c->draw_stream) {
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->draw_stream, hipStreamNonBlocking));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->draw_free, hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->draw_done, hipEventDisableTiming));
+    }
+    HIP_TRY(c, hipEventRecord(c->draw_free, c->stream));
+    HIP_TRY(c, hipStreamWaitEvent(c->draw_stream, c->draw_free, 0));
+    kb_refresh<<<dim3((unsigned)((c->g.Nh / 2 + 3) / 4), (unsigned)word_lattices(c)), 256, 0, c->draw_stream>>>(
+        geomb(c), c->bdr0, c->bdr1, (uint32_t)rho, daemon_thresholds(T));
+    const int st = check_launch(c, "kb_refresh (drawn ahead)");
+    if (st) return st;
+    HIP_TRY(c, hipEventRecord(c->draw_done, c->draw_stream));
+    return MICSA_OK;
+}
+
+// MicSA sweeps k .. k + n - 1 of the bit-plane layout on the one-launch
+// sweep; the levels of each refresh are drawn ahead on the side stream
+// (OPT_DRAW_AHEAD, default) while the sweeps before it run, or in place just
+// before it.
+int sweep_bitplane(micsa_ctx* c, int64_t n)
+{
+    const int64_t k_end = c->k + n;
+    int64_t drawn = -1;
+    int st;
+    if (c->draw_ahead && (drawn = next_refresh(c, c->k, k_end)) >= 0 && (st = draw_bp_levels(c, drawn))) return st;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t k = c->k;
+        const bool refresh = is_refresh(k, c->sched.period);
+        const int64_t rho = refresh_index(k, c->sched.period);
+        const double T = temperature(c->sched, rho);
+        if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
+        const bool use_drawn = refresh && drawn == k;
+        if (use_drawn) {
+            HIP_TRY(c, hipStreamWaitEvent(c->stream, c->draw_done, 0));
+        } else if (refresh) {
+            TimedLaunch t(c, kTimeRefresh);
+            kb_refresh<<<dim3((unsigned)((c->g.Nh / 2 + 3) / 4), (unsigned)word_lattices(c)), 256, 0, c->stream>>>(
+                geomb(c), c->bdm0, c->bdm1, (uint32_t)rho, daemon_thresholds(T));
+            if ((st = check_launch(c, "kb_refresh"))) return st;
+        }
+        if ((st = launch_bp_sweep(c, use_drawn))) return st;
+        if (use_drawn && (drawn = next_refresh(c, k + 1, k_end)) >= 0 && (st = draw_bp_levels(c, drawn))) return st;
+        c->k = k + 1;
+    }
+    return MICSA_OK;
+}
 
 int launch_bitplane_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
 {
-    const int WL = c->G * c->p.n_replicas;
+    const int WL = word_lattices(c);
     if (refresh) {
         TimedLaunch t(c, kTimeRefresh);
         kb_refresh<<<dim3((unsigned)((c->g.Nh / 2 + 3) / 4), (unsigned)WL), 256, 0, c->stream>>>(
@@ -274,6 +423,7 @@ int launch_bitplane_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
     }
     int st = check_launch(c, "kb_refresh");
     if (st) return st;
+    c->tally_ok = false;
     const dim3 grid = grid_for(c->g.Nh, WL);
     {
         TimedLaunch t(c, kTimeSweep);
@@ -295,7 +445,7 @@ int enqueue_lane_count(micsa_ctx* c, unsigned long long* dst, int ra, int rb)
     int st = zero_slots(c, dst, ent);
     if (st) return st;
     const int64_t per_block = 128;
-    const unsigned ny = (unsigned)(KIND == 2 ? c->G : c->G * c->p.n_replicas);
+    const unsigned ny = (unsigned)(KIND == 2 ? (c->p.lane_mode ? c->p.n_samples : c->G) : word_lattices(c));
     {
         TimedLaunch t(c, kTimeReduce);
         kb_lane_count<KIND><<<dim3((unsigned)((c->g.Nh + per_block - 1) / per_block), ny), 64, 0, c->stream>>>(
@@ -673,12 +823,13 @@ int enqueue_dev_sweep(micsa_ctx* c, int32_t algo, hipStream_t st)
 {
     const int32_t P = c->sched.period;
     if (c->bit) {
-        const int WL = c->G * c->p.n_replicas;
+        const int WL = word_lattices(c);
         kb_refresh_dev<<<dim3((unsigned)((c->g.Nh / 2 + 3) / 4), (unsigned)WL), 256, 0, st>>>(
             geomb(c), c->bdm0, c->bdm1, c->d_k, P, c->d_dth);
         const dim3 grid = grid_for(c->g.Nh, WL);
         kb_micsa_half<0><<<grid, kBlock, 0, st>>>(geomb(c), c->bspin, c->bdm0, c->bdm1, c->bJ);
         kb_micsa_half<1><<<grid, kBlock, 0, st>>>(geomb(c), c->bspin, c->bdm0, c->bdm1, c->bJ);
+        c->tally_ok = false;
     } else {
         const int64_t words = (int64_t)c->g.rows * c->g.Wr;
         if (algo == MICSA_ALGO_MICSA) {
@@ -787,6 +938,45 @@ MscTile msc_tile(const micsa_ctx* c)
     return f;
 }
 
+// Tile of the two-sweep multispin pass (msc2_kernels.hpp): (TY + 8) W lanes,
+// whole waves up to kMsc2Lanes (Lx = 512: 40 rows, 192 lanes); TZ as the
+// one-sweep tile.
+constexpr int kMscPassSweeps = 2;
+
+MscTile msc2_tile(const micsa_ctx* c)
+{
+    const int W = c->p.Lx / 128, ring = 4 * kMscPassSweeps;
+    MscTile f{};
+    if (c->tile_y) {
+        f.TY = c->tile_y;
+    } else {
+        int rows = 0;
+        for (int r = ring + 1; r * W <= 192; ++r)
+            if ((r * W) % 64 == 0) rows = r;
+        f.TY = rows ? std::min(rows - ring, c->p.Ly) : std::max(1, std::min(c->p.Ly, kMsc2Lanes / W - ring));
+    }
+    f.TZ = c->tile_z ? c->tile_z : divisor_at_most(c->p.Lz, 8);
+    f.nty = (c->p.Ly + f.TY - 1) / f.TY;
+    f.ntz = c->p.Lz / f.TZ;
+    f.xcd = c->xcd_map == 2 && f.ntz % 8 == 0 ? 2 : (c->xcd_map && (f.nty * f.ntz) % 8 == 0 ? 1 : 0);
+    return f;
+}
+
+size_t msc2_lds(const MscTile& f, int W)
+{
+    constexpr int H = 2 * kMscPassSweeps, D = 2 * kMscPassSweeps + 1;
+    return (size_t)8 * (2 * H + 6 * D) * (size_t)((f.TY + 2 * H) * W);
+}
+
+// The pass fits a work-group: lanes and LDS (two work-groups per CU).
+bool msc2_fits(const micsa_ctx* c)
+{
+    const MscTile f = msc2_tile(c);
+    const int W = c->p.Lx / 128;
+    return c->msc_pass == 2 && ((f.TY + 4 * kMscPassSweeps) * W + 63) / 64 * 64 <= kMsc2Lanes &&
+           msc2_lds(f, W) <= 80 * 1024;
+}
+
 bool msc_one_launch(const micsa_ctx* c)
 {
     return c->msc_fused && ((msc_tile(c).TY + 4) * (c->p.Lx / 128) + 63) / 64 * 64 <= kMscSweepLanes;
@@ -886,6 +1076,64 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
         const double T = temperature(c->sched, rho);
         if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
         const DaemonThresholds th = refresh ? daemon_thresholds(T) : DaemonThresholds{0, 0, 0};
+        if (one && !walkers && c->pend_wander < 0 && i + 1 < n && msc2_fits(c)) {
+            // sweeps k and k + 1 in one pass; a refresh among them reads its
+            // drawn levels (at most one refresh per pass, drawn ahead)
+            const bool refresh2 = is_refresh(k + 1, c->sched.period);
+            const bool ok2 = (!refresh || (ahead && drawn == k)) && (!refresh2 || (ahead && drawn == k + 1)) &&
+                             !(refresh && refresh2);
+            if (ok2) {
+                if (refresh || refresh2) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->draw_done, 0));
+                const MscTile f2 = msc2_tile(c);
+                const int lanes2 = (f2.TY + 4 * kMscPassSweeps) * m.W;
+                const dim3 grid2((unsigned)(f2.nty * f2.ntz), (unsigned)c->L);
+                const unsigned block2 = (unsigned)((lanes2 + 63) / 64 * 64);
+                const size_t lds2 = msc2_lds(f2, m.W);
+                const auto kern = k_msc_sweep_multi<kMscPassSweeps>;
+                if (lds2 > 64 * 1024 &&
+                    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2) !=
+                        hipSuccess)
+                    return fail(c, MICSA_EHIP, "k_msc_sweep_multi LDS attribute");
+                Geom a_g = c->g;
+                MscGeom a_m = m;
+                MscTile a_f = f2;
+                const uint64_t *a_s = c->ms, *a_d0 = refresh ? c->mdr0 : c->md0, *a_d1 = refresh ? c->mdr1 : c->md1,
+                               *a_b = c->mb, *a_r0 = c->mdr0, *a_r1 = c->mdr1;
+                int a_rj = refresh2 ? 1 : -1;
+                uint64_t *o_s = c->ms_alt, *o_d0 = c->md0_alt, *o_d1 = c->md1_alt;
+                unsigned long long* a_t = c->tally;
+                void* args[] = {&a_g, &a_m, &a_f, &a_s, &a_d0, &a_d1, &a_b, &a_r0, &a_r1, &a_rj, &o_s, &o_d0, &o_d1,
+                                &a_t};
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (c->timing && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
+                    if (e0) (void)hipEventDestroy(e0);
+                    e0 = e1 = nullptr;
+                }
+                const hipError_t le =
+                    hipExtLaunchKernel((const void*)kern, grid2, block2, args, lds2, c->stream, e0, e1, 0);
+                if (e0 && e1) {
+                    if (le == hipSuccess) {
+                        c->events[kTimeSweep].push_back({e0, e1});
+                    } else {
+                        (void)hipEventDestroy(e0);
+                        (void)hipEventDestroy(e1);
+                    }
+                }
+                if (le != hipSuccess)
+                    return fail(c, MICSA_EHIP, std::string("k_msc_sweep_multi: ") + hipGetErrorString(le));
+                if ((st = check_launch(c, "k_msc_sweep_multi"))) return st;
+                if ((refresh || refresh2) && (drawn = next_refresh(c, k + 2, k_end)) >= 0 &&
+                    (st = draw_levels(c, m, drawn)))
+                    return st;
+                std::swap(c->ms, c->ms_alt);
+                std::swap(c->md0, c->md0_alt);
+                std::swap(c->md1, c->md1_alt);
+                c->pend_wander = -1;
+                c->k = k + 2;
+                ++i;
+                continue;
+            }
+        }
         if (one) {
             // a refresh sweep with levels drawn ahead is a plain sweep reading them
             const bool use_drawn = refresh && ahead && drawn == k;
@@ -997,6 +1245,7 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
         if (use_resident(c)) return launch_resident(c, algo, n, nullptr, 0);
         if (use_graph(c) && n >= kGraphSweeps) return sweep_graph(c, algo, n);
     }
+    if (algo == MICSA_ALGO_MICSA && bp_one_launch(c)) return sweep_bitplane(c, n);
     for (int64_t i = 0; i < n; ++i) {
         // sweep k is sweep fam of timestep t (Sec. 2.8)
         const int64_t k = c->k;
@@ -1070,6 +1319,8 @@ void free_all(micsa_ctx* c)
     if (c->draw_done) (void)hipEventDestroy(c->draw_done);
     if (c->draw_stream) (void)hipStreamDestroy(c->draw_stream);
     if (c->bdm0) (void)hipFree(c->bdm0);
+    for (uint64_t* q : {c->bspin_alt, c->bdm0_alt, c->bdm1_alt, c->bdr0, c->bdr1})
+        if (q) (void)hipFree(q);
     if (c->bdm1) (void)hipFree(c->bdm1);
     if (c->bJ) (void)hipFree(c->bJ);
     if (c->d_dth) (void)hipFree(c->d_dth);
@@ -1099,7 +1350,7 @@ bool params_ok(const micsa_params* p)
     const int gamma = p->gamma == 0 ? 1 : p->gamma;
     if (gamma < 1 || gamma > 6 || (gamma > 1 && p->layout != MICSA_LAYOUT_BYTE)) return false;
     if (p->lane_mode != MICSA_LANES_SAMPLES && p->lane_mode != MICSA_LANES_REPLICAS) return false;
-    if (p->lane_mode == MICSA_LANES_REPLICAS) return false;  // not built yet
+    if (p->lane_mode == MICSA_LANES_REPLICAS && p->layout != MICSA_LAYOUT_BITPLANE) return false;
     return (int64_t)gamma * N / 4 < ((int64_t)1 << 32);  // daemon counters (a*N + i) >> 2 fit 32 bits
 }
 
@@ -1140,7 +1391,7 @@ int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
     c->stream = (hipStream_t)hip_stream;
     c->L = p->n_samples * p->n_replicas;
     c->bit = p->layout == MICSA_LAYOUT_BITPLANE;
-    c->G = (p->n_samples + 63) / 64;
+    c->G = p->lane_mode == MICSA_LANES_REPLICAS ? (p->n_replicas + 63) / 64 : (p->n_samples + 63) / 64;
     Geom& g = c->g;
     g.Lx = p->Lx;
     g.Ly = p->Ly;
@@ -1160,14 +1411,14 @@ int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
               hipMalloc(&c->red, nred * kSlots * 8) == hipSuccess;
     const size_t state = (size_t)c->L * 2 * (size_t)g.Nh;
     const size_t dstate = state * (size_t)gamma;  // every daemon family
-    const size_t words = (size_t)c->G * p->n_replicas * 2 * (size_t)g.Nh;
+    const size_t words = (size_t)word_lattices(c) * 2 * (size_t)g.Nh;
     if (ok && !c->bit) {
         ok = hipMalloc(&c->spin, state) == hipSuccess && hipMalloc(&c->dem, dstate) == hipSuccess &&
              hipMalloc(&c->spin_alt, state) == hipSuccess && hipMalloc(&c->dem_alt, dstate) == hipSuccess;
     } else if (ok) {
         ok = hipMalloc(&c->bspin, words * 8) == hipSuccess && hipMalloc(&c->bdm0, words * 8) == hipSuccess &&
              hipMalloc(&c->bdm1, words * 8) == hipSuccess &&
-             hipMalloc(&c->bJ, (size_t)c->G * 6 * (size_t)g.Nh * 8) == hipSuccess;
+             hipMalloc(&c->bJ, (size_t)bp_coupling_sets(geomb(c)) * 6 * (size_t)g.Nh * 8) == hipSuccess;
     }
     if (!ok) {
         (void)hipGetLastError();
@@ -1183,8 +1434,9 @@ int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
         if (!st) st = enqueue_bonds(c);
         if (!st && hipMemsetAsync(c->dem, 0, dstate, c->stream) != hipSuccess) st = MICSA_EHIP;
     } else {
-        const int WL = c->G * p->n_replicas;
-        kb_init_couplings<<<dim3((unsigned)((g.Nh + 3) / 4), (unsigned)c->G), 256, 0, c->stream>>>(geomb(c), c->bJ);
+        const int WL = word_lattices(c);
+        kb_init_couplings<<<dim3((unsigned)((g.Nh + 3) / 4), (unsigned)bp_coupling_sets(geomb(c))), 256, 0,
+                            c->stream>>>(geomb(c), c->bJ);
         st = check_launch(c, "kb_init_couplings");
         if (!st) {
             kb_init_spins<<<dim3((unsigned)((g.Nh / 2 + 3) / 4), (unsigned)WL), 256, 0, c->stream>>>(geomb(c),
@@ -1381,7 +1633,9 @@ int micsa_read_energy(micsa_ctx* ctx, int64_t* E)
 int micsa_read_energy_tally(micsa_ctx* ctx, int64_t* E)
 {
     if (!ctx || !E) return MICSA_EINVAL;
-    if (ctx->bit) return fail(ctx, MICSA_ESTATE, "the bit-plane layout keeps no incremental tally");
+    if (ctx->bit && !ctx->tally_ok)
+        return fail(ctx, MICSA_ESTATE, "the bit-plane tally is kept by the one-launch sweep only (a per-half "
+                                       "sweep ran since the spins were last set)");
     std::vector<int64_t> v;
     int st = read_slots(ctx, ctx->tally, ctx->L, v);
     if (st) return st;
@@ -1424,10 +1678,10 @@ static int c4_counts(micsa_ctx* c, const C4Geom& cg, std::vector<int64_t>& D)
             TimedLaunch t(c, kTimeReduce);
             if (c->bit)
                 k_pack_overlap<true><<<dim3((unsigned)((per_pair + 255) / 256), n), 256, 0, c->stream>>>(
-                    c->g, cg, (int)sp0, nullptr, c->bspin, Q);
+                    geomb(c), cg, (int)sp0, nullptr, c->bspin, Q);
             else
                 k_pack_overlap<false><<<dim3((unsigned)((per_pair + 255) / 256), n), 256, 0, c->stream>>>(
-                    c->g, cg, (int)sp0, c->spin, nullptr, Q);
+                    geomb(c), cg, (int)sp0, c->spin, nullptr, Q);
         }
         if ((st = check_launch(c, "k_pack_overlap"))) break;
         {
@@ -1550,13 +1804,14 @@ static int read_state(micsa_ctx* ctx, const uint8_t* dev, uint8_t* host, int64_t
     return MICSA_OK;
 }
 
-// Bit-plane words [G][R][2][Nh] -> host values [S][R][N]; with two planes
+// Bit-plane words [WL][2][Nh] -> host values [S][R][N]; with two planes
 // (daemons) the value is bit0 + 2 bit1.
 static int read_words(micsa_ctx* ctx, const uint64_t* w0, const uint64_t* w1, uint8_t* host)
 {
     const int64_t N = n_sites(ctx);
     const int R = ctx->p.n_replicas;
-    const size_t n = (size_t)ctx->G * R * 2 * (size_t)ctx->g.Nh;
+    const GeomB gb = geomb(ctx);
+    const size_t n = (size_t)word_lattices(ctx) * 2 * (size_t)ctx->g.Nh;
     std::vector<uint64_t> a(n), b(w1 ? n : 0);
     HIP_TRY(ctx, hipMemcpyAsync(a.data(), w0, n * 8, hipMemcpyDeviceToHost, ctx->stream));
     if (w1) HIP_TRY(ctx, hipMemcpyAsync(b.data(), w1, n * 8, hipMemcpyDeviceToHost, ctx->stream));
@@ -1567,8 +1822,8 @@ static int read_words(micsa_ctx* ctx, const uint64_t* w0, const uint64_t* w1, ui
                 int par;
                 int64_t h;
                 split_index(ctx, i, par, h);
-                const size_t idx = (((size_t)(s / 64) * R + r) * 2 + par) * ctx->g.Nh + h;
-                const int lane = s % 64;
+                int lane;
+                const size_t idx = ((size_t)bp_word_of(gb, s, r, lane) * 2 + par) * ctx->g.Nh + h;
                 uint8_t v = (uint8_t)((a[idx] >> lane) & 1u);
                 if (w1) v = (uint8_t)(v | (((b[idx] >> lane) & 1u) << 1));
                 host[((int64_t)s * R + r) * N + i] = v;
@@ -1600,7 +1855,7 @@ int micsa_read_couplings(micsa_ctx* ctx, uint8_t* j)
     std::vector<uint8_t> jbytes;
     std::vector<uint64_t> wplanes;
     if (ctx->bit) {
-        wplanes.resize((size_t)ctx->G * 6 * g.Nh);
+        wplanes.resize((size_t)bp_coupling_sets(geomb(ctx)) * 6 * g.Nh);
         HIP_TRY(ctx, hipMemcpyAsync(wplanes.data(), ctx->bJ, wplanes.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
     } else {
         // bits 1..6 of the even spin bytes of replica 0 of each sample
@@ -1614,6 +1869,8 @@ int micsa_read_couplings(micsa_ctx* ctx, uint8_t* j)
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     const int64_t N = n_sites(ctx);
     auto bit = [&](int s, int d, int64_t h) -> uint32_t {
+        if (ctx->bit && ctx->p.lane_mode == MICSA_LANES_REPLICAS)  // broadcast words: every bit the same
+            return (uint32_t)(wplanes[((size_t)s * 6 + d) * g.Nh + (size_t)h] & 1u);
         if (ctx->bit)
             return (uint32_t)((wplanes[((size_t)(s / 64) * 6 + d) * g.Nh + (size_t)h] >> (s % 64)) & 1u);
         return (uint32_t)(jbytes[(size_t)s * g.Nh + (size_t)h] >> d) & 1u;
@@ -1661,7 +1918,8 @@ static int write_words(micsa_ctx* ctx, uint64_t* w0, uint64_t* w1, const uint8_t
 {
     const int64_t N = n_sites(ctx);
     const int R = ctx->p.n_replicas;
-    const size_t n = (size_t)ctx->G * R * 2 * (size_t)ctx->g.Nh;
+    const GeomB gb = geomb(ctx);
+    const size_t n = (size_t)word_lattices(ctx) * 2 * (size_t)ctx->g.Nh;
     std::vector<uint64_t> a(n, 0), b(w1 ? n : 0, 0);
     for (int s = 0; s < ctx->p.n_samples; ++s)
         for (int r = 0; r < R; ++r)
@@ -1671,9 +1929,10 @@ static int write_words(micsa_ctx* ctx, uint64_t* w0, uint64_t* w1, const uint8_t
                 int par;
                 int64_t h;
                 split_index(ctx, i, par, h);
-                const size_t idx = (((size_t)(s / 64) * R + r) * 2 + par) * ctx->g.Nh + h;
-                a[idx] |= (uint64_t)(v & 1u) << (s % 64);
-                if (w1) b[idx] |= (uint64_t)(v >> 1) << (s % 64);
+                int lane;
+                const size_t idx = ((size_t)bp_word_of(gb, s, r, lane) * 2 + par) * ctx->g.Nh + h;
+                a[idx] |= (uint64_t)(v & 1u) << lane;
+                if (w1) b[idx] |= (uint64_t)(v >> 1) << lane;
             }
     HIP_TRY(ctx, hipMemcpyAsync(w0, a.data(), n * 8, hipMemcpyHostToDevice, ctx->stream));
     if (w1) HIP_TRY(ctx, hipMemcpyAsync(w1, b.data(), n * 8, hipMemcpyHostToDevice, ctx->stream));
@@ -1689,7 +1948,9 @@ int micsa_write_spins(micsa_ctx* ctx, const uint8_t* sigma)
     if (st) return st;
     std::vector<int64_t> E((size_t)ctx->L);
     if ((st = micsa_read_energy(ctx, E.data()))) return st;
-    return set_tally(ctx, E);
+    if ((st = set_tally(ctx, E))) return st;
+    ctx->tally_ok = true;
+    return MICSA_OK;
 }
 
 int micsa_write_demons(micsa_ctx* ctx, const uint8_t* m)
@@ -1789,7 +2050,7 @@ int micsa_save(micsa_ctx* ctx, void* buf, size_t* len)
     if ((st = micsa_read_spins(ctx, spins))) return st;
     if ((st = micsa_read_couplings(ctx, coup))) return st;
     std::vector<int64_t> E(L);
-    st = ctx->bit ? micsa_read_energy(ctx, E.data()) : micsa_read_energy_tally(ctx, E.data());
+    st = ctx->bit && !ctx->tally_ok ? micsa_read_energy(ctx, E.data()) : micsa_read_energy_tally(ctx, E.data());
     if (st) return st;
     std::memcpy(tally, E.data(), L * 8);
     h.k = ctx->k;
@@ -1851,7 +2112,7 @@ int micsa_load(micsa_ctx* ctx, const void* buf, size_t len)
     }
     if ((st = micsa_write_spins(ctx, spins))) return st;
     if ((st = micsa_write_demons(ctx, dems))) return st;
-    if (!ctx->bit) {
+    {
         std::vector<int64_t> E(L);
         std::memcpy(E.data(), tally, L * 8);
         if ((st = set_tally(ctx, E))) return st;
@@ -1933,7 +2194,8 @@ int micsa_get_timing(micsa_ctx* ctx, int32_t kind, double* total_ms, int64_t* la
 
 const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
 {
-    if (ctx && ctx->bit) return algo == MICSA_ALGO_MICSA ? "kb_micsa_half" : "";
+    if (ctx && ctx->bit)
+        return algo == MICSA_ALGO_MICSA ? (bp_one_launch(ctx) && !use_graph(ctx) ? "kb_sweep" : "kb_micsa_half") : "";
     if (ctx && algo == MICSA_ALGO_MICSA && use_msc(ctx))
         return msc_one_launch(ctx) ? "k_msc_sweep" : "k_msc_half";
     // walkers on the fused sweeps wander on the next sweep's loads
@@ -1991,6 +2253,10 @@ int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value)
         if (value != 1 && value != 2) return fail(ctx, MICSA_EINVAL, "temporal is 1 or 2");
         ctx->temporal = (int32_t)value;
         return MICSA_OK;
+    case MICSA_OPT_MSC_PASS:
+        if (value != 1 && value != 2) return fail(ctx, MICSA_EINVAL, "msc_pass is 1 or 2");
+        ctx->msc_pass = (int32_t)value;
+        return MICSA_OK;
     case MICSA_OPT_PREFETCH:
         if (value != 1 && value != 2) return fail(ctx, MICSA_EINVAL, "prefetch is 1 or 2");
         ctx->prefetch = (int32_t)value;
@@ -2028,8 +2294,11 @@ size_t footprint(const micsa_params* p)
     const size_t L = (size_t)p->n_samples * p->n_replicas;
     const size_t slots = (L + (size_t)p->n_samples) * kSlots * 8;
     if (p->layout == MICSA_LAYOUT_BITPLANE) {
-        const size_t G = ((size_t)p->n_samples + 63) / 64;
-        return G * p->n_replicas * N * 8 * 3 + G * 6 * (N / 2) * 8 + slots;
+        const bool reps = p->lane_mode == MICSA_LANES_REPLICAS;
+        const size_t WL = reps ? (size_t)p->n_samples * (((size_t)p->n_replicas + 63) / 64)
+                               : (((size_t)p->n_samples + 63) / 64) * p->n_replicas;
+        const size_t NJ = reps ? (size_t)p->n_samples : ((size_t)p->n_samples + 63) / 64;
+        return 2 * WL * N * 8 * 3 + NJ * 6 * (N / 2) * 8 + slots;  // state and its alternate
     }
     const size_t gamma = p->gamma == 0 ? 1 : (size_t)p->gamma;
     // 2 state buffers x (spin + gamma daemons); the couplings live in the even spin bytes

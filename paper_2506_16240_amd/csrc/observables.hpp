@@ -32,9 +32,10 @@ struct C4Geom {
 // Thread per output word; the bits come from the spin bytes (byte layout) or
 // from the lane of the sample in the bit-plane words.
 template <bool BIT>
-__global__ void __launch_bounds__(256) k_pack_overlap(Geom g, C4Geom cg, int sp0, const uint8_t* __restrict__ spin,
+__global__ void __launch_bounds__(256) k_pack_overlap(GeomB gb, C4Geom cg, int sp0, const uint8_t* __restrict__ spin,
                                                       const uint64_t* __restrict__ bspin, uint32_t* __restrict__ Q)
 {
+    const Geom& g = gb.g;
     const int64_t per_pair = (int64_t)2 * g.rows * cg.E;
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= per_pair) return;
@@ -56,10 +57,10 @@ __global__ void __launch_bounds__(256) k_pack_overlap(Geom g, C4Geom cg, int sp0
         const int64_t h = row * g.Kx + k;
         uint32_t va, vb;
         if (BIT) {
-            const int grp = s >> 6, lane = s & 63;
-            const int64_t base = ((int64_t)grp * g.R) * 2 * g.Nh;
-            va = (uint32_t)(bspin[base + ((int64_t)a * 2 + p) * g.Nh + h] >> lane) & 1u;
-            vb = (uint32_t)(bspin[base + ((int64_t)b * 2 + p) * g.Nh + h] >> lane) & 1u;
+            int la, lb;
+            const int64_t wa = bp_word_of(gb, s, a, la), wb = bp_word_of(gb, s, b, lb);
+            va = (uint32_t)(bspin[(wa * 2 + p) * g.Nh + h] >> la) & 1u;
+            vb = (uint32_t)(bspin[(wb * 2 + p) * g.Nh + h] >> lb) & 1u;
         } else {
             va = spin[(((int64_t)s * g.R + a) * 2 + p) * g.Nh + h];
             vb = spin[(((int64_t)s * g.R + b) * 2 + p) * g.Nh + h];

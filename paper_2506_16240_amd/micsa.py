@@ -24,6 +24,7 @@ REFRESH_LOG2 = 0
 TIME_SWEEP, TIME_REFRESH, TIME_HEATBATH, TIME_REDUCE, TIME_METROPOLIS = 0, 1, 2, 3, 4
 OPT_SWEEP_KERNEL, OPT_TILE_Y, OPT_TILE_Z, OPT_XCD_MAP, OPT_GRAPHS, OPT_PREFETCH, OPT_TEMPORAL, OPT_MSC_FUSED = 1, 2, 3, 4, 5, 6, 7, 8
 OPT_DRAW_AHEAD = 9
+OPT_MSC_PASS = 10
 KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_FUSED, KERNEL_RESIDENT, KERNEL_MULTISPIN = 0, 1, 2, 3, 4
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_RELEASED = 0, 1, 2, 3
 PT_WALKERS, PT_METROPOLIS = 0, 1

@@ -411,10 +411,14 @@ def test_multispin_launch_shapes_give_the_same_bits():
     ref = None
     variants = [(0, 0, 0, 1, 1), (1, 0, 0, 0, 1), (1, 3, 2, 0, 1), (1, 5, 3, 0, 1), (1, 3, 3, 1, 0), (1, 1, 1, 1, 0)] + [
         (1, ty, tz, 1, 1) for ty in (1, 3, 4, 5, 7, 12) for tz in (1, 2, 3, 6)]  # 24, 72, 8 tiles: XCD order
+    # two sweeps per pass (fused = 2 below): tiles of 1 .. 12 rows, z depths 1 .. 6, both tile orders
+    variants += [(2, ty, tz, 1, xcd) for ty, tz, xcd in ((0, 0, 1), (1, 1, 1), (3, 2, 0), (5, 3, 1), (12, 6, 1),
+                                                         (4, 1, 0))]
     for fused, ty, tz, ahead, xcd in variants:
         g = M.Lattice(*shape, seed=2025)
         g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_MULTISPIN)
-        g.set_option(M.OPT_MSC_FUSED, fused)
+        g.set_option(M.OPT_MSC_FUSED, min(fused, 1))
+        g.set_option(M.OPT_MSC_PASS, 2 if fused == 2 else 1)
         g.set_option(M.OPT_DRAW_AHEAD, ahead)
         g.set_option(M.OPT_XCD_MAP, xcd)
         if ty:
@@ -435,6 +439,39 @@ def test_multispin_launch_shapes_give_the_same_bits():
         else:
             assert all(np.array_equal(a, b) for a, b in zip(ref, got)), (fused, ty, tz, ahead, xcd)
         g.close()
+
+
+@pytest.mark.parametrize("shape,ty,tz", [((512, 50, 8, 1, 1), 0, 0), ((256, 12, 6, 1, 2), 5, 3),
+                                         ((128, 6, 2, 2, 1), 0, 0), ((384, 10, 10, 1, 1), 2, 5)])
+def test_multispin_two_sweeps_per_pass_match_oracle(shape, ty, tz):
+    """Two sweeps per pass over the multispin planes (the default) against
+    one sweep per pass and the oracle: calls that start at even and odd k,
+    refreshes (period 5) on the first and on the second sweep of a pass,
+    with the levels drawn ahead; a last odd sweep of a call on the one-sweep
+    kernel; the ragged last y tile of the automatic 40-row tile."""
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.6, 0.4, 80, 5)
+    o = O.Lattice(*shape, 0x2B)
+    runs = {}
+    for temporal in (2, 1):
+        g = M.Lattice(*shape, 0x2B)
+        g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_MULTISPIN)
+        g.set_option(M.OPT_MSC_PASS, temporal)
+        if ty:
+            g.set_option(M.OPT_TILE_Y, ty)
+            g.set_option(M.OPT_TILE_Z, tz)
+        g.set_schedule(gs)
+        states = []
+        for n in (10, 9, 1, 14, 3):  # k = 0, 10, 19, 20, 34 at the starts
+            g.sweep(M.ALGO_MICSA, n)
+            if temporal == 2:
+                o.run(O.ALGO_MICSA, os_, n, 0)
+                same_state(g, o)
+                assert np.array_equal(g.energy_tally(), o.energy())
+            states.append((g.spins(), g.daemons(), g.energy_tally()))
+        runs[temporal] = states
+        g.close()
+    for a, b in zip(runs[2], runs[1]):
+        assert all(np.array_equal(x, y) for x, y in zip(a, b))
 
 
 def test_multispin_tile_orders_give_the_same_bits():
@@ -625,20 +662,55 @@ def test_bitplane_trajectory_matches_oracle(shape):
     same_state(g, o)
     if shape[4] > 1:
         assert np.array_equal(g.overlap(0, 1), o.overlap(0, 1))
+    # the one-launch sweep keeps a per-lane incremental tally (conservation)
+    assert g.kernel_name(M.ALGO_MICSA) == "kb_sweep"
+    assert np.array_equal(g.energy_tally(), o.energy())
+
+
+@pytest.mark.parametrize("shape,tz", [((16, 6, 10, 65, 2), 1), ((16, 6, 10, 65, 2), 2), ((8, 2, 2, 3, 2), 2),
+                                      ((8, 2, 2, 3, 2), 1), ((32, 8, 8, 64, 3), 2), ((64, 32, 4, 70, 1), 1),
+                                      ((64, 32, 4, 70, 1), 2)])
+def test_bitplane_one_launch_tiles_match_oracle(shape, tz):
+    """The one-launch bit-plane sweep with one and two planes per work-group
+    (ring planes recomputed; planes that wrap onto a side of 2; two planes
+    only where a plane has at most 512 words, else one), the largest plane of
+    1024 words, two lane groups with a ragged last group."""
+    g, o = bpair(*shape, seed=2718)
+    g.set_option(M.OPT_TILE_Z, tz)
+    n = 23
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.4, 0.3, n, 5)
+    g.set_schedule(gs)
+    for m in (9, 1, 13):
+        g.sweep(M.ALGO_MICSA, m)
+        o.run(O.ALGO_MICSA, os_, m, 0)
+        same_state(g, o)
+    assert g.kernel_name(M.ALGO_MICSA) == "kb_sweep"
+    E = o.energy()
+    assert np.array_equal(g.energy(), E) and np.array_equal(g.energy_tally(), E)
+    assert np.array_equal(g.daemon_energy(), o.daemon_energy())
 
 
 def test_bitplane_batched_L32_shape():
-    """256 samples x 2 replicas of L = 32 bit-packed in 4 lane groups."""
+    """256 samples x 2 replicas of L = 32 bit-packed in 4 lane groups, the
+    launch the benchmark times (no option): 21 sweeps in one call (refreshes
+    before sweeps 0, 10, 20), then 12 logged; per-lane tally equals the
+    from-scratch energy of every lattice."""
     w = W.BATCHED_L32
-    n = 12
     g, o = bpair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
     gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
     g.set_schedule(gs)
+    g.sweep(M.ALGO_MICSA, 21)
+    o.run(O.ALGO_MICSA, os_, 21, 0)
+    same_state(g, o)
+    assert np.array_equal(g.energy_tally(), o.energy())
+    n = 12
     Eg, Dg = g.sweep_logged(M.ALGO_MICSA, n, 4)
     Eo, Do = o.run(O.ALGO_MICSA, os_, n, 4)
     assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
     assert np.array_equal(g.overlap(0, 1), o.overlap(0, 1))
     same_state(g, o)
+    assert g.kernel_name(M.ALGO_MICSA) == "kb_sweep"
+    assert np.array_equal(g.energy_tally(), o.energy())
 
 
 def test_bitplane_long_calls_match_oracle():
@@ -680,9 +752,16 @@ def test_bitplane_error_paths():
         with pytest.raises(M.MicsaError) as e:
             g.sweep(algo, 1)
         assert e.value.status == M.EINVAL
+    assert np.array_equal(g.energy_tally(), g.energy())
+    # the per-half kernels keep no tally: it is refused until the spins are set again
+    g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_SIMPLE)
+    assert g.kernel_name(M.ALGO_MICSA) == "kb_micsa_half"
+    g.sweep(M.ALGO_MICSA, 2)
     with pytest.raises(M.MicsaError) as e:
         g.energy_tally()
     assert e.value.status == M.ESTATE
+    g.write_spins(g.spins())
+    assert np.array_equal(g.energy_tally(), g.energy())
     with pytest.raises(M.MicsaError) as e:
         g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)
     assert e.value.status == M.EINVAL
@@ -853,3 +932,71 @@ def test_autotuner_gate_and_choice_match_oracle(tmp_path, monkeypatch):
     Eo, Do = o.run(O.ALGO_MICSA, os_, 30, 5)
     assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
     same_state(g, o)
+
+
+# lanes = replicas of one sample, couplings broadcast (serving jobs of 1-64
+# replicas of one instance; lane l of group g is replica 64 g + l)
+REPLICA_SHAPES = [
+    (16, 8, 8, 1, 5),     # one sample, five live lanes
+    (8, 2, 2, 2, 3),      # minimum sides, two samples
+    (32, 8, 6, 3, 70),    # two replica groups per sample
+    (24, 6, 4, 1, 64),    # one full group
+]
+
+
+@pytest.mark.parametrize("shape", REPLICA_SHAPES)
+def test_bitplane_replica_lanes_match_oracle(shape):
+    Lx, Ly, Lz, S, R = shape
+    g = M.Lattice(Lx, Ly, Lz, S, R, 0xBEEF, layout=M.LAYOUT_BITPLANE, lane_mode=M.LANES_REPLICAS)
+    o = O.Lattice(Lx, Ly, Lz, S, R, 0xBEEF)
+    assert np.array_equal(g.couplings(), o.J)
+    same_state(g, o)
+    n = 22
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.5, 0.4, n, 4)
+    g.set_schedule(gs)
+    g.sweep(M.ALGO_MICSA, 9)
+    o.run(O.ALGO_MICSA, os_, 9, 0)
+    same_state(g, o)
+    Eg, Dg = g.sweep_logged(M.ALGO_MICSA, n - 9, 1)
+    Eo, Do = o.run(O.ALGO_MICSA, os_, n - 9, 1)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    same_state(g, o)
+    assert g.kernel_name(M.ALGO_MICSA) == "kb_sweep"
+    assert np.array_equal(g.energy_tally(), o.energy())
+    if R > 1:
+        for a, b in ((0, R - 1), (1, 0), (0, min(R - 1, 65))):
+            if a != b:
+                assert np.array_equal(g.overlap(a, b), o.overlap(a, b))
+        assert np.array_equal(g.c4_sums(), o.c4_sums())
+    # the same lattices in the samples lane mode and in the byte layout agree
+    for kw in (dict(layout=M.LAYOUT_BITPLANE), dict()):
+        h = M.Lattice(Lx, Ly, Lz, S, R, 0xBEEF, **kw)
+        h.set_schedule(gs)
+        h.sweep(M.ALGO_MICSA, n)
+        assert np.array_equal(h.spins(), o.sigma) and np.array_equal(h.daemons(), o.m)
+        h.close()
+    g.close()
+
+
+def test_bitplane_replica_lanes_per_half_and_checkpoint():
+    """The per-half kernels and a checkpoint split in the replicas lane mode."""
+    shape = (16, 6, 4, 2, 7)
+    gs, os_ = scheds(M.SCHED_CONST, 0.9, 0.9, 30, 5)
+    o = O.Lattice(*shape, 99)
+    o.run(O.ALGO_MICSA, os_, 30, 0)
+    g = M.Lattice(*shape, 99, layout=M.LAYOUT_BITPLANE, lane_mode=M.LANES_REPLICAS)
+    g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_SIMPLE)
+    g.set_schedule(gs)
+    g.sweep(M.ALGO_MICSA, 12)
+    image = g.save()
+    g.close()
+    h = M.Lattice(*shape, 99, layout=M.LAYOUT_BITPLANE, lane_mode=M.LANES_REPLICAS)
+    h.load(image)
+    h.sweep(M.ALGO_MICSA, 18)
+    same_state(h, o)
+    assert np.array_equal(h.energy_tally(), o.energy())
+    # an image of one lane mode does not load into the other
+    k = M.Lattice(*shape, 99, layout=M.LAYOUT_BITPLANE)
+    assert M.lib().micsa_load(k._ctx, image, len(image)) == M.EINVAL
+    k.close()
+    h.close()
