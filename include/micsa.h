@@ -175,6 +175,19 @@ int micsa_read_overlap(micsa_ctx* ctx, int32_t a, int32_t b, int64_t* Q);
    [S][3][rmax + 1]; EINVAL unless R >= 2.  Allocates and frees a device
    buffer of at most 256 MiB for the packed overlap fields. */
 int micsa_read_c4(micsa_ctx* ctx, int64_t* G);
+/* micsa_read_c4 without allocation, for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving loops,
+   harnesses that forbid hipMalloc).  Same output as micsa_read_c4.  The
+   packed overlap rows and the count slots live in one static device array
+   of 32 MiB per device, held until the process ends; the call allocates no
+   device memory.  Limit: S*3*(rmax+1)*520 bytes (rounded up to 256 twice)
+   plus one replica pair's rows, 8*Ly*Lz*floor((Lx/2 + 63)/32) bytes, must
+   fit the 32 MiB (e.g. up to 512^3 with two replicas); ERANGE otherwise.
+   Every call on a device shares that device's array and leaves its
+   contents behind: calls that overlap in time on one device (two host
+   threads, or two streams) race and may return wrong sums.  Synchronous. */
+int micsa_read_c4_static(micsa_ctx* ctx, int64_t* G);
+
 /* Coherence lengths per sample (eq. xi-def): I_n = sum_{r=0}^{rmin} r^n C4(r),
    rmin = min(Lx, Ly, Lz)/2 (the integral read as the sum over lattice
    distances up to half the side), xi12 = I2/I1, xi23 = I3/I2 (NaN if I1 or

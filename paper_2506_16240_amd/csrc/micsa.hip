@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -49,6 +50,7 @@ struct Schedule {
 struct micsa_ctx {
     micsa_params p{};
     hipStream_t stream = nullptr;
+    int device = 0;  // the device current at creation, which holds the state
     Geom g{};
     int L = 0;  // lattices = S * R
     int gamma = 1;  // daemons (walkers) per site; a timestep is gamma sweeps
@@ -1385,6 +1387,11 @@ int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
 
     micsa_ctx* c = new (std::nothrow) micsa_ctx();
     if (!c) return MICSA_ENOMEM;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return MICSA_EHIP;
+    }
     c->p = *p;
     c->p.gamma = gamma;
     c->gamma = gamma;
@@ -1722,6 +1729,96 @@ int micsa_read_c4(micsa_ctx* ctx, int64_t* G)
             for (int r = 0; r <= cg.rmax; ++r) {
                 const int64_t e = ((int64_t)s * 3 + mu) * (cg.rmax + 1) + r;
                 G[e] = 2 * r <= side[mu] ? N * cg.npair - 2 * D[(size_t)e] : 0;
+            }
+    return MICSA_OK;
+}
+
+// ------------------------------------------- C4 into a static scratch array
+// The overlap rows and the count slots of micsa_read_c4 live in `scratch`, a
+// file-scope device array (one copy per device, held until the process
+// ends), so this call allocates nothing.  Host code never passes the
+// array's name to a kernel or a copy: it uses the device address that
+// hipGetSymbolAddress returns for the device the context lives on.
+constexpr size_t kC4ScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) uint8_t scratch[kC4ScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the context's device (looked up once per
+// device, with that device current).
+int scratch_address(micsa_ctx* c, uint8_t** out)
+{
+    if (c->device < 0 || c->device >= kMaxDevices) return fail(c, MICSA_EINVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[c->device]) {
+        int prev = 0;
+        HIP_TRY(c, hipGetDevice(&prev));
+        if (prev != c->device) HIP_TRY(c, hipSetDevice(c->device));
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (prev != c->device) (void)hipSetDevice(prev);
+        if (e != hipSuccess || !ptr)
+            return fail(c, MICSA_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_addr[c->device] = static_cast<uint8_t*>(ptr);
+    }
+    *out = g_scratch_addr[c->device];
+    return MICSA_OK;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+}  // namespace
+
+int micsa_read_c4_static(micsa_ctx* ctx, int64_t* G)
+{
+    if (!ctx || !G) return MICSA_EINVAL;
+    if (ctx->p.n_replicas < 2) return fail(ctx, MICSA_EINVAL, "C4 needs at least two replicas");
+    const C4Geom cg = c4_geom(ctx);
+    const int64_t ent = (int64_t)ctx->p.n_samples * 3 * (cg.rmax + 1);
+    const int64_t per_pair = (int64_t)2 * ctx->g.rows * cg.E;  // 32-bit words of one pair's rows
+    const int64_t total = (int64_t)ctx->p.n_samples * cg.npair;
+    const size_t slots_bytes = align256((size_t)ent * kSlots * 8), sums_bytes = align256((size_t)ent * 8);
+    const size_t head = slots_bytes + sums_bytes;
+    if (head + (size_t)per_pair * 4 > kC4ScratchBytes)
+        return fail(ctx, MICSA_ERANGE, "lattice too large for the 32 MiB static scratch (use micsa_read_c4)");
+    uint8_t* base = nullptr;
+    int st = scratch_address(ctx, &base);
+    if (st) return st;
+    auto* dD = reinterpret_cast<unsigned long long*>(base);
+    auto* sums = reinterpret_cast<long long*>(base + slots_bytes);
+    auto* Q = reinterpret_cast<uint32_t*>(base + head);
+    const int64_t chunk =
+        std::max<int64_t>(1, std::min<int64_t>({total, (int64_t)((kC4ScratchBytes - head) / 4) / per_pair, 65535}));
+    // the array keeps the previous call's contents: clear the count slots
+    k_fill_i64<<<grid_for(ent * kSlots, 1), kBlock, 0, ctx->stream>>>(dD, ent * kSlots, 0ull);
+    if ((st = check_launch(ctx, "k_fill_i64"))) return st;
+    const int64_t valid = (int64_t)2 * ctx->g.rows * cg.Wv;
+    for (int64_t sp0 = 0; sp0 < total; sp0 += chunk) {
+        const unsigned n = (unsigned)std::min(chunk, total - sp0);
+        if (ctx->bit)
+            k_pack_overlap<true><<<dim3((unsigned)((per_pair + 255) / 256), n), 256, 0, ctx->stream>>>(
+                geomb(ctx), cg, (int)sp0, nullptr, ctx->bspin, Q);
+        else
+            k_pack_overlap<false><<<dim3((unsigned)((per_pair + 255) / 256), n), 256, 0, ctx->stream>>>(
+                geomb(ctx), cg, (int)sp0, ctx->spin, nullptr, Q);
+        if ((st = check_launch(ctx, "k_pack_overlap"))) return st;
+        k_c4_count<<<dim3((unsigned)((valid + 255) / 256), (unsigned)(3 * (cg.rmax + 1)), n), 256, 0,
+                     ctx->stream>>>(ctx->g, cg, (int)sp0, Q, dD);
+        if ((st = check_launch(ctx, "k_c4_count"))) return st;
+    }
+    k_sum_slots<<<grid_for(ent, 1), kBlock, 0, ctx->stream>>>(dD, ent, sums);
+    if ((st = check_launch(ctx, "k_sum_slots"))) return st;
+    HIP_TRY(ctx, hipMemcpyAsync(G, sums, (size_t)ent * 8, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    const int64_t N = n_sites(ctx);
+    const int side[3] = {ctx->p.Lx, ctx->p.Ly, ctx->p.Lz};
+    for (int s = 0; s < ctx->p.n_samples; ++s)
+        for (int mu = 0; mu < 3; ++mu)
+            for (int r = 0; r <= cg.rmax; ++r) {
+                const int64_t e = ((int64_t)s * 3 + mu) * (cg.rmax + 1) + r;
+                G[e] = 2 * r <= side[mu] ? N * cg.npair - 2 * G[e] : 0;
             }
     return MICSA_OK;
 }

@@ -115,4 +115,15 @@ __global__ void __launch_bounds__(256) k_c4_count(Geom g, C4Geom cg, int sp0, co
     block_add(D + ((int64_t)(s * 3 + mu) * (cg.rmax + 1) + r) * kSlots, cnt);
 }
 
+// out[e] = sum of the kSlots accumulator slots of entity e (thread per entity).
+__global__ void __launch_bounds__(256) k_sum_slots(const unsigned long long* __restrict__ slots, int64_t n,
+                                                   long long* __restrict__ out)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    unsigned long long t = 0;
+    for (int k = 0; k < kSlots; ++k) t += slots[e * kSlots + k];
+    out[e] = (long long)t;
+}
+
 }  // namespace micsa

@@ -88,6 +88,7 @@ _SIGNATURES = [
     ("micsa_get_heatbath_thresholds", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     ("micsa_get_metropolis_thresholds", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     ("micsa_read_c4", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_read_c4_static", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("micsa_read_xi", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     ("micsa_write_spins", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("micsa_write_demons", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -300,6 +301,13 @@ class Lattice:
         rmax = max(self.Lx, self.Ly, self.Lz) // 2
         out = np.zeros((self.S, 3, rmax + 1), np.int64)
         self._check(lib().micsa_read_c4(self._ctx, _ptr(out)), "read_c4")
+        return out
+
+    def c4_sums_static(self) -> np.ndarray:
+        """As c4_sums, through micsa_read_c4_static (no device allocation)."""
+        rmax = max(self.Lx, self.Ly, self.Lz) // 2
+        out = np.zeros((self.S, 3, rmax + 1), np.int64)
+        self._check(lib().micsa_read_c4_static(self._ctx, _ptr(out)), "read_c4_static")
         return out
 
     def xi(self) -> np.ndarray:
