@@ -370,8 +370,11 @@ def main() -> int:
     ap.add_argument("--algo", choices=("micsa", "walkers"), default="micsa",
                     help="daemons (default) or walkers wandering every timestep (Sec. 2.6)")
     ap.add_argument("--gamma", type=int, default=1, help="daemons (walkers) per site (Sec. 2.8)")
-    ap.add_argument("--kernel", choices=("auto", "fused", "multispin"), default="auto",
-                    help="MicSA sweep kernel: library choice, the fused byte sweep, or multispin bit planes")
+    ap.add_argument("--kernel", choices=("auto", "fused", "multispin", "slab", "simple"), default="auto",
+                    help="MicSA sweep kernel: library choice, the fused byte sweep, multispin bit planes, the "
+                         "one-launch slab sweep or the per-half kernels")
+    ap.add_argument("--hb-kernel", choices=("auto", "fused", "simple"), default="auto",
+                    help="kernel of the heat-bath and Metropolis legs (library choice by default)")
     ap.add_argument("--refresh", choices=("period", "log2"), default="period",
                     help="refresh every period of the workload, or before every sweep t with t + 1 a power "
                          "of two (the procedure of Sec. 2.8.1: refresh, 2^s steps, refresh, ...)")
@@ -442,7 +445,9 @@ def main() -> int:
     if args.gamma != 1 and (layout or tile):
         tile = None  # gamma > 1 runs the per-half kernels
     log(f"{algo_name}: {w.name}, {sweeps} sweeps, gamma {args.gamma}, refresh {args.refresh}")
-    kern = {"auto": 0, "fused": M.KERNEL_FUSED, "multispin": M.KERNEL_MULTISPIN}[args.kernel]
+    kern = {"auto": 0, "fused": M.KERNEL_FUSED, "multispin": M.KERNEL_MULTISPIN, "slab": M.KERNEL_SLAB,
+            "simple": M.KERNEL_SIMPLE}[args.kernel]
+    hb_kern = {"auto": 0, "fused": M.KERNEL_FUSED, "simple": M.KERNEL_SIMPLE}[args.hb_kernel]
     mi = run_gpu(w, algo_name, steps, args.warmup, stream, tile, layout, gamma=args.gamma, period=period,
                  c4=args.c4, kernel=kern)
     log(f"{algo_name}: {mi['ms']:.1f} ms, tally check {mi['tally_check']}")
@@ -453,12 +458,12 @@ def main() -> int:
     hb = None
     if not args.no_heatbath:
         log(f"heatbath: {w.name}, {sweeps} sweeps")
-        hb = run_gpu(w, "heatbath", steps, args.warmup, stream)
+        hb = run_gpu(w, "heatbath", steps, args.warmup, stream, kernel=hb_kern)
         log(f"heatbath: {hb['ms']:.1f} ms")
     mp = None
     if not args.no_metropolis:
         log(f"metropolis: {w.name}, {sweeps} sweeps")
-        mp = run_gpu(w, "metropolis", steps, args.warmup, stream)
+        mp = run_gpu(w, "metropolis", steps, args.warmup, stream, kernel=hb_kern)
         log(f"metropolis: {mp['ms']:.1f} ms")
     wk = None
     if not args.no_walkers and algo_name == "micsa" and args.gamma == 1 and not layout:

@@ -297,13 +297,16 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
    MICSA_OPT_PREFETCH: steps of global loads in flight in the fused MicSA
      sweep, 1 (default) or 2 (used for work-groups of at most 640 lanes,
      i.e. (tile_y + 4) * Lx / 32 <= 640; larger tiles run with 1).
-   MICSA_OPT_DRAW_AHEAD: one-launch multispin sweep only.  1 (default) draws
+   MICSA_OPT_DRAW_AHEAD: one-launch multispin and bit-plane sweeps.  1 (default
+     for the multispin sweep; the bit-plane layout defaults to 0) draws
      the daemon levels of each refresh (Sec. 2.3; they depend on the refresh
      index and temperature, not on the state) in a kernel of their own on a
      second stream of the library, while the sweeps before the refresh run;
-     the refresh sweep then reads them.  0 draws them inside the refresh
-     sweep.  Every draw is joined into the context's stream before the call
-     that launched it returns.  Results are identical.
+     the refresh sweep then reads them.  0 draws them in place: inside the
+     refresh sweep (multispin), or in a draw kernel just before it on the
+     library's stream (bit-plane).  Every draw is joined into the context's
+     stream before the call that launched it returns.  Results are
+     identical.
    Errors: EINVAL for an unknown option or a value the lattice cannot use. */
 enum micsa_option {
     MICSA_OPT_SWEEP_KERNEL = 1,
@@ -323,7 +326,10 @@ enum micsa_kernel_choice {
     MICSA_KERNEL_SIMPLE = 1,  /* one launch per half sweep (bit-plane layout: instead of its one-launch sweep) */
     MICSA_KERNEL_FUSED = 2,   /* one launch per sweep, refresh fused in (Lx % 32 == 0) */
     MICSA_KERNEL_RESIDENT = 3, /* one work-group per lattice keeps it in LDS for many sweeps (<= 102400 sites) */
-    MICSA_KERNEL_MULTISPIN = 4 /* MicSA daemon sweeps on bit planes, 64 sites of a row per word (Lx % 128 == 0) */
+    MICSA_KERNEL_MULTISPIN = 4, /* MicSA daemon sweeps on bit planes, 64 sites of a row per word (Lx % 128 == 0) */
+    MICSA_KERNEL_SLAB = 5       /* MicSA, one launch per sweep, a z plane per work-group with its neighbour
+                                   planes recomputed (byte layout, gamma = 1, Ly * Lx / 8 <= 1024); AUTO takes it
+                                   for lattices too large for the resident sweep with Lx < 128 (e.g. L = 64) */
 };
 int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value);
 
@@ -335,12 +341,18 @@ int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value);
    admitted in arrival order while their device footprint fits the pool's
    HBM budget (and fewer than max_running jobs run); an admitted job keeps
    its lattices and daemons resident until it is released.  micsa_pool_step
-   advances every running job by the same number of sweeps ("batching by
-   sweep"): the jobs whose lattices fit one work-group's LDS advance
-   together in one batched launch, each lattice at its own sweep index and
-   temperature; larger jobs run their own kernels on the same stream.  A job
-   that reaches the end of its schedule is DONE; its state stays readable
-   through micsa_pool_job_context until micsa_pool_release frees it.
+   enqueues the next chunk of sweeps of every running job ("batching by
+   sweep") and returns without waiting for the device: the jobs whose
+   lattices fit one work-group's LDS advance together in one batched launch
+   on the pool's stream, each lattice at its own sweep index and
+   temperature; every larger job runs its own kernels on a stream of its own
+   (default priority), so jobs overlap on the device.  At most two chunks
+   of a job (and two batched launches) are in flight: a call skips a job
+   whose two previous chunks have not finished, so calling micsa_pool_step
+   in a loop keeps the device busy while new jobs are submitted and
+   admitted.  A job whose every sweep has been enqueued and has finished on
+   the device is DONE; its state stays readable through
+   micsa_pool_job_context until micsa_pool_release frees it.
    Results never depend on the other jobs in the pool: every random number
    is keyed by the job's own seed, sample, replica, site and time.
    ------------------------------------------------------------------------ */
@@ -361,12 +373,16 @@ int micsa_pool_destroy(micsa_pool* pool); /* frees every job; NULL accepted */
    budget (it could never be admitted). */
 int micsa_pool_submit(micsa_pool* pool, const micsa_params* p, const micsa_schedule* s, int64_t* job);
 
-/* Admit what fits, advance every running job by up to `sweeps` sweeps,
-   retire the finished ones (synchronous).  Outputs (may be NULL): number
-   of running and queued jobs after the step. */
+/* Retire the jobs whose work has finished, admit what fits, enqueue up to
+   `sweeps` more sweeps of every running job with a free chunk slot
+   (asynchronous).  Outputs (may be NULL): number of running and queued jobs
+   after the step. */
 int micsa_pool_step(micsa_pool* pool, int64_t sweeps, int32_t* running, int32_t* queued);
 
-/* State of a job and its sweep counter. */
+/* Wait until every enqueued chunk of every job has finished. */
+int micsa_pool_sync(micsa_pool* pool);
+
+/* State of a job and its sweep counter (sweeps enqueued so far). */
 int micsa_pool_job_state(micsa_pool* pool, int64_t job, int32_t* state, int64_t* k);
 
 /* The context of a RUNNING or DONE job (owned by the pool; valid until

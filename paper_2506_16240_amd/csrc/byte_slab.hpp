@@ -1,0 +1,172 @@
+// One launch per MicSA sweep for mid-size byte-layout lattices (too large
+// for one work-group's LDS, too few sites to fill the GPU with the z-marching
+// fused sweep, e.g. L = 64): a work-group owns one z plane of one lattice,
+// with one thread per 4-site word of a plane (Ly * Lx / 8 <= 1024 words).
+//
+// Both halves of the sweep (Sec. 2.8) run in the work-group:
+//   1. every load is issued up front: the old odd words of planes z - 2 ..
+//      z + 2, the even words (spins with their six coupling bits) of planes
+//      z - 1 .. z + 1 with their daemon words, the odd daemon word of plane z;
+//      at a refresh point (Sec. 2.7) the daemons of those even planes and of
+//      the odd plane are drawn here instead, with the counters of k_refresh;
+//   2. the old odd planes go to LDS; the even half runs on planes z - 1, z,
+//      z + 1 (the outer two recomputed from the same old state as their
+//      owners, so no work-group waits for another) and leaves the new even
+//      words in LDS;
+//   3. the odd half runs on plane z with its neighbours' new even words; an
+//      odd site's couplings are read from those words (the bond bits ride in
+//      the even spin bytes, geometry.hpp).
+// State is read from the current arrays and written to the alternate ones.
+// The Creutz move is micsa_word (4 sites per 32-bit word, byte-wise).
+#pragma once
+#include "byte_kernels.hpp"
+
+namespace micsa {
+
+constexpr int kSlabLanes = 1024;
+
+template <bool REFRESH>
+__global__ __launch_bounds__(kSlabLanes) void k_micsa_slab(Geom g, const uint8_t* __restrict__ spin_in,
+                                                          const uint8_t* __restrict__ dem_in,
+                                                          uint8_t* __restrict__ spin_out,
+                                                          uint8_t* __restrict__ dem_out,
+                                                          unsigned long long* __restrict__ tally, uint32_t rho,
+                                                          DaemonThresholds th)
+{
+    extern __shared__ uint32_t lds_slab[];
+    const int P = g.Ly * g.Wr;  // 4-site words of one parity in a plane
+    uint32_t* LO = lds_slab;          // old odd words, planes z - 2 .. z + 2
+    uint32_t* LE = lds_slab + 5 * P;  // new even words, planes z - 1 .. z + 1
+    // One-dimensional grid over (lattice, plane); XCD x (block b on XCD b % 8)
+    // takes the contiguous planes [x T/8, (x + 1) T/8) when T divides by 8.
+    const int nt = gridDim.x;
+    int t = blockIdx.x;
+    if ((nt & 7) == 0) t = (t & 7) * (nt >> 3) + (t >> 3);
+    const int l = t / g.Lz, z0 = t - l * g.Lz;
+    const int s = l / g.R, r = l - s * g.R;
+    const int pos = threadIdx.x;
+    const bool live = pos < P;
+    const int pq = live ? pos : 0;  // idle lanes read word 0 (in bounds) and store nothing
+    const int y = pq / g.Wr, c = pq - y * g.Wr;
+    const int yp = y + 1 == g.Ly ? 0 : y + 1, ym = y == 0 ? g.Ly - 1 : y - 1;
+    const int cp = c + 1 == g.Wr ? 0 : c + 1, cm = c == 0 ? g.Wr - 1 : c - 1;
+    auto wrapz = [&](int z) { return z < 0 ? z + g.Lz : (z >= g.Lz ? z - g.Lz : z); };
+    const int64_t Nh = g.Nh;
+    const uint32_t* ev_in = reinterpret_cast<const uint32_t*>(spin_in + (int64_t)l * 2 * Nh);
+    const uint32_t* od_in = reinterpret_cast<const uint32_t*>(spin_in + ((int64_t)l * 2 + 1) * Nh);
+    const uint32_t* de_in = reinterpret_cast<const uint32_t*>(dem_in + (int64_t)l * 2 * Nh);
+    const uint32_t* do_in = reinterpret_cast<const uint32_t*>(dem_in + ((int64_t)l * 2 + 1) * Nh);
+    uint32_t* ev_out = reinterpret_cast<uint32_t*>(spin_out + (int64_t)l * 2 * Nh);
+    uint32_t* od_out = reinterpret_cast<uint32_t*>(spin_out + ((int64_t)l * 2 + 1) * Nh);
+    uint32_t* de_out = reinterpret_cast<uint32_t*>(dem_out + (int64_t)l * 2 * Nh);
+    uint32_t* do_out = reinterpret_cast<uint32_t*>(dem_out + ((int64_t)l * 2 + 1) * Nh);
+    const uint32_t m1 = 0x01010101u;
+
+    // ---- loads (and draws)
+    uint32_t Od[5], Ev[3], Me[3], Mo = 0;
+#pragma unroll
+    for (int e = 0; e < 5; ++e) Od[e] = od_in[(int64_t)wrapz(z0 - 2 + e) * P + pq];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int64_t w = (int64_t)wrapz(z0 - 1 + e) * P + pq;
+        Ev[e] = ev_in[w];
+        if (!REFRESH) Me[e] = de_in[w];
+    }
+    if (!REFRESH) Mo = do_in[(int64_t)z0 * P + pq];
+    if (REFRESH) {
+        // word w of either parity holds natural sites 8w .. 8w + 7 (the two
+        // Philox calls of k_refresh)
+        const uint32_t sw = stream_word(kStreamDaemon, (uint32_t)s);
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const int64_t i0 = 8 * ((int64_t)wrapz(z0 - 1 + e) * P + pq);
+            const u32x4 a = philox10((uint32_t)(i0 >> 2), rho, (uint32_t)r, sw, g.key0, g.key1);
+            const u32x4 b = philox10((uint32_t)(i0 >> 2) + 1u, rho, (uint32_t)r, sw, g.key0, g.key1);
+            uint32_t we, wo;
+            split8(g, i0, a, b, [&](uint32_t u) { return daemon_level(u, th); }, we, wo);
+            Me[e] = we;
+            if (e == 1) Mo = wo;
+        }
+    }
+
+    // ---- old odd planes into LDS
+    if (live) {
+#pragma unroll
+        for (int e = 0; e < 5; ++e) LO[e * P + pos] = Od[e];
+    }
+    __syncthreads();
+
+    int dE = 0;
+    // ---- even half on planes z - 1, z, z + 1
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int z = wrapz(z0 - 1 + e);
+        const int q = (y + z) & 1;
+        const int dir = q ? 1 : -1;  // the shifted x neighbour of an even site
+        const uint32_t* Oz = LO + (e + 1) * P;
+        const uint32_t W0 = Ev[e];
+        Nbhd n;
+        const uint32_t w0 = Oz[y * g.Wr + c];
+        const uint32_t w1 = shift_word(w0, Oz[y * g.Wr + (dir > 0 ? cp : cm)], dir);
+        const uint32_t w[6] = {w0, w1, Oz[yp * g.Wr + c], Oz[ym * g.Wr + c], (Oz + P)[pq], (Oz - P)[pq]};
+#pragma unroll
+        for (int d = 0; d < 6; ++d) n.nb[d] = w[d] & m1;
+        const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
+        const uint32_t jw = W0 >> 1;
+        n.jb[0] = jbits(jw, dA);
+        n.jb[1] = jbits(jw, dB);
+        n.jb[2] = jbits(jw, kPy);
+        n.jb[3] = jbits(jw, kMy);
+        n.jb[4] = jbits(jw, kPz);
+        n.jb[5] = jbits(jw, kMz);
+        const uint32_t S0 = W0 & m1;
+        uint32_t S = S0, M = Me[e];
+        int d_e = 0;
+        micsa_word(S, M, n, d_e);
+        const uint32_t Wn = W0 ^ S ^ S0;  // the bond bits stay
+        if (live) {
+            LE[e * P + pos] = Wn;
+            if (e == 1) {
+                ev_out[(int64_t)z * P + pos] = Wn;
+                de_out[(int64_t)z * P + pos] = M;
+                dE += d_e;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- odd half on plane z, with the new even words
+    {
+        const int z = z0;
+        const int q = (y + z) & 1;
+        const int dir = q ? -1 : 1;  // the shifted x neighbour of an odd site
+        const uint32_t* Ez = LE + P;
+        Nbhd n;
+        const uint32_t w0 = Ez[y * g.Wr + c];
+        const uint32_t w1 = shift_word(w0, Ez[y * g.Wr + (dir > 0 ? cp : cm)], dir);
+        const uint32_t w[6] = {w0, w1, Ez[yp * g.Wr + c], Ez[ym * g.Wr + c], (Ez + P)[pq], (Ez - P)[pq]};
+#pragma unroll
+        for (int d = 0; d < 6; ++d) n.nb[d] = w[d] & m1;
+        // an odd site reads each bond from its even neighbour's opposite slot
+        const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
+        n.jb[0] = jbits(w[0] >> 1, dA);
+        n.jb[1] = jbits(w[1] >> 1, dB);
+        n.jb[2] = jbits(w[2] >> 1, kMy);
+        n.jb[3] = jbits(w[3] >> 1, kPy);
+        n.jb[4] = jbits(w[4] >> 1, kMz);
+        n.jb[5] = jbits(w[5] >> 1, kPz);
+        const uint32_t W0 = Od[2];
+        const uint32_t S0 = W0 & m1;
+        uint32_t S = S0, M = Mo;
+        int d_o = 0;
+        micsa_word(S, M, n, d_o);
+        if (live) {
+            od_out[(int64_t)z * P + pos] = W0 ^ S ^ S0;
+            do_out[(int64_t)z * P + pos] = M;
+            dE += d_o;
+        }
+    }
+    block_add(tally + (int64_t)l * kSlots, dE);
+}
+
+}  // namespace micsa

@@ -18,6 +18,7 @@
 
 #include "bitplane_kernels.hpp"
 #include "bitplane_sweep.hpp"
+#include "byte_slab.hpp"
 #include "fused_kernels.hpp"
 #include "fused2_kernels.hpp"
 #include "msc_kernels.hpp"
@@ -509,9 +510,51 @@ bool use_msc(const micsa_ctx* c, int64_t n = kMscMinSweeps, int32_t algo = MICSA
     return c->kernel_opt == MICSA_KERNEL_AUTO && !use_resident(c) && n >= kMscMinSweeps;
 }
 
+// One launch per sweep with a z plane per work-group (byte_slab.hpp): a
+// plane's 4-site words fit one work-group.
+bool slab_eligible(const micsa_ctx* c)
+{
+    return !c->bit && c->gamma == 1 && (int64_t)c->p.Ly * (c->p.Lx / 8) <= kSlabLanes;
+}
+
+bool use_fused(const micsa_ctx* c);
+
+// AUTO takes it for lattices the resident kernel does not hold that are too
+// narrow for the fused sweep (Lx < 128).
+bool use_slab(const micsa_ctx* c)
+{
+    if (!slab_eligible(c)) return false;
+    if (c->kernel_opt == MICSA_KERNEL_SLAB) return true;
+    return c->kernel_opt == MICSA_KERNEL_AUTO && !use_resident(c) && !use_fused(c);
+}
+
+int launch_slab_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
+{
+    const int P = c->p.Ly * (c->p.Lx / 8);
+    const dim3 grid((unsigned)(c->L * c->p.Lz));
+    const unsigned block = (unsigned)((P + 63) / 64 * 64);
+    const size_t lds = (size_t)8 * P * 4;
+    {
+        TimedLaunch t(c, kTimeSweep);
+        if (refresh)
+            k_micsa_slab<true><<<grid, block, lds, c->stream>>>(c->g, c->spin, c->dem, c->spin_alt, c->dem_alt,
+                                                                c->tally, (uint32_t)rho, daemon_thresholds(T));
+        else
+            k_micsa_slab<false><<<grid, block, lds, c->stream>>>(c->g, c->spin, c->dem, c->spin_alt, c->dem_alt,
+                                                                 c->tally, 0u, DaemonThresholds{0, 0, 0});
+    }
+    const int st = check_launch(c, "k_micsa_slab");
+    if (st) return st;
+    std::swap(c->spin, c->spin_alt);
+    std::swap(c->dem, c->dem_alt);
+    return MICSA_OK;
+}
+
 bool use_fused(const micsa_ctx* c)
 {
-    if (c->bit || c->kernel_opt == MICSA_KERNEL_SIMPLE || c->kernel_opt == MICSA_KERNEL_RESIDENT) return false;
+    if (c->bit || c->kernel_opt == MICSA_KERNEL_SIMPLE || c->kernel_opt == MICSA_KERNEL_RESIDENT ||
+        c->kernel_opt == MICSA_KERNEL_SLAB)
+        return false;
     if (c->kernel_opt == MICSA_KERNEL_FUSED) return true;
     return fused_eligible(c) && c->p.Lx >= 128;
 }
@@ -1292,6 +1335,8 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
                 c->pend_wander = (int32_t)(t & 1);  // this timestep's wandering, owed to the next sweep
             } else if (use_fused(c)) {
                 if ((st = launch_fused_sweep(c, refresh, rho, T))) return st;
+            } else if (algo == MICSA_ALGO_MICSA && use_slab(c)) {
+                if ((st = launch_slab_sweep(c, refresh, rho, T))) return st;
             } else {
                 if (refresh && (st = launch_refresh(c, rho, T))) return st;
                 if ((st = launch_micsa_sweep(c, fam))) return st;
@@ -1398,6 +1443,9 @@ int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
     c->stream = (hipStream_t)hip_stream;
     c->L = p->n_samples * p->n_replicas;
     c->bit = p->layout == MICSA_LAYOUT_BITPLANE;
+    // the bit-plane sweep is latency-bound: a draw beside it slows it more
+    // than the draw costs in place (measured on MI355X), so it draws in place
+    if (c->bit) c->draw_ahead = 0;
     c->G = p->lane_mode == MICSA_LANES_REPLICAS ? (p->n_replicas + 63) / 64 : (p->n_samples + 63) / 64;
     Geom& g = c->g;
     g.Lx = p->Lx;
@@ -2310,6 +2358,7 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
         return ctx && use_fused(ctx) ? "k_heatbath_sweep_fused<1>" : "k_heatbath_half<1>";
     if (ctx && use_fused(ctx))
         return ctx->temporal == 2 && sweep2_eligible(ctx) ? "k_micsa_sweep2_fused" : "k_micsa_sweep_fused";
+    if (ctx && use_slab(ctx)) return "k_micsa_slab";
     return "k_micsa_half";
 }
 
@@ -2319,8 +2368,10 @@ int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value)
     switch (option) {
     case MICSA_OPT_SWEEP_KERNEL:
         if (value != MICSA_KERNEL_AUTO && value != MICSA_KERNEL_SIMPLE && value != MICSA_KERNEL_FUSED &&
-            value != MICSA_KERNEL_RESIDENT && value != MICSA_KERNEL_MULTISPIN)
+            value != MICSA_KERNEL_RESIDENT && value != MICSA_KERNEL_MULTISPIN && value != MICSA_KERNEL_SLAB)
             return fail(ctx, MICSA_EINVAL, "unknown sweep kernel");
+        if (value == MICSA_KERNEL_SLAB && !slab_eligible(ctx))
+            return fail(ctx, MICSA_EINVAL, "the slab sweep needs the byte layout, gamma = 1 and Ly * Lx / 8 <= 1024");
         if (value == MICSA_KERNEL_MULTISPIN && !msc_eligible(ctx))
             return fail(ctx, MICSA_EINVAL, "the multispin sweep needs the byte layout, gamma = 1 and Lx % 128 == 0");
         if (value == MICSA_KERNEL_RESIDENT && !resident_eligible(ctx))
@@ -2383,6 +2434,14 @@ struct PoolJob {
     int32_t state = MICSA_JOB_QUEUED;
     size_t bytes = 0;
     micsa_ctx* ctx = nullptr;
+    // Jobs the resident kernel holds run in the pool's batched launch on the
+    // pool stream; every other job gets a stream of its own (default
+    // priority), so large jobs overlap with each other and with the batch.
+    bool batched = false;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};  // end of the last two chunks of sweeps
+    int64_t chunks = 0;                     // chunks enqueued so far
+    int64_t last_batch = -1;                // batched jobs: the batch that holds their latest chunk
 };
 
 size_t footprint(const micsa_params* p)
@@ -2416,9 +2475,42 @@ struct micsa_pool {
     hipStream_t stream = nullptr;
     int64_t next_id = 1;
     std::vector<PoolJob> jobs;  // every job not yet released, in arrival order
-    ResidentItem* d_items = nullptr;
-    size_t d_items_cap = 0;
+    // batched launches: two launches in flight at most, each with its item
+    // table (the host may refill one while the other is read)
+    ResidentItem* d_items[2] = {nullptr, nullptr};
+    size_t d_items_cap[2] = {0, 0};
+    std::vector<ResidentItem> h_items[2];  // host copy of each table, kept until its launch has finished
+    hipEvent_t bev[2] = {nullptr, nullptr};
+    int64_t batches = 0;
 };
+
+namespace {
+
+// The chunk slot `n` of a job (or of the batch) may be refilled once the
+// chunk two before it has finished.
+bool slot_free(hipEvent_t e)
+{
+    if (!e) return true;
+    const hipError_t q = hipEventQuery(e);
+    if (q == hipErrorNotReady) return false;
+    (void)hipGetLastError();
+    return true;
+}
+
+void free_job_stream(PoolJob& j)
+{
+    for (auto& e : j.ev)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+    if (j.stream) {
+        (void)hipStreamDestroy(j.stream);
+        j.stream = nullptr;
+    }
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -2446,10 +2538,25 @@ int micsa_pool_create(size_t hbm_budget, int32_t max_running, void* hip_stream, 
 int micsa_pool_destroy(micsa_pool* pool)
 {
     if (!pool) return MICSA_OK;
-    for (auto& j : pool->jobs)
-        if (j.ctx) micsa_destroy(j.ctx);
-    if (pool->d_items) (void)hipFree(pool->d_items);
+    (void)hipStreamSynchronize(pool->stream);
+    for (auto& j : pool->jobs) {
+        if (j.ctx) micsa_destroy(j.ctx);  // synchronises the job's stream
+        free_job_stream(j);
+    }
+    for (int b = 0; b < 2; ++b) {
+        if (pool->d_items[b]) (void)hipFree(pool->d_items[b]);
+        if (pool->bev[b]) (void)hipEventDestroy(pool->bev[b]);
+    }
     delete pool;
+    return MICSA_OK;
+}
+
+int micsa_pool_sync(micsa_pool* pool)
+{
+    if (!pool) return MICSA_EINVAL;
+    if (hipStreamSynchronize(pool->stream) != hipSuccess) return MICSA_EHIP;
+    for (auto& j : pool->jobs)
+        if (j.stream && hipStreamSynchronize(j.stream) != hipSuccess) return MICSA_EHIP;
     return MICSA_OK;
 }
 
@@ -2494,15 +2601,48 @@ static PoolJob* find_job(micsa_pool* pool, int64_t id)
 int micsa_pool_step(micsa_pool* pool, int64_t sweeps, int32_t* running, int32_t* queued)
 {
     if (!pool || sweeps < 0) return MICSA_EINVAL;
-    // 1. admit queued jobs in arrival order while they fit
+    // 1. retire jobs whose last chunk has finished on the device (a batch's
+    // event is recorded again only after that batch has finished)
+    for (auto& j : pool->jobs) {
+        if (j.state != MICSA_JOB_RUNNING || j.ctx->k < j.ctx->sched.n_sweeps) continue;
+        const bool fin = j.batched ? (j.last_batch < 0 || pool->batches > j.last_batch + 2 ||
+                                      slot_free(pool->bev[j.last_batch & 1]))
+                                   : (j.chunks == 0 || slot_free(j.ev[(j.chunks - 1) & 1]));
+        if (fin) j.state = MICSA_JOB_DONE;
+    }
+    // 2. admit queued jobs in arrival order while they fit
     int32_t nrun = 0;
     for (auto& j : pool->jobs) nrun += j.state == MICSA_JOB_RUNNING;
     for (auto& j : pool->jobs) {
         if (j.state != MICSA_JOB_QUEUED) continue;
         if (nrun >= pool->max_running || pool->used + j.bytes > pool->budget) break;
-        int st = micsa_create(&j.p, pool->stream, &j.ctx);
-        if (st == MICSA_ENOMEM) break;  // the device is fuller than the budget says: retry next step
-        if (st) return st;
+        micsa_params pr = j.p;
+        micsa_ctx* probe = nullptr;
+        // the resident kernel's jobs share the pool stream; the others get their own
+        const bool batched = pr.layout == MICSA_LAYOUT_BYTE && (pr.gamma == 0 || pr.gamma == 1) &&
+                             (size_t)((int64_t)pr.Lx * pr.Ly * pr.Lz / 2) * 3 <= kResidentLdsMax;
+        hipStream_t st_job = pool->stream;
+        if (!batched) {
+            if (hipStreamCreateWithFlags(&j.stream, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&j.ev[0], hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&j.ev[1], hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                free_job_stream(j);
+                return MICSA_EHIP;
+            }
+            st_job = j.stream;
+        }
+        int st = micsa_create(&pr, st_job, &probe);
+        if (st == MICSA_ENOMEM) {  // the device is fuller than the budget says: retry next step
+            free_job_stream(j);
+            break;
+        }
+        if (st) {
+            free_job_stream(j);
+            return st;
+        }
+        j.ctx = probe;
+        j.batched = batched;
         micsa_schedule cs{j.sched.kind, j.sched.period, j.sched.T0, j.sched.T1, j.sched.n_sweeps,
                           j.sched.table.empty() ? nullptr : j.sched.table.data(), (int64_t)j.sched.table.size()};
         if ((st = micsa_set_schedule(j.ctx, &cs))) return st;
@@ -2510,36 +2650,45 @@ int micsa_pool_step(micsa_pool* pool, int64_t sweeps, int32_t* running, int32_t*
         pool->used += j.bytes;
         ++nrun;
     }
-    // 2. advance: LDS-resident jobs in one batched launch, the others alone.
-    // A resident job's counter moves only once its batch is launched, so an
-    // error leaves every job's counter at the sweeps it really has enqueued.
-    std::vector<ResidentItem> items;
-    std::vector<std::pair<micsa_ctx*, int64_t>> batched;
+    // 3. enqueue the next chunk of sweeps of every running job with a free
+    // chunk slot (at most two chunks in flight per job, and per batch).
+    // Nothing waits for the device: the call returns once the work is queued.
+    const int bslot = (int)(pool->batches & 1);
+    std::vector<ResidentItem>& items = pool->h_items[bslot];
+    std::vector<std::pair<PoolJob*, int64_t>> batched;
     size_t lds = 0;
-    for (auto& j : pool->jobs) {
-        if (j.state != MICSA_JOB_RUNNING) continue;
-        micsa_ctx* c = j.ctx;
-        const int64_t n = std::min<int64_t>(sweeps, c->sched.n_sweeps - c->k);
-        if (n <= 0 || !use_resident(c)) continue;
-        ResidentSched rs{c->k, n, 0, c->sched.period, 0, 0};
-        for (int l = 0; l < c->L; ++l)
-            items.push_back(ResidentItem{c->g, c->spin, c->dem, c->tally, c->d_dth, rs, l});
-        lds = std::max(lds, (size_t)c->g.Nh * 3);
-        batched.emplace_back(c, n);
+    if (slot_free(pool->bev[bslot])) {
+        items.clear();
+        for (auto& j : pool->jobs) {
+            if (j.state != MICSA_JOB_RUNNING || !j.batched) continue;
+            micsa_ctx* c = j.ctx;
+            const int64_t n = std::min<int64_t>(sweeps, c->sched.n_sweeps - c->k);
+            if (n <= 0) continue;
+            ResidentSched rs{c->k, n, 0, c->sched.period, 0, 0};
+            for (int l = 0; l < c->L; ++l)
+                items.push_back(ResidentItem{c->g, c->spin, c->dem, c->tally, c->d_dth, rs, l});
+            lds = std::max(lds, (size_t)c->g.Nh * 3);
+            batched.emplace_back(&j, n);
+        }
     }
-    if (!items.empty()) {
-        if (items.size() > pool->d_items_cap) {
-            if (pool->d_items) (void)hipFree(pool->d_items);
-            pool->d_items = nullptr;
-            pool->d_items_cap = 0;
-            if (hipMalloc(&pool->d_items, items.size() * sizeof(ResidentItem)) != hipSuccess) {
+    if (!batched.empty()) {
+        // a resident job's counter moves only once its batch is launched
+        if (items.size() > pool->d_items_cap[bslot]) {
+            if (pool->d_items[bslot]) (void)hipFree(pool->d_items[bslot]);
+            pool->d_items[bslot] = nullptr;
+            pool->d_items_cap[bslot] = 0;
+            if (hipMalloc(&pool->d_items[bslot], items.size() * sizeof(ResidentItem)) != hipSuccess) {
                 (void)hipGetLastError();
                 return MICSA_ENOMEM;
             }
-            pool->d_items_cap = items.size();
+            pool->d_items_cap[bslot] = items.size();
         }
-        if (hipMemcpyAsync(pool->d_items, items.data(), items.size() * sizeof(ResidentItem), hipMemcpyHostToDevice,
-                           pool->stream) != hipSuccess)
+        if (!pool->bev[bslot] && hipEventCreateWithFlags(&pool->bev[bslot], hipEventDisableTiming) != hipSuccess)
+            return MICSA_EHIP;
+        // the table is copied from pageable memory: the copy returns once the
+        // host buffer may be reused, and the stream orders it before the launch
+        if (hipMemcpyAsync(pool->d_items[bslot], items.data(), items.size() * sizeof(ResidentItem),
+                           hipMemcpyHostToDevice, pool->stream) != hipSuccess)
             return MICSA_EHIP;
         static bool attr = false;
         if (!attr) {
@@ -2548,23 +2697,28 @@ int micsa_pool_step(micsa_pool* pool, int64_t sweeps, int32_t* running, int32_t*
                 return MICSA_EHIP;
             attr = true;
         }
-        k_resident_batch<<<(unsigned)items.size(), kResidentBlock, lds, pool->stream>>>(pool->d_items);
+        k_resident_batch<<<(unsigned)items.size(), kResidentBlock, lds, pool->stream>>>(pool->d_items[bslot]);
         if (hipGetLastError() != hipSuccess) return MICSA_EHIP;
-        for (auto& b : batched) b.first->k += b.second;
+        if (hipEventRecord(pool->bev[bslot], pool->stream) != hipSuccess) return MICSA_EHIP;
+        for (auto& b : batched) {
+            b.first->ctx->k += b.second;
+            b.first->last_batch = pool->batches;
+        }
+        ++pool->batches;
     }
     for (auto& j : pool->jobs) {
-        if (j.state != MICSA_JOB_RUNNING) continue;
+        if (j.state != MICSA_JOB_RUNNING || j.batched) continue;
         micsa_ctx* c = j.ctx;
         const int64_t n = std::min<int64_t>(sweeps, c->sched.n_sweeps - c->k);
-        if (n <= 0 || use_resident(c)) continue;
+        const int slot = (int)(j.chunks & 1);
+        if (n <= 0 || !slot_free(j.ev[slot])) continue;
         const int st = micsa_sweep(c, MICSA_ALGO_MICSA, n);
         if (st) return st;
+        if (hipEventRecord(j.ev[slot], j.stream) != hipSuccess) return MICSA_EHIP;
+        ++j.chunks;
     }
-    if (hipStreamSynchronize(pool->stream) != hipSuccess) return MICSA_EHIP;
-    // 3. retire finished jobs
     int32_t r = 0, q = 0;
     for (auto& j : pool->jobs) {
-        if (j.state == MICSA_JOB_RUNNING && j.ctx->k >= j.ctx->sched.n_sweeps) j.state = MICSA_JOB_DONE;
         r += j.state == MICSA_JOB_RUNNING;
         q += j.state == MICSA_JOB_QUEUED;
     }
@@ -2606,7 +2760,8 @@ int micsa_pool_release(micsa_pool* pool, int64_t job)
         PoolJob& j = pool->jobs[i];
         if (j.id != job) continue;
         if (j.state != MICSA_JOB_DONE) return MICSA_EINVAL;
-        micsa_destroy(j.ctx);
+        micsa_destroy(j.ctx);  // synchronises the job's stream
+        free_job_stream(j);
         pool->used -= j.bytes;
         pool->jobs.erase(pool->jobs.begin() + (long)i);
         return MICSA_OK;

@@ -25,7 +25,7 @@ TIME_SWEEP, TIME_REFRESH, TIME_HEATBATH, TIME_REDUCE, TIME_METROPOLIS = 0, 1, 2,
 OPT_SWEEP_KERNEL, OPT_TILE_Y, OPT_TILE_Z, OPT_XCD_MAP, OPT_GRAPHS, OPT_PREFETCH, OPT_TEMPORAL, OPT_MSC_FUSED = 1, 2, 3, 4, 5, 6, 7, 8
 OPT_DRAW_AHEAD = 9
 OPT_MSC_PASS = 10
-KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_FUSED, KERNEL_RESIDENT, KERNEL_MULTISPIN = 0, 1, 2, 3, 4
+KERNEL_AUTO, KERNEL_SIMPLE, KERNEL_FUSED, KERNEL_RESIDENT, KERNEL_MULTISPIN, KERNEL_SLAB = 0, 1, 2, 3, 4, 5
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_RELEASED = 0, 1, 2, 3
 PT_WALKERS, PT_METROPOLIS = 0, 1
 PT_TIME_EMCS, PT_TIME_SWAP = 0, 1
@@ -107,6 +107,7 @@ _SIGNATURES = [
                                          ctypes.POINTER(ctypes.c_int64)]),
     ("micsa_pool_step", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32)]),
+    ("micsa_pool_sync", ctypes.c_int, [ctypes.c_void_p]),
     ("micsa_pool_job_state", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_int64)]),
     ("micsa_pool_job_context", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_void_p)]),
@@ -421,6 +422,9 @@ class Pool:
         r, q = ctypes.c_int32(), ctypes.c_int32()
         self._check(lib().micsa_pool_step(self._pool, int(sweeps), ctypes.byref(r), ctypes.byref(q)), "pool_step")
         return r.value, q.value
+
+    def sync(self) -> None:
+        self._check(lib().micsa_pool_sync(self._pool), "pool_sync")
 
     def state(self, job: int) -> tuple[int, int]:
         st, k = ctypes.c_int32(), ctypes.c_int64()

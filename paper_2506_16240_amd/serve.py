@@ -4,9 +4,11 @@ Jobs are instances of the 3D EA +-J model with L uniform in {8, 16, 32, 64,
 128} and 1..64 replicas of one sample, annealed with MicSA from T = 3.0 to
 0.1 over 2000 sweeps (refresh every 10 sweeps).  Arrivals follow a Poisson
 process of the given rate; each arrival is submitted to the pool as soon as
-its time has passed, and the pool advances every running job by
-`sweeps_per_step` sweeps per step, admitting queued jobs as memory frees
-up.  The time to solution of a job is its completion time minus its arrival
+its time has passed.  The loop calls the pool's step over and over: each
+call admits what fits and enqueues the next `sweeps_per_step` sweeps of
+every job whose previous chunks have finished, without waiting for the
+device, so jobs run concurrently (each large job on its own stream, the
+small ones in one batched launch) while new arrivals are admitted.  The time to solution of a job is its completion time minus its arrival
 time.  All device work happens in libmicsa.
 """
 from __future__ import annotations
@@ -72,7 +74,7 @@ def job_stream(n_jobs: int, rate: float, seed: int, n_sweeps: int = 2000, L_choi
 
 
 def serve(stream: list[tuple[float, JobSpec]], hbm_budget: int, sweeps_per_step: int = 100,
-          max_running: int = 1 << 20) -> tuple[list[JobResult], dict]:
+          max_running: int = 1 << 20, poll_s: float = 2e-4) -> tuple[list[JobResult], dict]:
     """Run the arrival stream through a pool; returns per-job results and metrics."""
     pool = M.Pool(hbm_budget, max_running)
     results: dict[int, JobResult] = {}
@@ -91,9 +93,12 @@ def serve(stream: list[tuple[float, JobSpec]], hbm_budget: int, sweeps_per_step:
         if not live:
             time.sleep(max(0.0, min(pending[0][0] - now, 0.05)))
             continue
+        # enqueue the next chunk of every job with a free slot; the call does
+        # not wait for the device, so arrivals keep being admitted while it runs
         running, _ = pool.step(sweeps_per_step)
         max_running_seen = max(max_running_seen, running)
         now = time.perf_counter() - t0
+        finished = 0
         for job in list(live):
             st, _ = pool.state(job)
             if st == M.JOB_DONE:
@@ -103,6 +108,9 @@ def serve(stream: list[tuple[float, JobSpec]], hbm_budget: int, sweeps_per_step:
                 r.done, r.energies, r.best_energy = now, E, int(E.min())
                 pool.release(job)
                 live.discard(job)
+                finished += 1
+        if not finished:
+            time.sleep(poll_s)  # every job has work in flight: poll again shortly
     wall = time.perf_counter() - t0
     pool.close()
     res = [results[j] for j in sorted(results)]

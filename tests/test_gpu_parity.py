@@ -154,6 +154,54 @@ def test_quench_L64_shape():
         same_state(g, o)
 
 
+SLAB_SHAPES = [(8, 2, 2, 1, 1), (8, 4, 6, 2, 3), (24, 6, 10, 1, 2), (64, 16, 4, 3, 1), (128, 64, 6, 1, 1),
+               (40, 10, 8, 2, 2)]
+
+
+@pytest.mark.parametrize("shape", SLAB_SHAPES)
+def test_slab_sweep_matches_oracle(shape):
+    """The one-launch slab sweep (a z plane per work-group, neighbour planes
+    recomputed, refresh drawn in the kernel): minimum sides (one word per
+    row, planes that wrap onto a side of 2), several samples and replicas,
+    ragged words per row, a plane of 1024 words, refresh every sweep and
+    every fourth; logged energies, tally and state against the oracle."""
+    g, o = pair(*shape, seed=0x51AB)
+    g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_SLAB)
+    assert g.kernel_name(M.ALGO_MICSA) == "k_micsa_slab"
+    for P, n in ((1, 5), (4, 13)):
+        gs, os_ = scheds(M.SCHED_LINEAR, 2.5, 0.4, 100, P)
+        g.set_schedule(gs)
+        o_k = g.counters()[0]
+        Eg, Dg = g.sweep_logged(M.ALGO_MICSA, n, 1)
+        Eo, Do = o.run(O.ALGO_MICSA, os_, n, 1)
+        assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do), (P, o_k)
+        same_state(g, o)
+        assert np.array_equal(g.energy_tally(), o.energy())
+    g.sweep(M.ALGO_HEATBATH, 2)  # the baselines keep their own kernels on the same context
+    o.run(O.ALGO_HEATBATH, os_, 2)
+    same_state(g, o)
+
+
+def test_quench_L64_slab_1000_sweeps():
+    """Configuration 2 (L = 64, two replicas, T = 0.7, refresh every 10) on the
+    library's own kernel choice, the slab sweep, for 1000 sweeps in long
+    calls: state, energies, daemon energies, tally and overlap equal the
+    oracle's."""
+    w = W.QUENCH_L64
+    g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
+    assert g.kernel_name(M.ALGO_MICSA) == "k_micsa_slab"
+    gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
+    g.set_schedule(gs)
+    for n in (333, 1, 666):
+        g.sweep(M.ALGO_MICSA, n)
+        o.run(O.ALGO_MICSA, os_, n, 0)
+    same_state(g, o)
+    E = o.energy()
+    assert np.array_equal(g.energy(), E) and np.array_equal(g.energy_tally(), E)
+    assert np.array_equal(g.daemon_energy(), o.daemon_energy())
+    assert np.array_equal(g.overlap(0, 1), o.overlap(0, 1))
+
+
 def test_batched_L32_shape():
     """L = 32, 256 samples x 2 replicas in one context (byte layout)."""
     w = W.BATCHED_L32
@@ -713,11 +761,14 @@ def test_bitplane_batched_L32_shape():
     assert np.array_equal(g.energy_tally(), o.energy())
 
 
-def test_bitplane_long_calls_match_oracle():
-    """Bit-plane layout, calls of many sweeps with a refresh every 3 (the
-    refresh kernel ahead of each refresh sweep inside one call), against the
-    oracle; two lane groups, two replicas."""
+@pytest.mark.parametrize("ahead", [0, 1], ids=["draw-in-place", "draw-ahead"])
+def test_bitplane_long_calls_match_oracle(ahead):
+    """Bit-plane layout, calls of many sweeps with a refresh every 3, the
+    levels drawn just before each refresh sweep or ahead of it on the side
+    stream while the sweeps before it run, against the oracle; two lane
+    groups, two replicas."""
     g, o = bpair(32, 12, 10, 70, 2, seed=9090)
+    g.set_option(M.OPT_DRAW_AHEAD, ahead)
     gs, os_ = scheds(M.SCHED_LINEAR, 2.5, 0.4, 80, 3)
     g.set_schedule(gs)
     for n in (31, 1, 2, 17):

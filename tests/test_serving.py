@@ -1,5 +1,7 @@
 """Serving pool: admission by HBM footprint, continuous batching, and results
 that do not depend on the other jobs in the pool."""
+import time
+
 import numpy as np
 import pytest
 
@@ -61,11 +63,18 @@ def _run_alone(spec, sweeps_per_step):
     return out
 
 
+TARGETS = [SV.JobSpec(16, 3, 0xC0FFEE, n_sweeps=300),   # batched resident launch
+           SV.JobSpec(64, 2, 0xC0FFEF, n_sweeps=120),   # own stream, slab sweep
+           SV.JobSpec(128, 1, 0xC0FFF0, n_sweeps=60)]   # own stream, multispin planes
+
+
 @pytest.mark.gpu
-def test_job_alone_equals_job_in_the_mix():
+@pytest.mark.parametrize("target", TARGETS, ids=["L16-batched", "L64-slab", "L128-multispin"])
+def test_job_alone_equals_job_in_the_mix(target):
     """A job's final state is bit-identical alone and among other jobs that
-    arrive before and after it, of other sizes and kernels."""
-    target = SV.JobSpec(16, 3, 0xC0FFEE, n_sweeps=300)
+    arrive before and after it, of other sizes and kernels, running
+    concurrently on their own streams and in the batched launch; and it
+    equals the oracle's trajectory."""
     alone = _run_alone(target, 37)
     others = [SV.JobSpec(8, 5, 11, n_sweeps=120), SV.JobSpec(32, 2, 12, n_sweeps=400),
               SV.JobSpec(64, 1, 13, n_sweeps=90), SV.JobSpec(16, 7, 14, n_sweeps=250),
@@ -88,9 +97,12 @@ def test_job_alone_equals_job_in_the_mix():
     for a, b in zip(alone, mixed):
         assert np.array_equal(a, b)
     # and the job equals the oracle's trajectory
-    o = O.Lattice(16, 16, 16, 1, 3, 0xC0FFEE)
-    o.run(O.ALGO_MICSA, O.Schedule(O.SCHED_LINEAR, 3.0, 0.1, 300, 10), 300, 0)
+    t = target
+    o = O.Lattice(t.L, t.L, t.L, 1, t.R, t.seed)
+    o.run(O.ALGO_MICSA, O.Schedule(O.SCHED_LINEAR, t.T0, t.T1, t.n_sweeps, t.period), t.n_sweeps, 0)
     assert np.array_equal(mixed[1], o.sigma) and np.array_equal(mixed[0], o.energy())
+    assert np.array_equal(mixed[2], o.m)
+    pool.sync()
     pool.close()
 
 
@@ -102,16 +114,16 @@ def test_admission_respects_the_budget():
     jobs = [pool.submit(32, 32, 32, 1, 4, 100 + i, M.Schedule(M.SCHED_LINEAR, 3.0, 0.1, 60, 10)) for i in range(5)]
     seen = 0
     finished = set()
-    for _ in range(50):
-        running, queued = pool.step(20)
+    t_end = time.monotonic() + 60
+    while len(finished) < len(jobs) and time.monotonic() < t_end:
+        running, queued = pool.step(20)  # enqueues without waiting for the device
         assert running <= 2
         seen = max(seen, running)
         for j in jobs:
             if j not in finished and pool.state(j)[0] == M.JOB_DONE:
                 finished.add(j)
                 pool.release(j)
-        if len(finished) == len(jobs):
-            break
+        time.sleep(1e-3)
     assert seen == 2 and len(finished) == 5
     del spec
     pool.close()
