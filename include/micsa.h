@@ -153,6 +153,19 @@ int micsa_sweep(micsa_ctx* ctx, int32_t algo, int64_t n);
 int micsa_sweep_logged(micsa_ctx* ctx, int32_t algo, int64_t n, int64_t stride, int64_t* E_log,
                        int64_t* D_log);
 
+/* As micsa_sweep_logged with the logs in device memory: E_log and D_log are
+   device arrays of int64 [n/stride][S*R] (either may be NULL), written in
+   stream order; the call only enqueues (it does not synchronise), so the
+   logs are complete once the stream has reached this call's last sweep, as
+   for a kernel the caller launched on the same stream.  The arrays stay the
+   caller's and must stay allocated until then.  The library keeps one
+   device row of reduction slots per context, allocated on the first call;
+   on lattices swept by the resident kernel it keeps a buffer of the whole
+   log that grows (after synchronising the stream) when a call logs more
+   rows than any call before it.  Errors as micsa_sweep_logged. */
+int micsa_sweep_logged_d(micsa_ctx* ctx, int32_t algo, int64_t n, int64_t stride, int64_t* E_log,
+                         int64_t* D_log);
+
 /* Wait for all enqueued work. */
 int micsa_sync(micsa_ctx* ctx);
 
@@ -282,7 +295,8 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      and a counter kernel to every sweep).  Per-launch timing
      (micsa_set_timing) always launches every kernel.
    MICSA_OPT_TEMPORAL: MicSA sweeps per pass over memory on the fused byte
-     sweep: 2 (default) runs sweeps k and k + 1 in one launch wherever a call
+     sweep and the slab sweep: 2 (default) runs sweeps k and k + 1 in one
+     launch wherever a call
      sweeps at least two (the state is read and written once per pair); 1
      runs one sweep per launch.  Results are identical.
    MICSA_OPT_MSC_PASS: MicSA sweeps per pass on the one-launch multispin
@@ -327,9 +341,10 @@ enum micsa_kernel_choice {
     MICSA_KERNEL_FUSED = 2,   /* one launch per sweep, refresh fused in (Lx % 32 == 0) */
     MICSA_KERNEL_RESIDENT = 3, /* one work-group per lattice keeps it in LDS for many sweeps (<= 102400 sites) */
     MICSA_KERNEL_MULTISPIN = 4, /* MicSA daemon sweeps on bit planes, 64 sites of a row per word (Lx % 128 == 0) */
-    MICSA_KERNEL_SLAB = 5       /* MicSA, one launch per sweep, a z plane per work-group with its neighbour
-                                   planes recomputed (byte layout, gamma = 1, Ly * Lx / 8 <= 1024); AUTO takes it
-                                   for lattices too large for the resident sweep with Lx < 128 (e.g. L = 64) */
+    MICSA_KERNEL_SLAB = 5       /* MicSA, one launch per two sweeps (two per pass, the default) or per sweep, a z
+                                   plane per work-group with its neighbour planes recomputed (byte layout,
+                                   gamma = 1, Ly * Lx / 8 <= 1024); AUTO takes it for lattices too large for the
+                                   resident sweep with Lx < 128 (e.g. L = 64) */
 };
 int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value);
 

@@ -170,3 +170,213 @@ __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab(Geom g, const uint8_t
 }
 
 }  // namespace micsa
+
+namespace micsa {
+
+// Two sweeps (A, then B) per launch on the slab layout: the four half sweeps
+// A-even, A-odd, B-even, B-odd run on 7, 5, 3 and 1 planes around the owned
+// plane z (each ring plane recomputed from the same old state as its owner),
+// with the old odd planes z - 4 .. z + 4 and each half's results exchanged
+// through LDS, so the state is read and written once per pair of sweeps.
+// REFA / REFB: sweep A / B is a refresh point; its levels are drawn in the
+// kernel (the counters of k_refresh, refresh index and thresholds per sweep).
+struct SlabRefresh {
+    uint32_t rho;
+    DaemonThresholds th;
+};
+
+// Neighbourhood of a 4-site word from LDS planes of the other parity:
+// src is the plane of the word's own z, up / dn the planes at z + 1 / z - 1.
+template <int P>
+__device__ __forceinline__ Nbhd slab_gather(const Geom& g, uint32_t own, const uint32_t* src, const uint32_t* up,
+                                            const uint32_t* dn, int y, int c, int yp, int ym, int cp, int cm, int q,
+                                            int pq)
+{
+    const uint32_t m1 = 0x01010101u;
+    const int dir = (q ^ P) ? 1 : -1;
+    const uint32_t w0 = src[y * g.Wr + c];
+    const uint32_t w[6] = {w0, shift_word(w0, src[y * g.Wr + (dir > 0 ? cp : cm)], dir), src[yp * g.Wr + c],
+                           src[ym * g.Wr + c], up[pq], dn[pq]};
+    Nbhd n;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) n.nb[d] = w[d] & m1;
+    const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
+    if (P == 0) {
+        const uint32_t jw = own >> 1;
+        n.jb[0] = jbits(jw, dA);
+        n.jb[1] = jbits(jw, dB);
+        n.jb[2] = jbits(jw, kPy);
+        n.jb[3] = jbits(jw, kMy);
+        n.jb[4] = jbits(jw, kPz);
+        n.jb[5] = jbits(jw, kMz);
+    } else {  // an odd site reads each bond from its even neighbour's opposite slot
+        n.jb[0] = jbits(w[0] >> 1, dA);
+        n.jb[1] = jbits(w[1] >> 1, dB);
+        n.jb[2] = jbits(w[2] >> 1, kMy);
+        n.jb[3] = jbits(w[3] >> 1, kPy);
+        n.jb[4] = jbits(w[4] >> 1, kMz);
+        n.jb[5] = jbits(w[5] >> 1, kPz);
+    }
+    return n;
+}
+
+template <bool REFA, bool REFB>
+__global__ __launch_bounds__(kSlabLanes) void k_micsa_slab2(Geom g, const uint8_t* __restrict__ spin_in,
+                                                           const uint8_t* __restrict__ dem_in,
+                                                           uint8_t* __restrict__ spin_out,
+                                                           uint8_t* __restrict__ dem_out,
+                                                           unsigned long long* __restrict__ tally, SlabRefresh ra,
+                                                           SlabRefresh rb)
+{
+    extern __shared__ uint32_t lds_slab2[];
+    const int P = g.Ly * g.Wr;
+    uint32_t* LO = lds_slab2;        // old odd words, planes z - 4 .. z + 4
+    uint32_t* LEA = LO + 9 * P;      // A-even results, planes z - 3 .. z + 3
+    uint32_t* LOA = LEA + 7 * P;     // A-odd results, planes z - 2 .. z + 2
+    uint32_t* LEB = LOA + 5 * P;     // B-even results, planes z - 1 .. z + 1
+    const int nt = gridDim.x;
+    int t = blockIdx.x;
+    if ((nt & 7) == 0) t = (t & 7) * (nt >> 3) + (t >> 3);
+    const int l = t / g.Lz, z0 = t - l * g.Lz;
+    const int s = l / g.R, r = l - s * g.R;
+    const int pos = threadIdx.x;
+    const bool live = pos < P;
+    const int pq = live ? pos : 0;
+    const int y = pq / g.Wr, c = pq - y * g.Wr;
+    const int yp = y + 1 == g.Ly ? 0 : y + 1, ym = y == 0 ? g.Ly - 1 : y - 1;
+    const int cp = c + 1 == g.Wr ? 0 : c + 1, cm = c == 0 ? g.Wr - 1 : c - 1;
+    auto wrapz = [&](int z) {
+        z %= g.Lz;
+        return z < 0 ? z + g.Lz : z;
+    };
+    const int64_t Nh = g.Nh;
+    const uint32_t* ev_in = reinterpret_cast<const uint32_t*>(spin_in + (int64_t)l * 2 * Nh);
+    const uint32_t* od_in = reinterpret_cast<const uint32_t*>(spin_in + ((int64_t)l * 2 + 1) * Nh);
+    const uint32_t* de_in = reinterpret_cast<const uint32_t*>(dem_in + (int64_t)l * 2 * Nh);
+    const uint32_t* do_in = reinterpret_cast<const uint32_t*>(dem_in + ((int64_t)l * 2 + 1) * Nh);
+    uint32_t* ev_out = reinterpret_cast<uint32_t*>(spin_out + (int64_t)l * 2 * Nh);
+    uint32_t* od_out = reinterpret_cast<uint32_t*>(spin_out + ((int64_t)l * 2 + 1) * Nh);
+    uint32_t* de_out = reinterpret_cast<uint32_t*>(dem_out + (int64_t)l * 2 * Nh);
+    uint32_t* do_out = reinterpret_cast<uint32_t*>(dem_out + ((int64_t)l * 2 + 1) * Nh);
+    const uint32_t m1 = 0x01010101u;
+    const uint32_t sw = stream_word(kStreamDaemon, (uint32_t)s);
+    // levels of the even and odd words of plane zz drawn for refresh f
+    auto draw = [&](const SlabRefresh& f, int zz, uint32_t& we, uint32_t& wo) {
+        const int64_t i0 = 8 * ((int64_t)wrapz(zz) * P + pq);
+        const u32x4 a = philox10((uint32_t)(i0 >> 2), f.rho, (uint32_t)r, sw, g.key0, g.key1);
+        const u32x4 b = philox10((uint32_t)(i0 >> 2) + 1u, f.rho, (uint32_t)r, sw, g.key0, g.key1);
+        split8(g, i0, a, b, [&](uint32_t u) { return daemon_level(u, f.th); }, we, wo);
+    };
+
+    // ---- loads (and the draws of sweep A)
+    uint32_t Od[9], Ev[7], Me[7], Mo[5];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) Od[e] = od_in[(int64_t)wrapz(z0 - 4 + e) * P + pq];
+#pragma unroll
+    for (int e = 0; e < 7; ++e) {
+        const int64_t w = (int64_t)wrapz(z0 - 3 + e) * P + pq;
+        Ev[e] = ev_in[w];
+        if (!REFA) Me[e] = de_in[w];
+    }
+    if (!REFA) {
+#pragma unroll
+        for (int e = 0; e < 5; ++e) Mo[e] = do_in[(int64_t)wrapz(z0 - 2 + e) * P + pq];
+    } else {
+#pragma unroll
+        for (int e = 0; e < 7; ++e) {
+            uint32_t we, wo;
+            draw(ra, z0 - 3 + e, we, wo);
+            Me[e] = we;
+            if (e >= 1 && e <= 5) Mo[e - 1] = wo;
+        }
+    }
+    if (live) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) LO[e * P + pos] = Od[e];
+    }
+    __syncthreads();
+
+    int dE = 0;
+    // ---- A even: planes z - 3 .. z + 3 (old odd neighbours)
+#pragma unroll
+    for (int e = 0; e < 7; ++e) {
+        const int z = wrapz(z0 - 3 + e);
+        const uint32_t* src = LO + (e + 1) * P;
+        const Nbhd n = slab_gather<0>(g, Ev[e], src, src + P, src - P, y, c, yp, ym, cp, cm, (y + z) & 1, pq);
+        const uint32_t S0 = Ev[e] & m1;
+        uint32_t S = S0;
+        int d = 0;
+        micsa_word(S, Me[e], n, d);
+        Ev[e] ^= S ^ S0;  // the bond bits stay
+        if (live) LEA[e * P + pos] = Ev[e];
+        if (e == 3) dE += d;
+    }
+    __syncthreads();
+    // ---- A odd: planes z - 2 .. z + 2 (A-even neighbours)
+    uint32_t Oa[5];
+#pragma unroll
+    for (int e = 0; e < 5; ++e) {
+        const int z = wrapz(z0 - 2 + e);
+        const uint32_t* src = LEA + (e + 1) * P;
+        const uint32_t W0 = Od[e + 2];
+        const Nbhd n = slab_gather<1>(g, W0, src, src + P, src - P, y, c, yp, ym, cp, cm, (y + z) & 1, pq);
+        const uint32_t S0 = W0 & m1;
+        uint32_t S = S0;
+        int d = 0;
+        micsa_word(S, Mo[e], n, d);
+        Oa[e] = W0 ^ S ^ S0;
+        if (live) LOA[e * P + pos] = Oa[e];
+        if (e == 2) dE += d;
+    }
+    __syncthreads();
+    // ---- B even: planes z - 1 .. z + 1 (A-odd neighbours); levels of B drawn at its refresh
+    uint32_t Eb1 = 0, Mb1 = 0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int z = wrapz(z0 - 1 + e);
+        const uint32_t* src = LOA + (e + 1) * P;
+        const uint32_t W0 = Ev[e + 2];
+        uint32_t M = Me[e + 2];
+        if (REFB) {
+            uint32_t we, wo;
+            draw(rb, z0 - 1 + e, we, wo);
+            M = we;
+            if (e == 1) Mo[2] = wo;
+        }
+        const Nbhd n = slab_gather<0>(g, W0, src, src + P, src - P, y, c, yp, ym, cp, cm, (y + z) & 1, pq);
+        const uint32_t S0 = W0 & m1;
+        uint32_t S = S0;
+        int d = 0;
+        micsa_word(S, M, n, d);
+        const uint32_t Wn = W0 ^ S ^ S0;
+        if (live) LEB[e * P + pos] = Wn;
+        if (e == 1) {
+            Eb1 = Wn;
+            Mb1 = M;
+            dE += d;
+        }
+    }
+    __syncthreads();
+    // ---- B odd: plane z (B-even neighbours)
+    {
+        const int z = z0;
+        const uint32_t* src = LEB + P;
+        const uint32_t W0 = Oa[2];
+        const Nbhd n = slab_gather<1>(g, W0, src, src + P, src - P, y, c, yp, ym, cp, cm, (y + z) & 1, pq);
+        const uint32_t S0 = W0 & m1;
+        uint32_t S = S0, M = Mo[2];
+        int d = 0;
+        micsa_word(S, M, n, d);
+        dE += d;
+        if (live) {
+            const int64_t w = (int64_t)z * P + pos;
+            ev_out[w] = Eb1;
+            de_out[w] = Mb1;
+            od_out[w] = W0 ^ S ^ S0;
+            do_out[w] = M;
+        }
+    }
+    block_add(tally + (int64_t)l * kSlots, live ? dE : 0);  // idle lanes repeat word 0's moves
+}
+
+}  // namespace micsa

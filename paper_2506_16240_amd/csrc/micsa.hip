@@ -106,6 +106,11 @@ struct micsa_ctx {
     const void* gkey[kAlgos] = {};  // state buffer the graph was captured with
     unsigned long long* tally = nullptr;  // [L][kSlots]
     unsigned long long* red = nullptr;    // [max(L, S)][kSlots] reduction scratch
+    // device-pointer logging: one row of slots [2][L][kSlots] (energy, then
+    // level sums), and the resident kernel's (U, sum m) pairs, grown on demand
+    unsigned long long* logslots = nullptr;
+    long long* rlog = nullptr;
+    size_t rlog_cap = 0;  // entries of rlog
     Schedule sched;
     // device tables of the installed schedule, one entry per refresh index
     DaemonThresholds* d_dth = nullptr;
@@ -544,6 +549,32 @@ int launch_slab_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
                                                                  c->tally, 0u, DaemonThresholds{0, 0, 0});
     }
     const int st = check_launch(c, "k_micsa_slab");
+    if (st) return st;
+    std::swap(c->spin, c->spin_alt);
+    std::swap(c->dem, c->dem_alt);
+    return MICSA_OK;
+}
+
+// Sweeps k and k + 1 in one slab launch (refreshA / refreshB: k / k + 1 are
+// refresh points).
+int launch_slab_sweep2(micsa_ctx* c, bool refreshA, int64_t rhoA, double TA, bool refreshB, int64_t rhoB, double TB)
+{
+    const int P = c->p.Ly * (c->p.Lx / 8);
+    const dim3 grid((unsigned)(c->L * c->p.Lz));
+    const unsigned block = (unsigned)((P + 63) / 64 * 64);
+    const size_t lds = (size_t)24 * P * 4;
+    const SlabRefresh ra{(uint32_t)rhoA, refreshA ? daemon_thresholds(TA) : DaemonThresholds{0, 0, 0}};
+    const SlabRefresh rb{(uint32_t)rhoB, refreshB ? daemon_thresholds(TB) : DaemonThresholds{0, 0, 0}};
+    const auto kern = refreshA ? (refreshB ? k_micsa_slab2<true, true> : k_micsa_slab2<true, false>)
+                               : (refreshB ? k_micsa_slab2<false, true> : k_micsa_slab2<false, false>);
+    if (lds > 64 * 1024 &&
+        hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return fail(c, MICSA_EHIP, "k_micsa_slab2 LDS attribute");
+    {
+        TimedLaunch t(c, kTimeSweep);
+        kern<<<grid, block, lds, c->stream>>>(c->g, c->spin, c->dem, c->spin_alt, c->dem_alt, c->tally, ra, rb);
+    }
+    const int st = check_launch(c, "k_micsa_slab2");
     if (st) return st;
     std::swap(c->spin, c->spin_alt);
     std::swap(c->dem, c->dem_alt);
@@ -1325,6 +1356,17 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
             ++i;
             continue;
         }
+        if (algo == MICSA_ALGO_MICSA && c->temporal == 2 && i + 1 < n && use_slab(c)) {
+            // sweeps k and k + 1 in one slab launch (gamma = 1)
+            const bool refreshB = is_refresh(k + 1, c->sched.period);
+            const int64_t rhoB = refresh_index(k + 1, c->sched.period);
+            const double TB = temperature(c->sched, rhoB);
+            if (!(TB > 0.0) || !std::isfinite(TB)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
+            if ((st = launch_slab_sweep2(c, is_refresh(k, c->sched.period), rho, T, refreshB, rhoB, TB))) return st;
+            c->k = k + 2;
+            ++i;
+            continue;
+        }
         if (algo == MICSA_ALGO_MICSA || algo == MICSA_ALGO_WALKERS) {
             const bool refresh = fam == 0 && is_refresh(t, c->sched.period);
             if (c->bit) {
@@ -1379,6 +1421,8 @@ void free_all(micsa_ctx* c)
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->tally) (void)hipFree(c->tally);
     if (c->red) (void)hipFree(c->red);
+    if (c->logslots) (void)hipFree(c->logslots);
+    if (c->rlog) (void)hipFree(c->rlog);
     for (auto& v : c->events)
         for (auto& e : v) {
             (void)hipEventDestroy(e.first);
@@ -1603,6 +1647,61 @@ int micsa_set_schedule(micsa_ctx* ctx, const micsa_schedule* s)
 }
 
 int micsa_sweep(micsa_ctx* ctx, int32_t algo, int64_t n) { return sweep_impl(ctx, algo, n); }
+
+int micsa_sweep_logged_d(micsa_ctx* ctx, int32_t algo, int64_t n, int64_t stride, int64_t* E_log,
+                         int64_t* D_log)
+{
+    if (!ctx) return MICSA_EINVAL;
+    if (stride < 1) return fail(ctx, MICSA_EINVAL, "stride must be >= 1");
+    if (!ctx->sched.set) return fail(ctx, MICSA_ESTATE, "no schedule installed");
+    if (n < 0 || ctx->k + n > ctx->sched.n_sweeps) return fail(ctx, MICSA_ERANGE, "sweeps beyond the schedule");
+    const int64_t rows = n / stride;
+    const int L = ctx->L;
+    const int64_t N = n_sites(ctx);
+    int st = check_sweep(ctx, algo, n);
+    if (st) return st;
+    if (rows == 0 || (!E_log && !D_log)) return sweep_impl(ctx, algo, n);
+    if (use_resident(ctx) && algo != MICSA_ALGO_WALKERS) {
+        const size_t need = (size_t)rows * L * 2;
+        if (need > ctx->rlog_cap) {
+            // the old buffer may still be in use by enqueued work
+            if (ctx->rlog) {
+                HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+                (void)hipFree(ctx->rlog);
+                ctx->rlog = nullptr;
+                ctx->rlog_cap = 0;
+            }
+            if (hipMalloc(&ctx->rlog, need * 8) != hipSuccess) {
+                (void)hipGetLastError();
+                ctx->rlog = nullptr;
+                return fail(ctx, MICSA_ENOMEM, "log buffer");
+            }
+            ctx->rlog_cap = need;
+        }
+        if ((st = launch_resident(ctx, algo, n, ctx->rlog, stride))) return st;
+        const int64_t e = rows * L;
+        k_log_from_pairs<<<(unsigned)((e + 255) / 256), 256, 0, ctx->stream>>>(
+            ctx->rlog, e, N, reinterpret_cast<long long*>(E_log), reinterpret_cast<long long*>(D_log));
+        return check_launch(ctx, "k_log_from_pairs");
+    }
+    if (!ctx->logslots && hipMalloc(&ctx->logslots, (size_t)2 * L * kSlots * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->logslots = nullptr;
+        return fail(ctx, MICSA_ENOMEM, "log slots");
+    }
+    unsigned long long* U = ctx->logslots;
+    unsigned long long* Ms = ctx->logslots + (size_t)L * kSlots;
+    for (int64_t r = 0; r < rows; ++r) {
+        if ((st = sweep_impl(ctx, algo, stride))) return st;
+        if (E_log && (st = enqueue_energy(ctx, U))) return st;
+        if (D_log && (st = enqueue_level_sum(ctx, Ms))) return st;
+        k_log_from_slots<<<(unsigned)((L + 255) / 256), 256, 0, ctx->stream>>>(
+            U, Ms, L, N, E_log ? reinterpret_cast<long long*>(E_log + r * L) : nullptr,
+            D_log ? reinterpret_cast<long long*>(D_log + r * L) : nullptr);
+        if ((st = check_launch(ctx, "k_log_from_slots"))) return st;
+    }
+    return n > rows * stride ? sweep_impl(ctx, algo, n - rows * stride) : MICSA_OK;
+}
 
 int micsa_sweep_logged(micsa_ctx* ctx, int32_t algo, int64_t n, int64_t stride, int64_t* E_log, int64_t* D_log)
 {
@@ -2358,7 +2457,7 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
         return ctx && use_fused(ctx) ? "k_heatbath_sweep_fused<1>" : "k_heatbath_half<1>";
     if (ctx && use_fused(ctx))
         return ctx->temporal == 2 && sweep2_eligible(ctx) ? "k_micsa_sweep2_fused" : "k_micsa_sweep_fused";
-    if (ctx && use_slab(ctx)) return "k_micsa_slab";
+    if (ctx && use_slab(ctx)) return ctx->temporal == 2 ? "k_micsa_slab2" : "k_micsa_slab";
     return "k_micsa_half";
 }
 

@@ -126,4 +126,33 @@ __global__ void __launch_bounds__(256) k_sum_slots(const unsigned long long* __r
     out[e] = (long long)t;
 }
 
+// Device-pointer logging: one row of the energy and daemon logs from the
+// slots of every lattice (thread per lattice): E = 2 U - 3 N from the
+// unsatisfied-bond count U, D = 4 sum m.  A null output is skipped.
+__global__ void __launch_bounds__(256) k_log_from_slots(const unsigned long long* __restrict__ U,
+                                                        const unsigned long long* __restrict__ Ms, int L,
+                                                        int64_t N, long long* __restrict__ E,
+                                                        long long* __restrict__ D)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= L) return;
+    unsigned long long u = 0, m = 0;
+    for (int k = 0; k < kSlots; ++k) {
+        if (E) u += U[(int64_t)l * kSlots + k];
+        if (D) m += Ms[(int64_t)l * kSlots + k];
+    }
+    if (E) E[l] = 2 * (long long)u - 3 * N;
+    if (D) D[l] = 4 * (long long)m;
+}
+
+// The same from the resident kernel's log of (U, sum m) pairs, n = rows x L.
+__global__ void __launch_bounds__(256) k_log_from_pairs(const long long* __restrict__ raw, int64_t n, int64_t N,
+                                                        long long* __restrict__ E, long long* __restrict__ D)
+{
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    if (E) E[e] = 2 * raw[2 * e] - 3 * N;
+    if (D) D[e] = 4 * raw[2 * e + 1];
+}
+
 }  // namespace micsa

@@ -74,6 +74,8 @@ _SIGNATURES = [
     ("micsa_sweep", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64]),
     ("micsa_sweep_logged", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                           ctypes.c_void_p, ctypes.c_void_p]),
+    ("micsa_sweep_logged_d", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                            ctypes.c_void_p, ctypes.c_void_p]),
     ("micsa_sync", ctypes.c_int, [ctypes.c_void_p]),
     ("micsa_read_energy", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     ("micsa_read_energy_tally", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -252,6 +254,15 @@ class Lattice:
         D = np.zeros((rows, self.S * self.R), np.int64)
         self._check(lib().micsa_sweep_logged(self._ctx, algo, n, stride, _ptr(E), _ptr(D)), "sweep_logged")
         return E, D
+
+    def sweep_logged_d(self, algo: int, n: int, stride: int, E_log, D_log) -> None:
+        """micsa_sweep_logged_d: E_log / D_log are device int64 buffers of
+        [n // stride][S * R] entries (objects with data_ptr(), raw addresses
+        or None); enqueue only."""
+        def addr(t):
+            return None if t is None else (t.data_ptr() if hasattr(t, "data_ptr") else int(t))
+        self._check(lib().micsa_sweep_logged_d(self._ctx, algo, n, stride, addr(E_log), addr(D_log)),
+                    "sweep_logged_d")
 
     def sync(self) -> None:
         self._check(lib().micsa_sync(self._ctx), "sync")

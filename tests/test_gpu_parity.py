@@ -167,7 +167,7 @@ def test_slab_sweep_matches_oracle(shape):
     every fourth; logged energies, tally and state against the oracle."""
     g, o = pair(*shape, seed=0x51AB)
     g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_SLAB)
-    assert g.kernel_name(M.ALGO_MICSA) == "k_micsa_slab"
+    assert g.kernel_name(M.ALGO_MICSA) == "k_micsa_slab2"
     for P, n in ((1, 5), (4, 13)):
         gs, os_ = scheds(M.SCHED_LINEAR, 2.5, 0.4, 100, P)
         g.set_schedule(gs)
@@ -175,6 +175,15 @@ def test_slab_sweep_matches_oracle(shape):
         Eg, Dg = g.sweep_logged(M.ALGO_MICSA, n, 1)
         Eo, Do = o.run(O.ALGO_MICSA, os_, n, 1)
         assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do), (P, o_k)
+        same_state(g, o)
+        assert np.array_equal(g.energy_tally(), o.energy())
+    # long calls: two sweeps per launch (refresh on the first, the second or
+    # both sweeps of a pair; a call starting at odd k; a last single sweep)
+    for P, n in ((3, 11), (1, 6), (3, 9)):
+        gs, os_ = scheds(M.SCHED_LINEAR, 2.5, 0.4, 100, P)
+        g.set_schedule(gs)
+        g.sweep(M.ALGO_MICSA, n)
+        o.run(O.ALGO_MICSA, os_, n, 0)
         same_state(g, o)
         assert np.array_equal(g.energy_tally(), o.energy())
     g.sweep(M.ALGO_HEATBATH, 2)  # the baselines keep their own kernels on the same context
@@ -189,10 +198,10 @@ def test_quench_L64_slab_1000_sweeps():
     oracle's."""
     w = W.QUENCH_L64
     g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
-    assert g.kernel_name(M.ALGO_MICSA) == "k_micsa_slab"
+    assert g.kernel_name(M.ALGO_MICSA) == "k_micsa_slab2"
     gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
     g.set_schedule(gs)
-    for n in (333, 1, 666):
+    for n in (333, 666, 1):  # pairs with the refresh first, then (from k = 333) second in the pair
         g.sweep(M.ALGO_MICSA, n)
         o.run(O.ALGO_MICSA, os_, n, 0)
     same_state(g, o)
