@@ -311,8 +311,12 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
    MICSA_OPT_PREFETCH: steps of global loads in flight in the fused MicSA
      sweep, 1 (default) or 2 (used for work-groups of at most 640 lanes,
      i.e. (tile_y + 4) * Lx / 32 <= 640; larger tiles run with 1).
-   MICSA_OPT_DRAW_AHEAD: one-launch multispin and bit-plane sweeps.  1 (default
-     for the multispin sweep; the bit-plane layout defaults to 0) draws
+   MICSA_OPT_DRAW_AHEAD: one-launch multispin, slab and bit-plane sweeps.  On
+     two-sweep slab launches, 1 (default) has a launch without a refresh of
+     its own draw the levels of the schedule's next refresh for its planes,
+     kept across calls until the schedule changes, and 0 draws them inside
+     the refresh launch.  Elsewhere, 1 (default for the multispin sweep;
+     the bit-plane layout defaults to 0) draws
      the daemon levels of each refresh (Sec. 2.3; they depend on the refresh
      index and temperature, not on the state) in a kernel of their own on a
      second stream of the library, while the sweeps before the refresh run;
@@ -341,10 +345,11 @@ enum micsa_kernel_choice {
     MICSA_KERNEL_FUSED = 2,   /* one launch per sweep, refresh fused in (Lx % 32 == 0) */
     MICSA_KERNEL_RESIDENT = 3, /* one work-group per lattice keeps it in LDS for many sweeps (<= 102400 sites) */
     MICSA_KERNEL_MULTISPIN = 4, /* MicSA daemon sweeps on bit planes, 64 sites of a row per word (Lx % 128 == 0) */
-    MICSA_KERNEL_SLAB = 5       /* MicSA, one launch per two sweeps (two per pass, the default) or per sweep, a z
-                                   plane per work-group with its neighbour planes recomputed (byte layout,
-                                   gamma = 1, Ly * Lx / 8 <= 1024); AUTO takes it for lattices too large for the
-                                   resident sweep with Lx < 128 (e.g. L = 64) */
+    MICSA_KERNEL_SLAB = 5       /* MicSA, a z plane per work-group with its neighbour planes recomputed (byte
+                                   layout, gamma = 1, Ly * Lx / 8 <= 1024): two sweeps per launch while the
+                                   lattices have fewer planes than the device has compute units (and two per
+                                   pass are set, the default), else one; AUTO takes it for lattices too large
+                                   for the resident sweep with Lx < 128 (e.g. L = 64) */
 };
 int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value);
 

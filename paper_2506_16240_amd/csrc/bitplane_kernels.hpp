@@ -22,6 +22,8 @@
 // window 3 <= m + u <= 6 tested and the new level m + u - 3 formed, each as
 // a handful of 64-bit logic operations.
 #pragma once
+#include <type_traits>
+#include <utility>
 #include "geometry.hpp"
 #include "philox.hpp"
 
@@ -183,26 +185,90 @@ __global__ void __launch_bounds__(256) kb_init_spins(GeomB b, uint64_t* __restri
             spin + (int64_t)wl * 2 * g.Nh, nullptr, live);
 }
 
+// Refresh draws: a wave draws kRefreshCounters consecutive Philox counters
+// (4 sites each) for its 64 lattices, one per lane; the levels of site j of
+// the wave's run are gathered into lane j by ballots, so each lane stores
+// the two level-plane words of one site (consecutive sites, coalesced).
+constexpr int kRefreshCounters = 16;
+
+// v with lane J replaced by the wave-uniform value w (v_writelane_b32, lane
+// select an inline constant).
+template <int J>
+__device__ __forceinline__ uint64_t put_lane(uint64_t v, uint64_t w)
+{
+    static_assert(J >= 0 && J < 64, "lane");
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(lo) : "s"((uint32_t)w), "i"(J));
+    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(hi) : "s"((uint32_t)(w >> 32)), "i"(J));
+    return ((uint64_t)hi << 32) | lo;
+}
+constexpr int kRefreshSites = 4 * kRefreshCounters;  // one per lane
+static_assert(kRefreshSites == 64, "one site per lane");
+
+// f(integral_constant<int, C>) for C = C0 .. kRefreshCounters - 1, unrolled.
+template <int C, class F>
+__device__ __forceinline__ void for_counters(F& f)
+{
+    if constexpr (C < kRefreshCounters) {
+        f(std::integral_constant<int, C>{});
+        for_counters<C + 1>(f);
+    }
+}
+
+__device__ __forceinline__ void bp_draw_levels(const GeomB& b, int wl, uint32_t rho, const DaemonThresholds& th,
+                                               uint64_t* __restrict__ dm0, uint64_t* __restrict__ dm1)
+{
+    const Geom& g = b.g;
+    // first counter of this wave (wave-uniform)
+    const int64_t tb = ((int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) *
+                       kRefreshCounters;
+    const int64_t nt = g.Nh / 2;  // counters per lattice
+    if (tb >= nt) return;         // whole waves only
+    int si, r;
+    const int lane = lane_id();
+    const bool lane_ok = bp_lattice(b, wl, lane, si, r);
+    const uint32_t sw = stream_word(kStreamDaemon, (uint32_t)si);
+    uint64_t W0 = 0, W1 = 0;  // level planes of site 4 tb + lane
+    const uint32_t u0 = (uint32_t)(th.t0 - 1u), u1 = (uint32_t)(th.t1 - 1u), u2 = (uint32_t)(th.t2 - 1u);
+    // m = [u >= t0] + [u >= t1] + [u >= t2] with t0 <= t1 <= t2, so the high
+    // bit of m is [u >= t1] and the low bit the XOR of the three
+    auto site = [&](uint32_t u, auto J) {
+        const uint64_t a0 = __ballot(u > u0), a1 = __ballot(u > u1), a2 = __ballot(u > u2);
+        W0 = put_lane<decltype(J)::value>(W0, a0 ^ a1 ^ a2);
+        W1 = put_lane<decltype(J)::value>(W1, a1);
+    };
+    auto counter = [&](auto C) {
+        constexpr int c = decltype(C)::value;
+        const int64_t t = tb + c;
+        u32x4 o = {0, 0, 0, 0};  // counters past the lattice: sites that are not stored
+        if (lane_ok && t < nt) o = philox10((uint32_t)t, rho, (uint32_t)r, sw, g.key0, g.key1);
+        site(o.v0, std::integral_constant<int, 4 * c>{});
+        site(o.v1, std::integral_constant<int, 4 * c + 1>{});
+        site(o.v2, std::integral_constant<int, 4 * c + 2>{});
+        site(o.v3, std::integral_constant<int, 4 * c + 3>{});
+    };
+    for_counters<0>(counter);
+    const int64_t i = 4 * tb + lane;
+    if (i < 4 * nt) {
+        const int x = (int)(i % g.Lx);
+        const int64_t row = i / g.Lx;
+        const int y = (int)(row % g.Ly), z = (int)(row / g.Ly);
+        const int64_t at = (int64_t)((x + y + z) & 1) * g.Nh + (i >> 1);
+        dm0[(int64_t)wl * 2 * g.Nh + at] = W0;
+        dm1[(int64_t)wl * 2 * g.Nh + at] = W1;
+    }
+}
+
+// Work-groups of the refresh draw along x (4 waves of kRefreshCounters counters each).
+__host__ __device__ inline unsigned bp_refresh_blocks(const Geom& g)
+{
+    return (unsigned)((g.Nh / 2 + 4 * kRefreshCounters - 1) / (4 * kRefreshCounters));
+}
+
 __global__ void __launch_bounds__(256) kb_refresh(GeomB b, uint64_t* __restrict__ dm0, uint64_t* __restrict__ dm1,
                                                   uint32_t rho, DaemonThresholds th)
 {
-    const Geom& g = b.g;
-    const int wl = blockIdx.y;
-    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const bool live = t < g.Nh / 2;
-    int si, r;
-    const bool lane_ok = bp_lattice(b, wl, lane_id(), si, r);
-    const uint32_t s = (uint32_t)si;
-    u32x4 o = {0, 0, 0, 0};
-    if (live && lane_ok)
-        o = philox10((uint32_t)t, rho, (uint32_t)r, stream_word(kStreamDaemon, s), g.key0, g.key1);
-    ballot4(g, live ? 4 * t : 0, o,
-            [&](uint32_t u, uint32_t& b0, uint32_t& b1) {
-                const uint32_t m = daemon_level(u, th);
-                b0 = m & 1u;
-                b1 = m >> 1;
-            },
-            dm0 + (int64_t)wl * 2 * g.Nh, dm1 + (int64_t)wl * 2 * g.Nh, live);
+    bp_draw_levels(b, blockIdx.y, rho, th, dm0, dm1);
 }
 
 // kb_refresh with the sweep index in device memory (replayable graphs).
@@ -213,24 +279,7 @@ __global__ void __launch_bounds__(256) kb_refresh_dev(GeomB b, uint64_t* __restr
     const int64_t k = *dk;
     if (!(period >= 1 ? (k % period == 0) : (((k + 1) & k) == 0))) return;
     const int64_t rho = period >= 1 ? k / period : 63 - __clzll((unsigned long long)(k + 1));
-    const DaemonThresholds th = dth[rho];
-    const Geom& g = b.g;
-    const int wl = blockIdx.y;
-    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const bool live = t < g.Nh / 2;
-    int si, r;
-    const bool lane_ok = bp_lattice(b, wl, lane_id(), si, r);
-    const uint32_t s = (uint32_t)si;
-    u32x4 o = {0, 0, 0, 0};
-    if (live && lane_ok)
-        o = philox10((uint32_t)t, (uint32_t)rho, (uint32_t)r, stream_word(kStreamDaemon, s), g.key0, g.key1);
-    ballot4(g, live ? 4 * t : 0, o,
-            [&](uint32_t u, uint32_t& b0, uint32_t& b1) {
-                const uint32_t m = daemon_level(u, th);
-                b0 = m & 1u;
-                b1 = m >> 1;
-            },
-            dm0 + (int64_t)wl * 2 * g.Nh, dm1 + (int64_t)wl * 2 * g.Nh, live);
+    bp_draw_levels(b, blockIdx.y, (uint32_t)rho, dth[rho], dm0, dm1);
 }
 
 // ------------------------------------------------------------- half sweep

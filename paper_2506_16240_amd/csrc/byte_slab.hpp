@@ -13,6 +13,8 @@
 //      z + 1 (the outer two recomputed from the same old state as their
 //      owners, so no work-group waits for another) and leaves the new even
 //      words in LDS;
+//      a word's x and y neighbours come from LDS, its own column at z and
+//      z +- 1 from the thread's registers;
 //   3. the odd half runs on plane z with its neighbours' new even words; an
 //      odd site's couplings are read from those words (the bond bits ride in
 //      the even spin bytes, geometry.hpp).
@@ -24,6 +26,40 @@
 namespace micsa {
 
 constexpr int kSlabLanes = 1024;
+
+// Neighbourhood of a 4-site word from the other parity's words: w0, up and
+// dn the thread's own column at z, z + 1 and z - 1 (registers), src the
+// LDS plane at z for the x and y neighbours.
+template <int P>
+__device__ __forceinline__ Nbhd slab_gather(const Geom& g, uint32_t own, uint32_t w0, uint32_t up, uint32_t dn,
+                                            const uint32_t* src, int y, int c, int yp, int ym, int cp, int cm, int q)
+{
+    const uint32_t m1 = 0x01010101u;
+    const int dir = (q ^ P) ? 1 : -1;
+    const uint32_t w[6] = {w0, shift_word(w0, src[y * g.Wr + (dir > 0 ? cp : cm)], dir), src[yp * g.Wr + c],
+                           src[ym * g.Wr + c], up, dn};
+    Nbhd n;
+#pragma unroll
+    for (int d = 0; d < 6; ++d) n.nb[d] = w[d] & m1;
+    const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
+    if (P == 0) {
+        const uint32_t jw = own >> 1;
+        n.jb[0] = jbits(jw, dA);
+        n.jb[1] = jbits(jw, dB);
+        n.jb[2] = jbits(jw, kPy);
+        n.jb[3] = jbits(jw, kMy);
+        n.jb[4] = jbits(jw, kPz);
+        n.jb[5] = jbits(jw, kMz);
+    } else {  // an odd site reads each bond from its even neighbour's opposite slot
+        n.jb[0] = jbits(w[0] >> 1, dA);
+        n.jb[1] = jbits(w[1] >> 1, dB);
+        n.jb[2] = jbits(w[2] >> 1, kMy);
+        n.jb[3] = jbits(w[3] >> 1, kPy);
+        n.jb[4] = jbits(w[4] >> 1, kMz);
+        n.jb[5] = jbits(w[5] >> 1, kPz);
+    }
+    return n;
+}
 
 template <bool REFRESH>
 __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab(Geom g, const uint8_t* __restrict__ spin_in,
@@ -97,33 +133,20 @@ __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab(Geom g, const uint8_t
     __syncthreads();
 
     int dE = 0;
+    uint32_t En[3];  // new even words of planes z - 1, z, z + 1
     // ---- even half on planes z - 1, z, z + 1
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
         const int z = wrapz(z0 - 1 + e);
         const int q = (y + z) & 1;
-        const int dir = q ? 1 : -1;  // the shifted x neighbour of an even site
-        const uint32_t* Oz = LO + (e + 1) * P;
         const uint32_t W0 = Ev[e];
-        Nbhd n;
-        const uint32_t w0 = Oz[y * g.Wr + c];
-        const uint32_t w1 = shift_word(w0, Oz[y * g.Wr + (dir > 0 ? cp : cm)], dir);
-        const uint32_t w[6] = {w0, w1, Oz[yp * g.Wr + c], Oz[ym * g.Wr + c], (Oz + P)[pq], (Oz - P)[pq]};
-#pragma unroll
-        for (int d = 0; d < 6; ++d) n.nb[d] = w[d] & m1;
-        const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
-        const uint32_t jw = W0 >> 1;
-        n.jb[0] = jbits(jw, dA);
-        n.jb[1] = jbits(jw, dB);
-        n.jb[2] = jbits(jw, kPy);
-        n.jb[3] = jbits(jw, kMy);
-        n.jb[4] = jbits(jw, kPz);
-        n.jb[5] = jbits(jw, kMz);
+        const Nbhd n = slab_gather<0>(g, W0, Od[e + 1], Od[e + 2], Od[e], LO + (e + 1) * P, y, c, yp, ym, cp, cm, q);
         const uint32_t S0 = W0 & m1;
         uint32_t S = S0, M = Me[e];
         int d_e = 0;
         micsa_word(S, M, n, d_e);
         const uint32_t Wn = W0 ^ S ^ S0;  // the bond bits stay
+        En[e] = Wn;
         if (live) {
             LE[e * P + pos] = Wn;
             if (e == 1) {
@@ -139,22 +162,7 @@ __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab(Geom g, const uint8_t
     {
         const int z = z0;
         const int q = (y + z) & 1;
-        const int dir = q ? -1 : 1;  // the shifted x neighbour of an odd site
-        const uint32_t* Ez = LE + P;
-        Nbhd n;
-        const uint32_t w0 = Ez[y * g.Wr + c];
-        const uint32_t w1 = shift_word(w0, Ez[y * g.Wr + (dir > 0 ? cp : cm)], dir);
-        const uint32_t w[6] = {w0, w1, Ez[yp * g.Wr + c], Ez[ym * g.Wr + c], (Ez + P)[pq], (Ez - P)[pq]};
-#pragma unroll
-        for (int d = 0; d < 6; ++d) n.nb[d] = w[d] & m1;
-        // an odd site reads each bond from its even neighbour's opposite slot
-        const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
-        n.jb[0] = jbits(w[0] >> 1, dA);
-        n.jb[1] = jbits(w[1] >> 1, dB);
-        n.jb[2] = jbits(w[2] >> 1, kMy);
-        n.jb[3] = jbits(w[3] >> 1, kPy);
-        n.jb[4] = jbits(w[4] >> 1, kMz);
-        n.jb[5] = jbits(w[5] >> 1, kPz);
+        const Nbhd n = slab_gather<1>(g, Od[2], En[1], En[2], En[0], LE + P, y, c, yp, ym, cp, cm, q);
         const uint32_t W0 = Od[2];
         const uint32_t S0 = W0 & m1;
         uint32_t S = S0, M = Mo;
@@ -185,49 +193,20 @@ struct SlabRefresh {
     DaemonThresholds th;
 };
 
-// Neighbourhood of a 4-site word from LDS planes of the other parity:
-// src is the plane of the word's own z, up / dn the planes at z + 1 / z - 1.
-template <int P>
-__device__ __forceinline__ Nbhd slab_gather(const Geom& g, uint32_t own, const uint32_t* src, const uint32_t* up,
-                                            const uint32_t* dn, int y, int c, int yp, int ym, int cp, int cm, int q,
-                                            int pq)
-{
-    const uint32_t m1 = 0x01010101u;
-    const int dir = (q ^ P) ? 1 : -1;
-    const uint32_t w0 = src[y * g.Wr + c];
-    const uint32_t w[6] = {w0, shift_word(w0, src[y * g.Wr + (dir > 0 ? cp : cm)], dir), src[yp * g.Wr + c],
-                           src[ym * g.Wr + c], up[pq], dn[pq]};
-    Nbhd n;
-#pragma unroll
-    for (int d = 0; d < 6; ++d) n.nb[d] = w[d] & m1;
-    const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
-    if (P == 0) {
-        const uint32_t jw = own >> 1;
-        n.jb[0] = jbits(jw, dA);
-        n.jb[1] = jbits(jw, dB);
-        n.jb[2] = jbits(jw, kPy);
-        n.jb[3] = jbits(jw, kMy);
-        n.jb[4] = jbits(jw, kPz);
-        n.jb[5] = jbits(jw, kMz);
-    } else {  // an odd site reads each bond from its even neighbour's opposite slot
-        n.jb[0] = jbits(w[0] >> 1, dA);
-        n.jb[1] = jbits(w[1] >> 1, dB);
-        n.jb[2] = jbits(w[2] >> 1, kMy);
-        n.jb[3] = jbits(w[3] >> 1, kPy);
-        n.jb[4] = jbits(w[4] >> 1, kMz);
-        n.jb[5] = jbits(w[5] >> 1, kPz);
-    }
-    return n;
-}
 
-template <bool REFA, bool REFB>
+// DRAW: also draw the levels of a later refresh rn for the owned plane (both
+// parities) into dnext (daemon layout), for the launch that will start at
+// that refresh; levels depend on the refresh index and temperature only.
+template <bool REFA, bool REFB, bool DRAW>
 __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab2(Geom g, const uint8_t* __restrict__ spin_in,
                                                            const uint8_t* __restrict__ dem_in,
                                                            uint8_t* __restrict__ spin_out,
                                                            uint8_t* __restrict__ dem_out,
                                                            unsigned long long* __restrict__ tally, SlabRefresh ra,
-                                                           SlabRefresh rb)
+                                                           SlabRefresh rb, SlabRefresh rn,
+                                                           uint8_t* __restrict__ dnext)
 {
+    static_assert(!(DRAW && (REFA || REFB)), "a launch that draws at a refresh draws nothing ahead");
     extern __shared__ uint32_t lds_slab2[];
     const int P = g.Ly * g.Wr;
     uint32_t* LO = lds_slab2;        // old odd words, planes z - 4 .. z + 4
@@ -290,6 +269,15 @@ __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab2(Geom g, const uint8_
             if (e >= 1 && e <= 5) Mo[e - 1] = wo;
         }
     }
+    if (DRAW) {  // while the loads are in flight
+        uint32_t we, wo;
+        draw(rn, z0, we, wo);
+        if (live) {
+            const int64_t w = (int64_t)z0 * P + pos;
+            reinterpret_cast<uint32_t*>(dnext + (int64_t)l * 2 * Nh)[w] = we;
+            reinterpret_cast<uint32_t*>(dnext + ((int64_t)l * 2 + 1) * Nh)[w] = wo;
+        }
+    }
     if (live) {
 #pragma unroll
         for (int e = 0; e < 9; ++e) LO[e * P + pos] = Od[e];
@@ -302,7 +290,7 @@ __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab2(Geom g, const uint8_
     for (int e = 0; e < 7; ++e) {
         const int z = wrapz(z0 - 3 + e);
         const uint32_t* src = LO + (e + 1) * P;
-        const Nbhd n = slab_gather<0>(g, Ev[e], src, src + P, src - P, y, c, yp, ym, cp, cm, (y + z) & 1, pq);
+        const Nbhd n = slab_gather<0>(g, Ev[e], Od[e + 1], Od[e + 2], Od[e], src, y, c, yp, ym, cp, cm, (y + z) & 1);
         const uint32_t S0 = Ev[e] & m1;
         uint32_t S = S0;
         int d = 0;
@@ -319,7 +307,7 @@ __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab2(Geom g, const uint8_
         const int z = wrapz(z0 - 2 + e);
         const uint32_t* src = LEA + (e + 1) * P;
         const uint32_t W0 = Od[e + 2];
-        const Nbhd n = slab_gather<1>(g, W0, src, src + P, src - P, y, c, yp, ym, cp, cm, (y + z) & 1, pq);
+        const Nbhd n = slab_gather<1>(g, W0, Ev[e + 1], Ev[e + 2], Ev[e], src, y, c, yp, ym, cp, cm, (y + z) & 1);
         const uint32_t S0 = W0 & m1;
         uint32_t S = S0;
         int d = 0;
@@ -330,7 +318,7 @@ __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab2(Geom g, const uint8_
     }
     __syncthreads();
     // ---- B even: planes z - 1 .. z + 1 (A-odd neighbours); levels of B drawn at its refresh
-    uint32_t Eb1 = 0, Mb1 = 0;
+    uint32_t Eb[3], Mb1 = 0;
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
         const int z = wrapz(z0 - 1 + e);
@@ -343,15 +331,14 @@ __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab2(Geom g, const uint8_
             M = we;
             if (e == 1) Mo[2] = wo;
         }
-        const Nbhd n = slab_gather<0>(g, W0, src, src + P, src - P, y, c, yp, ym, cp, cm, (y + z) & 1, pq);
+        const Nbhd n = slab_gather<0>(g, W0, Oa[e + 1], Oa[e + 2], Oa[e], src, y, c, yp, ym, cp, cm, (y + z) & 1);
         const uint32_t S0 = W0 & m1;
         uint32_t S = S0;
         int d = 0;
         micsa_word(S, M, n, d);
-        const uint32_t Wn = W0 ^ S ^ S0;
-        if (live) LEB[e * P + pos] = Wn;
+        Eb[e] = W0 ^ S ^ S0;
+        if (live) LEB[e * P + pos] = Eb[e];
         if (e == 1) {
-            Eb1 = Wn;
             Mb1 = M;
             dE += d;
         }
@@ -362,7 +349,7 @@ __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab2(Geom g, const uint8_
         const int z = z0;
         const uint32_t* src = LEB + P;
         const uint32_t W0 = Oa[2];
-        const Nbhd n = slab_gather<1>(g, W0, src, src + P, src - P, y, c, yp, ym, cp, cm, (y + z) & 1, pq);
+        const Nbhd n = slab_gather<1>(g, W0, Eb[1], Eb[2], Eb[0], src, y, c, yp, ym, cp, cm, (y + z) & 1);
         const uint32_t S0 = W0 & m1;
         uint32_t S = S0, M = Mo[2];
         int d = 0;
@@ -370,7 +357,7 @@ __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab2(Geom g, const uint8_
         dE += d;
         if (live) {
             const int64_t w = (int64_t)z * P + pos;
-            ev_out[w] = Eb1;
+            ev_out[w] = Eb[1];
             de_out[w] = Mb1;
             od_out[w] = W0 ^ S ^ S0;
             do_out[w] = M;

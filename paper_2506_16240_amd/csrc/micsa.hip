@@ -52,6 +52,7 @@ struct micsa_ctx {
     micsa_params p{};
     hipStream_t stream = nullptr;
     int device = 0;  // the device current at creation, which holds the state
+    int cus = 0;     // its compute units
     Geom g{};
     int L = 0;  // lattices = S * R
     int gamma = 1;  // daemons (walkers) per site; a timestep is gamma sweeps
@@ -60,6 +61,10 @@ struct micsa_ctx {
     uint8_t* spin = nullptr;  // [L][2][Nh] current
     uint8_t* dem = nullptr;   // [L][2][Nh] current
     uint8_t* spin_alt = nullptr;
+    // two-sweep slab launches: levels of later refreshes drawn ahead (shape of
+    // dem) and the sweep index each holds the levels of (-1: none)
+    uint8_t* sdr[2] = {nullptr, nullptr};
+    int64_t sdr_k[2] = {-1, -1};
     uint8_t* dem_alt = nullptr;
     // bit-plane layout (MICSA_LAYOUT_BITPLANE): 64 samples per word
     bool bit = false;
@@ -381,7 +386,7 @@ int draw_bp_levels(micsa_ctx* c, int64_t kr)
     }
     HIP_TRY(c, hipEventRecord(c->draw_free, c->stream));
     HIP_TRY(c, hipStreamWaitEvent(c->draw_stream, c->draw_free, 0));
-    kb_refresh<<<dim3((unsigned)((c->g.Nh / 2 + 3) / 4), (unsigned)word_lattices(c)), 256, 0, c->draw_stream>>>(
+    kb_refresh<<<dim3(bp_refresh_blocks(c->g), (unsigned)word_lattices(c)), 256, 0, c->draw_stream>>>(
         geomb(c), c->bdr0, c->bdr1, (uint32_t)rho, daemon_thresholds(T));
     const int st = check_launch(c, "kb_refresh (drawn ahead)");
     if (st) return st;
@@ -410,7 +415,7 @@ int sweep_bitplane(micsa_ctx* c, int64_t n)
             HIP_TRY(c, hipStreamWaitEvent(c->stream, c->draw_done, 0));
         } else if (refresh) {
             TimedLaunch t(c, kTimeRefresh);
-            kb_refresh<<<dim3((unsigned)((c->g.Nh / 2 + 3) / 4), (unsigned)word_lattices(c)), 256, 0, c->stream>>>(
+            kb_refresh<<<dim3(bp_refresh_blocks(c->g), (unsigned)word_lattices(c)), 256, 0, c->stream>>>(
                 geomb(c), c->bdm0, c->bdm1, (uint32_t)rho, daemon_thresholds(T));
             if ((st = check_launch(c, "kb_refresh"))) return st;
         }
@@ -426,7 +431,7 @@ int launch_bitplane_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
     const int WL = word_lattices(c);
     if (refresh) {
         TimedLaunch t(c, kTimeRefresh);
-        kb_refresh<<<dim3((unsigned)((c->g.Nh / 2 + 3) / 4), (unsigned)WL), 256, 0, c->stream>>>(
+        kb_refresh<<<dim3(bp_refresh_blocks(c->g), (unsigned)WL), 256, 0, c->stream>>>(
             geomb(c), c->bdm0, c->bdm1, (uint32_t)rho, daemon_thresholds(T));
     }
     int st = check_launch(c, "kb_refresh");
@@ -533,19 +538,22 @@ bool use_slab(const micsa_ctx* c)
     return c->kernel_opt == MICSA_KERNEL_AUTO && !use_resident(c) && !use_fused(c);
 }
 
-int launch_slab_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
+// One slab sweep.  refresh: draw the levels in the kernel; drawn (not
+// null): read them from levels drawn ahead in place of the stored daemons.
+int launch_slab_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T, const uint8_t* drawn = nullptr)
 {
     const int P = c->p.Ly * (c->p.Lx / 8);
     const dim3 grid((unsigned)(c->L * c->p.Lz));
     const unsigned block = (unsigned)((P + 63) / 64 * 64);
     const size_t lds = (size_t)8 * P * 4;
+    const uint8_t* dem_in = drawn ? drawn : c->dem;
     {
         TimedLaunch t(c, kTimeSweep);
-        if (refresh)
-            k_micsa_slab<true><<<grid, block, lds, c->stream>>>(c->g, c->spin, c->dem, c->spin_alt, c->dem_alt,
+        if (refresh && !drawn)
+            k_micsa_slab<true><<<grid, block, lds, c->stream>>>(c->g, c->spin, dem_in, c->spin_alt, c->dem_alt,
                                                                 c->tally, (uint32_t)rho, daemon_thresholds(T));
         else
-            k_micsa_slab<false><<<grid, block, lds, c->stream>>>(c->g, c->spin, c->dem, c->spin_alt, c->dem_alt,
+            k_micsa_slab<false><<<grid, block, lds, c->stream>>>(c->g, c->spin, dem_in, c->spin_alt, c->dem_alt,
                                                                  c->tally, 0u, DaemonThresholds{0, 0, 0});
     }
     const int st = check_launch(c, "k_micsa_slab");
@@ -555,29 +563,117 @@ int launch_slab_sweep(micsa_ctx* c, bool refresh, int64_t rho, double T)
     return MICSA_OK;
 }
 
-// Sweeps k and k + 1 in one slab launch (refreshA / refreshB: k / k + 1 are
-// refresh points).
-int launch_slab_sweep2(micsa_ctx* c, bool refreshA, int64_t rhoA, double TA, bool refreshB, int64_t rhoB, double TB)
+// Sweeps k and k + 1 in one slab launch.  refreshA / refreshB: k / k + 1 are
+// refresh points whose levels the kernel draws; drawnA (not null): the
+// levels of sweep k, drawn ahead, read in place of the stored daemons;
+// next (not null, no refresh in the launch): also draw the levels of refresh
+// rhoN at temperature TN into next.
+int launch_slab_sweep2(micsa_ctx* c, bool refreshA, int64_t rhoA, double TA, bool refreshB, int64_t rhoB, double TB,
+                       const uint8_t* drawnA, uint8_t* next, int64_t rhoN, double TN)
 {
+    if (drawnA) refreshA = false;
+    if (refreshA || refreshB) next = nullptr;
     const int P = c->p.Ly * (c->p.Lx / 8);
     const dim3 grid((unsigned)(c->L * c->p.Lz));
     const unsigned block = (unsigned)((P + 63) / 64 * 64);
     const size_t lds = (size_t)24 * P * 4;
     const SlabRefresh ra{(uint32_t)rhoA, refreshA ? daemon_thresholds(TA) : DaemonThresholds{0, 0, 0}};
     const SlabRefresh rb{(uint32_t)rhoB, refreshB ? daemon_thresholds(TB) : DaemonThresholds{0, 0, 0}};
-    const auto kern = refreshA ? (refreshB ? k_micsa_slab2<true, true> : k_micsa_slab2<true, false>)
-                               : (refreshB ? k_micsa_slab2<false, true> : k_micsa_slab2<false, false>);
+    const SlabRefresh rn{(uint32_t)rhoN, next ? daemon_thresholds(TN) : DaemonThresholds{0, 0, 0}};
+    const auto kern = next ? k_micsa_slab2<false, false, true>
+                           : refreshA ? (refreshB ? k_micsa_slab2<true, true, false> : k_micsa_slab2<true, false, false>)
+                                      : (refreshB ? k_micsa_slab2<false, true, false> : k_micsa_slab2<false, false, false>);
     if (lds > 64 * 1024 &&
         hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return fail(c, MICSA_EHIP, "k_micsa_slab2 LDS attribute");
     {
         TimedLaunch t(c, kTimeSweep);
-        kern<<<grid, block, lds, c->stream>>>(c->g, c->spin, c->dem, c->spin_alt, c->dem_alt, c->tally, ra, rb);
+        kern<<<grid, block, lds, c->stream>>>(c->g, c->spin, drawnA ? drawnA : c->dem, c->spin_alt, c->dem_alt,
+                                              c->tally, ra, rb, rn, next);
     }
     const int st = check_launch(c, "k_micsa_slab2");
     if (st) return st;
     std::swap(c->spin, c->spin_alt);
     std::swap(c->dem, c->dem_alt);
+    return MICSA_OK;
+}
+
+// Two sweeps per slab launch pay off while the one-sweep launch leaves
+// compute units idle (fewer planes than units, e.g. L = 64 with 2
+// replicas): they halve the launches on a latency-bound path, at twice the
+// arithmetic per sweep.  A full grid keeps one sweep per launch.
+bool slab_pairs(const micsa_ctx* c)
+{
+    return c->temporal == 2 && (int64_t)c->L * c->p.Lz < (c->cus > 0 ? c->cus : 256);
+}
+
+int64_t next_refresh(const micsa_ctx* c, int64_t from, int64_t end);
+
+constexpr int64_t kSlabDrawWindow = 1024;  // how far ahead a launch looks for the next refresh
+
+// MicSA sweeps k .. k + n - 1 on the slab sweep (gamma = 1): two per launch
+// where slab_pairs() holds, else one.  With OPT_DRAW_AHEAD (default) a
+// two-sweep launch with no refresh of its own also draws the levels of the
+// next refresh of the schedule (each work-group its own plane) into one of
+// two buffers; the launch that starts at that refresh, in this call or a
+// later one, reads them, and the buffer it reads is never the one its own
+// draw writes.  Other refreshes are drawn inside the refresh launch.
+int sweep_slab(micsa_ctx* c, int64_t n)
+{
+    const int64_t k_end = c->k + n;
+    const bool pairs = slab_pairs(c);
+    const bool ahead = c->draw_ahead != 0 && pairs;
+    int st;
+    if (ahead && !c->sdr[0]) {
+        const size_t bytes = (size_t)c->L * 2 * (size_t)c->g.Nh;
+        for (auto& q : c->sdr)
+            if (hipMalloc(&q, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                for (auto& f : c->sdr)
+                    if (f) (void)hipFree(f);
+                c->sdr[0] = c->sdr[1] = nullptr;
+                return fail(c, MICSA_ENOMEM, "slab drawn levels");
+            }
+        c->sdr_k[0] = c->sdr_k[1] = -1;
+    }
+    while (c->k < k_end) {
+        const int64_t k = c->k;
+        const bool refresh = is_refresh(k, c->sched.period);
+        const int64_t rho = refresh_index(k, c->sched.period);
+        const double T = temperature(c->sched, rho);
+        if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
+        int rd = -1;  // buffer holding this refresh's levels
+        if (refresh && ahead)
+            for (int b = 0; b < 2; ++b)
+                if (c->sdr_k[b] == k) rd = b;
+        const uint8_t* drawn = rd >= 0 ? c->sdr[rd] : nullptr;
+        if (pairs && k + 1 < k_end) {
+            const bool refreshB = is_refresh(k + 1, c->sched.period);
+            const int64_t rhoB = refresh_index(k + 1, c->sched.period);
+            const double TB = temperature(c->sched, rhoB);
+            if (!(TB > 0.0) || !std::isfinite(TB)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
+            // the next refresh after this pair, if no buffer holds it yet
+            uint8_t* next = nullptr;
+            int wb = -1;
+            int64_t kn = -1, rhoN = 0;
+            double TN = 0.0;
+            if (ahead && !(refresh && !drawn) && !refreshB &&
+                (kn = next_refresh(c, k + 2, std::min(c->sched.n_sweeps, k + 2 + kSlabDrawWindow))) >= 0 &&
+                c->sdr_k[0] != kn && c->sdr_k[1] != kn) {
+                wb = rd >= 0 ? 1 - rd : (c->sdr_k[0] < c->sdr_k[1] ? 0 : 1);
+                rhoN = refresh_index(kn, c->sched.period);
+                TN = temperature(c->sched, rhoN);
+                if (!(TN > 0.0) || !std::isfinite(TN)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
+                next = c->sdr[wb];
+            }
+            if ((st = launch_slab_sweep2(c, refresh, rho, T, refreshB, rhoB, TB, drawn, next, rhoN, TN))) return st;
+            if (next) c->sdr_k[wb] = kn;
+            c->k = k + 2;
+        } else {
+            if ((st = launch_slab_sweep(c, refresh, rho, T, drawn))) return st;
+            c->k = k + 1;
+        }
+    }
     return MICSA_OK;
 }
 
@@ -900,7 +996,7 @@ int enqueue_dev_sweep(micsa_ctx* c, int32_t algo, hipStream_t st)
     const int32_t P = c->sched.period;
     if (c->bit) {
         const int WL = word_lattices(c);
-        kb_refresh_dev<<<dim3((unsigned)((c->g.Nh / 2 + 3) / 4), (unsigned)WL), 256, 0, st>>>(
+        kb_refresh_dev<<<dim3(bp_refresh_blocks(c->g), (unsigned)WL), 256, 0, st>>>(
             geomb(c), c->bdm0, c->bdm1, c->d_k, P, c->d_dth);
         const dim3 grid = grid_for(c->g.Nh, WL);
         kb_micsa_half<0><<<grid, kBlock, 0, st>>>(geomb(c), c->bspin, c->bdm0, c->bdm1, c->bJ);
@@ -1322,6 +1418,7 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
         if (use_graph(c) && n >= kGraphSweeps) return sweep_graph(c, algo, n);
     }
     if (algo == MICSA_ALGO_MICSA && bp_one_launch(c)) return sweep_bitplane(c, n);
+    if (algo == MICSA_ALGO_MICSA && use_slab(c)) return sweep_slab(c, n);
     for (int64_t i = 0; i < n; ++i) {
         // sweep k is sweep fam of timestep t (Sec. 2.8)
         const int64_t k = c->k;
@@ -1356,17 +1453,6 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
             ++i;
             continue;
         }
-        if (algo == MICSA_ALGO_MICSA && c->temporal == 2 && i + 1 < n && use_slab(c)) {
-            // sweeps k and k + 1 in one slab launch (gamma = 1)
-            const bool refreshB = is_refresh(k + 1, c->sched.period);
-            const int64_t rhoB = refresh_index(k + 1, c->sched.period);
-            const double TB = temperature(c->sched, rhoB);
-            if (!(TB > 0.0) || !std::isfinite(TB)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
-            if ((st = launch_slab_sweep2(c, is_refresh(k, c->sched.period), rho, T, refreshB, rhoB, TB))) return st;
-            c->k = k + 2;
-            ++i;
-            continue;
-        }
         if (algo == MICSA_ALGO_MICSA || algo == MICSA_ALGO_WALKERS) {
             const bool refresh = fam == 0 && is_refresh(t, c->sched.period);
             if (c->bit) {
@@ -1377,8 +1463,6 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
                 c->pend_wander = (int32_t)(t & 1);  // this timestep's wandering, owed to the next sweep
             } else if (use_fused(c)) {
                 if ((st = launch_fused_sweep(c, refresh, rho, T))) return st;
-            } else if (algo == MICSA_ALGO_MICSA && use_slab(c)) {
-                if ((st = launch_slab_sweep(c, refresh, rho, T))) return st;
             } else {
                 if (refresh && (st = launch_refresh(c, rho, T))) return st;
                 if ((st = launch_micsa_sweep(c, fam))) return st;
@@ -1399,6 +1483,8 @@ void free_all(micsa_ctx* c)
     if (c->spin) (void)hipFree(c->spin);
     if (c->dem) (void)hipFree(c->dem);
     if (c->spin_alt) (void)hipFree(c->spin_alt);
+    for (uint8_t* q : c->sdr)
+        if (q) (void)hipFree(q);
     if (c->dem_alt) (void)hipFree(c->dem_alt);
     if (c->bspin) (void)hipFree(c->bspin);
     if (c->draw_stream) (void)hipStreamSynchronize(c->draw_stream);
@@ -1480,6 +1566,10 @@ int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
         (void)hipGetLastError();
         delete c;
         return MICSA_EHIP;
+    }
+    if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        c->cus = 0;
     }
     c->p = *p;
     c->p.gamma = gamma;
@@ -1643,6 +1733,7 @@ int micsa_set_schedule(micsa_ctx* ctx, const micsa_schedule* s)
     ctx->d_hth = d2;
     ctx->d_mth = d3;
     ctx->sched = std::move(n);
+    ctx->sdr_k[0] = ctx->sdr_k[1] = -1;  // levels drawn ahead under the old temperatures
     return MICSA_OK;
 }
 
@@ -2353,6 +2444,7 @@ int micsa_load(micsa_ctx* ctx, const void* buf, size_t len)
         if ((st = micsa_set_schedule(ctx, &s))) return st;
     } else {
         ctx->sched = Schedule{};
+        ctx->sdr_k[0] = ctx->sdr_k[1] = -1;
     }
     if ((st = micsa_write_spins(ctx, spins))) return st;
     if ((st = micsa_write_demons(ctx, dems))) return st;
@@ -2457,7 +2549,7 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
         return ctx && use_fused(ctx) ? "k_heatbath_sweep_fused<1>" : "k_heatbath_half<1>";
     if (ctx && use_fused(ctx))
         return ctx->temporal == 2 && sweep2_eligible(ctx) ? "k_micsa_sweep2_fused" : "k_micsa_sweep_fused";
-    if (ctx && use_slab(ctx)) return ctx->temporal == 2 ? "k_micsa_slab2" : "k_micsa_slab";
+    if (ctx && use_slab(ctx)) return slab_pairs(ctx) ? "k_micsa_slab2" : "k_micsa_slab";
     return "k_micsa_half";
 }
 
@@ -2563,6 +2655,12 @@ size_t footprint(const micsa_params* p)
     // levels (2) and the six coupling planes of the even sites (3 words per
     // word of sites), each 1 bit per site: 11/8 B per site per lattice
     if (gamma == 1 && p->Lx % 128 == 0) bytes += 11 * L * N / 8;
+    // lattices the slab sweep takes (too large for the resident sweep,
+    // narrower than the fused one) draw refresh levels ahead into two
+    // buffers of a byte per site per lattice
+    else if (gamma == 1 && (size_t)p->Ly * (p->Lx / 8) <= (size_t)kSlabLanes && N / 2 * 3 > kResidentLdsMax &&
+             p->Lx < 128)
+        bytes += 2 * L * N;
     return bytes;
 }
 

@@ -157,3 +157,19 @@ def test_pool_footprint_counts_the_multispin_planes():
         assert fp(128, 8, 8, S, R) - fp(64, 16, 8, S, R) == 11 * L * N // 8
     # gamma > 1 never runs multispin
     assert fp(128, 8, 8, 1, 1, gamma=2) - fp(64, 16, 8, 1, 1, gamma=2) == 0
+
+
+def test_pool_footprint_counts_the_slab_levels():
+    """A byte-layout job on the slab sweep (too large for the resident
+    sweep, Lx < 128) draws refresh levels ahead into two buffers of a byte
+    per site per lattice; a resident-size lattice and a gamma > 1 one do
+    not."""
+    def fp(*shape, gamma=1):
+        out = ctypes.c_size_t()
+        assert M.lib().micsa_pool_footprint(ctypes.byref(M._params(*shape, 0, 1, gamma)), ctypes.byref(out)) == M.OK
+        return out.value
+    N, L = 64 ** 3, 2
+    base = 2 * L * N * 2 + (L + 1) * 64 * 8  # two state buffers of spin + daemon bytes, and the slots
+    assert fp(64, 64, 64, 1, 2) - base == 2 * L * N
+    assert fp(32, 32, 32, 1, 2) == 2 * L * 32 ** 3 * 2 + (L + 1) * 64 * 8  # resident: no drawn levels
+    assert fp(64, 64, 64, 1, 2, gamma=2) == 2 * L * N * 3 + (L + 1) * 64 * 8

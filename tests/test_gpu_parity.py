@@ -10,6 +10,7 @@ first sweeps otherwise).
 """
 import numpy as np
 import pytest
+import torch
 
 from oracle import oracle as O
 from paper_2506_16240_amd import micsa as M
@@ -155,19 +156,31 @@ def test_quench_L64_shape():
 
 
 SLAB_SHAPES = [(8, 2, 2, 1, 1), (8, 4, 6, 2, 3), (24, 6, 10, 1, 2), (64, 16, 4, 3, 1), (128, 64, 6, 1, 1),
-               (40, 10, 8, 2, 2)]
+               (40, 10, 8, 2, 2),
+               (64, 8, 64, 1, 4)]  # 256 planes: a full grid keeps one sweep per launch
 
 
+def slab_kernel(shape):
+    """The slab launch the library picks: two sweeps per launch while the
+    lattices have fewer planes than the device has compute units."""
+    Lx, Ly, Lz, S, R = shape
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    return "k_micsa_slab2" if S * R * Lz < cus else "k_micsa_slab"
+
+
+@pytest.mark.parametrize("ahead", [1, 0], ids=["drawn-ahead", "drawn-in-kernel"])
 @pytest.mark.parametrize("shape", SLAB_SHAPES)
-def test_slab_sweep_matches_oracle(shape):
+def test_slab_sweep_matches_oracle(shape, ahead):
     """The one-launch slab sweep (a z plane per work-group, neighbour planes
-    recomputed, refresh drawn in the kernel): minimum sides (one word per
-    row, planes that wrap onto a side of 2), several samples and replicas,
-    ragged words per row, a plane of 1024 words, refresh every sweep and
+    recomputed): minimum sides (one word per row, planes that wrap onto a
+    side of 2), several samples and replicas, ragged words per row, a plane
+    of 1024 words, a grid of one plane per compute unit; refresh levels
+    drawn ahead on the side stream or in the kernel; refresh every sweep and
     every fourth; logged energies, tally and state against the oracle."""
     g, o = pair(*shape, seed=0x51AB)
     g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_SLAB)
-    assert g.kernel_name(M.ALGO_MICSA) == "k_micsa_slab2"
+    g.set_option(M.OPT_DRAW_AHEAD, ahead)
+    assert g.kernel_name(M.ALGO_MICSA) == slab_kernel(shape)
     for P, n in ((1, 5), (4, 13)):
         gs, os_ = scheds(M.SCHED_LINEAR, 2.5, 0.4, 100, P)
         g.set_schedule(gs)
@@ -191,13 +204,15 @@ def test_slab_sweep_matches_oracle(shape):
     same_state(g, o)
 
 
-def test_quench_L64_slab_1000_sweeps():
+@pytest.mark.parametrize("ahead", [1, 0], ids=["drawn-ahead", "drawn-in-kernel"])
+def test_quench_L64_slab_1000_sweeps(ahead):
     """Configuration 2 (L = 64, two replicas, T = 0.7, refresh every 10) on the
-    library's own kernel choice, the slab sweep, for 1000 sweeps in long
-    calls: state, energies, daemon energies, tally and overlap equal the
-    oracle's."""
+    library's own kernel choice, the two-sweep slab launch, for 1000 sweeps in
+    long calls, refresh levels drawn ahead (the default) or in the kernel:
+    state, energies, daemon energies, tally and overlap equal the oracle's."""
     w = W.QUENCH_L64
     g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
+    g.set_option(M.OPT_DRAW_AHEAD, ahead)
     assert g.kernel_name(M.ALGO_MICSA) == "k_micsa_slab2"
     gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
     g.set_schedule(gs)
