@@ -365,8 +365,9 @@ def main() -> int:
     ap.add_argument("--layout", choices=("byte", "bitplane"), default="byte",
                     help="MicSA layout (the baselines always run in the byte layout)")
     ap.add_argument("--tile", default="tune",
-                    help="fused-sweep tile: 'tune' (autotuner, bit-exact gated), 'auto' (library default) "
-                         "or TY,TZ[,PREFETCH[,SWEEPS_PER_PASS]]")
+                    help="launch shape: 'tune' (autotuner, bit-exact gated), 'auto' (library default), "
+                         "TY,TZ[,PREFETCH[,SWEEPS_PER_PASS]] (fused sweep) or library options by name, "
+                         "e.g. OPT_TILE_Y=24,OPT_TILE_Z=16,OPT_MSC_PASS=2")
     ap.add_argument("--algo", choices=("micsa", "walkers"), default="micsa",
                     help="daemons (default) or walkers wandering every timestep (Sec. 2.6)")
     ap.add_argument("--gamma", type=int, default=1, help="daemons (walkers) per site (Sec. 2.8)")
@@ -438,6 +439,13 @@ def main() -> int:
             tile = (best.ty, best.tz, best.prefetch, best.temporal)
             log(f"tile TY={best.ty} TZ={best.tz} prefetch {best.prefetch} sweeps/pass {best.temporal} "
                 f"({best.us_per_sweep:.1f} us/sweep in tuning)")
+    elif args.tile not in ("auto", "tune") and "=" in args.tile:
+        # library options by name, e.g. OPT_TILE_Y=24,OPT_TILE_Z=16,OPT_MSC_PASS=2
+        tile = {k.strip(): int(v) for k, v in (kv.split("=") for kv in args.tile.split(","))}
+        for k in tile:
+            if not (k.startswith("OPT_") and hasattr(M, k)):
+                print(f"--tile: unknown option {k}", file=sys.stderr)
+                return 2
     elif args.tile not in ("auto", "tune"):
         tile = tuple(int(v) for v in args.tile.split(","))
     algo_name = args.algo

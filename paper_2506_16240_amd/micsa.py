@@ -420,8 +420,9 @@ class Pool:
         if st != OK:
             raise MicsaError(st, f"{what}: {lib().micsa_status_string(st).decode()}")
 
-    def submit(self, Lx, Ly, Lz, S, R, seed, sched: Schedule, layout: int = LAYOUT_BYTE, gamma: int = 1) -> int:
-        p = _params(Lx, Ly, Lz, S, R, layout, seed, gamma)
+    def submit(self, Lx, Ly, Lz, S, R, seed, sched: Schedule, layout: int = LAYOUT_BYTE, gamma: int = 1,
+               lane_mode: int = LANES_SAMPLES) -> int:
+        p = _params(Lx, Ly, Lz, S, R, layout, seed, gamma, lane_mode)
         cs, keep = _schedule_struct(sched)
         job = ctypes.c_int64()
         self._check(lib().micsa_pool_submit(self._pool, ctypes.byref(p), ctypes.byref(cs), ctypes.byref(job)),

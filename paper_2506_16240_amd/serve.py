@@ -2,7 +2,8 @@
 
 Jobs are instances of the 3D EA +-J model with L uniform in {8, 16, 32, 64,
 128} and 1..64 replicas of one sample, annealed with MicSA from T = 3.0 to
-0.1 over 2000 sweeps (refresh every 10 sweeps).  Arrivals follow a Poisson
+0.1 over 2000 sweeps (refresh every 10 sweeps), each in the layout
+job_layout() picks for its size.  Arrivals follow a Poisson
 process of the given rate; each arrival is submitted to the pool as soon as
 its time has passed.  The loop calls the pool's step over and over: each
 call admits what fits and enqueues the next `sweeps_per_step` sweeps of
@@ -21,6 +22,8 @@ import numpy as np
 from . import micsa as M
 
 L_CHOICES = (8, 16, 32, 64, 128)
+# L = 64 jobs with at least this many replicas run in the bit-plane layout
+BITPLANE_MIN_REPLICAS = 16
 
 
 def splitmix64(x: int) -> int:
@@ -59,6 +62,29 @@ class JobResult:
         return self.done - self.arrival
 
 
+def job_layout(spec: "JobSpec") -> tuple[int, int]:
+    """(layout, lane mode) a job runs in.  L = 64 jobs of many replicas take
+    the bit-plane layout with lanes = replicas: a word holds one site of up
+    to 64 replicas of the instance, the couplings broadcast to every lane
+    (multispin coding of replicas, Sec. 2.5).  There it beats the byte
+    slab sweep from about 16 replicas on (1.2x at 20, 1.8x at 37, 2.4x at
+    53 on one MI355X), and loses below.  Every other job keeps the byte
+    layout: the batched resident launch for L <= 32, the multispin planes
+    for L = 128 (faster than bit planes at every replica count there).
+    Results do not depend on the layout."""
+    if spec.L == 64 and spec.R >= BITPLANE_MIN_REPLICAS:
+        return M.LAYOUT_BITPLANE, M.LANES_REPLICAS
+    return M.LAYOUT_BYTE, M.LANES_SAMPLES
+
+
+def submit(pool: "M.Pool", spec: "JobSpec") -> int:
+    """Submit a job in the layout job_layout() picks."""
+    layout, lanes = job_layout(spec)
+    return pool.submit(spec.L, spec.L, spec.L, 1, spec.R, spec.seed,
+                       M.Schedule(M.SCHED_LINEAR, spec.T0, spec.T1, spec.n_sweeps, spec.period),
+                       layout=layout, lane_mode=lanes)
+
+
 def job_stream(n_jobs: int, rate: float, seed: int, n_sweeps: int = 2000, L_choices=L_CHOICES,
                max_replicas: int = 64) -> list[tuple[float, JobSpec]]:
     """Poisson arrivals (exponential gaps of mean 1/rate seconds) with random sizes."""
@@ -86,8 +112,7 @@ def serve(stream: list[tuple[float, JobSpec]], hbm_budget: int, sweeps_per_step:
         now = time.perf_counter() - t0
         while pending and pending[0][0] <= now:
             arr, spec = pending.pop(0)
-            job = pool.submit(spec.L, spec.L, spec.L, 1, spec.R, spec.seed,
-                              M.Schedule(M.SCHED_LINEAR, spec.T0, spec.T1, spec.n_sweeps, spec.period))
+            job = submit(pool, spec)
             results[job] = JobResult(spec, arr)
             live.add(job)
         if not live:

@@ -65,23 +65,37 @@ def _run_alone(spec, sweeps_per_step):
 
 TARGETS = [SV.JobSpec(16, 3, 0xC0FFEE, n_sweeps=300),   # batched resident launch
            SV.JobSpec(64, 2, 0xC0FFEF, n_sweeps=120),   # own stream, slab sweep
-           SV.JobSpec(128, 1, 0xC0FFF0, n_sweeps=60)]   # own stream, multispin planes
+           SV.JobSpec(128, 1, 0xC0FFF0, n_sweeps=60),   # own stream, multispin planes
+           SV.JobSpec(64, 20, 0xC0FFF1, n_sweeps=40)]   # own stream, bit planes (lanes = replicas)
+
+
+def test_job_layout_policy():
+    """L = 64 jobs of BITPLANE_MIN_REPLICAS or more replicas take the bit
+    planes with lanes = replicas; every other job the byte layout."""
+    for L in SV.L_CHOICES:
+        for R in (1, SV.BITPLANE_MIN_REPLICAS - 1, SV.BITPLANE_MIN_REPLICAS, 64):
+            layout, lanes = SV.job_layout(SV.JobSpec(L, R, 1))
+            if L == 64 and R >= SV.BITPLANE_MIN_REPLICAS:
+                assert (layout, lanes) == (M.LAYOUT_BITPLANE, M.LANES_REPLICAS)
+            else:
+                assert (layout, lanes) == (M.LAYOUT_BYTE, M.LANES_SAMPLES)
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("target", TARGETS, ids=["L16-batched", "L64-slab", "L128-multispin"])
+@pytest.mark.parametrize("target", TARGETS, ids=["L16-batched", "L64-slab", "L128-multispin", "L64-bitplane"])
 def test_job_alone_equals_job_in_the_mix(target):
-    """A job's final state is bit-identical alone and among other jobs that
-    arrive before and after it, of other sizes and kernels, running
-    concurrently on their own streams and in the batched launch; and it
-    equals the oracle's trajectory."""
+    """A job's final state is bit-identical alone (byte layout) and among
+    other jobs that arrive before and after it, of other sizes, kernels and
+    layouts, running concurrently on their own streams and in the batched
+    launch, each in the layout the serving driver picks (the L = 64 target
+    of 20 replicas in bit planes: layouts agree bit for bit); and it equals
+    the oracle's trajectory."""
     alone = _run_alone(target, 37)
     others = [SV.JobSpec(8, 5, 11, n_sweeps=120), SV.JobSpec(32, 2, 12, n_sweeps=400),
               SV.JobSpec(64, 1, 13, n_sweeps=90), SV.JobSpec(16, 7, 14, n_sweeps=250),
-              SV.JobSpec(128, 1, 15, n_sweeps=20)]
+              SV.JobSpec(128, 1, 15, n_sweeps=20), SV.JobSpec(64, 17, 16, n_sweeps=30)]
     pool = M.Pool(1 << 34)
-    sub = lambda s: pool.submit(s.L, s.L, s.L, 1, s.R, s.seed,
-                                M.Schedule(M.SCHED_LINEAR, s.T0, s.T1, s.n_sweeps, s.period))
+    sub = lambda s: SV.submit(pool, s)
     ids = [sub(others[0]), sub(others[1])]
     pool.step(50)
     tid = sub(target)  # arrives while others are running
@@ -91,11 +105,15 @@ def test_job_alone_equals_job_in_the_mix(target):
         pool.step(37)
         steps += 1
         if steps == 2:
-            ids += [sub(others[3]), sub(others[4])]
+            ids += [sub(others[3]), sub(others[4]), sub(others[5])]
     lat = pool.lattice(tid)
-    mixed = (lat.energy(), lat.spins(), lat.daemons(), lat.energy_tally())
+    mixed = (lat.energy(), lat.spins(), lat.daemons())
     for a, b in zip(alone, mixed):
         assert np.array_equal(a, b)
+    assert np.array_equal(alone[3], alone[0])  # the byte job's tally
+    if SV.job_layout(target)[0] == M.LAYOUT_BYTE:
+        assert np.array_equal(lat.energy_tally(), mixed[0])
+    # (the bit-plane per-half sweep of L = 64 keeps no tally)
     # and the job equals the oracle's trajectory
     t = target
     o = O.Lattice(t.L, t.L, t.L, 1, t.R, t.seed)
