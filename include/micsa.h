@@ -265,7 +265,11 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
    tuner and for tests that compare variants).
    MICSA_OPT_SWEEP_KERNEL: MICSA_KERNEL_AUTO (default), MICSA_KERNEL_SIMPLE
      (one launch per half sweep), MICSA_KERNEL_FUSED (one launch per sweep,
-     refresh fused in; needs Lx % 32 == 0), MICSA_KERNEL_RESIDENT (whole
+     refresh fused in; byte layout: needs Lx % 32 == 0; bit-plane layout:
+     the one-launch sweep with its per-lane tally, which AUTO takes where a
+     plane has at most 1024 words and which on larger planes runs in row
+     tiles only on this request, the per-half kernels being faster there),
+     MICSA_KERNEL_RESIDENT (whole
      lattice in LDS for many sweeps per launch; byte layout, N <= 102400),
      MICSA_KERNEL_MULTISPIN (MicSA with daemons, gamma = 1, Lx % 128 == 0:
      multispin coding, Sec. 2.5 -- a sweep call packs the state into bit

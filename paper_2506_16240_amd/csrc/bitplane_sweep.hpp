@@ -45,6 +45,8 @@ struct BpTile {
     int32_t TZ;   // planes a work-group owns (divides Lz)
     int32_t ntz;  // Lz / TZ
     int32_t P;    // words of one parity per plane = Ly * Kx
+    int32_t TY;   // kb_sweep_rows: rows a work-group owns (the last tile along y what is left of Ly)
+    int32_t nty;  // kb_sweep_rows: tiles along y
 };
 
 constexpr int kBpLanes = 1024;  // largest work-group
@@ -310,6 +312,205 @@ __global__ __launch_bounds__(TZ == 1 ? 1024 : 512) void kb_sweep(GeomB gb, BpTil
             int s, r;
             if (dE != 0 && bp_lattice(gb, wl, (int)threadIdx.x, s, r))
                 atomicAdd(&tally[((int64_t)s * g.R + r) * kSlots + (t % kSlots)], (unsigned long long)dE);
+        }
+    }
+}
+
+
+// Planes of more than 1024 words: a work-group owns TY rows (f.TY; the last
+// tile along y what is left of Ly) of one plane of one word lattice, with two
+// ring rows on each side.  The old odd spins are staged on the TY + 4 rows
+// of planes z - 2 .. z + 2; the even half runs on planes z - 1 .. z + 1 and
+// on the TY + 2 rows whose results the odd half reads (ring rows and planes
+// recomputed from the same old values as their owners, so no work-group
+// waits for another); the odd half runs on the owned rows of plane z.  One
+// thread per word position of the TY + 4 rows; every global load is issued
+// at the start, as in kb_sweep.  Lanes of a ragged last tile beyond its rows
+// load their tile's last row and store nothing.
+template <bool TALLY>
+__global__ __launch_bounds__(1024) void kb_sweep_rows(GeomB gb, BpTile f, const uint64_t* __restrict__ spin_in,
+                                                      const uint64_t* __restrict__ d0_in,
+                                                      const uint64_t* __restrict__ d1_in,
+                                                      const uint64_t* __restrict__ Jw,
+                                                      uint64_t* __restrict__ spin_out,
+                                                      uint64_t* __restrict__ d0_out,
+                                                      uint64_t* __restrict__ d1_out,
+                                                      unsigned long long* __restrict__ tally)
+{
+    extern __shared__ uint64_t lds_bp[];
+    const Geom& g = gb.g;
+    // one-dimensional grid over (word lattice, plane, y tile), y tiles
+    // fastest; XCD x takes a contiguous run of tiles when their count divides by 8
+    const int ntiles = gridDim.x;
+    int t = blockIdx.x;
+    if ((ntiles & 7) == 0) t = (t & 7) * (ntiles >> 3) + (t >> 3);
+    const int per_wl = f.ntz * f.nty;
+    const int wl = t / per_wl;
+    const int rem = t - wl * per_wl;
+    const int z = rem / f.nty, ty = rem - z * f.nty;
+    const int y0 = ty * f.TY;
+    const int own = min(f.TY, g.Ly - y0);
+    const int Kx = g.Kx;
+    const int PT = (f.TY + 4) * Kx;  // words of one LDS plane
+    const int P = f.P;
+    const int64_t Nh = g.Nh;
+    uint64_t* LO = lds_bp;           // old odd spins, planes z - 2 .. z + 2, rows y0 - 2 .. y0 + TY + 1
+    uint64_t* LE = lds_bp + 5 * PT;  // new even spins, planes z - 1 .. z + 1
+    const uint64_t* ev_in = spin_in + (int64_t)wl * 2 * Nh;
+    const uint64_t* od_in = ev_in + Nh;
+    const uint64_t* m0e = d0_in + (int64_t)wl * 2 * Nh;
+    const uint64_t* m1e = d1_in + (int64_t)wl * 2 * Nh;
+    uint64_t* ev_out = spin_out + (int64_t)wl * 2 * Nh;
+    uint64_t* n0e = d0_out + (int64_t)wl * 2 * Nh;
+    uint64_t* n1e = d1_out + (int64_t)wl * 2 * Nh;
+    const uint64_t* J = Jw + (int64_t)bp_cset(gb, wl) * 6 * Nh;
+    auto wrapz = [&](int v) { return v < 0 ? v + g.Lz : (v >= g.Lz ? v - g.Lz : v); };
+    auto wrapy = [&](int v) {
+        v %= g.Ly;
+        return v < 0 ? v + g.Ly : v;
+    };
+    const int pos = threadIdx.x;
+    const int r0 = pos / Kx, k = pos - r0 * Kx;
+    const bool active = r0 < own + 4;
+    const int r = active ? r0 : own + 3;  // tile row
+    const int me = r * Kx + k;
+    const int rup = min(r + 1, own + 3), rdn = max(r - 1, 0);  // in-tile rows r +- 1 (clamped at the ring's edge)
+    const int y = wrapy(y0 - 2 + r), yp = wrapy(y0 - 1 + r), ym = wrapy(y0 - 3 + r);
+    const int kp = k + 1 == Kx ? 0 : k + 1, km = k == 0 ? Kx - 1 : k - 1;
+    const bool own_row = active && r >= 2 && r <= own + 1;
+    const int yw = y * Kx;
+
+    // ---- every load of the sweep
+    uint64_t Od[5];
+#pragma unroll
+    for (int e = 0; e < 5; ++e) Od[e] = od_in[(int64_t)wrapz(z - 2 + e) * P + yw + k];
+    uint64_t Es[3], Ej[3][6], Em0[3], Em1[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int zz = wrapz(z - 1 + e);
+        const int64_t h = (int64_t)zz * P + yw + k;
+        const int q = (y + zz) & 1;
+        const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
+        Es[e] = ev_in[h];
+        Ej[e][0] = J[dA * Nh + h];
+        Ej[e][1] = J[dB * Nh + h];
+        Ej[e][2] = J[kPy * Nh + h];
+        Ej[e][3] = J[kMy * Nh + h];
+        Ej[e][4] = J[kPz * Nh + h];
+        Ej[e][5] = J[kMz * Nh + h];
+        Em0[e] = m0e[h];
+        Em1[e] = m1e[h];
+    }
+    uint64_t Oj[6], Om0, Om1;
+    {
+        // an odd site's coupling is its even neighbour's in the opposite direction
+        const int zp = wrapz(z + 1), zm = wrapz(z - 1);
+        const int64_t h = (int64_t)z * P + yw + k;
+        const int q = (y + z) & 1;
+        const int ks = q ? km : kp;
+        const int dA = q ? kMx : kPx, dB = q ? kPx : kMx;
+        Oj[0] = J[dA * Nh + h];
+        Oj[1] = J[dB * Nh + (int64_t)z * P + yw + ks];
+        Oj[2] = J[kMy * Nh + (int64_t)z * P + yp * Kx + k];
+        Oj[3] = J[kPy * Nh + (int64_t)z * P + ym * Kx + k];
+        Oj[4] = J[kMz * Nh + (int64_t)zp * P + yw + k];
+        Oj[5] = J[kPz * Nh + (int64_t)zm * P + yw + k];
+        Om0 = m0e[Nh + h];
+        Om1 = m1e[Nh + h];
+    }
+
+    // ---- old odd spins of the ring-extended tile into LDS
+    if (active) {
+#pragma unroll
+        for (int e = 0; e < 5; ++e) LO[(size_t)e * PT + me] = Od[e];
+    }
+    __syncthreads();
+
+    uint64_t cnt[kBpPlanes];
+#pragma unroll
+    for (int b = 0; b < kBpPlanes; ++b) cnt[b] = 0;
+
+    // ---- even half on planes z - 1 .. z + 1 (rows 1 .. own + 2 are read by the odd half)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int zz = wrapz(z - 1 + e);
+        const int q = (y + zz) & 1;
+        const int ks = q ? kp : km;
+        const uint64_t* Oz = LO + (size_t)(e + 1) * PT;  // odd plane z - 1 + e
+        const uint64_t S = Es[e];
+        const uint64_t nb[6] = {Oz[me], Oz[r * Kx + ks], Oz[rup * Kx + k], Oz[rdn * Kx + k], (Oz + PT)[me],
+                                (Oz - PT)[me]};
+        const uint64_t a[6] = {xor3(S, nb[0], Ej[e][0]), xor3(S, nb[1], Ej[e][1]), xor3(S, nb[2], Ej[e][2]),
+                               xor3(S, nb[3], Ej[e][3]), xor3(S, nb[4], Ej[e][4]), xor3(S, nb[5], Ej[e][5])};
+        uint64_t M0 = Em0[e], M1 = Em1[e];
+        const uint64_t Sn = bp_move(S, a, M0, M1);
+        if (active) LE[(size_t)e * PT + me] = Sn;
+        if (e == 1 && own_row) {  // the owned plane and rows
+            const int64_t h = (int64_t)z * P + yw + k;
+            ev_out[h] = Sn;
+            n0e[h] = M0;
+            n1e[h] = M1;
+            if (TALLY) vc_word(cnt, Em0[e], Em1[e], M0, M1);
+        }
+    }
+    __syncthreads();
+
+    // ---- odd half on the owned rows of plane z, with the new even spins
+    {
+        const int q = (y + z) & 1;
+        const int ks = q ? km : kp;
+        const uint64_t* Ez = LE + (size_t)PT;  // new even plane z
+        const uint64_t S = Od[2];
+        const uint64_t nb[6] = {Ez[me], Ez[r * Kx + ks], Ez[rup * Kx + k], Ez[rdn * Kx + k], (Ez + PT)[me],
+                                (Ez - PT)[me]};
+        const uint64_t a[6] = {xor3(S, nb[0], Oj[0]), xor3(S, nb[1], Oj[1]), xor3(S, nb[2], Oj[2]),
+                               xor3(S, nb[3], Oj[3]), xor3(S, nb[4], Oj[4]), xor3(S, nb[5], Oj[5])};
+        uint64_t M0 = Om0, M1 = Om1;
+        const uint64_t Sn = bp_move(S, a, M0, M1);
+        if (own_row) {
+            const int64_t h = (int64_t)z * P + yw + k;
+            ev_out[Nh + h] = Sn;
+            n0e[Nh + h] = M0;
+            n1e[Nh + h] = M1;
+            if (TALLY) vc_word(cnt, Om0, Om1, M0, M1);
+        }
+    }
+
+    if (TALLY) {
+        // per-lane tally as in kb_sweep: DPP reduction of the vertical
+        // counters into lane 63, each lane's count, the waves' counts in LDS
+        constexpr int NW = kBpPlanes + 6;
+        uint64_t c[NW];
+#pragma unroll
+        for (int b = 0; b < NW; ++b) c[b] = b < kBpPlanes ? cnt[b] : 0;
+        vc_dpp_level<0xB1, 0xF, kBpPlanes + 1>(c);
+        vc_dpp_level<0x4E, 0xF, kBpPlanes + 2>(c);
+        vc_dpp_level<0x124, 0xF, kBpPlanes + 3>(c);
+        vc_dpp_level<0x128, 0xF, kBpPlanes + 4>(c);
+        vc_dpp_level<0x142, 0xA, kBpPlanes + 5>(c);
+        vc_dpp_level<0x143, 0xC, kBpPlanes + 6>(c);
+        const int lane = threadIdx.x & 63;
+        long long mine = 0;
+#pragma unroll
+        for (int b = 0; b < NW; ++b) {
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)c[b], 63);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(c[b] >> 32), 63);
+            const uint32_t bit = lane < 32 ? (lo >> lane) & 1u : (hi >> (lane - 32)) & 1u;
+            mine += (long long)bit << b;
+        }
+        __syncthreads();  // LDS planes are no longer read
+        long long* part = reinterpret_cast<long long*>(lds_bp);
+        const int wave = threadIdx.x >> 6, nwaves = (blockDim.x + 63) >> 6;
+        part[wave * 64 + lane] = mine;
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            long long sum = 0;
+            for (int w = 0; w < nwaves; ++w) sum += part[w * 64 + threadIdx.x];
+            // every lane counted m + (3 - m') over the 2 own Kx words the group owns
+            const long long dE = 4 * (sum - 3ll * 2 * own * Kx);
+            int s, rr;
+            if (dE != 0 && bp_lattice(gb, wl, (int)threadIdx.x, s, rr))
+                atomicAdd(&tally[((int64_t)s * g.R + rr) * kSlots + (t % kSlots)], (unsigned long long)dE);
         }
     }
 }

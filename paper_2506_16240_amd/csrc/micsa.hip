@@ -301,25 +301,58 @@ struct BpLaunch {
 BpLaunch bp_launch(const micsa_ctx* c)
 {
     BpLaunch b{};
-    const int P = c->p.Ly * (c->p.Lx / 2);
+    const int Kx = c->p.Lx / 2;
+    const int P = c->p.Ly * Kx;
+    if (P > 1024) {
+        // kb_sweep_rows: tiles of TY rows plus two ring rows on each side, a
+        // word position per thread; TY keeps the rows computed per plane
+        // (nty (TY + 4)) smallest, the larger TY on ties
+        const int tymax = std::min(1024 / Kx - 4, c->p.Ly);
+        int best = 0;
+        int64_t cost = 0;
+        for (int ty = 1; ty <= tymax; ++ty) {
+            const int64_t n = (c->p.Ly + ty - 1) / ty, w = n * (ty + 4);
+            if (!best || w <= cost) {
+                best = ty;
+                cost = w;
+            }
+        }
+        if (c->tile_y > 0) best = std::min(c->tile_y, tymax);
+        const int TY = std::max(best, 1);
+        b.f = BpTile{1, c->p.Lz, P, TY, (c->p.Ly + TY - 1) / TY};
+        const int PT = (TY + 4) * Kx;
+        b.block = (unsigned)((PT + 63) / 64 * 64);
+        b.lds = std::max((size_t)8 * PT * 8, (size_t)(b.block / 64) * 64 * 8);
+        return b;
+    }
     const int TZ = c->tile_z == 2 && c->p.Lz % 2 == 0 && P <= 512 ? 2 : 1;
-    b.f = BpTile{TZ, c->p.Lz / TZ, P};
+    b.f = BpTile{TZ, c->p.Lz / TZ, P, c->p.Ly, 1};
     b.block = (unsigned)((P + 63) / 64 * 64);
     const size_t planes = (size_t)(2 * TZ + 6) * P * 8, part = (size_t)(b.block / 64) * 64 * 8;
     b.lds = std::max(planes, part);
     return b;
 }
 
+bool bp_rows(const BpLaunch& b) { return b.f.nty > 1 || b.f.P > 1024; }
+
 // The one-launch sweep fits: a word position per thread (at most 1024 per
-// work-group) and LDS within a work-group's 160 KB.
+// work-group: a whole plane, or TY + 4 >= 5 rows of one) and LDS within a
+// work-group's 160 KB.
 bool bp_fits(const micsa_ctx* c, const BpLaunch& b)
 {
+    if (bp_rows(b)) return 1024 / (c->p.Lx / 2) - 4 >= 1 && b.lds <= 160 * 1024;
     return b.f.P <= (b.f.TZ == 1 ? 1024 : 512) && b.lds <= 160 * 1024;
 }
 
+// AUTO takes the one-launch sweep where a plane fits a work-group; on larger
+// planes its row tiles (kb_sweep_rows) run only on request (KERNEL_FUSED):
+// there the per-half kernels are faster (8.6 against 11.9 us per sweep at
+// L = 64 on one MI355X), but keep no per-lane tally.
 bool bp_one_launch(const micsa_ctx* c)
 {
-    return c->bit && c->kernel_opt != MICSA_KERNEL_SIMPLE && bp_fits(c, bp_launch(c));
+    if (!c->bit || c->kernel_opt == MICSA_KERNEL_SIMPLE) return false;
+    const BpLaunch b = bp_launch(c);
+    return bp_fits(c, b) && (!bp_rows(b) || c->kernel_opt == MICSA_KERNEL_FUSED);
 }
 
 // One-launch bit-plane sweep; with drawn the levels are read from the drawn
@@ -341,11 +374,11 @@ int launch_bp_sweep(micsa_ctx* c, bool drawn)
             return fail(c, MICSA_ENOMEM, "bit-plane sweep buffers");
         }
     }
-    const auto kern = b.f.TZ == 2 ? kb_sweep<true, 2> : kb_sweep<true, 1>;
+    const auto kern = bp_rows(b) ? kb_sweep_rows<true> : b.f.TZ == 2 ? kb_sweep<true, 2> : kb_sweep<true, 1>;
     if (b.lds > 64 * 1024 &&
         hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.lds) != hipSuccess)
         return fail(c, MICSA_EHIP, "kb_sweep LDS attribute");
-    const dim3 grid((unsigned)(b.f.ntz * word_lattices(c)));
+    const dim3 grid((unsigned)(b.f.ntz * b.f.nty * word_lattices(c)));
     {
         TimedLaunch t(c, kTimeSweep);
         kern<<<grid, b.block, b.lds, c->stream>>>(geomb(c), b.f, c->bspin, drawn ? c->bdr0 : c->bdm0,
@@ -2531,7 +2564,10 @@ int micsa_get_timing(micsa_ctx* ctx, int32_t kind, double* total_ms, int64_t* la
 const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
 {
     if (ctx && ctx->bit)
-        return algo == MICSA_ALGO_MICSA ? (bp_one_launch(ctx) && !use_graph(ctx) ? "kb_sweep" : "kb_micsa_half") : "";
+        return algo == MICSA_ALGO_MICSA
+                   ? (bp_one_launch(ctx) && !use_graph(ctx) ? (bp_rows(bp_launch(ctx)) ? "kb_sweep_rows" : "kb_sweep")
+                                                            : "kb_micsa_half")
+                   : "";
     if (ctx && algo == MICSA_ALGO_MICSA && use_msc(ctx))
         return msc_one_launch(ctx) ? "k_msc_sweep" : "k_msc_half";
     // walkers on the fused sweeps wander on the next sweep's loads
@@ -2567,7 +2603,9 @@ int micsa_set_option(micsa_ctx* ctx, int32_t option, int64_t value)
             return fail(ctx, MICSA_EINVAL, "the multispin sweep needs the byte layout, gamma = 1 and Lx % 128 == 0");
         if (value == MICSA_KERNEL_RESIDENT && !resident_eligible(ctx))
             return fail(ctx, MICSA_EINVAL, "the resident sweep needs a byte-layout lattice of at most 102400 sites");
-        if (value == MICSA_KERNEL_FUSED && !fused_eligible(ctx))
+        if (value == MICSA_KERNEL_FUSED && ctx->bit && !bp_fits(ctx, bp_launch(ctx)))
+            return fail(ctx, MICSA_EINVAL, "the one-launch bit-plane sweep needs five rows of a plane in a work-group");
+        if (value == MICSA_KERNEL_FUSED && !ctx->bit && !fused_eligible(ctx))
             return fail(ctx, MICSA_EINVAL, "the fused sweep needs Lx % 32 == 0");
         ctx->kernel_opt = (int32_t)value;
         return MICSA_OK;

@@ -164,14 +164,17 @@ def main() -> int:
     ap.add_argument("--sweeps", type=int, default=2000)
     ap.add_argument("--sweeps-per-step", type=int, default=100)
     ap.add_argument("--hbm-gib", type=float, default=64.0)
+    ap.add_argument("--capacity-runs", type=int, default=3, help="capacity is the median of this many runs")
     args = ap.parse_args()
     budget = int(args.hbm_gib * (1 << 30))
     # the job sizes do not depend on the arrival rate (the gaps scale one
     # exponential draw each), so every load level serves this same mix
     specs = [spec for _, spec in job_stream(args.jobs, 1.0, args.seed, args.sweeps)]
-    cap = capacity(specs, budget, args.sweeps_per_step)
+    runs = [capacity(specs, budget, args.sweeps_per_step) for _ in range(max(1, args.capacity_runs))]
+    cap = float(np.median(runs))
     mean_updates = float(np.mean([s.updates for s in specs]))
-    print(json.dumps({"capacity_updates_per_ns": round(cap, 1), "mean_job_updates": mean_updates}), flush=True)
+    print(json.dumps({"capacity_updates_per_ns": round(cap, 1), "capacity_runs": [round(r, 1) for r in runs],
+                      "mean_job_updates": mean_updates}), flush=True)
     for load in (float(x) for x in args.loads.split(",")):
         rate = load * cap * 1e9 / mean_updates  # jobs per second
         res, m = serve(job_stream(args.jobs, rate, args.seed, args.sweeps), budget, args.sweeps_per_step)

@@ -762,6 +762,43 @@ def test_bitplane_one_launch_tiles_match_oracle(shape, tz):
     assert np.array_equal(g.daemon_energy(), o.daemon_energy())
 
 
+# planes of more than 1024 words: tiles of rows with two ring rows a side
+ROW_TILE_SHAPES = [
+    ((72, 30, 4, 65, 1), M.LANES_SAMPLES),    # 1080 words a plane: two tiles of 15 rows, two lane groups
+    ((128, 18, 2, 3, 2), M.LANES_SAMPLES),    # 64 words a row, planes that wrap onto a side of 2
+    ((64, 64, 6, 1, 20), M.LANES_REPLICAS),   # serving-size rows: tiles of 22, 22 and 20 rows
+    ((64, 40, 4, 70, 1), M.LANES_SAMPLES),
+]
+
+
+@pytest.mark.parametrize("shape,lanes", ROW_TILE_SHAPES)
+def test_bitplane_row_tiles_match_oracle(shape, lanes):
+    """The one-launch bit-plane sweep on planes too large for one
+    work-group (kb_sweep_rows, on request): refreshes every 4 sweeps, calls that split
+    a refresh period, logged energies, per-lane tally and state against the
+    oracle, in both lane modes."""
+    Lx, Ly, Lz, S, R = shape
+    g = M.Lattice(Lx, Ly, Lz, S, R, 0x7011, layout=M.LAYOUT_BITPLANE, lane_mode=lanes)
+    o = O.Lattice(Lx, Ly, Lz, S, R, 0x7011)
+    assert g.kernel_name(M.ALGO_MICSA) == "kb_micsa_half"  # the automatic choice on such planes
+    g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)
+    assert g.kernel_name(M.ALGO_MICSA) == "kb_sweep_rows"
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.4, 0.3, 40, 4)
+    g.set_schedule(gs)
+    for m in (9, 1, 6):
+        g.sweep(M.ALGO_MICSA, m)
+        o.run(O.ALGO_MICSA, os_, m, 0)
+        same_state(g, o)
+    Eg, Dg = g.sweep_logged(M.ALGO_MICSA, 6, 2)
+    Eo, Do = o.run(O.ALGO_MICSA, os_, 6, 2)
+    assert np.array_equal(Eg, Eo) and np.array_equal(Dg, Do)
+    same_state(g, o)
+    E = o.energy()
+    assert np.array_equal(g.energy(), E) and np.array_equal(g.energy_tally(), E)
+    assert np.array_equal(g.daemon_energy(), o.daemon_energy())
+    g.close()
+
+
 def test_bitplane_batched_L32_shape():
     """256 samples x 2 replicas of L = 32 bit-packed in 4 lane groups, the
     launch the benchmark times (no option): 21 sweeps in one call (refreshes
