@@ -874,9 +874,13 @@ def test_bitplane_error_paths():
     assert e.value.status == M.ESTATE
     g.write_spins(g.spins())
     assert np.array_equal(g.energy_tally(), g.energy())
-    with pytest.raises(M.MicsaError) as e:
-        g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)
-    assert e.value.status == M.EINVAL
+    # KERNEL_FUSED asks for the one-launch sweep; the byte-layout kernels are refused
+    g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_FUSED)
+    assert g.kernel_name(M.ALGO_MICSA) == "kb_sweep"
+    for bad in (M.KERNEL_MULTISPIN, M.KERNEL_SLAB, M.KERNEL_RESIDENT):
+        with pytest.raises(M.MicsaError) as e:
+            g.set_option(M.OPT_SWEEP_KERNEL, bad)
+        assert e.value.status == M.EINVAL
 
 
 # ------------------------------------------------ gamma daemons / walkers
