@@ -105,23 +105,31 @@ __global__ void k_init_couplings(Geom g, uint8_t* __restrict__ spin)
 // Thread per 8 consecutive natural sites i0 .. i0+7 (same row since Lx % 8 == 0):
 // two Philox calls give 8 draws; the 4 sites of each parity land in one word.
 template <typename F>
+__device__ __forceinline__ void split8q(int q, const u32x4& a, const u32x4& b, F&& val, uint32_t& w_even,
+                                        uint32_t& w_odd)
+{
+    // q = (x0 + y + z) & 1 of the first of the eight sites: site t has the
+    // parity of q + t, so sites 0, 2, 4, 6 form one word and 1, 3, 5, 7 the
+    // other (values selected, not output addresses)
+    const uint32_t d[8] = {a.v0, a.v1, a.v2, a.v3, b.v0, b.v1, b.v2, b.v3};
+    uint32_t first = 0, second = 0;
+#pragma unroll
+    for (int t = 0; t < 8; t += 2) {
+        first |= val(d[t]) << (8 * (t >> 1));
+        second |= val(d[t + 1]) << (8 * (t >> 1));
+    }
+    w_even = q ? second : first;
+    w_odd = q ? first : second;
+}
+
+template <class F>
 __device__ __forceinline__ void split8(const Geom& g, int64_t i0, const u32x4& a, const u32x4& b, F&& val,
                                        uint32_t& w_even, uint32_t& w_odd)
 {
     const int x0 = (int)(i0 % g.Lx);
     const int64_t row = i0 / g.Lx;
     const int y = (int)(row % g.Ly), z = (int)(row / g.Ly);
-    const uint32_t d[8] = {a.v0, a.v1, a.v2, a.v3, b.v0, b.v1, b.v2, b.v3};
-    w_even = 0;
-    w_odd = 0;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const uint32_t v = val(d[t]);
-        if (((x0 + t + y + z) & 1) == 0)
-            w_even |= v << (8 * (t >> 1));
-        else
-            w_odd |= v << (8 * (t >> 1));
-    }
+    split8q((x0 + y + z) & 1, a, b, val, w_even, w_odd);
 }
 
 __global__ void k_init_spins(Geom g, uint8_t* __restrict__ spin)

@@ -119,7 +119,8 @@ __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab(Geom g, const uint8_t
             const u32x4 a = philox10((uint32_t)(i0 >> 2), rho, (uint32_t)r, sw, g.key0, g.key1);
             const u32x4 b = philox10((uint32_t)(i0 >> 2) + 1u, rho, (uint32_t)r, sw, g.key0, g.key1);
             uint32_t we, wo;
-            split8(g, i0, a, b, [&](uint32_t u) { return daemon_level(u, th); }, we, wo);
+            // sites 8w .. 8w + 7 start at x = 8 (w mod Lx / 8), an even x
+            split8q((y + wrapz(z0 - 1 + e)) & 1, a, b, [&](uint32_t u) { return daemon_level(u, th); }, we, wo);
             Me[e] = we;
             if (e == 1) Mo = wo;
         }
@@ -244,7 +245,8 @@ __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab2(Geom g, const uint8_
         const int64_t i0 = 8 * ((int64_t)wrapz(zz) * P + pq);
         const u32x4 a = philox10((uint32_t)(i0 >> 2), f.rho, (uint32_t)r, sw, g.key0, g.key1);
         const u32x4 b = philox10((uint32_t)(i0 >> 2) + 1u, f.rho, (uint32_t)r, sw, g.key0, g.key1);
-        split8(g, i0, a, b, [&](uint32_t u) { return daemon_level(u, f.th); }, we, wo);
+        // sites 8w .. 8w + 7 start at x = 8 (w mod Lx / 8), an even x
+        split8q((y + wrapz(zz)) & 1, a, b, [&](uint32_t u) { return daemon_level(u, f.th); }, we, wo);
     };
 
     // ---- loads (and the draws of sweep A)
@@ -267,15 +269,6 @@ __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab2(Geom g, const uint8_
             draw(ra, z0 - 3 + e, we, wo);
             Me[e] = we;
             if (e >= 1 && e <= 5) Mo[e - 1] = wo;
-        }
-    }
-    if (DRAW) {  // while the loads are in flight
-        uint32_t we, wo;
-        draw(rn, z0, we, wo);
-        if (live) {
-            const int64_t w = (int64_t)z0 * P + pos;
-            reinterpret_cast<uint32_t*>(dnext + (int64_t)l * 2 * Nh)[w] = we;
-            reinterpret_cast<uint32_t*>(dnext + ((int64_t)l * 2 + 1) * Nh)[w] = wo;
         }
     }
     if (live) {
@@ -361,6 +354,15 @@ __global__ __launch_bounds__(kSlabLanes) void k_micsa_slab2(Geom g, const uint8_
             de_out[w] = Mb1;
             od_out[w] = W0 ^ S ^ S0;
             do_out[w] = M;
+        }
+    }
+    if (DRAW) {  // last, when the registers of the four halves are free
+        uint32_t we, wo;
+        draw(rn, z0, we, wo);
+        if (live) {
+            const int64_t w = (int64_t)z0 * P + pos;
+            reinterpret_cast<uint32_t*>(dnext + (int64_t)l * 2 * Nh)[w] = we;
+            reinterpret_cast<uint32_t*>(dnext + ((int64_t)l * 2 + 1) * Nh)[w] = wo;
         }
     }
     block_add(tally + (int64_t)l * kSlots, live ? dE : 0);  // idle lanes repeat word 0's moves
