@@ -274,9 +274,12 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      MICSA_KERNEL_MULTISPIN (MicSA with daemons, gamma = 1, Lx % 128 == 0:
      multispin coding, Sec. 2.5 -- a sweep call packs the state into bit
      planes of 64 sites per word, sweeps there with one launch per sweep
-     (or per half sweep, MICSA_OPT_MSC_FUSED) and the refresh fused in, and
-     unpacks it at the end; walkers (gamma = 1) run on the one-launch form
-     too; the heat bath and Metropolis keep the fused path).
+     (or per half sweep, MICSA_OPT_MSC_FUSED) and the refresh fused in; the
+     planes stay the working state after the call and are unpacked only
+     when an entry point next reads or writes the state or sweeps it on
+     another path, so consecutive multispin calls pack once; walkers
+     (gamma = 1) run on the one-launch form too; the heat bath and
+     Metropolis keep the fused path).
    MICSA_OPT_TILE_Y / MICSA_OPT_TILE_Z: rows / planes per work-group of the
      fused and one-launch multispin sweeps (0 = automatic); TILE_Z is also
      the planes per work-group of the one-launch bit-plane sweep.  TILE_Z must

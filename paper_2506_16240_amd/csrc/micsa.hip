@@ -104,6 +104,13 @@ struct micsa_ctx {
     // walkers on the fused sweep: parity of a forward-X wandering the stored
     // daemons still owe (applied by the next fused sweep on load), or -1
     int32_t pend_wander = -1;
+    // the multispin planes hold the state and the byte arrays are stale (a
+    // multispin call leaves its planes live; whatever reads or writes the
+    // byte arrays unpacks them first)
+    bool msc_live = false;
+    // refresh sweep whose levels the multispin draw planes hold, drawn during
+    // an earlier call (-1: none)
+    int64_t msc_drawn = -1;
     // replayable graphs of kGraphSweeps sweeps for the per-half paths, per algo
     int64_t* d_k = nullptr;  // device copy of the sweep counter
     hipStream_t cap_stream = nullptr;
@@ -137,6 +144,8 @@ int fail(micsa_ctx* c, int status, const std::string& msg)
     if (c) c->err = msg;
     return status;
 }
+
+int settle_msc(micsa_ctx* c);
 
 #define HIP_TRY(ctx, call)                                                                       \
     do {                                                                                         \
@@ -925,6 +934,7 @@ int enqueue_bonds(micsa_ctx* c)
 // Enqueue: dst[l] = from-scratch H^EA of lattice l.
 int enqueue_energy(micsa_ctx* c, unsigned long long* dst)
 {
+    if (int st = settle_msc(c)) return st;
     if (c->bit) return enqueue_lane_count<0>(c, dst, 0, 0);
     int st = zero_slots(c, dst, c->L);
     if (st) return st;
@@ -936,6 +946,7 @@ int enqueue_energy(micsa_ctx* c, unsigned long long* dst)
 
 int enqueue_level_sum(micsa_ctx* c, unsigned long long* dst)
 {
+    if (int st = settle_msc(c)) return st;
     if (c->bit) return enqueue_lane_count<1>(c, dst, 0, 0);
     int st = zero_slots(c, dst, c->L);
     if (st) return st;
@@ -1223,12 +1234,38 @@ int64_t next_refresh(const micsa_ctx* c, int64_t from, int64_t end)
 // refresh drawn inside), unpack.  Walkers (one-launch only): each sweep
 // applies the previous timestep's wandering as it loads the levels; the last
 // one is left owed to the byte layout (pend_wander).
-int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
+MscGeom msc_geom(const micsa_ctx* c)
 {
     MscGeom m;
     m.W = c->p.Lx / 128;
     m.R = c->g.rows;
     m.plane = (int64_t)m.R * m.W;
+    return m;
+}
+
+// Unpack live multispin planes into the byte arrays (before anything reads
+// or writes those).
+int settle_msc(micsa_ctx* c)
+{
+    if (!c->msc_live) return MICSA_OK;
+    const MscGeom m = msc_geom(c);
+    const dim3 cgrid((unsigned)((2 * m.plane + 255) / 256), (unsigned)c->L);
+    {
+        TimedLaunch t(c, kTimeReduce);
+        k_msc_unpack<<<cgrid, 256, 0, c->stream>>>(c->g, m, c->ms, c->md0, c->md1, c->mb, c->spin, c->dem);
+    }
+    const int st = check_launch(c, "k_msc_unpack");
+    if (!st) c->msc_live = false;
+    return st;
+}
+
+// How far past the end of a call the next refresh's levels are drawn ahead
+// (they are ready for the next call if it starts there).
+constexpr int64_t kMscDrawWindow = 1024;
+
+int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
+{
+    const MscGeom m = msc_geom(c);
     const size_t words = (size_t)c->L * 2 * (size_t)m.plane;
     const MscTile f = msc_tile(c);
     const int lanes = (f.TY + 4) * m.W;
@@ -1261,19 +1298,25 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
         HIP_TRY(c, hipEventCreateWithFlags(&c->draw_done, hipEventDisableTiming));
     }
     const dim3 cgrid((unsigned)((2 * m.plane + 255) / 256), (unsigned)c->L);
-    {
-        TimedLaunch t(c, kTimeReduce);
-        k_msc_pack<<<cgrid, 256, 0, c->stream>>>(c->g, m, c->spin, c->dem, c->ms, c->md0, c->md1, c->mb);
+    int st = MICSA_OK;
+    if (!c->msc_live) {
+        {
+            TimedLaunch t(c, kTimeReduce);
+            k_msc_pack<<<cgrid, 256, 0, c->stream>>>(c->g, m, c->spin, c->dem, c->ms, c->md0, c->md1, c->mb);
+        }
+        if ((st = check_launch(c, "k_msc_pack"))) return st;
     }
-    int st = check_launch(c, "k_msc_pack");
-    if (st) return st;
     const dim3 grid((unsigned)((m.plane + 255) / 256), (unsigned)c->L);
     const dim3 sgrid((unsigned)(f.nty * f.ntz), (unsigned)c->L);
     const unsigned sblock = (unsigned)((lanes + 63) / 64 * 64);
     const size_t slds = (size_t)96 * lanes;  // 6 planes x 2 step buffers x 8 B per lane
     const int64_t k_end = c->k + n;
     int64_t drawn = -1;  // refresh sweep whose levels the draw planes hold (or are being drawn)
-    if (ahead && (drawn = next_refresh(c, c->k, k_end)) >= 0 && (st = draw_levels(c, m, drawn))) return st;
+    // the first refresh of the call may have been drawn during the previous one
+    if (ahead && (drawn = next_refresh(c, c->k, k_end)) >= 0 && drawn != c->msc_drawn &&
+        (st = draw_levels(c, m, drawn)))
+        return st;
+    c->msc_drawn = -1;
     for (int64_t i = 0; i < n; ++i) {
         const int64_t k = c->k;
         const bool refresh = is_refresh(k, c->sched.period);
@@ -1382,7 +1425,10 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
                 if (le != hipSuccess) return fail(c, MICSA_EHIP, std::string("k_msc_sweep: ") + hipGetErrorString(le));
             }
             if ((st = check_launch(c, "k_msc_sweep"))) return st;
-            if (use_drawn && (drawn = next_refresh(c, k + 1, k_end)) >= 0 && (st = draw_levels(c, m, drawn)))
+            // the next refresh, in this call or (within the window) a later one
+            if (use_drawn &&
+                (drawn = next_refresh(c, k + 1, std::min(c->sched.n_sweeps, k_end + kMscDrawWindow))) >= 0 &&
+                (st = draw_levels(c, m, drawn)))
                 return st;
             std::swap(c->ms, c->ms_alt);
             std::swap(c->md0, c->md0_alt);
@@ -1414,17 +1460,22 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
         if ((st = check_launch(c, "k_msc_half<1>"))) return st;
         c->k = k + 1;
     }
-    {
-        TimedLaunch t(c, kTimeReduce);
-        k_msc_unpack<<<cgrid, 256, 0, c->stream>>>(c->g, m, c->ms, c->md0, c->md1, c->mb, c->spin, c->dem);
+    // the planes stay live (unpacked when the byte arrays are next needed); a
+    // draw for a refresh after this call is joined into the library stream
+    // here and kept for the call that starts there
+    c->msc_live = true;
+    if (ahead && drawn >= k_end) {
+        HIP_TRY(c, hipStreamWaitEvent(c->stream, c->draw_done, 0));
+        c->msc_drawn = drawn;
     }
-    return check_launch(c, "k_msc_unpack");
+    return MICSA_OK;
 }
 
 // Apply a wandering the daemons still owe (walkers on the fused sweep).
 int settle_wander(micsa_ctx* c)
 {
     if (c->pend_wander < 0) return MICSA_OK;
+    if (int st = settle_msc(c)) return st;  // the wandering kernel moves the byte arrays' levels
     const int p = c->pend_wander;
     c->pend_wander = -1;
     return launch_wander(c, p);
@@ -1446,6 +1497,8 @@ int sweep_impl(micsa_ctx* c, int32_t algo, int64_t n)
         return st0;
     if (walk_msc) return n > 0 ? sweep_msc(c, n, true) : MICSA_OK;
     if (algo == MICSA_ALGO_MICSA && use_msc(c, n)) return n > 0 ? sweep_msc(c, n) : MICSA_OK;
+    // every other path sweeps the byte arrays
+    if ((st0 = settle_msc(c))) return st0;
     if (algo != MICSA_ALGO_WALKERS) {
         if (use_resident(c)) return launch_resident(c, algo, n, nullptr, 0);
         if (use_graph(c) && n >= kGraphSweeps) return sweep_graph(c, algo, n);
@@ -1767,6 +1820,7 @@ int micsa_set_schedule(micsa_ctx* ctx, const micsa_schedule* s)
     ctx->d_mth = d3;
     ctx->sched = std::move(n);
     ctx->sdr_k[0] = ctx->sdr_k[1] = -1;  // levels drawn ahead under the old temperatures
+    ctx->msc_drawn = -1;
     return MICSA_OK;
 }
 
@@ -1988,6 +2042,7 @@ static C4Geom c4_geom(const micsa_ctx* c)
 int micsa_read_c4(micsa_ctx* ctx, int64_t* G)
 {
     if (!ctx || !G) return MICSA_EINVAL;
+    if (int st_ = settle_msc(ctx)) return st_;  // the byte arrays are read or written
     if (ctx->p.n_replicas < 2) return fail(ctx, MICSA_EINVAL, "C4 needs at least two replicas");
     const C4Geom cg = c4_geom(ctx);
     std::vector<int64_t> D;
@@ -2045,6 +2100,7 @@ size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 int micsa_read_c4_static(micsa_ctx* ctx, int64_t* G)
 {
     if (!ctx || !G) return MICSA_EINVAL;
+    if (int st_ = settle_msc(ctx)) return st_;  // the byte arrays are read or written
     if (ctx->p.n_replicas < 2) return fail(ctx, MICSA_EINVAL, "C4 needs at least two replicas");
     const C4Geom cg = c4_geom(ctx);
     const int64_t ent = (int64_t)ctx->p.n_samples * 3 * (cg.rmax + 1);
@@ -2097,6 +2153,7 @@ int micsa_read_c4_static(micsa_ctx* ctx, int64_t* G)
 int micsa_read_xi(micsa_ctx* ctx, double* xi12, double* xi23)
 {
     if (!ctx || !xi12 || !xi23) return MICSA_EINVAL;
+    if (int st_ = settle_msc(ctx)) return st_;  // the byte arrays are read or written
     if (ctx->p.n_replicas < 2) return fail(ctx, MICSA_EINVAL, "xi needs at least two replicas");
     const C4Geom cg = c4_geom(ctx);
     std::vector<int64_t> G((size_t)ctx->p.n_samples * 3 * (cg.rmax + 1));
@@ -2131,6 +2188,7 @@ int micsa_read_xi(micsa_ctx* ctx, double* xi12, double* xi23)
 int micsa_read_overlap(micsa_ctx* ctx, int32_t a, int32_t b, int64_t* Q)
 {
     if (!ctx || !Q) return MICSA_EINVAL;
+    if (int st_ = settle_msc(ctx)) return st_;  // the byte arrays are read or written
     if (a < 0 || b < 0 || a >= ctx->p.n_replicas || b >= ctx->p.n_replicas || a == b)
         return fail(ctx, MICSA_EINVAL, "replica indices out of range or equal");
     const int S = ctx->p.n_samples;
@@ -2202,6 +2260,7 @@ static int read_words(micsa_ctx* ctx, const uint64_t* w0, const uint64_t* w1, ui
 int micsa_read_spins(micsa_ctx* ctx, uint8_t* sigma)
 {
     if (!ctx || !sigma) return MICSA_EINVAL;
+    if (int st_ = settle_msc(ctx)) return st_;  // the byte arrays are read or written
     if (ctx->bit) return read_words(ctx, ctx->bspin, nullptr, sigma);
     return read_state(ctx, ctx->spin, sigma, ctx->L, 1);  // bit 0: even bytes also hold their bonds
 }
@@ -2209,6 +2268,7 @@ int micsa_read_spins(micsa_ctx* ctx, uint8_t* sigma)
 int micsa_read_demons(micsa_ctx* ctx, uint8_t* m)
 {
     if (!ctx || !m) return MICSA_EINVAL;
+    if (int st_ = settle_msc(ctx)) return st_;  // the byte arrays are read or written
     if (ctx->bit) return read_words(ctx, ctx->bdm0, ctx->bdm1, m);
     const int st = settle_wander(ctx);
     if (st) return st;
@@ -2218,6 +2278,7 @@ int micsa_read_demons(micsa_ctx* ctx, uint8_t* m)
 int micsa_read_couplings(micsa_ctx* ctx, uint8_t* j)
 {
     if (!ctx || !j) return MICSA_EINVAL;
+    if (int st_ = settle_msc(ctx)) return st_;  // the byte arrays are read or written
     const Geom& g = ctx->g;
     const int S = ctx->p.n_samples;
     std::vector<uint8_t> jbytes;
@@ -2311,6 +2372,7 @@ static int write_words(micsa_ctx* ctx, uint64_t* w0, uint64_t* w1, const uint8_t
 int micsa_write_spins(micsa_ctx* ctx, const uint8_t* sigma)
 {
     if (!ctx || !sigma) return MICSA_EINVAL;
+    if (int st_ = settle_msc(ctx)) return st_;  // the byte arrays are read or written
     int st = ctx->bit ? write_words(ctx, ctx->bspin, nullptr, sigma, 1) : write_state(ctx, ctx->spin, sigma, 1, ctx->L);
     if (!st && !ctx->bit) st = enqueue_bonds(ctx);  // the written bytes hold spins only: restore the bond bits
     if (st) return st;
@@ -2324,6 +2386,7 @@ int micsa_write_spins(micsa_ctx* ctx, const uint8_t* sigma)
 int micsa_write_demons(micsa_ctx* ctx, const uint8_t* m)
 {
     if (!ctx || !m) return MICSA_EINVAL;
+    if (int st_ = settle_msc(ctx)) return st_;  // the byte arrays are read or written
     if (ctx->bit) return write_words(ctx, ctx->bdm0, ctx->bdm1, m, 3);
     const int st = write_state(ctx, ctx->dem, m, 3, (int64_t)ctx->L * ctx->gamma);
     if (!st) ctx->pend_wander = -1;  // the written daemons are where they are
@@ -2378,6 +2441,7 @@ bool same_params(const micsa_params& a, const micsa_params& b)
 int micsa_save(micsa_ctx* ctx, void* buf, size_t* len)
 {
     if (!ctx || !len) return MICSA_EINVAL;
+    if (int st_ = settle_msc(ctx)) return st_;  // the byte arrays are read or written
     const int64_t T_len = ctx->sched.set ? (int64_t)ctx->sched.table.size() : 0;
     const size_t total = ck_bytes(ctx, T_len);
     if (!buf) {
@@ -2432,6 +2496,7 @@ int micsa_save(micsa_ctx* ctx, void* buf, size_t* len)
 int micsa_load(micsa_ctx* ctx, const void* buf, size_t len)
 {
     if (!ctx) return MICSA_EINVAL;
+    if (int st_ = settle_msc(ctx)) return st_;  // the byte arrays are read or written
     if (!buf) return fail(ctx, MICSA_EINVAL, "null checkpoint");
     const uint8_t* in = static_cast<const uint8_t*>(buf);
     CkHeader h;
@@ -2478,6 +2543,7 @@ int micsa_load(micsa_ctx* ctx, const void* buf, size_t len)
     } else {
         ctx->sched = Schedule{};
         ctx->sdr_k[0] = ctx->sdr_k[1] = -1;
+        ctx->msc_drawn = -1;
     }
     if ((st = micsa_write_spins(ctx, spins))) return st;
     if ((st = micsa_write_demons(ctx, dems))) return st;

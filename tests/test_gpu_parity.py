@@ -445,6 +445,63 @@ def test_multispin_matches_oracle(shape, fused, ahead):
     same_state(g, o)
 
 
+@pytest.mark.parametrize("ahead", [1, 0], ids=["drawn-ahead", "drawn-in-sweep"])
+def test_multispin_planes_live_between_calls(ahead):
+    """A multispin call leaves its planes live and (with the draw ahead) the
+    levels of the next call's first refresh drawn: calls that end between
+    refreshes and start at a drawn one, reads between calls, a heat-bath
+    call, a short call on the byte path, walkers, a schedule change (the
+    drawn levels are dropped), a checkpoint into a fresh context, the
+    written state of write_spins; every state against the oracle."""
+    shape = (256, 6, 4, 1, 2)
+    g, o = pair(*shape, seed=0x11FE)
+    g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_MULTISPIN)
+    g.set_option(M.OPT_DRAW_AHEAD, ahead)
+    gs, os_ = scheds(M.SCHED_LINEAR, 2.6, 0.3, 200, 5)
+    g.set_schedule(gs)
+
+    def both(algo, n):
+        g.sweep(algo, n)
+        o.run(algo, os_, n, 0)
+
+    both(M.ALGO_MICSA, 12)  # ends between refreshes; the refresh at 15 is drawn ahead
+    both(M.ALGO_MICSA, 8)   # starts at 12, uses it
+    assert np.array_equal(g.energy(), o.energy())
+    both(M.ALGO_MICSA, 10)
+    same_state(g, o)
+    both(M.ALGO_HEATBATH, 2)  # the byte arrays, then the planes packed again
+    both(M.ALGO_MICSA, 9)
+    both(M.ALGO_MICSA, 3)    # a short call
+    both(M.ALGO_MICSA, 16)
+    both(M.ALGO_WALKERS, 12)
+    both(M.ALGO_MICSA, 10)
+    assert np.array_equal(g.energy_tally(), o.energy())
+    same_state(g, o)
+    gs2, os2 = scheds(M.SCHED_LINEAR, 1.9, 0.5, 200, 5)  # other temperatures: drawn levels dropped
+    g.set_schedule(gs2)
+    os_ = os2
+    both(M.ALGO_MICSA, 13)
+    both(M.ALGO_MICSA, 11)
+    image = g.save()
+    h = M.Lattice(*shape, seed=0x11FE)
+    h.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_MULTISPIN)
+    h.load(image)
+    both(M.ALGO_MICSA, 9)
+    h.sweep(M.ALGO_MICSA, 9)
+    for x in (g, h):
+        same_state(x, o)
+        assert np.array_equal(x.energy(), o.energy())
+    spins = o.sigma.copy()
+    spins[0, 0, :7] ^= 1
+    g.write_spins(spins)
+    o.sigma = spins
+    both(M.ALGO_MICSA, 14)
+    same_state(g, o)
+    assert np.array_equal(g.energy_tally(), o.energy())
+    h.close()
+    g.close()
+
+
 @pytest.mark.parametrize("shape", [(128, 4, 4, 1, 1), (256, 6, 4, 1, 2), (384, 4, 6, 2, 1), (512, 50, 4, 1, 1)])
 def test_multispin_walkers_match_oracle(shape):
     """Walkers (gamma = 1, forward-X wandering after every timestep, Sec.
