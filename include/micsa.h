@@ -125,7 +125,10 @@ const char* micsa_last_error(const micsa_ctx* ctx);
    m = 0 and are drawn at the first refresh point).  hip_stream is a
    hipStream_t (NULL = the null stream) on which every later call enqueues
    its work.  On success *out owns all device memory; on failure *out is
-   NULL and nothing is leaked.
+   NULL and nothing is leaked.  The working buffers of the sweep path the
+   lattice takes by default (the multispin planes, the slab sweep's drawn
+   levels) are allocated here when they fit, else by the first sweep call
+   that needs them.
    Errors: EINVAL (bad sides/counts/layout/gamma), ENOMEM, EHIP. */
 int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out);
 
@@ -327,7 +330,10 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      the daemon levels of each refresh (Sec. 2.3; they depend on the refresh
      index and temperature, not on the state) in a kernel of their own on a
      second stream of the library, while the sweeps before the refresh run;
-     the refresh sweep then reads them.  0 draws them in place: inside the
+     the refresh sweep then reads them (multispin: the first refresh after
+     a call is drawn during it and kept for the call that starts there,
+     until the schedule changes; a refresh at a call's first sweep with no
+     such levels is drawn inside that sweep).  0 draws them in place: inside the
      refresh sweep (multispin), or in a draw kernel just before it on the
      library's stream (bit-plane).  Every draw is joined into the context's
      stream before the call that launched it returns.  Results are

@@ -653,6 +653,23 @@ int64_t next_refresh(const micsa_ctx* c, int64_t from, int64_t end);
 
 constexpr int64_t kSlabDrawWindow = 1024;  // how far ahead a launch looks for the next refresh
 
+// The two buffers of levels drawn ahead for two-sweep slab launches.
+int slab_alloc(micsa_ctx* c)
+{
+    if (c->sdr[0]) return MICSA_OK;
+    const size_t bytes = (size_t)c->L * 2 * (size_t)c->g.Nh;
+    for (auto& q : c->sdr)
+        if (hipMalloc(&q, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            for (auto& f : c->sdr)
+                if (f) (void)hipFree(f);
+            c->sdr[0] = c->sdr[1] = nullptr;
+            return fail(c, MICSA_ENOMEM, "slab drawn levels");
+        }
+    c->sdr_k[0] = c->sdr_k[1] = -1;
+    return MICSA_OK;
+}
+
 // MicSA sweeps k .. k + n - 1 on the slab sweep (gamma = 1): two per launch
 // where slab_pairs() holds, else one.  With OPT_DRAW_AHEAD (default) a
 // two-sweep launch with no refresh of its own also draws the levels of the
@@ -666,18 +683,7 @@ int sweep_slab(micsa_ctx* c, int64_t n)
     const bool pairs = slab_pairs(c);
     const bool ahead = c->draw_ahead != 0 && pairs;
     int st;
-    if (ahead && !c->sdr[0]) {
-        const size_t bytes = (size_t)c->L * 2 * (size_t)c->g.Nh;
-        for (auto& q : c->sdr)
-            if (hipMalloc(&q, bytes) != hipSuccess) {
-                (void)hipGetLastError();
-                for (auto& f : c->sdr)
-                    if (f) (void)hipFree(f);
-                c->sdr[0] = c->sdr[1] = nullptr;
-                return fail(c, MICSA_ENOMEM, "slab drawn levels");
-            }
-        c->sdr_k[0] = c->sdr_k[1] = -1;
-    }
+    if (ahead && (st = slab_alloc(c))) return st;
     while (c->k < k_end) {
         const int64_t k = c->k;
         const bool refresh = is_refresh(k, c->sched.period);
@@ -1259,6 +1265,43 @@ int settle_msc(micsa_ctx* c)
     return st;
 }
 
+// The multispin planes a sweep call needs (the alternates for the one-launch
+// sweep, the drawn levels for the draw ahead) and the draw stream.  A failed
+// allocation frees only what this call allocated (the planes may hold the
+// live state).
+int msc_alloc(micsa_ctx* c, bool one, bool ahead)
+{
+    const MscGeom m = msc_geom(c);
+    const size_t words = (size_t)c->L * 2 * (size_t)m.plane;
+    std::vector<uint64_t**> fresh;
+    auto get = [&](uint64_t** q, size_t n) {
+        if (*q) return true;
+        if (hipMalloc(q, n * 8) != hipSuccess) {
+            *q = nullptr;
+            return false;
+        }
+        fresh.push_back(q);
+        return true;
+    };
+    bool ok = get(&c->ms, words) && get(&c->md0, words) && get(&c->md1, words) && get(&c->mb, words * 3);
+    if (ok && one) ok = get(&c->ms_alt, words) && get(&c->md0_alt, words) && get(&c->md1_alt, words);
+    if (ok && ahead) ok = get(&c->mdr0, words) && get(&c->mdr1, words);
+    if (!ok) {
+        (void)hipGetLastError();
+        for (uint64_t** q : fresh) {
+            (void)hipFree(*q);
+            *q = nullptr;
+        }
+        return fail(c, MICSA_ENOMEM, "multispin planes");
+    }
+    if (ahead && !c->draw_stream) {
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->draw_stream, hipStreamNonBlocking));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->draw_free, hipEventDisableTiming));
+        HIP_TRY(c, hipEventCreateWithFlags(&c->draw_done, hipEventDisableTiming));
+    }
+    return MICSA_OK;
+}
+
 // How far past the end of a call the next refresh's levels are drawn ahead
 // (they are ready for the next call if it starts there).
 constexpr int64_t kMscDrawWindow = 1024;
@@ -1271,32 +1314,8 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
     const int lanes = (f.TY + 4) * m.W;
     const bool one = msc_one_launch(c);
     const bool ahead = one && c->draw_ahead;
-    if (!c->ms || (one && !c->ms_alt) || (ahead && !c->mdr0)) {
-        bool ok = true;
-        for (uint64_t** q : {&c->ms, &c->md0, &c->md1})
-            if (!*q) ok = ok && hipMalloc(q, words * 8) == hipSuccess;
-        if (ok && !c->mb) ok = hipMalloc(&c->mb, words * 3 * 8) == hipSuccess;
-        if (ok && one)
-            for (uint64_t** q : {&c->ms_alt, &c->md0_alt, &c->md1_alt})
-                if (!*q) ok = ok && hipMalloc(q, words * 8) == hipSuccess;
-        if (ok && ahead)
-            for (uint64_t** q : {&c->mdr0, &c->mdr1})
-                if (!*q) ok = ok && hipMalloc(q, words * 8) == hipSuccess;
-        if (!ok) {
-            (void)hipGetLastError();
-            for (uint64_t** q :
-                 {&c->ms, &c->md0, &c->md1, &c->mb, &c->ms_alt, &c->md0_alt, &c->md1_alt, &c->mdr0, &c->mdr1}) {
-                if (*q) (void)hipFree(*q);
-                *q = nullptr;
-            }
-            return fail(c, MICSA_ENOMEM, "multispin planes");
-        }
-    }
-    if (ahead && !c->draw_stream) {
-        HIP_TRY(c, hipStreamCreateWithFlags(&c->draw_stream, hipStreamNonBlocking));
-        HIP_TRY(c, hipEventCreateWithFlags(&c->draw_free, hipEventDisableTiming));
-        HIP_TRY(c, hipEventCreateWithFlags(&c->draw_done, hipEventDisableTiming));
-    }
+    (void)words;
+    if (int st = msc_alloc(c, one, ahead)) return st;
     const dim3 cgrid((unsigned)((2 * m.plane + 255) / 256), (unsigned)c->L);
     int st = MICSA_OK;
     if (!c->msc_live) {
@@ -1312,10 +1331,15 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
     const size_t slds = (size_t)96 * lanes;  // 6 planes x 2 step buffers x 8 B per lane
     const int64_t k_end = c->k + n;
     int64_t drawn = -1;  // refresh sweep whose levels the draw planes hold (or are being drawn)
-    // the first refresh of the call may have been drawn during the previous one
-    if (ahead && (drawn = next_refresh(c, c->k, k_end)) >= 0 && drawn != c->msc_drawn &&
-        (st = draw_levels(c, m, drawn)))
-        return st;
+    // the first refresh of the call may have been drawn during the previous
+    // one; a refresh at the call's first sweep, with no sweep of the call
+    // before it to hide a draw behind, is drawn inside that sweep instead
+    if (ahead && (drawn = next_refresh(c, c->k, k_end)) >= 0 && drawn != c->msc_drawn) {
+        if (drawn == c->k)
+            drawn = -1;
+        else if ((st = draw_levels(c, m, drawn)))
+            return st;
+    }
     c->msc_drawn = -1;
     for (int64_t i = 0; i < n; ++i) {
         const int64_t k = c->k;
@@ -1425,8 +1449,9 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
                 if (le != hipSuccess) return fail(c, MICSA_EHIP, std::string("k_msc_sweep: ") + hipGetErrorString(le));
             }
             if ((st = check_launch(c, "k_msc_sweep"))) return st;
-            // the next refresh, in this call or (within the window) a later one
-            if (use_drawn &&
+            // after a refresh: the next one, in this call or (within the
+            // window) a later one
+            if (refresh && ahead &&
                 (drawn = next_refresh(c, k + 1, std::min(c->sched.n_sweeps, k_end + kMscDrawWindow))) >= 0 &&
                 (st = draw_levels(c, m, drawn)))
                 return st;
@@ -1736,6 +1761,14 @@ int micsa_create(const micsa_params* p, void* hip_stream, micsa_ctx** out)
         free_all(c);
         delete c;
         return st;
+    }
+    // the working buffers of the sweep path the lattice takes by default
+    // (counted in the pool footprint), so that the first sweep call does not
+    // allocate; if they do not fit now, that call tries again
+    if (!c->bit && c->gamma == 1 && msc_eligible(c) && !resident_eligible(c)) {
+        if (msc_alloc(c, true, true) != MICSA_OK) c->err.clear();
+    } else if (use_slab(c) && slab_pairs(c)) {
+        if (slab_alloc(c) != MICSA_OK) c->err.clear();
     }
     *out = c;
     return MICSA_OK;

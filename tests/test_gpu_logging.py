@@ -6,11 +6,14 @@ and the oracle's, on every sweep path: the resident kernel, the per-half
 kernels, the slab, the fused byte sweep, the multispin and bit-plane
 layouts, and the heat bath.
 
-The 512^3 anneal is too long for the oracle beyond its first sweeps, so
-the whole 10^4-sweep schedule is checked by state hashes at k = 10^j: the
-multispin sweep (the bench's path), the fused byte sweep and the per-half
-kernels, three independent implementations of the same trajectory, must
-reach identical spins, daemons and energies at k = 10, 100, 1000 and 10^4.
+The configurations' full schedules are too long for the oracle beyond
+their first sweeps, so they are checked by state hashes at k = 10^j: on the
+512^3 anneal the multispin sweep (the bench's path), the fused byte sweep
+and the per-half kernels; on the 64^3 quench (10^5 sweeps) the two-sweep and
+one-sweep slab launches and the per-half kernels; on the batched 32^3
+lattices the one-launch and per-half bit-plane sweeps and the byte layout's
+resident kernel -- independent implementations of the same trajectory must
+reach identical spins, daemons and energies.
 """
 import hashlib
 
@@ -93,9 +96,14 @@ def test_device_log_without_rows_only_sweeps():
     g.close()
 
 
-def _digest(g):
+def _digest(g, tally=True):
+    """Spins, daemons, energy, daemon energy and (where the path keeps one)
+    the incremental tally."""
     h = hashlib.sha256()
-    for x in (g.spins(), g.daemons(), g.energy(), g.energy_tally(), g.daemon_energy()):
+    parts = [g.spins(), g.daemons(), g.energy(), g.daemon_energy()]
+    if tally:
+        parts.append(g.energy_tally())
+    for x in parts:
         h.update(np.ascontiguousarray(x).tobytes())
     return h.hexdigest()
 
@@ -124,3 +132,50 @@ def test_anneal_L512_state_hashes_at_powers_of_ten():
         hashes[name] = got
         g.close()
     assert hashes["multispin"] == hashes["fused"] == hashes["per-half"]
+
+
+def _run_hashes(w, marks, layout, kernel):
+    g = M.Lattice(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed, layout=layout)
+    g.set_option(M.OPT_SWEEP_KERNEL, kernel)
+    g.set_schedule(M.Schedule(w.kind, w.T0, w.T1, w.n_sweeps, w.period))
+    name = g.kernel_name(M.ALGO_MICSA)
+    k, got = 0, []
+    for mark in marks:
+        g.sweep(M.ALGO_MICSA, mark - k)
+        k = mark
+        got.append(_digest(g, tally=False))  # the bit-plane per-half kernels keep no tally
+    g.close()
+    return name, got
+
+
+def test_quench_L64_state_hashes_at_powers_of_ten():
+    """Configuration 2 over its whole 10^5-sweep schedule: the two-sweep slab
+    launch (the library's choice), the one-sweep slab launch and the per-half
+    kernels agree at k = 10 .. 10^5."""
+    w = W.QUENCH_L64
+    marks = [10, 100, 1000, 10000, 100000]
+    assert marks[-1] == w.n_sweeps
+    runs = {}
+    for kernel in (M.KERNEL_AUTO, M.KERNEL_SLAB, M.KERNEL_SIMPLE):
+        name, got = _run_hashes(w, marks, M.LAYOUT_BYTE, kernel)
+        runs[name] = got
+        print(f"[hash] {name}: " + " ".join(f"k={m}:{d[:12]}" for m, d in zip(marks, got)), flush=True)
+    assert "k_micsa_slab2" in runs and "k_micsa_half" in runs
+    assert len({tuple(v) for v in runs.values()}) == 1
+
+
+def test_batched_L32_state_hashes_at_powers_of_ten():
+    """Configuration 3 over its whole 10^4-sweep schedule: the one-launch
+    bit-plane sweep (the library's choice), the bit-plane per-half kernels
+    and the byte layout's resident kernel agree at k = 10 .. 10^4."""
+    w = W.BATCHED_L32
+    marks = [10, 100, 1000, 10000]
+    assert marks[-1] == w.n_sweeps
+    runs = []
+    for layout, kernel in ((M.LAYOUT_BITPLANE, M.KERNEL_AUTO), (M.LAYOUT_BITPLANE, M.KERNEL_SIMPLE),
+                           (M.LAYOUT_BYTE, M.KERNEL_AUTO)):
+        name, got = _run_hashes(w, marks, layout, kernel)
+        runs.append((name, got))
+        print(f"[hash] {name}: " + " ".join(f"k={m}:{d[:12]}" for m, d in zip(marks, got)), flush=True)
+    assert [n for n, _ in runs] == ["kb_sweep", "kb_micsa_half", "k_resident<0>"]
+    assert runs[0][1] == runs[1][1] == runs[2][1]
