@@ -32,9 +32,10 @@
 // conserved by every move (eq. H-total), so the lattice energy changes by
 // 4 (sum m - sum m') over the moves.  Each thread adds m + (3 - m') of every
 // word it owns into a vertical counter (bit plane b holds bit b of the
-// per-lane count), the counters are summed over the wave by a butterfly of
-// bit-sliced adders, each thread then reads its lane's count, and the
-// waves' counts are summed in LDS and added to the lane's lattice.
+// per-lane count); half the waves take the other half's counters through
+// LDS and sum them over their lanes by a butterfly of bit-sliced adders;
+// each lane then reads its lattice's count, and the counts are summed in
+// LDS and added to the lane's lattice (bp_tally_counts).
 #pragma once
 #include "bitplane_kernels.hpp"
 #include "msc_kernels.hpp"
@@ -120,6 +121,66 @@ __device__ __forceinline__ void vc_word(uint64_t (&c)[NP], uint64_t o0, uint64_t
     vc_add(c, s0, 0);
     vc_add(c, s1, 1);
     vc_add(c, k1, 2);
+}
+
+// Per-lane tally counts of a work-group.  Waves w >= H (H: half the waves,
+// rounded up) hand their vertical counters to wave w - H through LDS; the H
+// waves (one or two per SIMD) add them and sum their counters over the 64
+// lanes into lane 63 by bit-sliced adders over DPP lane moves (within rows of
+// 16: swap neighbours, swap pairs, rotate by 4 and by 8; then the last lane
+// of row 0 into row 1, of rows 2 / 3 ... as row broadcasts); each lane reads
+// its lattice's count out of lane 63's planes; the H waves' counts meet in
+// LDS.  Returns the lane's total in threads < 64 (0 elsewhere).  Starts with
+// a barrier, after which the caller's LDS is reused.
+__device__ __forceinline__ long long bp_tally_counts(const uint64_t (&cnt)[kBpPlanes], uint64_t* lds)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = (blockDim.x + 63) >> 6, H = (nwaves + 1) >> 1;
+    __syncthreads();  // the caller's LDS planes are no longer read
+    if (wave >= H) {
+#pragma unroll
+        for (int b = 0; b < kBpPlanes; ++b) lds[((wave - H) * kBpPlanes + b) * 64 + lane] = cnt[b];
+    }
+    __syncthreads();
+    long long mine = 0;
+    if (wave < H) {  // uniform per wave: DPP moves see every lane
+        constexpr int NP0 = kBpPlanes + 1;  // a wave's counter plus its partner's
+        constexpr int NW = NP0 + 6;
+        uint64_t c[NW];
+#pragma unroll
+        for (int b = 0; b < NW; ++b) c[b] = b < kBpPlanes ? cnt[b] : 0;
+        if (wave + H < nwaves) {
+            uint64_t carry = 0;
+#pragma unroll
+            for (int b = 0; b < NP0; ++b) {
+                const uint64_t x = b < kBpPlanes ? lds[(wave * kBpPlanes + b) * 64 + lane] : 0;
+                const uint64_t sum = xor3(c[b], x, carry);
+                carry = maj3w(c[b], x, carry);
+                c[b] = sum;
+            }
+        }
+        vc_dpp_level<0xB1, 0xF, NP0 + 1>(c);   // quad_perm [1,0,3,2]
+        vc_dpp_level<0x4E, 0xF, NP0 + 2>(c);   // quad_perm [2,3,0,1]
+        vc_dpp_level<0x124, 0xF, NP0 + 3>(c);  // row_ror:4
+        vc_dpp_level<0x128, 0xF, NP0 + 4>(c);  // row_ror:8
+        vc_dpp_level<0x142, 0xA, NP0 + 5>(c);  // row_bcast:15 into rows 1, 3
+        vc_dpp_level<0x143, 0xC, NP0 + 6>(c);  // row_bcast:31 into rows 2, 3
+#pragma unroll
+        for (int b = 0; b < NW; ++b) {
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)c[b], 63);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(c[b] >> 32), 63);
+            const uint32_t bit = lane < 32 ? (lo >> lane) & 1u : (hi >> (lane - 32)) & 1u;
+            mine += (long long)bit << b;
+        }
+    }
+    __syncthreads();  // the handed-over counters are no longer read
+    long long* part = reinterpret_cast<long long*>(lds);
+    if (wave < H) part[wave * 64 + lane] = mine;
+    __syncthreads();
+    long long total = 0;
+    if (threadIdx.x < 64)
+        for (int w = 0; w < H; ++w) total += part[w * 64 + threadIdx.x];
+    return total;
 }
 
 // One thread per word position of a plane (P <= block); every global load of
@@ -271,42 +332,10 @@ __global__ __launch_bounds__(TZ == 1 ? 1024 : 512) void kb_sweep(GeomB gb, BpTil
             if (TALLY) vc_word(cnt, Om0[e], Om1[e], M0, M1);
         }
     }
-    const int nthreads = blockDim.x;
-
     if (TALLY) {
-        // 4. per-lane tally: the wave's vertical counters are summed into lane
-        // 63 by bit-sliced adders over DPP lane moves (within rows of 16: swap
-        // neighbours, swap pairs, rotate by 4 and by 8; then the last lane of
-        // row 0 into row 1, of rows 2 / 3 ... as row broadcasts), each thread
-        // reads lane 63's planes and extracts its lane's count; the waves'
-        // counts meet in LDS.
-        constexpr int NW = kBpPlanes + 6;
-        uint64_t c[NW];
-#pragma unroll
-        for (int b = 0; b < NW; ++b) c[b] = b < kBpPlanes ? cnt[b] : 0;
-        vc_dpp_level<0xB1, 0xF, kBpPlanes + 1>(c);   // quad_perm [1,0,3,2]
-        vc_dpp_level<0x4E, 0xF, kBpPlanes + 2>(c);   // quad_perm [2,3,0,1]
-        vc_dpp_level<0x124, 0xF, kBpPlanes + 3>(c);  // row_ror:4
-        vc_dpp_level<0x128, 0xF, kBpPlanes + 4>(c);  // row_ror:8
-        vc_dpp_level<0x142, 0xA, kBpPlanes + 5>(c);  // row_bcast:15 into rows 1, 3
-        vc_dpp_level<0x143, 0xC, kBpPlanes + 6>(c);  // row_bcast:31 into rows 2, 3
-        const int lane = threadIdx.x & 63;
-        long long mine = 0;
-#pragma unroll
-        for (int b = 0; b < NW; ++b) {
-            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)c[b], 63);
-            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(c[b] >> 32), 63);
-            const uint32_t bit = lane < 32 ? (lo >> lane) & 1u : (hi >> (lane - 32)) & 1u;
-            mine += (long long)bit << b;
-        }
-        __syncthreads();  // LDS planes are no longer read
-        long long* part = reinterpret_cast<long long*>(lds);
-        const int wave = threadIdx.x >> 6, nwaves = (nthreads + 63) >> 6;
-        part[wave * 64 + lane] = mine;
-        __syncthreads();
+        // 4. per-lane tally: the work-group's counts per lane (bp_tally_counts)
+        const long long sum = bp_tally_counts(cnt, lds);
         if (threadIdx.x < 64) {
-            long long sum = 0;
-            for (int w = 0; w < nwaves; ++w) sum += part[w * 64 + threadIdx.x];
             // every lane counted m + (3 - m') over the 2 TZ P words the group owns
             const long long dE = 4 * (sum - 3ll * 2 * TZ * P);
             int s, r;
@@ -477,35 +506,8 @@ __global__ __launch_bounds__(1024) void kb_sweep_rows(GeomB gb, BpTile f, const 
     }
 
     if (TALLY) {
-        // per-lane tally as in kb_sweep: DPP reduction of the vertical
-        // counters into lane 63, each lane's count, the waves' counts in LDS
-        constexpr int NW = kBpPlanes + 6;
-        uint64_t c[NW];
-#pragma unroll
-        for (int b = 0; b < NW; ++b) c[b] = b < kBpPlanes ? cnt[b] : 0;
-        vc_dpp_level<0xB1, 0xF, kBpPlanes + 1>(c);
-        vc_dpp_level<0x4E, 0xF, kBpPlanes + 2>(c);
-        vc_dpp_level<0x124, 0xF, kBpPlanes + 3>(c);
-        vc_dpp_level<0x128, 0xF, kBpPlanes + 4>(c);
-        vc_dpp_level<0x142, 0xA, kBpPlanes + 5>(c);
-        vc_dpp_level<0x143, 0xC, kBpPlanes + 6>(c);
-        const int lane = threadIdx.x & 63;
-        long long mine = 0;
-#pragma unroll
-        for (int b = 0; b < NW; ++b) {
-            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)c[b], 63);
-            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(c[b] >> 32), 63);
-            const uint32_t bit = lane < 32 ? (lo >> lane) & 1u : (hi >> (lane - 32)) & 1u;
-            mine += (long long)bit << b;
-        }
-        __syncthreads();  // LDS planes are no longer read
-        long long* part = reinterpret_cast<long long*>(lds_bp);
-        const int wave = threadIdx.x >> 6, nwaves = (blockDim.x + 63) >> 6;
-        part[wave * 64 + lane] = mine;
-        __syncthreads();
+        const long long sum = bp_tally_counts(cnt, lds_bp);
         if (threadIdx.x < 64) {
-            long long sum = 0;
-            for (int w = 0; w < nwaves; ++w) sum += part[w * 64 + threadIdx.x];
             // every lane counted m + (3 - m') over the 2 own Kx words the group owns
             const long long dE = 4 * (sum - 3ll * 2 * own * Kx);
             int s, rr;
