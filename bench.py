@@ -496,7 +496,7 @@ def main() -> int:
     per_update = BYTES_PER_UPDATE_BITPLANE if layout else BYTES_PER_UPDATE[algo_name]
     if "k_wander" in mi["kernel"]:  # a separate wandering kernel moves every daemon byte once more
         per_update += 2.0
-    if mi["kernel"] in ("k_msc_half", "k_msc_sweep"):
+    if mi["kernel"] in ("k_msc_half", "k_msc_sweep", "k_msc_sweep_multi"):
         per_update = BYTES_PER_UPDATE_MULTISPIN
     bytes_launch = per_update * w.N * w.lattices * min(1.0, sweeps_per_launch)
     achieved = bytes_launch / (avg_ms * 1e6)  # GB/s

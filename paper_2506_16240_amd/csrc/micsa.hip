@@ -1184,10 +1184,12 @@ MscTile msc2_tile(const micsa_ctx* c)
     return f;
 }
 
+int msc2_block(const MscTile& f, int W) { return ((f.TY + 4 * kMscPassSweeps) * W + 63) / 64 * 64; }
+
 size_t msc2_lds(const MscTile& f, int W)
 {
     constexpr int H = 2 * kMscPassSweeps, D = 2 * kMscPassSweeps + 1;
-    return (size_t)8 * (2 * H + 6 * D) * (size_t)((f.TY + 2 * H) * W);
+    return (size_t)8 * (2 * H + 6 * D) * (size_t)(msc2_block(f, W) + W);
 }
 
 // The pass fits a work-group: lanes and LDS (two work-groups per CU).
@@ -1195,8 +1197,7 @@ bool msc2_fits(const micsa_ctx* c)
 {
     const MscTile f = msc2_tile(c);
     const int W = c->p.Lx / 128;
-    return c->msc_pass == 2 && ((f.TY + 4 * kMscPassSweeps) * W + 63) / 64 * 64 <= kMsc2Lanes &&
-           msc2_lds(f, W) <= 80 * 1024;
+    return c->msc_pass == 2 && msc2_block(f, W) <= kMsc2Lanes && msc2_lds(f, W) <= 80 * 1024;
 }
 
 bool msc_one_launch(const micsa_ctx* c)
@@ -1357,11 +1358,10 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
             if (ok2) {
                 if (refresh || refresh2) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->draw_done, 0));
                 const MscTile f2 = msc2_tile(c);
-                const int lanes2 = (f2.TY + 4 * kMscPassSweeps) * m.W;
                 const dim3 grid2((unsigned)(f2.nty * f2.ntz), (unsigned)c->L);
-                const unsigned block2 = (unsigned)((lanes2 + 63) / 64 * 64);
+                const unsigned block2 = (unsigned)msc2_block(f2, m.W);
                 const size_t lds2 = msc2_lds(f2, m.W);
-                const auto kern = k_msc_sweep_multi<kMscPassSweeps>;
+                const auto kern = refresh2 ? k_msc_sweep_multi<kMscPassSweeps, 1> : k_msc_sweep_multi<kMscPassSweeps, -1>;
                 if (lds2 > 64 * 1024 &&
                     hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2) !=
                         hipSuccess)
@@ -1371,10 +1371,9 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
                 MscTile a_f = f2;
                 const uint64_t *a_s = c->ms, *a_d0 = refresh ? c->mdr0 : c->md0, *a_d1 = refresh ? c->mdr1 : c->md1,
                                *a_b = c->mb, *a_r0 = c->mdr0, *a_r1 = c->mdr1;
-                int a_rj = refresh2 ? 1 : -1;
                 uint64_t *o_s = c->ms_alt, *o_d0 = c->md0_alt, *o_d1 = c->md1_alt;
                 unsigned long long* a_t = c->tally;
-                void* args[] = {&a_g, &a_m, &a_f, &a_s, &a_d0, &a_d1, &a_b, &a_r0, &a_r1, &a_rj, &o_s, &o_d0, &o_d1,
+                void* args[] = {&a_g, &a_m, &a_f, &a_s, &a_d0, &a_d1, &a_b, &a_r0, &a_r1, &o_s, &o_d0, &o_d1,
                                 &a_t};
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (c->timing && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
@@ -2667,8 +2666,8 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
                    ? (bp_one_launch(ctx) && !use_graph(ctx) ? (bp_rows(bp_launch(ctx)) ? "kb_sweep_rows" : "kb_sweep")
                                                             : "kb_micsa_half")
                    : "";
-    if (ctx && algo == MICSA_ALGO_MICSA && use_msc(ctx))
-        return msc_one_launch(ctx) ? "k_msc_sweep" : "k_msc_half";
+    if (ctx && algo == MICSA_ALGO_MICSA && use_msc(ctx))  // a long call runs its sweeps in pairs where it can
+        return msc_one_launch(ctx) ? (msc2_fits(ctx) ? "k_msc_sweep_multi" : "k_msc_sweep") : "k_msc_half";
     // walkers on the fused sweeps wander on the next sweep's loads
     if (ctx && algo == MICSA_ALGO_WALKERS && use_msc(ctx, kMscMinSweeps, algo)) return "k_msc_sweep";
     if (algo == MICSA_ALGO_WALKERS)

@@ -28,37 +28,77 @@
 // Refresh: the levels of a refresh sweep are drawn ahead (k_msc_draw) and
 // read in place of the stored ones -- by the host passing the drawn planes
 // as the input levels when the first sweep of the pass refreshes, and by
-// the kernel loading them for halves 2 rj and 2 rj + 1 when sweep rj >= 1 of
-// the pass refreshes.  Walkers keep the one-sweep kernel.
-// The energy tally adds 4 (sum m - sum m') of every half on the owned sites.
+// the kernel loading them for halves 2 RJ and 2 RJ + 1 when sweep RJ >= 1 of
+// the pass refreshes (RJ < 0: none does).  Walkers keep the one-sweep kernel.
 //
-// Grid (nty * ntz, L); block 64 ceil((TY + 4T) W / 64) <= kMsc2Lanes;
-// LDS 8 (4T + 6 (2T + 1)) (TY + 4T) W bytes.
+// Energy tally: 4 (sum m - sum m') of every half on the owned sites.  Half
+// h >= 2 starts from the levels half h - 2 left at the same site, so the sum
+// telescopes: the levels going into halves 0 and 1, minus those leaving the
+// last two halves, plus, at a refresh half, the drawn levels minus those
+// they replace.
+//
+// Cost per step.  Every lane runs every half that has started (lanes outside
+// a half's rows compute values nobody reads: the rows a half reads are the
+// rows its predecessor got right); only the stores and the tally look at
+// ownership.  Plane indices along z move by one per step and are wrapped by
+// a compare, and the ring slot of the couplings likewise, so no step divides;
+// the march is unrolled by six steps, so the three-step histories of the
+// half results and the two register stages rotate by renaming.
+//
+// Grid (nty * ntz, L); block B = 64 ceil((TY + 4T) W / 64) <= kMsc2Lanes;
+// LDS planes of B + W words (lane t owns word t; the slack keeps the x and
+// y neighbour reads of the last lanes inside): 8 (4T + 6 (2T + 1)) (B + W)
+// bytes.
 #pragma once
+#include <type_traits>
 #include "msc_kernels.hpp"
 
 namespace micsa {
 
 constexpr int kMsc2Lanes = 256;
 
+template <bool DRAWN>
 struct Msc2Stage {
     uint64_t O, Es, J[6], me0, me1, mo0, mo1;
-    uint64_t re0, re1, ro0, ro1;  // drawn levels for the halves of a refresh sweep rj >= 1
+};
+template <>
+struct Msc2Stage<true> {
+    uint64_t O, Es, J[6], me0, me1, mo0, mo1;
+    uint64_t re0, re1, ro0, ro1;  // drawn levels for the halves of the refresh sweep RJ
 };
 
-template <int T>
+// A wrapped index moved by dz = +-1 along an axis of length L.
+__device__ __forceinline__ int step_wrap(int v, int dz, int L)
+{
+    v += dz;
+    return v == L ? 0 : (v < 0 ? L - 1 : v);
+}
+
+__device__ __forceinline__ int level_count(uint64_t m0, uint64_t m1)
+{
+    return __popcll(m0) + 2 * __popcll(m1);
+}
+
+template <int T, int RJ>
 __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
     Geom g, MscGeom m, MscTile f, const uint64_t* __restrict__ spin_in, const uint64_t* __restrict__ d0_in,
     const uint64_t* __restrict__ d1_in, const uint64_t* __restrict__ bond, const uint64_t* __restrict__ dr0,
-    const uint64_t* __restrict__ dr1, int rj, uint64_t* __restrict__ spin_out, uint64_t* __restrict__ d0_out,
+    const uint64_t* __restrict__ dr1, uint64_t* __restrict__ spin_out, uint64_t* __restrict__ d0_out,
     uint64_t* __restrict__ d1_out, unsigned long long* __restrict__ tally)
 {
     constexpr int H = 2 * T;      // halves per pass
     constexpr int D = 2 * T + 1;  // planes in the coupling ring
+    constexpr bool DRAWN = RJ >= 1;
+    static_assert(RJ < T, "the refresh sweep is one of the pass");
+    constexpr int ZH = H + 1;  // wrapped planes kept: zz, zz - dz, .., zz - H dz
+    // planes of the drawn levels, as zc indices: for the next step (even, odd)
+    // and for step 0 (even, odd)
+    constexpr int kRe = DRAWN ? 2 * RJ - 1 : 0, kRo = DRAWN ? 2 * RJ : 0;
+    constexpr int kRe0 = DRAWN ? 2 * RJ : 0, kRo0 = DRAWN ? 2 * RJ + 1 : 0;
     __builtin_amdgcn_s_setprio(1);
     extern __shared__ uint64_t lds_m2[];
     const int W = m.W;
-    const int ps = (f.TY + 2 * H) * W;  // words per LDS plane (one per lane)
+    const int ps = (int)blockDim.x + W;  // words per LDS plane
     // SB[buf][0]: old odd spins of plane z; SB[buf][h]: half h - 1's result plane
     auto SB = [&](int buf, int k) { return lds_m2 + ((size_t)buf * H + k) * ps; };
     auto CB = [&](int slot, int d) { return lds_m2 + (size_t)2 * H * ps + ((size_t)slot * 6 + d) * ps; };
@@ -81,15 +121,17 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
     const int ry = threadIdx.x / W, w = threadIdx.x - (threadIdx.x / W) * W;
     const int own = min(f.TY, g.Ly - y0);
     const int nrows = own + 2 * H;  // rows of this tile with their rings
-    const bool active = ry < nrows;
     auto wrap = [](int v, int L) { v %= L; return v < 0 ? v + L : v; };
     auto clampr = [&](int lo, int hi) { return wrap(y0 - H + min(max(ry, lo), hi), g.Ly); };
     const int y = wrap(y0 - H + ry, g.Ly);
     const bool own_row = ry >= H && ry < own + H;
     const int yO = clampr(0, nrows - 1), yE = clampr(1, nrows - 2), yD = clampr(2, nrows - 3);
-    const int yRe = clampr(2 * rj + 1, nrows - 2 - 2 * rj), yRo = clampr(2 * rj + 2, nrows - 3 - 2 * rj);
-    const int wn = w + 1 == W ? 0 : w + 1, wp = w == 0 ? W - 1 : w - 1;
-    const int me = ry * W + w;
+    const int yRe = clampr(2 * RJ + 1, nrows - 2 - 2 * RJ), yRo = clampr(2 * RJ + 2, nrows - 3 - 2 * RJ);
+    const int me = threadIdx.x;  // = ry W + w
+    const int rowW = ry * W;
+    const int mxn = rowW + (w + 1 == W ? 0 : w + 1), mxp = rowW + (w == 0 ? W - 1 : w - 1);
+    const int myn = me + W, myp = ry > 0 ? me - W : me;  // rows y +- 1 (row 0 reads itself: never used)
+    const int ybit = y & 1;
 
     const int64_t lp = (int64_t)l * 2 * m.plane;
     const uint64_t* ev_in = spin_in + lp;
@@ -98,7 +140,7 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
     const uint32_t zstride = (uint32_t)(g.Ly * W);
     const uint32_t rO = (uint32_t)(yO * W + w), rE = (uint32_t)(yE * W + w), rD = (uint32_t)(yD * W + w),
                    rY = (uint32_t)(y * W + w), rRe = (uint32_t)(yRe * W + w), rRo = (uint32_t)(yRo * W + w);
-    auto zoff = [&](int zz) { return (uint32_t)zz * zstride; };
+    auto zoff = [&](int z) { return (uint32_t)z * zstride; };
     auto ld = [](const uint64_t* base, uint32_t i) {
         return *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(base) + (i << 3));
     };
@@ -106,97 +148,119 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
         *reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(base) + (i << 3)) = v;
     };
 
-    uint64_t O_prev = ld(od_in, zoff(wrap(zstart - dz, g.Lz)) + rO);  // old odd spins at z - dz, z, z + dz
-    uint64_t O_cur = ld(od_in, zoff(wrap(zstart, g.Lz)) + rO);
-    uint64_t O_next = 0;
-    uint64_t RES[H][3];          // half h's result at its site: this step, one and two steps ago
-    uint64_t LV0[H][3], LV1[H][3];  // its levels (read by half h + 2)
+    // zc[k] = the wrapped plane zz - k dz of the current step (uniform)
+    int zc[ZH];
 #pragma unroll
-    for (int h = 0; h < H; ++h)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) RES[h][k] = LV0[h][k] = LV1[h][k] = 0;
+    for (int k = 0; k < ZH; ++k) zc[k] = wrap(zstart - dz * k, g.Lz);
+    int slot0 = 0;  // st mod D
 
-    auto load = [&](int st2, Msc2Stage& S) {
-        const int zz2 = zstart + dz * st2;
-        const int z2 = wrap(zz2, g.Lz);
-        S.O = ld(od_in, zoff(wrap(zz2 + dz, g.Lz)) + rO);
-        const uint32_t h = zoff(z2) + rE;
+    using Stage = Msc2Stage<DRAWN>;
+    // the operands of the step whose wrapped plane zz2 is zE: odd spins at
+    // zz2 + dz, even words at zz2, odd levels at zz2 - dz; drawn levels at
+    // zz2 - 2 RJ dz (even) and zz2 - (2 RJ + 1) dz (odd)
+    auto load = [&](Stage& S, int zOn, int zE, int zDn, int zRe, int zRo) {
+        S.O = ld(od_in, zoff(zOn) + rO);
+        const uint32_t h = zoff(zE) + rE;
         S.Es = ld(ev_in, h);
 #pragma unroll
         for (int d = 0; d < 6; ++d) S.J[d] = ld(bl + (int64_t)d * m.plane, h);
         S.me0 = ld(d0_in + lp, h);
         S.me1 = ld(d1_in + lp, h);
-        const uint32_t ho = zoff(wrap(zz2 - dz, g.Lz)) + rD;
+        const uint32_t ho = zoff(zDn) + rD;
         S.mo0 = ld(d0_in + lp + m.plane, ho);
         S.mo1 = ld(d1_in + lp + m.plane, ho);
-        if (rj > 0) {
-            const uint32_t he = zoff(wrap(zz2 - dz * 2 * rj, g.Lz)) + rRe;
-            const uint32_t hr = zoff(wrap(zz2 - dz * (2 * rj + 1), g.Lz)) + rRo;
+        if constexpr (DRAWN) {
+            const uint32_t he = zoff(zRe) + rRe, hr = zoff(zRo) + rRo;
             S.re0 = ld(dr0 + lp, he);
             S.re1 = ld(dr1 + lp, he);
             S.ro0 = ld(dr0 + lp + m.plane, hr);
             S.ro1 = ld(dr1 + lp + m.plane, hr);
         }
     };
-    long long so = 0, sn = 0;
-    auto step = [&](int st, Msc2Stage& S, Msc2Stage& N) {
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // stage S complete (vmcnt(0))
-        const int buf = st & 1, pb = buf ^ 1;
+
+    Stage STG[2] = {};
+    uint64_t Oq[3];                          // old odd spins loaded at steps st, st - 1, st - 2 (by st mod 3)
+    uint64_t RES[H - 1][3] = {};             // half h's result at its site, by st mod 3
+    uint64_t LV0[H > 2 ? H - 2 : 1][3] = {}, LV1[H > 2 ? H - 2 : 1][3] = {};  // its levels (read by half h + 2)
+    int cin = 0, cout = 0;                   // telescoped level sums of the owned sites
+    {
+        // before step 0: odd spins of zstart - dz and zstart (ring positions of steps -2 and -1)
+        Oq[1] = ld(od_in, zoff(zc[1]) + rO);
+        Oq[2] = ld(od_in, zoff(zc[0]) + rO);
+        Oq[0] = 0;
+        const int zp = wrap(zstart + dz, g.Lz);
+        load(STG[0], zp, zc[0], zc[1], zc[kRe0], zc[kRo0]);
+    }
+
+    auto step = [&](auto phc, int st) {
+        constexpr int ph = decltype(phc)::value;
+        constexpr int c0 = ph % 3, c1 = (ph + 2) % 3, c2 = (ph + 1) % 3;  // st, st - 1, st - 2 (mod 3)
+        constexpr int buf = ph & 1, pb = buf ^ 1;
+        Stage& C = STG[buf];
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // stage C complete (vmcnt(0))
         const int zz = zstart + dz * st;
-        O_next = S.O;
-        const Msc2Stage& C = S;
-        if (st + 1 < steps) load(st + 1, N);
-        if (active) SB(buf, 0)[me] = O_cur;
+        // next step's planes: zz2 = zz + dz
+        const int zp1 = step_wrap(zc[0], dz, g.Lz), zp2 = step_wrap(zp1, dz, g.Lz);
+        if (st + 1 < steps)
+            load(STG[pb], zp2, zp1, zc[0], zc[kRe], zc[kRo]);
+        Oq[c0] = C.O;
+        SB(buf, 0)[me] = Oq[c1];
         lds_barrier();
-        const int slot0 = st % D;
-        if (active) {
+        // after the barrier: the slot's last reader is the step before (its
+        // odd halves' z couplings); this step reads it only at the lane's own word
 #pragma unroll
-            for (int d = 0; d < 6; ++d) CB(slot0, d)[me] = C.J[d];
-        }
+        for (int d = 0; d < 6; ++d) CB(slot0, d)[me] = C.J[d];
+        auto slot = [&](int k) {  // (st - k) mod D, 0 <= k < D
+            const int v = slot0 - k;
+            return v < 0 ? v + D : v;
+        };
 #pragma unroll
         for (int h = 0; h < H; ++h) {
-            if (st < 2 * h) continue;  // not needed yet (uniform)
-            const bool rows_h = ry >= h + 1 && ry < nrows - 1 - h;
-            if (!rows_h) continue;
+            if (st < 2 * h) break;  // halves h and later not started yet (uniform)
             const int zh_u = zz - dz * h;  // unwrapped plane of this half
-            const int zh = wrap(zh_u, g.Lz);
+            const int zh = zc[h];
             const int par = h & 1;
-            const int q = (par + y + zh) & 1;
+            const int q = (par + ybit + zh) & 1;
             const uint64_t* src = SB(h == 0 ? buf : pb, h);
-            const uint64_t Cc = src[me];
-            const uint64_t nxp = q ? shift_next(Cc, src[ry * W + wn]) : Cc;
-            const uint64_t nxm = q ? Cc : shift_prev(Cc, src[ry * W + wp]);
-            const uint64_t nyp = src[me + W], nym = src[me - W];
+            // every read unconditional (a select, not a branch, picks the shifted word)
+            const uint64_t Cc = src[me], Cn = src[mxn], Cp = src[mxp];
+            const uint64_t nyp = src[myn], nym = src[myp];
+            const uint64_t sn_ = shift_next(Cc, Cn), sp_ = shift_prev(Cc, Cp);
+            const uint64_t nxp = q ? sn_ : Cc;
+            const uint64_t nxm = q ? Cc : sp_;
             uint64_t up, dn;  // source results at planes zh + dz and zh - dz
             if (h == 0) {
-                up = O_next;
-                dn = O_prev;
+                up = Oq[c0];
+                dn = Oq[c2];
             } else {
-                up = RES[h - 1][0];
-                dn = RES[h - 1][2];
+                up = RES[h - 1][c0];
+                dn = RES[h - 1][c2];
             }
             const uint64_t nzp = dz > 0 ? up : dn, nzm = dz > 0 ? dn : up;
             uint64_t jb[6];
-            const int sl = ((st - h) % D + D) % D;
             if (par == 0) {
                 if (h == 0) {
 #pragma unroll
                     for (int d = 0; d < 6; ++d) jb[d] = C.J[d];
                 } else {
+                    const int sl = slot(h);
 #pragma unroll
                     for (int d = 0; d < 6; ++d) jb[d] = CB(sl, d)[me];
                 }
             } else {  // an odd site's coupling in direction d is its even neighbour's in direction -d
+                const int sl = slot(h);
                 const uint64_t* Mx = CB(sl, kMx);
                 const uint64_t* Px = CB(sl, kPx);
-                jb[0] = q ? shift_next(Mx[me], Mx[ry * W + wn]) : Mx[me];
-                jb[1] = q ? Px[me] : shift_prev(Px[me], Px[ry * W + wp]);
-                jb[2] = CB(sl, kMy)[me + W];
-                jb[3] = CB(sl, kPy)[me - W];
-                const int s_up = ((st - h + 1) % D + D) % D, s_dn = ((st - h - 1) % D + D) % D;
+                const uint64_t mx = Mx[me], px = Px[me], mxs = shift_next(mx, Mx[mxn]), pxs = shift_prev(px, Px[mxp]);
+                jb[0] = q ? mxs : mx;
+                jb[1] = q ? px : pxs;
+                jb[2] = CB(sl, kMy)[myn];
+                jb[3] = CB(sl, kPy)[myp];
+                const int s_up = slot(h - 1), s_dn = slot(h + 1);
                 jb[4] = CB(dz > 0 ? s_up : s_dn, kMz)[me];  // even site at plane zh + 1
                 jb[5] = CB(dz > 0 ? s_dn : s_up, kPz)[me];  // even site at plane zh - 1
             }
+            const bool owned = own_row && zh_u >= z0 && zh_u < z0 + f.TZ;
             // own spin and levels
             uint64_t s0, m0, m1;
             if (h == 0) {
@@ -204,31 +268,36 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
                 m0 = C.me0;
                 m1 = C.me1;
             } else if (h == 1) {
-                s0 = O_prev;
+                s0 = Oq[c2];
                 m0 = C.mo0;
                 m1 = C.mo1;
             } else {
-                s0 = RES[h - 2][2];
-                if (rj > 0 && (h >> 1) == rj) {
-                    m0 = par ? C.ro0 : C.re0;
-                    m1 = par ? C.ro1 : C.re1;
-                } else {
-                    m0 = LV0[h - 2][2];
-                    m1 = LV1[h - 2][2];
+                s0 = RES[h - 2][c2];
+                m0 = LV0[h - 2][c2];
+                m1 = LV1[h - 2][c2];
+                if constexpr (DRAWN) {
+                    if ((h >> 1) == RJ) {  // the refresh: drawn levels replace those half h - 2 left
+                        const uint64_t r0 = par ? C.ro0 : C.re0, r1 = par ? C.ro1 : C.re1;
+                        const int dc = level_count(r0, r1) - level_count(m0, m1);
+                        cin += owned ? dc : 0;
+                        m0 = r0;
+                        m1 = r1;
+                    }
                 }
             }
+            if (h < 2) cin += owned ? level_count(m0, m1) : 0;
             const uint64_t nb[6] = {nxp, nxm, nyp, nym, nzp, nzm};
             long long a = 0, b = 0;
-            const uint64_t Sn = msc_move(s0, nb, jb, m0, m1, a, b);
-            RES[h][0] = Sn;
-            LV0[h][0] = m0;
-            LV1[h][0] = m1;
+            const uint64_t Sn = msc_move(s0, nb, jb, m0, m1, a, b);  // a, b unused: the tally telescopes
+            if (h < H - 1) RES[h][c0] = Sn;
+            if (h < H - 2) {
+                LV0[h][c0] = m0;
+                LV1[h][c0] = m1;
+            }
             if (h + 1 < H) SB(buf, h + 1)[me] = Sn;
-            const bool own_plane = zh_u >= z0 && zh_u < z0 + f.TZ;
-            if (own_row && own_plane) {
-                so += a;
-                sn += b;
-                if (h >= H - 2) {
+            if (h >= H - 2) {
+                cout += owned ? level_count(m0, m1) : 0;
+                if (owned) {
                     const uint32_t ho = zoff(zh) + rY;
                     const int64_t pp = lp + (par ? m.plane : 0);
                     st8(spin_out + pp, ho, Sn);
@@ -237,25 +306,26 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
                 }
             }
         }
-        O_prev = O_cur;
-        O_cur = O_next;
+        // advance the wrapped planes and the ring slot by one step
 #pragma unroll
-        for (int h = 0; h < H; ++h) {
-            RES[h][2] = RES[h][1];
-            RES[h][1] = RES[h][0];
-            LV0[h][2] = LV0[h][1];
-            LV0[h][1] = LV0[h][0];
-            LV1[h][2] = LV1[h][1];
-            LV1[h][1] = LV1[h][0];
-        }
+        for (int k = ZH - 1; k > 0; --k) zc[k] = zc[k - 1];
+        zc[0] = zp1;
+        slot0 = slot0 + 1 == D ? 0 : slot0 + 1;
     };
-    Msc2Stage SA = {}, SBs = {};
-    load(0, SA);
-    for (int st = 0; st < steps; st += 2) {
-        step(st, SA, SBs);
-        if (st + 1 < steps) step(st + 1, SBs, SA);
+    for (int st = 0; st < steps; st += 6) {
+        step(std::integral_constant<int, 0>{}, st);
+        if (st + 1 >= steps) break;
+        step(std::integral_constant<int, 1>{}, st + 1);
+        if (st + 2 >= steps) break;
+        step(std::integral_constant<int, 2>{}, st + 2);
+        if (st + 3 >= steps) break;
+        step(std::integral_constant<int, 3>{}, st + 3);
+        if (st + 4 >= steps) break;
+        step(std::integral_constant<int, 4>{}, st + 4);
+        if (st + 5 >= steps) break;
+        step(std::integral_constant<int, 5>{}, st + 5);
     }
-    block_add(tally + (int64_t)l * kSlots, 4 * (so - sn));
+    block_add(tally + (int64_t)l * kSlots, 4ll * (long long)(cin - cout));
 }
 
 }  // namespace micsa

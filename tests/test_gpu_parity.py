@@ -290,6 +290,35 @@ def test_anneal_L512_default_launch_full_size(algo):
         assert np.array_equal(g.energy_tally(), E)
 
 
+@pytest.mark.parametrize("ty,tz", [(0, 0), (24, 16)])
+def test_anneal_L512_two_sweep_pass_full_size(ty, tz):
+    """The 512^3 anneal with two multispin sweeps per pass (the automatic
+    tile and the 24 x 16 tile), in calls of 41, 19 and 2 sweeps: a refresh
+    drawn inside the first sweep of the first call (one-sweep kernel), the
+    refreshes at sweeps 20 and 40 on the second sweep of a pass (drawn ahead,
+    read by the pass), the refresh at 60 on the first sweep of a pass (drawn
+    during the call before), and a last odd sweep of a call on the one-sweep
+    kernel.  Spins, daemons, energy, daemon energy and tally equal the
+    oracle's bit for bit after every call."""
+    w = W.ANNEAL_L512
+    g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
+    g.set_option(M.OPT_MSC_PASS, 2)
+    if ty:
+        g.set_option(M.OPT_TILE_Y, ty)
+        g.set_option(M.OPT_TILE_Z, tz)
+    gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
+    g.set_schedule(gs)
+    for n in (41, 19, 2):
+        g.sweep(M.ALGO_MICSA, n)
+        o.run(O.ALGO_MICSA, os_, n, 0)
+        assert g.kernel_name(M.ALGO_MICSA) == "k_msc_sweep_multi"
+        same_state(g, o)
+        E = o.energy()
+        assert np.array_equal(g.energy(), E)
+        assert np.array_equal(g.daemon_energy(), o.daemon_energy())
+        assert np.array_equal(g.energy_tally(), E)
+
+
 @pytest.mark.parametrize("algo", [M.ALGO_HEATBATH, M.ALGO_METROPOLIS])
 def test_anneal_L512_baseline_first_sweeps_full_size(algo):
     """The heat-bath and Metropolis baselines on the 512^3 lattice: first 6
