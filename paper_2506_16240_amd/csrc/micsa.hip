@@ -1186,18 +1186,14 @@ MscTile msc2_tile(const micsa_ctx* c)
 
 int msc2_block(const MscTile& f, int W) { return ((f.TY + 4 * kMscPassSweeps) * W + 63) / 64 * 64; }
 
-size_t msc2_lds(const MscTile& f, int W)
-{
-    constexpr int H = 2 * kMscPassSweeps, D = 2 * kMscPassSweeps + 1;
-    return (size_t)8 * (2 * H + 6 * D) * (size_t)(msc2_block(f, W) + W);
-}
+size_t msc2_lds(const MscTile& f, int W) { return (size_t)8 * kMsc2Words * (size_t)(msc2_block(f, W) + W); }
 
 // The pass fits a work-group: lanes and LDS (two work-groups per CU).
 bool msc2_fits(const micsa_ctx* c)
 {
     const MscTile f = msc2_tile(c);
     const int W = c->p.Lx / 128;
-    return c->msc_pass == 2 && msc2_block(f, W) <= kMsc2Lanes && msc2_lds(f, W) <= 80 * 1024;
+    return c->msc_pass == 2 && msc2_block(f, W) <= kMsc2Lanes && msc2_lds(f, W) <= 96 * 1024;
 }
 
 bool msc_one_launch(const micsa_ctx* c)

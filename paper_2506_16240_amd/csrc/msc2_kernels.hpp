@@ -45,10 +45,18 @@
 // the march is unrolled by six steps, so the three-step histories of the
 // half results and the two register stages rotate by renaming.
 //
+// LDS, lane-major: lane t owns the kMsc2Words words from t kMsc2Words on,
+// its word of each plane -- the 4T result planes (two step buffers) and six
+// coupling planes for each of six ring slots, slot st mod 6 written at step
+// st (six slots, one more than the ring needs, so that the slot is the
+// step's phase in the unrolled march) -- an odd number of 64-bit words, so
+// that a wave's 64-bit reads at consecutive lanes fall in distinct banks.
+// Every LDS address is then one of five per-lane registers (the lane's word
+// and its x and y neighbours') plus a constant.
+//
 // Grid (nty * ntz, L); block B = 64 ceil((TY + 4T) W / 64) <= kMsc2Lanes;
-// LDS planes of B + W words (lane t owns word t; the slack keeps the x and
-// y neighbour reads of the last lanes inside): 8 (4T + 6 (2T + 1)) (B + W)
-// bytes.
+// LDS 8 kMsc2Words (B + W) bytes (the slack W keeps the neighbour reads of
+// the last lanes inside).
 #pragma once
 #include <type_traits>
 #include "msc_kernels.hpp"
@@ -56,6 +64,7 @@
 namespace micsa {
 
 constexpr int kMsc2Lanes = 256;
+constexpr int kMsc2Words = 45;  // LDS words per lane: 8 result planes + 6 x 6 coupling planes, made odd
 
 template <bool DRAWN>
 struct Msc2Stage {
@@ -72,6 +81,58 @@ __device__ __forceinline__ int step_wrap(int v, int dz, int L)
 {
     v += dz;
     return v == L ? 0 : (v < 0 ? L - 1 : v);
+}
+
+// The Creutz move of msc_move with the gates of a 32-bit half fused into
+// three-input v_bitop3 operations (24 per half instead of about 30), every
+// truth table symmetric in its first and third operands.  With x0 = ~w0
+// (w0 = m0 ^ s1 ^ s2, the sum bit of m + u): cw0 = m0 & (s1 ^ s2), the
+// carry into bit 1; acc = !w3 & (w2 ^ (w1 & w0)) with w2 = u2 ^ cw1 and
+// w3 = u2 & cw1; m' = acc ? (w2 & (w1 | w0), ~w0) : (m1, m0).
+template <int TT>
+__device__ __forceinline__ uint64_t b3(uint64_t a, uint64_t b, uint64_t c)
+{
+    const uint32_t lo = __builtin_amdgcn_bitop3_b32((uint32_t)a, (uint32_t)b, (uint32_t)c, TT);
+    const uint32_t hi = __builtin_amdgcn_bitop3_b32((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32), TT);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+__device__ __forceinline__ uint64_t msc_move_fused(uint64_t s, const uint64_t (&n)[6], const uint64_t (&j)[6],
+                                                   uint64_t& m0, uint64_t& m1)
+{
+    const uint64_t a = xor3(s, n[0], j[0]), b = xor3(s, n[1], j[1]), c = xor3(s, n[2], j[2]);
+    const uint64_t d = xor3(s, n[3], j[3]), e = xor3(s, n[4], j[4]), f = xor3(s, n[5], j[5]);
+    const uint64_t s1 = xor3(a, b, c), c1 = maj3w(a, b, c);
+    const uint64_t s2 = xor3(d, e, f), c2 = maj3w(d, e, f);
+    const uint64_t k0 = s1 & s2;
+    const uint64_t u1 = xor3(c1, c2, k0), u2 = maj3w(c1, c2, k0);
+    const uint64_t x0 = b3<0x69>(s1, m0, s2);   // ~(m0 ^ s1 ^ s2) = ~w0
+    const uint64_t cw0 = b3<0x48>(s1, m0, s2);  // m0 & (s1 ^ s2)
+    const uint64_t w1 = xor3(m1, u1, cw0), cw1 = maj3w(m1, u1, cw0);
+    const uint64_t p = b3<0x30>(w1, x0, w1);    // w1 & w0 (first and third operand the same)
+    const uint64_t r = b3<0xF3>(w1, x0, w1);    // w1 | w0
+    const uint64_t acc = b3<0x16>(u2, p, cw1);  // ~(u2 & cw1) & (u2 ^ cw1 ^ p)
+    const uint64_t v = b3<0x48>(u2, r, cw1);    // (u2 ^ cw1) & r
+    const uint64_t n0 = (acc & x0) | (~acc & m0);
+    const uint64_t n1 = (acc & v) | (~acc & m1);
+    m0 = n0;
+    m1 = n1;
+    return s ^ acc;
+}
+
+// v shifted right by q in {0, 1} with bit 0 of nxt moving in at bit 63
+// (shift_next for q = 1): two funnel shifts.
+__device__ __forceinline__ uint64_t shr_q(uint64_t v, uint64_t nxt, uint32_t q)
+{
+    const uint32_t vl = (uint32_t)v, vh = (uint32_t)(v >> 32), nl = (uint32_t)nxt;
+    const uint32_t lo = __builtin_amdgcn_alignbit(vh, vl, q);
+    const uint32_t hi = __builtin_amdgcn_alignbit(nl, vh, q);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+// v shifted left by t in {0, 1} with bit 63 of prv moving in at bit 0
+// (shift_prev for t = 1).
+__device__ __forceinline__ uint64_t shl_t(uint64_t v, uint64_t prv, uint32_t t)
+{
+    return (v << t) | (uint64_t)((uint32_t)(prv >> 63) & t);
 }
 
 __device__ __forceinline__ int level_count(uint64_t m0, uint64_t m1)
@@ -96,12 +157,13 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
     constexpr int kRe = DRAWN ? 2 * RJ - 1 : 0, kRo = DRAWN ? 2 * RJ : 0;
     constexpr int kRe0 = DRAWN ? 2 * RJ : 0, kRo0 = DRAWN ? 2 * RJ + 1 : 0;
     __builtin_amdgcn_s_setprio(1);
+    static_assert(D <= 6 && 2 * H + 36 <= kMsc2Words, "six ring slots, one per step phase");
     extern __shared__ uint64_t lds_m2[];
     const int W = m.W;
-    const int ps = (int)blockDim.x + W;  // words per LDS plane
-    // SB[buf][0]: old odd spins of plane z; SB[buf][h]: half h - 1's result plane
-    auto SB = [&](int buf, int k) { return lds_m2 + ((size_t)buf * H + k) * ps; };
-    auto CB = [&](int slot, int d) { return lds_m2 + (size_t)2 * H * ps + ((size_t)slot * 6 + d) * ps; };
+    // word k of a lane: SB(buf, 0) old odd spins of plane z, SB(buf, h) half
+    // h - 1's result plane; CB(slot, d) coupling d of the even sites
+    constexpr auto SB = [](int buf, int k) { return buf * H + k; };
+    constexpr auto CB = [](int slot, int d) { return 2 * H + slot * 6 + d; };
 
     const int l = blockIdx.y;
     int t = blockIdx.x, ty, tz;
@@ -131,6 +193,11 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
     const int rowW = ry * W;
     const int mxn = rowW + (w + 1 == W ? 0 : w + 1), mxp = rowW + (w == 0 ? W - 1 : w - 1);
     const int myn = me + W, myp = ry > 0 ? me - W : me;  // rows y +- 1 (row 0 reads itself: never used)
+    uint64_t* const Lme = lds_m2 + me * kMsc2Words;
+    const uint64_t* const Lxn = lds_m2 + mxn * kMsc2Words;
+    const uint64_t* const Lxp = lds_m2 + mxp * kMsc2Words;
+    const uint64_t* const Lyn = lds_m2 + myn * kMsc2Words;
+    const uint64_t* const Lyp = lds_m2 + myp * kMsc2Words;
     const int ybit = y & 1;
 
     const int64_t lp = (int64_t)l * 2 * m.plane;
@@ -138,6 +205,11 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
     const uint64_t* od_in = spin_in + lp + m.plane;
     const uint64_t* bl = bond + (int64_t)l * 6 * m.plane;
     const uint32_t zstride = (uint32_t)(g.Ly * W);
+    // z couplings in march orientation: word 4 of a stage (and of the LDS
+    // coupling ring) is the bond towards z + dz, word 5 the bond towards z - dz
+    const int kFw = dz > 0 ? kPz : kMz, kBw = dz > 0 ? kMz : kPz;
+    const uint64_t* const bfw = bl + (int64_t)kFw * m.plane;
+    const uint64_t* const bbw = bl + (int64_t)kBw * m.plane;
     const uint32_t rO = (uint32_t)(yO * W + w), rE = (uint32_t)(yE * W + w), rD = (uint32_t)(yD * W + w),
                    rY = (uint32_t)(y * W + w), rRe = (uint32_t)(yRe * W + w), rRo = (uint32_t)(yRo * W + w);
     auto zoff = [&](int z) { return (uint32_t)z * zstride; };
@@ -152,7 +224,6 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
     int zc[ZH];
 #pragma unroll
     for (int k = 0; k < ZH; ++k) zc[k] = wrap(zstart - dz * k, g.Lz);
-    int slot0 = 0;  // st mod D
 
     using Stage = Msc2Stage<DRAWN>;
     // the operands of the step whose wrapped plane zz2 is zE: odd spins at
@@ -163,7 +234,9 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
         const uint32_t h = zoff(zE) + rE;
         S.Es = ld(ev_in, h);
 #pragma unroll
-        for (int d = 0; d < 6; ++d) S.J[d] = ld(bl + (int64_t)d * m.plane, h);
+        for (int d = 0; d < 4; ++d) S.J[d] = ld(bl + (int64_t)d * m.plane, h);
+        S.J[4] = ld(bfw, h);
+        S.J[5] = ld(bbw, h);
         S.me0 = ld(d0_in + lp, h);
         S.me1 = ld(d1_in + lp, h);
         const uint32_t ho = zoff(zDn) + rD;
@@ -204,30 +277,27 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
         if (st + 1 < steps)
             load(STG[pb], zp2, zp1, zc[0], zc[kRe], zc[kRo]);
         Oq[c0] = C.O;
-        SB(buf, 0)[me] = Oq[c1];
-        lds_barrier();
-        // after the barrier: the slot's last reader is the step before (its
-        // odd halves' z couplings); this step reads it only at the lane's own word
+        Lme[SB(buf, 0)] = Oq[c1];
+        // the slot of this step (st mod 6) was last read at step st - 2
 #pragma unroll
-        for (int d = 0; d < 6; ++d) CB(slot0, d)[me] = C.J[d];
-        auto slot = [&](int k) {  // (st - k) mod D, 0 <= k < D
-            const int v = slot0 - k;
-            return v < 0 ? v + D : v;
-        };
+        for (int d = 0; d < 6; ++d) Lme[CB(ph, d)] = C.J[d];
+        lds_barrier();
+        constexpr auto slot = [](int k) { return ((ph - k) % 6 + 6) % 6; };  // (st - k) mod 6
+        // x offset of the row's sites of the half's parity: (par + y + zh) & 1
+        // = (y + zz) & 1 for every half of the step (zh = zz - dz h, even sides)
+        const uint32_t q = (uint32_t)((ybit + zc[0]) & 1), qn = q ^ 1u;
 #pragma unroll
         for (int h = 0; h < H; ++h) {
             if (st < 2 * h) break;  // halves h and later not started yet (uniform)
             const int zh_u = zz - dz * h;  // unwrapped plane of this half
             const int zh = zc[h];
             const int par = h & 1;
-            const int q = (par + ybit + zh) & 1;
-            const uint64_t* src = SB(h == 0 ? buf : pb, h);
+            const int src = SB(h == 0 ? buf : pb, h);
             // every read unconditional (a select, not a branch, picks the shifted word)
-            const uint64_t Cc = src[me], Cn = src[mxn], Cp = src[mxp];
-            const uint64_t nyp = src[myn], nym = src[myp];
-            const uint64_t sn_ = shift_next(Cc, Cn), sp_ = shift_prev(Cc, Cp);
-            const uint64_t nxp = q ? sn_ : Cc;
-            const uint64_t nxm = q ? Cc : sp_;
+            const uint64_t Cc = Lme[src], Cn = Lxn[src], Cp = Lxp[src];
+            const uint64_t nyp = Lyn[src], nym = Lyp[src];
+            const uint64_t nxp = shr_q(Cc, Cn, q);   // q ? shift_next(Cc, Cn) : Cc
+            const uint64_t nxm = shl_t(Cc, Cp, qn);  // q ? Cc : shift_prev(Cc, Cp)
             uint64_t up, dn;  // source results at planes zh + dz and zh - dz
             if (h == 0) {
                 up = Oq[c0];
@@ -236,7 +306,6 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
                 up = RES[h - 1][c0];
                 dn = RES[h - 1][c2];
             }
-            const uint64_t nzp = dz > 0 ? up : dn, nzm = dz > 0 ? dn : up;
             uint64_t jb[6];
             if (par == 0) {
                 if (h == 0) {
@@ -245,20 +314,19 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
                 } else {
                     const int sl = slot(h);
 #pragma unroll
-                    for (int d = 0; d < 6; ++d) jb[d] = CB(sl, d)[me];
+                    for (int d = 0; d < 6; ++d) jb[d] = Lme[CB(sl, d)];
                 }
             } else {  // an odd site's coupling in direction d is its even neighbour's in direction -d
                 const int sl = slot(h);
-                const uint64_t* Mx = CB(sl, kMx);
-                const uint64_t* Px = CB(sl, kPx);
-                const uint64_t mx = Mx[me], px = Px[me], mxs = shift_next(mx, Mx[mxn]), pxs = shift_prev(px, Px[mxp]);
-                jb[0] = q ? mxs : mx;
-                jb[1] = q ? px : pxs;
-                jb[2] = CB(sl, kMy)[myn];
-                jb[3] = CB(sl, kPy)[myp];
-                const int s_up = slot(h - 1), s_dn = slot(h + 1);
-                jb[4] = CB(dz > 0 ? s_up : s_dn, kMz)[me];  // even site at plane zh + 1
-                jb[5] = CB(dz > 0 ? s_dn : s_up, kPz)[me];  // even site at plane zh - 1
+                jb[0] = shr_q(Lme[CB(sl, kMx)], Lxn[CB(sl, kMx)], q);
+                jb[1] = shl_t(Lme[CB(sl, kPx)], Lxp[CB(sl, kPx)], qn);
+                jb[2] = Lyn[CB(sl, kMy)];
+                jb[3] = Lyp[CB(sl, kPy)];
+                // the even site at plane zh + dz (ring slot of step st - h + 1)
+                // bonds to this site with its bond towards z - dz, the one at
+                // zh - dz (step st - h - 1) with its bond towards z + dz
+                jb[4] = Lme[CB(slot(h - 1), 5)];
+                jb[5] = Lme[CB(slot(h + 1), 4)];
             }
             const bool owned = own_row && zh_u >= z0 && zh_u < z0 + f.TZ;
             // own spin and levels
@@ -286,15 +354,14 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
                 }
             }
             if (h < 2) cin += owned ? level_count(m0, m1) : 0;
-            const uint64_t nb[6] = {nxp, nxm, nyp, nym, nzp, nzm};
-            long long a = 0, b = 0;
-            const uint64_t Sn = msc_move(s0, nb, jb, m0, m1, a, b);  // a, b unused: the tally telescopes
+            const uint64_t nb[6] = {nxp, nxm, nyp, nym, up, dn};
+            const uint64_t Sn = msc_move_fused(s0, nb, jb, m0, m1);
             if (h < H - 1) RES[h][c0] = Sn;
             if (h < H - 2) {
                 LV0[h][c0] = m0;
                 LV1[h][c0] = m1;
             }
-            if (h + 1 < H) SB(buf, h + 1)[me] = Sn;
+            if (h + 1 < H) Lme[SB(buf, h + 1)] = Sn;
             if (h >= H - 2) {
                 cout += owned ? level_count(m0, m1) : 0;
                 if (owned) {
@@ -310,7 +377,6 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
 #pragma unroll
         for (int k = ZH - 1; k > 0; --k) zc[k] = zc[k - 1];
         zc[0] = zp1;
-        slot0 = slot0 + 1 == D ? 0 : slot0 + 1;
     };
     for (int st = 0; st < steps; st += 6) {
         step(std::integral_constant<int, 0>{}, st);
