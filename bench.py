@@ -413,7 +413,8 @@ def main() -> int:
     layout = 1 if args.layout == "bitplane" else 0
     fused = layout == 0 and w.Lx % 32 == 0 and w.Lx >= 128
     # MicSA on the multispin planes (the library's choice for long calls on
-    # lattices with Lx % 128 == 0) has no tile to tune
+    # lattices with Lx % 128 == 0): the tuner picks its tile, tile order and
+    # sweeps per pass
     multispin = (layout == 0 and args.kernel in ("auto", "multispin") and w.Lx % 128 == 0 and args.gamma == 1
                  and args.algo == "micsa" and w.N * 3 > 150 * 1024 * 2)
     tile = None

@@ -310,12 +310,13 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      sweeps at least two (the state is read and written once per pair); 1
      runs one sweep per launch.  Results are identical.
    MICSA_OPT_MSC_PASS: MicSA sweeps per pass on the one-launch multispin
-     sweep: 1 (default) or 2 (sweeps k and k + 1 in one launch, rings of 8
-     rows and planes, the state read and written once per pair; a pass whose
+     sweep: 2 (default: sweeps k and k + 1 in one launch, rings of 8 rows
+     and planes, the state read and written once per pair; a pass whose
      sweeps include a refresh takes the levels drawn ahead, and a pair with
-     two refreshes, or a refresh with DRAW_AHEAD 0, runs one sweep per
-     launch).  Results are identical; on MI355X the pair form is bound by
-     VALU latency and slower at 512^3, so it is off by default.
+     two refreshes, a refresh with DRAW_AHEAD 0, the last odd sweep of a
+     call, walkers, or a tile whose work-group does not fit runs one sweep
+     per launch) or 1 (one sweep per launch).  Results are identical; at
+     512^3 on MI355X the pair takes 36 us against 2 x 27 us.
    MICSA_OPT_MSC_FUSED: the multispin sweep in one launch per sweep marching
      along z (1, default) or one launch per half sweep (0).
    MICSA_OPT_PREFETCH: steps of global loads in flight in the fused MicSA

@@ -99,7 +99,7 @@ struct micsa_ctx {
     int32_t xcd_map = 2;  // XCD-aware tile order for the fused sweeps (2: z bands on the multispin sweep)
     int32_t prefetch = 1;  // steps of loads in flight in the fused MicSA sweep (1 or 2)
     int32_t temporal = 2;  // MicSA sweeps per pass of the fused kernel (1 or 2)
-    int32_t msc_pass = 1;  // MicSA sweeps per pass of the one-launch multispin sweep (1 or 2)
+    int32_t msc_pass = 2;  // MicSA sweeps per pass of the one-launch multispin sweep (1 or 2)
     int32_t use_graphs = 0;
     // walkers on the fused sweep: parity of a forward-X wandering the stored
     // daemons still owe (applied by the next fused sweep on load), or -1
@@ -1161,8 +1161,9 @@ MscTile msc_tile(const micsa_ctx* c)
 }
 
 // Tile of the two-sweep multispin pass (msc2_kernels.hpp): (TY + 8) W lanes,
-// whole waves up to kMsc2Lanes (Lx = 512: 40 rows, 192 lanes); TZ as the
-// one-sweep tile.
+// whole waves up to two (Lx = 512: 24 rows, 128 lanes), and up to 16 planes,
+// so that the march's ramp of six steps is a small share of it (at 512^3:
+// 18.2 us per sweep, against 22.4 with 40 rows and 8 planes).
 constexpr int kMscPassSweeps = 2;
 
 MscTile msc2_tile(const micsa_ctx* c)
@@ -1173,11 +1174,11 @@ MscTile msc2_tile(const micsa_ctx* c)
         f.TY = c->tile_y;
     } else {
         int rows = 0;
-        for (int r = ring + 1; r * W <= 192; ++r)
+        for (int r = ring + 1; r * W <= 128; ++r)
             if ((r * W) % 64 == 0) rows = r;
         f.TY = rows ? std::min(rows - ring, c->p.Ly) : std::max(1, std::min(c->p.Ly, kMsc2Lanes / W - ring));
     }
-    f.TZ = c->tile_z ? c->tile_z : divisor_at_most(c->p.Lz, 8);
+    f.TZ = c->tile_z ? c->tile_z : divisor_at_most(c->p.Lz, 16);
     f.nty = (c->p.Ly + f.TY - 1) / f.TY;
     f.ntz = c->p.Lz / f.TZ;
     f.xcd = c->xcd_map == 2 && f.ntz % 8 == 0 ? 2 : (c->xcd_map && (f.nty * f.ntz) % 8 == 0 ? 1 : 0);

@@ -268,12 +268,14 @@ def test_anneal_L512_first_sweeps_full_size(prefetch, temporal, kernel):
 @pytest.mark.parametrize("algo", [M.ALGO_MICSA, M.ALGO_WALKERS])
 def test_anneal_L512_default_launch_full_size(algo):
     """The 512^3 anneal exactly as the benchmark times it: no launch option
-    (the library's own choice: the one-launch multispin sweep with its
-    automatic 44-row tile and ragged last y tile, z-band XCD order over the
-    z tiles, refresh levels drawn ahead on the side stream), 41 sweeps in ONE
-    call (refreshes before sweeps 0, 20 and 40, two of them drawn ahead
-    inside the call), then 3 more in a second call.  Spins, daemons, energy,
-    daemon energy and the tally equal the oracle's bit for bit."""
+    (the library's own choice: MicSA two sweeps per pass over the multispin
+    planes with the automatic 24-row, 16-plane tile and its ragged last y
+    tile, z-band XCD order over the z tiles, refresh levels drawn ahead on
+    the side stream; walkers one sweep per launch with the automatic 44-row
+    tile), 41 sweeps in ONE call (refreshes before sweeps 0, 20 and 40, two
+    of them drawn ahead inside the call), then 3 more in a second call.
+    Spins, daemons, energy, daemon energy and the tally equal the oracle's
+    bit for bit."""
     w = W.ANNEAL_L512
     g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
     gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
@@ -282,7 +284,7 @@ def test_anneal_L512_default_launch_full_size(algo):
     for n in (41, 3):
         g.sweep(algo, n)
         o.run(oalgo, os_, n, 0)
-        assert g.kernel_name(algo) == "k_msc_sweep"
+        assert g.kernel_name(algo) == ("k_msc_sweep_multi" if algo == M.ALGO_MICSA else "k_msc_sweep")
         same_state(g, o)
         E = o.energy()
         assert np.array_equal(g.energy(), E)
@@ -455,6 +457,7 @@ def test_multispin_matches_oracle(shape, fused, ahead):
     g, o = pair(*shape, seed=0x77AA)
     g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_MULTISPIN)
     g.set_option(M.OPT_MSC_FUSED, fused)
+    g.set_option(M.OPT_MSC_PASS, 1)  # one sweep per launch (two per pass: test_multispin_two_sweeps_per_pass...)
     g.set_option(M.OPT_DRAW_AHEAD, ahead)
     assert g.kernel_name(M.ALGO_MICSA) == ("k_msc_sweep" if fused else "k_msc_half")
     gs, os_ = scheds(M.SCHED_LINEAR, 2.4, 0.3, 60, 3)
@@ -606,7 +609,7 @@ def test_multispin_two_sweeps_per_pass_match_oracle(shape, ty, tz):
     one sweep per pass and the oracle: calls that start at even and odd k,
     refreshes (period 5) on the first and on the second sweep of a pass,
     with the levels drawn ahead; a last odd sweep of a call on the one-sweep
-    kernel; the ragged last y tile of the automatic 40-row tile."""
+    kernel; the ragged last y tile of the automatic 24-row tile."""
     gs, os_ = scheds(M.SCHED_LINEAR, 2.6, 0.4, 80, 5)
     o = O.Lattice(*shape, 0x2B)
     runs = {}

@@ -89,3 +89,43 @@ def test_symmetric_truth_tables_do_not_depend_on_operand_order():
         for x, y, z in itertools.product((0, 1), repeat=3):
             k_msb, k_lsb = x << 2 | y << 1 | z, z << 2 | y << 1 | x
             assert (t >> k_msb) & 1 == (t >> k_lsb) & 1 == f(x, y, z)
+
+
+def move_fused(s, a, m0, m1, msb_first=True):
+    """The two-sweep pass's form of the move (csrc/msc2_kernels.hpp,
+    msc_move_fused): the same decision with the gates of each 32-bit half
+    fused into three-input v_bitop3 tables, each symmetric in its first and
+    third operands, and two-way selects (v_bfi)."""
+    b3 = lambda x, y, z, t: bitop3(x, y, z, t, msb_first)
+    xor3 = lambda x, y, z: b3(x, y, z, 0x96)
+    maj3 = lambda x, y, z: b3(x, y, z, 0xE8)
+    sel = lambda c, x, y: ((c & x) | (~c & y)) & MASK
+    s1, c1 = xor3(a[0], a[1], a[2]), maj3(a[0], a[1], a[2])
+    s2, c2 = xor3(a[3], a[4], a[5]), maj3(a[3], a[4], a[5])
+    k0 = s1 & s2
+    u1, u2 = xor3(c1, c2, k0), maj3(c1, c2, k0)
+    x0 = b3(s1, m0, s2, 0x69)    # ~(m0 ^ s1 ^ s2)
+    cw0 = b3(s1, m0, s2, 0x48)   # m0 & (s1 ^ s2)
+    w1, cw1 = xor3(m1, u1, cw0), maj3(m1, u1, cw0)
+    p = b3(w1, x0, w1, 0x30)     # w1 & ~x0
+    r = b3(w1, x0, w1, 0xF3)     # w1 | ~x0
+    acc = b3(u2, p, cw1, 0x16)   # ~(u2 & cw1) & (u2 ^ cw1 ^ p)
+    v = b3(u2, r, cw1, 0x48)     # (u2 ^ cw1) & r
+    return s ^ acc, sel(acc, x0, m0), sel(acc, v, m1), acc
+
+
+@pytest.mark.parametrize("msb_first", [True, False], ids=["table-msb-first", "table-lsb-first"])
+def test_fused_gate_move_equals_the_move(msb_first):
+    """Every (level, placement of unsatisfied bonds, spin): the fused form
+    gives the same new spin, levels and acceptance as the move above, under
+    either operand order of the truth tables."""
+    for chunk in cases():
+        s = m0 = m1 = 0
+        a = [0] * 6
+        for lane, (m, bits, sp) in enumerate(chunk):
+            s |= sp << lane
+            m0 |= (m & 1) << lane
+            m1 |= (m >> 1) << lane
+            for d in range(6):
+                a[d] |= ((bits >> d) & 1) << lane
+        assert move_fused(s, a, m0, m1, msb_first) == move(s, a, m0, m1, True)
