@@ -334,7 +334,8 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo);
      the refresh sweep then reads them (multispin: the first refresh after
      a call is drawn during it and kept for the call that starts there,
      until the schedule changes; a refresh at a call's first sweep with no
-     such levels is drawn inside that sweep).  0 draws them in place: inside the
+     such levels is drawn by a full grid, beside the call's pack of the
+     planes when there is one).  0 draws them in place: inside the
      refresh sweep (multispin), or in a draw kernel just before it on the
      library's stream (bit-plane).  Every draw is joined into the context's
      stream before the call that launched it returns.  Results are

@@ -1208,13 +1208,15 @@ constexpr int64_t kDrawBlocks = 1024;  // draw-ahead grid: one wave per SIMD, be
 // Launch the draw of refresh sweep kr's levels on the side stream, after
 // everything the library stream holds so far (the previous refresh sweep
 // reads the same planes); the refresh sweep waits for draw_done.
-int draw_levels(micsa_ctx* c, const MscGeom& m, int64_t kr)
+// alone: nothing of the call runs beside the draw (a refresh at the call's
+// first sweep), so it takes a full grid, a thread per word
+int draw_levels(micsa_ctx* c, const MscGeom& m, int64_t kr, bool alone = false)
 {
     const int64_t rho = refresh_index(kr, c->sched.period);
     const double T = temperature(c->sched, rho);
     if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
     const int64_t total = (int64_t)c->L * m.plane;
-    const unsigned blocks = (unsigned)std::min<int64_t>((total + 63) / 64, kDrawBlocks);
+    const unsigned blocks = (unsigned)(alone ? (total + 63) / 64 : std::min<int64_t>((total + 63) / 64, kDrawBlocks));
     HIP_TRY(c, hipEventRecord(c->draw_free, c->stream));
     HIP_TRY(c, hipStreamWaitEvent(c->draw_stream, c->draw_free, 0));
     k_msc_draw<<<blocks, 64, 0, c->draw_stream>>>(c->g, m, c->L, c->mdr0, c->mdr1, (uint32_t)rho,
@@ -1316,6 +1318,17 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
     if (int st = msc_alloc(c, one, ahead)) return st;
     const dim3 cgrid((unsigned)((2 * m.plane + 255) / 256), (unsigned)c->L);
     int st = MICSA_OK;
+    const int64_t k_end = c->k + n;
+    int64_t drawn = -1;  // refresh sweep whose levels the draw planes hold (or are being drawn)
+    // The first refresh of the call may have been drawn during the previous
+    // one.  A refresh at the call's first sweep has no sweep of the call to
+    // hide a draw behind: its levels (which depend on the schedule only) are
+    // drawn by a full grid, enqueued before the pack so that the two run side
+    // by side, and the call's first sweeps read them like any other.
+    if (ahead && (drawn = next_refresh(c, c->k, k_end)) >= 0 && drawn != c->msc_drawn &&
+        (st = draw_levels(c, m, drawn, drawn == c->k)))
+        return st;
+    c->msc_drawn = -1;
     if (!c->msc_live) {
         {
             TimedLaunch t(c, kTimeReduce);
@@ -1327,18 +1340,6 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
     const dim3 sgrid((unsigned)(f.nty * f.ntz), (unsigned)c->L);
     const unsigned sblock = (unsigned)((lanes + 63) / 64 * 64);
     const size_t slds = (size_t)96 * lanes;  // 6 planes x 2 step buffers x 8 B per lane
-    const int64_t k_end = c->k + n;
-    int64_t drawn = -1;  // refresh sweep whose levels the draw planes hold (or are being drawn)
-    // the first refresh of the call may have been drawn during the previous
-    // one; a refresh at the call's first sweep, with no sweep of the call
-    // before it to hide a draw behind, is drawn inside that sweep instead
-    if (ahead && (drawn = next_refresh(c, c->k, k_end)) >= 0 && drawn != c->msc_drawn) {
-        if (drawn == c->k)
-            drawn = -1;
-        else if ((st = draw_levels(c, m, drawn)))
-            return st;
-    }
-    c->msc_drawn = -1;
     for (int64_t i = 0; i < n; ++i) {
         const int64_t k = c->k;
         const bool refresh = is_refresh(k, c->sched.period);
