@@ -2,10 +2,11 @@
 """Spin updates/ns of MicSA and of the heat-bath and Metropolis baselines on one MI355X.
 
 Workload (default): the large anneal -- one 512^3 lattice (134M spins) of the
-3D EA +-J model, byte layout, linear schedule T = 3.0 -> 0.2 over 10^4 sweeps,
-daemon refresh every 20 sweeps.  A step is one refresh period: the refresh
-and 20 sweeps (even half + odd half each, with the incremental energy
-tally).  --steps 500 is the whole anneal.  The heat bath and Metropolis run
+3D EA +-J model (byte arrays at the library's boundary, swept on multispin
+bit planes), linear schedule T = 3.0 -> 0.2 over 10^4 sweeps, daemon refresh
+every 20 sweeps.  A step is one refresh period: the refresh and 20 sweeps
+(even half + odd half each, with the incremental energy tally).  --steps 500
+is the whole anneal.  The heat bath and Metropolis run
 the same steps on lattices from the same seed.  Prints one JSON line.
 
 --workload pt_gauss_L10_200x2x40: the equilibrium workload of App. C
