@@ -156,11 +156,12 @@ __global__ void __launch_bounds__(kSweep2Lanes) k_micsa_sweep2_fused(
     auto sh_even = [&](int w, int z) { return w == 0 ? ((y + z) & 1) : ((y + z) & 1) - 1; };
     auto sh_odd = [&](int w, int z) { return w == 0 ? -((y + z) & 1) : 1 - ((y + z) & 1); };
     auto row_of = [&](int z) { return (int64_t)y * g.Kx + plane * z; };
-    auto load_step = [&](int st2) {
-        const int z2 = zof(st2);
+    // the loads of march step st2 at wrapped planes z2 = zof(st2), z2p =
+    // zof(st2 + 1) and z2m = zof(st2 - 1)
+    auto load_step = [&](int st2, int z2, int z2p, int z2m) {
         nMex = 0u;
         nMox = 0u;
-        if (active) nSo = ldg16(od_in + hof(wrap(z2 + dz, g.Lz)));
+        if (active) nSo = ldg16(od_in + hof(z2p));
         if (rowA_e) {
             const int64_t h2 = hof(z2);
             nSe = ldg16(ev_in + h2);
@@ -175,7 +176,7 @@ __global__ void __launch_bounds__(kSweep2Lanes) k_micsa_sweep2_fused(
             }
         }
         if (!RA && rowA_o && st2 >= 2) {
-            const int zo2 = wrap(z2 - dz, g.Lz);
+            const int zo2 = z2m;
             if (!WALK || wanderA < 0) {
                 nMo = ldg16(mo_in + hof(zo2));
             } else {  // new odd daemons come from the even array
@@ -192,18 +193,23 @@ __global__ void __launch_bounds__(kSweep2Lanes) k_micsa_sweep2_fused(
         const uint32_t give = sh > 0 ? v.w[0] : v.w[3];
         return (uint32_t)__shfl((int)give, sh > 0 ? lane_next : lane_prev, 64);
     };
+    // zr[k] = zof(st + 2 - k), k = 0 .. 5: the wrapped planes of the step's
+    // loads and halves, moved by one plane per step (a compare, no division)
+    int zr[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) zr[k] = zof(2 - k);
     if (active) {
-        Oo_prev = ldg16(od_in + hof(wrap(zstart - dz, g.Lz)));
-        Oo_cur = ldg16(od_in + hof(zof(0)));
+        Oo_prev = ldg16(od_in + hof(zr[3]));
+        Oo_cur = ldg16(od_in + hof(zr[2]));
     }
-    load_step(0);
+    load_step(0, zr[2], zr[1], zr[3]);
     uint32_t sum_old = 0, sum_new = 0;  // level sums before/after the owned moves of both sweeps
     for (int st = 0; st < steps; ++st) {
         const int buf = st & 1, pb = buf ^ 1;
-        const int zA = zof(st);           // A-even plane p
-        const int zAo = zof(st - 1);      // A-odd plane p - dz
-        const int zBe = zof(st - 2);      // B-even plane p - 2dz
-        const int zBo = zof(st - 3);      // B-odd plane p - 3dz
+        const int zA = zr[2];   // A-even plane p
+        const int zAo = zr[3];  // A-odd plane p - dz
+        const int zBe = zr[4];  // B-even plane p - 2dz
+        const int zBo = zr[5];  // B-odd plane p - 3dz
         Oo_next = nSo;
         V4 Se = nSe, Me = nMe, Mo = nMo;
         if (WALK && !RA && wanderA >= 0) {
@@ -219,7 +225,7 @@ __global__ void __launch_bounds__(kSweep2Lanes) k_micsa_sweep2_fused(
             edgeBe = edge_from(NA1, sh_even(wanderAB, zBe));
             edgeBo = edge_from(MA3, sh_odd(wanderAB, zBo));
         }
-        if (st + 1 < steps) load_step(st + 1);
+        if (st + 1 < steps) load_step(st + 1, zr[1], zr[0], zr[2]);
         V4 MoA_next{}, MoB_next{};
         if (RA && rowA_e) refresh_chunk(g, y + g.Ly * zA, c, (y + zA) & 1, rhoA, (uint32_t)r, sw, thA, Me, MoA_next);
         if (active) sts16(&SoO[buf * plane_slots + ry * f.NC + c], Oo_cur);
@@ -326,6 +332,9 @@ __global__ void __launch_bounds__(kSweep2Lanes) k_micsa_sweep2_fused(
         XB1 = XB0;
         MoA_gen = MoA_next;
         MoB_gen = MoB_next;
+#pragma unroll
+        for (int k = 5; k > 0; --k) zr[k] = zr[k - 1];
+        zr[0] = zr[1] + dz == g.Lz ? 0 : (zr[1] + dz < 0 ? g.Lz - 1 : zr[1] + dz);
     }
     // dH = 4 (sum of old levels - sum of new levels) over the owned moves of both sweeps
     block_add(tally + (int64_t)l * kSlots, 4 * ((long long)sum_old - (long long)sum_new));
