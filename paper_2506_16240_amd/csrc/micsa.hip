@@ -1189,7 +1189,8 @@ int msc2_block(const MscTile& f, int W) { return ((f.TY + 4 * kMscPassSweeps) * 
 
 size_t msc2_lds(const MscTile& f, int W) { return (size_t)8 * kMsc2Words * (size_t)(msc2_block(f, W) + W); }
 
-// The pass fits a work-group: lanes and LDS (two work-groups per CU).
+// The pass fits a work-group: lanes and LDS (at most 96 KiB: one or two
+// work-groups per CU).
 bool msc2_fits(const micsa_ctx* c)
 {
     const MscTile f = msc2_tile(c);
@@ -1235,11 +1236,13 @@ int64_t next_refresh(const micsa_ctx* c, int64_t from, int64_t end)
     return -1;
 }
 
-// MicSA sweeps k .. k + n - 1 on multispin planes: pack the byte state,
-// sweep (one launch per sweep marching along z, or one per half sweep; the
-// refresh drawn inside), unpack.  Walkers (one-launch only): each sweep
-// applies the previous timestep's wandering as it loads the levels; the last
-// one is left owed to the byte layout (pend_wander).
+// MicSA sweeps k .. k + n - 1 on multispin planes: pack the byte state
+// unless the planes are live, sweep (two sweeps per launch where the pass
+// applies, else one launch per sweep marching along z, or one per half
+// sweep; refresh levels drawn ahead on the side stream, or in the sweep),
+// and leave the planes live.  Walkers (one-launch only): each sweep applies
+// the previous timestep's wandering as it loads the levels; the last one is
+// left owed to the byte layout (pend_wander).
 MscGeom msc_geom(const micsa_ctx* c)
 {
     MscGeom m;

@@ -41,9 +41,12 @@
 // a half's rows compute values nobody reads: the rows a half reads are the
 // rows its predecessor got right); only the stores and the tally look at
 // ownership.  Plane indices along z move by one per step and are wrapped by
-// a compare, and the ring slot of the couplings likewise, so no step divides;
-// the march is unrolled by six steps, so the three-step histories of the
-// half results and the two register stages rotate by renaming.
+// a compare, so no step divides; the march is unrolled by six steps, so the
+// three-step histories of the half results and the two register stages
+// rotate by renaming, and the coupling ring's slot is the step's phase.
+// The z couplings are loaded in march orientation (word 4 towards z + dz,
+// word 5 towards z - dz), so no half selects by direction, and the shifted
+// x neighbours are funnel shifts by the row's parity offset.
 //
 // LDS, lane-major: lane t owns the kMsc2Words words from t kMsc2Words on,
 // its word of each plane -- the 4T result planes (two step buffers) and six
