@@ -538,7 +538,14 @@ def main() -> int:
                      "event_launch_ms": round(event_ms, 5),
                      "bytes_per_launch": bytes_launch, "launches": mk["kernel_launches"],
                      "sweeps_per_launch": round(sweeps_per_launch, 3),
-                     "bytes_per_update": round(bytes_launch / (sweeps_per_launch * w.N * w.lattices), 3)},
+                     "bytes_per_update": round(bytes_launch / (sweeps_per_launch * w.N * w.lattices), 3),
+                     # the HBM rate a kernel making one sweep per pass over the
+                     # state (per_update bytes per update) would need for the
+                     # same throughput; above 1 when two sweeps per pass beat the
+                     # one-sweep ceiling
+                     "one_sweep_equivalent": {"bytes_per_update": per_update,
+                                              "GBs": round(value * per_update, 1),
+                                              "frac": round(value * per_update / HBM_PEAK_GBS, 4)}},
         "checks": {"micsa_tally_equals_energy": mi["tally_check"]},
     }
     if mi["c4_ms"] is not None:
