@@ -1350,7 +1350,9 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
         const double T = temperature(c->sched, rho);
         if (!(T > 0.0) || !std::isfinite(T)) return fail(c, MICSA_ERANGE, "no temperature for this refresh");
         const DaemonThresholds th = refresh ? daemon_thresholds(T) : DaemonThresholds{0, 0, 0};
-        if (one && !walkers && c->pend_wander < 0 && i + 1 < n && msc2_fits(c)) {
+        // walkers pass their levels' carry words between the lanes of a row,
+        // which share a wave when Lx / 128 divides 64
+        if (one && (walkers ? 64 % m.W == 0 : c->pend_wander < 0) && i + 1 < n && msc2_fits(c)) {
             // sweeps k and k + 1 in one pass; a refresh among them reads its
             // drawn levels (at most one refresh per pass, drawn ahead)
             const bool refresh2 = is_refresh(k + 1, c->sched.period);
@@ -1362,7 +1364,10 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
                 const dim3 grid2((unsigned)(f2.nty * f2.ntz), (unsigned)c->L);
                 const unsigned block2 = (unsigned)msc2_block(f2, m.W);
                 const size_t lds2 = msc2_lds(f2, m.W);
-                const auto kern = refresh2 ? k_msc_sweep_multi<kMscPassSweeps, 1> : k_msc_sweep_multi<kMscPassSweeps, -1>;
+                const auto kern = walkers ? (refresh2 ? k_msc_sweep_multi<kMscPassSweeps, 1, true>
+                                                      : k_msc_sweep_multi<kMscPassSweeps, -1, true>)
+                                          : (refresh2 ? k_msc_sweep_multi<kMscPassSweeps, 1, false>
+                                                      : k_msc_sweep_multi<kMscPassSweeps, -1, false>);
                 if (lds2 > 64 * 1024 &&
                     hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2) !=
                         hipSuccess)
@@ -1374,8 +1379,13 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
                                *a_b = c->mb, *a_r0 = c->mdr0, *a_r1 = c->mdr1;
                 uint64_t *o_s = c->ms_alt, *o_d0 = c->md0_alt, *o_d1 = c->md1_alt;
                 unsigned long long* a_t = c->tally;
+                // walkers: the wandering owed to sweep k's levels (none after a
+                // refresh), and sweep k's own, applied before sweep k + 1 (none
+                // when that one refreshes)
+                int a_w = walkers && !refresh ? c->pend_wander : -1;
+                int a_wA = walkers && !refresh2 ? (int)(k & 1) : -1;
                 void* args[] = {&a_g, &a_m, &a_f, &a_s, &a_d0, &a_d1, &a_b, &a_r0, &a_r1, &o_s, &o_d0, &o_d1,
-                                &a_t};
+                                &a_t, &a_w, &a_wA};
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (c->timing && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
                     if (e0) (void)hipEventDestroy(e0);
@@ -1400,7 +1410,8 @@ int sweep_msc(micsa_ctx* c, int64_t n, bool walkers = false)
                 std::swap(c->ms, c->ms_alt);
                 std::swap(c->md0, c->md0_alt);
                 std::swap(c->md1, c->md1_alt);
-                c->pend_wander = -1;
+                // gamma = 1: sweep k + 1 is timestep k + 1; walkers owe its wandering
+                c->pend_wander = walkers ? (int32_t)((k + 1) & 1) : -1;
                 c->k = k + 2;
                 ++i;
                 continue;
@@ -2670,7 +2681,9 @@ const char* micsa_kernel_name(const micsa_ctx* ctx, int32_t algo)
     if (ctx && algo == MICSA_ALGO_MICSA && use_msc(ctx))  // a long call runs its sweeps in pairs where it can
         return msc_one_launch(ctx) ? (msc2_fits(ctx) ? "k_msc_sweep_multi" : "k_msc_sweep") : "k_msc_half";
     // walkers on the fused sweeps wander on the next sweep's loads
-    if (ctx && algo == MICSA_ALGO_WALKERS && use_msc(ctx, kMscMinSweeps, algo)) return "k_msc_sweep";
+    if (ctx && algo == MICSA_ALGO_WALKERS && use_msc(ctx, kMscMinSweeps, algo))
+        return msc_one_launch(ctx) && msc2_fits(ctx) && 64 % (ctx->p.Lx / 128) == 0 ? "k_msc_sweep_multi"
+                                                                                    : "k_msc_sweep";
     if (algo == MICSA_ALGO_WALKERS)
         return ctx && use_fused(ctx) && ctx->gamma == 1
                    ? (ctx->temporal == 2 && sweep2_walk_eligible(ctx) ? "k_micsa_sweep2_fused" : "k_micsa_sweep_fused")

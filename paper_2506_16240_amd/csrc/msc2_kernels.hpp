@@ -29,13 +29,25 @@
 // read in place of the stored ones -- by the host passing the drawn planes
 // as the input levels when the first sweep of the pass refreshes, and by
 // the kernel loading them for halves 2 RJ and 2 RJ + 1 when sweep RJ >= 1 of
-// the pass refreshes (RJ < 0: none does).  Walkers keep the one-sweep kernel.
+// the pass refreshes (RJ < 0: none does).
+//
+// Walkers (WALK; Sec. 2.6, forward-X wandering; a row's lanes share a wave,
+// Lx / 128 dividing 64): the levels move by 0 or +-1 site across the two
+// parities' planes at the end of each timestep.  The wandering owed from
+// before the pass (parity `wander`, -1 none) is applied as halves 0 and 1
+// load their levels, from the other parity's planes, as the one-sweep kernel
+// does; that of the pass's first sweep (parity `wanderA`, -1 when the second
+// sweep refreshes) moves half 1's levels of the step before into half 2 and
+// half 0's levels of three steps before into half 3.  The carry word of a
+// shift comes from the neighbouring lane of the row by a shuffle.  The pass
+// leaves its second sweep's wandering owed.
 //
 // Energy tally: 4 (sum m - sum m') of every half on the owned sites.  Half
 // h >= 2 starts from the levels half h - 2 left at the same site, so the sum
 // telescopes: the levels going into halves 0 and 1, minus those leaving the
 // last two halves, plus, at a refresh half, the drawn levels minus those
-// they replace.
+// they replace.  With walkers the levels move between sites, and every half
+// counts its own.
 //
 // Cost per step.  Every lane runs every half that has started (lanes outside
 // a half's rows compute values nobody reads: the rows a half reads are the
@@ -138,19 +150,34 @@ __device__ __forceinline__ uint64_t shl_t(uint64_t v, uint64_t prv, uint32_t t)
     return (v << t) | (uint64_t)((uint32_t)(prv >> 63) & t);
 }
 
+// The levels of a row moved by sh in {-1, 0, +1} sites (the wandering): the
+// carry word from the row's lane ln (sh > 0) or lp (sh < 0) of the wave.
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+__device__ __forceinline__ uint64_t wander_shift(uint64_t v, int sh, int ln, int lp)
+{
+    const uint64_t c = shfl64(v, sh > 0 ? ln : lp);
+    return sh > 0 ? shr_q(v, c, 1u) : (sh < 0 ? shl_t(v, c, 1u) : v);
+}
+
 __device__ __forceinline__ int level_count(uint64_t m0, uint64_t m1)
 {
     return __popcll(m0) + 2 * __popcll(m1);
 }
 
-template <int T, int RJ>
+template <int T, int RJ, bool WALK>
 __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
     Geom g, MscGeom m, MscTile f, const uint64_t* __restrict__ spin_in, const uint64_t* __restrict__ d0_in,
     const uint64_t* __restrict__ d1_in, const uint64_t* __restrict__ bond, const uint64_t* __restrict__ dr0,
     const uint64_t* __restrict__ dr1, uint64_t* __restrict__ spin_out, uint64_t* __restrict__ d0_out,
-    uint64_t* __restrict__ d1_out, unsigned long long* __restrict__ tally)
+    uint64_t* __restrict__ d1_out, unsigned long long* __restrict__ tally, int wander, int wanderA)
 {
     constexpr int H = 2 * T;      // halves per pass
+    static_assert(!WALK || T == 2, "walkers: two sweeps per pass");
     constexpr int D = 2 * T + 1;  // planes in the coupling ring
     constexpr bool DRAWN = RJ >= 1;
     static_assert(RJ < T, "the refresh sweep is one of the pass");
@@ -202,6 +229,9 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
     const uint64_t* const Lyn = lds_m2 + myn * kMsc2Words;
     const uint64_t* const Lyp = lds_m2 + myp * kMsc2Words;
     const int ybit = y & 1;
+    // walkers: the wave lanes holding this row's next and previous words
+    const int lane_n = mxn & 63, lane_p = mxp & 63;
+    const bool owedA = WALK && wander >= 0;  // A's input levels come from the other parity's planes
 
     const int64_t lp = (int64_t)l * 2 * m.plane;
     const uint64_t* ev_in = spin_in + lp;
@@ -240,11 +270,12 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
         for (int d = 0; d < 4; ++d) S.J[d] = ld(bl + (int64_t)d * m.plane, h);
         S.J[4] = ld(bfw, h);
         S.J[5] = ld(bbw, h);
-        S.me0 = ld(d0_in + lp, h);
-        S.me1 = ld(d1_in + lp, h);
+        const int64_t pe = lp + (owedA ? m.plane : 0), po = lp + (owedA ? 0 : m.plane);
+        S.me0 = ld(d0_in + pe, h);
+        S.me1 = ld(d1_in + pe, h);
         const uint32_t ho = zoff(zDn) + rD;
-        S.mo0 = ld(d0_in + lp + m.plane, ho);
-        S.mo1 = ld(d1_in + lp + m.plane, ho);
+        S.mo0 = ld(d0_in + po, ho);
+        S.mo1 = ld(d1_in + po, ho);
         if constexpr (DRAWN) {
             const uint32_t he = zoff(zRe) + rRe, hr = zoff(zRo) + rRo;
             S.re0 = ld(dr0 + lp, he);
@@ -258,7 +289,8 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
     uint64_t Oq[3];                          // old odd spins loaded at steps st, st - 1, st - 2 (by st mod 3)
     uint64_t RES[H - 1][3] = {};             // half h's result at its site, by st mod 3
     uint64_t LV0[H > 2 ? H - 2 : 1][3] = {}, LV1[H > 2 ? H - 2 : 1][3] = {};  // its levels (read by half h + 2)
-    int cin = 0, cout = 0;                   // telescoped level sums of the owned sites
+    uint64_t L3a = 0, L3b = 0;               // walkers: half 0's levels three steps back
+    int cin = 0, cout = 0;                   // level sums of the owned sites (telescoped without walkers)
     {
         // before step 0: odd spins of zstart - dz and zstart (ring positions of steps -2 and -1)
         Oq[1] = ld(od_in, zoff(zc[1]) + rO);
@@ -338,25 +370,51 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
                 s0 = C.Es;
                 m0 = C.me0;
                 m1 = C.me1;
+                if (owedA) {  // even sites take the odd sites' levels, moved by she(wander)
+                    const int sh = wander == 0 ? (int)q : (int)q - 1;
+                    m0 = wander_shift(m0, sh, lane_n, lane_p);
+                    m1 = wander_shift(m1, sh, lane_n, lane_p);
+                }
             } else if (h == 1) {
                 s0 = Oq[c2];
                 m0 = C.mo0;
                 m1 = C.mo1;
+                if (owedA) {  // odd sites take the even sites' levels, moved by sho(wander)
+                    const int sh = wander == 0 ? (int)q - 1 : (int)q;
+                    m0 = wander_shift(m0, sh, lane_n, lane_p);
+                    m1 = wander_shift(m1, sh, lane_n, lane_p);
+                }
             } else {
                 s0 = RES[h - 2][c2];
                 m0 = LV0[h - 2][c2];
                 m1 = LV1[h - 2][c2];
+                bool drawn_here = false;
                 if constexpr (DRAWN) {
                     if ((h >> 1) == RJ) {  // the refresh: drawn levels replace those half h - 2 left
                         const uint64_t r0 = par ? C.ro0 : C.re0, r1 = par ? C.ro1 : C.re1;
-                        const int dc = level_count(r0, r1) - level_count(m0, m1);
-                        cin += owned ? dc : 0;
+                        if (!WALK) {
+                            const int dc = level_count(r0, r1) - level_count(m0, m1);
+                            cin += owned ? dc : 0;
+                        }
                         m0 = r0;
                         m1 = r1;
+                        drawn_here = true;
+                    }
+                }
+                if constexpr (WALK) {
+                    if (!drawn_here && wanderA >= 0) {
+                        // sweep A's wandering: even sites of half 2 take half 1's
+                        // levels of the step before (same plane), odd sites of
+                        // half 3 half 0's of three steps before, each moved by
+                        // she / sho of the parity wanderA
+                        const uint64_t a0 = par ? L3a : LV0[1][c1], a1 = par ? L3b : LV1[1][c1];
+                        const int sh = (par == 0) == (wanderA == 0) ? (int)q : (int)q - 1;
+                        m0 = wander_shift(a0, sh, lane_n, lane_p);
+                        m1 = wander_shift(a1, sh, lane_n, lane_p);
                     }
                 }
             }
-            if (h < 2) cin += owned ? level_count(m0, m1) : 0;
+            if (WALK || h < 2) cin += owned ? level_count(m0, m1) : 0;
             const uint64_t nb[6] = {nxp, nxm, nyp, nym, up, dn};
             const uint64_t Sn = msc_move_fused(s0, nb, jb, m0, m1);
             if (h < H - 1) RES[h][c0] = Sn;
@@ -365,6 +423,7 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
                 LV1[h][c0] = m1;
             }
             if (h + 1 < H) Lme[SB(buf, h + 1)] = Sn;
+            if (WALK && h < H - 2) cout += owned ? level_count(m0, m1) : 0;
             if (h >= H - 2) {
                 cout += owned ? level_count(m0, m1) : 0;
                 if (owned) {
@@ -376,10 +435,14 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
                 }
             }
         }
-        // advance the wrapped planes and the ring slot by one step
+        // advance the wrapped planes by one step
 #pragma unroll
         for (int k = ZH - 1; k > 0; --k) zc[k] = zc[k - 1];
         zc[0] = zp1;
+        if constexpr (WALK) {  // half 0's levels of step st - 2: three steps back at the next step
+            L3a = LV0[0][c2];
+            L3b = LV1[0][c2];
+        }
     };
     for (int st = 0; st < steps; st += 6) {
         step(std::integral_constant<int, 0>{}, st);

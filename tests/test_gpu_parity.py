@@ -268,14 +268,14 @@ def test_anneal_L512_first_sweeps_full_size(prefetch, temporal, kernel):
 @pytest.mark.parametrize("algo", [M.ALGO_MICSA, M.ALGO_WALKERS])
 def test_anneal_L512_default_launch_full_size(algo):
     """The 512^3 anneal exactly as the benchmark times it: no launch option
-    (the library's own choice: MicSA two sweeps per pass over the multispin
-    planes with the automatic 24-row, 16-plane tile and its ragged last y
-    tile, z-band XCD order over the z tiles, refresh levels drawn ahead on
-    the side stream; walkers one sweep per launch with the automatic 44-row
-    tile), 41 sweeps in ONE call (refreshes before sweeps 0, 20 and 40, two
-    of them drawn ahead inside the call), then 3 more in a second call.
-    Spins, daemons, energy, daemon energy and the tally equal the oracle's
-    bit for bit."""
+    (the library's own choice: two sweeps per pass over the multispin planes
+    with the automatic 24-row, 16-plane tile and its ragged last y tile,
+    z-band XCD order over the z tiles, refresh levels drawn ahead on the
+    side stream; walkers wander between the pass's two sweeps and owe the
+    second's to the next call), 41 sweeps in ONE call (refreshes before
+    sweeps 0, 20 and 40, two of them drawn ahead inside the call), then 3
+    more in a second call.  Spins, daemons, energy, daemon energy and the
+    tally equal the oracle's bit for bit."""
     w = W.ANNEAL_L512
     g, o = pair(w.Lx, w.Ly, w.Lz, w.S, w.R, w.seed)
     gs, os_ = scheds(w.kind, w.T0, w.T1, w.n_sweeps, w.period)
@@ -284,7 +284,7 @@ def test_anneal_L512_default_launch_full_size(algo):
     for n in (41, 3):
         g.sweep(algo, n)
         o.run(oalgo, os_, n, 0)
-        assert g.kernel_name(algo) == ("k_msc_sweep_multi" if algo == M.ALGO_MICSA else "k_msc_sweep")
+        assert g.kernel_name(algo) == "k_msc_sweep_multi"
         same_state(g, o)
         E = o.energy()
         assert np.array_equal(g.energy(), E)
@@ -534,17 +534,23 @@ def test_multispin_planes_live_between_calls(ahead):
     g.close()
 
 
+@pytest.mark.parametrize("passes", [1, 2], ids=["one-sweep", "two-sweep"])
 @pytest.mark.parametrize("shape", [(128, 4, 4, 1, 1), (256, 6, 4, 1, 2), (384, 4, 6, 2, 1), (512, 50, 4, 1, 1)])
-def test_multispin_walkers_match_oracle(shape):
+def test_multispin_walkers_match_oracle(shape, passes):
     """Walkers (gamma = 1, forward-X wandering after every timestep, Sec.
     2.6) on the one-launch multispin sweep: each sweep applies the previous
     timestep's wandering as it loads the levels (one or three words per
-    row), the last one is left owed to the byte state.  Calls of walkers
-    and daemons in turn, the daemons read back in between, single sweeps
-    and long calls, against the oracle."""
+    row), the last one is left owed to the byte state; and two sweeps per
+    pass, the first sweep's wandering applied between them (rows of one,
+    two and four words; three words per row fall back to one sweep per
+    launch).  Calls of walkers and daemons in turn, the daemons read back in
+    between, single sweeps and long calls, against the oracle."""
     g, o = pair(*shape, seed=0x77AB)
     g.set_option(M.OPT_SWEEP_KERNEL, M.KERNEL_MULTISPIN)
-    assert g.kernel_name(M.ALGO_WALKERS) == "k_msc_sweep"
+    g.set_option(M.OPT_MSC_PASS, passes)
+    W = shape[0] // 128
+    expect = "k_msc_sweep_multi" if passes == 2 and 64 % W == 0 else "k_msc_sweep"
+    assert g.kernel_name(M.ALGO_WALKERS) == expect
     gs, os_ = scheds(M.SCHED_LINEAR, 2.4, 0.3, 90, 7)
     g.set_schedule(gs)
     for algo, oalgo, n in ((M.ALGO_WALKERS, O.ALGO_WALKERS, 12), (M.ALGO_WALKERS, O.ALGO_WALKERS, 1),
