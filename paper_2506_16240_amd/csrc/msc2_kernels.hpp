@@ -150,18 +150,20 @@ __device__ __forceinline__ uint64_t shl_t(uint64_t v, uint64_t prv, uint32_t t)
     return (v << t) | (uint64_t)((uint32_t)(prv >> 63) & t);
 }
 
-// The levels of a row moved by sh in {-1, 0, +1} sites (the wandering): the
-// carry word from the row's lane ln (sh > 0) or lp (sh < 0) of the wave.
+// The levels of a row moved by amt in {0, 1} sites (the wandering) towards
+// lower sites (fwd: site k takes site k + amt, the carry word from the row's
+// next lane ln of the wave) or higher ones (site k takes site k - amt, the
+// carry from the previous lane lp).  The direction is uniform in a step,
+// the amount the row's parity offset.
 __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
 {
     const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
     const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
     return (uint64_t)lo | ((uint64_t)hi << 32);
 }
-__device__ __forceinline__ uint64_t wander_shift(uint64_t v, int sh, int ln, int lp)
+__device__ __forceinline__ uint64_t wander_shift(uint64_t v, bool fwd, uint32_t amt, int ln, int lp)
 {
-    const uint64_t c = shfl64(v, sh > 0 ? ln : lp);
-    return sh > 0 ? shr_q(v, c, 1u) : (sh < 0 ? shl_t(v, c, 1u) : v);
+    return fwd ? shr_q(v, shfl64(v, ln), amt) : shl_t(v, shfl64(v, lp), amt);
 }
 
 __device__ __forceinline__ int level_count(uint64_t m0, uint64_t m1)
@@ -370,19 +372,19 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
                 s0 = C.Es;
                 m0 = C.me0;
                 m1 = C.me1;
-                if (owedA) {  // even sites take the odd sites' levels, moved by she(wander)
-                    const int sh = wander == 0 ? (int)q : (int)q - 1;
-                    m0 = wander_shift(m0, sh, lane_n, lane_p);
-                    m1 = wander_shift(m1, sh, lane_n, lane_p);
+                if (owedA) {  // even sites take the odd sites' levels: by +q (wander 0) or -(1 - q)
+                    const bool fwd = wander == 0;
+                    m0 = wander_shift(m0, fwd, fwd ? q : qn, lane_n, lane_p);
+                    m1 = wander_shift(m1, fwd, fwd ? q : qn, lane_n, lane_p);
                 }
             } else if (h == 1) {
                 s0 = Oq[c2];
                 m0 = C.mo0;
                 m1 = C.mo1;
-                if (owedA) {  // odd sites take the even sites' levels, moved by sho(wander)
-                    const int sh = wander == 0 ? (int)q - 1 : (int)q;
-                    m0 = wander_shift(m0, sh, lane_n, lane_p);
-                    m1 = wander_shift(m1, sh, lane_n, lane_p);
+                if (owedA) {  // odd sites take the even sites' levels: by -(1 - q) (wander 0) or +q
+                    const bool fwd = wander != 0;
+                    m0 = wander_shift(m0, fwd, fwd ? q : qn, lane_n, lane_p);
+                    m1 = wander_shift(m1, fwd, fwd ? q : qn, lane_n, lane_p);
                 }
             } else {
                 s0 = RES[h - 2][c2];
@@ -408,9 +410,9 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
                         // half 3 half 0's of three steps before, each moved by
                         // she / sho of the parity wanderA
                         const uint64_t a0 = par ? L3a : LV0[1][c1], a1 = par ? L3b : LV1[1][c1];
-                        const int sh = (par == 0) == (wanderA == 0) ? (int)q : (int)q - 1;
-                        m0 = wander_shift(a0, sh, lane_n, lane_p);
-                        m1 = wander_shift(a1, sh, lane_n, lane_p);
+                        const bool fwd = (par == 0) == (wanderA == 0);
+                        m0 = wander_shift(a0, fwd, fwd ? q : qn, lane_n, lane_p);
+                        m1 = wander_shift(a1, fwd, fwd ? q : qn, lane_n, lane_p);
                     }
                 }
             }
