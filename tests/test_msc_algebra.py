@@ -1,11 +1,12 @@
 """The multispin sweep's bit-sliced Creutz move against the rule it encodes.
 
-The one-launch multispin sweep (csrc/msc_kernels.hpp, msc_move) decides 64
-sites per word with boolean algebra.  Its three-input XOR and majority are
-single gfx950 v_bitop3 instructions given by an 8-bit truth table.  This test
-restates that algebra on the CPU, emulating v_bitop3 from its table, and
-checks it site by site against the move of Sec. 2.3 with the 2-bit daemon
-of Sec. 2.5.  A site with u unsatisfied bonds has local energy 2u - 6, and
+The multispin sweeps decide 64 sites per word with boolean algebra: the
+one-sweep kernel with msc_move (csrc/msc_kernels.hpp), the two-sweep pass
+with msc_move_fused (csrc/msc2_kernels.hpp), whose gates are fused further.
+Their three-input gates are single gfx950 v_bitop3 instructions given by an
+8-bit truth table.  This test restates that algebra on the CPU, emulating
+v_bitop3 from its table, and checks it site by site against the move of
+Sec. 2.3 with the 2-bit daemon of Sec. 2.5.  A site with u unsatisfied bonds has local energy 2u - 6, and
 flipping it changes the energy by dH = 12 - 4u.  The daemon holds n = 4m,
 m in 0..3, and the flip is accepted iff 0 <= n - dH <= 12, i.e. iff
 3 <= m + u <= 6, leaving m' = m + u - 3.  The check covers every (m, u) and
