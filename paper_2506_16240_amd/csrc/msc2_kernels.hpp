@@ -46,8 +46,10 @@
 // h >= 2 starts from the levels half h - 2 left at the same site, so the sum
 // telescopes: the levels going into halves 0 and 1, minus those leaving the
 // last two halves, plus, at a refresh half, the drawn levels minus those
-// they replace.  With walkers the levels move between sites, and every half
-// counts its own.
+// they replace.  Walkers move levels only within a row, cyclically, and a
+// tile owns whole rows of a plane, so the sum over a row's two parities
+// that the next half starts from is the sum the half before left, and the
+// same telescoped count holds.
 //
 // Cost per step.  Every lane runs every half that has started (lanes outside
 // a half's rows compute values nobody reads: the rows a half reads are the
@@ -292,7 +294,7 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
     uint64_t RES[H - 1][3] = {};             // half h's result at its site, by st mod 3
     uint64_t LV0[H > 2 ? H - 2 : 1][3] = {}, LV1[H > 2 ? H - 2 : 1][3] = {};  // its levels (read by half h + 2)
     uint64_t L3a = 0, L3b = 0;               // walkers: half 0's levels three steps back
-    int cin = 0, cout = 0;                   // level sums of the owned sites (telescoped without walkers)
+    int cin = 0, cout = 0;                   // telescoped level sums of the owned sites
     {
         // before step 0: odd spins of zstart - dz and zstart (ring positions of steps -2 and -1)
         Oq[1] = ld(od_in, zoff(zc[1]) + rO);
@@ -394,10 +396,8 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
                 if constexpr (DRAWN) {
                     if ((h >> 1) == RJ) {  // the refresh: drawn levels replace those half h - 2 left
                         const uint64_t r0 = par ? C.ro0 : C.re0, r1 = par ? C.ro1 : C.re1;
-                        if (!WALK) {
-                            const int dc = level_count(r0, r1) - level_count(m0, m1);
-                            cin += owned ? dc : 0;
-                        }
+                        const int dc = level_count(r0, r1) - level_count(m0, m1);
+                        cin += owned ? dc : 0;
                         m0 = r0;
                         m1 = r1;
                         drawn_here = true;
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
                     }
                 }
             }
-            if (WALK || h < 2) cin += owned ? level_count(m0, m1) : 0;
+            if (h < 2) cin += owned ? level_count(m0, m1) : 0;
             const uint64_t nb[6] = {nxp, nxm, nyp, nym, up, dn};
             const uint64_t Sn = msc_move_fused(s0, nb, jb, m0, m1);
             if (h < H - 1) RES[h][c0] = Sn;
@@ -425,7 +425,6 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
                 LV1[h][c0] = m1;
             }
             if (h + 1 < H) Lme[SB(buf, h + 1)] = Sn;
-            if (WALK && h < H - 2) cout += owned ? level_count(m0, m1) : 0;
             if (h >= H - 2) {
                 cout += owned ? level_count(m0, m1) : 0;
                 if (owned) {
