@@ -304,14 +304,17 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
         load(STG[0], zp, zc[0], zc[1], zc[kRe0], zc[kRo0]);
     }
 
-    auto step = [&](auto phc, int st) {
+    // One step of the march.  FIRST: the first six steps, where half h
+    // starts at step 2h (known at compile time); after them every half runs.
+    auto step = [&](auto phc, auto firstc, int st) {
         constexpr int ph = decltype(phc)::value;
+        constexpr bool FIRST = decltype(firstc)::value;
+        constexpr auto live = [](int h) { return !FIRST || ph >= 2 * h; };
         constexpr int c0 = ph % 3, c1 = (ph + 2) % 3, c2 = (ph + 1) % 3;  // st, st - 1, st - 2 (mod 3)
         constexpr int buf = ph & 1, pb = buf ^ 1;
         Stage& C = STG[buf];
         __builtin_amdgcn_s_waitcnt(0x0F70);  // stage C complete (vmcnt(0))
-        const int zz = zstart + dz * st;
-        // next step's planes: zz2 = zz + dz
+        // next step's planes: zz2 = zz + dz (zz = zstart + dz st, the unwrapped plane)
         const int zp1 = step_wrap(zc[0], dz, g.Lz), zp2 = step_wrap(zp1, dz, g.Lz);
         if (st + 1 < steps)
             load(STG[pb], zp2, zp1, zc[0], zc[kRe], zc[kRo]);
@@ -327,8 +330,7 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
         const uint32_t q = (uint32_t)((ybit + zc[0]) & 1), qn = q ^ 1u;
 #pragma unroll
         for (int h = 0; h < H; ++h) {
-            if (st < 2 * h) break;  // halves h and later not started yet (uniform)
-            const int zh_u = zz - dz * h;  // unwrapped plane of this half
+            if (!live(h)) continue;  // not started yet
             const int zh = zc[h];
             const int par = h & 1;
             const int src = SB(h == 0 ? buf : pb, h);
@@ -367,7 +369,9 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
                 jb[4] = Lme[CB(slot(h - 1), 5)];
                 jb[5] = Lme[CB(slot(h + 1), 4)];
             }
-            const bool owned = own_row && zh_u >= z0 && zh_u < z0 + f.TZ;
+            // the half's plane is owned iff 0 <= st - h - (H - 1) < TZ, in
+            // either march direction
+            const bool owned = own_row && (uint32_t)(st - h - (H - 1)) < (uint32_t)f.TZ;
             // own spin and levels
             uint64_t s0, m0, m1;
             if (h == 0) {
@@ -445,18 +449,28 @@ __global__ __launch_bounds__(kMsc2Lanes, 2) void k_msc_sweep_multi(
             L3b = LV1[0][c2];
         }
     };
-    for (int st = 0; st < steps; st += 6) {
-        step(std::integral_constant<int, 0>{}, st);
+    using Yes = std::true_type;
+    using No = std::false_type;
+    static_assert(2 * (H - 1) <= 6, "every half has started by step 6");
+    // steps = TZ + 2H - 2 >= 7: the first six steps always run
+    step(std::integral_constant<int, 0>{}, Yes{}, 0);
+    step(std::integral_constant<int, 1>{}, Yes{}, 1);
+    step(std::integral_constant<int, 2>{}, Yes{}, 2);
+    step(std::integral_constant<int, 3>{}, Yes{}, 3);
+    step(std::integral_constant<int, 4>{}, Yes{}, 4);
+    step(std::integral_constant<int, 5>{}, Yes{}, 5);
+    for (int st = 6; st < steps; st += 6) {
+        step(std::integral_constant<int, 0>{}, No{}, st);
         if (st + 1 >= steps) break;
-        step(std::integral_constant<int, 1>{}, st + 1);
+        step(std::integral_constant<int, 1>{}, No{}, st + 1);
         if (st + 2 >= steps) break;
-        step(std::integral_constant<int, 2>{}, st + 2);
+        step(std::integral_constant<int, 2>{}, No{}, st + 2);
         if (st + 3 >= steps) break;
-        step(std::integral_constant<int, 3>{}, st + 3);
+        step(std::integral_constant<int, 3>{}, No{}, st + 3);
         if (st + 4 >= steps) break;
-        step(std::integral_constant<int, 4>{}, st + 4);
+        step(std::integral_constant<int, 4>{}, No{}, st + 4);
         if (st + 5 >= steps) break;
-        step(std::integral_constant<int, 5>{}, st + 5);
+        step(std::integral_constant<int, 5>{}, No{}, st + 5);
     }
     block_add(tally + (int64_t)l * kSlots, 4ll * (long long)(cin - cout));
 }
